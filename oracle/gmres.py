@@ -1,0 +1,394 @@
+"""CPU oracle for restarted GMRES: test infrastructure, not part of the product.
+
+A plain, slow and deliberately unoptimised NumPy implementation of the
+method of Lindquist, Luszczek and Dongarra, "Improving the Performance of
+the GMRES Method using Mixed-Precision Techniques" (arXiv 2011.01850).
+Only the test-suite, the smoke check and the CPU-baseline leg of the
+benchmark may import it; the GPU library never does, and this module never
+imports the GPU library.
+
+Everything follows Algorithm 1 (restarted GMRES) of the paper, in its order
+and notation, with the orthogonalisation procedures MGS and CGSR given with
+it.  Floating point is float64 unless an emulated precision is requested.
+
+Readings taken where the paper is silent or garbled (each one is also
+listed in the design notes of the repository):
+
+* CGSR shows one projection only; its name and the orthogonality property it
+  is used for are those of re-orthogonalised classical Gram-Schmidt, so the
+  oracle always performs two full projections (CGS2) and sums them.
+* ``s_0 <- beta`` is read as s_1 = beta (1-based), consistent with the
+  update of (s_j, s_{j+1}) in the Givens step.
+* ``rotation_matrix`` is not defined; with the paper's matrix
+  [[alpha, beta], [-beta, alpha]] the rotation that zeroes h_{j+1,j} is
+  alpha = a / rho, beta = b / rho with rho = hypot(a, b), and (1, 0) when
+  b = 0.
+* The restart condition is not specified: the inner loop ends when j = m,
+  when the Arnoldi residual |s_{j+1}| / ||b|| <= tol, on an exact breakdown
+  (h_{j+1,j} = 0), when the iteration budget is spent, or, optionally, when
+  |s_{j+1}| <= delta * beta (the improvement trigger of the restart study).
+* "Small enough" is the relative residual ||b - A x||_2 / ||b||_2 <= tol,
+  computed in float64 at every restart.
+* The residual is z = b - A x (the numerics section writes A x - b; the norm
+  is the same).
+* A singular least-squares factor is truncated to its largest leading block
+  with pivots |H_ii| > 16 k u max|H| (u of the Arnoldi arithmetic).
+
+Emulated precisions (for predicting iteration counts, never for bitwise
+parity): ``fp32`` keeps the Krylov basis, w and the Arnoldi copy of A in
+float32 while the residual, the update, H, the rotations and the
+back-solve stay float64 (the precision split of the numerics section);
+``bf16`` / ``fp16`` additionally store each basis vector rounded to nearest
+even in the 2-byte format after multiplying by a per-vector power-of-two
+scale.  Two debug switches reproduce the negative control of the
+per-variable study (section 4.1): ``residual_fp32`` computes the restart
+residual in float32 and ``update_fp32`` keeps x in float32.
+
+Parity pins for this module live in tests/test_oracle.py.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+RUNNING, CONVERGED, MAXITER, STALLED = 0, 1, 2, 3
+STATUS_NAMES = {RUNNING: "RUNNING", CONVERGED: "CONVERGED", MAXITER: "MAXITER", STALLED: "STALLED"}
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+class Matrix:
+    """CSR matrix with a plain product: y_i = sum over the stored entries of row i of a_ik x_k."""
+
+    def __init__(self, row_ptr, col_idx, vals, n=None):
+        self.row_ptr = np.asarray(row_ptr, dtype=np.int64)
+        self.col_idx = np.asarray(col_idx, dtype=np.int64)
+        self.vals = np.asarray(vals, dtype=np.float64)
+        self.n = int(n if n is not None else self.row_ptr.size - 1)
+        self.rows = np.repeat(np.arange(self.n), np.diff(self.row_ptr))
+        self.vals32 = self.vals.astype(np.float32)
+
+    @classmethod
+    def from_csr(cls, A):
+        return cls(A.row_ptr, A.col_idx, A.vals, A.n)
+
+    def matvec(self, x):
+        """Float64 product (sums taken by bincount, in storage order)."""
+        x = np.asarray(x, dtype=np.float64)
+        return np.bincount(self.rows, weights=self.vals * x[self.col_idx], minlength=self.n)
+
+    def matvec32(self, x32):
+        """Emulated single-precision product: float32 products, result rounded to float32."""
+        prod = (self.vals32 * np.asarray(x32, dtype=np.float32)[self.col_idx]).astype(np.float64)
+        return np.bincount(self.rows, weights=prod, minlength=self.n).astype(np.float32)
+
+    def diagonal(self):
+        d = np.zeros(self.n)
+        on = self.rows == self.col_idx
+        d[self.rows[on]] = self.vals[on]
+        return d
+
+    def dense(self):
+        D = np.zeros((self.n, self.n))
+        np.add.at(D, (self.rows, self.col_idx), self.vals)
+        return D
+
+
+# ---------------------------------------------------------------------------
+# 2-byte storage of a basis vector (the half-precision direction of the
+# conclusion's future work; the paper prints no format, so the scale rule is
+# this project's reading: a power of two that puts max|v| in (T/2, T]).
+
+FMT_TARGET_LOG2 = {"fp16": 15, "bf16": 0}
+
+
+def round_bf16(x32):
+    """Round float32 values to bfloat16 (nearest, ties to even); returns float32."""
+    b = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def round_fp16(x32):
+    """Round float32 values to IEEE half (nearest, ties to even); returns float32."""
+    return np.asarray(x32, dtype=np.float32).astype(np.float16).astype(np.float32)
+
+
+def scale_exponent(vmax: float, fmt: str) -> int:
+    """e such that vmax * 2**e lies in (T/2, T], T = 2**FMT_TARGET_LOG2[fmt]."""
+    if not (vmax > 0.0) or not math.isfinite(vmax):
+        return 0
+    f, p = math.frexp(vmax)  # vmax = f * 2**p, f in [0.5, 1)
+    return FMT_TARGET_LOG2[fmt] - p + (1 if f == 0.5 else 0)
+
+
+def encode(w32, inv_h: float, fmt: str):
+    """Store v = w / h in a 2-byte format with a power-of-two scale.
+
+    vmax = max|w| / h; e = scale_exponent(vmax); f = float32(2**e / h);
+    stored = round(float32(w * f)); the decoded vector is stored * 2**-e.
+    Returns (stored values as float32, decode scale 2**-e).
+    """
+    w32 = np.asarray(w32, dtype=np.float32)
+    vmax = float(np.max(np.abs(w32))) * inv_h if w32.size else 0.0
+    e = scale_exponent(vmax, fmt)
+    f = np.float32(math.ldexp(1.0, e) * inv_h)
+    t = (w32 * f).astype(np.float32)
+    stored = round_fp16(t) if fmt == "fp16" else round_bf16(t)
+    return stored, math.ldexp(1.0, -e)
+
+
+# ---------------------------------------------------------------------------
+
+def givens(a: float, b: float):
+    """(alpha, beta) of the rotation [[alpha, beta], [-beta, alpha]] taking (a, b) to (rho, 0)."""
+    if b == 0.0:
+        return 1.0, 0.0
+    rho = math.hypot(a, b)
+    return a / rho, b / rho
+
+
+def back_solve(H, s, k, u):
+    """y = H[:k,:k]^-1 s[:k] for upper-triangular H, truncated where H is singular.
+
+    The leading block kept is the longest one whose pivots all exceed
+    16 k u max|H|, u being the unit roundoff of the Arnoldi arithmetic.
+    """
+    if k == 0:
+        return np.zeros(0), 0
+    Hk = H[:k, :k]
+    hn = np.max(np.abs(Hk))
+    thr = 16 * k * u * hn
+    kk = 0
+    while kk < k and abs(Hk[kk, kk]) > thr:
+        kk += 1
+    y = np.zeros(kk)
+    for i in range(kk - 1, -1, -1):
+        y[i] = (s[i] - np.dot(Hk[i, i + 1:kk], y[i + 1:kk])) / Hk[i, i]
+    return y, kk
+
+
+def stall_window(m: int) -> int:
+    """5% of the inner iterations per restart, at least one (the stall definition of Table 1)."""
+    return max(1, math.ceil(0.05 * m))
+
+
+def stall_point(arnoldi_res, m: int):
+    """Number of inner iterations before the Arnoldi residual stalls (Table 1's definition).
+
+    ``arnoldi_res[j]`` is the Arnoldi residual |s_{j+1}| after j inner steps
+    of one cycle (``arnoldi_res[0]`` = beta).  The improvement has stalled
+    after j steps when the next window of w = max(1, ceil(0.05 m)) steps
+    improves it by less than a factor 1.001.  Returns the first such j, or
+    None when no stall is seen in the recorded steps.
+    """
+    w = stall_window(m)
+    seq = list(arnoldi_res)
+    for j in range(len(seq) - w):
+        if seq[j + w] > seq[j] / 1.001:
+            return j
+    return None
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    status: int
+    iters: int
+    restarts: int
+    rel_residual: float
+    history: list = field(default_factory=list)  # relative restart residuals
+    arnoldi: list = field(default_factory=list)  # per cycle: list of |s_{j+1}| / ||b||
+    cycles: list = field(default_factory=list)  # per cycle (record=True): dict(V, Hbar, H, s, k, beta)
+    fallback_used: bool = False
+
+    @property
+    def status_name(self):
+        return STATUS_NAMES[self.status]
+
+
+def _cast(v, precision):
+    return np.asarray(v, dtype=np.float64 if precision == "fp64" else np.float32)
+
+
+def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
+          precision="fp64", precond=None, restart_improve=0.0, stall_cycles=3,
+          fallback=True, record=False, residual_fp32=False, update_fp32=False):
+    """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
+
+    ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> z applied
+    on the right: z_j = M v_j, w = A z_j, and the correction is Z y
+    (flexible GMRES).  The paper itself preconditions on the left; the
+    right-preconditioned form is what the learned preconditioner uses.
+    """
+    if ortho not in ("mgs", "cgsr"):
+        raise ValueError(ortho)
+    if precision not in ("fp64", "fp32", "bf16", "fp16"):
+        raise ValueError(precision)
+    b = np.asarray(b, dtype=np.float64)
+    n = A.n
+    bn = float(np.linalg.norm(b))
+    if bn == 0.0:
+        return Result(np.zeros(n), CONVERGED, 0, 0, 0.0, [0.0])
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    if update_fp32:
+        x = x.astype(np.float32).astype(np.float64)
+    lowp = precision != "fp64"
+    two_byte = precision in ("bf16", "fp16")
+    total = 0
+    restarts = 0
+    hist, arn, cyc = [], [], []
+    status = RUNNING
+    fallback_used = False
+    best_beta = math.inf
+    no_progress = 0
+    prev_beta = math.inf
+    use_pc = precond is not None
+    while True:
+        # Alg. 1: residual, in full precision unless the negative control asks otherwise
+        if residual_fp32:
+            Ax = A.matvec32(x.astype(np.float32)).astype(np.float64)
+            z = (b.astype(np.float32) - Ax.astype(np.float32)).astype(np.float64)
+        else:
+            z = b - A.matvec(x)
+        beta = float(np.linalg.norm(z))
+        rel = beta / bn
+        hist.append(rel)
+        if rel <= tol:
+            status = CONVERGED
+            break
+        if not math.isfinite(beta):
+            status = STALLED
+            break
+        if total >= max_iters:
+            status = MAXITER
+            break
+        # outer stall: a cycle that does not lower beta at all, several times running
+        if beta >= best_beta:
+            no_progress += 1
+        else:
+            no_progress = 0
+        best_beta = min(best_beta, beta)
+        if no_progress >= stall_cycles:
+            status = STALLED
+            break
+        # fallback of the flexible solver: a cycle gaining less than 1.001x
+        if use_pc and fallback and beta > prev_beta / 1.001:
+            use_pc = False
+            fallback_used = True
+        prev_beta = beta
+
+        V = [None] * (m + 1)  # stored basis entries (float32 / float64)
+        scale = np.zeros(m + 1)  # decode scale per vector
+        Z = [None] * m
+        H = np.zeros((m + 1, m))
+        Hbar = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        s = np.zeros(m + 1)
+        s[0] = beta  # s_1 = beta
+        if two_byte:
+            V[0], scale[0] = encode(z.astype(np.float32), 1.0 / beta, precision)
+        elif lowp:
+            V[0] = (z.astype(np.float32) * np.float32(1.0 / beta)).astype(np.float32)
+            scale[0] = 1.0
+        else:
+            V[0] = z / beta
+            scale[0] = 1.0
+
+        def basis(i):
+            if two_byte:
+                return (V[i] * np.float32(scale[i])).astype(np.float32)
+            return V[i]
+
+        k = 0
+        cycle_arn = []
+        for j in range(m):
+            vj = basis(j)
+            # w <- A v_j (flexible form: z_j = M v_j, w <- A z_j)
+            if use_pc:
+                Z[j] = _cast(precond(vj), precision)
+                src = Z[j]
+            else:
+                src = vj
+            w = A.matvec32(src) if lowp else A.matvec(src)
+            # orthogonalize(w, V_j)
+            hcol = np.zeros(j + 1)
+            if ortho == "mgs":
+                for i in range(j + 1):
+                    vi = basis(i)
+                    hij = float(np.dot(w, vi))
+                    hcol[i] = hij
+                    w = (w - (np.float32(hij) if lowp else hij) * vi).astype(w.dtype)
+            else:
+                Vj = np.stack([basis(i) for i in range(j + 1)], axis=1)
+                for _ in range(2):  # classical Gram-Schmidt, then its re-orthogonalisation pass
+                    hp = Vj.T @ w
+                    w = (w - Vj @ hp.astype(w.dtype)).astype(w.dtype)
+                    hcol += hp.astype(np.float64)
+            hnext = float(np.linalg.norm(w.astype(np.float64)))
+            H[: j + 1, j] = hcol
+            H[j + 1, j] = hnext
+            Hbar[: j + 2, j] = H[: j + 2, j]
+            total += 1
+            k = j + 1
+            # apply the previous rotations to the new column
+            for i in range(j):
+                a, c = H[i, j], H[i + 1, j]
+                H[i, j] = cs[i] * a + sn[i] * c
+                H[i + 1, j] = -sn[i] * a + cs[i] * c
+            # form rotation j and update (s_j, s_{j+1}) and (h_jj, h_{j+1,j})
+            cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+            s[j + 1] = -sn[j] * s[j]
+            s[j] = cs[j] * s[j]
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            cycle_arn.append(abs(s[j + 1]) / bn)
+            if hnext == 0.0 or not math.isfinite(hnext):
+                if not math.isfinite(hnext):
+                    k = j  # drop the non-finite column
+                break
+            if two_byte:
+                V[j + 1], scale[j + 1] = encode(w.astype(np.float32), 1.0 / hnext, precision)
+            elif lowp:
+                V[j + 1] = (w * np.float32(1.0 / hnext)).astype(np.float32)
+                scale[j + 1] = 1.0
+            else:
+                V[j + 1] = w / hnext
+                scale[j + 1] = 1.0
+            if abs(s[j + 1]) / bn <= tol or total >= max_iters:
+                break
+            if restart_improve > 0.0 and abs(s[j + 1]) <= restart_improve * beta:
+                break
+        # correction u = V_j H^-1 s (Z y in the flexible form), applied in full precision
+        y, kk = back_solve(H, s, k, U32 if lowp else U64)
+        u = np.zeros(n)
+        for i in range(kk):
+            src = Z[i] if use_pc else basis(i)
+            u += y[i] * src.astype(np.float64)
+        if update_fp32:
+            x = (x.astype(np.float32) + u.astype(np.float32)).astype(np.float64)
+        else:
+            x = x + u
+        restarts += 1
+        arn.append(cycle_arn)
+        if record:
+            cyc.append({"V": [basis(i).astype(np.float64) for i in range(k + 1) if V[i] is not None],
+                        "Hbar": Hbar[: k + 1, :k].copy(), "H": H[:k, :k].copy(), "s": s[: k + 1].copy(),
+                        "k": k, "beta": beta, "y": y, "cs": cs[:k].copy(), "sn": sn[:k].copy()})
+    return Result(x, status, total, restarts, hist[-1], hist, arn, cyc, fallback_used)
+
+
+def relative_residual(A: Matrix, b, x) -> float:
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(b - A.matvec(x)) / np.linalg.norm(b))
+
+
+def backward_error(A: Matrix, b, x) -> float:
+    """||r|| / (||A||_F ||x|| + ||b||): normwise backward error with ||A||_F for ||A||_2."""
+    r = np.asarray(b) - A.matvec(x)
+    return float(np.linalg.norm(r) / (np.linalg.norm(A.vals) * np.linalg.norm(x) + np.linalg.norm(b)))

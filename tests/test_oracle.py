@@ -1,0 +1,344 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by the mathematics.
+
+None of these tests re-types the oracle's own formulas: each compares it with
+a hand-worked example, a closed form, a textbook invariant, a library routine
+or brute force, chosen so that a dropped term, a wrong sign, a wrong index or
+a transposed operand in the oracle fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import problems as P
+from oracle import gmres as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _mat(A):
+    return O.Matrix.from_csr(A)
+
+
+def _load_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
+# --------------------------------------------------------------------------
+# hand-worked example (Algorithm 1 on a 2x2 system)
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_golden_2x2_worked_example(ortho):
+    g = _load_golden("gmres_2x2_worked.txt")
+    A = _mat(P.dense_to_csr(np.array([[2.0, 1.0], [0.0, 3.0]])))
+    r = O.gmres(A, np.array([0.0, 1.0]), m=2, tol=1e-15, ortho=ortho, record=True)
+    assert r.iters == int(g["iters"]) and r.restarts == 1
+    c = r.cycles[0]
+    Hb = c["Hbar"]
+    assert Hb[0, 0] == g["hbar_11"] and Hb[1, 0] == g["hbar_21"]
+    assert abs(Hb[0, 1] - g["hbar_12"]) < 1e-15 and abs(Hb[1, 1] - g["hbar_22"]) < 1e-15
+    assert abs(Hb[2, 1] - g["hbar_32"]) < 1e-15
+    assert math.isclose(c["cs"][0], g["alpha_1"], rel_tol=1e-15)
+    assert math.isclose(c["sn"][0], g["beta_1"], rel_tol=1e-15)
+    assert c["cs"][1] == g["alpha_2"] and c["sn"][1] == g["beta_2"]
+    assert math.isclose(r.arnoldi[0][0], g["s_after_1"], rel_tol=1e-15)
+    assert abs(r.arnoldi[0][1] - g["s_after_2"]) < 1e-15
+    assert np.allclose(c["y"], [g["y_1"], g["y_2"]], rtol=1e-15, atol=1e-16)
+    assert np.allclose(r.x, [g["x_1"], g["x_2"]], rtol=1e-15, atol=1e-16)
+
+
+# --------------------------------------------------------------------------
+# building blocks against library routines / brute force
+
+def test_csr_matvec_integer_exact_vs_dense():
+    g = np.random.default_rng(1)
+    D = g.integers(-5, 6, size=(37, 37)).astype(float)
+    D[g.random((37, 37)) < 0.6] = 0.0
+    D[5, :] = 0.0  # an empty row
+    A = _mat(P.dense_to_csr(D))
+    x = g.integers(-7, 8, size=37).astype(float)
+    assert np.array_equal(A.matvec(x), D @ x)
+    assert np.array_equal(A.matvec32(x.astype(np.float32)), (D @ x).astype(np.float32))
+
+
+def test_givens_zeroes_subdiagonal():
+    g = np.random.default_rng(2)
+    for a, b in list(g.standard_normal((50, 2))) + [(0.0, 1.0), (3.0, 0.0), (-2.0, 0.0), (0.0, 0.0)]:
+        b = abs(b)
+        c, s = O.givens(a, b)
+        assert abs(c * c + s * s - 1.0) < 1e-15
+        top = c * a + s * b
+        bot = -s * a + c * b
+        assert abs(bot) <= 1e-15 * max(1.0, abs(a), b)
+        if b != 0.0:
+            assert math.isclose(top, math.hypot(a, b), rel_tol=1e-15)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    g = np.random.default_rng(3)
+    x = (g.standard_normal(20000) * 10.0 ** g.integers(-8, 8, 20000)).astype(np.float32)
+    # exact ties: low 16 bits = 0x8000, both parities of the kept lsb
+    ties = (np.array([0x3F808000, 0x3F818000, 0xBF808000, 0x40490000 | 0x8000], dtype=np.uint32)
+            .view(np.float32))
+    x = np.concatenate([x, ties])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(O.round_bf16(x), ref)
+    # ties go to even: 1 + 2^-8 (halfway between 1 and 1 + 2^-7) rounds to 1
+    assert O.round_bf16(np.float32(1.0 + 2.0 ** -8)) == np.float32(1.0)
+    assert O.round_bf16(np.float32(1.0 + 3 * 2.0 ** -8)) == np.float32(1.0 + 2.0 ** -6)
+
+
+def test_fp16_rounding_ties_to_even():
+    assert O.round_fp16(np.float32(1.0 + 2.0 ** -11)) == np.float32(1.0)
+    assert O.round_fp16(np.float32(1.0 + 3 * 2.0 ** -11)) == np.float32(1.0 + 2.0 ** -9)
+    assert O.round_fp16(np.float32(32768.0 * (1 + 2.0 ** -20))) == np.float32(32768.0)
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+def test_encode_scale_range_and_exact_decode(fmt):
+    g = np.random.default_rng(4)
+    T = 2.0 ** O.FMT_TARGET_LOG2[fmt]
+    for mag in [1e-30, 1e-6, 0.3, 1.0, 7.0, 2.0 ** 10, 1e20]:
+        w = (g.standard_normal(1000) * mag).astype(np.float32)
+        h = float(np.linalg.norm(w.astype(np.float64)))
+        st, sc = O.encode(w, 1.0 / h, fmt)
+        mx = float(np.max(np.abs(st)))
+        assert T / 2 * (1 - 2 ** -10) < mx <= T
+        # decode is a power-of-two scaling: exact
+        dec = st.astype(np.float64) * sc
+        assert np.array_equal(dec, (st * np.float32(sc)).astype(np.float64))
+        rel = np.linalg.norm(dec - w / h) / np.linalg.norm(w / h)
+        assert rel < (2 ** -8 if fmt == "bf16" else 2 ** -11)
+    # power of two exactly at the boundary
+    assert O.scale_exponent(1.0, fmt) == O.FMT_TARGET_LOG2[fmt]
+    assert O.scale_exponent(0.75, fmt) == O.FMT_TARGET_LOG2[fmt]
+
+
+def test_stall_point_definition():
+    # 5% of m = 40 is 2 inner steps: steady 10x gains, then flat after 7 steps
+    seq = [10.0 ** -j for j in range(8)] + [1e-7 * (1 - 1e-5 * i) for i in range(1, 6)]
+    assert O.stall_window(40) == 2
+    assert O.stall_point(seq, 40) == 7
+    assert O.stall_point([1.0, 0.5, 0.25, 0.1], 40) is None
+    assert O.stall_window(10) == 1
+
+
+# --------------------------------------------------------------------------
+# Arnoldi process: relation, orthogonality, least-squares residual
+
+def _one_cycle(A, b, m, ortho):
+    return O.gmres(A, b, m=m, tol=0.0, max_iters=m, ortho=ortho, record=True).cycles[0]
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_arnoldi_relation(ortho):
+    Ac = P.random_dense_nonsym(80, 1, shift=2.0)
+    A = _mat(Ac)
+    D = A.dense()
+    b = np.random.default_rng(5).standard_normal(80)
+    c = _one_cycle(A, b, 30, ortho)
+    k = c["k"]
+    V = np.stack(c["V"], 1)
+    lhs = D @ V[:, :k] - V[:, : k + 1] @ c["Hbar"]
+    assert np.linalg.norm(lhs) <= 10 * k * O.U64 * np.linalg.norm(D)
+
+
+def test_cgs2_orthogonality_and_mgs_loss():
+    # a convection-diffusion Krylov basis is ill-conditioned: one classical pass
+    # loses orthogonality to about 1e-11 here, the re-orthogonalised pair keeps it at u
+    A = _mat(P.convdiff(32, (20.0, 10.0)))
+    b = np.random.default_rng(6).standard_normal(A.n)
+    out = {}
+    for ortho in ("cgsr", "mgs"):
+        c = _one_cycle(A, b, 60, ortho)
+        V = np.stack(c["V"], 1)
+        out[ortho] = np.linalg.norm(np.eye(V.shape[1]) - V.T @ V, 2)
+    assert out["cgsr"] <= 10 * 60 * O.U64
+    # MGS loses orthogonality in proportion to the conditioning of the basis
+    assert out["cgsr"] < out["mgs"] < 1e-8
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_arnoldi_residual_is_least_squares_minimum(ortho):
+    Ac = P.random_dense_nonsym(60, 3, shift=1.0)
+    A = _mat(Ac)
+    b = np.random.default_rng(7).standard_normal(60)
+    m = 25
+    r = O.gmres(A, b, m=m, tol=0.0, max_iters=m, ortho=ortho, record=True)
+    c = r.cycles[0]
+    beta = c["beta"]
+    bn = np.linalg.norm(b)
+    for j in range(1, c["k"] + 1):
+        Hj = c["Hbar"][: j + 1, :j]
+        rhs = np.zeros(j + 1)
+        rhs[0] = beta
+        y, *_ = np.linalg.lstsq(Hj, rhs, rcond=None)
+        ls = np.linalg.norm(rhs - Hj @ y)
+        assert abs(r.arnoldi[0][j - 1] * bn - ls) <= 1e-12 * beta
+    # closed form after the first step: |s_2| = beta h21 / hypot(h11, h21)
+    h11, h21 = c["Hbar"][0, 0], c["Hbar"][1, 0]
+    assert math.isclose(r.arnoldi[0][0] * bn, beta * h21 / math.hypot(h11, h21), rel_tol=1e-13)
+    # monotone non-increasing inside the cycle
+    seq = [beta / bn] + r.arnoldi[0]
+    assert all(seq[i + 1] <= seq[i] * (1 + 1e-14) for i in range(len(seq) - 1))
+    # the Arnoldi residual predicts the true residual of the cycle's x (exact arithmetic up to u)
+    assert math.isclose(np.linalg.norm(b - A.matvec(r.x)) / bn, r.arnoldi[0][-1], rel_tol=1e-6)
+
+
+# --------------------------------------------------------------------------
+# whole solver
+
+def test_finite_termination_distinct_eigenvalues():
+    n, kdist = 48, 6
+    g = np.random.default_rng(8)
+    Q = np.eye(n) + 0.3 * g.standard_normal((n, n)) / np.sqrt(n)
+    lam = np.repeat(np.arange(1.0, kdist + 1.0), n // kdist)
+    D = Q @ np.diag(lam) @ np.linalg.inv(Q)
+    A = _mat(P.dense_to_csr(D))
+    b = g.standard_normal(n)
+    for ortho in ("mgs", "cgsr"):
+        r = O.gmres(A, b, m=20, tol=1e-11, ortho=ortho)
+        assert r.status == O.CONVERGED
+        assert r.iters == kdist
+        assert np.allclose(D @ r.x, b, atol=1e-9)
+
+
+def test_random_small_systems_converge_within_n_steps():
+    for seed in range(4):
+        n = 16 + 4 * seed
+        Ac = P.random_dense_nonsym(n, 10 + seed, shift=0.0)
+        A = _mat(Ac)
+        b = np.random.default_rng(seed).standard_normal(n)
+        r = O.gmres(A, b, m=n, tol=1e-11, ortho="cgsr")
+        assert r.status == O.CONVERGED and r.iters <= n
+
+
+def test_identity_and_scaled_identity():
+    n = 50
+    b = np.random.default_rng(9).standard_normal(n)
+    I = _mat(P.dense_to_csr(np.eye(n)))
+    r = O.gmres(I, b, m=10, tol=1e-14)
+    assert r.iters == 1 and np.allclose(r.x, b, rtol=8 * O.U64, atol=0)
+    S = _mat(P.dense_to_csr(3.0 * np.eye(n)))
+    r = O.gmres(S, b, m=10, tol=1e-14)
+    assert r.iters == 1 and np.allclose(r.x, b / 3.0, rtol=8 * O.U64, atol=0)
+
+
+def test_zero_rhs_returns_zero_without_iterating():
+    A = _mat(P.convdiff(8, (1.0, 1.0)))
+    r = O.gmres(A, np.zeros(64), x0=np.ones(64), m=10, tol=1e-10)
+    assert r.iters == 0 and r.status == O.CONVERGED and not r.x.any()
+
+
+def test_singular_matrix_stops_without_nan():
+    D = np.diag([1.0, 2.0, 3.0, 0.0, 5.0])
+    A = _mat(P.dense_to_csr(D))
+    b = np.ones(5)
+    r = O.gmres(A, b, m=5, tol=1e-12, max_iters=200)
+    assert r.status in (O.MAXITER, O.STALLED)
+    assert np.all(np.isfinite(r.x))
+    # no correction can remove the component of b along the null space
+    assert min(r.history) >= (1.0 - 1e-9) / math.sqrt(5.0)
+    # the first cycle reaches that floor: the Krylov space is invariant after 5 steps
+    assert math.isclose(r.history[1], 1.0 / math.sqrt(5.0), rel_tol=1e-6)
+
+
+def test_dense_lu_agrees_on_c1():
+    pr = P.c1_convdiff2d()
+    A = _mat(pr.A)
+    D = A.dense()
+    x_lu = np.linalg.solve(D, pr.b)
+    r = O.gmres(A, pr.b, m=pr.m, tol=1e-12, ortho="mgs")
+    assert r.status == O.CONVERGED
+    kappa = np.linalg.cond(D, 1)
+    err = np.linalg.norm(r.x - x_lu) / np.linalg.norm(x_lu)
+    assert err <= kappa * 1e-12
+    assert np.linalg.norm(x_lu - pr.x_true) / np.linalg.norm(pr.x_true) <= kappa * 1e-15
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_power_of_two_scaling_is_bitwise_invariant(ortho, precision):
+    pr = P.c1_convdiff2d(24)
+    A = _mat(pr.A)
+    r0 = O.gmres(A, pr.b, m=20, tol=1e-10, ortho=ortho, precision=precision)
+    As = _mat(pr.A.scaled(2.0 ** 7))
+    r1 = O.gmres(As, pr.b * 2.0 ** 7, m=20, tol=1e-10, ortho=ortho, precision=precision)
+    assert r0.iters == r1.iters and r0.restarts == r1.restarts
+    assert np.array_equal(r0.x, r1.x)
+
+
+def test_restart_residuals_never_increase():
+    pr = P.c1_convdiff2d(32)
+    A = _mat(pr.A)
+    r = O.gmres(A, pr.b, m=8, tol=1e-10, ortho="mgs")
+    assert r.status == O.CONVERGED and r.restarts > 5
+    h = r.history
+    assert all(h[i + 1] <= h[i] for i in range(len(h) - 1))
+
+
+# --------------------------------------------------------------------------
+# mixed precision: the claims of the numerics section and section 4.1
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_mixed_reaches_double_accuracy_after_restarts(ortho):
+    pr = P.c1_convdiff2d(32)
+    A = _mat(pr.A)
+    r64 = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho)
+    r32 = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho, precision="fp32")
+    assert r32.status == O.CONVERGED and r32.rel_residual <= 1e-10
+    assert r32.restarts >= 2
+    # with restarts forced well before the FP32 stall, counts match FP64 closely
+    assert abs(r32.iters - r64.iters) <= 30
+
+
+@pytest.mark.parametrize("flag", ["residual_fp32", "update_fp32"])
+def test_negative_control_reduced_precision_residual_or_update_stalls(flag):
+    pr = P.c1_convdiff2d(32)
+    A = _mat(pr.A)
+    r = O.gmres(A, pr.b, m=30, tol=1e-10, ortho="mgs", max_iters=1500, **{flag: True})
+    assert r.status != O.CONVERGED
+    assert min(r.history) > 1e-9
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_two_byte_basis_still_reaches_double_accuracy(fmt):
+    pr = P.c1_convdiff2d(24)
+    A = _mat(pr.A)
+    r = O.gmres(A, pr.b, m=20, tol=1e-10, ortho="cgsr", precision=fmt, max_iters=4000)
+    assert r.status == O.CONVERGED
+
+
+# --------------------------------------------------------------------------
+# flexible (right-preconditioned) form
+
+def test_fgmres_with_identity_is_plain_gmres_bitwise():
+    pr = P.c1_convdiff2d(20)
+    A = _mat(pr.A)
+    r0 = O.gmres(A, pr.b, m=15, tol=1e-10)
+    r1 = O.gmres(A, pr.b, m=15, tol=1e-10, precond=lambda v: v.copy())
+    assert r0.iters == r1.iters and np.array_equal(r0.x, r1.x)
+
+
+def test_fgmres_with_jacobi_equals_right_preconditioned_gmres():
+    A0 = P.varcoef3d(10, family=90, index=1)
+    A = _mat(A0)
+    d = A.diagonal()
+    xt = np.random.default_rng(11).uniform(-1, 1, A.n)
+    b = A.matvec(xt)
+    r1 = O.gmres(A, b, m=20, tol=1e-11, precond=lambda v: v / d, fallback=False)
+    # explicit right preconditioning: solve (A D^-1) u = b, then x = D^-1 u
+    AD = O.Matrix(A0.row_ptr, A0.col_idx, A0.vals / d[A0.col_idx], A.n)
+    r2 = O.gmres(AD, b, m=20, tol=1e-11)
+    assert r1.iters == r2.iters and r1.restarts == r2.restarts
+    assert np.linalg.norm(r1.x - r2.x / d) <= 1e-9 * np.linalg.norm(r1.x)

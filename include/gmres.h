@@ -1,0 +1,192 @@
+/*
+ * libgmres: restarted GMRES(m) for sparse non-symmetric systems on gfx950.
+ *
+ * Method: Lindquist, Luszczek, Dongarra, "Improving the Performance of the
+ * GMRES Method using Mixed-Precision Techniques" (arXiv 2011.01850).
+ * Algorithm 1 (restarted GMRES, MGS or CGSR orthogonalisation) runs with the
+ * precision split of the paper's numerics section: the restart residual
+ * z = b - A x and the update x += u are float64, the Arnoldi process
+ * (SpMV, orthogonalisation, normalisation) runs in float32, or stores its
+ * basis in bfloat16 / IEEE half with a per-vector power-of-two scale.  The
+ * Hessenberg matrix, its Givens rotations and the back-solve are float64.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers unless stated otherwise
+ *    (e.g. torch tensors on the current HIP device).  Options and results
+ *    are host structs.
+ *  - CSR: row_ptr int32[n+1] (row_ptr[0] = 0, non-decreasing), col_idx
+ *    int32[nnz] in [0, n), values float64[nnz].  Column order inside a row
+ *    is free; duplicates are summed.
+ *  - Return value: GMRES_OK (0) or a negative error code (gmres_strerror).
+ *    Not converging is not an error: gmres_solve returns GMRES_OK and
+ *    reports the outcome in gmres_result.status.
+ *  - All device work is enqueued on the handle's stream; calls that return
+ *    results to the host synchronise that stream.  A handle must be used by
+ *    one host thread at a time.
+ */
+#ifndef GMRES_H_
+#define GMRES_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmres_ctx* gmres_handle;
+
+/* orthogonalisation of Algorithm 1: modified Gram-Schmidt, or classical
+ * Gram-Schmidt with one full re-orthogonalisation pass (two projections,
+ * coefficients summed). */
+enum { GMRES_MGS = 0, GMRES_CGSR = 1 };
+
+/* precision of the Arnoldi process (numerics section; 2-byte formats follow
+ * the half-precision direction of the conclusion).  The residual, the update,
+ * H, the rotations and the back-solve are float64 in every mode. */
+enum {
+  GMRES_FP64 = 0,       /* everything float64 (the baseline) */
+  GMRES_MIXED_FP32 = 1, /* float32 A copy, basis, w and dot products */
+  GMRES_MIXED_BF16 = 2, /* float32 arithmetic, basis stored as bfloat16 */
+  GMRES_MIXED_FP16 = 3  /* float32 arithmetic, basis stored as IEEE half */
+};
+
+/* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y) */
+enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2 };
+
+/* gmres_result.status */
+enum { GMRES_RUNNING = 0, GMRES_CONVERGED = 1, GMRES_MAXITER = 2, GMRES_STALLED = 3 };
+
+/* error codes */
+enum {
+  GMRES_OK = 0,
+  GMRES_EINVAL = -1,  /* invalid argument: n <= 0, m < 1 or m > 256, tol < 0, bad CSR, NULL pointer */
+  GMRES_EHIP = -2,    /* a HIP runtime call failed */
+  GMRES_ENOMEM = -3,  /* device allocation failed */
+  GMRES_EHANDLE = -4, /* NULL or destroyed handle */
+  GMRES_ESTATE = -5   /* call not valid for this handle (e.g. SPAI values on a handle created without SPAI) */
+};
+
+typedef struct {
+  int32_t m;                /* restart length, 1..256 */
+  double tol;               /* stop when ||b - A x||_2 / ||b||_2 <= tol (float64 residual) */
+  int64_t max_iters;        /* budget of inner (Arnoldi) iterations over all cycles */
+  int32_t ortho;            /* GMRES_MGS or GMRES_CGSR */
+  int32_t precision;        /* GMRES_FP64 ... GMRES_MIXED_FP16 */
+  int32_t precond;          /* GMRES_PRECOND_* */
+  double restart_improve;   /* 0 = off; else end a cycle once |s_{j+1}| <= restart_improve * beta
+                               (the improvement trigger of the restart-strategy study) */
+  int32_t stall_cycles;     /* STALLED after this many cycles in a row that do not lower beta */
+  int32_t use_graph;        /* 1: capture one restart cycle as a hipGraph and replay it */
+  int32_t autotune;         /* 1: time SpMV tile variants at create time and keep the fastest */
+} gmres_options;
+
+typedef struct {
+  int32_t status;        /* GMRES_CONVERGED / MAXITER / STALLED */
+  int64_t iters;         /* inner Arnoldi iterations, summed over cycles */
+  int64_t restarts;      /* completed cycles (corrections applied) */
+  double rel_residual;   /* ||b - A x||_2 / ||b||_2 in float64, at exit */
+  double seconds;        /* wall time of the solve call (setup excluded) */
+  int32_t fallback_used; /* the preconditioner was switched off (stall or non-finite values) */
+  int32_t first_stall;   /* inner iterations before the Arnoldi residual stalled in the first
+                            cycle (improvement < 1.001x over the next 5% of m); -1 if none */
+} gmres_result;
+
+/* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
+ * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 3,
+ * use_graph = 1, autotune = 1. */
+void gmres_default_options(gmres_options* opt);
+
+/* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).
+ * Copies A into library storage (float64 values, a float32 copy for the
+ * mixed modes, shared indices, SpMV row blocks), allocates the workspace
+ * (basis of m+1 vectors, H, rotations, reductions) and, if requested, runs
+ * the SpMV autotuner.  The caller may free its CSR arrays afterwards.
+ * hip_stream: the hipStream_t to use (NULL = the null stream).
+ * Errors: EINVAL (n <= 0, nnz < 0, NULL pointers, bad options, bad CSR),
+ * ENOMEM, EHIP. */
+int gmres_create(gmres_handle* out, int64_t n, int64_t nnz, const int32_t* row_ptr,
+                 const int32_t* col_idx, const double* vals, const gmres_options* opt,
+                 void* hip_stream);
+
+/* Create one solver for nsys independent systems that are advanced
+ * together (the batch path): the k-th system is n[k] x n[k] with nnz[k]
+ * entries given by the k-th pointers of the (HOST) pointer arrays, which
+ * point to device memory.  Every kernel launch covers all systems; each
+ * system keeps its own Hessenberg matrix, rotations, restart and stop
+ * decisions, so its iterates are exactly those of a single-system solve. */
+int gmres_batch_create(gmres_handle* out, int32_t nsys, const int64_t* n, const int64_t* nnz,
+                       const int32_t* const* row_ptr, const int32_t* const* col_idx,
+                       const double* const* vals, const gmres_options* opt, void* hip_stream);
+
+/* Values of a sparse approximate inverse M on the sparsity pattern of A
+ * (float32, device, one value per stored entry of A in A's storage order,
+ * systems concatenated for a batch handle).  Used as z = M v in the
+ * flexible (right-preconditioned) solve.  Errors: ESTATE unless the handle
+ * was created with precond = GMRES_PRECOND_SPAI. */
+int gmres_set_preconditioner(gmres_handle h, const float* spai_vals);
+
+/* Solve A x = b.  b: float64[n], read only.  x: float64[n], in: x0, out:
+ * the final iterate.  b = 0 gives x = 0 with 0 iterations.  Synchronises
+ * the stream and fills *res (res may be NULL). */
+int gmres_solve(gmres_handle h, const double* b, double* x, gmres_result* res);
+
+/* Batch solve: b[k], x[k] are device pointers of system k (host arrays of
+ * nsys pointers); res is a host array of nsys results. */
+int gmres_batch_solve(gmres_handle h, const double* const* b, double* const* x, gmres_result* res);
+
+/* Free everything owned by the handle.  Safe on NULL. */
+int gmres_destroy(gmres_handle h);
+
+const char* gmres_strerror(int code);
+
+/* r = b - A x in float64 with the stored A (single-system handles or the
+ * concatenation of a batch), and *norm_out = ||r||_2 (host, may be NULL).
+ * r may be NULL when only the norm is wanted. */
+int gmres_residual(gmres_handle h, const double* b, const double* x, double* r, double* norm_out);
+
+/* y = A x with the stored float64 values (precision = GMRES_FP64, x and y
+ * float64) or the stored float32 copy (GMRES_MIXED_FP32, float32 x, y).
+ * The mixed copy exists only on mixed-precision handles (else ESTATE). */
+int gmres_spmv(gmres_handle h, int32_t precision, const void* x, void* y);
+
+/* Store v = w * inv_h in a 2-byte format (precision GMRES_MIXED_BF16 or
+ * GMRES_MIXED_FP16) exactly as the solver stores a basis vector: with
+ * e such that max|v| * 2^e lies in (T/2, T] (T = 1 for bfloat16, 2^15 for
+ * half), out = round_to_nearest_even(float32(w * float32(2^e * inv_h))), and
+ * *scale_out = 2^-e (host) so that v ~ out * scale.  w: float32[n] device;
+ * out: uint16[n] device.  Runs on hip_stream and synchronises it. */
+int gmres_encode(int32_t precision, int64_t n, const float* w, double inv_h, void* out,
+                 double* scale_out, void* hip_stream);
+
+/* After a solve, the last cycle of system sys: *k_out = number of Arnoldi
+ * steps, Hbar_out (HOST, float64, (m+1) x m column-major, may be NULL) =
+ * the unrotated Hessenberg matrix, V_out (DEVICE, float64, n x (k+1)
+ * column-major, may be NULL) = the decoded basis vectors (v_{k+1} only
+ * when it was formed).  For tests of the Arnoldi relation. */
+int gmres_last_cycle(gmres_handle h, int32_t sys, int32_t* k_out, double* Hbar_out, double* V_out);
+
+/* Float64 relative restart residuals of system sys (HOST out[cap]); *count
+ * = number recorded in the last solve (at most cap are copied). */
+int gmres_history(gmres_handle h, int32_t sys, double* out, int32_t cap, int32_t* count);
+
+/* Device bytes held by the handle (matrix copies, workspace, scratch). */
+int gmres_memory_bytes(gmres_handle h, size_t* bytes);
+
+/* Kernel timing harness for the roofline report: launches one hot-path
+ * kernel `reps` times at Arnoldi column j with the solver's own launch
+ * configuration, between HIP events on the handle's stream, and returns
+ * the mean duration in milliseconds (*avg_ms) and the algorithmic bytes
+ * one launch must move (*bytes).  The handle's solver state is clobbered
+ * (the next gmres_solve starts afresh).  kernel: 0 = Arnoldi SpMV,
+ * 1 = CGSR projection pass 1, 2 = CGSR projection pass 2, 3 = final
+ * update + norm pass, 4 = MGS dot step (column j), 5 = float64 residual,
+ * 6 = float64 solution update (j + 1 columns). */
+int gmres_time_kernel(gmres_handle h, int32_t kernel, int32_t j, int32_t reps, double* avg_ms,
+                      double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMRES_H_ */

@@ -1,0 +1,120 @@
+"""ctypes declarations of libgmres (include/gmres.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgmres.so")
+
+MGS, CGSR = 0, 1
+FP64, MIXED_FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_SPAI = 0, 1, 2
+RUNNING, CONVERGED, MAXITER, STALLED = 0, 1, 2, 3
+OK, EINVAL, EHIP, ENOMEM, EHANDLE, ESTATE = 0, -1, -2, -3, -4, -5
+
+STATUS_NAMES = {RUNNING: "RUNNING", CONVERGED: "CONVERGED", MAXITER: "MAXITER", STALLED: "STALLED"}
+PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
+ORTHOS = {"mgs": MGS, "cgsr": CGSR}
+PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "spai": PRECOND_SPAI}
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("m", C.c_int32),
+        ("tol", C.c_double),
+        ("max_iters", C.c_int64),
+        ("ortho", C.c_int32),
+        ("precision", C.c_int32),
+        ("precond", C.c_int32),
+        ("restart_improve", C.c_double),
+        ("stall_cycles", C.c_int32),
+        ("use_graph", C.c_int32),
+        ("autotune", C.c_int32),
+    ]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32),
+        ("iters", C.c_int64),
+        ("restarts", C.c_int64),
+        ("rel_residual", C.c_double),
+        ("seconds", C.c_double),
+        ("fallback_used", C.c_int32),
+        ("first_stall", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {
+            "status": STATUS_NAMES.get(self.status, str(self.status)),
+            "iters": int(self.iters),
+            "restarts": int(self.restarts),
+            "rel_residual": float(self.rel_residual),
+            "seconds": float(self.seconds),
+            "fallback_used": bool(self.fallback_used),
+            "first_stall": int(self.first_stall),
+        }
+
+
+_vp = C.c_void_p
+_SIGS = {
+    "gmres_default_options": (None, [C.POINTER(Options)]),
+    "gmres_strerror": (C.c_char_p, [C.c_int]),
+    "gmres_create": (C.c_int, [C.POINTER(_vp), C.c_int64, C.c_int64, _vp, _vp, _vp, C.POINTER(Options), _vp]),
+    "gmres_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(Options), _vp]),
+    "gmres_set_preconditioner": (C.c_int, [_vp, _vp]),
+    "gmres_solve": (C.c_int, [_vp, _vp, _vp, C.POINTER(Result)]),
+    "gmres_batch_solve": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(Result)]),
+    "gmres_destroy": (C.c_int, [_vp]),
+    "gmres_residual": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "gmres_spmv": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
+    "gmres_encode": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_double, _vp, C.POINTER(C.c_double), _vp]),
+    "gmres_last_cycle": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _vp, _vp]),
+    "gmres_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, C.POINTER(C.c_int32)]),
+    "gmres_memory_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "gmres_time_kernel": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
+}
+
+_LIB = None
+
+
+class GmresError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+def load(path: str | None = None):
+    """Load the built library (fails loudly when it has not been built)."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libgmres.so is not built ({p}); run `python -m paper_2011_01850_amd.build`")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().gmres_strerror(int(code)).decode()
+
+
+def check(code: int, what: str):
+    if code != OK:
+        raise GmresError(code, what)
+
+
+def default_options() -> Options:
+    o = Options()
+    load().gmres_default_options(C.byref(o))
+    return o

@@ -1,0 +1,771 @@
+// Host engine and C-ABI of libgmres: setup (matrix copies, row blocks,
+// autotuner, workspace), the restart-cycle schedule (direct launches or one
+// captured hipGraph per cycle) and the entry points declared in gmres.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "../../include/gmres.h"
+#include "gmres_internal.hpp"
+
+using namespace gm;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x474d5253u;  // "GMRS"
+
+struct Fail {
+  int code;
+};
+
+inline void hip_check(hipError_t e) {
+  if (e == hipErrorOutOfMemory) throw Fail{GMRES_ENOMEM};
+  if (e != hipSuccess) throw Fail{GMRES_EHIP};
+}
+
+struct System {
+  int64_t n = 0, nnz = 0;
+  int64_t row0 = 0;  // first global row
+  int64_t nz0 = 0;   // first global non-zero
+  int32_t nch = 0, ch0 = 0, nrb = 0, rb0 = 0;
+};
+
+}  // namespace
+
+struct gmres_ctx {
+  uint32_t magic = kMagic;
+  hipStream_t stream = nullptr;  // library-owned, default priority
+  gmres_options opt{};
+  std::vector<System> sys;
+  int64_t ld = 0, nnz = 0, nrows = 0;
+  int32_t nchunk = 0, nrb = 0;
+  std::vector<int32_t> rp_host;  // global row pointer (ld + 1)
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  KArgs a{};
+  // host mirror of per-system state
+  SysState* st_host = nullptr;  // pinned
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool spai_set = false;
+  // batch gather/scatter pointer tables (device)
+  const double** bptrs = nullptr;
+  double** xptrs = nullptr;
+  // staging for the plain SpMV / residual entry points (ld rows each)
+  double* xs = nullptr;
+  double* ys = nullptr;
+
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    const size_t nb = std::max<size_t>(count * sizeof(T), 256);
+    hipError_t e = hipMalloc(&p, nb);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Fail{GMRES_ENOMEM};
+    }
+    allocs.push_back(p);
+    bytes += nb;
+    return static_cast<T*>(p);
+  }
+
+  ~gmres_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (void* p : allocs) (void)hipFree(p);
+    if (st_host) (void)hipHostFree(st_host);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (stream) (void)hipStreamDestroy(stream);
+    magic = 0;
+  }
+};
+
+namespace {
+
+bool valid_options(const gmres_options* o) {
+  if (!o) return false;
+  if (o->m < 1 || o->m > kMaxM) return false;
+  if (!(o->tol >= 0.0)) return false;
+  if (o->max_iters < 0) return false;
+  if (o->ortho != GMRES_MGS && o->ortho != GMRES_CGSR) return false;
+  if (o->precision < GMRES_FP64 || o->precision > GMRES_MIXED_FP16) return false;
+  if (o->precond < GMRES_PRECOND_NONE || o->precond > GMRES_PRECOND_SPAI) return false;
+  if (o->precond != GMRES_PRECOND_NONE && o->precision == GMRES_FP64) return false;
+  if (!(o->restart_improve >= 0.0)) return false;
+  if (o->stall_cycles < 1) return false;
+  return true;
+}
+
+// Adaptive-CSR row blocks over global rows [r_begin, r_end): up to kBlock
+// rows whose non-zeros fit `budget`, or a single longer row.
+void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r_end, int budget,
+                      std::vector<int32_t>& rb) {
+  int64_t r = r_begin;
+  while (r < r_end) {
+    rb.push_back((int32_t)r);
+    int64_t nz = 0, rows = 0;
+    while (r < r_end && rows < kBlock) {
+      const int64_t len = (int64_t)rp[r + 1] - rp[r];
+      if (rows > 0 && nz + len > budget) break;
+      nz += len;
+      ++rows;
+      ++r;
+      if (nz > budget) break;
+    }
+  }
+}
+
+void set_row_blocks(gmres_ctx* h, int budget) {
+  std::vector<int32_t> rb, rb_sys;
+  for (size_t k = 0; k < h->sys.size(); ++k) {
+    System& s = h->sys[k];
+    const size_t before = rb.size();
+    build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, budget, rb);
+    s.rb0 = (int32_t)before;
+    s.nrb = (int32_t)(rb.size() - before);
+    rb_sys.insert(rb_sys.end(), rb.size() - before, (int32_t)k);
+  }
+  rb.push_back((int32_t)h->ld);  // sentinel; no block starts in the padding
+  // the last block of each system must end at that system's last real row:
+  // pad rows are empty, so ending at the next block start (or ld) is exact.
+  h->nrb = (int32_t)rb_sys.size();
+  int32_t* d_rb = h->alloc<int32_t>(rb.size());
+  int32_t* d_rbs = h->alloc<int32_t>(std::max<size_t>(rb_sys.size(), 1));
+  hip_check(hipMemcpy(d_rb, rb.data(), rb.size() * 4, hipMemcpyHostToDevice));
+  if (!rb_sys.empty()) hip_check(hipMemcpy(d_rbs, rb_sys.data(), rb_sys.size() * 4, hipMemcpyHostToDevice));
+  std::vector<int32_t> rb0(h->sys.size()), nrb(h->sys.size());
+  for (size_t k = 0; k < h->sys.size(); ++k) {
+    rb0[k] = h->sys[k].rb0;
+    nrb[k] = h->sys[k].nrb;
+  }
+  int32_t* d_rb0 = h->alloc<int32_t>(rb0.size());
+  int32_t* d_nrb = h->alloc<int32_t>(nrb.size());
+  hip_check(hipMemcpy(d_rb0, rb0.data(), rb0.size() * 4, hipMemcpyHostToDevice));
+  hip_check(hipMemcpy(d_nrb, nrb.data(), nrb.size() * 4, hipMemcpyHostToDevice));
+  h->a.rb = d_rb;
+  h->a.rb_sys = d_rbs;
+  h->a.sys_rb0 = d_rb0;
+  h->a.sys_nrb = d_nrb;
+  h->a.nrb = h->nrb;
+  h->a.spmv_budget = budget;
+}
+
+int64_t vbytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+int64_t wbytes(int prec) { return prec == P64 ? 8 : 4; }
+
+// Enqueue one restart cycle: residual and stop test, m Arnoldi steps,
+// back-solve and update.  Every kernel is gated on the device.
+hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
+  const KArgs& a = h->a;
+  const bool two = a.prec == PBF16 || a.prec == PF16;
+  hipError_t e = launch_residual(a, st);
+  if (e == hipSuccess && two) e = launch_encode(a, 0, st);
+  for (int j = 0; j < a.m && e == hipSuccess; ++j) {
+    if (a.precond != 0) e = launch_precond(a, j, st);
+    if (e == hipSuccess) e = launch_spmv_arnoldi(a, j, st);
+    if (e != hipSuccess) break;
+    if (h->opt.ortho == GMRES_CGSR) {
+      e = launch_cgs_pass1(a, j, st);
+      if (e == hipSuccess) e = launch_cgs_pass2(a, j, st);
+      if (e == hipSuccess) e = launch_final_pass(a, j, 0, st);
+    } else {
+      for (int i = 0; i <= j && e == hipSuccess; ++i) e = launch_mgs_dot(a, j, i, st);
+      if (e == hipSuccess) e = launch_final_pass(a, j, j, st);
+    }
+    if (e == hipSuccess && two && j + 1 <= a.m) e = launch_encode(a, j + 1, st);
+  }
+  if (e == hipSuccess) e = launch_backsolve(a, st);
+  if (e == hipSuccess) e = launch_update(a, st);
+  return e;
+}
+
+void build_graph(gmres_ctx* h) {
+  if (h->gexec) return;
+  hipGraph_t g = nullptr;
+  hip_check(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_cycle(h, h->stream);
+  hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    throw Fail{GMRES_EHIP};
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  hip_check(e);
+  h->gexec = ex;
+}
+
+// Times the Arnoldi SpMV for a few row-block budgets and keeps the fastest.
+void autotune_spmv(gmres_ctx* h) {
+  const int cands[] = {1024, 2048, 4096};
+  float best = 1e30f;
+  int best_budget = h->a.spmv_budget, best_remap = h->a.xcd_remap;
+  // exercise with a column of the zero-initialised basis; force the kernel on
+  hip_check(launch_set_force(h->a, 1, h->stream));
+  const int reps = 5;
+  for (int budget : cands) {
+    set_row_blocks(h, budget);
+    for (int remap = 0; remap <= 1; ++remap) {
+      h->a.xcd_remap = remap;
+      hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));  // warm
+      hip_check(hipEventRecord(h->ev0, h->stream));
+      for (int r = 0; r < reps; ++r) hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));
+      hip_check(hipEventRecord(h->ev1, h->stream));
+      hip_check(hipEventSynchronize(h->ev1));
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      if (ms < best) {
+        best = ms;
+        best_budget = budget;
+        best_remap = remap;
+      }
+    }
+  }
+  hip_check(launch_set_force(h->a, 0, h->stream));
+  set_row_blocks(h, best_budget);
+  h->a.xcd_remap = best_remap;
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
+void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, const int32_t* const* rp,
+           const int32_t* const* ci, const double* const* vals, const gmres_options* opt, void* user_stream) {
+  (void)user_stream;
+  h->opt = *opt;
+  hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  hip_check(hipEventCreate(&h->ev0));
+  hip_check(hipEventCreate(&h->ev1));
+  const int m = opt->m;
+  const int prec = opt->precision;
+  h->sys.resize(nsys);
+  int64_t row = 0, nz = 0, ch = 0;
+  for (int k = 0; k < nsys; ++k) {
+    System& s = h->sys[k];
+    s.n = n[k];
+    s.nnz = nnz[k];
+    s.row0 = row;
+    s.nz0 = nz;
+    s.ch0 = (int32_t)ch;
+    s.nch = (int32_t)((s.n + kChunk - 1) / kChunk);
+    row += (int64_t)s.nch * kChunk;
+    nz += s.nnz;
+    ch += s.nch;
+    h->nrows += s.n;
+  }
+  if (row >= (int64_t)INT32_MAX || nz >= (int64_t)INT32_MAX) throw Fail{GMRES_EINVAL};
+  h->ld = row;
+  h->nnz = nz;
+  h->nchunk = (int32_t)ch;
+
+  // ---- global CSR (rows of padding are empty; columns shifted per system)
+  h->rp_host.assign(h->ld + 1, 0);
+  std::vector<int32_t> tmp;
+  for (int k = 0; k < nsys; ++k) {
+    const System& s = h->sys[k];
+    tmp.resize(s.n + 1);
+    hip_check(hipMemcpy(tmp.data(), rp[k], (s.n + 1) * 4, hipMemcpyDeviceToHost));
+    if (tmp[0] != 0 || tmp[s.n] != s.nnz) throw Fail{GMRES_EINVAL};
+    for (int64_t i = 0; i < s.n; ++i) {
+      if (tmp[i + 1] < tmp[i]) throw Fail{GMRES_EINVAL};
+      h->rp_host[s.row0 + i] = (int32_t)(s.nz0 + tmp[i]);
+    }
+    const int64_t end = s.row0 + (int64_t)s.nch * kChunk;
+    for (int64_t i = s.row0 + s.n; i <= end; ++i) h->rp_host[i] = (int32_t)(s.nz0 + s.nnz);
+  }
+  KArgs& a = h->a;
+  a.S = nsys;
+  a.m = m;
+  a.ld = h->ld;
+  a.nchunk = h->nchunk;
+  a.ps = m + 3;
+  a.prec = prec;
+  a.precond = opt->precond;
+  a.xcd_remap = 1;
+  int32_t* d_rp = h->alloc<int32_t>(h->ld + 1);
+  hip_check(hipMemcpy(d_rp, h->rp_host.data(), (h->ld + 1) * 4, hipMemcpyHostToDevice));
+  int32_t* d_ci = h->alloc<int32_t>(h->nnz);
+  double* d_a64 = h->alloc<double>(h->nnz);
+  for (int k = 0; k < nsys; ++k) {
+    const System& s = h->sys[k];
+    if (s.nnz == 0) continue;
+    hip_check(launch_shift_cols(ci[k], d_ci + s.nz0, s.nnz, (int32_t)s.row0, h->stream));
+    hip_check(hipMemcpyAsync(d_a64 + s.nz0, vals[k], s.nnz * 8, hipMemcpyDeviceToDevice, h->stream));
+  }
+  a.rp = d_rp;
+  a.ci = d_ci;
+  a.a64 = d_a64;
+  if (prec != P64) {
+    float* d_a32 = h->alloc<float>(h->nnz);
+    hip_check(launch_convert_f32(d_a64, d_a32, h->nnz, h->stream));
+    a.a32 = d_a32;
+  }
+  // ---- per-system tables
+  std::vector<int32_t> ch_sys(h->nchunk), ch0(nsys), nch(nsys), sn(nsys);
+  std::vector<int64_t> row0(nsys);
+  for (int k = 0; k < nsys; ++k) {
+    const System& s = h->sys[k];
+    for (int c = 0; c < s.nch; ++c) ch_sys[s.ch0 + c] = k;
+    ch0[k] = s.ch0;
+    nch[k] = s.nch;
+    sn[k] = (int32_t)s.n;
+    row0[k] = s.row0;
+  }
+  auto up32 = [&](const std::vector<int32_t>& v) {
+    int32_t* d = h->alloc<int32_t>(v.size());
+    hip_check(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    return d;
+  };
+  a.ch_sys = up32(ch_sys);
+  a.sys_ch0 = up32(ch0);
+  a.sys_nch = up32(nch);
+  a.sys_n = up32(sn);
+  {
+    int64_t* d = h->alloc<int64_t>(nsys);
+    hip_check(hipMemcpy(d, row0.data(), nsys * 8, hipMemcpyHostToDevice));
+    a.sys_row0 = d;
+  }
+  // ---- workspace
+  const int64_t M1 = m + 1, M2 = m + 2;
+  // the basis is addressed through 32-bit buffer offsets
+  if (M1 * h->ld * vbytes(prec) >= (int64_t)1 << 32) throw Fail{GMRES_ENOMEM};
+  a.V = h->alloc<uint8_t>((size_t)(M1 * h->ld * vbytes(prec)));
+  hip_check(hipMemsetAsync(a.V, 0, (size_t)(M1 * h->ld * vbytes(prec)), h->stream));
+  a.w = h->alloc<uint8_t>((size_t)(h->ld * wbytes(prec)));
+  hip_check(hipMemsetAsync(a.w, 0, (size_t)(h->ld * wbytes(prec)), h->stream));
+  if (opt->precond != GMRES_PRECOND_NONE) {
+    a.Z = h->alloc<float>((size_t)(m * h->ld));
+    hip_check(hipMemsetAsync(a.Z, 0, (size_t)(m * h->ld * 4), h->stream));
+  }
+  a.x = h->alloc<double>(h->ld);
+  a.b = h->alloc<double>(h->ld);
+  hip_check(hipMemsetAsync(a.x, 0, h->ld * 8, h->stream));
+  hip_check(hipMemsetAsync(a.b, 0, h->ld * 8, h->stream));
+  a.st = h->alloc<SysState>(nsys);
+  a.cnt = h->alloc<uint32_t>(nsys);
+  hip_check(hipMemsetAsync(a.cnt, 0, nsys * 4, h->stream));
+  a.H = h->alloc<double>(nsys * M1 * m);
+  a.Hbar = h->alloc<double>(nsys * M1 * m);
+  hip_check(hipMemsetAsync(a.Hbar, 0, nsys * M1 * m * 8, h->stream));
+  a.cs = h->alloc<double>(nsys * m);
+  a.sn = h->alloc<double>(nsys * m);
+  a.s = h->alloc<double>(nsys * M1);
+  a.y = h->alloc<double>(nsys * m);
+  a.sc = h->alloc<double>(nsys * M1);
+  hip_check(hipMemsetAsync(a.sc, 0, nsys * M1 * 8, h->stream));
+  a.hacc = h->alloc<double>(nsys * M2);
+  a.h1 = h->alloc<double>(nsys * M2);
+  a.coef = h->alloc<double>(nsys * M2);
+  a.ares = h->alloc<double>(nsys * M1);
+  a.hist = h->alloc<double>((size_t)nsys * kHistCap);
+  a.tol = opt->tol;
+  a.restart_improve = opt->restart_improve;
+  a.max_iters = opt->max_iters;
+  a.stall_cycles = opt->stall_cycles;
+  a.stall_win = std::max(1, (int)std::ceil(0.05 * m));
+  hip_check(hipHostMalloc((void**)&h->st_host, sizeof(SysState) * nsys, hipHostMallocDefault));
+  if (opt->precond == GMRES_PRECOND_JACOBI) {
+    float* d = h->alloc<float>(h->ld);
+    hip_check(launch_jacobi_setup(a, d, h->stream));
+    a.dinv = d;
+  }
+  if (opt->precond == GMRES_PRECOND_SPAI) {
+    float* d = h->alloc<float>(h->nnz);
+    hip_check(hipMemsetAsync(d, 0, h->nnz * 4, h->stream));
+    a.mval = d;
+  }
+  // ---- partials sized for the largest grid any budget candidate can give
+  {
+    std::vector<int32_t> rbtmp;
+    for (const System& s : h->sys) build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, 1024, rbtmp);
+    const int64_t maxblk = std::max<int64_t>((int64_t)rbtmp.size(), h->nchunk);
+    a.part = h->alloc<double>((size_t)maxblk * a.ps);
+  }
+  {
+    int32_t* bad = h->alloc<int32_t>(1);
+    hip_check(hipMemsetAsync(bad, 0, 4, h->stream));
+    hip_check(launch_check_cols(a, bad, h->stream));
+    int32_t hb = 0;
+    hip_check(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    if (hb) throw Fail{GMRES_EINVAL};
+  }
+  set_row_blocks(h, 2048);
+  hip_check(launch_init_state(a, h->stream));
+  if (opt->autotune) autotune_spmv(h);
+  h->xs = h->alloc<double>(h->ld);
+  h->ys = h->alloc<double>(h->ld);
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
+int finish(gmres_ctx* h, gmres_result* res, int32_t nres, double seconds) {
+  for (int k = 0; k < nres; ++k) {
+    const SysState& S = h->st_host[k];
+    gmres_result r{};
+    r.status = S.status;
+    r.iters = S.iters;
+    r.restarts = S.restarts;
+    r.rel_residual = S.rel;
+    r.seconds = seconds;
+    r.fallback_used = S.fallback_used;
+    r.first_stall = S.first_stall;
+    res[k] = r;
+  }
+  return GMRES_OK;
+}
+
+// The cycle loop shared by single and batch solves; b and x are already in
+// the internal buffers.
+void run_cycles(gmres_ctx* h) {
+  KArgs& a = h->a;
+  hip_check(launch_init_state(a, h->stream));
+  hip_check(launch_bnorm(a, h->stream));
+  if (h->opt.use_graph) build_graph(h);
+  const int S = a.S;
+  const int64_t cap = h->opt.max_iters / 1 + 8;
+  for (int64_t cyc = 0; cyc <= cap; ++cyc) {
+    if (h->opt.use_graph)
+      hip_check(hipGraphLaunch(h->gexec, h->stream));
+    else
+      hip_check(enqueue_cycle(h, h->stream));
+    hip_check(hipMemcpyAsync(h->st_host, a.st, sizeof(SysState) * S, hipMemcpyDeviceToHost, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    bool running = false;
+    for (int k = 0; k < S && !running; ++k) running = h->st_host[k].status == RUNNING;
+    if (!running) break;
+  }
+}
+
+gmres_ctx* get(gmres_handle h) {
+  if (!h || h->magic != kMagic) throw Fail{GMRES_EHANDLE};
+  return h;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+void gmres_default_options(gmres_options* o) {
+  if (!o) return;
+  o->m = 50;
+  o->tol = 1e-10;
+  o->max_iters = 100000;
+  o->ortho = GMRES_CGSR;
+  o->precision = GMRES_MIXED_FP32;
+  o->precond = GMRES_PRECOND_NONE;
+  o->restart_improve = 0.0;
+  o->stall_cycles = 3;
+  o->use_graph = 1;
+  o->autotune = 1;
+}
+
+const char* gmres_strerror(int code) {
+  switch (code) {
+    case GMRES_OK: return "ok";
+    case GMRES_EINVAL: return "invalid argument";
+    case GMRES_EHIP: return "HIP runtime error";
+    case GMRES_ENOMEM: return "out of device memory";
+    case GMRES_EHANDLE: return "invalid handle";
+    case GMRES_ESTATE: return "operation not valid for this handle";
+  }
+  return "unknown error";
+}
+
+int gmres_batch_create(gmres_handle* out, int32_t nsys, const int64_t* n, const int64_t* nnz,
+                       const int32_t* const* row_ptr, const int32_t* const* col_idx,
+                       const double* const* vals, const gmres_options* opt, void* hip_stream) {
+  if (!out || nsys < 1 || !n || !nnz || !row_ptr || !col_idx || !vals || !valid_options(opt))
+    return GMRES_EINVAL;
+  *out = nullptr;
+  for (int k = 0; k < nsys; ++k) {
+    if (n[k] <= 0 || nnz[k] < 0 || !row_ptr[k] || (nnz[k] > 0 && (!col_idx[k] || !vals[k])))
+      return GMRES_EINVAL;
+  }
+  gmres_ctx* h = new (std::nothrow) gmres_ctx();
+  if (!h) return GMRES_ENOMEM;
+  try {
+    setup(h, nsys, n, nnz, row_ptr, col_idx, vals, opt, hip_stream);
+  } catch (const Fail& f) {
+    delete h;
+    (void)hipGetLastError();
+    return f.code;
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return GMRES_ENOMEM;
+  }
+  *out = h;
+  return GMRES_OK;
+}
+
+int gmres_create(gmres_handle* out, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                 const double* vals, const gmres_options* opt, void* hip_stream) {
+  return gmres_batch_create(out, 1, &n, &nnz, &row_ptr, &col_idx, &vals, opt, hip_stream);
+}
+
+int gmres_set_preconditioner(gmres_handle hh, const float* spai_vals) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (h->opt.precond != GMRES_PRECOND_SPAI) return GMRES_ESTATE;
+    if (!spai_vals) return GMRES_EINVAL;
+    hip_check(hipMemcpyAsync((void*)h->a.mval, spai_vals, h->nnz * 4, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    h->spai_set = true;
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int gmres_solve(gmres_handle hh, const double* b, double* x, gmres_result* res) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (h->a.S != 1) return GMRES_ESTATE;
+    if (!b || !x) return GMRES_EINVAL;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->sys[0].n;
+    hip_check(hipMemcpyAsync(h->a.b, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipMemcpyAsync(h->a.x, x, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    run_cycles(h);
+    hip_check(hipMemcpyAsync(x, h->a.x, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (res) finish(h, res, 1, sec);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_batch_solve(gmres_handle hh, const double* const* b, double* const* x, gmres_result* res) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!b || !x) return GMRES_EINVAL;
+    const int S = h->a.S;
+    for (int k = 0; k < S; ++k)
+      if (!b[k] || !x[k]) return GMRES_EINVAL;
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!h->bptrs) {
+      h->bptrs = (const double**)h->alloc<void*>(S);
+      h->xptrs = (double**)h->alloc<void*>(S);
+    }
+    hip_check(hipMemcpyAsync((void*)h->bptrs, b, S * sizeof(void*), hipMemcpyHostToDevice, h->stream));
+    hip_check(hipMemcpyAsync((void*)h->xptrs, x, S * sizeof(void*), hipMemcpyHostToDevice, h->stream));
+    int64_t maxn = 0;
+    for (const System& s : h->sys) maxn = std::max(maxn, s.n);
+    hip_check(launch_gather(h->bptrs, h->a.b, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream));
+    hip_check(launch_gather((const double* const*)h->xptrs, h->a.x, h->a.sys_row0, h->a.sys_n, S, maxn,
+                            h->stream));
+    run_cycles(h);
+    hip_check(launch_scatter(h->a.x, h->xptrs, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (res) finish(h, res, S, sec);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_destroy(gmres_handle hh) {
+  if (!hh) return GMRES_OK;
+  if (hh->magic != kMagic) return GMRES_EHANDLE;
+  (void)hipStreamSynchronize(hh->stream);
+  delete hh;
+  return GMRES_OK;
+}
+
+int gmres_residual(gmres_handle hh, const double* b, const double* x, double* r, double* norm_out) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!b || !x) return GMRES_EINVAL;
+    if (h->sys.size() != 1) return GMRES_ESTATE;
+    const int64_t n = h->sys[0].n;
+    // kernels index padded global rows: stage b and x in padded buffers
+    hip_check(hipMemsetAsync(h->xs, 0, h->ld * 8, h->stream));
+    hip_check(hipMemsetAsync(h->ys, 0, h->ld * 8, h->stream));
+    hip_check(hipMemcpyAsync(h->ys, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipMemcpyAsync(h->xs, x, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(launch_residual_plain(h->a, h->ys, h->xs, h->ys, h->stream));
+    std::vector<double> part((size_t)h->nrb * h->a.ps);
+    hip_check(hipMemcpyAsync(part.data(), h->a.part, part.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    if (r) hip_check(hipMemcpyAsync(r, h->ys, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    double sq = 0.0;
+    for (int i = 0; i < h->nrb; ++i) sq += part[(size_t)i * h->a.ps];
+    if (norm_out) *norm_out = std::sqrt(sq);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_spmv(gmres_handle hh, int32_t precision, const void* x, void* y) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!x || !y) return GMRES_EINVAL;
+    if (precision != GMRES_FP64 && precision != GMRES_MIXED_FP32) return GMRES_EINVAL;
+    if (precision == GMRES_MIXED_FP32 && !h->a.a32) return GMRES_ESTATE;
+    if (h->sys.size() != 1) return GMRES_ESTATE;
+    const int64_t n = h->sys[0].n;
+    const size_t eb = precision == GMRES_FP64 ? 8 : 4;
+    // padded staging so that the kernel's global indexing is valid
+    hip_check(hipMemsetAsync(h->xs, 0, h->ld * 8, h->stream));
+    hip_check(hipMemcpyAsync(h->xs, x, n * eb, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(launch_spmv_plain(h->a, precision == GMRES_FP64 ? P64 : P32, h->xs, h->ys, h->stream));
+    hip_check(hipMemcpyAsync(y, h->ys, n * eb, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_encode(int32_t precision, int64_t n, const float* w, double inv_h, void* out, double* scale_out,
+                 void* hip_stream) {
+  if (precision != GMRES_MIXED_BF16 && precision != GMRES_MIXED_FP16) return GMRES_EINVAL;
+  if (n < 0 || (n > 0 && (!w || !out)) || !(inv_h > 0.0)) return GMRES_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int nblk = 256;
+  float* part = nullptr;
+  if (hipMalloc(&part, nblk * sizeof(float)) != hipSuccess) return GMRES_ENOMEM;
+  int rc = GMRES_OK;
+  std::vector<float> hp(nblk);
+  if (launch_absmax(w, n, part, nblk, st) != hipSuccess ||
+      hipMemcpyAsync(hp.data(), part, nblk * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    rc = GMRES_EHIP;
+  } else {
+    float mx = 0.0f;
+    for (float v : hp) mx = std::max(mx, v);
+    const double vmax = (double)mx * inv_h;
+    int e = 0;
+    if (vmax > 0.0 && std::isfinite(vmax)) {
+      int p;
+      const double f = std::frexp(vmax, &p);
+      e = (precision == GMRES_MIXED_FP16 ? 15 : 0) - p + (f == 0.5 ? 1 : 0);
+    }
+    const float fac = (float)(std::ldexp(1.0, e) * inv_h);
+    if (launch_encode_plain(precision, n, w, fac, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+      rc = GMRES_EHIP;
+    if (scale_out) *scale_out = std::ldexp(1.0, -e);
+  }
+  (void)hipFree(part);
+  return rc;
+}
+
+int gmres_last_cycle(gmres_handle hh, int32_t sys, int32_t* k_out, double* Hbar_out, double* V_out) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (sys < 0 || sys >= h->a.S) return GMRES_EINVAL;
+    SysState S{};
+    hip_check(hipMemcpy(&S, h->a.st + sys, sizeof(SysState), hipMemcpyDeviceToHost));
+    if (k_out) *k_out = S.k;
+    const int m = h->a.m;
+    if (Hbar_out)
+      hip_check(hipMemcpy(Hbar_out, h->a.Hbar + (size_t)sys * (m + 1) * m, (size_t)(m + 1) * m * 8,
+                          hipMemcpyDeviceToHost));
+    if (V_out) {
+      const int64_t n = h->sys[sys].n;
+      const int ncols = std::min(S.k + 1, m + 1);
+      for (int c = 0; c < ncols; ++c)
+        hip_check(launch_decode_column(h->a, sys, c, V_out + (int64_t)c * n, h->stream));
+      hip_check(hipStreamSynchronize(h->stream));
+    }
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int gmres_history(gmres_handle hh, int32_t sys, double* out, int32_t cap, int32_t* count) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (sys < 0 || sys >= h->a.S || cap < 0 || (cap > 0 && !out)) return GMRES_EINVAL;
+    SysState S{};
+    hip_check(hipMemcpy(&S, h->a.st + sys, sizeof(SysState), hipMemcpyDeviceToHost));
+    const int nrec = std::min(S.nhist, kHistCap);
+    if (count) *count = nrec;
+    const int ncopy = std::min(nrec, (int)cap);
+    if (ncopy > 0)
+      hip_check(hipMemcpy(out, h->a.hist + (size_t)sys * kHistCap, ncopy * 8, hipMemcpyDeviceToHost));
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int gmres_memory_bytes(gmres_handle hh, size_t* bytes) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!bytes) return GMRES_EINVAL;
+    *bytes = h->bytes;
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, double* avg_ms, double* bytes) {
+  try {
+    gmres_ctx* h = get(hh);
+    const KArgs& a = h->a;
+    if (j < 0 || j >= a.m || reps < 1 || !avg_ms) return GMRES_EINVAL;
+    const int prec = a.prec;
+    const double n = (double)h->nrows, nnz = (double)h->nnz;
+    const double sv = (double)vbytes(prec), sw = (double)wbytes(prec), sa = prec == P64 ? 8.0 : 4.0;
+    double bts = 0.0;
+    auto run = [&]() -> hipError_t {
+      switch (kernel) {
+        case 0: return launch_spmv_arnoldi(a, j, h->stream);
+        case 1: return launch_cgs_pass1(a, j, h->stream);
+        case 2: return launch_cgs_pass2(a, j, h->stream);
+        case 3: return launch_final_pass(a, j, 0, h->stream);
+        case 4: return launch_mgs_dot(a, j, j, h->stream);
+        case 5: return launch_residual(a, h->stream);
+        case 6: return launch_update(a, h->stream);
+      }
+      return hipErrorInvalidValue;
+    };
+    switch (kernel) {
+      case 0: bts = nnz * (sa + 4.0) + 4.0 * (n + 1) + n * sv + n * sw; break;
+      case 1: bts = (j + 1) * n * sv + n * sw; break;
+      case 2: bts = (j + 1) * n * sv + 2.0 * n * sw; break;
+      case 3: bts = (j + 1) * n * sv + n * sw + n * (sv == 2 ? sw : sv); break;
+      case 4: bts = (j > 0 ? 2.0 : 1.0) * n * sv + (j > 0 ? 2.0 : 1.0) * n * sw; break;
+      case 5: bts = nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * (sv == 2 ? sw : sv); break;
+      case 6: bts = (j + 1) * n * sv + 16.0 * n; break;
+      default: return GMRES_EINVAL;
+    }
+    hip_check(launch_set_force(a, 1, h->stream));
+    hip_check(run());
+    hip_check(hipEventRecord(h->ev0, h->stream));
+    for (int r = 0; r < reps; ++r) hip_check(run());
+    hip_check(hipEventRecord(h->ev1, h->stream));
+    hip_check(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    hip_check(launch_set_force(a, 0, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    *avg_ms = (double)ms / reps;
+    if (bytes) *bytes = bts;
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+}  // extern "C"

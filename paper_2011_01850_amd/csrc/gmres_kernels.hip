@@ -1,0 +1,1258 @@
+// HIP kernels of restarted GMRES(m) for gfx950 (wave64).
+//
+// Method: Algorithm 1 of Lindquist, Luszczek, Dongarra (arXiv 2011.01850):
+// float64 residual and update, float32 (or 2-byte-stored) Arnoldi process,
+// MGS or CGSR (two classical projections) orthogonalisation, Givens QR of
+// the Hessenberg matrix in float64.
+//
+// Execution model.  Every system of a handle is a contiguous, zero-padded
+// range of rows; a basis pass runs one 256-thread workgroup per 2048-row
+// chunk, a matrix pass one workgroup per CSR row block.  Reductions are
+// deterministic: per-lane sums, a fixed in-wave butterfly, a fixed
+// cross-wave order, and one float64 partial per workgroup; the last
+// workgroup of a system to finish (an agent-scope counter) reduces the
+// partials in a fixed order and runs that system's scalar step (Givens
+// rotation, restart and stop decisions).  Kernels of a cycle are gated by
+// the device-side `active` flag of their system, so a whole restart cycle
+// can be enqueued (or captured in one graph) without host round trips.
+#include <math.h>
+
+#include <algorithm>
+
+#include "gmres_internal.hpp"
+
+namespace gm {
+
+struct bf16_t {
+  uint16_t b;
+};
+using f16_t = _Float16;
+
+template <typename T>
+struct AccOf {
+  using type = float;
+};
+template <>
+struct AccOf<double> {
+  using type = double;
+};
+
+__device__ __forceinline__ float ldv(float v) { return v; }
+__device__ __forceinline__ double ldv(double v) { return v; }
+__device__ __forceinline__ float ldv(bf16_t v) { return __uint_as_float(((uint32_t)v.b) << 16); }
+__device__ __forceinline__ float ldv(f16_t v) { return (float)v; }
+
+template <typename T>
+__device__ __forceinline__ T stv(float v);
+template <>
+__device__ __forceinline__ float stv<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ bf16_t stv<bf16_t>(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | 0x40u)};  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return bf16_t{(uint16_t)(u >> 16)};
+}
+template <>
+__device__ __forceinline__ f16_t stv<f16_t>(float v) { return (f16_t)v; }  // v_cvt_f16_f32: RNE
+
+template <typename T>
+__device__ __forceinline__ T stw(double v);
+template <>
+__device__ __forceinline__ double stw<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ float stw<float>(double v) { return (float)v; }
+
+// ------------------------------------------------------------ block helpers
+
+__device__ __forceinline__ int remap_block(int b, int G, int on) {
+  // consecutive logical blocks on one XCD: dispatch is round-robin over 8 XCDs
+  if (!on) return b;
+  const int per = G >> 3, rem = G & 7, x = b & 7, q = b >> 3;
+  return x * per + (x < rem ? x : rem) + q;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Sum over the 256 threads, identical result in every thread.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v) {
+  __shared__ T red[kBlock / 64];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T t = red[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+template <typename T>
+__device__ __forceinline__ T block_max(T v) {
+  __shared__ T red[kBlock / 64];
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T t = red[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) t = fmax(t, red[i]);
+  __syncthreads();
+  return t;
+}
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// In-wave reduce-scatter of L column values (L a power of two <= 64):
+// afterwards lane l holds the wave-wide sum of column (l >> (6 - log2 L)).
+template <int L, typename T>
+__device__ __forceinline__ T reduce_scatter(T (&p)[L], int lane) {
+  constexpr int P = ilog2c(L);
+#pragma unroll
+  for (int st = 0; st < P; ++st) {
+    const int o = 32 >> st;
+    const int half = (L >> st) >> 1;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      // select values, not array slots: a conditional lvalue would make the
+      // array addressable and push it to scratch memory
+      const T lo = p[q], hi = p[q + half];
+      const T keep = up ? hi : lo;
+      const T send = up ? lo : hi;
+      p[q] = keep + __shfl_xor(send, o);
+    }
+  }
+  T v = p[0];
+#pragma unroll
+  for (int o = 32 >> P; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// True in the block that finishes last among `total` blocks sharing *cnt.
+// Partials written before the call are visible to that block afterwards.
+__device__ __forceinline__ bool last_block(uint32_t* cnt, int total) {
+  __shared__ int flag;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev = atomicAdd(cnt, 1u);
+    flag = (prev + 1u == (uint32_t)total) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// out[col] = sum (or max for col == maxcol) of part[(c0 + c) * ps + col] over
+// c in [0, nc), in a fixed order.  Called by all threads of one block.
+__device__ void reduce_partials(const double* part, int ps, int c0, int nc, int ncol, int maxcol,
+                                double* out) {
+  __shared__ double red[kBlock / 64][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  constexpr int G = kBlock / 64;
+  for (int base = 0; base < ncol; base += 64) {
+    const int col = base + lane;
+    double a0 = 0.0, a1 = 0.0;
+    if (col < ncol) {
+      const double* p = part + (int64_t)c0 * ps + col;
+      int c = g;
+      if (col == maxcol) {
+        for (; c + G < nc; c += 2 * G) {
+          a0 = fmax(a0, p[(int64_t)c * ps]);
+          a1 = fmax(a1, p[(int64_t)(c + G) * ps]);
+        }
+        if (c < nc) a0 = fmax(a0, p[(int64_t)c * ps]);
+        a0 = fmax(a0, a1);
+      } else {
+        for (; c + G < nc; c += 2 * G) {
+          a0 += p[(int64_t)c * ps];
+          a1 += p[(int64_t)(c + G) * ps];
+        }
+        if (c < nc) a0 += p[(int64_t)c * ps];
+        a0 += a1;
+      }
+    }
+    red[g][lane] = a0;
+    __syncthreads();
+    if (g == 0 && col < ncol) {
+      double r = red[0][lane];
+      for (int k = 1; k < G; ++k) r = (col == maxcol) ? fmax(r, red[k][lane]) : r + red[k][lane];
+      out[col] = r;
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ bool gated(const KArgs& a, int s) {
+  const SysState& S = a.st[s];
+  return S.active != 0 || S.force != 0;
+}
+
+__device__ __forceinline__ double unit_roundoff(int prec) {
+  return prec == P64 ? 0x1p-53 : 0x1p-24;
+}
+
+// e with vmax * 2^e in (T/2, T]; T = 2^15 for half, 1 for bfloat16.
+__device__ __forceinline__ int scale_exp(double vmax, int prec) {
+  if (!(vmax > 0.0) || !isfinite(vmax)) return 0;
+  int p;
+  const double f = frexp(vmax, &p);
+  return (prec == PF16 ? 15 : 0) - p + (f == 0.5 ? 1 : 0);
+}
+
+__device__ __forceinline__ void givens(double a, double b, double& c, double& s) {
+  if (b == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  const double rho = hypot(a, b);
+  c = a / rho;
+  s = b / rho;
+}
+
+// ------------------------------------------------------------- finalisers
+// All run in the last block of a pass; `red` holds the reduced partials.
+
+__device__ void fin_pass1(const KArgs& a, int s, int j, const double* red) {
+  const int M2 = a.m + 2, M1 = a.m + 1;
+  const double* sc = a.sc + (int64_t)s * M1;
+  double* h1 = a.h1 + (int64_t)s * M2;
+  double* coef = a.coef + (int64_t)s * M2;
+  for (int q = threadIdx.x; q <= j; q += kBlock) {
+    const double h = sc[q] * red[q];
+    h1[q] = h;
+    coef[q] = h * sc[q];
+  }
+  if (threadIdx.x == 0) a.st[s].wnorm_pre = sqrt(red[j + 1]);
+}
+
+__device__ void fin_pass2(const KArgs& a, int s, int j, const double* red) {
+  const int M2 = a.m + 2, M1 = a.m + 1;
+  const double* sc = a.sc + (int64_t)s * M1;
+  const double* h1 = a.h1 + (int64_t)s * M2;
+  double* hc = a.hacc + (int64_t)s * M2;
+  double* coef = a.coef + (int64_t)s * M2;
+  for (int q = threadIdx.x; q <= j; q += kBlock) {
+    const double h = sc[q] * red[q];
+    hc[q] = h1[q] + h;
+    coef[q] = h * sc[q];
+  }
+}
+
+__device__ void fin_mgs(const KArgs& a, int s, int i, const double* red) {
+  if (threadIdx.x != 0) return;
+  const int M2 = a.m + 2, M1 = a.m + 1;
+  const double sci = a.sc[(int64_t)s * M1 + i];
+  const double h = sci * red[0];
+  a.hacc[(int64_t)s * M2 + i] = h;
+  a.coef[(int64_t)s * M2 + i] = h * sci;
+  if (i == 0) a.st[s].wnorm_pre = sqrt(red[1]);
+}
+
+// Givens update of column j, restart / stop decisions (one lane).
+__device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax) {
+  SysState& S = a.st[s];
+  const int m = a.m, M1 = m + 1, M2 = m + 2;
+  double* Hs = a.H + (int64_t)s * M1 * m;
+  double* Hb = a.Hbar + (int64_t)s * M1 * m;
+  const double* hc = a.hacc + (int64_t)s * M2;
+  double* cs = a.cs + (int64_t)s * m;
+  double* sn = a.sn + (int64_t)s * m;
+  double* sv = a.s + (int64_t)s * M1;
+  double* sc = a.sc + (int64_t)s * M1;
+  double* ar = a.ares + (int64_t)s * M1;
+  const double hn = sqrt(sumsq);
+  bool finite = isfinite(hn);
+  for (int i = 0; i <= j; ++i) finite = finite && isfinite(hc[i]);
+  if (!finite) {
+    // drop the column; the cycle ends with the finite part of the basis
+    S.k = j;
+    S.need_update = j > 0 ? 1 : 0;
+    S.active = 0;
+    if (a.precond != 0 && S.precond_on) {
+      S.precond_on = 0;
+      S.fallback_used = 1;
+    }
+    return;
+  }
+  double* col = Hs + (int64_t)j * M1;
+  double* bcol = Hb + (int64_t)j * M1;
+  for (int i = 0; i <= j; ++i) {
+    bcol[i] = hc[i];
+    col[i] = hc[i];
+  }
+  bcol[j + 1] = hn;
+  for (int i = 0; i < j; ++i) {  // previous rotations
+    const double a0 = col[i], a1 = col[i + 1];
+    col[i] = cs[i] * a0 + sn[i] * a1;
+    col[i + 1] = -sn[i] * a0 + cs[i] * a1;
+  }
+  double c, sg;
+  givens(col[j], hn, c, sg);
+  cs[j] = c;
+  sn[j] = sg;
+  sv[j + 1] = -sg * sv[j];
+  sv[j] = c * sv[j];
+  col[j] = c * col[j] + sg * hn;
+  col[j + 1] = 0.0;
+  S.iters += 1;
+  S.k = j + 1;
+  S.need_update = 1;
+  const double res = fabs(sv[j + 1]);
+  ar[j + 1] = res;
+  if (S.cycle == 1 && S.first_stall < 0) {
+    const int J = j + 1 - a.stall_win;
+    if (J >= 0 && ar[j + 1] > ar[J] / 1.001) S.first_stall = J;
+  }
+  const double bd = 16.0 * (double)(j + 1) * unit_roundoff(a.prec);
+  const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
+                   S.iters >= a.max_iters ||
+                   (a.restart_improve > 0.0 && res <= a.restart_improve * S.beta);
+  if (!end) {
+    if (a.prec == PBF16 || a.prec == PF16) {
+      const int e = scale_exp(wmax / hn, a.prec);
+      sc[j + 1] = ldexp(1.0, -e);
+      S.enc_f = (float)(ldexp(1.0, e) / hn);
+    } else {
+      sc[j + 1] = 1.0 / hn;
+    }
+  }
+  S.active = end ? 0 : 1;
+}
+
+__device__ void fin_residual(const KArgs& a, int s, double sumsq, double zmax) {
+  SysState& S = a.st[s];
+  const int M1 = a.m + 1;
+  S.need_update = 0;
+  S.active = 0;
+  const double beta = sqrt(sumsq);
+  S.beta = beta;
+  S.rel = beta / S.bnorm;
+  if (S.nhist < kHistCap) a.hist[(int64_t)s * kHistCap + S.nhist] = S.rel;
+  S.nhist += 1;
+  if (S.force) return;
+  if (S.rel <= a.tol) {
+    S.status = CONVERGED;
+    return;
+  }
+  if (!isfinite(beta)) {
+    S.status = STALLED;
+    return;
+  }
+  if (S.iters >= a.max_iters) {
+    S.status = MAXITER;
+    return;
+  }
+  if (beta >= S.best_beta)
+    S.no_progress += 1;
+  else
+    S.no_progress = 0;
+  S.best_beta = fmin(S.best_beta, beta);
+  if (S.no_progress >= a.stall_cycles) {
+    S.status = STALLED;
+    return;
+  }
+  if (a.precond != 0 && S.precond_on && beta > S.prev_beta / 1.001) {
+    S.precond_on = 0;
+    S.fallback_used = 1;
+  }
+  S.prev_beta = beta;
+  S.k = 0;
+  S.cycle += 1;
+  a.s[(int64_t)s * M1] = beta;
+  a.ares[(int64_t)s * M1] = beta;
+  if (a.prec == PBF16 || a.prec == PF16) {
+    const int e = scale_exp(zmax / beta, a.prec);
+    a.sc[(int64_t)s * M1] = ldexp(1.0, -e);
+    S.enc_f = (float)(ldexp(1.0, e) / beta);
+  } else {
+    a.sc[(int64_t)s * M1] = 1.0 / beta;
+  }
+  S.active = 1;
+}
+
+// ------------------------------------------------------------------ SpMV
+
+enum SpmvMode { SM_ARNOLDI = 0, SM_PRECOND = 1, SM_AZ = 2, SM_RESID = 3, SM_PLAIN = 4, SM_RESID_PLAIN = 5 };
+
+// Adaptive CSR: a row block is either up to 256 rows whose non-zeros fit
+// the streaming budget (products staged in LDS, each row reduced by a
+// power-of-two group of lanes) or one long row reduced by the whole block.
+template <typename TA, typename TX, typename TY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__ vals,
+                                                 const TX* __restrict__ x, TY* __restrict__ y,
+                                                 const double* __restrict__ bvec, int j) {
+  using ACC = typename AccOf<TA>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  ACC* prod = reinterpret_cast<ACC*>(smem_raw);
+  const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.rb_sys[blk];
+  if (MODE == SM_ARNOLDI || MODE == SM_PRECOND || MODE == SM_AZ) {
+    if (!gated(a, s)) return;
+  } else if (MODE == SM_RESID) {
+    const SysState& S = a.st[s];
+    if (S.status != RUNNING && !S.force) return;
+  }
+  const int t = threadIdx.x;
+  const int r0 = a.rb[blk], r1 = a.rb[blk + 1];
+  const int p0 = a.rp[r0], p1 = a.rp[r1];
+  ACC scale = (ACC)1;
+  if (MODE == SM_ARNOLDI || MODE == SM_PRECOND) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
+  if (MODE == SM_PRECOND && !a.st[s].precond_on) {
+    // preconditioner switched off: z_j = v_j
+    for (int r = r0 + t; r < r1; r += kBlock) y[r] = (TY)(scale * (ACC)ldv(x[r]));
+    return;
+  }
+  double zsq = 0.0, zmax = 0.0;
+  auto emit = [&](int r, ACC acc) {
+    if (MODE == SM_RESID || MODE == SM_RESID_PLAIN) {
+      const double z = bvec[r] - (double)acc;
+      zsq += z * z;
+      zmax = fmax(zmax, fabs(z));
+      y[r] = (TY)z;
+    } else {
+      y[r] = (TY)(acc * scale);
+    }
+  };
+  if (p1 - p0 > a.spmv_budget) {  // one long row
+    ACC acc = (ACC)0;
+    for (int k = p0 + t; k < p1; k += kBlock) acc += (ACC)vals[k] * (ACC)ldv(x[a.ci[k]]);
+    acc = block_sum(acc);
+    if (t == 0) emit(r0, acc);
+  } else {
+    for (int k = p0 + t; k < p1; k += kBlock) prod[k - p0] = (ACC)vals[k] * (ACC)ldv(x[a.ci[k]]);
+    __syncthreads();
+    const int nr = r1 - r0;
+    int tpr = 1;
+    while (tpr < 64 && tpr * 2 * nr <= kBlock) tpr *= 2;
+    const int g = t / tpr, l = t % tpr, ng = kBlock / tpr;
+    for (int r = r0 + g; r < r1; r += ng) {
+      ACC acc = (ACC)0;
+      const int e = a.rp[r + 1];
+      for (int k = a.rp[r] + l; k < e; k += tpr) acc += prod[k - p0];
+      for (int o = tpr >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (l == 0) emit(r, acc);
+    }
+  }
+  if (MODE == SM_RESID || MODE == SM_RESID_PLAIN) {
+    zsq = block_sum(zsq);
+    if (MODE == SM_RESID) zmax = block_max(zmax);
+    if (t == 0) {
+      a.part[(int64_t)blk * a.ps] = zsq;
+      if (MODE == SM_RESID) a.part[(int64_t)blk * a.ps + 1] = zmax;
+    }
+    if (MODE == SM_RESID) {
+      if (last_block(a.cnt + s, a.sys_nrb[s])) {
+        __shared__ double red[2];
+        reduce_partials(a.part, a.ps, a.sys_rb0[s], a.sys_nrb[s], 2, 1, red);
+        __syncthreads();
+        if (t == 0) {
+          fin_residual(a, s, red[0], red[1]);
+          a.cnt[s] = 0;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ basis passes
+
+// ------------------------------------------------------- buffer loads
+// The basis is read through one buffer resource: a per-lane byte offset of
+// the row plus a scalar byte offset of the column, so a register tile of up
+// to 64 columns needs no per-column 64-bit addresses.  Reads past the end
+// of the resource return zero.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+template <>
+__device__ __forceinline__ bf16_t bload<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return bf16_t{(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0)};
+}
+template <>
+__device__ __forceinline__ f16_t bload<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+}
+// Resource over basis columns [0, ncols): a tile load of a column >= ncols
+// is pointed at column ncols, which lies past the range and reads zero, so
+// tiles of L >= ncols columns need no per-column guards.
+template <typename TV>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t basis_rsrc(const KArgs& a, int ncols) {
+  return make_rsrc(a.V, (uint32_t)((int64_t)ncols * a.ld * (int64_t)sizeof(TV)));
+}
+
+template <typename T>
+__device__ __forceinline__ const T* col_ptr(const KArgs& a, int i) {
+  return reinterpret_cast<const T*>(a.V) + (int64_t)i * a.ld;
+}
+
+// Writes the per-wave column sums (lane-owned after reduce_scatter) into
+// part[c][col0 + q] for q < ncol, in a fixed cross-wave order.
+template <int L, typename ACC>
+__device__ __forceinline__ void store_colsums(const KArgs& a, int c, int col0, int ncol, ACC colsum) {
+  __shared__ ACC lds[kBlock / 64][L];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int R = 64 / L;  // lanes per column
+  if ((lane & (R - 1)) == 0) lds[wv][lane / R] = colsum;
+  __syncthreads();
+  if (threadIdx.x < ncol) {
+    ACC tot = lds[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < kBlock / 64; ++k) tot += lds[k][threadIdx.x];
+    a.part[(int64_t)c * a.ps + col0 + threadIdx.x] = (double)tot;
+  }
+  __syncthreads();
+}
+
+// CGSR projection 1 (columns [col0, col0 + L) of V^T w) and ||w||^2.
+// mode 1: finalise as the first projection; mode 2: as the second.
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, int j, int col0, int mode) {
+  using ACC = typename AccOf<TV>::type;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int ncol = min(L, j + 1 - col0);
+  const TW* w = reinterpret_cast<const TW*>(a.w);
+  const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, col0 + ncol);
+  const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
+  const uint32_t c0off = (uint32_t)col0 * cstride;
+  const int64_t base = (int64_t)c * kChunk + t;
+  ACC colsum = (ACC)0, ww = (ACC)0;
+  uint32_t cs = cstride;
+#pragma unroll 1
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    // column offsets are rebuilt per tile (a scalar add each) instead of
+    // being hoisted into L live scalar registers
+    asm volatile("" : "+s"(cs));
+    const int64_t r = base + u * kBlock;
+    const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV)) + c0off;
+    const ACC wr = (ACC)w[r];
+    ww += wr * wr;
+    ACC p[L];
+    uint32_t so = 0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      p[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0)) * wr;
+      if (q < ncol) so += cs;
+    }
+    colsum += reduce_scatter<L>(p, lane);
+  }
+  store_colsums<L>(a, c, col0, ncol, colsum);
+  const bool last_window = col0 + L >= j + 1;
+  if (col0 == 0 && mode == 1) {
+    const ACC tot = block_sum(ww);
+    if (t == 0) a.part[(int64_t)c * a.ps + j + 1] = (double)tot;
+  }
+  if (!last_window) return;
+  if (last_block(a.cnt + s, a.sys_nch[s])) {
+    __shared__ double red[kMaxM + 3];
+    const int nred = mode == 1 ? j + 2 : j + 1;
+    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], nred, -1, red);
+    __syncthreads();
+    if (mode == 1)
+      fin_pass1(a, s, j, red);
+    else
+      fin_pass2(a, s, j, red);
+    if (t == 0) a.cnt[s] = 0;
+  }
+}
+
+// CGSR projection 2, fused: w' = w - V coef (coef from projection 1), then
+// V^T w' from the same register tile of V.  Requires j + 1 <= L <= 64.
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_axpy_mdot(KArgs a, int j) {
+  using ACC = typename AccOf<TV>::type;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x, lane = t & 63;
+  const int ncol = j + 1;
+  TW* w = reinterpret_cast<TW*>(a.w);
+  const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, ncol);
+  const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
+  const double* coefd = a.coef + (int64_t)s * (a.m + 2);
+  __shared__ ACC cf[L];
+  if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
+  __syncthreads();
+  const int64_t base = (int64_t)c * kChunk + t;
+  ACC colsum = (ACC)0;
+  uint32_t cs = cstride;
+#pragma unroll 1
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    asm volatile("" : "+s"(cs));
+    const int64_t r = base + u * kBlock;
+    const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
+    ACC v[L];
+    uint32_t so = 0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
+      if (q < ncol) so += cs;
+    }
+    ACC wr = (ACC)w[r];
+#pragma unroll
+    for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
+    w[r] = (TW)wr;
+#pragma unroll
+    for (int q = 0; q < L; ++q) v[q] *= wr;
+    colsum += reduce_scatter<L>(v, lane);
+  }
+  store_colsums<L>(a, c, 0, ncol, colsum);
+  if (last_block(a.cnt + s, a.sys_nch[s])) {
+    __shared__ double red[kMaxM + 3];
+    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], j + 1, -1, red);
+    __syncthreads();
+    fin_pass2(a, s, j, red);
+    if (t == 0) a.cnt[s] = 0;
+  }
+}
+
+// w -= V[:, col0:col0+L] coef (no reduction): the first half of projection 2
+// when j + 1 > 64.
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, int j, int col0) {
+  using ACC = typename AccOf<TV>::type;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x;
+  const int ncol = min(L, j + 1 - col0);
+  TW* w = reinterpret_cast<TW*>(a.w);
+  const TV* V0 = col_ptr<TV>(a, col0);
+  const double* coefd = a.coef + (int64_t)s * (a.m + 2) + col0;
+  const int64_t base = (int64_t)c * kChunk + t;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    ACC wr = (ACC)w[r];
+    for (int q = 0; q < ncol; ++q) wr -= (ACC)coefd[q] * (ACC)ldv(V0[(int64_t)q * a.ld + r]);
+    w[r] = (TW)wr;
+  }
+}
+
+// Last pass of a step: w'' = w - sum_{i0 <= i <= j} coef_i v_i, ||w''||^2 and
+// max|w''|; w'' goes to basis column j+1 (float32 / float64 basis, where
+// the decode scale 1/h_{j+1,j} normalises it) or stays in w (2-byte basis,
+// encoded by k_encode).  The last block runs the Givens step.
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kBlock) void k_final(KArgs a, int j, int i0) {
+  using ACC = typename AccOf<TV>::type;
+  constexpr bool kTwoByte = sizeof(TV) == 2;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x;
+  TW* w = reinterpret_cast<TW*>(a.w);
+  const double* coefd = a.coef + (int64_t)s * (a.m + 2);
+  const int64_t base = (int64_t)c * kChunk + t;
+  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
+  ACC sq = (ACC)0, mx = (ACC)0;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    ACC wr = (ACC)w[r];
+    for (int i = i0; i <= j; ++i) wr -= (ACC)coefd[i] * (ACC)ldv(col_ptr<TV>(a, i)[r]);
+    sq += wr * wr;
+    mx = fmax(mx, fabs(wr));
+    if constexpr (kTwoByte)
+      w[r] = (TW)wr;
+    else
+      vout[r] = (TV)wr;
+  }
+  const double tsq = (double)block_sum(sq);
+  const double tmx = (double)block_max(mx);
+  if (t == 0) {
+    a.part[(int64_t)c * a.ps] = tsq;
+    a.part[(int64_t)c * a.ps + 1] = tmx;
+  }
+  if (last_block(a.cnt + s, a.sys_nch[s])) {
+    __shared__ double red[2];
+    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], 2, 1, red);
+    __syncthreads();
+    if (t == 0) {
+      fin_step(a, s, j, red[0], red[1]);
+      a.cnt[s] = 0;
+    }
+  }
+}
+
+// MGS step i of Arnoldi column j: w -= h_{i-1} v_{i-1} (i > 0), then
+// h_i = w . v_i (plus ||w||^2 when i = 0).
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
+  using ACC = typename AccOf<TV>::type;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x;
+  TW* w = reinterpret_cast<TW*>(a.w);
+  const TV* vi = col_ptr<TV>(a, i);
+  const TV* vp = col_ptr<TV>(a, i > 0 ? i - 1 : 0);
+  const ACC cprev = i > 0 ? (ACC)a.coef[(int64_t)s * (a.m + 2) + i - 1] : (ACC)0;
+  const int64_t base = (int64_t)c * kChunk + t;
+  ACC d = (ACC)0, ww = (ACC)0;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    ACC wr = (ACC)w[r];
+    if (i > 0) {
+      wr -= cprev * (ACC)ldv(vp[r]);
+      w[r] = (TW)wr;
+    } else {
+      ww += wr * wr;
+    }
+    d += wr * (ACC)ldv(vi[r]);
+  }
+  const double td = (double)block_sum(d);
+  double tw = 0.0;
+  if (i == 0) tw = (double)block_sum(ww);
+  if (t == 0) {
+    a.part[(int64_t)c * a.ps] = td;
+    if (i == 0) a.part[(int64_t)c * a.ps + 1] = tw;
+  }
+  if (last_block(a.cnt + s, a.sys_nch[s])) {
+    __shared__ double red[2];
+    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], i == 0 ? 2 : 1, -1, red);
+    __syncthreads();
+    fin_mgs(a, s, i, red);
+    if (t == 0) a.cnt[s] = 0;
+  }
+}
+
+// 2-byte store of w as basis column col (scale prepared by the finaliser).
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_encode(KArgs a, int col) {
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const float f = a.st[s].enc_f;
+  const float* w = reinterpret_cast<const float*>(a.w);
+  TV* out = reinterpret_cast<TV*>(a.V) + (int64_t)col * a.ld;
+  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    out[r] = stv<TV>(w[r] * f);
+  }
+}
+
+// Jacobi: z_j = D^-1 v_j (or v_j once the preconditioner is switched off).
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_jacobi(KArgs a, int j) {
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const float scale = (float)a.sc[(int64_t)s * (a.m + 1) + j];
+  const bool on = a.st[s].precond_on != 0;
+  const TV* v = col_ptr<TV>(a, j);
+  float* z = a.Z + (int64_t)j * a.ld;
+  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    // (d^-1 v) * scale: the same rounding as a sparse M = D^-1 applied by the SpMV
+    const float vr = (float)ldv(v[r]);
+    z[r] = on ? (a.dinv[r] * vr) * scale : vr * scale;
+  }
+}
+
+// y = H^-1 s by back-substitution, one wave per system, with truncation of
+// a singular leading block.  Also turns y into update coefficients.
+__global__ __launch_bounds__(64) void k_backsolve(KArgs a) {
+  const int s = blockIdx.x;
+  SysState& S = a.st[s];
+  if (!S.need_update && !S.force) return;
+  const int m = a.m, M1 = m + 1;
+  const int k = S.k;
+  const double* Hs = a.H + (int64_t)s * M1 * m;
+  const double* sv = a.s + (int64_t)s * M1;
+  const int lane = threadIdx.x;
+  __shared__ double ys[kMaxM];
+  __shared__ int kk_s;
+  double hm = 0.0;
+  for (int jj = 0; jj < k; ++jj)
+    for (int i = lane; i <= jj; i += 64) hm = fmax(hm, fabs(Hs[(int64_t)jj * M1 + i]));
+  hm = wave_max(hm);
+  if (lane == 0) {
+    const double thr = 16.0 * (double)k * unit_roundoff(a.prec) * hm;
+    int kk = 0;
+    while (kk < k && fabs(Hs[(int64_t)kk * M1 + kk]) > thr) ++kk;
+    kk_s = kk;
+  }
+  for (int i = lane; i < k; i += 64) ys[i] = sv[i];
+  __syncthreads();
+  const int kk = kk_s;
+  for (int i = kk - 1; i >= 0; --i) {
+    if (lane == 0) ys[i] = ys[i] / Hs[(int64_t)i * M1 + i];
+    __syncthreads();
+    const double yi = ys[i];
+    for (int l = lane; l < i; l += 64) ys[l] -= Hs[(int64_t)i * M1 + l] * yi;
+    __syncthreads();
+  }
+  const bool useZ = a.precond != 0;
+  for (int i = lane; i < kk; i += 64)
+    a.y[(int64_t)s * m + i] = useZ ? ys[i] : ys[i] * a.sc[(int64_t)s * M1 + i];
+  if (lane == 0) {
+    S.kk = kk;
+    if (!S.force) S.restarts += 1;
+  }
+}
+
+// x += sum_i y_i v_i (float64 accumulation over the decoded basis), or
+// x += Z y in the flexible form.
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_update(KArgs a) {
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  const SysState& S = a.st[s];
+  if (!S.need_update && !S.force) return;
+  const int kk = S.kk;
+  const double* yv = a.y + (int64_t)s * a.m;
+  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
+  const bool useZ = a.precond != 0;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    double acc = a.x[r];
+    if (useZ) {
+      for (int i = 0; i < kk; ++i) acc += yv[i] * (double)a.Z[(int64_t)i * a.ld + r];
+    } else {
+      for (int i = 0; i < kk; ++i) acc += yv[i] * (double)ldv(col_ptr<TV>(a, i)[r]);
+    }
+    a.x[r] = acc;
+  }
+}
+
+// ||b||_2 per system; systems with b = 0 are done (x = 0).
+__global__ __launch_bounds__(kBlock) void k_bnorm(KArgs a) {
+  const int c = blockIdx.x;
+  const int s = a.ch_sys[c];
+  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
+  double sq = 0.0;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const double v = a.b[base + u * kBlock];
+    sq += v * v;
+  }
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) a.part[(int64_t)c * a.ps] = sq;
+  if (last_block(a.cnt + s, a.sys_nch[s])) {
+    __shared__ double red[1];
+    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], 1, -1, red);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      SysState& S = a.st[s];
+      S.bnorm = sqrt(red[0]);
+      if (S.bnorm == 0.0) {
+        S.status = CONVERGED;
+        S.rel = 0.0;
+      }
+      a.cnt[s] = 0;
+    }
+  }
+}
+
+__global__ void k_zero_x_if_b_zero(KArgs a) {
+  const int c = blockIdx.x;
+  const int s = a.ch_sys[c];
+  if (a.st[s].bnorm != 0.0) return;
+  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
+  for (int u = 0; u < kRowsPerThread; ++u) a.x[base + u * kBlock] = 0.0;
+}
+
+__global__ void k_init_state(KArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.S) return;
+  SysState S{};
+  S.active = 0;
+  S.status = RUNNING;
+  S.best_beta = INFINITY;
+  S.prev_beta = INFINITY;
+  S.precond_on = a.precond != 0 ? 1 : 0;
+  S.first_stall = -1;
+  a.st[s] = S;
+  a.cnt[s] = 0;
+}
+
+__global__ void k_set_force(KArgs a, int on) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < a.S) a.st[s].force = on;
+}
+
+// flags a column index outside its row's own system
+__global__ void k_check_cols(KArgs a, int32_t* bad) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.ld) return;
+  const int s = a.ch_sys[r / kChunk];
+  const int64_t lo = a.sys_row0[s], hi = lo + a.sys_n[s];
+  for (int k = a.rp[r]; k < a.rp[r + 1]; ++k) {
+    const int64_t c = a.ci[k];
+    if (c < lo || c >= hi) {
+      atomicOr(bad, 1);
+      return;
+    }
+  }
+}
+
+__global__ void k_convert_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) dst[k] = (float)src[k];
+}
+
+__global__ void k_jacobi_setup(KArgs a, float* dinv) {
+  // one thread per row of the real (unpadded) rows; padding stays 0
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.ld) return;
+  const int p0 = a.rp[r], p1 = a.rp[r + 1];
+  double d = 0.0;
+  for (int k = p0; k < p1; ++k)
+    if (a.ci[k] == r) d += a.a64[k];
+  dinv[r] = (p1 > p0 && d != 0.0) ? (float)(1.0 / d) : 0.0f;
+}
+
+__global__ void k_shift_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n,
+                            int32_t shift) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = i; k < n; k += stride) dst[k] = src[k] + shift;
+}
+
+__global__ void k_gather(const double* const* __restrict__ src, double* __restrict__ dst,
+                         const int64_t* __restrict__ row0, const int32_t* __restrict__ n) {
+  const int s = blockIdx.y;
+  const double* p = src[s];
+  const int64_t base = row0[s];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n[s];
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[base + i] = p[i];
+}
+
+__global__ void k_scatter(const double* __restrict__ src, double* const* __restrict__ dst,
+                          const int64_t* __restrict__ row0, const int32_t* __restrict__ n) {
+  const int s = blockIdx.y;
+  double* p = dst[s];
+  const int64_t base = row0[s];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n[s];
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = src[base + i];
+}
+
+__global__ void k_sumsq(const double* __restrict__ v, int64_t n, double* part) {
+  double sq = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    sq += v[i] * v[i];
+  sq = block_sum(sq);
+  if (threadIdx.x == 0) part[blockIdx.x] = sq;
+}
+
+__global__ void k_absmax(const float* __restrict__ v, int64_t n, float* part) {
+  float mx = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    mx = fmaxf(mx, fabsf(v[i]));
+  mx = block_max(mx);
+  if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+template <typename TV>
+__global__ void k_encode_plain(const float* __restrict__ w, int64_t n, float f, TV* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = stv<TV>(w[i] * f);
+}
+
+template <typename TV>
+__global__ void k_decode_column(KArgs a, int sys, int col, double* out) {
+  const int64_t row0 = a.sys_row0[sys];
+  const int n = a.sys_n[sys];
+  const double sc = a.sc[(int64_t)sys * (a.m + 1) + col];
+  const TV* v = col_ptr<TV>(a, col);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = sc * (double)ldv(v[row0 + i]);
+}
+
+// ----------------------------------------------------------------- launchers
+
+static inline int lanes_for(int ncol) {
+  int L = 8;
+  while (L < ncol && L < 64) L *= 2;
+  return L;
+}
+
+template <typename F>
+static hipError_t launch_by_prec(int prec, F&& f) {
+  switch (prec) {
+    case P64: return f(double{}, double{});
+    case P32: return f(float{}, float{});
+    case PBF16: return f(bf16_t{}, float{});
+    case PF16: return f(f16_t{}, float{});
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
+  const size_t sh = (size_t)a.spmv_budget * (a.prec == P64 ? 8 : 4);
+  if (a.precond != 0) {  // w = A z_j
+    hipLaunchKernelGGL((k_spmv<float, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                       a.a32, a.Z + (int64_t)j * a.ld, (float*)a.w, nullptr, j);
+    return hipGetLastError();
+  }
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
+    if constexpr (sizeof(TW) == 8) {
+      hipLaunchKernelGGL((k_spmv<double, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                         a.a64, x, (TW*)a.w, nullptr, j);
+    } else {
+      hipLaunchKernelGGL((k_spmv<float, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                         a.a32, x, (TW*)a.w, nullptr, j);
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
+  if (a.precond == 0) return hipSuccess;
+  return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
+    using TV = decltype(tv);
+    if (a.precond == 1) {
+      hipLaunchKernelGGL((k_jacobi<TV>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j);
+    } else {
+      const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
+      hipLaunchKernelGGL((k_spmv<float, TV, float, SM_PRECOND>), dim3(a.nrb), dim3(kBlock),
+                         (size_t)a.spmv_budget * 4, st, a, a.mval, x, a.Z + (int64_t)j * a.ld, nullptr, j);
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_residual(const KArgs& a, hipStream_t st) {
+  const size_t sh = (size_t)a.spmv_budget * 8;
+  return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
+    using TV = decltype(tv);
+    if constexpr (sizeof(TV) == 2) {
+      hipLaunchKernelGGL((k_spmv<double, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st,
+                         a, a.a64, a.x, (float*)a.w, a.b, 0);
+    } else {
+      hipLaunchKernelGGL((k_spmv<double, double, TV, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                         a.a64, a.x, (TV*)a.V, a.b, 0);
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_encode(const KArgs& a, int col, hipStream_t st) {
+  if (a.prec == PBF16)
+    hipLaunchKernelGGL((k_encode<bf16_t>), dim3(a.nchunk), dim3(kBlock), 0, st, a, col);
+  else if (a.prec == PF16)
+    hipLaunchKernelGGL((k_encode<f16_t>), dim3(a.nchunk), dim3(kBlock), 0, st, a, col);
+  return hipGetLastError();
+}
+
+template <typename TV, typename TW>
+static hipError_t launch_mdot_window(const KArgs& a, int j, int col0, int mode, int L, hipStream_t st) {
+  switch (L) {
+    case 8: hipLaunchKernelGGL((k_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
+    case 16: hipLaunchKernelGGL((k_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
+    case 32: hipLaunchKernelGGL((k_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
+    default: hipLaunchKernelGGL((k_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st) {
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const int ncol = j + 1;
+    if (ncol <= 64) return launch_mdot_window<TV, TW>(a, j, 0, 1, lanes_for(ncol), st);
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+      hipError_t e = launch_mdot_window<TV, TW>(a, j, c0, 1, 64, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+}
+
+hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st) {
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const int ncol = j + 1;
+    if (ncol <= 64) {
+      switch (lanes_for(ncol)) {
+        case 8: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        case 16: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        case 32: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        default: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+      }
+      return hipGetLastError();
+    }
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+      hipLaunchKernelGGL((k_axpy<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, c0);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+      hipError_t e = launch_mdot_window<TV, TW>(a, j, c0, 2, 64, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+}
+
+hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st) {
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    hipLaunchKernelGGL((k_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i0);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st) {
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    hipLaunchKernelGGL((k_mgs<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_backsolve(const KArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_backsolve, dim3(a.S), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const KArgs& a, hipStream_t st) {
+  return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
+    using TV = decltype(tv);
+    hipLaunchKernelGGL((k_update<TV>), dim3(a.nchunk), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_bnorm(const KArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_bnorm, dim3(a.nchunk), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(k_zero_x_if_b_zero, dim3(a.nchunk), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_state(const KArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_state, dim3((a.S + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_force(const KArgs& a, int on, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_force, dim3((a.S + 255) / 256), dim3(256), 0, st, a, on);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_cols(const KArgs& a, int32_t* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_cols, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  if (blocks > 0) hipLaunchKernelGGL(k_convert_f32, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_setup, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, dinv);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st) {
+  if (prec == P64) {
+    hipLaunchKernelGGL((k_spmv<double, double, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock),
+                       (size_t)a.spmv_budget * 8, st, a, a.a64, (const double*)x, (double*)y, nullptr, 0);
+  } else {
+    hipLaunchKernelGGL((k_spmv<float, float, float, SM_PLAIN>), dim3(a.nrb), dim3(kBlock),
+                       (size_t)a.spmv_budget * 4, st, a, a.a32, (const float*)x, (float*)y, nullptr, 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL((k_spmv<double, double, double, SM_RESID_PLAIN>), dim3(a.nrb), dim3(kBlock),
+                     (size_t)a.spmv_budget * 8, st, a, a.a64, x, r, b, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double* v, int64_t n, double* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nblk), dim3(kBlock), 0, st, v, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const float* w, int64_t n, float* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(kBlock), 0, st, w, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_plain(int prec, int64_t n, const float* w, float f, void* out, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  if (blocks == 0) return hipSuccess;
+  if (prec == PBF16)
+    hipLaunchKernelGGL((k_encode_plain<bf16_t>), dim3(blocks), dim3(256), 0, st, w, n, f, (bf16_t*)out);
+  else
+    hipLaunchKernelGGL((k_encode_plain<f16_t>), dim3(blocks), dim3(256), 0, st, w, n, f, (f16_t*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_column(const KArgs& a, int sys, int col, double* out, hipStream_t st) {
+  return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
+    using TV = decltype(tv);
+    hipLaunchKernelGGL((k_decode_column<TV>), dim3(256), dim3(256), 0, st, a, sys, col, out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_shift_cols(const int32_t* src, int32_t* dst, int64_t nnz, int32_t shift, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<int64_t>((nnz + 255) / 256, 65536);
+  if (blocks > 0) hipLaunchKernelGGL(k_shift_i32, dim3(blocks), dim3(256), 0, st, src, dst, nnz, shift);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_rowptr(const int32_t* src, int32_t* dst, int64_t n, int32_t shift, hipStream_t st) {
+  return launch_shift_cols(src, dst, n, shift, st);
+}
+
+hipError_t launch_gather(const double* const* src, double* dst, const int64_t* row0, const int32_t* n,
+                         int S, int64_t maxn, hipStream_t st) {
+  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxn + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_gather, dim3(bx, S), dim3(256), 0, st, src, dst, row0, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double* src, double* const* dst, const int64_t* row0, const int32_t* n,
+                          int S, int64_t maxn, hipStream_t st) {
+  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxn + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_scatter, dim3(bx, S), dim3(256), 0, st, src, dst, row0, n);
+  return hipGetLastError();
+}
+
+}  // namespace gm

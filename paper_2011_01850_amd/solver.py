@@ -1,0 +1,243 @@
+"""Python front end of libgmres: device memory via torch, every step in the HIP library.
+
+The classes only move arguments across the C-ABI: they allocate torch
+tensors on the GPU for inputs and outputs and pass their device pointers.
+No part of the solve runs in Python, and there is no CPU fallback: without
+a GPU or without the built library the constructors raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("libgmres needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _dev(t, dtype, torch):
+    """A contiguous device tensor of the given dtype (copies numpy / host input)."""
+    if isinstance(t, torch.Tensor):
+        t = t.to(device="cuda", dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(t), dtype=dtype, device="cuda")
+    return t.contiguous()
+
+
+def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
+             autotune) -> L.Options:
+    o = L.default_options()
+    o.m = int(m)
+    o.tol = float(tol)
+    o.max_iters = int(max_iters)
+    o.ortho = L.ORTHOS[ortho] if isinstance(ortho, str) else int(ortho)
+    o.precision = L.PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.precond = L.PRECONDS[precond] if isinstance(precond, str) else int(precond)
+    o.restart_improve = float(restart_improve)
+    o.stall_cycles = int(stall_cycles)
+    o.use_graph = int(bool(use_graph))
+    o.autotune = int(bool(autotune))
+    return o
+
+
+class Solver:
+    """Restarted GMRES(m) for one sparse system A x = b on the current GPU."""
+
+    def __init__(self, row_ptr, col_idx, vals, m=50, tol=1e-10, ortho="cgsr", precision="fp32",
+                 precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=3,
+                 use_graph=True, autotune=True):
+        torch = _torch()
+        self._torch = torch
+        self.lib = L.load()
+        rp = _dev(row_ptr, torch.int32, torch)
+        ci = _dev(col_idx, torch.int32, torch)
+        va = _dev(vals, torch.float64, torch)
+        self.n = int(rp.numel() - 1)
+        self.nnz = int(ci.numel())
+        self.m = int(m)
+        self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
+                            use_graph, autotune)
+        h = C.c_void_p()
+        stream = torch.cuda.current_stream().cuda_stream
+        torch.cuda.synchronize()
+        rc = self.lib.gmres_create(C.byref(h), self.n, self.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr(),
+                                   C.byref(self.opt), C.c_void_p(stream))
+        L.check(rc, "gmres_create")
+        self.h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gmres_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- solve
+    def solve(self, b, x0=None):
+        """Returns (x, info): x a float64 device tensor, info a dict (status, iters, ...)."""
+        torch = self._torch
+        bt = _dev(b, torch.float64, torch)
+        x = torch.zeros(self.n, dtype=torch.float64, device="cuda") if x0 is None else \
+            _dev(x0, torch.float64, torch).clone()
+        torch.cuda.synchronize()
+        res = L.Result()
+        L.check(self.lib.gmres_solve(self.h, bt.data_ptr(), x.data_ptr(), C.byref(res)), "gmres_solve")
+        return x, res.as_dict()
+
+    def set_preconditioner(self, spai_vals):
+        torch = self._torch
+        v = _dev(spai_vals, torch.float32, torch)
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_set_preconditioner(self.h, v.data_ptr()), "gmres_set_preconditioner")
+
+    def residual(self, b, x):
+        """(r, ||r||) with r = b - A x in float64 on the GPU."""
+        torch = self._torch
+        bt = _dev(b, torch.float64, torch)
+        xt = _dev(x, torch.float64, torch)
+        r = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        nrm = C.c_double()
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_residual(self.h, bt.data_ptr(), xt.data_ptr(), r.data_ptr(), C.byref(nrm)),
+                "gmres_residual")
+        return r, nrm.value
+
+    def spmv(self, x, precision="fp64"):
+        torch = self._torch
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        xt = _dev(x, dt, torch)
+        y = torch.empty(self.n, dtype=dt, device="cuda")
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_spmv(self.h, L.PRECISIONS[precision], xt.data_ptr(), y.data_ptr()), "gmres_spmv")
+        return y
+
+    def last_cycle(self, with_basis=True):
+        """(k, Hbar [(m+1) x m numpy], V [n x (k+1)] device tensor or None)."""
+        torch = self._torch
+        k = C.c_int32()
+        Hb = np.zeros((self.m, self.m + 1), dtype=np.float64)  # column-major storage
+        L.check(self.lib.gmres_last_cycle(self.h, 0, C.byref(k), Hb.ctypes.data, None), "gmres_last_cycle")
+        V = None
+        if with_basis:
+            V = torch.zeros((self.m + 1, self.n), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            L.check(self.lib.gmres_last_cycle(self.h, 0, None, None, V.data_ptr()), "gmres_last_cycle")
+            V = V[: k.value + 1].T
+        return k.value, Hb.T.copy(), V
+
+    def history(self, cap=4096):
+        out = np.zeros(cap, dtype=np.float64)
+        cnt = C.c_int32()
+        L.check(self.lib.gmres_history(self.h, 0, out.ctypes.data, cap, C.byref(cnt)), "gmres_history")
+        return out[: min(cnt.value, cap)].copy()
+
+    def memory_bytes(self):
+        v = C.c_size_t()
+        L.check(self.lib.gmres_memory_bytes(self.h, C.byref(v)), "gmres_memory_bytes")
+        return int(v.value)
+
+    def time_kernel(self, kernel, j, reps=20):
+        """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""
+        ms = C.c_double()
+        by = C.c_double()
+        L.check(self.lib.gmres_time_kernel(self.h, int(kernel), int(j), int(reps), C.byref(ms), C.byref(by)),
+                "gmres_time_kernel")
+        return ms.value, by.value
+
+
+class BatchSolver:
+    """Many independent systems advanced together by every kernel launch."""
+
+    def __init__(self, systems, m=40, tol=1e-10, ortho="mgs", precision="fp32", precond="none",
+                 max_iters=100_000, restart_improve=0.0, stall_cycles=3, use_graph=True, autotune=True):
+        torch = _torch()
+        self._torch = torch
+        self.lib = L.load()
+        self._keep = []
+        ns, nnzs, rps, cis, vas = [], [], [], [], []
+        for (rp, ci, va) in systems:
+            rp = _dev(rp, torch.int32, torch)
+            ci = _dev(ci, torch.int32, torch)
+            va = _dev(va, torch.float64, torch)
+            self._keep += [rp, ci, va]
+            ns.append(rp.numel() - 1)
+            nnzs.append(ci.numel())
+            rps.append(rp.data_ptr())
+            cis.append(ci.data_ptr())
+            vas.append(va.data_ptr())
+        S = len(ns)
+        self.S = S
+        self.ns = ns
+        self.m = int(m)
+        self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
+                            use_graph, autotune)
+        arr64 = C.c_int64 * S
+        arrp = C.c_void_p * S
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        rc = self.lib.gmres_batch_create(C.byref(h), S, arr64(*ns), arr64(*nnzs), arrp(*rps), arrp(*cis),
+                                         arrp(*vas), C.byref(self.opt), None)
+        self._keep = []
+        L.check(rc, "gmres_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.gmres_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, bs, x0s=None):
+        """Returns (list of x device tensors, list of info dicts)."""
+        torch = self._torch
+        bt = [_dev(b, torch.float64, torch) for b in bs]
+        xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for n in self.ns] if x0s is None else \
+            [_dev(x, torch.float64, torch).clone() for x in x0s]
+        arrp = C.c_void_p * self.S
+        res = (L.Result * self.S)()
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_batch_solve(self.h, arrp(*[t.data_ptr() for t in bt]),
+                                           arrp(*[t.data_ptr() for t in xs]), res), "gmres_batch_solve")
+        return xs, [r.as_dict() for r in res]
+
+    def history(self, sys, cap=4096):
+        out = np.zeros(cap, dtype=np.float64)
+        cnt = C.c_int32()
+        L.check(self.lib.gmres_history(self.h, int(sys), out.ctypes.data, cap, C.byref(cnt)), "gmres_history")
+        return out[: min(cnt.value, cap)].copy()
+
+
+def encode(w, inv_h, fmt="fp16"):
+    """2-byte basis storage of v = w * inv_h exactly as the solver does it: (uint16 tensor, scale)."""
+    torch = _torch()
+    lib = L.load()
+    wt = _dev(w, torch.float32, torch)
+    out = torch.empty(wt.numel(), dtype=torch.int16, device="cuda")
+    sc = C.c_double()
+    torch.cuda.synchronize()
+    L.check(lib.gmres_encode(L.PRECISIONS[fmt], wt.numel(), wt.data_ptr(), float(inv_h), out.data_ptr(),
+                             C.byref(sc), C.c_void_p(torch.cuda.current_stream().cuda_stream)), "gmres_encode")
+    return out, sc.value

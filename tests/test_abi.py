@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library: it loads, exports what the header declares,
+and rejects bad arguments before touching the GPU (no compute calls here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2011_01850_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gmres.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gmres_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares every one of them
+    assert set(names) == set(L._SIGS), set(names) ^ set(L._SIGS)
+
+
+def test_default_options(lib):
+    o = L.default_options()
+    assert (o.m, o.tol, o.max_iters) == (50, 1e-10, 100000)
+    assert o.ortho == L.CGSR and o.precision == L.MIXED_FP32 and o.precond == L.PRECOND_NONE
+    assert o.restart_improve == 0.0 and o.stall_cycles == 3 and o.use_graph == 1 and o.autotune == 1
+
+
+def test_strerror(lib):
+    assert L.strerror(0) == "ok"
+    assert "invalid" in L.strerror(L.EINVAL)
+    assert "handle" in L.strerror(L.EHANDLE)
+    assert L.strerror(-99) == "unknown error"
+
+
+def test_invalid_arguments_rejected_before_device_work(lib):
+    o = L.default_options()
+    h = C.c_void_p()
+    assert lib.gmres_create(C.byref(h), 0, 0, None, None, None, C.byref(o), None) == L.EINVAL
+    assert lib.gmres_create(C.byref(h), 10, 5, None, None, None, C.byref(o), None) == L.EINVAL
+    assert lib.gmres_create(None, 10, 5, 1, 1, 1, C.byref(o), None) == L.EINVAL
+    for field, bad in [("m", 0), ("m", 257), ("tol", -1.0), ("ortho", 7), ("precision", 9),
+                       ("precond", 5), ("stall_cycles", 0), ("restart_improve", -0.5)]:
+        ob = L.default_options()
+        setattr(ob, field, bad)
+        assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
+    # preconditioning is defined for the mixed modes only
+    ob = L.default_options()
+    ob.precision = L.FP64
+    ob.precond = L.PRECOND_JACOBI
+    assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL
+    assert lib.gmres_encode(L.FP64, 10, 1, 1.0, 1, None, None) == L.EINVAL
+    assert lib.gmres_encode(L.MIXED_FP16, 10, 1, 0.0, 1, None, None) == L.EINVAL
+
+
+def test_handle_checks(lib):
+    assert lib.gmres_destroy(None) == L.OK
+    r = L.Result()
+    assert lib.gmres_solve(None, 1, 1, C.byref(r)) == L.EHANDLE
+    v = C.c_size_t()
+    assert lib.gmres_memory_bytes(None, C.byref(v)) == L.EHANDLE
+    # a pointer to something that is not a handle
+    junk = (C.c_uint32 * 64)()
+    assert lib.gmres_memory_bytes(C.cast(junk, C.c_void_p), C.byref(v)) == L.EHANDLE
+
+
+def test_struct_layouts_match_header():
+    # offsets that C gives the two structs on x86-64
+    assert C.sizeof(L.Options) == 64
+    assert L.Options.tol.offset == 8 and L.Options.max_iters.offset == 16
+    assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
+    assert C.sizeof(L.Result) == 48
+    assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44

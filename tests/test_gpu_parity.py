@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Floating-point outcomes are compared where the method defines them (the
+float64 residual, the solution, the Arnoldi relation of the GPU's own basis);
+integer-valued inputs give exact sums, so kernels are compared bitwise there.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import problems as P
+from oracle import gmres as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU-only hosts
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2011_01850_amd import _lib as L  # noqa: E402
+from paper_2011_01850_amd.solver import BatchSolver, Solver, encode  # noqa: E402
+
+
+def _solver(A, **kw):
+    return Solver(A.row_ptr, A.col_idx, A.vals, **kw)
+
+
+def _relres(A, b, x):
+    return O.relative_residual(O.Matrix.from_csr(A), b, x)
+
+
+def _int_csr(n, seed, long_rows=()):
+    """Integer-valued CSR with empty rows, ragged row lengths and optional long rows."""
+    g = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for i in range(n):
+        if i % 97 == 13:
+            continue  # empty row
+        L_ = int(g.integers(1, 12)) if i not in long_rows else 5000
+        cs = np.unique(g.integers(0, n, L_))
+        rows += [i] * cs.size
+        cols += list(cs)
+        vals += list(g.integers(-8, 9, cs.size).astype(float))
+    rows = np.array(rows)
+    order = np.lexsort((np.array(cols), rows))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp)
+    return P.CSR(n, rp.astype(np.int32), np.array(cols)[order].astype(np.int32),
+                 np.array(vals)[order].astype(np.float64))
+
+
+@pytest.mark.parametrize("n,long_rows", [(5000, ()), (7001, (3, 4000)), (33, ())])
+def test_spmv_integer_inputs_bitwise(n, long_rows):
+    A = _int_csr(n, n, long_rows)
+    M = O.Matrix.from_csr(A)
+    g = np.random.default_rng(1)
+    x = g.integers(-16, 17, n).astype(np.float64)
+    s = _solver(A, precision="fp32", m=4)
+    y64 = s.spmv(x, "fp64").cpu().numpy()
+    y32 = s.spmv(x.astype(np.float32), "fp32").cpu().numpy()
+    ref = M.matvec(x)
+    assert np.array_equal(y64, ref)
+    assert np.array_equal(y32, ref.astype(np.float32))
+    b = g.integers(-100, 101, n).astype(np.float64)
+    r, nrm = s.residual(b, x)
+    assert np.array_equal(r.cpu().numpy(), b - ref)
+    assert math.isclose(nrm, float(np.linalg.norm(b - ref)), rel_tol=1e-14)
+    s.close()
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+def test_encode_bitwise_against_oracle(fmt):
+    g = np.random.default_rng(2)
+    for n, mag in [(1, 3.0), (1000, 1e-3), (65537, 7.0), (4096, 1e12)]:
+        w = (g.standard_normal(n) * mag).astype(np.float32)
+        h = float(np.linalg.norm(w.astype(np.float64)))
+        st, sc = encode(w, 1.0 / h, fmt)
+        ref, rsc = O.encode(w, 1.0 / h, fmt)
+        bits = st.cpu().numpy().view(np.uint16)
+        if fmt == "fp16":
+            got = bits.view(np.float16).astype(np.float32)
+        else:
+            got = (bits.astype(np.uint32) << 16).view(np.float32)
+        assert sc == rsc
+        assert np.array_equal(got, ref)
+
+
+def _parity_case(A, b, m, ortho, precision, tol=1e-13, max_iters=20000, **kw):
+    s = _solver(A, m=m, ortho=ortho, precision=precision, tol=tol, max_iters=max_iters, **kw)
+    x, info = s.solve(b)
+    s.close()
+    return x.cpu().numpy(), info
+
+
+CASES = [
+    ("c1_2d64", lambda: P.c1_convdiff2d(64), 50),
+    ("3d17_ragged", lambda: P.Problem("3d17", P.convdiff(17, (50.0, 20.0, 10.0)), None, None, 20, 0, ""), 20),
+    ("powerlaw_6000", lambda: P.Problem("pl", P.powerlaw(6000, family=93), None, None, 30, 0, ""), 30),
+]
+
+
+def _case(name):
+    for nm, mk, m in CASES:
+        if nm == name:
+            pr = mk()
+            if pr.b is None:
+                xt, b = P.manufactured_rhs(pr.A, 97, 0)
+                pr.b, pr.x_true = b, xt
+            return pr, m
+    raise KeyError(name)
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle_x(name, ortho):
+    key = (name, ortho)
+    if key not in _ORACLE_CACHE:
+        pr, m = _case(name)
+        r = O.gmres(O.Matrix.from_csr(pr.A), pr.b, m=m, tol=1e-13, ortho=ortho)
+        assert r.status == O.CONVERGED
+        _ORACLE_CACHE[key] = r
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("name", [c[0] for c in CASES])
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
+def test_solver_matches_oracle(name, ortho, precision):
+    pr, m = _case(name)
+    ref = _oracle_x(name, ortho)
+    x, info = _parity_case(pr.A, pr.b, m, ortho, precision)
+    print(f"{name} {ortho} {precision}: gpu iters {info['iters']} restarts {info['restarts']} "
+          f"relres {info['rel_residual']:.3e} | oracle fp64 iters {ref.iters}", flush=True)
+    assert info["status"] == "CONVERGED"
+    rr = _relres(pr.A, pr.b, x)
+    assert rr <= 1e-13 * 1.01
+    assert info["rel_residual"] == pytest.approx(rr, rel=1e-6)
+    err = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    assert err <= 1e-8
+    if precision == "fp64":
+        # same method and precision: the counts agree up to reduction-order effects
+        assert abs(info["iters"] - ref.iters) <= max(2, ref.iters // 50)
+
+
+@pytest.mark.parametrize("precision,u", [("fp64", O.U64), ("fp32", O.U32)])
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_gpu_basis_satisfies_arnoldi_relation(precision, u, ortho):
+    A = P.convdiff(24, (20.0, 10.0))
+    M = O.Matrix.from_csr(A)
+    D = M.dense()
+    b = np.random.default_rng(3).standard_normal(A.n)
+    m = 30
+    s = _solver(A, m=m, ortho=ortho, precision=precision, tol=0.0, max_iters=m)
+    s.solve(b)
+    k, Hb, V = s.last_cycle()
+    s.close()
+    V = V.cpu().numpy()
+    assert k == m
+    R = D @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k]
+    # the float32 basis is stored unnormalised; its decode scale is exact to u32
+    assert np.linalg.norm(R) <= 10 * k * u * np.linalg.norm(D) * (50 if precision == "fp32" else 1)
+    orth = np.linalg.norm(np.eye(k + 1) - V.T @ V, 2)
+    if ortho == "cgsr":
+        assert orth <= 10 * (k + 1) * u * (10 if precision == "fp32" else 1)
+    else:
+        assert orth < (1e-6 if precision == "fp64" else 1e-2)
+
+
+def test_edge_cases():
+    A = P.convdiff(20, (5.0, 1.0))
+    n = A.n
+    s = _solver(A, m=10, precision="fp32")
+    # b = 0: x = 0 without iterating, whatever x0 is
+    x, info = s.solve(np.zeros(n), x0=np.ones(n))
+    assert info["iters"] == 0 and info["status"] == "CONVERGED" and not x.abs().sum().item()
+    # iteration budget: stops at MAXITER with the budget spent exactly
+    b = np.ones(n)
+    s2 = _solver(A, m=10, precision="fp32", max_iters=7)
+    x, info = s2.solve(b)
+    assert info["status"] == "MAXITER" and info["iters"] == 7
+    assert np.all(np.isfinite(x.cpu().numpy()))
+    s.close()
+    s2.close()
+    # identity: converges after a couple of cycles (one in float64)
+    I = P.dense_to_csr(np.eye(300))
+    s3 = _solver(I, m=5, precision="fp64", tol=1e-14)
+    x, info = s3.solve(np.arange(300.0))
+    assert info["iters"] == 1 and np.allclose(x.cpu().numpy(), np.arange(300.0), rtol=1e-15)
+    s3.close()
+    # m = 1 and a 1 x 1 system
+    s4 = _solver(P.dense_to_csr(np.array([[4.0]])), m=1, precision="fp32", tol=1e-14)
+    x, info = s4.solve(np.array([2.0]))
+    assert info["status"] == "CONVERGED" and abs(x.item() - 0.5) < 1e-15
+    s4.close()
+
+
+def test_singular_system_stops_without_nan():
+    D = np.diag([1.0, 2.0, 3.0, 0.0, 5.0] * 20)
+    s = _solver(P.dense_to_csr(D + np.diag(np.ones(99), 1) * 0.0), m=10, precision="fp32",
+                max_iters=300)
+    x, info = s.solve(np.ones(100))
+    s.close()
+    assert info["status"] in ("MAXITER", "STALLED")
+    assert np.all(np.isfinite(x.cpu().numpy()))
+
+
+def test_deterministic_and_graph_equals_stream():
+    pr = P.c1_convdiff2d(48)
+    xs = []
+    for use_graph in (True, True, False):
+        s = _solver(pr.A, m=30, precision="fp32", ortho="cgsr", use_graph=use_graph, autotune=False)
+        x, info = s.solve(pr.b)
+        xs.append((x.cpu().numpy(), info["iters"]))
+        s.close()
+    assert all(np.array_equal(xs[0][0], x) and xs[0][1] == it for x, it in xs[1:])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_batch_equals_single_solves_bitwise(precision):
+    systems = [P.convdiff(N, beta) for N, beta in [(33, (10.0, 3.0)), (20, (0.0, 0.0)), (64, (80.0, 40.0)),
+                                                    (45, (1.0, 90.0))]]
+    rhs = [P.manufactured_rhs(A, 95, i)[1] for i, A in enumerate(systems)]
+    bs = BatchSolver([(A.row_ptr, A.col_idx, A.vals) for A in systems], m=20, ortho="mgs",
+                     precision=precision, autotune=False)
+    xb, infos = bs.solve(rhs)
+    bs.close()
+    for A, b, x, info in zip(systems, rhs, xb, infos):
+        s = _solver(A, m=20, ortho="mgs", precision=precision, autotune=False)
+        x1, i1 = s.solve(b)
+        s.close()
+        assert info["status"] == "CONVERGED" and i1["iters"] == info["iters"]
+        assert np.array_equal(x.cpu().numpy(), x1.cpu().numpy())
+
+
+def test_jacobi_fgmres_matches_oracle():
+    A0 = P.varcoef3d(16, family=94, index=0)
+    M = O.Matrix.from_csr(A0)
+    xt, b = P.manufactured_rhs(A0, 94, 0)
+    d = M.diagonal()
+    ref = O.gmres(M, b, m=30, tol=1e-11, precond=lambda v: v / d, fallback=False)
+    s = _solver(A0, m=30, precision="fp32", precond="jacobi", tol=1e-11)
+    x, info = s.solve(b)
+    s.close()
+    assert info["status"] == "CONVERGED"
+    assert _relres(A0, b, x.cpu().numpy()) <= 1.01e-11
+    assert abs(info["iters"] - ref.iters) <= 30
+    # the SPAI path with M = D^-1 on A's pattern is the same preconditioner
+    rows = np.repeat(np.arange(A0.n), np.diff(A0.row_ptr))
+    mv = np.where(A0.col_idx == rows, 1.0 / d[rows], 0.0).astype(np.float32)
+    s2 = _solver(A0, m=30, precision="fp32", precond="spai", tol=1e-11)
+    s2.set_preconditioner(mv)
+    x2, info2 = s2.solve(b)
+    s2.close()
+    assert info2["status"] == "CONVERGED" and info2["iters"] == info["iters"]
+    assert np.array_equal(x2.cpu().numpy(), x.cpu().numpy())
+
+
+def test_spai_nonfinite_values_fall_back_to_plain_gmres():
+    A0 = P.varcoef3d(12, family=94, index=1)
+    xt, b = P.manufactured_rhs(A0, 94, 1)
+    mv = np.full(A0.nnz, np.nan, dtype=np.float32)
+    s = _solver(A0, m=20, precision="fp32", precond="spai", tol=1e-10)
+    s.set_preconditioner(mv)
+    x, info = s.solve(b)
+    s.close()
+    assert info["fallback_used"] and info["status"] == "CONVERGED"
+    assert _relres(A0, b, x.cpu().numpy()) <= 1.01e-10

@@ -166,7 +166,7 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
   const KArgs& a = h->a;
   const bool two = a.prec == PBF16 || a.prec == PF16;
   hipError_t e = launch_residual(a, st);
-  if (e == hipSuccess && two) e = launch_encode(a, 0, st);
+  if (e == hipSuccess) e = launch_encode(a, 0, st);
   for (int j = 0; j < a.m && e == hipSuccess; ++j) {
     if (a.precond != 0) e = launch_precond(a, j, st);
     if (e == hipSuccess) e = launch_spmv_arnoldi(a, j, st);
@@ -745,7 +745,7 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
       case 2: bts = (j + 1) * n * sv + 2.0 * n * sw; break;
       case 3: bts = (j + 1) * n * sv + n * sw + n * (sv == 2 ? sw : sv); break;
       case 4: bts = (j > 0 ? 2.0 : 1.0) * n * sv + (j > 0 ? 2.0 : 1.0) * n * sw; break;
-      case 5: bts = nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * (sv == 2 ? sw : sv); break;
+      case 5: bts = nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * sw; break;
       case 6: bts = (j + 1) * n * sv + 16.0 * n; break;
       default: return GMRES_EINVAL;
     }

@@ -56,6 +56,15 @@ __device__ __forceinline__ bf16_t stv<bf16_t>(float v) {
 template <>
 __device__ __forceinline__ f16_t stv<f16_t>(float v) { return (f16_t)v; }  // v_cvt_f16_f32: RNE
 
+// The stored 2-byte value is round(float32(w * f)): the product is its own
+// float32 rounding, never fused with the conversion (v_fma_mix would round
+// the exact product once).
+__device__ __forceinline__ float mul_rn(float a, float b) {
+  float t = a * b;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 template <typename T>
 __device__ __forceinline__ T stw(double v);
 template <>
@@ -321,14 +330,16 @@ __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax
   const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
                    S.iters >= a.max_iters ||
                    (a.restart_improve > 0.0 && res <= a.restart_improve * S.beta);
-  if (!end) {
-    if (a.prec == PBF16 || a.prec == PF16) {
+  if (a.prec == PBF16 || a.prec == PF16) {
+    if (!end) {
       const int e = scale_exp(wmax / hn, a.prec);
       sc[j + 1] = ldexp(1.0, -e);
       S.enc_f = (float)(ldexp(1.0, e) / hn);
-    } else {
-      sc[j + 1] = 1.0 / hn;
     }
+  } else if (hn > 0.0) {
+    // w'' is already stored as column j+1; its scale also completes the
+    // last cycle's basis when the cycle ends here
+    sc[j + 1] = 1.0 / hn;
   }
   S.active = end ? 0 : 1;
 }
@@ -742,19 +753,23 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
   }
 }
 
-// 2-byte store of w as basis column col (scale prepared by the finaliser).
-template <typename TV>
+// Store w as basis column col: a 2-byte encoding with the scale prepared by
+// the finaliser, or a plain copy for the float32 / float64 basis.
+template <typename TV, typename TW>
 __global__ __launch_bounds__(kBlock) void k_encode(KArgs a, int col) {
   const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
   const int s = a.ch_sys[c];
   if (!gated(a, s)) return;
   const float f = a.st[s].enc_f;
-  const float* w = reinterpret_cast<const float*>(a.w);
+  const TW* w = reinterpret_cast<const TW*>(a.w);
   TV* out = reinterpret_cast<TV*>(a.V) + (int64_t)col * a.ld;
   const int64_t base = (int64_t)c * kChunk + threadIdx.x;
   for (int u = 0; u < kRowsPerThread; ++u) {
     const int64_t r = base + u * kBlock;
-    out[r] = stv<TV>(w[r] * f);
+    if constexpr (sizeof(TV) == 2)
+      out[r] = stv<TV>(mul_rn((float)w[r], f));
+    else
+      out[r] = (TV)w[r];
   }
 }
 
@@ -977,7 +992,7 @@ template <typename TV>
 __global__ void k_encode_plain(const float* __restrict__ w, int64_t n, float f, TV* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = stv<TV>(w[i] * f);
+    out[i] = stv<TV>(mul_rn(w[i], f));
 }
 
 template <typename TV>
@@ -1048,26 +1063,25 @@ hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
 }
 
 hipError_t launch_residual(const KArgs& a, hipStream_t st) {
+  // z goes to w; the cycle's first basis column is written from it only
+  // once the stop test has decided that a cycle starts (launch_encode)
   const size_t sh = (size_t)a.spmv_budget * 8;
-  return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
-    using TV = decltype(tv);
-    if constexpr (sizeof(TV) == 2) {
-      hipLaunchKernelGGL((k_spmv<double, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st,
-                         a, a.a64, a.x, (float*)a.w, a.b, 0);
-    } else {
-      hipLaunchKernelGGL((k_spmv<double, double, TV, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
-                         a.a64, a.x, (TV*)a.V, a.b, 0);
-    }
-    return hipGetLastError();
-  });
+  if (a.prec == P64)
+    hipLaunchKernelGGL((k_spmv<double, double, double, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                       a.a64, a.x, (double*)a.w, a.b, 0);
+  else
+    hipLaunchKernelGGL((k_spmv<double, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                       a.a64, a.x, (float*)a.w, a.b, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_encode(const KArgs& a, int col, hipStream_t st) {
-  if (a.prec == PBF16)
-    hipLaunchKernelGGL((k_encode<bf16_t>), dim3(a.nchunk), dim3(kBlock), 0, st, a, col);
-  else if (a.prec == PF16)
-    hipLaunchKernelGGL((k_encode<f16_t>), dim3(a.nchunk), dim3(kBlock), 0, st, a, col);
-  return hipGetLastError();
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    hipLaunchKernelGGL((k_encode<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, col);
+    return hipGetLastError();
+  });
 }
 
 template <typename TV, typename TW>

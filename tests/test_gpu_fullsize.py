@@ -1,0 +1,59 @@
+"""The benchmark workload at full size (128^3 convection-diffusion, n = 2,097,152)
+in the launch configuration bench.py times, checked by properties that hold at
+any size and by outputs the oracle computes one by one."""
+import numpy as np
+import pytest
+
+import problems as P
+from oracle import gmres as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2011_01850_amd.solver import Solver  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return P.c2_convdiff3d(128)
+
+
+def test_fullsize_spmv_rows_sampled(c2):
+    A = c2.A
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=50, ortho="cgsr", precision="fp32")
+    g = np.random.default_rng(7)
+    x = g.standard_normal(A.n)
+    y64 = s.spmv(x, "fp64").cpu().numpy()
+    y32 = s.spmv(x.astype(np.float32), "fp32").cpu().numpy()
+    s.close()
+    rows = np.concatenate([g.integers(0, A.n, 2000), [0, 1, A.n - 2, A.n - 1, 128 * 128 - 1]])
+    for r in rows:
+        lo, hi = A.row_ptr[r], A.row_ptr[r + 1]
+        ref = float(np.dot(A.vals[lo:hi], x[A.col_idx[lo:hi]]))
+        ref32 = float(np.dot(A.vals[lo:hi].astype(np.float32).astype(np.float64),
+                             x.astype(np.float32)[A.col_idx[lo:hi]].astype(np.float64)))
+        scale = float(np.abs(A.vals[lo:hi]).dot(np.abs(x[A.col_idx[lo:hi]])))
+        assert abs(y64[r] - ref) <= 8 * O.U64 * scale
+        assert abs(y32[r] - ref32) <= 8 * O.U32 * scale
+
+
+@pytest.mark.parametrize("ortho", ["cgsr", "mgs"])
+def test_fullsize_mixed_solve_reaches_1e10(c2, ortho):
+    A = c2.A
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=50, ortho=ortho, precision="fp32", tol=1e-10)
+    x, info = s.solve(c2.b)
+    hist = s.history()
+    s.close()
+    x = x.cpu().numpy()
+    rr = O.relative_residual(O.Matrix.from_csr(A), c2.b, x)
+    fwd = np.linalg.norm(x - c2.x_true) / np.linalg.norm(c2.x_true)
+    print(f"128^3 {ortho} fp32: {info['status']} iters {info['iters']} restarts {info['restarts']} "
+          f"relres {rr:.3e} forward error {fwd:.2e}", flush=True)
+    assert info["status"] == "CONVERGED"
+    assert rr <= 1e-10 * 1.001
+    assert info["rel_residual"] == pytest.approx(rr, rel=1e-6)
+    # restart residuals never increase (the convergence argument of the numerics section)
+    assert np.all(np.diff(hist) <= 0)

@@ -85,7 +85,8 @@ def roofline(solver, m, reps):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     # the rest of the step's kernels at the last column, for the report
     other = {}
-    for k, name in [(0, "spmv_arnoldi"), (1, "cgs_pass1"), (3, "final_pass"), (5, "residual64"), (6, "update64")]:
+    for k, name in [(0, "spmv_arnoldi"), (1, "cgs_pass1"), (3, "final_pass"), (5, "residual64"), (6, "update64"),
+                    (7, "finalize_pass2")]:
         ms, by = solver.time_kernel(k, m - 1, reps)
         other[name] = {"ms": round(ms, 5), "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
     return {

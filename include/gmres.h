@@ -181,7 +181,9 @@ int gmres_memory_bytes(gmres_handle h, size_t* bytes);
  * (the next gmres_solve starts afresh).  kernel: 0 = Arnoldi SpMV,
  * 1 = CGSR projection pass 1, 2 = CGSR projection pass 2, 3 = final
  * update + norm pass, 4 = MGS dot step (column j), 5 = float64 residual,
- * 6 = float64 solution update (j + 1 columns). */
+ * 6 = float64 solution update (j + 1 columns), 7 = the per-system reduction
+ * that completes projection pass 2 (kernels 1-5 are timed without their
+ * completing reduction, which the solver launches right after them). */
 int gmres_time_kernel(gmres_handle h, int32_t kernel, int32_t j, int32_t reps, double* avg_ms,
                       double* bytes);
 

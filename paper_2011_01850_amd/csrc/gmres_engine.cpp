@@ -12,7 +12,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/gmres.h"
+#include "gmres.h"
 #include "gmres_internal.hpp"
 
 using namespace gm;
@@ -122,6 +122,38 @@ void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r
   }
 }
 
+// Groups of consecutive workgroups (per system) for the two-level reduction.
+struct Groups {
+  std::vector<int32_t> grp, gfirst, gn, g0, ng;
+};
+
+Groups make_groups(const std::vector<int32_t>& first, const std::vector<int32_t>& count) {
+  int32_t mx = 1;
+  for (int32_t c : count) mx = std::max(mx, c);
+  int GS = 8;
+  while (GS < 256 && (int64_t)GS * GS < mx) GS *= 2;
+  Groups G;
+  for (size_t s = 0; s < first.size(); ++s) {
+    G.g0.push_back((int32_t)G.gfirst.size());
+    const int32_t nb = count[s];
+    int32_t ng = 0;
+    for (int32_t b = 0; b < nb; b += GS, ++ng) {
+      const int32_t n = std::min<int32_t>(GS, nb - b);
+      for (int32_t k = 0; k < n; ++k) G.grp.push_back((int32_t)G.gfirst.size());
+      G.gfirst.push_back(first[s] + b);
+      G.gn.push_back(n);
+    }
+    G.ng.push_back(ng);
+  }
+  return G;
+}
+
+int32_t* upload32(gmres_ctx* h, const std::vector<int32_t>& v) {
+  int32_t* d = h->alloc<int32_t>(std::max<size_t>(v.size(), 1));
+  if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+  return d;
+}
+
 void set_row_blocks(gmres_ctx* h, int budget) {
   std::vector<int32_t> rb, rb_sys;
   for (size_t k = 0; k < h->sys.size(); ++k) {
@@ -155,6 +187,12 @@ void set_row_blocks(gmres_ctx* h, int budget) {
   h->a.sys_nrb = d_nrb;
   h->a.nrb = h->nrb;
   h->a.spmv_budget = budget;
+  const Groups G = make_groups(rb0, nrb);
+  h->a.rb_grp = upload32(h, G.grp);
+  h->a.rb_gfirst = upload32(h, G.gfirst);
+  h->a.rb_gn = upload32(h, G.gn);
+  h->a.sys_rg0 = upload32(h, G.g0);
+  h->a.sys_rng = upload32(h, G.ng);
 }
 
 int64_t vbytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -326,6 +364,14 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.ch_sys = up32(ch_sys);
   a.sys_ch0 = up32(ch0);
   a.sys_nch = up32(nch);
+  {
+    const Groups G = make_groups(ch0, nch);
+    a.ch_grp = up32(G.grp);
+    a.ch_gfirst = up32(G.gfirst);
+    a.ch_gn = up32(G.gn);
+    a.sys_cg0 = up32(G.g0);
+    a.sys_cng = up32(G.ng);
+  }
   a.sys_n = up32(sn);
   {
     int64_t* d = h->alloc<int64_t>(nsys);
@@ -387,6 +433,9 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     for (const System& s : h->sys) build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, 1024, rbtmp);
     const int64_t maxblk = std::max<int64_t>((int64_t)rbtmp.size(), h->nchunk);
     a.part = h->alloc<double>((size_t)maxblk * a.ps);
+    a.part2 = h->alloc<double>((size_t)maxblk * a.ps);
+    a.gcnt = h->alloc<uint32_t>((size_t)maxblk);
+    hip_check(hipMemsetAsync(a.gcnt, 0, maxblk * 4, h->stream));
   }
   {
     int32_t* bad = h->alloc<int32_t>(1);
@@ -730,12 +779,13 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
     auto run = [&]() -> hipError_t {
       switch (kernel) {
         case 0: return launch_spmv_arnoldi(a, j, h->stream);
-        case 1: return launch_cgs_pass1(a, j, h->stream);
-        case 2: return launch_cgs_pass2(a, j, h->stream);
-        case 3: return launch_final_pass(a, j, 0, h->stream);
-        case 4: return launch_mgs_dot(a, j, j, h->stream);
-        case 5: return launch_residual(a, h->stream);
+        case 1: return launch_cgs_pass1(a, j, h->stream, false);
+        case 2: return launch_cgs_pass2(a, j, h->stream, false);
+        case 3: return launch_final_pass(a, j, 0, h->stream, false);
+        case 4: return launch_mgs_dot(a, j, j, h->stream, false);
+        case 5: return launch_residual(a, h->stream, false);
         case 6: return launch_update(a, h->stream);
+        case 7: return launch_finalize(a, 1, j, 0, h->stream);
       }
       return hipErrorInvalidValue;
     };
@@ -747,6 +797,7 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
       case 4: bts = (j > 0 ? 2.0 : 1.0) * n * sv + (j > 0 ? 2.0 : 1.0) * n * sw; break;
       case 5: bts = nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * sw; break;
       case 6: bts = (j + 1) * n * sv + 16.0 * n; break;
+      case 7: bts = (double)h->nchunk * (j + 1) * 8.0; break;
       default: return GMRES_EINVAL;
     }
     hip_check(launch_set_force(a, 1, h->stream));

@@ -14,6 +14,7 @@ constexpr int kBlock = 256;
 constexpr int kChunk = 2048;
 constexpr int kRowsPerThread = kChunk / kBlock;  // 8
 constexpr int kMaxM = 256;
+constexpr int kFinBlock = 1024;  // threads of the per-system finalise kernels
 constexpr int kHistCap = 4096;
 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
@@ -81,9 +82,24 @@ struct KArgs {
   void* w;        // work vector: double (P64) or float
   double* x;      // iterate
   double* b;      // right-hand side
+  // two-level reduction: each workgroup writes one row of `part`; the last
+  // workgroup of a group reduces the group's rows into one row of `part2`;
+  // the last group of a system reduces those rows and finalises the system
+  const int32_t* ch_grp;    // group of each chunk
+  const int32_t* ch_gfirst; // first chunk of each chunk group
+  const int32_t* ch_gn;     // chunks in each chunk group
+  const int32_t* sys_cg0;   // first chunk group of each system
+  const int32_t* sys_cng;   // chunk groups of each system
+  const int32_t* rb_grp;    // same for the SpMV row blocks
+  const int32_t* rb_gfirst;
+  const int32_t* rb_gn;
+  const int32_t* sys_rg0;
+  const int32_t* sys_rng;
   // scratch
-  double* part;   // partials [max(nchunk, nrb)][ps]
-  uint32_t* cnt;  // last-block counters, one per system
+  double* part;    // level-1 partials [max(nchunk, nrb)][ps]
+  double* part2;   // level-2 partials [max(groups)][ps]
+  uint32_t* gcnt;  // group counters
+  uint32_t* cnt;   // system counters
   SysState* st;
   double* H;      // rotated Hessenberg, (m+1) x m per system, column-major
   double* Hbar;   // unrotated copy
@@ -109,13 +125,15 @@ struct KArgs {
 // Each launcher enqueues one kernel on `st` and returns hipGetLastError().
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st);   // w = A v_j or A z_j
 hipError_t launch_precond(const KArgs& a, int j, hipStream_t st);        // z_j = M v_j
-hipError_t launch_residual(const KArgs& a, hipStream_t st);             // z = b - A x, start cycle
+hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin = true);             // z = b - A x, start cycle
 hipError_t launch_encode(const KArgs& a, int col, hipStream_t st);       // 2-byte store of w
-hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st);
-hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st);
-hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st);
-hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st);
+hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
+hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
+hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st, bool with_fin = true);
+hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st, bool with_fin = true);
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st);
+// mode: 0 CGS projection 1, 1 projection 2, 2 Givens step, 3 MGS dot, 4 residual
+hipError_t launch_finalize(const KArgs& a, int mode, int j, int i, hipStream_t st);
 hipError_t launch_update(const KArgs& a, hipStream_t st);
 hipError_t launch_bnorm(const KArgs& a, hipStream_t st);
 hipError_t launch_init_state(const KArgs& a, hipStream_t st);

@@ -148,58 +148,46 @@ __device__ __forceinline__ T reduce_scatter(T (&p)[L], int lane) {
   return v;
 }
 
-// True in the block that finishes last among `total` blocks sharing *cnt.
-// Partials written before the call are visible to that block afterwards.
-__device__ __forceinline__ bool last_block(uint32_t* cnt, int total) {
-  __shared__ int flag;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = atomicAdd(cnt, 1u);
-    flag = (prev + 1u == (uint32_t)total) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = flag != 0;
-  if (last) __threadfence();
-  return last;
-}
-
-// out[col] = sum (or max for col == maxcol) of part[(c0 + c) * ps + col] over
-// c in [0, nc), in a fixed order.  Called by all threads of one block.
-__device__ void reduce_partials(const double* part, int ps, int c0, int nc, int ncol, int maxcol,
-                                double* out) {
-  __shared__ double red[kBlock / 64][64];
-  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-  constexpr int G = kBlock / 64;
-  for (int base = 0; base < ncol; base += 64) {
+// out[col] = sum (or max for col == maxcol) over rows r in [0, R) of
+// p[(row0 + r) * ps + col], for col in [0, ncol).  All threads of the block
+// take part: columns across lanes, rows across lane groups (several loads in
+// flight per thread), then a fixed-order tree over the groups, so the result
+// does not depend on timing.
+__device__ void reduce_rows(const double* p, int ps, int row0, int R, int ncol, int maxcol, double* out) {
+  __shared__ double red[kFinBlock];
+  const int t = threadIdx.x;
+  const int NT = blockDim.x;
+  int CP = 1;
+  while (CP < ncol && CP < 64) CP *= 2;
+  const int RG = NT / CP;
+  const int lane = t % CP, rg = t / CP;
+  for (int base = 0; base < ncol; base += CP) {
     const int col = base + lane;
-    double a0 = 0.0, a1 = 0.0;
+    const bool isMax = col == maxcol;
+    double acc = 0.0;
     if (col < ncol) {
-      const double* p = part + (int64_t)c0 * ps + col;
-      int c = g;
-      if (col == maxcol) {
-        for (; c + G < nc; c += 2 * G) {
-          a0 = fmax(a0, p[(int64_t)c * ps]);
-          a1 = fmax(a1, p[(int64_t)(c + G) * ps]);
+      const double* q = p + (int64_t)row0 * ps + col;
+      double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int r = rg;
+      for (; r + 3 * RG < R; r += 4 * RG) {
+        const double v0 = q[(int64_t)r * ps], v1 = q[(int64_t)(r + RG) * ps];
+        const double v2 = q[(int64_t)(r + 2 * RG) * ps], v3 = q[(int64_t)(r + 3 * RG) * ps];
+        if (isMax) {
+          acc = fmax(acc, v0); a1 = fmax(a1, v1); a2 = fmax(a2, v2); a3 = fmax(a3, v3);
+        } else {
+          acc += v0; a1 += v1; a2 += v2; a3 += v3;
         }
-        if (c < nc) a0 = fmax(a0, p[(int64_t)c * ps]);
-        a0 = fmax(a0, a1);
-      } else {
-        for (; c + G < nc; c += 2 * G) {
-          a0 += p[(int64_t)c * ps];
-          a1 += p[(int64_t)(c + G) * ps];
-        }
-        if (c < nc) a0 += p[(int64_t)c * ps];
-        a0 += a1;
       }
+      for (; r < R; r += RG) acc = isMax ? fmax(acc, q[(int64_t)r * ps]) : acc + q[(int64_t)r * ps];
+      acc = isMax ? fmax(fmax(acc, a1), fmax(a2, a3)) : (acc + a1) + (a2 + a3);
     }
-    red[g][lane] = a0;
+    red[t] = acc;
     __syncthreads();
-    if (g == 0 && col < ncol) {
-      double r = red[0][lane];
-      for (int k = 1; k < G; ++k) r = (col == maxcol) ? fmax(r, red[k][lane]) : r + red[k][lane];
-      out[col] = r;
+    for (int h = RG >> 1; h >= 1; h >>= 1) {
+      if (rg < h) red[t] = isMax ? fmax(red[t], red[t + h * CP]) : red[t] + red[t + h * CP];
+      __syncthreads();
     }
+    if (rg == 0 && col < ncol) out[col] = red[lane];
     __syncthreads();
   }
 }
@@ -240,7 +228,7 @@ __device__ void fin_pass1(const KArgs& a, int s, int j, const double* red) {
   const double* sc = a.sc + (int64_t)s * M1;
   double* h1 = a.h1 + (int64_t)s * M2;
   double* coef = a.coef + (int64_t)s * M2;
-  for (int q = threadIdx.x; q <= j; q += kBlock) {
+  for (int q = threadIdx.x; q <= j; q += blockDim.x) {
     const double h = sc[q] * red[q];
     h1[q] = h;
     coef[q] = h * sc[q];
@@ -254,7 +242,7 @@ __device__ void fin_pass2(const KArgs& a, int s, int j, const double* red) {
   const double* h1 = a.h1 + (int64_t)s * M2;
   double* hc = a.hacc + (int64_t)s * M2;
   double* coef = a.coef + (int64_t)s * M2;
-  for (int q = threadIdx.x; q <= j; q += kBlock) {
+  for (int q = threadIdx.x; q <= j; q += blockDim.x) {
     const double h = sc[q] * red[q];
     hc[q] = h1[q] + h;
     coef[q] = h * sc[q];
@@ -465,18 +453,74 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
       a.part[(int64_t)blk * a.ps] = zsq;
       if (MODE == SM_RESID) a.part[(int64_t)blk * a.ps + 1] = zmax;
     }
-    if (MODE == SM_RESID) {
-      if (last_block(a.cnt + s, a.sys_nrb[s])) {
-        __shared__ double red[2];
-        reduce_partials(a.part, a.ps, a.sys_rb0[s], a.sys_nrb[s], 2, 1, red);
-        __syncthreads();
-        if (t == 0) {
-          fin_residual(a, s, red[0], red[1]);
-          a.cnt[s] = 0;
-        }
+
+  }
+}
+
+// ---------------------------------------------------------------- finalise
+// One workgroup per system reduces the per-workgroup partial rows that the
+// preceding pass wrote (the kernel boundary makes them visible) and runs the
+// system's scalar step.
+
+enum FinMode { FIN_PASS1 = 0, FIN_PASS2 = 1, FIN_STEP = 2, FIN_MGS = 3, FIN_RESID = 4, FIN_BNORM = 5 };
+
+template <int MODE>
+__global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, int j, int i) {
+  const int s = blockIdx.x;
+  const SysState& S = a.st[s];
+  if (MODE == FIN_RESID) {
+    if (S.status != RUNNING && !S.force) return;
+  } else if (MODE != FIN_BNORM) {
+    if (!S.active && !S.force) return;
+  }
+  __shared__ double red[kMaxM + 3];
+  const int t = threadIdx.x;
+  if (MODE == FIN_RESID) {
+    reduce_rows(a.part, a.ps, a.sys_rb0[s], a.sys_nrb[s], 2, 1, red);
+    if (t == 0) fin_residual(a, s, red[0], red[1]);
+    return;
+  }
+  const int c0 = a.sys_ch0[s], nc = a.sys_nch[s];
+  if (MODE == FIN_PASS1) {
+    reduce_rows(a.part, a.ps, c0, nc, j + 2, -1, red);
+    fin_pass1(a, s, j, red);
+  } else if (MODE == FIN_PASS2) {
+    reduce_rows(a.part, a.ps, c0, nc, j + 1, -1, red);
+    fin_pass2(a, s, j, red);
+  } else if (MODE == FIN_STEP) {
+    reduce_rows(a.part, a.ps, c0, nc, 2, 1, red);
+    if (t == 0) fin_step(a, s, j, red[0], red[1]);
+  } else if (MODE == FIN_MGS) {
+    reduce_rows(a.part, a.ps, c0, nc, i == 0 ? 2 : 1, -1, red);
+    fin_mgs(a, s, i, red);
+  } else {  // FIN_BNORM
+    reduce_rows(a.part, a.ps, c0, nc, 1, -1, red);
+    if (t == 0) {
+      SysState& W = a.st[s];
+      W.bnorm = sqrt(red[0]);
+      if (W.bnorm == 0.0) {
+        W.status = CONVERGED;
+        W.rel = 0.0;
       }
     }
   }
+}
+
+template <int MODE>
+static hipError_t launch_fin(const KArgs& a, int j, int i, hipStream_t st) {
+  hipLaunchKernelGGL((k_fin<MODE>), dim3(a.S), dim3(kFinBlock), 0, st, a, j, i);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const KArgs& a, int mode, int j, int i, hipStream_t st) {
+  switch (mode) {
+    case FIN_PASS1: return launch_fin<FIN_PASS1>(a, j, i, st);
+    case FIN_PASS2: return launch_fin<FIN_PASS2>(a, j, i, st);
+    case FIN_STEP: return launch_fin<FIN_STEP>(a, j, i, st);
+    case FIN_MGS: return launch_fin<FIN_MGS>(a, j, i, st);
+    case FIN_RESID: return launch_fin<FIN_RESID>(a, j, i, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------ basis passes
@@ -575,22 +619,9 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, int j, int col0, int m
     colsum += reduce_scatter<L>(p, lane);
   }
   store_colsums<L>(a, c, col0, ncol, colsum);
-  const bool last_window = col0 + L >= j + 1;
   if (col0 == 0 && mode == 1) {
     const ACC tot = block_sum(ww);
     if (t == 0) a.part[(int64_t)c * a.ps + j + 1] = (double)tot;
-  }
-  if (!last_window) return;
-  if (last_block(a.cnt + s, a.sys_nch[s])) {
-    __shared__ double red[kMaxM + 3];
-    const int nred = mode == 1 ? j + 2 : j + 1;
-    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], nred, -1, red);
-    __syncthreads();
-    if (mode == 1)
-      fin_pass1(a, s, j, red);
-    else
-      fin_pass2(a, s, j, red);
-    if (t == 0) a.cnt[s] = 0;
   }
 }
 
@@ -635,13 +666,6 @@ __global__ __launch_bounds__(kBlock) void k_axpy_mdot(KArgs a, int j) {
     colsum += reduce_scatter<L>(v, lane);
   }
   store_colsums<L>(a, c, 0, ncol, colsum);
-  if (last_block(a.cnt + s, a.sys_nch[s])) {
-    __shared__ double red[kMaxM + 3];
-    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], j + 1, -1, red);
-    __syncthreads();
-    fin_pass2(a, s, j, red);
-    if (t == 0) a.cnt[s] = 0;
-  }
 }
 
 // w -= V[:, col0:col0+L] coef (no reduction): the first half of projection 2
@@ -700,14 +724,57 @@ __global__ __launch_bounds__(kBlock) void k_final(KArgs a, int j, int i0) {
     a.part[(int64_t)c * a.ps] = tsq;
     a.part[(int64_t)c * a.ps + 1] = tmx;
   }
-  if (last_block(a.cnt + s, a.sys_nch[s])) {
-    __shared__ double red[2];
-    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], 2, 1, red);
-    __syncthreads();
-    if (t == 0) {
-      fin_step(a, s, j, red[0], red[1]);
-      a.cnt[s] = 0;
+}
+
+// The same last pass for CGSR with j + 1 <= L <= 64 columns: the whole tile
+// of basis loads is issued at once through the bounded buffer resource.
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, int j) {
+  using ACC = typename AccOf<TV>::type;
+  constexpr bool kTwoByte = sizeof(TV) == 2;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x;
+  const int ncol = j + 1;
+  TW* w = reinterpret_cast<TW*>(a.w);
+  const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, ncol);
+  const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
+  const double* coefd = a.coef + (int64_t)s * (a.m + 2);
+  __shared__ ACC cf[L];
+  if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
+  __syncthreads();
+  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
+  const int64_t base = (int64_t)c * kChunk + t;
+  ACC sq = (ACC)0, mx = (ACC)0;
+  uint32_t cs = cstride;
+#pragma unroll 1
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    asm volatile("" : "+s"(cs));
+    const int64_t r = base + u * kBlock;
+    const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
+    ACC v[L];
+    uint32_t so = 0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
+      if (q < ncol) so += cs;
     }
+    ACC wr = (ACC)w[r];
+#pragma unroll
+    for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
+    sq += wr * wr;
+    mx = fmax(mx, fabs(wr));
+    if constexpr (kTwoByte)
+      w[r] = (TW)wr;
+    else
+      vout[r] = (TV)wr;
+  }
+  const double tsq = (double)block_sum(sq);
+  const double tmx = (double)block_max(mx);
+  if (t == 0) {
+    a.part[(int64_t)c * a.ps] = tsq;
+    a.part[(int64_t)c * a.ps + 1] = tmx;
   }
 }
 
@@ -743,13 +810,6 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
   if (t == 0) {
     a.part[(int64_t)c * a.ps] = td;
     if (i == 0) a.part[(int64_t)c * a.ps + 1] = tw;
-  }
-  if (last_block(a.cnt + s, a.sys_nch[s])) {
-    __shared__ double red[2];
-    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], i == 0 ? 2 : 1, -1, red);
-    __syncthreads();
-    fin_mgs(a, s, i, red);
-    if (t == 0) a.cnt[s] = 0;
   }
 }
 
@@ -870,20 +930,6 @@ __global__ __launch_bounds__(kBlock) void k_bnorm(KArgs a) {
   }
   sq = block_sum(sq);
   if (threadIdx.x == 0) a.part[(int64_t)c * a.ps] = sq;
-  if (last_block(a.cnt + s, a.sys_nch[s])) {
-    __shared__ double red[1];
-    reduce_partials(a.part, a.ps, a.sys_ch0[s], a.sys_nch[s], 1, -1, red);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      SysState& S = a.st[s];
-      S.bnorm = sqrt(red[0]);
-      if (S.bnorm == 0.0) {
-        S.status = CONVERGED;
-        S.rel = 0.0;
-      }
-      a.cnt[s] = 0;
-    }
-  }
 }
 
 __global__ void k_zero_x_if_b_zero(KArgs a) {
@@ -1062,7 +1108,7 @@ hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
   });
 }
 
-hipError_t launch_residual(const KArgs& a, hipStream_t st) {
+hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {
   // z goes to w; the cycle's first basis column is written from it only
   // once the stop test has decided that a cycle starts (launch_encode)
   const size_t sh = (size_t)a.spmv_budget * 8;
@@ -1072,7 +1118,9 @@ hipError_t launch_residual(const KArgs& a, hipStream_t st) {
   else
     hipLaunchKernelGGL((k_spmv<double, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
                        a.a64, a.x, (float*)a.w, a.b, 0);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !with_fin) return e;
+  return launch_fin<FIN_RESID>(a, 0, 0, st);
 }
 
 hipError_t launch_encode(const KArgs& a, int col, hipStream_t st) {
@@ -1095,22 +1143,24 @@ static hipError_t launch_mdot_window(const KArgs& a, int j, int col0, int mode, 
   return hipGetLastError();
 }
 
-hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st) {
-  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin) {
+  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     const int ncol = j + 1;
     if (ncol <= 64) return launch_mdot_window<TV, TW>(a, j, 0, 1, lanes_for(ncol), st);
     for (int c0 = 0; c0 < ncol; c0 += 64) {
-      hipError_t e = launch_mdot_window<TV, TW>(a, j, c0, 1, 64, st);
-      if (e != hipSuccess) return e;
+      hipError_t e2 = launch_mdot_window<TV, TW>(a, j, c0, 1, 64, st);
+      if (e2 != hipSuccess) return e2;
     }
     return hipSuccess;
   });
+  if (e != hipSuccess || !with_fin) return e;
+  return launch_fin<FIN_PASS1>(a, j, 0, st);
 }
 
-hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st) {
-  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin) {
+  hipError_t e0 = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     const int ncol = j + 1;
@@ -1134,24 +1184,39 @@ hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st) {
     }
     return hipSuccess;
   });
+  if (e0 != hipSuccess || !with_fin) return e0;
+  return launch_fin<FIN_PASS2>(a, j, 0, st);
 }
 
-hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st) {
-  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st, bool with_fin) {
+  hipError_t e0 = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
-    hipLaunchKernelGGL((k_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i0);
+    if (i0 == 0 && j + 1 <= 64) {
+      switch (lanes_for(j + 1)) {
+        case 8: hipLaunchKernelGGL((k_final_tile<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        case 16: hipLaunchKernelGGL((k_final_tile<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        case 32: hipLaunchKernelGGL((k_final_tile<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        default: hipLaunchKernelGGL((k_final_tile<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+      }
+    } else {
+      hipLaunchKernelGGL((k_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i0);
+    }
     return hipGetLastError();
   });
+  if (e0 != hipSuccess || !with_fin) return e0;
+  return launch_fin<FIN_STEP>(a, j, 0, st);
 }
 
-hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st) {
-  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st, bool with_fin) {
+  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     hipLaunchKernelGGL((k_mgs<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i);
     return hipGetLastError();
   });
+  if (e != hipSuccess || !with_fin) return e;
+  return launch_fin<FIN_MGS>(a, j, i, st);
 }
 
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st) {
@@ -1169,6 +1234,7 @@ hipError_t launch_update(const KArgs& a, hipStream_t st) {
 
 hipError_t launch_bnorm(const KArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_bnorm, dim3(a.nchunk), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_fin<FIN_BNORM>), dim3(a.S), dim3(kFinBlock), 0, st, a, 0, 0);
   hipLaunchKernelGGL(k_zero_x_if_b_zero, dim3(a.nchunk), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }

@@ -326,6 +326,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.ps = m + 3;
   a.prec = prec;
   a.precond = opt->precond;
+  a.ortho = opt->ortho;
   a.xcd_remap = 1;
   int32_t* d_rp = h->alloc<int32_t>(h->ld + 1);
   hip_check(hipMemcpy(d_rp, h->rp_host.data(), (h->ld + 1) * 4, hipMemcpyHostToDevice));
@@ -651,7 +652,7 @@ int gmres_residual(gmres_handle hh, const double* b, const double* x, double* r,
     if (r) hip_check(hipMemcpyAsync(r, h->ys, n * 8, hipMemcpyDeviceToDevice, h->stream));
     hip_check(hipStreamSynchronize(h->stream));
     double sq = 0.0;
-    for (int i = 0; i < h->nrb; ++i) sq += part[(size_t)i * h->a.ps];
+    for (int i = 0; i < h->nrb; ++i) sq += part[(size_t)i];
     if (norm_out) *norm_out = std::sqrt(sq);
     return GMRES_OK;
   } catch (const Fail& f) {

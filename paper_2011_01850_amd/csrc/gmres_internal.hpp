@@ -58,6 +58,7 @@ struct KArgs {
   int32_t ps;       // row stride of the partials table
   int32_t prec;     // Prec of the Arnoldi process
   int32_t precond;  // 0 none, 1 Jacobi, 2 SPAI
+  int32_t ortho;    // 0 MGS, 1 CGSR
   int32_t spmv_budget;  // nnz per SpMV row block (streaming mode)
   int32_t xcd_remap;    // map consecutive blocks onto one XCD
   // matrix: concatenated systems, global row and column numbering

@@ -81,6 +81,14 @@ __device__ __forceinline__ int remap_block(int b, int G, int on) {
   return x * per + (x < rem ? x : rem) + q;
 }
 
+// Chunk visited by workgroup b of a basis pass.  Passes that re-read the
+// same basis columns alternate direction, so each one starts on the rows the
+// previous pass touched last, which the memory-side cache still holds.
+__device__ __forceinline__ int pass_chunk(const KArgs& a, int rev) {
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  return rev ? a.nchunk - 1 - c : c;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -148,48 +156,32 @@ __device__ __forceinline__ T reduce_scatter(T (&p)[L], int lane) {
   return v;
 }
 
-// out[col] = sum (or max for col == maxcol) over rows r in [0, R) of
-// p[(row0 + r) * ps + col], for col in [0, ncol).  All threads of the block
-// take part: columns across lanes, rows across lane groups (several loads in
-// flight per thread), then a fixed-order tree over the groups, so the result
-// does not depend on timing.
-__device__ void reduce_rows(const double* p, int ps, int row0, int R, int ncol, int maxcol, double* out) {
-  __shared__ double red[kFinBlock];
-  const int t = threadIdx.x;
-  const int NT = blockDim.x;
-  int CP = 1;
-  while (CP < ncol && CP < 64) CP *= 2;
-  const int RG = NT / CP;
-  const int lane = t % CP, rg = t / CP;
-  for (int base = 0; base < ncol; base += CP) {
-    const int col = base + lane;
-    const bool isMax = col == maxcol;
-    double acc = 0.0;
-    if (col < ncol) {
-      const double* q = p + (int64_t)row0 * ps + col;
-      double a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int r = rg;
-      for (; r + 3 * RG < R; r += 4 * RG) {
-        const double v0 = q[(int64_t)r * ps], v1 = q[(int64_t)(r + RG) * ps];
-        const double v2 = q[(int64_t)(r + 2 * RG) * ps], v3 = q[(int64_t)(r + 3 * RG) * ps];
-        if (isMax) {
-          acc = fmax(acc, v0); a1 = fmax(a1, v1); a2 = fmax(a2, v2); a3 = fmax(a3, v3);
-        } else {
-          acc += v0; a1 += v1; a2 += v2; a3 += v3;
-        }
-      }
-      for (; r < R; r += RG) acc = isMax ? fmax(acc, q[(int64_t)r * ps]) : acc + q[(int64_t)r * ps];
-      acc = isMax ? fmax(fmax(acc, a1), fmax(a2, a3)) : (acc + a1) + (a2 + a3);
+// Sum (or maximum) of p[0, n) in a fixed order; called by every thread of
+// the block (up to kFinBlock threads), the result is returned in all of them.
+// Partial tables are column-major (one contiguous column per quantity), so
+// the loads here are contiguous.
+template <bool kMax>
+__device__ double reduce_col(const double* p, int n) {
+  __shared__ double sh[kFinBlock / 64];
+  const int t = threadIdx.x, NT = blockDim.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int r = t;
+  for (; r + 3 * NT < n; r += 4 * NT) {
+    if (kMax) {
+      a0 = fmax(a0, p[r]); a1 = fmax(a1, p[r + NT]); a2 = fmax(a2, p[r + 2 * NT]); a3 = fmax(a3, p[r + 3 * NT]);
+    } else {
+      a0 += p[r]; a1 += p[r + NT]; a2 += p[r + 2 * NT]; a3 += p[r + 3 * NT];
     }
-    red[t] = acc;
-    __syncthreads();
-    for (int h = RG >> 1; h >= 1; h >>= 1) {
-      if (rg < h) red[t] = isMax ? fmax(red[t], red[t + h * CP]) : red[t] + red[t + h * CP];
-      __syncthreads();
-    }
-    if (rg == 0 && col < ncol) out[col] = red[lane];
-    __syncthreads();
   }
+  for (; r < n; r += NT) a0 = kMax ? fmax(a0, p[r]) : a0 + p[r];
+  double v = kMax ? fmax(fmax(a0, a1), fmax(a2, a3)) : (a0 + a1) + (a2 + a3);
+  v = kMax ? wave_max(v) : wave_sum(v);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  double tot = sh[0];
+  for (int w = 1; w < NT / 64; ++w) tot = kMax ? fmax(tot, sh[w]) : tot + sh[w];
+  __syncthreads();
+  return tot;
 }
 
 __device__ __forceinline__ bool gated(const KArgs& a, int s) {
@@ -222,42 +214,6 @@ __device__ __forceinline__ void givens(double a, double b, double& c, double& s)
 
 // ------------------------------------------------------------- finalisers
 // All run in the last block of a pass; `red` holds the reduced partials.
-
-__device__ void fin_pass1(const KArgs& a, int s, int j, const double* red) {
-  const int M2 = a.m + 2, M1 = a.m + 1;
-  const double* sc = a.sc + (int64_t)s * M1;
-  double* h1 = a.h1 + (int64_t)s * M2;
-  double* coef = a.coef + (int64_t)s * M2;
-  for (int q = threadIdx.x; q <= j; q += blockDim.x) {
-    const double h = sc[q] * red[q];
-    h1[q] = h;
-    coef[q] = h * sc[q];
-  }
-  if (threadIdx.x == 0) a.st[s].wnorm_pre = sqrt(red[j + 1]);
-}
-
-__device__ void fin_pass2(const KArgs& a, int s, int j, const double* red) {
-  const int M2 = a.m + 2, M1 = a.m + 1;
-  const double* sc = a.sc + (int64_t)s * M1;
-  const double* h1 = a.h1 + (int64_t)s * M2;
-  double* hc = a.hacc + (int64_t)s * M2;
-  double* coef = a.coef + (int64_t)s * M2;
-  for (int q = threadIdx.x; q <= j; q += blockDim.x) {
-    const double h = sc[q] * red[q];
-    hc[q] = h1[q] + h;
-    coef[q] = h * sc[q];
-  }
-}
-
-__device__ void fin_mgs(const KArgs& a, int s, int i, const double* red) {
-  if (threadIdx.x != 0) return;
-  const int M2 = a.m + 2, M1 = a.m + 1;
-  const double sci = a.sc[(int64_t)s * M1 + i];
-  const double h = sci * red[0];
-  a.hacc[(int64_t)s * M2 + i] = h;
-  a.coef[(int64_t)s * M2 + i] = h * sci;
-  if (i == 0) a.st[s].wnorm_pre = sqrt(red[1]);
-}
 
 // Givens update of column j, restart / stop decisions (one lane).
 __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax) {
@@ -450,8 +406,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
     zsq = block_sum(zsq);
     if (MODE == SM_RESID) zmax = block_max(zmax);
     if (t == 0) {
-      a.part[(int64_t)blk * a.ps] = zsq;
-      if (MODE == SM_RESID) a.part[(int64_t)blk * a.ps + 1] = zmax;
+      a.part[blk] = zsq;
+      if (MODE == SM_RESID) a.part[(int64_t)a.nrb + blk] = zmax;
     }
 
   }
@@ -462,10 +418,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
 // preceding pass wrote (the kernel boundary makes them visible) and runs the
 // system's scalar step.
 
-enum FinMode { FIN_PASS1 = 0, FIN_PASS2 = 1, FIN_STEP = 2, FIN_MGS = 3, FIN_RESID = 4, FIN_BNORM = 5 };
+enum FinMode { FIN_PASS1 = 0, FIN_PASS2 = 1, FIN_STEP = 2, FIN_RESID = 4, FIN_BNORM = 5 };
 
+// Scalar completions with one or two reduced quantities.  `src` is the
+// partial table the pass wrote (chunk grid: column stride nchunk; row-block
+// grid: column stride nrb).
 template <int MODE>
-__global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, int j, int i) {
+__global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, const double* src, int j) {
   const int s = blockIdx.x;
   const SysState& S = a.st[s];
   if (MODE == FIN_RESID) {
@@ -473,31 +432,24 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, int j, int i) {
   } else if (MODE != FIN_BNORM) {
     if (!S.active && !S.force) return;
   }
-  __shared__ double red[kMaxM + 3];
   const int t = threadIdx.x;
   if (MODE == FIN_RESID) {
-    reduce_rows(a.part, a.ps, a.sys_rb0[s], a.sys_nrb[s], 2, 1, red);
-    if (t == 0) fin_residual(a, s, red[0], red[1]);
+    const int b0 = a.sys_rb0[s], nb = a.sys_nrb[s];
+    const double sq = reduce_col<false>(src + b0, nb);
+    const double mx = reduce_col<true>(src + a.nrb + b0, nb);
+    if (t == 0) fin_residual(a, s, sq, mx);
     return;
   }
   const int c0 = a.sys_ch0[s], nc = a.sys_nch[s];
-  if (MODE == FIN_PASS1) {
-    reduce_rows(a.part, a.ps, c0, nc, j + 2, -1, red);
-    fin_pass1(a, s, j, red);
-  } else if (MODE == FIN_PASS2) {
-    reduce_rows(a.part, a.ps, c0, nc, j + 1, -1, red);
-    fin_pass2(a, s, j, red);
-  } else if (MODE == FIN_STEP) {
-    reduce_rows(a.part, a.ps, c0, nc, 2, 1, red);
-    if (t == 0) fin_step(a, s, j, red[0], red[1]);
-  } else if (MODE == FIN_MGS) {
-    reduce_rows(a.part, a.ps, c0, nc, i == 0 ? 2 : 1, -1, red);
-    fin_mgs(a, s, i, red);
+  if (MODE == FIN_STEP) {
+    const double sq = reduce_col<false>(src + c0, nc);
+    const double mx = reduce_col<true>(src + a.nchunk + c0, nc);
+    if (t == 0) fin_step(a, s, j, sq, mx);
   } else {  // FIN_BNORM
-    reduce_rows(a.part, a.ps, c0, nc, 1, -1, red);
+    const double sq = reduce_col<false>(src + c0, nc);
     if (t == 0) {
       SysState& W = a.st[s];
-      W.bnorm = sqrt(red[0]);
+      W.bnorm = sqrt(sq);
       if (W.bnorm == 0.0) {
         W.status = CONVERGED;
         W.rel = 0.0;
@@ -506,21 +458,51 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, int j, int i) {
   }
 }
 
+// The CGS projections complete column by column: workgroup (s, q) reduces
+// column q of system s.  Pass 1: h1_q = sc_q * sum and the next axpy
+// coefficient h1_q * sc_q (column j+1 carries ||w||^2).  Pass 2: h2_q, the
+// column of H (h1 + h2) and the coefficient h2_q * sc_q.
 template <int MODE>
-static hipError_t launch_fin(const KArgs& a, int j, int i, hipStream_t st) {
-  hipLaunchKernelGGL((k_fin<MODE>), dim3(a.S), dim3(kFinBlock), 0, st, a, j, i);
-  return hipGetLastError();
+__global__ __launch_bounds__(kBlock) void k_fin_cols(KArgs a, int j) {
+  const int s = blockIdx.x, q = blockIdx.y;
+  const SysState& S = a.st[s];
+  if (!S.active && !S.force) return;
+  const double v = reduce_col<false>(a.part + (int64_t)q * a.nchunk + a.sys_ch0[s], a.sys_nch[s]);
+  if (threadIdx.x != 0) return;
+  const int M1 = a.m + 1, M2 = a.m + 2;
+  if (MODE == FIN_PASS1 && q == j + 1) {
+    a.st[s].wnorm_pre = sqrt(v);
+    return;
+  }
+  const double scq = a.sc[(int64_t)s * M1 + q];
+  const double h = scq * v;
+  if (MODE == FIN_PASS1) {
+    a.h1[(int64_t)s * M2 + q] = h;
+  } else {
+    a.hacc[(int64_t)s * M2 + q] = a.h1[(int64_t)s * M2 + q] + h;
+  }
+  a.coef[(int64_t)s * M2 + q] = h * scq;
 }
 
 hipError_t launch_finalize(const KArgs& a, int mode, int j, int i, hipStream_t st) {
+  (void)i;
   switch (mode) {
-    case FIN_PASS1: return launch_fin<FIN_PASS1>(a, j, i, st);
-    case FIN_PASS2: return launch_fin<FIN_PASS2>(a, j, i, st);
-    case FIN_STEP: return launch_fin<FIN_STEP>(a, j, i, st);
-    case FIN_MGS: return launch_fin<FIN_MGS>(a, j, i, st);
-    case FIN_RESID: return launch_fin<FIN_RESID>(a, j, i, st);
+    case FIN_PASS1:
+      hipLaunchKernelGGL((k_fin_cols<FIN_PASS1>), dim3(a.S, j + 2), dim3(kBlock), 0, st, a, j);
+      break;
+    case FIN_PASS2:
+      hipLaunchKernelGGL((k_fin_cols<FIN_PASS2>), dim3(a.S, j + 1), dim3(kBlock), 0, st, a, j);
+      break;
+    case FIN_STEP:
+      hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, j);
+      break;
+    case FIN_RESID:
+      hipLaunchKernelGGL((k_fin<FIN_RESID>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, j);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ basis passes
@@ -578,7 +560,7 @@ __device__ __forceinline__ void store_colsums(const KArgs& a, int c, int col0, i
     ACC tot = lds[0][threadIdx.x];
 #pragma unroll
     for (int k = 1; k < kBlock / 64; ++k) tot += lds[k][threadIdx.x];
-    a.part[(int64_t)c * a.ps + col0 + threadIdx.x] = (double)tot;
+    a.part[(int64_t)(col0 + threadIdx.x) * a.nchunk + c] = (double)tot;
   }
   __syncthreads();
 }
@@ -586,9 +568,9 @@ __device__ __forceinline__ void store_colsums(const KArgs& a, int c, int col0, i
 // CGSR projection 1 (columns [col0, col0 + L) of V^T w) and ||w||^2.
 // mode 1: finalise as the first projection; mode 2: as the second.
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, int j, int col0, int mode) {
+__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, int j, int col0, int mode, int rev) {
   using ACC = typename AccOf<TV>::type;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int c = pass_chunk(a, rev);
   const int s = a.ch_sys[c];
   if (!gated(a, s)) return;
   const int t = threadIdx.x, lane = t & 63;
@@ -621,16 +603,16 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, int j, int col0, int m
   store_colsums<L>(a, c, col0, ncol, colsum);
   if (col0 == 0 && mode == 1) {
     const ACC tot = block_sum(ww);
-    if (t == 0) a.part[(int64_t)c * a.ps + j + 1] = (double)tot;
+    if (t == 0) a.part[(int64_t)(j + 1) * a.nchunk + c] = (double)tot;
   }
 }
 
 // CGSR projection 2, fused: w' = w - V coef (coef from projection 1), then
 // V^T w' from the same register tile of V.  Requires j + 1 <= L <= 64.
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_axpy_mdot(KArgs a, int j) {
+__global__ __launch_bounds__(kBlock) void k_axpy_mdot(KArgs a, int j, int rev) {
   using ACC = typename AccOf<TV>::type;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int c = pass_chunk(a, rev);
   const int s = a.ch_sys[c];
   if (!gated(a, s)) return;
   const int t = threadIdx.x, lane = t & 63;
@@ -721,18 +703,18 @@ __global__ __launch_bounds__(kBlock) void k_final(KArgs a, int j, int i0) {
   const double tsq = (double)block_sum(sq);
   const double tmx = (double)block_max(mx);
   if (t == 0) {
-    a.part[(int64_t)c * a.ps] = tsq;
-    a.part[(int64_t)c * a.ps + 1] = tmx;
+    a.part[c] = tsq;
+    a.part[(int64_t)a.nchunk + c] = tmx;
   }
 }
 
 // The same last pass for CGSR with j + 1 <= L <= 64 columns: the whole tile
 // of basis loads is issued at once through the bounded buffer resource.
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, int j) {
+__global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, int j, int rev) {
   using ACC = typename AccOf<TV>::type;
   constexpr bool kTwoByte = sizeof(TV) == 2;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int c = pass_chunk(a, rev);
   const int s = a.ch_sys[c];
   if (!gated(a, s)) return;
   const int t = threadIdx.x;
@@ -773,13 +755,34 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, int j) {
   const double tsq = (double)block_sum(sq);
   const double tmx = (double)block_max(mx);
   if (t == 0) {
-    a.part[(int64_t)c * a.ps] = tsq;
-    a.part[(int64_t)c * a.ps + 1] = tmx;
+    a.part[c] = tsq;
+    a.part[(int64_t)a.nchunk + c] = tmx;
   }
 }
 
-// MGS step i of Arnoldi column j: w -= h_{i-1} v_{i-1} (i > 0), then
-// h_i = w . v_i (plus ||w||^2 when i = 0).
+// MGS, fused: step i of Arnoldi column j first completes dot i-1 itself
+// (every workgroup reduces the previous launch's partials of its system in
+// the same fixed order, so all hold the same h_{i-1}; the system's first
+// workgroup records it in H), then w -= h_{i-1} v_{i-1} and the partial dot
+// w . v_i.  Partial tables alternate between two buffers by the parity of i.
+__device__ __forceinline__ double mgs_complete(const KArgs& a, int s, int c, int i, const double* pin) {
+  const int c0 = a.sys_ch0[s], nc = a.sys_nch[s];
+  const int M1 = a.m + 1, M2 = a.m + 2;
+  const double d = reduce_col<false>(pin + c0, nc);
+  const double sci = a.sc[(int64_t)s * M1 + i];
+  const double h = sci * d;
+  if (c == c0) {
+    double wn = 0.0;
+    if (i == 0) wn = sqrt(reduce_col<false>(pin + a.nchunk + c0, nc));
+    if (threadIdx.x == 0) {
+      a.hacc[(int64_t)s * M2 + i] = h;
+      a.coef[(int64_t)s * M2 + i] = h * sci;
+      if (i == 0) a.st[s].wnorm_pre = wn;
+    }
+  }
+  return h * sci;
+}
+
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
   using ACC = typename AccOf<TV>::type;
@@ -787,10 +790,12 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
   const int s = a.ch_sys[c];
   if (!gated(a, s)) return;
   const int t = threadIdx.x;
+  double* pout = (i & 1) ? a.part2 : a.part;
+  const double* pin = (i & 1) ? a.part : a.part2;  // dot i-1
+  const ACC cprev = i > 0 ? (ACC)mgs_complete(a, s, c, i - 1, pin) : (ACC)0;
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* vi = col_ptr<TV>(a, i);
   const TV* vp = col_ptr<TV>(a, i > 0 ? i - 1 : 0);
-  const ACC cprev = i > 0 ? (ACC)a.coef[(int64_t)s * (a.m + 2) + i - 1] : (ACC)0;
   const int64_t base = (int64_t)c * kChunk + t;
   ACC d = (ACC)0, ww = (ACC)0;
   for (int u = 0; u < kRowsPerThread; ++u) {
@@ -808,8 +813,44 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
   double tw = 0.0;
   if (i == 0) tw = (double)block_sum(ww);
   if (t == 0) {
-    a.part[(int64_t)c * a.ps] = td;
-    if (i == 0) a.part[(int64_t)c * a.ps + 1] = tw;
+    pout[c] = td;
+    if (i == 0) pout[(int64_t)a.nchunk + c] = tw;
+  }
+}
+
+// Last MGS pass of column j: completes dot j, w'' = w - h_j v_j, and the
+// partials of ||w''||^2 and max|w''| for the Givens step.
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, int j) {
+  using ACC = typename AccOf<TV>::type;
+  constexpr bool kTwoByte = sizeof(TV) == 2;
+  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int s = a.ch_sys[c];
+  if (!gated(a, s)) return;
+  const int t = threadIdx.x;
+  const double* pin = (j & 1) ? a.part2 : a.part;
+  double* pout = (j & 1) ? a.part : a.part2;
+  const ACC cj = (ACC)mgs_complete(a, s, c, j, pin);
+  TW* w = reinterpret_cast<TW*>(a.w);
+  const TV* vj = col_ptr<TV>(a, j);
+  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
+  const int64_t base = (int64_t)c * kChunk + t;
+  ACC sq = (ACC)0, mx = (ACC)0;
+  for (int u = 0; u < kRowsPerThread; ++u) {
+    const int64_t r = base + u * kBlock;
+    const ACC wr = (ACC)w[r] - cj * (ACC)ldv(vj[r]);
+    sq += wr * wr;
+    mx = fmax(mx, fabs(wr));
+    if constexpr (kTwoByte)
+      w[r] = (TW)wr;
+    else
+      vout[r] = (TV)wr;
+  }
+  const double tsq = (double)block_sum(sq);
+  const double tmx = (double)block_max(mx);
+  if (t == 0) {
+    pout[c] = tsq;
+    pout[(int64_t)a.nchunk + c] = tmx;
   }
 }
 
@@ -929,7 +970,7 @@ __global__ __launch_bounds__(kBlock) void k_bnorm(KArgs a) {
     sq += v * v;
   }
   sq = block_sum(sq);
-  if (threadIdx.x == 0) a.part[(int64_t)c * a.ps] = sq;
+  if (threadIdx.x == 0) a.part[c] = sq;
 }
 
 __global__ void k_zero_x_if_b_zero(KArgs a) {
@@ -1120,7 +1161,7 @@ hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {
                        a.a64, a.x, (float*)a.w, a.b, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !with_fin) return e;
-  return launch_fin<FIN_RESID>(a, 0, 0, st);
+  return launch_finalize(a, FIN_RESID, 0, 0, st);
 }
 
 hipError_t launch_encode(const KArgs& a, int col, hipStream_t st) {
@@ -1132,13 +1173,18 @@ hipError_t launch_encode(const KArgs& a, int col, hipStream_t st) {
   });
 }
 
+// direction of the CGS passes: projection 1 forward, projection 2 backward,
+// the last pass forward again
+constexpr int kRevPass1 = 0, kRevPass2 = 1, kRevPass3 = 0;
+
 template <typename TV, typename TW>
 static hipError_t launch_mdot_window(const KArgs& a, int j, int col0, int mode, int L, hipStream_t st) {
+  const int rev = mode == 1 ? kRevPass1 : kRevPass2;
   switch (L) {
-    case 8: hipLaunchKernelGGL((k_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
-    case 16: hipLaunchKernelGGL((k_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
-    case 32: hipLaunchKernelGGL((k_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
-    default: hipLaunchKernelGGL((k_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode); break;
+    case 8: hipLaunchKernelGGL((k_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
+    case 16: hipLaunchKernelGGL((k_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
+    case 32: hipLaunchKernelGGL((k_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
+    default: hipLaunchKernelGGL((k_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
   }
   return hipGetLastError();
 }
@@ -1156,7 +1202,7 @@ hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin
     return hipSuccess;
   });
   if (e != hipSuccess || !with_fin) return e;
-  return launch_fin<FIN_PASS1>(a, j, 0, st);
+  return launch_finalize(a, FIN_PASS1, j, 0, st);
 }
 
 hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin) {
@@ -1166,10 +1212,10 @@ hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin
     const int ncol = j + 1;
     if (ncol <= 64) {
       switch (lanes_for(ncol)) {
-        case 8: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
-        case 16: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
-        case 32: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
-        default: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        case 8: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
+        case 16: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
+        case 32: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
+        default: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
       }
       return hipGetLastError();
     }
@@ -1185,19 +1231,22 @@ hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin
     return hipSuccess;
   });
   if (e0 != hipSuccess || !with_fin) return e0;
-  return launch_fin<FIN_PASS2>(a, j, 0, st);
+  return launch_finalize(a, FIN_PASS2, j, 0, st);
 }
 
 hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st, bool with_fin) {
+  const bool mgs = a.ortho == 0;
   hipError_t e0 = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
-    if (i0 == 0 && j + 1 <= 64) {
+    if (mgs) {
+      hipLaunchKernelGGL((k_mgs_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j);
+    } else if (j + 1 <= 64) {
       switch (lanes_for(j + 1)) {
-        case 8: hipLaunchKernelGGL((k_final_tile<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
-        case 16: hipLaunchKernelGGL((k_final_tile<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
-        case 32: hipLaunchKernelGGL((k_final_tile<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
-        default: hipLaunchKernelGGL((k_final_tile<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j); break;
+        case 8: hipLaunchKernelGGL((k_final_tile<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
+        case 16: hipLaunchKernelGGL((k_final_tile<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
+        case 32: hipLaunchKernelGGL((k_final_tile<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
+        default: hipLaunchKernelGGL((k_final_tile<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
       }
     } else {
       hipLaunchKernelGGL((k_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i0);
@@ -1205,18 +1254,19 @@ hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st, bool
     return hipGetLastError();
   });
   if (e0 != hipSuccess || !with_fin) return e0;
-  return launch_fin<FIN_STEP>(a, j, 0, st);
+  const double* src = mgs ? ((j & 1) ? a.part : a.part2) : a.part;
+  hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, src, j);
+  return hipGetLastError();
 }
 
 hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st, bool with_fin) {
-  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+  (void)with_fin;  // the next MGS launch completes this dot itself
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     hipLaunchKernelGGL((k_mgs<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i);
     return hipGetLastError();
   });
-  if (e != hipSuccess || !with_fin) return e;
-  return launch_fin<FIN_MGS>(a, j, i, st);
 }
 
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st) {
@@ -1234,7 +1284,7 @@ hipError_t launch_update(const KArgs& a, hipStream_t st) {
 
 hipError_t launch_bnorm(const KArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_bnorm, dim3(a.nchunk), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL((k_fin<FIN_BNORM>), dim3(a.S), dim3(kFinBlock), 0, st, a, 0, 0);
+  hipLaunchKernelGGL((k_fin<FIN_BNORM>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, 0);
   hipLaunchKernelGGL(k_zero_x_if_b_zero, dim3(a.nchunk), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }

@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=10)
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample: inner iterations")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="end with a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -210,6 +212,13 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, iters_ref, args.cpu_iters)
     else:
         rec["cpu_baseline"] = None
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
     print(json.dumps(rec), flush=True)
 
 

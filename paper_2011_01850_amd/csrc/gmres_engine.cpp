@@ -34,7 +34,7 @@ struct System {
   int64_t n = 0, nnz = 0;
   int64_t row0 = 0;  // first global row
   int64_t nz0 = 0;   // first global non-zero
-  int32_t nch = 0, ch0 = 0, nrb = 0, rb0 = 0;
+  int32_t nt = 0, t0 = 0, nrb = 0, rb0 = 0;  // tiles, first tile, SpMV row blocks
 };
 
 }  // namespace
@@ -45,7 +45,7 @@ struct gmres_ctx {
   gmres_options opt{};
   std::vector<System> sys;
   int64_t ld = 0, nnz = 0, nrows = 0;
-  int32_t nchunk = 0, nrb = 0;
+  int32_t ntile = 0, nrb = 0;
   std::vector<int32_t> rp_host;  // global row pointer (ld + 1)
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -122,32 +122,6 @@ void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r
   }
 }
 
-// Groups of consecutive workgroups (per system) for the two-level reduction.
-struct Groups {
-  std::vector<int32_t> grp, gfirst, gn, g0, ng;
-};
-
-Groups make_groups(const std::vector<int32_t>& first, const std::vector<int32_t>& count) {
-  int32_t mx = 1;
-  for (int32_t c : count) mx = std::max(mx, c);
-  int GS = 8;
-  while (GS < 256 && (int64_t)GS * GS < mx) GS *= 2;
-  Groups G;
-  for (size_t s = 0; s < first.size(); ++s) {
-    G.g0.push_back((int32_t)G.gfirst.size());
-    const int32_t nb = count[s];
-    int32_t ng = 0;
-    for (int32_t b = 0; b < nb; b += GS, ++ng) {
-      const int32_t n = std::min<int32_t>(GS, nb - b);
-      for (int32_t k = 0; k < n; ++k) G.grp.push_back((int32_t)G.gfirst.size());
-      G.gfirst.push_back(first[s] + b);
-      G.gn.push_back(n);
-    }
-    G.ng.push_back(ng);
-  }
-  return G;
-}
-
 int32_t* upload32(gmres_ctx* h, const std::vector<int32_t>& v) {
   int32_t* d = h->alloc<int32_t>(std::max<size_t>(v.size(), 1));
   if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice));
@@ -187,12 +161,41 @@ void set_row_blocks(gmres_ctx* h, int budget) {
   h->a.sys_nrb = d_nrb;
   h->a.nrb = h->nrb;
   h->a.spmv_budget = budget;
-  const Groups G = make_groups(rb0, nrb);
-  h->a.rb_grp = upload32(h, G.grp);
-  h->a.rb_gfirst = upload32(h, G.gfirst);
-  h->a.rb_gn = upload32(h, G.gn);
-  h->a.sys_rg0 = upload32(h, G.g0);
-  h->a.sys_rng = upload32(h, G.ng);
+}
+
+// Work split of the persistent basis passes for G workgroups: workgroup b
+// owns tiles [b T / G, (b+1) T / G), cut at system boundaries into segments.
+SegTab make_split(gmres_ctx* h, int G) {
+  const int64_t T = h->ntile;
+  std::vector<int32_t> bseg0, seg_t0, seg_nt, seg_sys, sys_sg0(h->sys.size(), -1), sys_nsg(h->sys.size(), 0);
+  size_t sysk = 0;
+  for (int b = 0; b < G; ++b) {
+    bseg0.push_back((int32_t)seg_t0.size());
+    int64_t t = (int64_t)b * T / G;
+    const int64_t t1 = (int64_t)(b + 1) * T / G;
+    while (t < t1) {
+      while (h->sys[sysk].t0 + h->sys[sysk].nt <= t) ++sysk;
+      const System& s = h->sys[sysk];
+      const int64_t e = std::min<int64_t>(t1, s.t0 + s.nt);
+      if (sys_sg0[sysk] < 0) sys_sg0[sysk] = (int32_t)seg_t0.size();
+      sys_nsg[sysk] += 1;
+      seg_t0.push_back((int32_t)t);
+      seg_nt.push_back((int32_t)(e - t));
+      seg_sys.push_back((int32_t)sysk);
+      t = e;
+    }
+  }
+  bseg0.push_back((int32_t)seg_t0.size());
+  SegTab sg{};
+  sg.G = G;
+  sg.nseg = (int32_t)seg_t0.size();
+  sg.bseg0 = upload32(h, bseg0);
+  sg.seg_t0 = upload32(h, seg_t0);
+  sg.seg_nt = upload32(h, seg_nt);
+  sg.seg_sys = upload32(h, seg_sys);
+  sg.sys_sg0 = upload32(h, sys_sg0);
+  sg.sys_nsg = upload32(h, sys_nsg);
+  return sg;
 }
 
 int64_t vbytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -212,10 +215,10 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
     if (h->opt.ortho == GMRES_CGSR) {
       e = launch_cgs_pass1(a, j, st);
       if (e == hipSuccess) e = launch_cgs_pass2(a, j, st);
-      if (e == hipSuccess) e = launch_final_pass(a, j, 0, st);
+      if (e == hipSuccess) e = launch_final_pass(a, j, st);
     } else {
       for (int i = 0; i <= j && e == hipSuccess; ++i) e = launch_mgs_dot(a, j, i, st);
-      if (e == hipSuccess) e = launch_final_pass(a, j, j, st);
+      if (e == hipSuccess) e = launch_final_pass(a, j, st);
     }
     if (e == hipSuccess && two && j + 1 <= a.m) e = launch_encode(a, j + 1, st);
   }
@@ -284,24 +287,24 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   const int m = opt->m;
   const int prec = opt->precision;
   h->sys.resize(nsys);
-  int64_t row = 0, nz = 0, ch = 0;
+  int64_t row = 0, nz = 0, tl = 0;
   for (int k = 0; k < nsys; ++k) {
     System& s = h->sys[k];
     s.n = n[k];
     s.nnz = nnz[k];
     s.row0 = row;
     s.nz0 = nz;
-    s.ch0 = (int32_t)ch;
-    s.nch = (int32_t)((s.n + kChunk - 1) / kChunk);
-    row += (int64_t)s.nch * kChunk;
+    s.t0 = (int32_t)tl;
+    s.nt = (int32_t)((s.n + kTile - 1) / kTile);
+    row += (int64_t)s.nt * kTile;
     nz += s.nnz;
-    ch += s.nch;
+    tl += s.nt;
     h->nrows += s.n;
   }
   if (row >= (int64_t)INT32_MAX || nz >= (int64_t)INT32_MAX) throw Fail{GMRES_EINVAL};
   h->ld = row;
   h->nnz = nz;
-  h->nchunk = (int32_t)ch;
+  h->ntile = (int32_t)tl;
 
   // ---- global CSR (rows of padding are empty; columns shifted per system)
   h->rp_host.assign(h->ld + 1, 0);
@@ -315,14 +318,20 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
       if (tmp[i + 1] < tmp[i]) throw Fail{GMRES_EINVAL};
       h->rp_host[s.row0 + i] = (int32_t)(s.nz0 + tmp[i]);
     }
-    const int64_t end = s.row0 + (int64_t)s.nch * kChunk;
+    const int64_t end = s.row0 + (int64_t)s.nt * kTile;
     for (int64_t i = s.row0 + s.n; i <= end; ++i) h->rp_host[i] = (int32_t)(s.nz0 + s.nnz);
   }
   KArgs& a = h->a;
   a.S = nsys;
   a.m = m;
   a.ld = h->ld;
-  a.nchunk = h->nchunk;
+  a.ntile = h->ntile;
+  {
+    int dev = 0, ncu = 0;
+    hip_check(hipGetDevice(&dev));
+    hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    a.ncu = std::max(1, ncu);
+  }
   a.ps = m + 3;
   a.prec = prec;
   a.precond = opt->precond;
@@ -330,8 +339,11 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.xcd_remap = 1;
   int32_t* d_rp = h->alloc<int32_t>(h->ld + 1);
   hip_check(hipMemcpy(d_rp, h->rp_host.data(), (h->ld + 1) * 4, hipMemcpyHostToDevice));
-  int32_t* d_ci = h->alloc<int32_t>(h->nnz);
-  double* d_a64 = h->alloc<double>(h->nnz);
+  // index and value arrays carry a zero pad of 4 entries (SpMV reads aligned groups of 4)
+  int32_t* d_ci = h->alloc<int32_t>(h->nnz + 4);
+  double* d_a64 = h->alloc<double>(h->nnz + 4);
+  hip_check(hipMemsetAsync(d_ci + h->nnz, 0, 16, h->stream));
+  hip_check(hipMemsetAsync(d_a64 + h->nnz, 0, 32, h->stream));
   for (int k = 0; k < nsys; ++k) {
     const System& s = h->sys[k];
     if (s.nnz == 0) continue;
@@ -342,18 +354,18 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.ci = d_ci;
   a.a64 = d_a64;
   if (prec != P64) {
-    float* d_a32 = h->alloc<float>(h->nnz);
-    hip_check(launch_convert_f32(d_a64, d_a32, h->nnz, h->stream));
+    float* d_a32 = h->alloc<float>(h->nnz + 4);
+    hip_check(launch_convert_f32(d_a64, d_a32, h->nnz + 4, h->stream));
     a.a32 = d_a32;
   }
   // ---- per-system tables
-  std::vector<int32_t> ch_sys(h->nchunk), ch0(nsys), nch(nsys), sn(nsys);
+  std::vector<int32_t> tile_sys(h->ntile), t0(nsys), nt(nsys), sn(nsys);
   std::vector<int64_t> row0(nsys);
   for (int k = 0; k < nsys; ++k) {
     const System& s = h->sys[k];
-    for (int c = 0; c < s.nch; ++c) ch_sys[s.ch0 + c] = k;
-    ch0[k] = s.ch0;
-    nch[k] = s.nch;
+    for (int c = 0; c < s.nt; ++c) tile_sys[s.t0 + c] = k;
+    t0[k] = s.t0;
+    nt[k] = s.nt;
     sn[k] = (int32_t)s.n;
     row0[k] = s.row0;
   }
@@ -362,17 +374,9 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     hip_check(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice));
     return d;
   };
-  a.ch_sys = up32(ch_sys);
-  a.sys_ch0 = up32(ch0);
-  a.sys_nch = up32(nch);
-  {
-    const Groups G = make_groups(ch0, nch);
-    a.ch_grp = up32(G.grp);
-    a.ch_gfirst = up32(G.gfirst);
-    a.ch_gn = up32(G.gn);
-    a.sys_cg0 = up32(G.g0);
-    a.sys_cng = up32(G.ng);
-  }
+  a.tile_sys = up32(tile_sys);
+  a.sys_t0 = up32(t0);
+  a.sys_nt = up32(nt);
   a.sys_n = up32(sn);
   {
     int64_t* d = h->alloc<int64_t>(nsys);
@@ -396,8 +400,6 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   hip_check(hipMemsetAsync(a.x, 0, h->ld * 8, h->stream));
   hip_check(hipMemsetAsync(a.b, 0, h->ld * 8, h->stream));
   a.st = h->alloc<SysState>(nsys);
-  a.cnt = h->alloc<uint32_t>(nsys);
-  hip_check(hipMemsetAsync(a.cnt, 0, nsys * 4, h->stream));
   a.H = h->alloc<double>(nsys * M1 * m);
   a.Hbar = h->alloc<double>(nsys * M1 * m);
   hip_check(hipMemsetAsync(a.Hbar, 0, nsys * M1 * m * 8, h->stream));
@@ -424,19 +426,21 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     a.dinv = d;
   }
   if (opt->precond == GMRES_PRECOND_SPAI) {
-    float* d = h->alloc<float>(h->nnz);
-    hip_check(hipMemsetAsync(d, 0, h->nnz * 4, h->stream));
+    float* d = h->alloc<float>(h->nnz + 4);
+    hip_check(hipMemsetAsync(d, 0, (h->nnz + 4) * 4, h->stream));
     a.mval = d;
   }
   // ---- partials sized for the largest grid any budget candidate can give
   {
     std::vector<int32_t> rbtmp;
     for (const System& s : h->sys) build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, 1024, rbtmp);
-    const int64_t maxblk = std::max<int64_t>((int64_t)rbtmp.size(), h->nchunk);
-    a.part = h->alloc<double>((size_t)maxblk * a.ps);
-    a.part2 = h->alloc<double>((size_t)maxblk * a.ps);
-    a.gcnt = h->alloc<uint32_t>((size_t)maxblk);
-    hip_check(hipMemsetAsync(a.gcnt, 0, maxblk * 4, h->stream));
+    int64_t maxrows = std::max<int64_t>((int64_t)rbtmp.size(), h->ntile);
+    for (int k = 1; k <= kMaxOcc; ++k) {
+      a.seg[k - 1] = make_split(h, (int)std::min<int64_t>((int64_t)k * a.ncu, h->ntile));
+      maxrows = std::max<int64_t>(maxrows, a.seg[k - 1].nseg);
+    }
+    a.part = h->alloc<double>((size_t)maxrows * a.ps);
+    a.part2 = h->alloc<double>((size_t)maxrows * a.ps);
   }
   {
     int32_t* bad = h->alloc<int32_t>(1);
@@ -448,6 +452,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     if (hb) throw Fail{GMRES_EINVAL};
   }
   set_row_blocks(h, 2048);
+  hip_check(prepare_occupancy(prec));
   hip_check(launch_init_state(a, h->stream));
   if (opt->autotune) autotune_spmv(h);
   h->xs = h->alloc<double>(h->ld);
@@ -782,11 +787,11 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
         case 0: return launch_spmv_arnoldi(a, j, h->stream);
         case 1: return launch_cgs_pass1(a, j, h->stream, false);
         case 2: return launch_cgs_pass2(a, j, h->stream, false);
-        case 3: return launch_final_pass(a, j, 0, h->stream, false);
-        case 4: return launch_mgs_dot(a, j, j, h->stream, false);
+        case 3: return launch_final_pass(a, j, h->stream, false);
+        case 4: return launch_mgs_dot(a, j, j, h->stream);
         case 5: return launch_residual(a, h->stream, false);
         case 6: return launch_update(a, h->stream);
-        case 7: return launch_finalize(a, 1, j, 0, h->stream);
+        case 7: return launch_finalize_pass2(a, j, h->stream);
       }
       return hipErrorInvalidValue;
     };
@@ -798,7 +803,7 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
       case 4: bts = (j > 0 ? 2.0 : 1.0) * n * sv + (j > 0 ? 2.0 : 1.0) * n * sw; break;
       case 5: bts = nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * sw; break;
       case 6: bts = (j + 1) * n * sv + 16.0 * n; break;
-      case 7: bts = (double)h->nchunk * (j + 1) * 8.0; break;
+      case 7: bts = (double)h->a.seg[kMaxOcc - 1].nseg * (j + 1) * 8.0; break;
       default: return GMRES_EINVAL;
     }
     hip_check(launch_set_force(a, 1, h->stream));

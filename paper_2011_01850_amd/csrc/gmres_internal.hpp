@@ -6,23 +6,23 @@
 
 namespace gm {
 
-// Rows per reduction chunk: one workgroup of kBlock threads owns kChunk
-// consecutive rows of one system for every basis pass.  Systems are padded
-// to a multiple of kChunk rows (padding rows of the basis and of w are zero
-// and stay zero), so the passes need no tail handling.
+// Rows are grouped in tiles of kTile rows: one row per thread of a kBlock
+// workgroup.  Every system is padded to a whole number of tiles (padding rows
+// of the basis, w, x and b are zero and stay zero), so no kernel needs tail
+// handling inside a tile.
 constexpr int kBlock = 256;
-constexpr int kChunk = 2048;
-constexpr int kRowsPerThread = kChunk / kBlock;  // 8
+constexpr int kTile = 256;
 constexpr int kMaxM = 256;
 constexpr int kFinBlock = 1024;  // threads of the per-system finalise kernels
 constexpr int kHistCap = 4096;
+constexpr int kMaxOcc = 8;       // persistent grids of ncu * k workgroups, k = 1..kMaxOcc
 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
 enum Status { RUNNING = 0, CONVERGED = 1, MAXITER = 2, STALLED = 3 };
 
-// Per-system scalar state, device resident.  Written only by single-lane
-// finalisers (the last workgroup of a pass) and by the small per-system
-// kernels; every other workgroup only reads `active` / `status`.
+// Per-system scalar state, device resident.  Written only by one lane of a
+// finalise kernel (or of a system's first workgroup); every other workgroup
+// only reads `active` / `status`.
 struct SysState {
   int32_t active;       // the current Arnoldi cycle continues
   int32_t status;       // Status
@@ -48,19 +48,34 @@ struct SysState {
   float pad_;
 };
 
+// Work split of a persistent basis pass with G workgroups: workgroup b owns
+// the contiguous tile range [b T / G, (b+1) T / G), cut at system
+// boundaries into segments; every segment writes one partial row.
+struct SegTab {
+  int32_t G;               // workgroups
+  int32_t nseg;            // segments (= partial rows; column stride of the partial table)
+  const int32_t* bseg0;    // [G + 1] first segment of each workgroup
+  const int32_t* seg_t0;   // first tile of each segment
+  const int32_t* seg_nt;   // tiles of each segment
+  const int32_t* seg_sys;  // system of each segment
+  const int32_t* sys_sg0;  // first segment of each system
+  const int32_t* sys_nsg;  // segments of each system
+};
+
 // Everything a kernel needs, passed by value.
 struct KArgs {
   int32_t S;        // systems
   int32_t m;        // restart length
   int64_t ld;       // padded rows over all systems: column stride of V, Z, w
-  int32_t nchunk;   // kChunk-row chunks over all systems
+  int32_t ntile;    // kTile-row tiles over all systems
   int32_t nrb;      // SpMV row blocks over all systems
-  int32_t ps;       // row stride of the partials table
+  int32_t ps;       // quantities per partial row (m + 3)
   int32_t prec;     // Prec of the Arnoldi process
   int32_t precond;  // 0 none, 1 Jacobi, 2 SPAI
   int32_t ortho;    // 0 MGS, 1 CGSR
   int32_t spmv_budget;  // nnz per SpMV row block (streaming mode)
   int32_t xcd_remap;    // map consecutive blocks onto one XCD
+  int32_t ncu;          // compute units of the device
   // matrix: concatenated systems, global row and column numbering
   const int32_t* rp;
   const int32_t* ci;
@@ -70,37 +85,23 @@ struct KArgs {
   const float* dinv;   // Jacobi: 1 / a_ii
   const int32_t* rb;       // row-block first rows [nrb + 1]
   const int32_t* rb_sys;   // system of each row block
-  const int32_t* ch_sys;   // system of each chunk
   const int32_t* sys_rb0;  // first row block of each system
   const int32_t* sys_nrb;
-  const int32_t* sys_ch0;  // first chunk of each system
-  const int32_t* sys_nch;
+  const int32_t* tile_sys;  // system of each tile
+  const int32_t* sys_t0;    // first tile of each system
+  const int32_t* sys_nt;    // tiles of each system
   const int64_t* sys_row0;  // first row of each system
   const int32_t* sys_n;
+  SegTab seg[kMaxOcc];      // seg[k - 1]: the split for G = k * ncu workgroups
   // vectors (ld rows each)
   void* V;        // m+1 basis columns, storage per prec
   float* Z;       // m preconditioned columns (flexible form)
   void* w;        // work vector: double (P64) or float
   double* x;      // iterate
   double* b;      // right-hand side
-  // two-level reduction: each workgroup writes one row of `part`; the last
-  // workgroup of a group reduces the group's rows into one row of `part2`;
-  // the last group of a system reduces those rows and finalises the system
-  const int32_t* ch_grp;    // group of each chunk
-  const int32_t* ch_gfirst; // first chunk of each chunk group
-  const int32_t* ch_gn;     // chunks in each chunk group
-  const int32_t* sys_cg0;   // first chunk group of each system
-  const int32_t* sys_cng;   // chunk groups of each system
-  const int32_t* rb_grp;    // same for the SpMV row blocks
-  const int32_t* rb_gfirst;
-  const int32_t* rb_gn;
-  const int32_t* sys_rg0;
-  const int32_t* sys_rng;
-  // scratch
-  double* part;    // level-1 partials [max(nchunk, nrb)][ps]
-  double* part2;   // level-2 partials [max(groups)][ps]
-  uint32_t* gcnt;  // group counters
-  uint32_t* cnt;   // system counters
+  // scratch: column-major partial tables (quantity q of row k at q * rows + k)
+  double* part;
+  double* part2;  // second table: MGS alternates between the two
   SysState* st;
   double* H;      // rotated Hessenberg, (m+1) x m per system, column-major
   double* Hbar;   // unrotated copy
@@ -123,18 +124,20 @@ struct KArgs {
 };
 
 // ---------------------------------------------------------------- launchers
-// Each launcher enqueues one kernel on `st` and returns hipGetLastError().
+// Each launcher enqueues its kernels on `st` and returns hipGetLastError().
+// The basis passes are followed by the kernel that completes them unless
+// with_fin is false (kernel timing).
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st);   // w = A v_j or A z_j
 hipError_t launch_precond(const KArgs& a, int j, hipStream_t st);        // z_j = M v_j
-hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin = true);             // z = b - A x, start cycle
-hipError_t launch_encode(const KArgs& a, int col, hipStream_t st);       // 2-byte store of w
+hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin = true);  // z = b - A x
+hipError_t launch_encode(const KArgs& a, int col, hipStream_t st);       // store w as basis column
 hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
 hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
-hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st, bool with_fin = true);
-hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st, bool with_fin = true);
+hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
+hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st);
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st);
-// mode: 0 CGS projection 1, 1 projection 2, 2 Givens step, 3 MGS dot, 4 residual
-hipError_t launch_finalize(const KArgs& a, int mode, int j, int i, hipStream_t st);
+// the kernel that completes CGS projection 2 at column j (timing)
+hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st);
 hipError_t launch_update(const KArgs& a, hipStream_t st);
 hipError_t launch_bnorm(const KArgs& a, hipStream_t st);
 hipError_t launch_init_state(const KArgs& a, hipStream_t st);
@@ -145,18 +148,18 @@ hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st);
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st);
-hipError_t launch_sumsq(const double* v, int64_t n, double* part, int nblk, hipStream_t st);
 hipError_t launch_encode_plain(int prec, int64_t n, const float* w, float f, void* out,
                                hipStream_t st);
 hipError_t launch_absmax(const float* w, int64_t n, float* part, int nblk, hipStream_t st);
 hipError_t launch_decode_column(const KArgs& a, int sys, int col, double* out, hipStream_t st);
 hipError_t launch_shift_cols(const int32_t* src, int32_t* dst, int64_t nnz, int32_t shift,
                              hipStream_t st);
-hipError_t launch_shift_rowptr(const int32_t* src, int32_t* dst, int64_t n, int32_t shift,
-                               hipStream_t st);
 hipError_t launch_gather(const double* const* src, double* dst, const int64_t* row0,
                          const int32_t* n, int S, int64_t maxn, hipStream_t st);
 hipError_t launch_scatter(const double* src, double* const* dst, const int64_t* row0,
                           const int32_t* n, int S, int64_t maxn, hipStream_t st);
+// Queries, once per process, how many workgroups of each persistent basis
+// pass of `prec` fit on one CU.  Must run before any graph capture.
+hipError_t prepare_occupancy(int prec);
 
 }  // namespace gm

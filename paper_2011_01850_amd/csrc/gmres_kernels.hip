@@ -6,18 +6,21 @@
 // the Hessenberg matrix in float64.
 //
 // Execution model.  Every system of a handle is a contiguous, zero-padded
-// range of rows; a basis pass runs one 256-thread workgroup per 2048-row
-// chunk, a matrix pass one workgroup per CSR row block.  Reductions are
-// deterministic: per-lane sums, a fixed in-wave butterfly, a fixed
-// cross-wave order, and one float64 partial per workgroup; the last
-// workgroup of a system to finish (an agent-scope counter) reduces the
-// partials in a fixed order and runs that system's scalar step (Givens
-// rotation, restart and stop decisions).  Kernels of a cycle are gated by
-// the device-side `active` flag of their system, so a whole restart cycle
-// can be enqueued (or captured in one graph) without host round trips.
+// range of 256-row tiles.  A basis pass is a persistent grid sized to the
+// kernel's occupancy: each workgroup streams a contiguous, balanced range of
+// tiles (one row per thread) and writes one partial row per system segment
+// it touches; the next kernel (a small per-system finalise, or the next MGS
+// step itself) reduces those partials in a fixed order.  Matrix passes run
+// one workgroup per CSR row block.  All reductions are deterministic: per-lane
+// sums, a fixed in-wave butterfly, a fixed cross-wave order and fixed-order
+// sums of the partials; no floating-point atomics.  Kernels of a cycle are
+// gated by the device-side `active` flag of their system, so a whole restart
+// cycle can be enqueued (or captured in one graph) without host round trips.
 #include <math.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "gmres_internal.hpp"
 
@@ -81,13 +84,6 @@ __device__ __forceinline__ int remap_block(int b, int G, int on) {
   return x * per + (x < rem ? x : rem) + q;
 }
 
-// Chunk visited by workgroup b of a basis pass.  Passes that re-read the
-// same basis columns alternate direction, so each one starts on the rows the
-// previous pass touched last, which the memory-side cache still holds.
-__device__ __forceinline__ int pass_chunk(const KArgs& a, int rev) {
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  return rev ? a.nchunk - 1 - c : c;
-}
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -216,76 +212,98 @@ __device__ __forceinline__ void givens(double a, double b, double& c, double& s)
 // All run in the last block of a pass; `red` holds the reduced partials.
 
 // Givens update of column j, restart / stop decisions (one lane).
+// Called by every thread of the finalising workgroup: the column and the
+// earlier rotations are staged in LDS in parallel, one lane runs the
+// sequential rotation chain in registers, and the column is written back in
+// parallel.
 __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax) {
+  __shared__ double hcol[kMaxM + 2], rc[kMaxM], rsn[kMaxM];
+  __shared__ int ok;
+  const int t = threadIdx.x, NT = blockDim.x;
   SysState& S = a.st[s];
   const int m = a.m, M1 = m + 1, M2 = m + 2;
-  double* Hs = a.H + (int64_t)s * M1 * m;
-  double* Hb = a.Hbar + (int64_t)s * M1 * m;
+  double* col = a.H + (int64_t)s * M1 * m + (int64_t)j * M1;
+  double* bcol = a.Hbar + (int64_t)s * M1 * m + (int64_t)j * M1;
   const double* hc = a.hacc + (int64_t)s * M2;
   double* cs = a.cs + (int64_t)s * m;
   double* sn = a.sn + (int64_t)s * m;
-  double* sv = a.s + (int64_t)s * M1;
-  double* sc = a.sc + (int64_t)s * M1;
-  double* ar = a.ares + (int64_t)s * M1;
   const double hn = sqrt(sumsq);
-  bool finite = isfinite(hn);
-  for (int i = 0; i <= j; ++i) finite = finite && isfinite(hc[i]);
-  if (!finite) {
-    // drop the column; the cycle ends with the finite part of the basis
-    S.k = j;
-    S.need_update = j > 0 ? 1 : 0;
-    S.active = 0;
-    if (a.precond != 0 && S.precond_on) {
-      S.precond_on = 0;
-      S.fallback_used = 1;
+  if (t == 0) ok = isfinite(hn) ? 1 : 0;
+  __syncthreads();
+  for (int i = t; i <= j; i += NT) {
+    const double v = hc[i];
+    hcol[i] = v;
+    if (!isfinite(v)) ok = 0;
+  }
+  for (int i = t; i < j; i += NT) {
+    rc[i] = cs[i];
+    rsn[i] = sn[i];
+  }
+  __syncthreads();
+  const bool finite = ok != 0;
+  if (t == 0) {
+    if (!finite) {
+      // drop the column; the cycle ends with the finite part of the basis
+      S.k = j;
+      S.need_update = j > 0 ? 1 : 0;
+      S.active = 0;
+      if (a.precond != 0 && S.precond_on) {
+        S.precond_on = 0;
+        S.fallback_used = 1;
+      }
+    } else {
+      double* sv = a.s + (int64_t)s * M1;
+      double* sc = a.sc + (int64_t)s * M1;
+      double* ar = a.ares + (int64_t)s * M1;
+      // apply the previous rotations; only the running entry is carried
+      double cur = hcol[0];
+      for (int i = 0; i < j; ++i) {
+        const double nxt = hcol[i + 1];
+        hcol[i] = rc[i] * cur + rsn[i] * nxt;
+        cur = -rsn[i] * cur + rc[i] * nxt;
+      }
+      double c, sg;
+      givens(cur, hn, c, sg);
+      cs[j] = c;
+      sn[j] = sg;
+      const double sj = sv[j];
+      sv[j + 1] = -sg * sj;
+      sv[j] = c * sj;
+      hcol[j] = c * cur + sg * hn;
+      hcol[j + 1] = 0.0;
+      S.iters += 1;
+      S.k = j + 1;
+      S.need_update = 1;
+      const double res = fabs(sg * sj);
+      ar[j + 1] = res;
+      if (S.cycle == 1 && S.first_stall < 0) {
+        const int J = j + 1 - a.stall_win;
+        if (J >= 0 && res > ar[J] / 1.001) S.first_stall = J;
+      }
+      const double bd = 16.0 * (double)(j + 1) * unit_roundoff(a.prec);
+      const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
+                       S.iters >= a.max_iters ||
+                       (a.restart_improve > 0.0 && res <= a.restart_improve * S.beta);
+      if (a.prec == PBF16 || a.prec == PF16) {
+        if (!end) {
+          const int e = scale_exp(wmax / hn, a.prec);
+          sc[j + 1] = ldexp(1.0, -e);
+          S.enc_f = (float)(ldexp(1.0, e) / hn);
+        }
+      } else if (hn > 0.0) {
+        // w'' is already stored as column j+1; its scale also completes the
+        // last cycle's basis when the cycle ends here
+        sc[j + 1] = 1.0 / hn;
+      }
+      S.active = end ? 0 : 1;
     }
-    return;
   }
-  double* col = Hs + (int64_t)j * M1;
-  double* bcol = Hb + (int64_t)j * M1;
-  for (int i = 0; i <= j; ++i) {
-    bcol[i] = hc[i];
-    col[i] = hc[i];
+  __syncthreads();
+  if (finite) {
+    for (int i = t; i <= j; i += NT) bcol[i] = hc[i];
+    if (t == 0) bcol[j + 1] = hn;
+    for (int i = t; i <= j + 1; i += NT) col[i] = hcol[i];
   }
-  bcol[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {  // previous rotations
-    const double a0 = col[i], a1 = col[i + 1];
-    col[i] = cs[i] * a0 + sn[i] * a1;
-    col[i + 1] = -sn[i] * a0 + cs[i] * a1;
-  }
-  double c, sg;
-  givens(col[j], hn, c, sg);
-  cs[j] = c;
-  sn[j] = sg;
-  sv[j + 1] = -sg * sv[j];
-  sv[j] = c * sv[j];
-  col[j] = c * col[j] + sg * hn;
-  col[j + 1] = 0.0;
-  S.iters += 1;
-  S.k = j + 1;
-  S.need_update = 1;
-  const double res = fabs(sv[j + 1]);
-  ar[j + 1] = res;
-  if (S.cycle == 1 && S.first_stall < 0) {
-    const int J = j + 1 - a.stall_win;
-    if (J >= 0 && ar[j + 1] > ar[J] / 1.001) S.first_stall = J;
-  }
-  const double bd = 16.0 * (double)(j + 1) * unit_roundoff(a.prec);
-  const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
-                   S.iters >= a.max_iters ||
-                   (a.restart_improve > 0.0 && res <= a.restart_improve * S.beta);
-  if (a.prec == PBF16 || a.prec == PF16) {
-    if (!end) {
-      const int e = scale_exp(wmax / hn, a.prec);
-      sc[j + 1] = ldexp(1.0, -e);
-      S.enc_f = (float)(ldexp(1.0, e) / hn);
-    }
-  } else if (hn > 0.0) {
-    // w'' is already stored as column j+1; its scale also completes the
-    // last cycle's basis when the cycle ends here
-    sc[j + 1] = 1.0 / hn;
-  }
-  S.active = end ? 0 : 1;
 }
 
 __device__ void fin_residual(const KArgs& a, int s, double sumsq, double zmax) {
@@ -388,7 +406,28 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
     acc = block_sum(acc);
     if (t == 0) emit(r0, acc);
   } else {
-    for (int k = p0 + t; k < p1; k += kBlock) prod[k - p0] = (ACC)vals[k] * (ACC)ldv(x[a.ci[k]]);
+    // products staged in LDS; indices and values are read as aligned groups
+    // of four (16-byte index loads; the matrix arrays carry a zero pad of
+    // four entries so a group never leaves them)
+    const int q0 = p0 & ~3;
+    for (int k4 = q0 + 4 * t; k4 < p1; k4 += 4 * kBlock) {
+      const int4 c4 = *reinterpret_cast<const int4*>(a.ci + k4);
+      TA v4[4];
+      if constexpr (sizeof(TA) == 4) {
+        const float4 f = *reinterpret_cast<const float4*>(vals + k4);
+        v4[0] = f.x; v4[1] = f.y; v4[2] = f.z; v4[3] = f.w;
+      } else {
+        const double2 f0 = *reinterpret_cast<const double2*>(vals + k4);
+        const double2 f1 = *reinterpret_cast<const double2*>(vals + k4 + 2);
+        v4[0] = f0.x; v4[1] = f0.y; v4[2] = f1.x; v4[3] = f1.y;
+      }
+      const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = k4 + e;
+        if (k >= p0 && k < p1) prod[k - p0] = (ACC)v4[e] * (ACC)ldv(x[cc[e]]);
+      }
+    }
     __syncthreads();
     const int nr = r1 - r0;
     int tpr = 1;
@@ -412,100 +451,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
 
   }
 }
-
-// ---------------------------------------------------------------- finalise
-// One workgroup per system reduces the per-workgroup partial rows that the
-// preceding pass wrote (the kernel boundary makes them visible) and runs the
-// system's scalar step.
-
-enum FinMode { FIN_PASS1 = 0, FIN_PASS2 = 1, FIN_STEP = 2, FIN_RESID = 4, FIN_BNORM = 5 };
-
-// Scalar completions with one or two reduced quantities.  `src` is the
-// partial table the pass wrote (chunk grid: column stride nchunk; row-block
-// grid: column stride nrb).
-template <int MODE>
-__global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, const double* src, int j) {
-  const int s = blockIdx.x;
-  const SysState& S = a.st[s];
-  if (MODE == FIN_RESID) {
-    if (S.status != RUNNING && !S.force) return;
-  } else if (MODE != FIN_BNORM) {
-    if (!S.active && !S.force) return;
-  }
-  const int t = threadIdx.x;
-  if (MODE == FIN_RESID) {
-    const int b0 = a.sys_rb0[s], nb = a.sys_nrb[s];
-    const double sq = reduce_col<false>(src + b0, nb);
-    const double mx = reduce_col<true>(src + a.nrb + b0, nb);
-    if (t == 0) fin_residual(a, s, sq, mx);
-    return;
-  }
-  const int c0 = a.sys_ch0[s], nc = a.sys_nch[s];
-  if (MODE == FIN_STEP) {
-    const double sq = reduce_col<false>(src + c0, nc);
-    const double mx = reduce_col<true>(src + a.nchunk + c0, nc);
-    if (t == 0) fin_step(a, s, j, sq, mx);
-  } else {  // FIN_BNORM
-    const double sq = reduce_col<false>(src + c0, nc);
-    if (t == 0) {
-      SysState& W = a.st[s];
-      W.bnorm = sqrt(sq);
-      if (W.bnorm == 0.0) {
-        W.status = CONVERGED;
-        W.rel = 0.0;
-      }
-    }
-  }
-}
-
-// The CGS projections complete column by column: workgroup (s, q) reduces
-// column q of system s.  Pass 1: h1_q = sc_q * sum and the next axpy
-// coefficient h1_q * sc_q (column j+1 carries ||w||^2).  Pass 2: h2_q, the
-// column of H (h1 + h2) and the coefficient h2_q * sc_q.
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_fin_cols(KArgs a, int j) {
-  const int s = blockIdx.x, q = blockIdx.y;
-  const SysState& S = a.st[s];
-  if (!S.active && !S.force) return;
-  const double v = reduce_col<false>(a.part + (int64_t)q * a.nchunk + a.sys_ch0[s], a.sys_nch[s]);
-  if (threadIdx.x != 0) return;
-  const int M1 = a.m + 1, M2 = a.m + 2;
-  if (MODE == FIN_PASS1 && q == j + 1) {
-    a.st[s].wnorm_pre = sqrt(v);
-    return;
-  }
-  const double scq = a.sc[(int64_t)s * M1 + q];
-  const double h = scq * v;
-  if (MODE == FIN_PASS1) {
-    a.h1[(int64_t)s * M2 + q] = h;
-  } else {
-    a.hacc[(int64_t)s * M2 + q] = a.h1[(int64_t)s * M2 + q] + h;
-  }
-  a.coef[(int64_t)s * M2 + q] = h * scq;
-}
-
-hipError_t launch_finalize(const KArgs& a, int mode, int j, int i, hipStream_t st) {
-  (void)i;
-  switch (mode) {
-    case FIN_PASS1:
-      hipLaunchKernelGGL((k_fin_cols<FIN_PASS1>), dim3(a.S, j + 2), dim3(kBlock), 0, st, a, j);
-      break;
-    case FIN_PASS2:
-      hipLaunchKernelGGL((k_fin_cols<FIN_PASS2>), dim3(a.S, j + 1), dim3(kBlock), 0, st, a, j);
-      break;
-    case FIN_STEP:
-      hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, j);
-      break;
-    case FIN_RESID:
-      hipLaunchKernelGGL((k_fin<FIN_RESID>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, j);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------ basis passes
 
 // ------------------------------------------------------- buffer loads
 // The basis is read through one buffer resource: a per-lane byte offset of
@@ -542,15 +487,34 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t basis_rsrc(const KArgs& a, int
   return make_rsrc(a.V, (uint32_t)((int64_t)ncols * a.ld * (int64_t)sizeof(TV)));
 }
 
+
+// ------------------------------------------------------- persistent passes
+
+// Logical workgroup of a persistent pass: consecutive logical workgroups are
+// placed on one XCD, and passes that re-read the same basis columns alternate
+// direction so each starts on the rows the previous pass touched last, which
+// the memory-side cache still holds.
+__device__ __forceinline__ int pass_block(const KArgs& a, const SegTab& sg, int rev) {
+  const int b = remap_block(blockIdx.x, sg.G, a.xcd_remap);
+  return rev ? sg.G - 1 - b : b;
+}
+
+__device__ __forceinline__ int64_t tile_row(const SegTab& sg, int k, int u, int rev) {
+  const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+  const int tile = rev ? t0 + nt - 1 - u : t0 + u;
+  return (int64_t)tile * kTile + threadIdx.x;
+}
+
 template <typename T>
 __device__ __forceinline__ const T* col_ptr(const KArgs& a, int i) {
   return reinterpret_cast<const T*>(a.V) + (int64_t)i * a.ld;
 }
 
-// Writes the per-wave column sums (lane-owned after reduce_scatter) into
-// part[c][col0 + q] for q < ncol, in a fixed cross-wave order.
+// Per-wave column sums (lane-owned after reduce_scatter) to quantities
+// col0 .. col0 + ncol - 1 of partial row k, in a fixed cross-wave order.
 template <int L, typename ACC>
-__device__ __forceinline__ void store_colsums(const KArgs& a, int c, int col0, int ncol, ACC colsum) {
+__device__ __forceinline__ void store_colsums(double* part, int nrows, int k, int col0, int ncol,
+                                              ACC colsum) {
   __shared__ ACC lds[kBlock / 64][L];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int R = 64 / L;  // lanes per column
@@ -559,221 +523,247 @@ __device__ __forceinline__ void store_colsums(const KArgs& a, int c, int col0, i
   if (threadIdx.x < ncol) {
     ACC tot = lds[0][threadIdx.x];
 #pragma unroll
-    for (int k = 1; k < kBlock / 64; ++k) tot += lds[k][threadIdx.x];
-    a.part[(int64_t)(col0 + threadIdx.x) * a.nchunk + c] = (double)tot;
+    for (int q = 1; q < kBlock / 64; ++q) tot += lds[q][threadIdx.x];
+    part[(int64_t)(col0 + threadIdx.x) * nrows + k] = (double)tot;
   }
   __syncthreads();
 }
 
-// CGSR projection 1 (columns [col0, col0 + L) of V^T w) and ||w||^2.
-// mode 1: finalise as the first projection; mode 2: as the second.
+// CGSR projection, first half: quantities col0 .. of V^T w for the columns
+// [col0, col0 + L) below j + 1, plus ||w||^2 (quantity j + 1) when col0 = 0
+// and mode = 1.  mode 2: the second projection's dots when j + 1 > 64.
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, int j, int col0, int mode, int rev) {
+__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int col0, int mode, int rev) {
   using ACC = typename AccOf<TV>::type;
-  const int c = pass_chunk(a, rev);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
-  const int t = threadIdx.x, lane = t & 63;
+  const int b = pass_block(a, sg, rev);
+  const int lane = threadIdx.x & 63;
   const int ncol = min(L, j + 1 - col0);
   const TW* w = reinterpret_cast<const TW*>(a.w);
   const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, col0 + ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
   const uint32_t c0off = (uint32_t)col0 * cstride;
-  const int64_t base = (int64_t)c * kChunk + t;
-  ACC colsum = (ACC)0, ww = (ACC)0;
   uint32_t cs = cstride;
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    if (!gated(a, sg.seg_sys[k])) continue;
+    const int nt = sg.seg_nt[k];
+    ACC colsum = (ACC)0, ww = (ACC)0;
 #pragma unroll 1
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    // column offsets are rebuilt per tile (a scalar add each) instead of
-    // being hoisted into L live scalar registers
-    asm volatile("" : "+s"(cs));
-    const int64_t r = base + u * kBlock;
-    const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV)) + c0off;
-    const ACC wr = (ACC)w[r];
-    ww += wr * wr;
-    ACC p[L];
-    uint32_t so = 0;
+    for (int u = 0; u < nt; ++u) {
+      // column offsets are rebuilt per tile (a scalar add each) instead of
+      // being hoisted into L live scalar registers
+      asm volatile("" : "+s"(cs));
+      const int64_t r = tile_row(sg, k, u, rev);
+      const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV)) + c0off;
+      const ACC wr = (ACC)w[r];
+      ww += wr * wr;
+      ACC p[L];
+      uint32_t so = 0;
 #pragma unroll
-    for (int q = 0; q < L; ++q) {
-      p[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0)) * wr;
-      if (q < ncol) so += cs;
+      for (int q = 0; q < L; ++q) {
+        p[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0)) * wr;
+        if (q < ncol) so += cs;
+      }
+      colsum += reduce_scatter<L>(p, lane);
     }
-    colsum += reduce_scatter<L>(p, lane);
-  }
-  store_colsums<L>(a, c, col0, ncol, colsum);
-  if (col0 == 0 && mode == 1) {
-    const ACC tot = block_sum(ww);
-    if (t == 0) a.part[(int64_t)(j + 1) * a.nchunk + c] = (double)tot;
+    store_colsums<L>(a.part, sg.nseg, k, col0, ncol, colsum);
+    if (col0 == 0 && mode == 1) {
+      const ACC tot = block_sum(ww);
+      if (threadIdx.x == 0) a.part[(int64_t)(j + 1) * sg.nseg + k] = (double)tot;
+    }
   }
 }
 
 // CGSR projection 2, fused: w' = w - V coef (coef from projection 1), then
 // V^T w' from the same register tile of V.  Requires j + 1 <= L <= 64.
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_axpy_mdot(KArgs a, int j, int rev) {
+__device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg, int j, int rev) {
   using ACC = typename AccOf<TV>::type;
-  const int c = pass_chunk(a, rev);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
+  const int b = pass_block(a, sg, rev);
   const int t = threadIdx.x, lane = t & 63;
   const int ncol = j + 1;
   TW* w = reinterpret_cast<TW*>(a.w);
   const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
-  const double* coefd = a.coef + (int64_t)s * (a.m + 2);
-  __shared__ ACC cf[L];
-  if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
-  __syncthreads();
-  const int64_t base = (int64_t)c * kChunk + t;
-  ACC colsum = (ACC)0;
   uint32_t cs = cstride;
+  __shared__ ACC cf[L];
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    const int s = sg.seg_sys[k];
+    if (!gated(a, s)) continue;
+    const double* coefd = a.coef + (int64_t)s * (a.m + 2);
+    if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
+    __syncthreads();
+    const int nt = sg.seg_nt[k];
+    ACC colsum = (ACC)0;
 #pragma unroll 1
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    asm volatile("" : "+s"(cs));
-    const int64_t r = base + u * kBlock;
-    const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
-    ACC v[L];
-    uint32_t so = 0;
+    for (int u = 0; u < nt; ++u) {
+      asm volatile("" : "+s"(cs));
+      const int64_t r = tile_row(sg, k, u, rev);
+      const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
+      ACC v[L];
+      uint32_t so = 0;
 #pragma unroll
-    for (int q = 0; q < L; ++q) {
-      v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
-      if (q < ncol) so += cs;
+      for (int q = 0; q < L; ++q) {
+        v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
+        if (q < ncol) so += cs;
+      }
+      ACC wr = (ACC)w[r];
+#pragma unroll
+      for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
+      w[r] = (TW)wr;
+#pragma unroll
+      for (int q = 0; q < L; ++q) v[q] *= wr;
+      colsum += reduce_scatter<L>(v, lane);
     }
-    ACC wr = (ACC)w[r];
-#pragma unroll
-    for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
-    w[r] = (TW)wr;
-#pragma unroll
-    for (int q = 0; q < L; ++q) v[q] *= wr;
-    colsum += reduce_scatter<L>(v, lane);
+    store_colsums<L>(a.part, sg.nseg, k, 0, ncol, colsum);
   }
-  store_colsums<L>(a, c, 0, ncol, colsum);
+}
+
+// 4-byte and 2-byte bases: capped at 128 registers so four workgroups fit on
+// a CU; the float64 tile needs more registers than that.
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_axpy_mdot(KArgs a, SegTab sg, int j, int rev) {
+  axpy_mdot_body<TV, TW, L>(a, sg, j, rev);
+}
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_axpy_mdot64(KArgs a, SegTab sg, int j, int rev) {
+  axpy_mdot_body<TV, TW, L>(a, sg, j, rev);
 }
 
 // w -= V[:, col0:col0+L] coef (no reduction): the first half of projection 2
 // when j + 1 > 64.
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, int j, int col0) {
+__global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, SegTab sg, int j, int col0) {
   using ACC = typename AccOf<TV>::type;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
-  const int t = threadIdx.x;
+  const int b = pass_block(a, sg, 0);
   const int ncol = min(L, j + 1 - col0);
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* V0 = col_ptr<TV>(a, col0);
-  const double* coefd = a.coef + (int64_t)s * (a.m + 2) + col0;
-  const int64_t base = (int64_t)c * kChunk + t;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    ACC wr = (ACC)w[r];
-    for (int q = 0; q < ncol; ++q) wr -= (ACC)coefd[q] * (ACC)ldv(V0[(int64_t)q * a.ld + r]);
-    w[r] = (TW)wr;
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    const int s = sg.seg_sys[k];
+    if (!gated(a, s)) continue;
+    const double* coefd = a.coef + (int64_t)s * (a.m + 2) + col0;
+    const int nt = sg.seg_nt[k];
+    for (int u = 0; u < nt; ++u) {
+      const int64_t r = tile_row(sg, k, u, 0);
+      ACC wr = (ACC)w[r];
+      for (int q = 0; q < ncol; ++q) wr -= (ACC)coefd[q] * (ACC)ldv(V0[(int64_t)q * a.ld + r]);
+      w[r] = (TW)wr;
+    }
   }
 }
 
-// Last pass of a step: w'' = w - sum_{i0 <= i <= j} coef_i v_i, ||w''||^2 and
-// max|w''|; w'' goes to basis column j+1 (float32 / float64 basis, where
-// the decode scale 1/h_{j+1,j} normalises it) or stays in w (2-byte basis,
-// encoded by k_encode).  The last block runs the Givens step.
-template <typename TV, typename TW>
-__global__ __launch_bounds__(kBlock) void k_final(KArgs a, int j, int i0) {
-  using ACC = typename AccOf<TV>::type;
-  constexpr bool kTwoByte = sizeof(TV) == 2;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
-  const int t = threadIdx.x;
-  TW* w = reinterpret_cast<TW*>(a.w);
-  const double* coefd = a.coef + (int64_t)s * (a.m + 2);
-  const int64_t base = (int64_t)c * kChunk + t;
-  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
-  ACC sq = (ACC)0, mx = (ACC)0;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    ACC wr = (ACC)w[r];
-    for (int i = i0; i <= j; ++i) wr -= (ACC)coefd[i] * (ACC)ldv(col_ptr<TV>(a, i)[r]);
-    sq += wr * wr;
-    mx = fmax(mx, fabs(wr));
-    if constexpr (kTwoByte)
-      w[r] = (TW)wr;
-    else
-      vout[r] = (TV)wr;
-  }
+// Writes the end-of-step partials (||w''||^2, max|w''|) of segment k.
+template <typename ACC>
+__device__ __forceinline__ void store_norm_partials(double* part, int nrows, int k, ACC sq, ACC mx) {
   const double tsq = (double)block_sum(sq);
   const double tmx = (double)block_max(mx);
-  if (t == 0) {
-    a.part[c] = tsq;
-    a.part[(int64_t)a.nchunk + c] = tmx;
+  if (threadIdx.x == 0) {
+    part[k] = tsq;
+    part[(int64_t)nrows + k] = tmx;
   }
 }
 
-// The same last pass for CGSR with j + 1 <= L <= 64 columns: the whole tile
-// of basis loads is issued at once through the bounded buffer resource.
+// Last CGSR pass of a step: w'' = w' - sum_{i <= j} coef_i v_i with the whole
+// tile of basis loads in flight (j + 1 <= L <= 64), ||w''||^2 and max|w''|.
+// w'' goes to basis column j+1 (float32 / float64 basis, normalised by the
+// decode scale 1/h_{j+1,j}) or stays in w (2-byte basis, encoded later).
 template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, int j, int rev) {
+__global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j, int rev) {
   using ACC = typename AccOf<TV>::type;
   constexpr bool kTwoByte = sizeof(TV) == 2;
-  const int c = pass_chunk(a, rev);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
+  const int b = pass_block(a, sg, rev);
   const int t = threadIdx.x;
   const int ncol = j + 1;
   TW* w = reinterpret_cast<TW*>(a.w);
   const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
-  const double* coefd = a.coef + (int64_t)s * (a.m + 2);
-  __shared__ ACC cf[L];
-  if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
-  __syncthreads();
-  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
-  const int64_t base = (int64_t)c * kChunk + t;
-  ACC sq = (ACC)0, mx = (ACC)0;
   uint32_t cs = cstride;
+  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
+  __shared__ ACC cf[L];
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    const int s = sg.seg_sys[k];
+    if (!gated(a, s)) continue;
+    const double* coefd = a.coef + (int64_t)s * (a.m + 2);
+    if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
+    __syncthreads();
+    const int nt = sg.seg_nt[k];
+    ACC sq = (ACC)0, mx = (ACC)0;
 #pragma unroll 1
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    asm volatile("" : "+s"(cs));
-    const int64_t r = base + u * kBlock;
-    const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
-    ACC v[L];
-    uint32_t so = 0;
+    for (int u = 0; u < nt; ++u) {
+      asm volatile("" : "+s"(cs));
+      const int64_t r = tile_row(sg, k, u, rev);
+      const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
+      ACC v[L];
+      uint32_t so = 0;
 #pragma unroll
-    for (int q = 0; q < L; ++q) {
-      v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
-      if (q < ncol) so += cs;
+      for (int q = 0; q < L; ++q) {
+        v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
+        if (q < ncol) so += cs;
+      }
+      ACC wr = (ACC)w[r];
+#pragma unroll
+      for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
+      sq += wr * wr;
+      mx = fmax(mx, fabs(wr));
+      if constexpr (kTwoByte)
+        w[r] = (TW)wr;
+      else
+        vout[r] = (TV)wr;
     }
-    ACC wr = (ACC)w[r];
-#pragma unroll
-    for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
-    sq += wr * wr;
-    mx = fmax(mx, fabs(wr));
-    if constexpr (kTwoByte)
-      w[r] = (TW)wr;
-    else
-      vout[r] = (TV)wr;
+    store_norm_partials(a.part, sg.nseg, k, sq, mx);
   }
-  const double tsq = (double)block_sum(sq);
-  const double tmx = (double)block_max(mx);
-  if (t == 0) {
-    a.part[c] = tsq;
-    a.part[(int64_t)a.nchunk + c] = tmx;
+}
+
+// The same last pass for j + 1 > 64 (column loop instead of a register tile).
+template <typename TV, typename TW>
+__global__ __launch_bounds__(kBlock) void k_final(KArgs a, SegTab sg, int j) {
+  using ACC = typename AccOf<TV>::type;
+  constexpr bool kTwoByte = sizeof(TV) == 2;
+  const int b = pass_block(a, sg, 0);
+  TW* w = reinterpret_cast<TW*>(a.w);
+  TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    const int s = sg.seg_sys[k];
+    if (!gated(a, s)) continue;
+    const double* coefd = a.coef + (int64_t)s * (a.m + 2);
+    const int nt = sg.seg_nt[k];
+    ACC sq = (ACC)0, mx = (ACC)0;
+    for (int u = 0; u < nt; ++u) {
+      const int64_t r = tile_row(sg, k, u, 0);
+      ACC wr = (ACC)w[r];
+      for (int i = 0; i <= j; ++i) wr -= (ACC)coefd[i] * (ACC)ldv(col_ptr<TV>(a, i)[r]);
+      sq += wr * wr;
+      mx = fmax(mx, fabs(wr));
+      if constexpr (kTwoByte)
+        w[r] = (TW)wr;
+      else
+        vout[r] = (TV)wr;
+    }
+    store_norm_partials(a.part, sg.nseg, k, sq, mx);
   }
 }
 
 // MGS, fused: step i of Arnoldi column j first completes dot i-1 itself
 // (every workgroup reduces the previous launch's partials of its system in
-// the same fixed order, so all hold the same h_{i-1}; the system's first
-// workgroup records it in H), then w -= h_{i-1} v_{i-1} and the partial dot
-// w . v_i.  Partial tables alternate between two buffers by the parity of i.
-__device__ __forceinline__ double mgs_complete(const KArgs& a, int s, int c, int i, const double* pin) {
-  const int c0 = a.sys_ch0[s], nc = a.sys_nch[s];
+// the same fixed order, so all hold the same h_{i-1}; the workgroup owning
+// the system's first segment records it in H), then w -= h_{i-1} v_{i-1} and
+// the partial dot w . v_i.  Partial tables alternate by the parity of i.
+constexpr int kMgsUnroll = 4;
+// the MGS steps use a fixed grid of kMgsOcc workgroups per CU: a step is
+// short, so the partial rows every workgroup re-reduces are kept few
+constexpr int kMgsOcc = 4;
+
+__device__ __forceinline__ double mgs_complete(const KArgs& a, const SegTab& sgp, int s, bool first,
+                                               int i, const double* pin) {
+  const int g0 = sgp.sys_sg0[s], ng = sgp.sys_nsg[s];
   const int M1 = a.m + 1, M2 = a.m + 2;
-  const double d = reduce_col<false>(pin + c0, nc);
+  const double d = reduce_col<false>(pin + g0, ng);
   const double sci = a.sc[(int64_t)s * M1 + i];
   const double h = sci * d;
-  if (c == c0) {
+  if (first) {
     double wn = 0.0;
-    if (i == 0) wn = sqrt(reduce_col<false>(pin + a.nchunk + c0, nc));
+    if (i == 0) wn = sqrt(reduce_col<false>(pin + sgp.nseg + g0, ng));
     if (threadIdx.x == 0) {
       a.hacc[(int64_t)s * M2 + i] = h;
       a.coef[(int64_t)s * M2 + i] = h * sci;
@@ -784,113 +774,190 @@ __device__ __forceinline__ double mgs_complete(const KArgs& a, int s, int c, int
 }
 
 template <typename TV, typename TW>
-__global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, int j, int i) {
+__global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i) {
   using ACC = typename AccOf<TV>::type;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
-  const int t = threadIdx.x;
+  const int b = pass_block(a, sg, i & 1);
   double* pout = (i & 1) ? a.part2 : a.part;
   const double* pin = (i & 1) ? a.part : a.part2;  // dot i-1
-  const ACC cprev = i > 0 ? (ACC)mgs_complete(a, s, c, i - 1, pin) : (ACC)0;
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* vi = col_ptr<TV>(a, i);
   const TV* vp = col_ptr<TV>(a, i > 0 ? i - 1 : 0);
-  const int64_t base = (int64_t)c * kChunk + t;
-  ACC d = (ACC)0, ww = (ACC)0;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    ACC wr = (ACC)w[r];
-    if (i > 0) {
-      wr -= cprev * (ACC)ldv(vp[r]);
-      w[r] = (TW)wr;
-    } else {
-      ww += wr * wr;
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    const int s = sg.seg_sys[k];
+    if (!gated(a, s)) continue;
+    const ACC cprev = i > 0 ? (ACC)mgs_complete(a, sg, s, k == sg.sys_sg0[s], i - 1, pin) : (ACC)0;
+    const int nt = sg.seg_nt[k];
+    ACC d = (ACC)0, ww = (ACC)0;
+    // kMgsUnroll tiles per iteration: all their loads are issued before use
+    for (int u = 0; u < nt; u += kMgsUnroll) {
+      int64_t r[kMgsUnroll];
+      ACC wv[kMgsUnroll], pv[kMgsUnroll], iv[kMgsUnroll];
+#pragma unroll
+      for (int q = 0; q < kMgsUnroll; ++q) {
+        r[q] = tile_row(sg, k, u + q < nt ? u + q : u, i & 1);
+        wv[q] = (ACC)w[r[q]];
+        pv[q] = i > 0 ? (ACC)ldv(vp[r[q]]) : (ACC)0;
+        iv[q] = (ACC)ldv(vi[r[q]]);
+      }
+#pragma unroll
+      for (int q = 0; q < kMgsUnroll; ++q) {
+        if (u + q >= nt) continue;
+        ACC wr = wv[q];
+        if (i > 0) {
+          wr -= cprev * pv[q];
+          w[r[q]] = (TW)wr;
+        } else {
+          ww += wr * wr;
+        }
+        d += wr * iv[q];
+      }
     }
-    d += wr * (ACC)ldv(vi[r]);
-  }
-  const double td = (double)block_sum(d);
-  double tw = 0.0;
-  if (i == 0) tw = (double)block_sum(ww);
-  if (t == 0) {
-    pout[c] = td;
-    if (i == 0) pout[(int64_t)a.nchunk + c] = tw;
+    const double td = (double)block_sum(d);
+    double tw = 0.0;
+    if (i == 0) tw = (double)block_sum(ww);
+    if (threadIdx.x == 0) {
+      pout[k] = td;
+      if (i == 0) pout[(int64_t)sg.nseg + k] = tw;
+    }
   }
 }
 
-// Last MGS pass of column j: completes dot j, w'' = w - h_j v_j, and the
-// partials of ||w''||^2 and max|w''| for the Givens step.
+// Last MGS pass of column j: completes dot j (partials written by k_mgs with
+// split sgp), w'' = w - h_j v_j, and the partials of ||w''||^2, max|w''|.
 template <typename TV, typename TW>
-__global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, int j) {
+__global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab sgp, int j) {
   using ACC = typename AccOf<TV>::type;
   constexpr bool kTwoByte = sizeof(TV) == 2;
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
-  if (!gated(a, s)) return;
-  const int t = threadIdx.x;
+  const int b = pass_block(a, sg, (j + 1) & 1);
   const double* pin = (j & 1) ? a.part2 : a.part;
   double* pout = (j & 1) ? a.part : a.part2;
-  const ACC cj = (ACC)mgs_complete(a, s, c, j, pin);
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* vj = col_ptr<TV>(a, j);
   TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
-  const int64_t base = (int64_t)c * kChunk + t;
-  ACC sq = (ACC)0, mx = (ACC)0;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    const ACC wr = (ACC)w[r] - cj * (ACC)ldv(vj[r]);
-    sq += wr * wr;
-    mx = fmax(mx, fabs(wr));
-    if constexpr (kTwoByte)
-      w[r] = (TW)wr;
-    else
-      vout[r] = (TV)wr;
-  }
-  const double tsq = (double)block_sum(sq);
-  const double tmx = (double)block_max(mx);
-  if (t == 0) {
-    pout[c] = tsq;
-    pout[(int64_t)a.nchunk + c] = tmx;
+  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
+    const int s = sg.seg_sys[k];
+    if (!gated(a, s)) continue;
+    const ACC cj = (ACC)mgs_complete(a, sgp, s, k == sg.sys_sg0[s], j, pin);
+    const int nt = sg.seg_nt[k];
+    ACC sq = (ACC)0, mx = (ACC)0;
+    for (int u = 0; u < nt; u += kMgsUnroll) {
+      int64_t r[kMgsUnroll];
+      ACC wv[kMgsUnroll], jv[kMgsUnroll];
+#pragma unroll
+      for (int q = 0; q < kMgsUnroll; ++q) {
+        r[q] = tile_row(sg, k, u + q < nt ? u + q : u, (j + 1) & 1);
+        wv[q] = (ACC)w[r[q]];
+        jv[q] = (ACC)ldv(vj[r[q]]);
+      }
+#pragma unroll
+      for (int q = 0; q < kMgsUnroll; ++q) {
+        if (u + q >= nt) continue;
+        const ACC wr = wv[q] - cj * jv[q];
+        sq += wr * wr;
+        mx = fmax(mx, fabs(wr));
+        if constexpr (kTwoByte)
+          w[r[q]] = (TW)wr;
+        else
+          vout[r[q]] = (TV)wr;
+      }
+    }
+    store_norm_partials(pout, sg.nseg, k, sq, mx);
   }
 }
+
+// ---------------------------------------------------------------- finalise
+// The per-system completions read the partial rows the preceding pass wrote
+// (the kernel boundary makes them visible) and run the system's scalar step.
+
+enum FinMode { FIN_STEP = 0, FIN_RESID = 1, FIN_BNORM = 2 };
+
+// `src` with column stride `rows`; system s owns rows [r0[s], r0[s] + nr[s]).
+template <int MODE>
+__global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, const double* src, int rows, const int32_t* r0,
+                                                  const int32_t* nr, int j) {
+  const int s = blockIdx.x;
+  const SysState& S = a.st[s];
+  if (MODE == FIN_RESID) {
+    if (S.status != RUNNING && !S.force) return;
+  } else if (MODE == FIN_STEP) {
+    if (!S.active && !S.force) return;
+  }
+  const int b0 = r0[s], n = nr[s];
+  const double sq = reduce_col<false>(src + b0, n);
+  if (MODE == FIN_BNORM) {
+    if (threadIdx.x == 0) {
+      SysState& W = a.st[s];
+      W.bnorm = sqrt(sq);
+      if (W.bnorm == 0.0) {
+        W.status = CONVERGED;
+        W.rel = 0.0;
+      }
+    }
+    return;
+  }
+  const double mx = reduce_col<true>(src + rows + b0, n);
+  if (MODE == FIN_RESID) {
+    if (threadIdx.x == 0) fin_residual(a, s, sq, mx);
+  } else {
+    fin_step(a, s, j, sq, mx);
+  }
+}
+
+// The CGS projections complete column by column: workgroup (s, q) reduces
+// quantity q of system s.  Pass 1: h1_q = sc_q * sum and the next axpy
+// coefficient h1_q * sc_q (quantity j+1 carries ||w||^2).  Pass 2: h2_q, the
+// column of H (h1 + h2) and the coefficient h2_q * sc_q.
+template <int PASS>
+__global__ __launch_bounds__(kBlock) void k_fin_cols(KArgs a, SegTab sg, int j) {
+  const int s = blockIdx.x, q = blockIdx.y;
+  const SysState& S = a.st[s];
+  if (!S.active && !S.force) return;
+  const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + sg.sys_sg0[s], sg.sys_nsg[s]);
+  if (threadIdx.x != 0) return;
+  const int M1 = a.m + 1, M2 = a.m + 2;
+  if (PASS == 1 && q == j + 1) {
+    a.st[s].wnorm_pre = sqrt(v);
+    return;
+  }
+  const double scq = a.sc[(int64_t)s * M1 + q];
+  const double h = scq * v;
+  if (PASS == 1)
+    a.h1[(int64_t)s * M2 + q] = h;
+  else
+    a.hacc[(int64_t)s * M2 + q] = a.h1[(int64_t)s * M2 + q] + h;
+  a.coef[(int64_t)s * M2 + q] = h * scq;
+}
+
+// ------------------------------------------------------------ tile kernels
+// One workgroup per 256-row tile, one row per thread.
 
 // Store w as basis column col: a 2-byte encoding with the scale prepared by
 // the finaliser, or a plain copy for the float32 / float64 basis.
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kBlock) void k_encode(KArgs a, int col) {
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
+  const int s = a.tile_sys[blockIdx.x];
   if (!gated(a, s)) return;
   const float f = a.st[s].enc_f;
   const TW* w = reinterpret_cast<const TW*>(a.w);
   TV* out = reinterpret_cast<TV*>(a.V) + (int64_t)col * a.ld;
-  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    if constexpr (sizeof(TV) == 2)
-      out[r] = stv<TV>(mul_rn((float)w[r], f));
-    else
-      out[r] = (TV)w[r];
-  }
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  if constexpr (sizeof(TV) == 2)
+    out[r] = stv<TV>(mul_rn((float)w[r], f));
+  else
+    out[r] = (TV)w[r];
 }
 
 // Jacobi: z_j = D^-1 v_j (or v_j once the preconditioner is switched off).
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_jacobi(KArgs a, int j) {
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
+  const int s = a.tile_sys[blockIdx.x];
   if (!gated(a, s)) return;
   const float scale = (float)a.sc[(int64_t)s * (a.m + 1) + j];
   const bool on = a.st[s].precond_on != 0;
-  const TV* v = col_ptr<TV>(a, j);
-  float* z = a.Z + (int64_t)j * a.ld;
-  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    // (d^-1 v) * scale: the same rounding as a sparse M = D^-1 applied by the SpMV
-    const float vr = (float)ldv(v[r]);
-    z[r] = on ? (a.dinv[r] * vr) * scale : vr * scale;
-  }
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  // (d^-1 v) * scale: the same rounding as a sparse M = D^-1 applied by the SpMV
+  const float vr = (float)ldv(col_ptr<TV>(a, j)[r]);
+  a.Z[(int64_t)j * a.ld + r] = on ? (a.dinv[r] * vr) * scale : vr * scale;
 }
 
 // y = H^-1 s by back-substitution, one wave per system, with truncation of
@@ -939,46 +1006,32 @@ __global__ __launch_bounds__(64) void k_backsolve(KArgs a) {
 // x += Z y in the flexible form.
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_update(KArgs a) {
-  const int c = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.ch_sys[c];
+  const int s = a.tile_sys[blockIdx.x];
   const SysState& S = a.st[s];
   if (!S.need_update && !S.force) return;
   const int kk = S.kk;
   const double* yv = a.y + (int64_t)s * a.m;
-  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
-  const bool useZ = a.precond != 0;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const int64_t r = base + u * kBlock;
-    double acc = a.x[r];
-    if (useZ) {
-      for (int i = 0; i < kk; ++i) acc += yv[i] * (double)a.Z[(int64_t)i * a.ld + r];
-    } else {
-      for (int i = 0; i < kk; ++i) acc += yv[i] * (double)ldv(col_ptr<TV>(a, i)[r]);
-    }
-    a.x[r] = acc;
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  double acc = a.x[r];
+  if (a.precond != 0) {
+    for (int i = 0; i < kk; ++i) acc += yv[i] * (double)a.Z[(int64_t)i * a.ld + r];
+  } else {
+    for (int i = 0; i < kk; ++i) acc += yv[i] * (double)ldv(col_ptr<TV>(a, i)[r]);
   }
+  a.x[r] = acc;
 }
 
-// ||b||_2 per system; systems with b = 0 are done (x = 0).
+// ||b||^2 partial per tile; systems with b = 0 are done (x = 0).
 __global__ __launch_bounds__(kBlock) void k_bnorm(KArgs a) {
-  const int c = blockIdx.x;
-  const int s = a.ch_sys[c];
-  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
-  double sq = 0.0;
-  for (int u = 0; u < kRowsPerThread; ++u) {
-    const double v = a.b[base + u * kBlock];
-    sq += v * v;
-  }
-  sq = block_sum(sq);
-  if (threadIdx.x == 0) a.part[c] = sq;
+  const double v = a.b[(int64_t)blockIdx.x * kTile + threadIdx.x];
+  const double sq = block_sum(v * v);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = sq;
 }
 
 __global__ void k_zero_x_if_b_zero(KArgs a) {
-  const int c = blockIdx.x;
-  const int s = a.ch_sys[c];
+  const int s = a.tile_sys[blockIdx.x];
   if (a.st[s].bnorm != 0.0) return;
-  const int64_t base = (int64_t)c * kChunk + threadIdx.x;
-  for (int u = 0; u < kRowsPerThread; ++u) a.x[base + u * kBlock] = 0.0;
+  a.x[(int64_t)blockIdx.x * kTile + threadIdx.x] = 0.0;
 }
 
 __global__ void k_init_state(KArgs a) {
@@ -992,7 +1045,6 @@ __global__ void k_init_state(KArgs a) {
   S.precond_on = a.precond != 0 ? 1 : 0;
   S.first_stall = -1;
   a.st[s] = S;
-  a.cnt[s] = 0;
 }
 
 __global__ void k_set_force(KArgs a, int on) {
@@ -1004,7 +1056,7 @@ __global__ void k_set_force(KArgs a, int on) {
 __global__ void k_check_cols(KArgs a, int32_t* bad) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
-  const int s = a.ch_sys[r / kChunk];
+  const int s = a.tile_sys[r / kTile];
   const int64_t lo = a.sys_row0[s], hi = lo + a.sys_n[s];
   for (int k = a.rp[r]; k < a.rp[r + 1]; ++k) {
     const int64_t c = a.ci[k];
@@ -1022,7 +1074,7 @@ __global__ void k_convert_f32(const double* __restrict__ src, float* __restrict_
 }
 
 __global__ void k_jacobi_setup(KArgs a, float* dinv) {
-  // one thread per row of the real (unpadded) rows; padding stays 0
+  // one thread per row; padding rows (empty) get 0
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
   const int p0 = a.rp[r], p1 = a.rp[r + 1];
@@ -1057,14 +1109,6 @@ __global__ void k_scatter(const double* __restrict__ src, double* const* __restr
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n[s];
        i += (int64_t)gridDim.x * blockDim.x)
     p[i] = src[base + i];
-}
-
-__global__ void k_sumsq(const double* __restrict__ v, int64_t n, double* part) {
-  double sq = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-    sq += v[i] * v[i];
-  sq = block_sum(sq);
-  if (threadIdx.x == 0) part[blockIdx.x] = sq;
 }
 
 __global__ void k_absmax(const float* __restrict__ v, int64_t n, float* part) {
@@ -1112,6 +1156,57 @@ static hipError_t launch_by_prec(int prec, F&& f) {
   return hipErrorInvalidValue;
 }
 
+// Resident workgroups per CU of each persistent kernel, queried once.
+static std::mutex g_occ_mu;
+static std::map<const void*, int> g_occ;
+
+static int occupancy_of(const void* fn) {
+  std::lock_guard<std::mutex> lock(g_occ_mu);
+  auto it = g_occ.find(fn);
+  if (it != g_occ.end()) return it->second;
+  int nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+  nb = std::min(nb, kMaxOcc);
+  g_occ[fn] = nb;
+  return nb;
+}
+
+template <typename K>
+static const SegTab& split_for(const KArgs& a, K kernel) {
+  return a.seg[occupancy_of(reinterpret_cast<const void*>(kernel)) - 1];
+}
+
+// direction of the CGS passes: projection 1 forward, projection 2 backward,
+// the last pass forward again
+constexpr int kRevPass1 = 0, kRevPass2 = 1, kRevPass3 = 0;
+
+template <typename TV, typename TW, int L>
+static hipError_t launch_mdot_L(const KArgs& a, int j, int col0, int mode, hipStream_t st, const SegTab** used) {
+  auto kern = k_mdot<TV, TW, L>;
+  const SegTab& sg = split_for(a, kern);
+  hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, col0, mode,
+                     mode == 1 ? kRevPass1 : kRevPass2);
+  if (used) *used = &sg;
+  return hipGetLastError();
+}
+
+template <typename TV, typename TW>
+static hipError_t launch_mdot_window(const KArgs& a, int j, int col0, int mode, int L, hipStream_t st,
+                                     const SegTab** used) {
+  switch (L) {
+    case 8: return launch_mdot_L<TV, TW, 8>(a, j, col0, mode, st, used);
+    case 16: return launch_mdot_L<TV, TW, 16>(a, j, col0, mode, st, used);
+    case 32: return launch_mdot_L<TV, TW, 32>(a, j, col0, mode, st, used);
+    default: return launch_mdot_L<TV, TW, 64>(a, j, col0, mode, st, used);
+  }
+}
+
+template <int PASS>
+static hipError_t launch_fin_cols(const KArgs& a, const SegTab& sg, int j, hipStream_t st) {
+  hipLaunchKernelGGL((k_fin_cols<PASS>), dim3(a.S, PASS == 1 ? j + 2 : j + 1), dim3(kBlock), 0, st, a, sg, j);
+  return hipGetLastError();
+}
+
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
   const size_t sh = (size_t)a.spmv_budget * (a.prec == P64 ? 8 : 4);
   if (a.precond != 0) {  // w = A z_j
@@ -1139,7 +1234,7 @@ hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
   return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
     using TV = decltype(tv);
     if (a.precond == 1) {
-      hipLaunchKernelGGL((k_jacobi<TV>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j);
+      hipLaunchKernelGGL((k_jacobi<TV>), dim3(a.ntile), dim3(kBlock), 0, st, a, j);
     } else {
       const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
       hipLaunchKernelGGL((k_spmv<float, TV, float, SM_PRECOND>), dim3(a.nrb), dim3(kBlock),
@@ -1161,111 +1256,177 @@ hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {
                        a.a64, a.x, (float*)a.w, a.b, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !with_fin) return e;
-  return launch_finalize(a, FIN_RESID, 0, 0, st);
+  hipLaunchKernelGGL((k_fin<FIN_RESID>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.nrb, a.sys_rb0,
+                     a.sys_nrb, 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_encode(const KArgs& a, int col, hipStream_t st) {
   return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
-    hipLaunchKernelGGL((k_encode<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, col);
+    hipLaunchKernelGGL((k_encode<TV, TW>), dim3(a.ntile), dim3(kBlock), 0, st, a, col);
     return hipGetLastError();
   });
 }
 
-// direction of the CGS passes: projection 1 forward, projection 2 backward,
-// the last pass forward again
-constexpr int kRevPass1 = 0, kRevPass2 = 1, kRevPass3 = 0;
-
-template <typename TV, typename TW>
-static hipError_t launch_mdot_window(const KArgs& a, int j, int col0, int mode, int L, hipStream_t st) {
-  const int rev = mode == 1 ? kRevPass1 : kRevPass2;
-  switch (L) {
-    case 8: hipLaunchKernelGGL((k_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
-    case 16: hipLaunchKernelGGL((k_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
-    case 32: hipLaunchKernelGGL((k_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
-    default: hipLaunchKernelGGL((k_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, col0, mode, rev); break;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin) {
+  const SegTab* used = nullptr;
   hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     const int ncol = j + 1;
-    if (ncol <= 64) return launch_mdot_window<TV, TW>(a, j, 0, 1, lanes_for(ncol), st);
+    if (ncol <= 64) return launch_mdot_window<TV, TW>(a, j, 0, 1, lanes_for(ncol), st, &used);
     for (int c0 = 0; c0 < ncol; c0 += 64) {
-      hipError_t e2 = launch_mdot_window<TV, TW>(a, j, c0, 1, 64, st);
+      hipError_t e2 = launch_mdot_window<TV, TW>(a, j, c0, 1, 64, st, &used);
       if (e2 != hipSuccess) return e2;
     }
     return hipSuccess;
   });
   if (e != hipSuccess || !with_fin) return e;
-  return launch_finalize(a, FIN_PASS1, j, 0, st);
+  return launch_fin_cols<1>(a, *used, j, st);
+}
+
+template <typename TV, typename TW, int L>
+static hipError_t launch_axpy_mdot_L(const KArgs& a, int j, hipStream_t st, const SegTab** used) {
+  if constexpr (sizeof(TV) == 8) {
+    auto kern = k_axpy_mdot64<TV, TW, L>;
+    const SegTab& sg = split_for(a, kern);
+    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass2);
+    *used = &sg;
+  } else {
+    auto kern = k_axpy_mdot<TV, TW, L>;
+    const SegTab& sg = split_for(a, kern);
+    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass2);
+    *used = &sg;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin) {
+  const SegTab* used = nullptr;
   hipError_t e0 = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     const int ncol = j + 1;
     if (ncol <= 64) {
       switch (lanes_for(ncol)) {
-        case 8: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
-        case 16: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
-        case 32: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
-        default: hipLaunchKernelGGL((k_axpy_mdot<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass2); break;
+        case 8: return launch_axpy_mdot_L<TV, TW, 8>(a, j, st, &used);
+        case 16: return launch_axpy_mdot_L<TV, TW, 16>(a, j, st, &used);
+        case 32: return launch_axpy_mdot_L<TV, TW, 32>(a, j, st, &used);
+        default: return launch_axpy_mdot_L<TV, TW, 64>(a, j, st, &used);
       }
-      return hipGetLastError();
     }
     for (int c0 = 0; c0 < ncol; c0 += 64) {
-      hipLaunchKernelGGL((k_axpy<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, c0);
+      auto kern = k_axpy<TV, TW, 64>;
+      const SegTab& sg = split_for(a, kern);
+      hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, c0);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
     for (int c0 = 0; c0 < ncol; c0 += 64) {
-      hipError_t e = launch_mdot_window<TV, TW>(a, j, c0, 2, 64, st);
+      hipError_t e = launch_mdot_window<TV, TW>(a, j, c0, 2, 64, st, &used);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   });
   if (e0 != hipSuccess || !with_fin) return e0;
-  return launch_finalize(a, FIN_PASS2, j, 0, st);
+  return launch_fin_cols<2>(a, *used, j, st);
 }
 
-hipError_t launch_final_pass(const KArgs& a, int j, int i0, hipStream_t st, bool with_fin) {
-  const bool mgs = a.ortho == 0;
+hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st) {
+  const SegTab* used = nullptr;
+  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    if (j + 1 <= 64) {
+      const int L = lanes_for(j + 1);
+      const void* k = nullptr;
+      if constexpr (sizeof(TV) == 8) {
+        k = L == 8 ? (const void*)k_axpy_mdot64<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64<TV, TW, 16>
+          : L == 32 ? (const void*)k_axpy_mdot64<TV, TW, 32> : (const void*)k_axpy_mdot64<TV, TW, 64>;
+      } else {
+        k = L == 8 ? (const void*)k_axpy_mdot<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot<TV, TW, 16>
+          : L == 32 ? (const void*)k_axpy_mdot<TV, TW, 32> : (const void*)k_axpy_mdot<TV, TW, 64>;
+      }
+      used = &a.seg[occupancy_of(k) - 1];
+    } else {
+      used = &a.seg[occupancy_of((const void*)k_mdot<TV, TW, 64>) - 1];
+    }
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
+  return launch_fin_cols<2>(a, *used, j, st);
+}
+
+hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fin) {
+  const SegTab* used = nullptr;
+  const double* src = a.part;
   hipError_t e0 = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
-    if (mgs) {
-      hipLaunchKernelGGL((k_mgs_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j);
-    } else if (j + 1 <= 64) {
+    if (a.ortho == 0) {  // MGS: complete dot j, then the final axpy
+      auto kern = k_mgs_final<TV, TW>;
+      const SegTab& sg = a.seg[kMgsOcc - 1];
+      hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, sg, j);
+      used = &sg;
+      src = (j & 1) ? a.part : a.part2;
+      return hipGetLastError();
+    }
+    if (j + 1 <= 64) {
+      auto go = [&](auto kern) {
+        const SegTab& sg = split_for(a, kern);
+        hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass3);
+        used = &sg;
+      };
       switch (lanes_for(j + 1)) {
-        case 8: hipLaunchKernelGGL((k_final_tile<TV, TW, 8>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
-        case 16: hipLaunchKernelGGL((k_final_tile<TV, TW, 16>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
-        case 32: hipLaunchKernelGGL((k_final_tile<TV, TW, 32>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
-        default: hipLaunchKernelGGL((k_final_tile<TV, TW, 64>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, kRevPass3); break;
+        case 8: go(k_final_tile<TV, TW, 8>); break;
+        case 16: go(k_final_tile<TV, TW, 16>); break;
+        case 32: go(k_final_tile<TV, TW, 32>); break;
+        default: go(k_final_tile<TV, TW, 64>); break;
       }
     } else {
-      hipLaunchKernelGGL((k_final<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i0);
+      auto kern = k_final<TV, TW>;
+      const SegTab& sg = split_for(a, kern);
+      hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j);
+      used = &sg;
     }
     return hipGetLastError();
   });
   if (e0 != hipSuccess || !with_fin) return e0;
-  const double* src = mgs ? ((j & 1) ? a.part : a.part2) : a.part;
-  hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, src, j);
+  hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, src, used->nseg, used->sys_sg0,
+                     used->sys_nsg, j);
   return hipGetLastError();
 }
 
-hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st, bool with_fin) {
-  (void)with_fin;  // the next MGS launch completes this dot itself
+hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st) {
+  // the next MGS launch completes this dot itself
   return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
-    hipLaunchKernelGGL((k_mgs<TV, TW>), dim3(a.nchunk), dim3(kBlock), 0, st, a, j, i);
+    auto kern = k_mgs<TV, TW>;
+    const SegTab& sg = a.seg[kMgsOcc - 1];
+    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, i);
     return hipGetLastError();
+  });
+}
+
+hipError_t prepare_occupancy(int prec) {
+  return launch_by_prec(prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const void* ks[] = {
+        (const void*)k_mdot<TV, TW, 8>, (const void*)k_mdot<TV, TW, 16>, (const void*)k_mdot<TV, TW, 32>,
+        (const void*)k_mdot<TV, TW, 64>, (const void*)k_axpy_mdot<TV, TW, 8>,
+        (const void*)k_axpy_mdot<TV, TW, 16>, (const void*)k_axpy_mdot<TV, TW, 32>,
+        (const void*)k_axpy_mdot<TV, TW, 64>, (const void*)k_axpy_mdot64<TV, TW, 8>,
+        (const void*)k_axpy_mdot64<TV, TW, 16>, (const void*)k_axpy_mdot64<TV, TW, 32>,
+        (const void*)k_axpy_mdot64<TV, TW, 64>, (const void*)k_axpy<TV, TW, 64>,
+        (const void*)k_final_tile<TV, TW, 8>, (const void*)k_final_tile<TV, TW, 16>,
+        (const void*)k_final_tile<TV, TW, 32>, (const void*)k_final_tile<TV, TW, 64>,
+        (const void*)k_final<TV, TW>, (const void*)k_mgs<TV, TW>, (const void*)k_mgs_final<TV, TW>};
+    for (const void* k : ks) occupancy_of(k);
+    return hipSuccess;
   });
 }
 
@@ -1277,15 +1438,16 @@ hipError_t launch_backsolve(const KArgs& a, hipStream_t st) {
 hipError_t launch_update(const KArgs& a, hipStream_t st) {
   return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
     using TV = decltype(tv);
-    hipLaunchKernelGGL((k_update<TV>), dim3(a.nchunk), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((k_update<TV>), dim3(a.ntile), dim3(kBlock), 0, st, a);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_bnorm(const KArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_bnorm, dim3(a.nchunk), dim3(kBlock), 0, st, a);
-  hipLaunchKernelGGL((k_fin<FIN_BNORM>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, 0);
-  hipLaunchKernelGGL(k_zero_x_if_b_zero, dim3(a.nchunk), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL(k_bnorm, dim3(a.ntile), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_fin<FIN_BNORM>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.ntile, a.sys_t0,
+                     a.sys_nt, 0);
+  hipLaunchKernelGGL(k_zero_x_if_b_zero, dim3(a.ntile), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1333,11 +1495,6 @@ hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const double* v, int64_t n, double* part, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_sumsq, dim3(nblk), dim3(kBlock), 0, st, v, n, part);
-  return hipGetLastError();
-}
-
 hipError_t launch_absmax(const float* w, int64_t n, float* part, int nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_absmax, dim3(nblk), dim3(kBlock), 0, st, w, n, part);
   return hipGetLastError();
@@ -1365,10 +1522,6 @@ hipError_t launch_shift_cols(const int32_t* src, int32_t* dst, int64_t nnz, int3
   const unsigned blocks = (unsigned)std::min<int64_t>((nnz + 255) / 256, 65536);
   if (blocks > 0) hipLaunchKernelGGL(k_shift_i32, dim3(blocks), dim3(256), 0, st, src, dst, nnz, shift);
   return hipGetLastError();
-}
-
-hipError_t launch_shift_rowptr(const int32_t* src, int32_t* dst, int64_t n, int32_t shift, hipStream_t st) {
-  return launch_shift_cols(src, dst, n, shift, st);
 }
 
 hipError_t launch_gather(const double* const* src, double* dst, const int64_t* row0, const int32_t* n,

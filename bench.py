@@ -19,6 +19,7 @@ Also reported, on the same JSON line:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -30,6 +31,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time to 1e-10 rel. residual: mixed/learned vs FP64 GMRES; HBM GB/s"
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the roofline kernel, from two rocprofv3 counter runs
+# of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by what it reads
+# for a plain 1 GiB device copy: x2.0 and x1.0), averaged over the roofline
+# launches.  Valid only for the kernel source they were taken from.
+TRAFFIC = {"bytes_per_launch": 346204006, "kernel_source_sha256": "06cb5d35e01ada360755015aa7968f1beb9fceb7ec9f8a3392699412cca2ca0a"}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
+
+
+def measured_traffic():
+    if TRAFFIC["bytes_per_launch"] is None:
+        return None
+    with open(KERNEL_SOURCE, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["kernel_source_sha256"]:
+            return None  # the kernels changed since the counters were taken
+    return TRAFFIC["bytes_per_launch"]
 
 
 def parse():
@@ -75,7 +92,13 @@ def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps,
 
 
 def roofline(solver, m, reps):
-    """Dominant kernel: fused CGS projection 2 at the 64-column tile (j = 31..m-1)."""
+    """Dominant kernel: fused CGS projection 2 at its 64-column tile (j = 31..m-1).
+
+    For each column j the library launches the kernel once untimed, then
+    `reps` times back to back between two HIP events on the solver's stream;
+    the timed launches sit in a ROCTx range named "timed:k_axpy_mdot(cgs pass
+    2)", which `rocprofv3 --marker-trace --kernel-rename` reports as one row.
+    """
     js = list(range(min(31, m - 1), m))
     t_ms, byts = [], []
     for j in js:
@@ -85,6 +108,7 @@ def roofline(solver, m, reps):
     avg_ms = sum(t_ms) / len(t_ms)
     avg_bytes = sum(byts) / len(byts)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
     # the rest of the step's kernels at the last column, for the report
     other = {}
     for k, name in [(0, "spmv_arnoldi"), (1, "cgs_pass1"), (3, "final_pass"), (5, "residual64"), (6, "update64"),
@@ -98,10 +122,11 @@ def roofline(solver, m, reps):
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_over_alg": (round(traffic / avg_bytes, 4) if traffic else None),
         "avg_launch_ms": round(avg_ms, 5),
         "alg_bytes_per_launch": avg_bytes,
-        "launches": f"j = {js[0]}..{js[-1]}, {reps} reps each",
+        "launches": f"j = {js[0]}..{js[-1]}, {reps} timed back-to-back launches each (after 1 untimed)",
         "other_kernels_at_j_last": other,
     }
 

@@ -20,9 +20,13 @@
  *  - Return value: GMRES_OK (0) or a negative error code (gmres_strerror).
  *    Not converging is not an error: gmres_solve returns GMRES_OK and
  *    reports the outcome in gmres_result.status.
- *  - All device work is enqueued on the handle's stream; calls that return
- *    results to the host synchronise that stream.  A handle must be used by
- *    one host thread at a time.
+ *  - Every handle owns a non-blocking stream of default priority on which
+ *    all its device work runs.  Each call that reads or writes caller memory
+ *    first makes that stream wait for the work already enqueued on the
+ *    caller's stream (the hip_stream given at creation; NULL = the null
+ *    stream), and returns only after its own stream has drained, so caller
+ *    memory may be used on the caller's stream as soon as the call returns.
+ *    A handle must be used by one host thread at a time.
  */
 #ifndef GMRES_H_
 #define GMRES_H_
@@ -102,7 +106,8 @@ void gmres_default_options(gmres_options* opt);
  * mixed modes, shared indices, SpMV row blocks), allocates the workspace
  * (basis of m+1 vectors, H, rotations, reductions) and, if requested, runs
  * the SpMV autotuner.  The caller may free its CSR arrays afterwards.
- * hip_stream: the hipStream_t to use (NULL = the null stream).
+ * hip_stream: the caller's hipStream_t (NULL = the null stream) that the
+ * handle's calls are ordered after; it is not used for the library's work.
  * Errors: EINVAL (n <= 0, nnz < 0, NULL pointers, bad options, bad CSR),
  * ENOMEM, EHIP. */
 int gmres_create(gmres_handle* out, int64_t n, int64_t nnz, const int32_t* row_ptr,
@@ -140,14 +145,15 @@ int gmres_destroy(gmres_handle h);
 
 const char* gmres_strerror(int code);
 
-/* r = b - A x in float64 with the stored A (single-system handles or the
- * concatenation of a batch), and *norm_out = ||r||_2 (host, may be NULL).
- * r may be NULL when only the norm is wanted. */
+/* r = b - A x in float64 with the stored A, and *norm_out = ||r||_2 (host,
+ * may be NULL).  r may be NULL when only the norm is wanted.  b, x, r:
+ * float64[n] device.  Single-system handles only (ESTATE on a batch handle). */
 int gmres_residual(gmres_handle h, const double* b, const double* x, double* r, double* norm_out);
 
 /* y = A x with the stored float64 values (precision = GMRES_FP64, x and y
  * float64) or the stored float32 copy (GMRES_MIXED_FP32, float32 x, y).
- * The mixed copy exists only on mixed-precision handles (else ESTATE). */
+ * The mixed copy exists only on mixed-precision handles (else ESTATE);
+ * single-system handles only (ESTATE on a batch handle). */
 int gmres_spmv(gmres_handle h, int32_t precision, const void* x, void* y);
 
 /* Store v = w * inv_h in a 2-byte format (precision GMRES_MIXED_BF16 or
@@ -182,8 +188,13 @@ int gmres_memory_bytes(gmres_handle h, size_t* bytes);
  * 1 = CGSR projection pass 1, 2 = CGSR projection pass 2, 3 = final
  * update + norm pass, 4 = MGS dot step (column j), 5 = float64 residual,
  * 6 = float64 solution update (j + 1 columns), 7 = the per-system reduction
- * that completes projection pass 2 (kernels 1-5 are timed without their
- * completing reduction, which the solver launches right after them). */
+ * that completes projection pass 2.  Kernels 1-5 are timed without their
+ * completing reduction, which the solver launches right after them.  One
+ * untimed launch precedes the timed ones; the timed launches run back to
+ * back, so caches hold only what the previous launch of the same kernel
+ * left (inside a solve, pass 2 follows pass 1 over the same columns).  The
+ * timed launches sit inside a ROCTx range "timed:<kernel>" when the ROCTx
+ * library can be loaded, for profilers that rename kernels by range. */
 int gmres_time_kernel(gmres_handle h, int32_t kernel, int32_t j, int32_t reps, double* avg_ms,
                       double* bytes);
 

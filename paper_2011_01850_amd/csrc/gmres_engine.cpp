@@ -1,6 +1,7 @@
 // Host engine and C-ABI of libgmres: setup (matrix copies, row blocks,
 // autotuner, workspace), the restart-cycle schedule (direct launches or one
 // captured hipGraph per cycle) and the entry points declared in gmres.h.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +55,8 @@ struct gmres_ctx {
   SysState* st_host = nullptr;  // pinned
   hipGraphExec_t gexec = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipStream_t user = nullptr;    // the caller's stream: work it enqueued comes first
+  hipEvent_t evu = nullptr;
   bool spai_set = false;
   // batch gather/scatter pointer tables (device)
   const double** bptrs = nullptr;
@@ -82,12 +85,41 @@ struct gmres_ctx {
     if (st_host) (void)hipHostFree(st_host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (evu) (void)hipEventDestroy(evu);
     if (stream) (void)hipStreamDestroy(stream);
     magic = 0;
   }
 };
 
 namespace {
+
+// ROCTx ranges around the timed launches of the kernel timing harness, so a
+// profiler that renames kernels by range reports exactly those launches on
+// a row of their own.  Resolved at run time; absent library = no markers.
+struct Roctx {
+  int (*push)(const char*) = nullptr;
+  int (*pop)() = nullptr;
+};
+const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    void* lib = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (lib) {
+      x.push = reinterpret_cast<int (*)(const char*)>(dlsym(lib, "roctxRangePushA"));
+      x.pop = reinterpret_cast<int (*)()>(dlsym(lib, "roctxRangePop"));
+      if (!x.push || !x.pop) x = Roctx{};
+    }
+    return x;
+  }();
+  return r;
+}
+
+// Orders the handle's stream after everything the caller has enqueued on its
+// own stream so far (inputs it produced there are complete before use).
+void after_caller(gmres_ctx* h) {
+  hip_check(hipEventRecord(h->evu, h->user));
+  hip_check(hipStreamWaitEvent(h->stream, h->evu, 0));
+}
 
 bool valid_options(const gmres_options* o) {
   if (!o) return false;
@@ -279,11 +311,13 @@ void autotune_spmv(gmres_ctx* h) {
 
 void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, const int32_t* const* rp,
            const int32_t* const* ci, const double* const* vals, const gmres_options* opt, void* user_stream) {
-  (void)user_stream;
   h->opt = *opt;
+  h->user = (hipStream_t)user_stream;
   hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
   hip_check(hipEventCreate(&h->ev0));
   hip_check(hipEventCreate(&h->ev1));
+  hip_check(hipEventCreateWithFlags(&h->evu, hipEventDisableTiming));
+  after_caller(h);
   const int m = opt->m;
   const int prec = opt->precision;
   h->sys.resize(nsys);
@@ -571,6 +605,7 @@ int gmres_set_preconditioner(gmres_handle hh, const float* spai_vals) {
     gmres_ctx* h = get(hh);
     if (h->opt.precond != GMRES_PRECOND_SPAI) return GMRES_ESTATE;
     if (!spai_vals) return GMRES_EINVAL;
+    after_caller(h);
     hip_check(hipMemcpyAsync((void*)h->a.mval, spai_vals, h->nnz * 4, hipMemcpyDeviceToDevice, h->stream));
     hip_check(hipStreamSynchronize(h->stream));
     h->spai_set = true;
@@ -587,6 +622,7 @@ int gmres_solve(gmres_handle hh, const double* b, double* x, gmres_result* res) 
     if (!b || !x) return GMRES_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = h->sys[0].n;
+    after_caller(h);
     hip_check(hipMemcpyAsync(h->a.b, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
     hip_check(hipMemcpyAsync(h->a.x, x, n * 8, hipMemcpyDeviceToDevice, h->stream));
     run_cycles(h);
@@ -609,6 +645,7 @@ int gmres_batch_solve(gmres_handle hh, const double* const* b, double* const* x,
     for (int k = 0; k < S; ++k)
       if (!b[k] || !x[k]) return GMRES_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
+    after_caller(h);
     if (!h->bptrs) {
       h->bptrs = (const double**)h->alloc<void*>(S);
       h->xptrs = (double**)h->alloc<void*>(S);
@@ -647,6 +684,7 @@ int gmres_residual(gmres_handle hh, const double* b, const double* x, double* r,
     if (h->sys.size() != 1) return GMRES_ESTATE;
     const int64_t n = h->sys[0].n;
     // kernels index padded global rows: stage b and x in padded buffers
+    after_caller(h);
     hip_check(hipMemsetAsync(h->xs, 0, h->ld * 8, h->stream));
     hip_check(hipMemsetAsync(h->ys, 0, h->ld * 8, h->stream));
     hip_check(hipMemcpyAsync(h->ys, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
@@ -676,6 +714,7 @@ int gmres_spmv(gmres_handle hh, int32_t precision, const void* x, void* y) {
     const int64_t n = h->sys[0].n;
     const size_t eb = precision == GMRES_FP64 ? 8 : 4;
     // padded staging so that the kernel's global indexing is valid
+    after_caller(h);
     hip_check(hipMemsetAsync(h->xs, 0, h->ld * 8, h->stream));
     hip_check(hipMemcpyAsync(h->xs, x, n * eb, hipMemcpyDeviceToDevice, h->stream));
     hip_check(launch_spmv_plain(h->a, precision == GMRES_FP64 ? P64 : P32, h->xs, h->ys, h->stream));
@@ -735,6 +774,7 @@ int gmres_last_cycle(gmres_handle hh, int32_t sys, int32_t* k_out, double* Hbar_
     if (V_out) {
       const int64_t n = h->sys[sys].n;
       const int ncols = std::min(S.k + 1, m + 1);
+      after_caller(h);
       for (int c = 0; c < ncols; ++c)
         hip_check(launch_decode_column(h->a, sys, c, V_out + (int64_t)c * n, h->stream));
       hip_check(hipStreamSynchronize(h->stream));
@@ -806,10 +846,19 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
       case 7: bts = (double)h->a.seg[kMaxOcc - 1].nseg * (j + 1) * 8.0; break;
       default: return GMRES_EINVAL;
     }
+    static const char* const kRange[] = {
+        "timed:k_spmv(arnoldi)",        "timed:k_mdot(cgs pass 1)",   "timed:k_axpy_mdot(cgs pass 2)",
+        "timed:k_final_tile(last pass)", "timed:k_mgs(mgs step)",      "timed:k_spmv(residual)",
+        "timed:k_update",               "timed:k_fin_cols(pass 2)"};
     hip_check(launch_set_force(a, 1, h->stream));
     hip_check(run());
     hip_check(hipEventRecord(h->ev0, h->stream));
-    for (int r = 0; r < reps; ++r) hip_check(run());
+    const Roctx& rx = roctx();
+    if (rx.push) rx.push(kRange[kernel]);
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = run();
+    if (rx.pop) rx.pop();
+    hip_check(err);
     hip_check(hipEventRecord(h->ev1, h->stream));
     hip_check(hipEventSynchronize(h->ev1));
     float ms = 0.f;

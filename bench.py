@@ -52,11 +52,15 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "powerlaw", "batch"],
+                    help="convdiff3d: the headline time-to-solution (default); powerlaw: the n = 1e6 "
+                         "power-law system in every precision mode; batch: 512 uneven 2-D systems in one handle")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid side (128 is the benchmark workload)")
     ap.add_argument("--ortho", default="cgsr", choices=["cgsr", "mgs"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16"],
+                    help="mixed mode timed as `value` (default fp32; bf16 for powerlaw)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=10)
@@ -161,21 +165,14 @@ def cpu_baseline(pr, m, ortho, iters_ref, sample_iters):
     }
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU row partitioning is a design note only)", file=sys.stderr)
-        sys.exit(2)
+def bench_convdiff3d(args):
     import numpy as np
     import torch
 
     import problems as P
     from paper_2011_01850_amd import Solver
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
+    args.precision = args.precision or "fp32"
     m = 50
     log(f"generating 3-D convection-diffusion N={args.N} ...")
     pr = P.c2_convdiff3d(args.N)
@@ -237,6 +234,177 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, iters_ref, args.cpu_iters)
     else:
         rec["cpu_baseline"] = None
+    return rec
+
+
+def _mode_summary(times, infos, fwd, mem):
+    return {"seconds_mean": statistics.mean(times), "seconds_median": statistics.median(times),
+            "seconds_min": min(times), "seconds_max": max(times),
+            "solve_seconds": infos[-1]["seconds"], "setup_seconds": infos[-1]["setup_seconds"],
+            "iters": infos[-1]["iters"], "restarts": infos[-1]["restarts"], "status": infos[-1]["status"],
+            "rel_residual": infos[-1]["rel_residual"], "forward_error": fwd, "memory_bytes": mem}
+
+
+def bench_powerlaw(args):
+    """n = 1e6 power-law system, GMRES(30) CGSR, every precision mode."""
+    import numpy as np
+    import torch
+
+    import problems as P
+    from paper_2011_01850_amd import Solver
+
+    value_mode = args.precision or "bf16"
+    m = 30
+    log("generating the power-law system n = 1e6 ...")
+    pr = P.c3_powerlaw()
+    A = pr.A
+    A_dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
+    b_dev = torch.as_tensor(pr.b, device="cuda")
+    torch.cuda.synchronize()
+    log(f"n = {A.n:,}, nnz = {A.nnz:,}; CGSR GMRES({m})")
+    modes, kern = {}, {}
+    for mode in ["fp64", "fp32", "bf16", "fp16"]:
+        t, inf, (s, x) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, mode,
+                                          args.steps, args.warmup)
+        xs = x.cpu().numpy()
+        fwd = float(np.linalg.norm(xs - pr.x_true) / np.linalg.norm(pr.x_true))
+        modes[mode] = _mode_summary(t, inf, fwd, s.memory_bytes())
+        ks = {}
+        for k, name in [(0, "spmv_arnoldi"), (1, "cgs_pass1"), (2, "cgs_pass2"), (3, "final_pass")]:
+            ms, by = s.time_kernel(k, m - 1, args.roofline_reps)
+            ks[name] = {"ms": round(ms, 5), "alg_bytes": by, "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
+        kern[mode] = ks
+        s.close()
+    for mode in modes:
+        modes[mode]["speedup_vs_fp64"] = round(modes["fp64"]["seconds_mean"] / modes[mode]["seconds_mean"], 3)
+    v = modes[value_mode]["seconds_mean"]
+    sp = kern[value_mode]["spmv_arnoldi"]
+    rec = {
+        "metric": METRIC, "value": round(v, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(v * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"{value_mode}+f32+f64" if value_mode != "fp32" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"power-law random sparse n={A.n}, nnz={A.nnz} (row lengths alpha=2.1, mean 20, "
+                               f"max 2000, a_ii = 1.2 sum|a_ij|), GMRES({m}) {args.ortho.upper()}, {value_mode} "
+                               f"basis, fp32 arithmetic, fp64 residual/update, tol 1e-10, time incl. setup",
+                   "n": A.n, "nnz": A.nnz, "m": m, "ortho": args.ortho, "precision": value_mode},
+        "modes": modes,
+        "kernels_at_j_last": kern,
+        "roofline": {"bound": "hbm", "kernel": f"k_spmv (Arnoldi SpMV, float32 A, {value_mode} x)",
+                     "achieved": sp["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(sp["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None,
+                     "avg_launch_ms": sp["ms"], "alg_bytes_per_launch": sp["alg_bytes"]},
+    }
+    if not args.no_cpu:
+        log("CPU oracle sample ...")
+        rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, modes["fp64"]["iters"], args.cpu_iters)
+    else:
+        rec["cpu_baseline"] = None
+    return rec
+
+
+def batch_alg_bytes(n, nnz, iters, restarts, m):
+    """Bytes one system's MGS solve must move with w held on chip (float32 A,
+    basis and w; float64 residual and update), given its iteration count."""
+    total, left = 0.0, iters
+    cycles = max(1, restarts)
+    for c in range(cycles):
+        k = min(m, left) if c < cycles - 1 else left
+        left -= k
+        total += 12.0 * nnz + 4.0 * (n + 1) + 20.0 * n            # float64 residual, v1
+        for j in range(k):
+            total += 8.0 * nnz + 4.0 * (n + 1) + 8.0 * n          # SpMV
+            total += (j + 1) * 4.0 * n + 12.0 * n                 # MGS with w on chip, v_{j+1} written
+        total += k * 4.0 * n + 16.0 * n                           # float64 update
+    return total
+
+
+def bench_batch(args):
+    """512 uneven 2-D convection-diffusion systems, GMRES(40) MGS, one handle."""
+    import numpy as np
+    import torch
+
+    import problems as P
+    from paper_2011_01850_amd import BatchSolver
+
+    m = 40
+    mode = args.precision or "fp32"
+    log("generating 512 2-D convection-diffusion systems ...")
+    probs = P.c4_batch()
+    systems = [tuple(torch.as_tensor(v, device="cuda") for v in (p.A.row_ptr, p.A.col_idx, p.A.vals))
+               for p in probs]
+    bs = [torch.as_tensor(p.b, device="cuda") for p in probs]
+    ns = [p.A.n for p in probs]
+    nnzs = [p.A.nnz for p in probs]
+    torch.cuda.synchronize()
+    log(f"{len(probs)} systems, sum n = {sum(ns):,}, sum nnz = {sum(nnzs):,}; MGS GMRES({m}) {mode}")
+
+    def run(prec, steps, warmup):
+        times, last = [], None
+        for it in range(warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bsol = BatchSolver(systems, m=m, tol=1e-10, ortho="mgs", precision=prec, max_iters=100_000)
+            xs, infos = bsol.solve(bs)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            bsol.close()
+            if it >= warmup:
+                times.append(dt)
+            iters = [i["iters"] for i in infos]
+            log(f"  {prec} {'warm' if it < warmup else 'step'} {it}: {dt * 1e3:.1f} ms, iterations "
+                f"min {min(iters)} median {int(np.median(iters))} max {max(iters)}, "
+                f"converged {sum(i['status'] == 'CONVERGED' for i in infos)}/{len(infos)}")
+            last = (xs, infos)
+        return times, last
+
+    t_mix, (xs, infos) = run(mode, args.steps, args.warmup)
+    fwd = [float(np.linalg.norm(x.cpu().numpy() - p.x_true) / np.linalg.norm(p.x_true)) for x, p in zip(xs, probs)]
+    alg = sum(batch_alg_bytes(n, z, i["iters"], i["restarts"], m) for n, z, i in zip(ns, nnzs, infos))
+    v = statistics.mean(t_mix)
+    out64 = None
+    if not args.no_fp64:
+        t64, (_, inf64) = run("fp64", 1, 0)
+        out64 = {"seconds": t64[0], "iters_total": sum(i["iters"] for i in inf64),
+                 "converged": sum(i["status"] == "CONVERGED" for i in inf64)}
+    iters = [i["iters"] for i in infos]
+    rec = {
+        "metric": "batch throughput: systems solved to 1e-10 rel. residual per second", "value": round(len(probs) / v, 3),
+        "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(v * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if mode == "fp32" else f"{mode}+f32+f64", "data": "synthetic",
+        "config": {"workload": f"{len(probs)} 2-D convection-diffusion systems, sides U{{32..256}}, beta ~ U[0,100]^2, "
+                               f"sum n={sum(ns)}, sum nnz={sum(nnzs)}, GMRES({m}) MGS, {mode} Arnoldi + fp64 "
+                               f"residual/update, tol 1e-10, one handle (create + solve timed)",
+                   "systems": len(probs), "sum_n": sum(ns), "sum_nnz": sum(nnzs), "m": m, "precision": mode},
+        "seconds": {"mean": v, "median": statistics.median(t_mix), "min": min(t_mix), "max": max(t_mix)},
+        "iterations": {"min": min(iters), "median": float(np.median(iters)), "max": max(iters), "total": sum(iters)},
+        "converged": sum(i["status"] == "CONVERGED" for i in infos),
+        "max_rel_residual": max(i["rel_residual"] for i in infos),
+        "max_forward_error": max(fwd),
+        "effective_GBps": round(alg / v / 1e9, 1),
+        "alg_bytes": alg,
+        "fp64": out64,
+        "roofline": {"bound": "hbm", "kernel": "whole batch solve (algorithmic bytes, MGS with w on chip)",
+                     "achieved": round(alg / v / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(alg / v / 1e9 / PEAK_HBM_GBS, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    return rec
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU row partitioning is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    rec = {"convdiff3d": bench_convdiff3d, "powerlaw": bench_powerlaw, "batch": bench_batch}[args.workload](args)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -133,7 +133,7 @@ def forward(theta: torch.Tensor, G: Graph, return_states=False):
         u = torch.cat([h[G.rows], h[G.cols], e], dim=1)
         m = relu(u @ P[f"W{l}"].T + P[f"b{l}"])
         agg = torch.zeros_like(h).index_add(0, G.rows, m)
-        h = h + agg / G.deg[:, None]
+        h = h + agg / torch.clamp(G.deg, min=1.0)[:, None]  # a row without entries gets no message
         e = m
         states.append((h, e))
     u = torch.cat([h[G.rows], h[G.cols], e], dim=1)

@@ -76,7 +76,18 @@ _SIGS = {
     "gmres_memory_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "gmres_time_kernel": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
+    "gmres_spai_infer": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "spai_create": (C.c_int, [C.POINTER(_vp), C.c_int64, C.c_int64, _vp, _vp, C.c_int32, _vp]),
+    "spai_set_values": (C.c_int, [_vp, _vp]),
+    "spai_forward": (C.c_int, [_vp, _vp, _vp]),
+    "spai_loss": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.POINTER(C.c_double), _vp]),
+    "spai_backward": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32]),
+    "spai_destroy": (C.c_int, [_vp]),
+    "spai_adam_step": (C.c_int, [C.c_int64, _vp, _vp, _vp, C.c_float, _vp, _vp, C.c_float, C.c_float, C.c_float,
+                                 C.c_float, C.c_int32, _vp]),
 }
+
+SPAI_NPARAMS, SPAI_HIDDEN = 9665, 32
 
 _LIB = None
 

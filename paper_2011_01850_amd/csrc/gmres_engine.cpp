@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "gmres.h"
+#include "spai.h"
 #include "gmres_internal.hpp"
 
 using namespace gm;
@@ -58,6 +59,7 @@ struct gmres_ctx {
   hipStream_t user = nullptr;    // the caller's stream: work it enqueued comes first
   hipEvent_t evu = nullptr;
   bool spai_set = false;
+  spai_handle spai = nullptr;    // network instance on this handle's pattern (gmres_spai_infer)
   // batch gather/scatter pointer tables (device)
   const double** bptrs = nullptr;
   double** xptrs = nullptr;
@@ -80,6 +82,7 @@ struct gmres_ctx {
   }
 
   ~gmres_ctx() {
+    if (spai) (void)spai_destroy(spai);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
@@ -611,6 +614,33 @@ int gmres_set_preconditioner(gmres_handle hh, const float* spai_vals) {
     h->spai_set = true;
     return GMRES_OK;
   } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int gmres_spai_infer(gmres_handle hh, const void* params, size_t param_bytes, float* m_out) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (h->opt.precond != GMRES_PRECOND_SPAI || h->sys.size() != 1) return GMRES_ESTATE;
+    if (!params || param_bytes != (size_t)SPAI_NPARAMS * 2) return GMRES_EINVAL;
+    after_caller(h);
+    // the handle's stream is the network's caller stream: the network waits
+    // for this handle's work and vice versa (every spai call drains its stream)
+    if (!h->spai) {
+      const int rc = spai_create(&h->spai, h->sys[0].n, h->nnz, h->a.rp, h->a.ci, 1, h->stream);
+      if (rc != GMRES_OK) return rc;
+    }
+    int rc = spai_set_values(h->spai, h->a.a64);
+    if (rc == GMRES_OK) rc = spai_forward(h->spai, (const uint16_t*)params, (float*)h->a.mval);
+    if (rc != GMRES_OK) return rc;
+    if (m_out) {
+      hip_check(hipMemcpyAsync(m_out, h->a.mval, h->nnz * 4, hipMemcpyDeviceToDevice, h->stream));
+      hip_check(hipStreamSynchronize(h->stream));
+    }
+    h->spai_set = true;
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
     return f.code;
   }
 }

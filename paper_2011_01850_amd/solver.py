@@ -108,6 +108,17 @@ class Solver:
         torch.cuda.synchronize()
         L.check(self.lib.gmres_set_preconditioner(self.h, v.data_ptr()), "gmres_set_preconditioner")
 
+    def spai_infer(self, params_bf16):
+        """Run the learned network on this solver's matrix and install M; returns M (float32 tensor)."""
+        torch = self._torch
+        pb = _dev(params_bf16, torch.int16, torch)
+        if pb.numel() != L.SPAI_NPARAMS:
+            raise ValueError(f"expected {L.SPAI_NPARAMS} bfloat16 parameters")
+        out = torch.empty(self.nnz, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_spai_infer(self.h, pb.data_ptr(), pb.numel() * 2, out.data_ptr()), "gmres_spai_infer")
+        return out
+
     def residual(self, b, x):
         """(r, ||r||) with r = b - A x in float64 on the GPU."""
         torch = self._torch

@@ -9,13 +9,16 @@ import pytest
 from paper_2011_01850_amd import _lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gmres.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("gmres.h", "spai.h")]
 
 
 def _declared():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gmres_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for hdr in HEADERS:
+        src = open(hdr).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b((?:gmres|spai)_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -25,7 +28,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) >= 14
+    assert len(names) >= 22
     for n in names:
         assert hasattr(lib, n), n
     # and the binding declares every one of them
@@ -84,3 +87,25 @@ def test_struct_layouts_match_header():
     assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
+
+
+def test_spai_arguments_rejected_before_device_work(lib):
+    h = C.c_void_p()
+    assert lib.spai_create(None, 10, 5, 1, 1, 4, None) == L.EINVAL
+    assert lib.spai_create(C.byref(h), 0, 5, 1, 1, 4, None) == L.EINVAL
+    assert lib.spai_create(C.byref(h), 10, 0, 1, 1, 4, None) == L.EINVAL
+    assert lib.spai_create(C.byref(h), 10, 5, None, 1, 4, None) == L.EINVAL
+    assert lib.spai_create(C.byref(h), 10, 5, 1, 1, 0, None) == L.EINVAL
+    assert lib.spai_create(C.byref(h), 10, 5, 1, 1, 65, None) == L.EINVAL
+    assert lib.spai_destroy(None) == L.OK
+    assert lib.spai_adam_step(0, 1, 1, 1, 1.0, 1, 1, 1e-3, 0.9, 0.999, 1e-8, 1, None) == L.EINVAL
+    assert lib.spai_adam_step(10, 1, 1, 1, 1.0, 1, 1, 1e-3, 1.0, 0.999, 1e-8, 1, None) == L.EINVAL
+    assert lib.spai_adam_step(10, 1, 1, 1, 1.0, 1, 1, 1e-3, 0.9, 0.999, 1e-8, 0, None) == L.EINVAL
+    assert lib.gmres_spai_infer(None, 1, 2 * L.SPAI_NPARAMS, None) == L.EHANDLE
+
+
+def test_spai_layout_matches_oracle():
+    from oracle import mpnn as N
+    from paper_2011_01850_amd import spai as S
+    assert S.NPARAMS == N.NPARAMS == L.SPAI_NPARAMS
+    assert S.offsets() == N.OFFSETS

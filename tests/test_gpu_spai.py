@@ -1,0 +1,247 @@
+"""Parity of the learned sparse approximate inverse (HIP, through the C-ABI)
+against the CPU oracle (oracle/mpnn.py), and what training gains.
+
+Tolerances: the message layers run on bfloat16 matrix cores with float32
+accumulation; activations enter as hi + lo bfloat16 pairs (about 2^-17
+relative each) against weights that are exact in bfloat16, and the oracle
+runs in float64 on the same bfloat16-rounded parameters.  The weight
+gradients are sums over all edges with strong cancellation (a CPU emulation
+showed a 20-30x amplification of operand rounding), so the bar is a
+relative L2 error <= 1e-3 per tensor (cosine >= 0.99999) for the learned
+part of M and for every parameter tensor.  The loss and dL/dM are float32
+sparse products (relative error ~1e-6), checked to 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import problems as P
+from oracle import gmres as O
+from oracle import mpnn as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2011_01850_amd import spai  # noqa: F401
+    return spai
+
+
+def random_nonsym(n=300, seed=3):
+    """Random sparse non-symmetric matrix with one-sided entries (some
+    transposed entries missing), rows of uneven length, positive diagonal."""
+    g = np.random.default_rng(seed)
+    D = np.zeros((n, n))
+    for i in range(n):
+        k = int(g.integers(1, 9))
+        for j in g.choice(n, size=k, replace=False):
+            if j != i:
+                D[i, j] = g.normal()
+        D[i, i] = 1.3 * np.abs(D[i]).sum() + 0.1
+    return P.dense_to_csr(D)
+
+
+MATS = {
+    "convdiff2d_20": lambda: P.convdiff(20, (20.0, 10.0)),
+    "varcoef3d_10": lambda: P.varcoef3d(10, index=7),
+    "random_300": lambda: random_nonsym(),
+}
+
+
+def theta_for(seed):
+    g = np.random.default_rng(seed)
+    th = N.init_params(seed)
+    o, _ = N.OFFSETS["wo"]
+    th[o:o + N.U] = g.normal(0, 0.05, N.U)
+    th[N.OFFSETS["bo"][0]] = 0.01
+    for name in ("bn", "be", "b1", "b2", "b3"):
+        o, shape = N.OFFSETS[name]
+        th[o:o + shape[0]] = g.normal(0, 0.1, shape[0])
+    return th
+
+
+def cos_rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    cos = float(a @ b / (np.linalg.norm(a) * nb)) if nb > 0 else 1.0
+    rel = float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    return cos, rel
+
+
+def net_for(lib, A, kmax=4):
+    net = lib.SpaiNet(A.row_ptr, A.col_idx, kmax=kmax)
+    net.set_values(A.vals)
+    return net
+
+
+def jacobi_part(A, G):
+    diag = (G.rows == G.cols).numpy()
+    return np.where(diag, G.sigma.numpy()[G.rows.numpy()] / np.sqrt(G.d.numpy()[G.rows.numpy()] ** 2), 0.0)
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_forward_matches_oracle(lib, name):
+    A = MATS[name]()
+    G = N.graph(A.n, A.row_ptr, A.col_idx, A.vals)
+    th = theta_for(1)
+    pb = lib.params_to_bf16(th)
+    M_or = N.forward(torch.as_tensor(N.round_bf16(th)), G).numpy()
+    net = net_for(lib, A)
+    M_gpu = net.forward(torch.as_tensor(pb).cuda()).cpu().numpy().astype(np.float64)
+    J = jacobi_part(A, G)
+    cos, rel = cos_rel(M_gpu - J, M_or - J)
+    print(f"{name}: learned part cos {cos:.6f} rel {rel:.3e}")
+    assert cos >= 0.99999 and rel <= 1e-3
+    assert np.all(np.isfinite(M_gpu))
+
+
+def test_zero_decoder_is_jacobi(lib):
+    A = MATS["varcoef3d_10"]()
+    net = net_for(lib, A)
+    pb = lib.params_to_bf16(N.init_params(4))
+    M = net.forward(torch.as_tensor(pb).cuda()).cpu().numpy().astype(np.float64)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    diag = rows == A.col_idx
+    np.testing.assert_allclose(M[diag], 1.0 / A.vals[diag], rtol=4e-7)
+    assert np.all(M[~diag] == 0.0)
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_loss_and_dM_match_oracle(lib, name):
+    A = MATS[name]()
+    G = N.graph(A.n, A.row_ptr, A.col_idx, A.vals)
+    th = theta_for(2)
+    Mv = N.forward(torch.as_tensor(N.round_bf16(th)), G).numpy().astype(np.float32)
+    Z = np.random.default_rng(5).normal(size=(3, A.n)).astype(np.float32)
+    net = net_for(lib, A)
+    Lg, dm = net.loss(torch.as_tensor(Mv).cuda(), torch.as_tensor(Z).cuda())
+    Lo = float(N.loss(torch.as_tensor(Mv.astype(np.float64)), G, torch.as_tensor(A.vals),
+                      torch.as_tensor(Z.T.astype(np.float64))))
+    dmo = N.loss_grad_M(torch.as_tensor(Mv.astype(np.float64)), G, torch.as_tensor(A.vals),
+                        torch.as_tensor(Z.T.astype(np.float64))).numpy()
+    assert Lg == pytest.approx(Lo, rel=1e-4)
+    cos, rel = cos_rel(dm.cpu().numpy(), dmo)
+    assert rel <= 1e-4, rel
+
+
+def test_zero_residual_is_rejected(lib):
+    A = MATS["convdiff2d_20"]()
+    net = net_for(lib, A)
+    M = net.forward(torch.as_tensor(lib.params_to_bf16(N.init_params(0))).cuda())
+    Z = torch.zeros((2, A.n), dtype=torch.float32, device="cuda")
+    Z[0, 3] = 1.0
+    from paper_2011_01850_amd import GmresError
+    with pytest.raises(GmresError):
+        net.loss(M, Z)
+
+
+BLOCKS = ["Wn", "bn", "We", "be", "W1", "b1", "W2", "b2", "W3", "b3", "wo", "bo"]
+
+
+@pytest.mark.parametrize("name", list(MATS))
+def test_backward_matches_oracle(lib, name):
+    """Parameter gradient for a given dL/dM, per parameter tensor."""
+    A = MATS[name]()
+    G = N.graph(A.n, A.row_ptr, A.col_idx, A.vals)
+    th = theta_for(3)
+    thr = N.round_bf16(th)
+    dM = np.random.default_rng(8).normal(size=A.nnz) * 1e-2
+    go = N.backprop_from_M(thr, G, dM)
+    net = net_for(lib, A)
+    pb = torch.as_tensor(lib.params_to_bf16(th)).cuda()
+    net.forward(pb)
+    gg = net.backward(pb, torch.as_tensor(dM.astype(np.float32)).cuda()).cpu().numpy()
+    worst = []
+    for blk in BLOCKS:
+        o, shape = N.OFFSETS[blk]
+        sz = int(np.prod(shape))
+        cos, rel = cos_rel(gg[o:o + sz], go[o:o + sz])
+        worst.append((blk, cos, rel))
+        assert cos >= 0.99999 and rel <= 1e-3, (blk, cos, rel)
+    print(name, " ".join(f"{b}:{c:.5f}/{r:.1e}" for b, c, r in worst))
+
+
+def test_end_to_end_gradient_and_determinism(lib):
+    A = MATS["varcoef3d_10"]()
+    G = N.graph(A.n, A.row_ptr, A.col_idx, A.vals)
+    th = theta_for(6)
+    Z = np.random.default_rng(2).normal(size=(4, A.n)).astype(np.float32)
+    Lo, go, _ = N.value_and_grad(N.round_bf16(th), G, A.vals, Z.T.astype(np.float64))
+    net = net_for(lib, A)
+    pb = torch.as_tensor(lib.params_to_bf16(th)).cuda()
+    grads = []
+    for _ in range(2):
+        M = net.forward(pb)
+        Lg, dm = net.loss(M, torch.as_tensor(Z).cuda())
+        grads.append(net.backward(pb, dm).cpu().numpy())
+    assert np.array_equal(grads[0], grads[1])
+    assert Lg == pytest.approx(Lo, rel=1e-4)
+    cos, rel = cos_rel(grads[0], go)
+    assert cos >= 0.99999 and rel <= 1e-3, (cos, rel)
+    # accumulate = sum of two
+    M = net.forward(pb)
+    _, dm = net.loss(M, torch.as_tensor(Z).cuda())
+    g = net.backward(pb, dm)
+    net.backward(pb, dm, grad=g, accumulate=True)
+    np.testing.assert_allclose(g.cpu().numpy(), 2 * grads[0], rtol=1e-6, atol=1e-12)
+
+
+def test_adam_step_matches_formula(lib):
+    g0 = np.random.default_rng(0)
+    theta = g0.normal(size=N.NPARAMS).astype(np.float32)
+    opt = lib.Adam(theta, lr=1e-2)
+    m1 = np.zeros(N.NPARAMS)
+    m2 = np.zeros(N.NPARAMS)
+    th = theta.astype(np.float64)
+    for t in range(1, 4):
+        grad = g0.normal(size=N.NPARAMS).astype(np.float32)
+        opt.step(torch.as_tensor(grad).cuda(), scale=0.5)
+        g = 0.5 * grad.astype(np.float64)
+        m1 = 0.9 * m1 + 0.1 * g
+        m2 = 0.999 * m2 + 0.001 * g * g
+        th = th - 1e-2 * (m1 / (1 - 0.9 ** t)) / (np.sqrt(m2 / (1 - 0.999 ** t)) + 1e-8)
+    np.testing.assert_allclose(opt.theta.cpu().numpy(), th, rtol=1e-5, atol=1e-6)
+    np.testing.assert_array_equal(opt.params.cpu().numpy(), lib.params_to_bf16(opt.theta.cpu().numpy()))
+
+
+def test_infer_installs_jacobi_for_zero_decoder(lib):
+    """gmres_spai_infer with a zero decoder gives Jacobi-preconditioned FGMRES."""
+    from paper_2011_01850_amd import Solver
+    pr = P.c5_varcoef(2000, N=12)
+    A = pr.A
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=30, tol=1e-10, ortho="cgsr", precision="fp32", precond="spai",
+               autotune=False)
+    M = s.spai_infer(torch.as_tensor(lib.params_to_bf16(N.init_params(0))).cuda())
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    diag = rows == A.col_idx
+    np.testing.assert_allclose(M.cpu().numpy()[diag], 1.0 / A.vals[diag], rtol=4e-7)
+    x, info = s.solve(pr.b)
+    sj = Solver(A.row_ptr, A.col_idx, A.vals, m=30, tol=1e-10, ortho="cgsr", precision="fp32", precond="jacobi",
+                autotune=False)
+    xj, ij = sj.solve(pr.b)
+    assert info["status"] == "CONVERGED" and ij["status"] == "CONVERGED"
+    assert abs(info["iters"] - ij["iters"]) <= 30
+    res = O.relative_residual(O.Matrix.from_csr(A), pr.b, x.cpu().numpy())
+    assert res <= 1e-10 * 1.01
+
+
+def test_training_gains_over_no_preconditioner(lib):
+    """A short GPU training run on residuals the solver produces lowers the
+    loss below its Jacobi start, and FGMRES with the trained network needs
+    far fewer iterations than plain GMRES on held-out instances; the
+    iterations with Jacobi are reported beside it."""
+    from paper_2011_01850_amd.train import collect_pairs, evaluate, train
+    Nside = 12
+    train_ids = list(range(6))
+    test_ids = [2000, 2001]
+    res = train(train_ids, N=Nside, steps=60, lr=3e-3, seed=0, pairs_per_instance=4, log=print)
+    assert res["loss_last"] < 0.9 * res["loss_first"], res
+    ev = evaluate(res["params"], test_ids, N=Nside)
+    for r in ev:
+        print(r)
+        assert r["learned"]["status"] == "CONVERGED"
+        assert r["learned"]["iters"] < 0.5 * r["none"]["iters"]

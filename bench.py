@@ -52,9 +52,17 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "powerlaw", "batch"],
+    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "powerlaw", "batch", "learned"],
                     help="convdiff3d: the headline time-to-solution (default); powerlaw: the n = 1e6 "
-                         "power-law system in every precision mode; batch: 512 uneven 2-D systems in one handle")
+                         "power-law system in every precision mode; batch: 512 uneven 2-D systems in one handle; "
+                         "learned: train the sparse-approximate-inverse network on the GPU, then FGMRES on "
+                         "held-out variable-coefficient systems")
+    ap.add_argument("--train-instances", type=int, default=2000)
+    ap.add_argument("--test-instances", type=int, default=200)
+    ap.add_argument("--baseline-instances", type=int, default=20,
+                    help="held-out instances also solved without preconditioner (float32 and float64)")
+    ap.add_argument("--epochs", type=float, default=2.0)
+    ap.add_argument("--learned-N", type=int, default=64)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--N", type=int, default=128, help="grid side (128 is the benchmark workload)")
@@ -393,18 +401,117 @@ def bench_batch(args):
     return rec
 
 
+def _gen_varcoef(job):
+    """Values and right-hand side of one variable-coefficient instance (host worker)."""
+    i, N = job
+    import problems as P
+
+    pr = P.c5_varcoef(i, N=N)
+    return pr.A.vals, pr.b
+
+
+def _varcoef_stream(ids, N, pool):
+    """(A, b) in order of ids, generated by the worker pool; the pattern is shared."""
+    from types import SimpleNamespace
+
+    import problems as P
+
+    pat = P.varcoef3d(N, 5, ids[0])
+    for vals, b in pool.imap(_gen_varcoef, [(i, N) for i in ids], chunksize=4):
+        yield SimpleNamespace(n=pat.n, nnz=pat.nnz, row_ptr=pat.row_ptr, col_idx=pat.col_idx, vals=vals), b
+
+
+def bench_learned(args, pool):
+    """Train the SPAI network on GPU-generated residual pairs, then time FGMRES(30) to 1e-10 on held-out
+    instances: learned vs Jacobi (float32 Arnoldi), and plain float32 / float64 GMRES on a subset."""
+    import numpy as np
+    import torch
+
+    from paper_2011_01850_amd import train as T
+
+    N = args.learned_N
+    m = 30
+    train_ids = list(range(args.train_instances))
+    test_ids = list(range(2000, 2000 + args.test_instances))
+    log(f"training data: {len(train_ids)} instances of the 3-D variable-coefficient family, N = {N} ...")
+    data = T.prepare(_varcoef_stream(train_ids, N, pool), K=4, m=m, log=log)
+    log(f"  data ready in {data.seconds:.1f} s; training {args.epochs} epochs")
+    res = T.train_on(data, epochs=args.epochs, lr=1e-3, batch=4, seed=0, log=log)
+    del data
+    torch.cuda.empty_cache()
+    log(f"  loss {res['loss_first']:.4f} (Jacobi start) -> {res['loss_last']:.4f} in {res['seconds_train']:.1f} s")
+    rows = []
+    nb = min(args.baseline_instances, len(test_ids))
+    for q, (A, b) in enumerate(_varcoef_stream(test_ids, N, pool)):
+        dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
+        bt = torch.as_tensor(b, device="cuda")
+        kinds = ["jacobi", "learned"] + (["none", "fp64"] if q < nb else [])
+        row = {"instance": test_ids[q]}
+        for kind in kinds:
+            _, row[kind] = T.solve_once(dev, bt, kind, params=res["params"], m=m)
+        rows.append(row)
+        if (q + 1) % 50 == 0:
+            log(f"  evaluated {q + 1} held-out instances")
+
+    def summary(kind, subset):
+        rs = [r[kind] for r in subset if kind in r]
+        return {"instances": len(rs), "seconds_mean": float(np.mean([r["seconds_total"] for r in rs])),
+                "iters_mean": float(np.mean([r["iters"] for r in rs])),
+                "iters_median": float(np.median([r["iters"] for r in rs])),
+                "converged": sum(r["status"] == "CONVERGED" for r in rs),
+                "fallback_used": sum(bool(r["fallback_used"]) for r in rs),
+                "max_rel_residual": float(max(r["rel_residual"] for r in rs))}
+
+    kinds_all = {k: summary(k, rows) for k in ("jacobi", "learned")}
+    kinds_sub = {k: summary(k, rows[:nb]) for k in ("fp64", "none", "jacobi", "learned")}
+    v = kinds_all["learned"]["seconds_mean"]
+    n_a = N ** 3
+    rec = {
+        "metric": METRIC, "value": round(v, 6), "unit": "s", "n_gpus": 1, "steps": len(rows), "warmup": 0,
+        "ms_per_step": round(v * 1e3, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-mfma-net+f32+f64", "data": "synthetic",
+        "config": {"workload": f"3-D variable-coefficient diffusion-convection {N}^3 (n={n_a}), kappa = exp(1.5 GRF), "
+                               f"beta=(30,0,0); learned SPAI (3-layer MPNN, width 32) trained on {len(train_ids)} "
+                               f"instances, FGMRES({m}) CGSR float32 Arnoldi + fp64 residual/update, tol 1e-10, "
+                               f"time per held-out instance incl. setup and inference",
+                   "N": N, "m": m, "train_instances": len(train_ids), "test_instances": len(test_ids)},
+        "held_out_all": kinds_all,
+        "held_out_baseline_subset": kinds_sub,
+        "speedup_learned_vs_fp64": round(kinds_sub["fp64"]["seconds_mean"] / kinds_sub["learned"]["seconds_mean"], 3),
+        "speedup_learned_vs_jacobi": round(kinds_all["jacobi"]["seconds_mean"] / v, 3),
+        "iteration_gain_vs_none": round(kinds_sub["none"]["iters_mean"] / kinds_sub["learned"]["iters_mean"], 3),
+        "training": {k: res[k] for k in ("loss_first", "loss_last", "seconds_data", "seconds_train", "steps",
+                                         "batch", "instances", "seconds_per_instance_step")},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU row partitioning is a design note only)", file=sys.stderr)
         sys.exit(2)
+    pool = None
+    if args.workload == "learned":
+        # host workers for the instance generator, started before the GPU is touched
+        import multiprocessing as mp
+
+        workers = max(1, min(16, len(os.sched_getaffinity(0)) - 1))
+        pool = mp.get_context("spawn").Pool(workers)
     import torch
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    rec = {"convdiff3d": bench_convdiff3d, "powerlaw": bench_powerlaw, "batch": bench_batch}[args.workload](args)
+    if pool is not None:
+        with pool:
+            rec = bench_learned(args, pool)
+    else:
+        rec = {"convdiff3d": bench_convdiff3d, "powerlaw": bench_powerlaw,
+               "batch": bench_batch}[args.workload](args)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

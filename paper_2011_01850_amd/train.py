@@ -5,11 +5,14 @@ training matrix, the restart residuals z_k = b - A x_k of a few cycles of
 unpreconditioned mixed-precision GMRES(m) (x_0 = 0, so z_0 = b).  The loss
 is L = mean_k ||A M z_k - z_k||^2 / ||z_k||^2 (spai.h); forward, loss,
 backward and the Adam update all run in the HIP library.  The network
-starts as Jacobi (zero decoder).
+starts as Jacobi (zero decoder).  Matrices of one family share a sparsity
+pattern, so one network instance serves them all and only the values
+change between steps.
 """
 from __future__ import annotations
 
 import time
+from dataclasses import dataclass, field
 
 import numpy as np
 
@@ -17,13 +20,13 @@ from . import spai as S
 from .solver import Solver, _torch
 
 
-def collect_pairs(A, b, K=4, m=30):
-    """K restart residuals (float32, K x n, on the GPU) of plain GMRES(m) on A x = b."""
+def collect_pairs(row_ptr, col_idx, vals, b, K=4, m=30):
+    """K restart residuals (float32, K x n, unit norm, on the GPU) of plain GMRES(m)."""
     torch = _torch()
-    s = Solver(A.row_ptr, A.col_idx, A.vals, m=m, tol=0.0, ortho="cgsr", precision="fp32", max_iters=m,
+    s = Solver(row_ptr, col_idx, vals, m=m, tol=0.0, ortho="cgsr", precision="fp32", max_iters=m,
                autotune=False, use_graph=False)
-    x = torch.zeros(A.n, dtype=torch.float64, device="cuda")
-    Z = torch.empty((K, A.n), dtype=torch.float32, device="cuda")
+    x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
+    Z = torch.empty((K, s.n), dtype=torch.float32, device="cuda")
     for k in range(K):
         r, nrm = s.residual(b, x)
         if not nrm > 0.0:
@@ -35,43 +38,59 @@ def collect_pairs(A, b, K=4, m=30):
     return Z
 
 
-def make_instances(ids, N, generator=None):
-    """(A, b) for each instance index of the variable-coefficient family."""
-    import problems as P
-
-    out = []
-    for i in ids:
-        pr = P.c5_varcoef(i, N=N)
-        out.append((pr.A, pr.b))
-    return out
+@dataclass
+class TrainingData:
+    row_ptr: object = None      # device int32
+    col_idx: object = None      # device int32
+    vals: list = field(default_factory=list)   # device float64 per instance
+    pairs: list = field(default_factory=list)  # device float32 K x n per instance
+    seconds: float = 0.0
 
 
-def train(train_ids, N=64, steps=100, lr=3e-3, seed=0, pairs_per_instance=4, batch=1, log=None,
-          instances=None):
-    """Adam on the residual loss over the training instances (cycled in order)."""
+def prepare(instances, K=4, m=30, log=None):
+    """GPU-resident training data from an iterable of (A, b) sharing one pattern."""
     torch = _torch()
     t0 = time.perf_counter()
-    inst = instances if instances is not None else make_instances(train_ids, N)
-    A0 = inst[0][0]
-    net = S.SpaiNet(A0.row_ptr, A0.col_idx, kmax=pairs_per_instance)
-    vals, pairs = [], []
-    for A, b in inst:
-        if A.nnz != A0.nnz or not np.array_equal(A.col_idx, A0.col_idx):
+    d = TrainingData()
+    ci_host = None
+    for q, (A, b) in enumerate(instances):
+        if d.row_ptr is None:
+            d.row_ptr = torch.as_tensor(A.row_ptr, dtype=torch.int32, device="cuda")
+            d.col_idx = torch.as_tensor(A.col_idx, dtype=torch.int32, device="cuda")
+            ci_host = np.asarray(A.col_idx)
+        elif A.nnz != ci_host.size or not np.array_equal(A.col_idx, ci_host):
             raise ValueError("training instances must share one sparsity pattern")
-        vals.append(torch.as_tensor(A.vals, device="cuda"))
-        pairs.append(collect_pairs(A, b, K=pairs_per_instance))
-    t_data = time.perf_counter() - t0
+        v = torch.as_tensor(A.vals, dtype=torch.float64, device="cuda")
+        bt = torch.as_tensor(b, dtype=torch.float64, device="cuda")
+        d.vals.append(v)
+        d.pairs.append(collect_pairs(d.row_ptr, d.col_idx, v, bt, K=K, m=m))
+        if log and (q + 1) % 200 == 0:
+            log(f"  prepared {q + 1} instances ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    d.seconds = time.perf_counter() - t0
+    return d
+
+
+def train_on(data: TrainingData, epochs=1.0, lr=1e-3, batch=4, seed=0, log=None):
+    """Adam on the residual loss, instances cycled in a seeded shuffled order."""
+    torch = _torch()
+    ninst = len(data.vals)
+    K = int(data.pairs[0].shape[0])
+    net = S.SpaiNet(data.row_ptr, data.col_idx, kmax=K)
     opt = S.Adam(S.init_params(seed), lr=lr)
     grad = torch.zeros(S.NPARAMS, dtype=torch.float32, device="cuda")
+    order = np.random.default_rng(seed).permutation(ninst)
+    steps = max(1, int(round(epochs * ninst / batch)))
     hist = []
+    torch.cuda.synchronize()
     t1 = time.perf_counter()
     for step in range(steps):
         Ls = []
         for q in range(batch):
-            k = (step * batch + q) % len(inst)
-            net.set_values(vals[k])
+            k = int(order[(step * batch + q) % ninst])
+            net.set_values(data.vals[k])
             M = net.forward(opt.params)
-            L, dm = net.loss(M, pairs[k])
+            L, dm = net.loss(M, data.pairs[k])
             net.backward(opt.params, dm, grad=grad, accumulate=q > 0)
             Ls.append(L)
         opt.step(grad, scale=1.0 / batch)
@@ -80,41 +99,65 @@ def train(train_ids, N=64, steps=100, lr=3e-3, seed=0, pairs_per_instance=4, bat
             log(f"  step {step:5d} loss {hist[-1]:.5f}")
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    # loss of the final parameters over all instances, and of the Jacobi start
+
     def mean_loss(params):
         out = []
-        for k in range(len(inst)):
-            net.set_values(vals[k])
-            out.append(net.loss(net.forward(params), pairs[k], grad=False)[0])
+        for k in range(ninst):
+            net.set_values(data.vals[k])
+            out.append(net.loss(net.forward(params), data.pairs[k], grad=False)[0])
         return float(np.mean(out))
 
     jac = torch.as_tensor(S.params_to_bf16(S.init_params(seed)), device="cuda")
     res = {"params": opt.params.clone(), "theta": opt.theta.clone(), "history": hist,
            "loss_first": mean_loss(jac), "loss_last": mean_loss(opt.params),
-           "seconds_data": t_data, "seconds_train": t_train, "steps": steps, "batch": batch,
-           "instances": len(inst)}
+           "seconds_data": data.seconds, "seconds_train": t_train, "steps": steps, "batch": batch,
+           "instances": ninst, "seconds_per_instance_step": t_train / (steps * batch)}
     net.close()
     return res
 
 
-def evaluate(params, test_ids, N=64, m=30, tol=1e-10, ortho="cgsr", instances=None, max_iters=100_000):
-    """Iterations and time to tol for none / Jacobi / learned right preconditioning."""
+def make_instances(ids, N):
+    """(A, b) for each instance index of the variable-coefficient family."""
+    import problems as P
+
+    for i in ids:
+        pr = P.c5_varcoef(i, N=N)
+        yield pr.A, pr.b
+
+
+def train(train_ids, N=64, steps=100, lr=3e-3, seed=0, pairs_per_instance=4, batch=1, log=None):
+    """Convenience wrapper: generate, prepare and train for a number of steps."""
+    data = prepare(make_instances(train_ids, N), K=pairs_per_instance, log=log)
+    return train_on(data, epochs=steps * batch / len(train_ids), lr=lr, batch=batch, seed=seed, log=log)
+
+
+def solve_once(A, b, kind, params=None, m=30, tol=1e-10, ortho="cgsr", max_iters=100_000):
+    """Time to tol including setup for one preconditioning kind:
+    fp64 (no preconditioner), none, jacobi, learned (float32 Arnoldi)."""
     torch = _torch()
-    inst = instances if instances is not None else make_instances(test_ids, N)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prec = "fp64" if kind == "fp64" else "fp32"
+    pc = {"fp64": "none", "none": "none", "jacobi": "jacobi", "learned": "spai"}[kind]
+    s = Solver(A[0], A[1], A[2], m=m, tol=tol, ortho=ortho, precision=prec, precond=pc, max_iters=max_iters)
+    if kind == "learned":
+        s.spai_infer(params)
+    x, info = s.solve(b)
+    torch.cuda.synchronize()
+    info["seconds_total"] = time.perf_counter() - t0
+    s.close()
+    return x, info
+
+
+def evaluate(params, test_ids, N=64, m=30, tol=1e-10, ortho="cgsr", kinds=("none", "jacobi", "learned")):
+    """Iterations and time to tol per instance and preconditioning kind."""
+    torch = _torch()
     out = []
-    for idx, (A, b) in zip(test_ids, inst):
+    for idx, (A, b) in zip(test_ids, make_instances(test_ids, N)):
+        dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
+        bt = torch.as_tensor(b, device="cuda")
         row = {"instance": idx}
-        for kind in ("none", "jacobi", "learned"):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s = Solver(A.row_ptr, A.col_idx, A.vals, m=m, tol=tol, ortho=ortho, precision="fp32",
-                       precond="spai" if kind == "learned" else kind, max_iters=max_iters)
-            if kind == "learned":
-                s.spai_infer(params)
-            x, info = s.solve(b)
-            torch.cuda.synchronize()
-            info["seconds_total"] = time.perf_counter() - t0
-            s.close()
-            row[kind] = info
+        for kind in kinds:
+            _, row[kind] = solve_once(dev, bt, kind, params=params, m=m, tol=tol, ortho=ortho)
         out.append(row)
     return out

@@ -79,6 +79,11 @@ int spai_loss(spai_handle h, const float* m_vals, const float* Z, int32_t K, dou
  * (deterministic). */
 int spai_backward(spai_handle h, const uint16_t* params, const float* dm, float* grad, int32_t accumulate);
 
+/* *same_out = 1 if (n, nnz, row_ptr, col_idx) (device CSR) is the
+ * network's pattern, else 0 (compared on the device). */
+int spai_same_pattern(spai_handle h, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      int32_t* same_out);
+
 int spai_destroy(spai_handle h);
 
 /* One Adam step (Kingma & Ba) on float32 master weights theta[count],
@@ -95,6 +100,12 @@ int spai_adam_step(int64_t count, float* theta, uint16_t* params_bf16, const flo
  * not NULL the M values are also copied there (float32[nnz]).
  * param_bytes must be SPAI_NPARAMS * 2. */
 int gmres_spai_infer(gmres_handle h, const void* params, size_t param_bytes, float* m_out);
+
+/* The same with a caller-owned network instance `net` created for this
+ * handle's pattern (checked on the device: ESTATE if it differs), so a
+ * family of matrices with one pattern pays the pattern setup once; the
+ * per-solve cost is the network inputs and one forward pass. */
+int gmres_spai_infer_with(gmres_handle h, spai_handle net, const void* params, size_t param_bytes, float* m_out);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,8 @@ _SIGS = {
     "spai_loss": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.POINTER(C.c_double), _vp]),
     "spai_backward": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int32]),
     "spai_destroy": (C.c_int, [_vp]),
+    "spai_same_pattern": (C.c_int, [_vp, C.c_int64, C.c_int64, _vp, _vp, C.POINTER(C.c_int32)]),
+    "gmres_spai_infer_with": (C.c_int, [_vp, _vp, _vp, C.c_size_t, _vp]),
     "spai_adam_step": (C.c_int, [C.c_int64, _vp, _vp, _vp, C.c_float, _vp, _vp, C.c_float, C.c_float, C.c_float,
                                  C.c_float, C.c_int32, _vp]),
 }

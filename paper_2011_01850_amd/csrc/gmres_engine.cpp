@@ -645,6 +645,32 @@ int gmres_spai_infer(gmres_handle hh, const void* params, size_t param_bytes, fl
   }
 }
 
+int gmres_spai_infer_with(gmres_handle hh, spai_handle net, const void* params, size_t param_bytes, float* m_out) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (h->opt.precond != GMRES_PRECOND_SPAI || h->sys.size() != 1) return GMRES_ESTATE;
+    if (!net || !params || param_bytes != (size_t)SPAI_NPARAMS * 2) return GMRES_EINVAL;
+    after_caller(h);
+    hip_check(hipStreamSynchronize(h->stream));  // the network's calls are ordered after this handle's work
+    int32_t same = 0;
+    int rc = spai_same_pattern(net, h->sys[0].n, h->nnz, h->a.rp, h->a.ci, &same);
+    if (rc != GMRES_OK) return rc;
+    if (!same) return GMRES_ESTATE;
+    rc = spai_set_values(net, h->a.a64);
+    if (rc == GMRES_OK) rc = spai_forward(net, (const uint16_t*)params, (float*)h->a.mval);
+    if (rc != GMRES_OK) return rc;
+    if (m_out) {
+      hip_check(hipMemcpyAsync(m_out, h->a.mval, h->nnz * 4, hipMemcpyDeviceToDevice, h->stream));
+      hip_check(hipStreamSynchronize(h->stream));
+    }
+    h->spai_set = true;
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
 int gmres_solve(gmres_handle hh, const double* b, double* x, gmres_result* res) {
   try {
     gmres_ctx* h = get(hh);

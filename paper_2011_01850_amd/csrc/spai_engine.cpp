@@ -37,6 +37,7 @@ struct spai_ctx {
   sp::Net a{};
   int kmax = 0, ncu = 1, nblk = 1;
   bool values_set = false, forward_done = false;
+  bool loss_ready = false, backward_ready = false;  // workspaces allocated on first use
   std::vector<void*> allocs;
 
   template <typename T>
@@ -146,19 +147,31 @@ void setup(spai_ctx* h, int64_t n64, int64_t nnz64, const int32_t* row_ptr, cons
     a.h[l] = h->alloc<float>((size_t)n * sp::kH);
     a.e[l] = h->alloc<float>((size_t)nnz * sp::kH);
   }
-  a.dh[0] = h->alloc<float>((size_t)n * sp::kH);
-  a.dh[1] = h->alloc<float>((size_t)n * sp::kH);
-  a.de = h->alloc<float>((size_t)nnz * sp::kH);
-  a.duhi = h->alloc<float>((size_t)nnz * sp::kH);
-  a.duhj = h->alloc<float>((size_t)nnz * sp::kH);
-  a.ds = h->alloc<float>(nnz);
-  a.part = h->alloc<float>(sp::backward_part_floats(n, nnz, h->ncu));
-  a.lpart = h->alloc<double>((size_t)2 * kmax * h->nblk);
-  a.kbuf = h->alloc<float>((size_t)3 * kmax * n);
-  a.coef = h->alloc<float>(kmax);
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
+void ensure_loss(spai_ctx* h) {
+  if (h->loss_ready) return;
+  sp::Net& a = h->a;
+  a.lpart = h->alloc<double>((size_t)2 * h->kmax * h->nblk);
+  a.kbuf = h->alloc<float>((size_t)3 * h->kmax * a.n);
+  a.coef = h->alloc<float>(h->kmax);
   a.lossv = h->alloc<double>(1);
   a.bad = h->alloc<int32_t>(1);
-  hip_check(hipStreamSynchronize(h->stream));
+  h->loss_ready = true;
+}
+
+void ensure_backward(spai_ctx* h) {
+  if (h->backward_ready) return;
+  sp::Net& a = h->a;
+  a.dh[0] = h->alloc<float>((size_t)a.n * sp::kH);
+  a.dh[1] = h->alloc<float>((size_t)a.n * sp::kH);
+  a.de = h->alloc<float>((size_t)a.nnz * sp::kH);
+  a.duhi = h->alloc<float>((size_t)a.nnz * sp::kH);
+  a.duhj = h->alloc<float>((size_t)a.nnz * sp::kH);
+  a.ds = h->alloc<float>(a.nnz);
+  a.part = h->alloc<float>(sp::backward_part_floats(a.n, a.nnz, h->ncu));
+  h->backward_ready = true;
 }
 
 template <typename F>
@@ -229,6 +242,7 @@ int spai_loss(spai_handle hh, const float* m_vals, const float* Z, int32_t K, do
     spai_ctx* h = get(hh);
     if (!m_vals || !Z || K < 1 || K > h->kmax) return GMRES_EINVAL;
     if (!h->values_set) return GMRES_ESTATE;
+    ensure_loss(h);
     after_caller(h);
     sp::Net a = h->a;
     a.K = K;
@@ -249,9 +263,30 @@ int spai_backward(spai_handle hh, const uint16_t* params, const float* dm, float
     spai_ctx* h = get(hh);
     if (!params || !dm || !grad) return GMRES_EINVAL;
     if (!h->forward_done) return GMRES_ESTATE;
+    ensure_backward(h);
     after_caller(h);
     hip_check(sp::launch_backward(h->a, params, dm, grad, accumulate, h->ncu, h->stream));
     hip_check(hipStreamSynchronize(h->stream));
+    return GMRES_OK;
+  });
+}
+
+int spai_same_pattern(spai_handle hh, int64_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                      int32_t* same_out) {
+  return guarded([&] {
+    spai_ctx* h = get(hh);
+    if (!row_ptr || !col_idx || !same_out) return GMRES_EINVAL;
+    if (n != h->a.n || nnz != h->a.nnz) {
+      *same_out = 0;
+      return GMRES_OK;
+    }
+    ensure_loss(h);  // for the device flag
+    after_caller(h);
+    hip_check(sp::launch_compare_pattern(h->a, row_ptr, col_idx, h->stream));
+    int32_t bad = 1;
+    hip_check(hipMemcpyAsync(&bad, h->a.bad, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    *same_out = bad ? 0 : 1;
     return GMRES_OK;
   });
 }

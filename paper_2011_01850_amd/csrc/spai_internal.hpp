@@ -63,6 +63,8 @@ hipError_t launch_forward(const Net& a, const uint16_t* prm, float* m_out, int n
 hipError_t launch_loss(const Net& a, const float* mv, const float* Z, int nblk, float* dm, hipStream_t st);
 hipError_t launch_backward(const Net& a, const uint16_t* prm, const float* dm, float* grad, int accumulate,
                            int ncu, hipStream_t st);
+// a.bad = 0 if (row_ptr, col_idx) equal the network's pattern, else 1
+hipError_t launch_compare_pattern(const Net& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t st);
 hipError_t launch_adam(int64_t count, float* theta, uint16_t* pb, const float* grad, float gscale, float* m1,
                        float* m2, float lr, float b1, float b2, float eps, int t, hipStream_t st);
 // rows of the partial table the backward pass needs for `ncu` compute units

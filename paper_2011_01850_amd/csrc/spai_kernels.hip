@@ -584,6 +584,17 @@ __global__ void k_reduce(const float* __restrict__ part, int rows, int stride, i
   grad[dst + c] = accumulate ? grad[dst + c] + (float)s : (float)s;
 }
 
+__global__ void k_flag_clear(int32_t* flag) { flag[0] = 0; }
+
+// sets flag when an entry of (row_ptr, col_idx) differs from the pattern
+__global__ void k_compare_pattern(Net a, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool diff = false;
+  if (k <= a.n) diff = rp[k] != a.rp[k];
+  if (k < a.nnz) diff = diff || ci[k] != a.ci[k];
+  if (diff) a.bad[0] = 1;
+}
+
 __global__ void k_adam(int64_t count, float* __restrict__ theta, uint16_t* __restrict__ pb,
                        const float* __restrict__ grad, float gscale, float* __restrict__ m1,
                        float* __restrict__ m2, float lr, float b1, float b2, float eps, float c1, float c2) {
@@ -689,6 +700,13 @@ hipError_t launch_backward(const Net& a, const uint16_t* prm, const float* dm, f
   hipLaunchKernelGGL(k_enc_bwd_edge, dim3(gs), dim3(256), 0, st, a);
   reduce(gs, kEncPart, 0, kH * kNin, oWe);
   reduce(gs, kEncPart, kH * kNin, kH, obe);
+  return hipGetLastError();
+}
+
+hipError_t launch_compare_pattern(const Net& a, const int32_t* row_ptr, const int32_t* col_idx, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, a.bad);
+  hipLaunchKernelGGL(k_compare_pattern, dim3(grid_for(std::max<int64_t>(a.n + 1, a.nnz))), dim3(256), 0, st, a,
+                     row_ptr, col_idx);
   return hipGetLastError();
 }
 

@@ -108,15 +108,24 @@ class Solver:
         torch.cuda.synchronize()
         L.check(self.lib.gmres_set_preconditioner(self.h, v.data_ptr()), "gmres_set_preconditioner")
 
-    def spai_infer(self, params_bf16):
-        """Run the learned network on this solver's matrix and install M; returns M (float32 tensor)."""
+    def spai_infer(self, params_bf16, net=None, return_m=True):
+        """Run the learned network on this solver's matrix and install M.
+
+        net: an optional SpaiNet created for the same sparsity pattern (reused
+        across a family of matrices); without it the handle builds its own.
+        Returns M (float32 tensor) or None."""
         torch = self._torch
         pb = _dev(params_bf16, torch.int16, torch)
         if pb.numel() != L.SPAI_NPARAMS:
             raise ValueError(f"expected {L.SPAI_NPARAMS} bfloat16 parameters")
-        out = torch.empty(self.nnz, dtype=torch.float32, device="cuda")
+        out = torch.empty(self.nnz, dtype=torch.float32, device="cuda") if return_m else None
+        optr = out.data_ptr() if return_m else None
         torch.cuda.synchronize()
-        L.check(self.lib.gmres_spai_infer(self.h, pb.data_ptr(), pb.numel() * 2, out.data_ptr()), "gmres_spai_infer")
+        if net is None:
+            L.check(self.lib.gmres_spai_infer(self.h, pb.data_ptr(), pb.numel() * 2, optr), "gmres_spai_infer")
+        else:
+            L.check(self.lib.gmres_spai_infer_with(self.h, net.h, pb.data_ptr(), pb.numel() * 2, optr),
+                    "gmres_spai_infer_with")
         return out
 
     def residual(self, b, x):

@@ -131,9 +131,11 @@ def train(train_ids, N=64, steps=100, lr=3e-3, seed=0, pairs_per_instance=4, bat
     return train_on(data, epochs=steps * batch / len(train_ids), lr=lr, batch=batch, seed=seed, log=log)
 
 
-def solve_once(A, b, kind, params=None, m=30, tol=1e-10, ortho="cgsr", max_iters=100_000):
+def solve_once(A, b, kind, params=None, m=30, tol=1e-10, ortho="cgsr", max_iters=100_000, net=None):
     """Time to tol including setup for one preconditioning kind:
-    fp64 (no preconditioner), none, jacobi, learned (float32 Arnoldi)."""
+    fp64 (no preconditioner), none, jacobi, learned (float32 Arnoldi).
+    For `learned`, `net` is an optional network instance shared by the
+    family's sparsity pattern (else the solver builds its own)."""
     torch = _torch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -141,7 +143,7 @@ def solve_once(A, b, kind, params=None, m=30, tol=1e-10, ortho="cgsr", max_iters
     pc = {"fp64": "none", "none": "none", "jacobi": "jacobi", "learned": "spai"}[kind]
     s = Solver(A[0], A[1], A[2], m=m, tol=tol, ortho=ortho, precision=prec, precond=pc, max_iters=max_iters)
     if kind == "learned":
-        s.spai_infer(params)
+        s.spai_infer(params, net=net, return_m=False)
     x, info = s.solve(b)
     torch.cuda.synchronize()
     info["seconds_total"] = time.perf_counter() - t0
@@ -153,11 +155,16 @@ def evaluate(params, test_ids, N=64, m=30, tol=1e-10, ortho="cgsr", kinds=("none
     """Iterations and time to tol per instance and preconditioning kind."""
     torch = _torch()
     out = []
+    net = None
     for idx, (A, b) in zip(test_ids, make_instances(test_ids, N)):
         dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
         bt = torch.as_tensor(b, device="cuda")
+        if net is None:
+            net = S.SpaiNet(dev[0], dev[1], kmax=1)
         row = {"instance": idx}
         for kind in kinds:
-            _, row[kind] = solve_once(dev, bt, kind, params=params, m=m, tol=tol, ortho=ortho)
+            _, row[kind] = solve_once(dev, bt, kind, params=params, m=m, tol=tol, ortho=ortho, net=net)
         out.append(row)
+    if net is not None:
+        net.close()
     return out

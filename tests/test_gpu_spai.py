@@ -245,3 +245,24 @@ def test_training_gains_over_no_preconditioner(lib):
         print(r)
         assert r["learned"]["status"] == "CONVERGED"
         assert r["learned"]["iters"] < 0.5 * r["none"]["iters"]
+
+
+def test_infer_with_shared_network(lib):
+    """A network instance shared by a family's pattern gives the same M as the
+    solver's own instance; a different pattern is refused."""
+    from paper_2011_01850_amd import GmresError, Solver
+    params = torch.as_tensor(lib.params_to_bf16(theta_for(5))).cuda()
+    a1, a2 = P.c5_varcoef(2001, N=10).A, P.c5_varcoef(2002, N=10).A
+    net = lib.SpaiNet(a1.row_ptr, a1.col_idx, kmax=1)
+    for A in (a1, a2):
+        s = Solver(A.row_ptr, A.col_idx, A.vals, m=20, precision="fp32", precond="spai", autotune=False)
+        m_own = s.spai_infer(params)
+        m_shared = s.spai_infer(params, net=net)
+        assert torch.equal(m_own, m_shared)
+        s.close()
+    other = P.convdiff(10, (1.0, 2.0))
+    s = Solver(other.row_ptr, other.col_idx, other.vals, m=20, precision="fp32", precond="spai", autotune=False)
+    with pytest.raises(GmresError):
+        s.spai_infer(params, net=net)
+    s.close()
+    net.close()

@@ -58,6 +58,17 @@ enum {
 /* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y) */
 enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2 };
 
+/* gmres_options.batch_schedule.
+ * DEVICE_WIDE: every kernel launch covers all systems of the handle (any
+ * options); one restart cycle is one graph launch.
+ * PERSISTENT: one kernel launch for the whole solve; each workgroup of 1024
+ * threads takes systems from a queue (largest first) and runs Algorithm 1
+ * on one system with its work vector in registers.  Requires MIXED_FP32,
+ * MGS, no preconditioner, m <= 64 and n <= 65536 for every system.
+ * AUTO: PERSISTENT for batch handles (gmres_batch_create) that meet those
+ * conditions, DEVICE_WIDE otherwise. */
+enum { GMRES_SCHEDULE_AUTO = 0, GMRES_SCHEDULE_DEVICE_WIDE = 1, GMRES_SCHEDULE_PERSISTENT = 2 };
+
 /* gmres_result.status */
 enum { GMRES_RUNNING = 0, GMRES_CONVERGED = 1, GMRES_MAXITER = 2, GMRES_STALLED = 3 };
 
@@ -83,6 +94,7 @@ typedef struct {
   int32_t stall_cycles;     /* STALLED after this many cycles in a row that do not lower beta */
   int32_t use_graph;        /* 1: capture one restart cycle as a hipGraph and replay it */
   int32_t autotune;         /* 1: time SpMV tile variants at create time and keep the fastest */
+  int32_t batch_schedule;   /* GMRES_SCHEDULE_*: how the systems of a handle share the GPU */
 } gmres_options;
 
 typedef struct {
@@ -98,7 +110,7 @@ typedef struct {
 
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 3,
- * use_graph = 1, autotune = 1. */
+ * use_graph = 1, autotune = 1, batch_schedule = AUTO. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).
@@ -114,12 +126,14 @@ int gmres_create(gmres_handle* out, int64_t n, int64_t nnz, const int32_t* row_p
                  const int32_t* col_idx, const double* vals, const gmres_options* opt,
                  void* hip_stream);
 
-/* Create one solver for nsys independent systems that are advanced
- * together (the batch path): the k-th system is n[k] x n[k] with nnz[k]
- * entries given by the k-th pointers of the (HOST) pointer arrays, which
- * point to device memory.  Every kernel launch covers all systems; each
- * system keeps its own Hessenberg matrix, rotations, restart and stop
- * decisions, so its iterates are exactly those of a single-system solve. */
+/* Create one solver for nsys independent systems (the batch path): the
+ * k-th system is n[k] x n[k] with nnz[k] entries given by the k-th pointers
+ * of the (HOST) pointer arrays, which point to device memory.  Each system
+ * keeps its own Hessenberg matrix, rotations, restart and stop decisions.
+ * Under the device-wide schedule its iterates are exactly those of a
+ * single-system solve; under the persistent schedule, exactly those of a
+ * persistent solve of that system alone.  Errors as gmres_create, and
+ * EINVAL for batch_schedule = PERSISTENT when its conditions fail. */
 int gmres_batch_create(gmres_handle* out, int32_t nsys, const int64_t* n, const int64_t* nnz,
                        const int32_t* const* row_ptr, const int32_t* const* col_idx,
                        const double* const* vals, const gmres_options* opt, void* hip_stream);
@@ -197,6 +211,7 @@ int gmres_memory_bytes(gmres_handle h, size_t* bytes);
  * library can be loaded, for profilers that rename kernels by range. */
 int gmres_time_kernel(gmres_handle h, int32_t kernel, int32_t j, int32_t reps, double* avg_ms,
                       double* bytes);
+/* (ESTATE on a handle that runs the persistent batch schedule.) */
 
 #ifdef __cplusplus
 }

@@ -17,6 +17,8 @@ STATUS_NAMES = {RUNNING: "RUNNING", CONVERGED: "CONVERGED", MAXITER: "MAXITER", 
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
 ORTHOS = {"mgs": MGS, "cgsr": CGSR}
 PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "spai": PRECOND_SPAI}
+SCHEDULE_AUTO, SCHEDULE_DEVICE_WIDE, SCHEDULE_PERSISTENT = 0, 1, 2
+SCHEDULES = {"auto": SCHEDULE_AUTO, "device_wide": SCHEDULE_DEVICE_WIDE, "persistent": SCHEDULE_PERSISTENT}
 
 
 class Options(C.Structure):
@@ -31,6 +33,7 @@ class Options(C.Structure):
         ("stall_cycles", C.c_int32),
         ("use_graph", C.c_int32),
         ("autotune", C.c_int32),
+        ("batch_schedule", C.c_int32),
     ]
 
 

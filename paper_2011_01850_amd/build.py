@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgmres.so")
 ARCH = os.environ.get("GMRES_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["gmres_kernels.hip", "gmres_engine.cpp", "spai_kernels.hip", "spai_engine.cpp"]
+SOURCES = ["gmres_kernels.hip", "gmres_engine.cpp", "batch_kernels.hip", "spai_kernels.hip", "spai_engine.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

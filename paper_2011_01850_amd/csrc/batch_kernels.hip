@@ -1,0 +1,424 @@
+// Persistent batch schedule of restarted GMRES(m) for gfx950: one workgroup
+// of 1024 threads solves one system from start to finish, and workgroups
+// take systems from a queue (largest first) until it is empty, all in one
+// kernel launch.
+//
+// Per system (Algorithm 1 with MGS, float32 Arnoldi, float64 residual,
+// update, Hessenberg matrix and rotations): the work vector w lives in
+// registers, R = ceil(n / 1024) rows per thread (n <= 65,536), and each
+// basis vector is kept in LDS between its dot product and its axpy (up to
+// 24 rows per thread), so an MGS step reads v_i once from memory (for n up
+// to 24,576; larger systems re-read the rest) and never streams w; H, the rotations
+// and the least-squares right-hand side live in LDS; the basis lives in
+// HBM in one contiguous block per system.  Every reduction is a fixed-order
+// block sum (per-thread float32 partials, float64 across threads), so a
+// system's result does not depend on the other systems of the batch or on
+// which workgroup ran it.
+#include <math.h>
+
+#include <algorithm>
+
+#include "gmres_internal.hpp"
+
+namespace gm {
+namespace {
+
+constexpr int kPB = 1024;        // threads per system
+constexpr int kPW = kPB / 64;    // waves per system
+constexpr int kStage = 24;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
+
+struct PShared {
+  double red[2][kPW][2];               // double-buffered wave partials (two sums each)
+  double H[(kMaxPM + 1) * kMaxPM];     // rotated Hessenberg matrix, column-major
+  double cs[kMaxPM], sn[kMaxPM], sv[kMaxPM + 1], y[kMaxPM], ar[kMaxPM + 1];
+  int ctl[4];
+  double dctl[2];
+  int sys;
+  float vst[kStage][kPB];              // staged rows of v_i (thread t owns column t)
+};
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum over the workgroup of (u, v), identical in every thread; `buf`
+// alternates between calls so one barrier per call suffices.
+__device__ __forceinline__ void bsum2(PShared& sh, int& buf, double& u, double& v) {
+  u = wsum(u);
+  v = wsum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh.red[buf][w][0] = u;
+    sh.red[buf][w][1] = v;
+  }
+  __syncthreads();
+  double su = 0.0, sv = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPW; ++q) {
+    su += sh.red[buf][q][0];
+    sv += sh.red[buf][q][1];
+  }
+  u = su;
+  v = sv;
+  buf ^= 1;
+}
+
+__device__ __forceinline__ double bsum(PShared& sh, int& buf, double u) {
+  double v = 0.0;
+  bsum2(sh, buf, u, v);
+  return u;
+}
+
+__device__ __forceinline__ void p_givens(double a, double b, double& c, double& s) {
+  if (b == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  const double rho = hypot(a, b);
+  c = a / rho;
+  s = b / rho;
+}
+
+// Buffer resources: every thread addresses its rows as one 32-bit lane
+// offset plus a scalar offset per row group, so R rows per thread cost no
+// per-row 64-bit addresses (the kernel runs at 128 registers per thread).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t mkr(const void* base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                           (int)(uint32_t)std::min<uint64_t>(bytes, 0xffffffffu), 0x00020000);
+}
+__device__ __forceinline__ float ldf(rsrc_t r, uint32_t vo, uint32_t so) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ int ldi(rsrc_t r, uint32_t vo, uint32_t so) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ double ldd(rsrc_t r, uint32_t vo, uint32_t so) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+__device__ __forceinline__ void stf(float x, rsrc_t r, uint32_t vo, uint32_t so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void std64(double x, rsrc_t r, uint32_t vo, uint32_t so) {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, (int)vo, (int)so, 0);
+}
+
+// Values that are the same in every lane, pinned to scalar registers: buffer
+// descriptors built from them must be scalar, else every access becomes a
+// loop over lanes.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Row q of thread t is r = t + 1024 q.  Every vector of the system is read
+// and written through a descriptor bounded to its n rows: loads past the end
+// return zero and stores past it are dropped, so the row loops need no
+// guards and a thread keeps up to 16 loads in flight.
+template <int R>
+__device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
+  const int t = threadIdx.x;
+  const int m = a.m, M1 = m + 1;
+  const int64_t row0 = uni64(a.sys_row0[s]);
+  const int n = uni(a.sys_n[s]);
+  const uint32_t pn = (uint32_t)uni(a.sys_nt[s]) * kTile;  // column stride of this system's basis
+  const uint32_t nz_end = (uint32_t)uni(a.rp[row0 + n]);    // entries of systems up to this one
+  float* Vs = static_cast<float*>(a.V) + (int64_t)M1 * row0;
+  auto col = [&](int i) { return mkr(Vs + (size_t)i * pn, (uint64_t)n * 4); };
+  const rsrc_t rpr = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
+  const rsrc_t cir = mkr(a.ci, (uint64_t)nz_end * 4);
+  const rsrc_t a32r = mkr(a.a32, (uint64_t)nz_end * 4);
+  const rsrc_t a64r = mkr(a.a64, (uint64_t)nz_end * 8);
+  const rsrc_t xall = mkr(a.x, (uint64_t)a.ld * 8);         // gathers by global column
+  const rsrc_t xs = mkr(a.x + row0, (uint64_t)n * 8);       // this system's rows
+  const rsrc_t br = mkr(a.b + row0, (uint64_t)n * 8);
+  double* hbar = a.Hbar + (int64_t)s * M1 * m;
+  const uint32_t t4 = (uint32_t)t * 4u, t8 = (uint32_t)t * 8u;
+  const int col0 = (int)row0;  // global column of local row 0
+  int buf = 0;
+  float w[R];
+
+  double bb = 0.0, dummy = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const double bv = ldd(br, t8, (uint32_t)q * kPB * 8u);
+    bb += bv * bv;
+  }
+  bsum2(sh, buf, bb, dummy);
+  const double bnorm = sqrt(bb);
+
+  int status = RUNNING, nhist = 0, cycle = 0, no_progress = 0, first_stall = -1, klast = 0;
+  int64_t iters = 0, restarts = 0;
+  double best = INFINITY, beta = 0.0, rel = 0.0;
+  if (bnorm == 0.0) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) std64(0.0, xs, t8, (uint32_t)q * kPB * 8u);
+    status = CONVERGED;
+  }
+  const double bd_u = 0x1p-24;
+  while (status == RUNNING) {
+    // ---- float64 restart residual z = b - A x, beta, stop tests, v_1
+    double zz = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t so = (uint32_t)q * kPB * 4u;
+      const int k0 = ldi(rpr, t4, so), k1 = ldi(rpr, t4, so + 4u);  // rows past n: empty
+      double acc = 0.0;
+      for (int kb = k0; kb < k1; kb += 4) {
+        double av[4];
+        int cv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          av[e] = ldd(a64r, (uint32_t)(kb + e) * 8u, 0);
+          cv[e] = ldi(cir, (uint32_t)(kb + e) * 4u, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double xv = ldd(xall, (uint32_t)cv[e] * 8u, 0);
+          if (kb + e < k1) acc += av[e] * xv;
+        }
+      }
+      const double z = ldd(br, t8, (uint32_t)q * kPB * 8u) - acc;  // zero past n
+      zz += z * z;
+      w[q] = (float)z;
+      __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounded registers
+    }
+    bsum2(sh, buf, zz, dummy);
+    beta = sqrt(zz);
+    rel = beta / bnorm;
+    if (t == 0 && nhist < kHistCap) a.hist[(int64_t)s * kHistCap + nhist] = rel;
+    ++nhist;
+    if (rel <= a.tol) {
+      status = CONVERGED;
+      break;
+    }
+    if (!isfinite(beta)) {
+      status = STALLED;
+      break;
+    }
+    if (iters >= a.max_iters) {
+      status = MAXITER;
+      break;
+    }
+    no_progress = beta >= best ? no_progress + 1 : 0;
+    best = fmin(best, beta);
+    if (no_progress >= a.stall_cycles) {
+      status = STALLED;
+      break;
+    }
+    ++cycle;
+    {
+      const float inv = (float)(1.0 / beta);
+      const rsrc_t v0 = col(0);
+#pragma unroll
+      for (int q = 0; q < R; ++q) stf(w[q] * inv, v0, t4, (uint32_t)q * kPB * 4u);
+    }
+    if (t == 0) {
+      sh.sv[0] = beta;
+      sh.ar[0] = beta;
+    }
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      __syncthreads();  // v_j complete (stores of every thread)
+      const rsrc_t vj = col(j);
+      // ---- w = A v_j (float32); entries are read in groups of 8, the ones
+      // past the row masked (their gathers may fall anywhere, or past v_j)
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const uint32_t so = (uint32_t)q * kPB * 4u;
+        const int k0 = ldi(rpr, t4, so), k1 = ldi(rpr, t4, so + 4u);
+        float acc = 0.f;
+        for (int kb = k0; kb < k1; kb += 8) {
+          float av[8];
+          int cv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            av[e] = ldf(a32r, (uint32_t)(kb + e) * 4u, 0);
+            cv[e] = ldi(cir, (uint32_t)(kb + e) * 4u, 0);
+          }
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float xv = ldf(vj, (uint32_t)(cv[e] - col0) * 4u, 0);
+            if (kb + e < k1) acc += av[e] * xv;
+          }
+        }
+        w[q] = acc;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      float wp = 0.f;
+#pragma unroll
+      for (int q = 0; q < R; ++q) wp += w[q] * w[q];
+      double wsq = (double)wp;
+      // ---- modified Gram-Schmidt: h_ij = w . v_i, w -= h_ij v_i
+      double wnorm_pre = 0.0;
+      for (int i = 0; i <= j; ++i) {
+        const rsrc_t vi = col(i);
+        float d = 0.f;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const float v = ldf(vi, t4, (uint32_t)q * kPB * 4u);
+          if (q < kStage) sh.vst[q][t] = v;  // read back by this thread only: no barrier
+          d += w[q] * v;
+          if ((q & 15) == 15) __builtin_amdgcn_sched_barrier(0);  // at most 16 loads in flight
+        }
+        double h = (double)d;
+        if (i == 0) {
+          bsum2(sh, buf, h, wsq);
+          wnorm_pre = sqrt(wsq);
+        } else {
+          h = bsum(sh, buf, h);
+        }
+        if (t == 0) {
+          sh.H[j * M1 + i] = h;
+          hbar[(int64_t)j * M1 + i] = h;
+        }
+        const float hf = (float)h;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          w[q] -= hf * (q < kStage ? sh.vst[q][t] : ldf(vi, t4, (uint32_t)q * kPB * 4u));
+          if ((q & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      float ws = 0.f;
+#pragma unroll
+      for (int q = 0; q < R; ++q) ws += w[q] * w[q];
+      const double hn = sqrt(bsum(sh, buf, (double)ws));
+      ++iters;
+      k = j + 1;
+      // ---- Givens rotations of column j, stop decisions (one lane)
+      if (t == 0) {
+        hbar[(int64_t)j * M1 + j + 1] = hn;
+        double* hc = sh.H + j * M1;
+        double cur = hc[0];
+        for (int i = 0; i < j; ++i) {
+          const double nxt = hc[i + 1];
+          hc[i] = sh.cs[i] * cur + sh.sn[i] * nxt;
+          cur = -sh.sn[i] * cur + sh.cs[i] * nxt;
+        }
+        double c, sg;
+        p_givens(cur, hn, c, sg);
+        sh.cs[j] = c;
+        sh.sn[j] = sg;
+        const double sjv = sh.sv[j];
+        sh.sv[j + 1] = -sg * sjv;
+        sh.sv[j] = c * sjv;
+        hc[j] = c * cur + sg * hn;
+        hc[j + 1] = 0.0;
+        const double res = fabs(sg * sjv);
+        sh.ar[j + 1] = res;
+        if (cycle == 1 && first_stall < 0) {
+          const int J = j + 1 - a.stall_win;
+          if (J >= 0 && res > sh.ar[J] / 1.001) first_stall = J;
+        }
+        const double bd = 16.0 * (double)(j + 1) * bd_u;
+        const bool fin = isfinite(hn) && isfinite(cur);
+        const bool end = !fin || (j + 1 >= m) || !(hn > bd * wnorm_pre) || res <= a.tol * bnorm ||
+                         iters >= a.max_iters || (a.restart_improve > 0.0 && res <= a.restart_improve * beta);
+        sh.ctl[0] = end ? 1 : 0;
+        sh.ctl[1] = fin ? 1 : 0;
+      }
+      __syncthreads();
+      const bool end = sh.ctl[0] != 0;
+      if (sh.ctl[1] == 0) {  // non-finite column: the cycle keeps the columns before it
+        k = j;
+        break;
+      }
+      if (hn > 0.0) {
+        const float inv = (float)(1.0 / hn);
+        const rsrc_t vn = col(j + 1);
+#pragma unroll
+        for (int q = 0; q < R; ++q) stf(w[q] * inv, vn, t4, (uint32_t)q * kPB * 4u);
+      }
+      if (end) break;
+    }
+    klast = k;
+    if (k == 0) continue;  // nothing to apply: the next residual decides (stall after stall_cycles)
+    // ---- back-substitution y = H_k^-1 s_k with truncation of a singular leading block (one lane)
+    if (t == 0) {
+      double hm = 0.0;
+      for (int jj = 0; jj < k; ++jj)
+        for (int i = 0; i <= jj; ++i) hm = fmax(hm, fabs(sh.H[jj * M1 + i]));
+      const double thr = 16.0 * (double)k * bd_u * hm;
+      int kk = 0;
+      while (kk < k && fabs(sh.H[kk * M1 + kk]) > thr) ++kk;
+      for (int i = 0; i < kk; ++i) sh.y[i] = sh.sv[i];
+      for (int i = kk - 1; i >= 0; --i) {
+        sh.y[i] /= sh.H[i * M1 + i];
+        for (int l = 0; l < i; ++l) sh.y[l] -= sh.H[i * M1 + l] * sh.y[i];
+      }
+      sh.ctl[2] = kk;
+    }
+    __syncthreads();
+    const int kk = sh.ctl[2];
+    // ---- x += sum_i y_i v_i (float64 accumulation)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const uint32_t xo = (uint32_t)q * kPB * 8u;
+      double acc = ldd(xs, t8, xo);
+      for (int i = 0; i < kk; ++i) acc += sh.y[i] * (double)ldf(col(i), t4, (uint32_t)q * kPB * 4u);
+      std64(acc, xs, t8, xo);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    ++restarts;
+    __syncthreads();  // x complete before the next residual reads it
+  }
+  if (t == 0) {
+    SysState& S = a.st[s];
+    S.status = status;
+    S.iters = iters;
+    S.restarts = restarts;
+    S.bnorm = bnorm;
+    S.beta = beta;
+    S.rel = bnorm == 0.0 ? 0.0 : rel;
+    S.first_stall = first_stall;
+    S.nhist = nhist;
+    S.k = klast;
+    S.cycle = cycle;
+    S.active = 0;
+  }
+  __syncthreads();  // the next system reuses the shared state
+}
+
+__global__ __launch_bounds__(kPB) void k_batch_persistent(KArgs a, const int32_t* __restrict__ order,
+                                                          int32_t* counter) {
+  __shared__ PShared sh;
+  for (;;) {
+    if (threadIdx.x == 0) sh.sys = atomicAdd(counter, 1);
+    __syncthreads();
+    // the whole workgroup works on one system: keep its index in scalar
+    // registers (read through LDS it would look divergent, and every buffer
+    // descriptor built from it would need a per-lane loop)
+    const int q = __builtin_amdgcn_readfirstlane(sh.sys);
+    __syncthreads();
+    if (q >= a.S) break;
+    const int s = __builtin_amdgcn_readfirstlane(order[q]);
+    const int rows = (a.sys_n[s] + kPB - 1) / kPB;
+    if (rows <= 1) p_system<1>(a, s, sh);
+    else if (rows <= 2) p_system<2>(a, s, sh);
+    else if (rows <= 4) p_system<4>(a, s, sh);
+    else if (rows <= 8) p_system<8>(a, s, sh);
+    else if (rows <= 16) p_system<16>(a, s, sh);
+    else if (rows <= 32) p_system<32>(a, s, sh);
+    else p_system<kMaxPR>(a, s, sh);
+  }
+}
+
+__global__ void k_counter_clear(int32_t* counter) { counter[0] = 0; }
+
+}  // namespace
+
+hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, hipStream_t st) {
+  const int grid = std::max(1, std::min(a.S, a.ncu));
+  hipLaunchKernelGGL(k_counter_clear, dim3(1), dim3(1), 0, st, counter);
+  hipLaunchKernelGGL(k_batch_persistent, dim3(grid), dim3(kPB), 0, st, a, order, counter);
+  return hipGetLastError();
+}
+
+}  // namespace gm

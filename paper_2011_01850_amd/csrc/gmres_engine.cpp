@@ -60,6 +60,11 @@ struct gmres_ctx {
   hipEvent_t evu = nullptr;
   bool spai_set = false;
   spai_handle spai = nullptr;    // network instance on this handle's pattern (gmres_spai_infer)
+  // persistent schedule: one workgroup per system, one launch per solve
+  bool persistent = false;
+  int32_t* order = nullptr;      // systems, largest first
+  int32_t* counter = nullptr;    // queue position
+  hipGraphExec_t pexec = nullptr;
   // batch gather/scatter pointer tables (device)
   const double** bptrs = nullptr;
   double** xptrs = nullptr;
@@ -84,6 +89,7 @@ struct gmres_ctx {
   ~gmres_ctx() {
     if (spai) (void)spai_destroy(spai);
     if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (pexec) (void)hipGraphExecDestroy(pexec);
     for (void* p : allocs) (void)hipFree(p);
     if (st_host) (void)hipHostFree(st_host);
     if (ev0) (void)hipEventDestroy(ev0);
@@ -135,7 +141,18 @@ bool valid_options(const gmres_options* o) {
   if (o->precond != GMRES_PRECOND_NONE && o->precision == GMRES_FP64) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
+  if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
   return true;
+}
+
+// Conditions of the persistent schedule (one workgroup of 1024 threads per
+// system, up to kMaxPR rows per thread, H in LDS, 32-bit buffer offsets).
+bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64_t nnz_total, int64_t ld) {
+  if (o->precision != GMRES_MIXED_FP32 || o->precond != GMRES_PRECOND_NONE || o->ortho != GMRES_MGS) return false;
+  if (o->m > kMaxPM) return false;
+  for (int k = 0; k < nsys; ++k)
+    if (n[k] > (int64_t)1024 * kMaxPR) return false;
+  return nnz_total * 8 < ((int64_t)1 << 32) && ld * 8 < ((int64_t)1 << 32);
 }
 
 // Adaptive-CSR row blocks over global rows [r_begin, r_end): up to kBlock
@@ -342,6 +359,12 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   h->ld = row;
   h->nnz = nz;
   h->ntile = (int32_t)tl;
+  {
+    const bool ok = persistent_ok(opt, n, nsys, nz, row);
+    if (opt->batch_schedule == GMRES_SCHEDULE_PERSISTENT && !ok) throw Fail{GMRES_EINVAL};
+    h->persistent = ok && (opt->batch_schedule == GMRES_SCHEDULE_PERSISTENT ||
+                           (opt->batch_schedule == GMRES_SCHEDULE_AUTO && nsys >= 2));
+  }
 
   // ---- global CSR (rows of padding are empty; columns shifted per system)
   h->rp_host.assign(h->ld + 1, 0);
@@ -491,7 +514,17 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   set_row_blocks(h, 2048);
   hip_check(prepare_occupancy(prec));
   hip_check(launch_init_state(a, h->stream));
-  if (opt->autotune) autotune_spmv(h);
+  if (h->persistent) {
+    a.vsys = 1;
+    std::vector<int32_t> ord(nsys);
+    for (int k = 0; k < nsys; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return h->sys[x].n > h->sys[y].n; });
+    h->order = h->alloc<int32_t>(nsys);
+    hip_check(hipMemcpy(h->order, ord.data(), nsys * 4, hipMemcpyHostToDevice));
+    h->counter = h->alloc<int32_t>(1);
+  } else if (opt->autotune) {
+    autotune_spmv(h);
+  }
   h->xs = h->alloc<double>(h->ld);
   h->ys = h->alloc<double>(h->ld);
   hip_check(hipStreamSynchronize(h->stream));
@@ -515,7 +548,17 @@ int finish(gmres_ctx* h, gmres_result* res, int32_t nres, double seconds) {
 
 // The cycle loop shared by single and batch solves; b and x are already in
 // the internal buffers.
+void run_persistent(gmres_ctx* h) {
+  hip_check(launch_batch_persistent(h->a, h->order, h->counter, h->stream));
+  hip_check(hipMemcpyAsync(h->st_host, h->a.st, sizeof(SysState) * h->a.S, hipMemcpyDeviceToHost, h->stream));
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
 void run_cycles(gmres_ctx* h) {
+  if (h->persistent) {
+    run_persistent(h);
+    return;
+  }
   KArgs& a = h->a;
   hip_check(launch_init_state(a, h->stream));
   hip_check(launch_bnorm(a, h->stream));
@@ -558,6 +601,7 @@ void gmres_default_options(gmres_options* o) {
   o->stall_cycles = 3;
   o->use_graph = 1;
   o->autotune = 1;
+  o->batch_schedule = GMRES_SCHEDULE_AUTO;
 }
 
 const char* gmres_strerror(int code) {
@@ -710,11 +754,37 @@ int gmres_batch_solve(gmres_handle hh, const double* const* b, double* const* x,
     hip_check(hipMemcpyAsync((void*)h->xptrs, x, S * sizeof(void*), hipMemcpyHostToDevice, h->stream));
     int64_t maxn = 0;
     for (const System& s : h->sys) maxn = std::max(maxn, s.n);
-    hip_check(launch_gather(h->bptrs, h->a.b, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream));
-    hip_check(launch_gather((const double* const*)h->xptrs, h->a.x, h->a.sys_row0, h->a.sys_n, S, maxn,
-                            h->stream));
-    run_cycles(h);
-    hip_check(launch_scatter(h->a.x, h->xptrs, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream));
+    auto gather = [&]() -> hipError_t {
+      hipError_t e = launch_gather(h->bptrs, h->a.b, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream);
+      if (e == hipSuccess)
+        e = launch_gather((const double* const*)h->xptrs, h->a.x, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream);
+      return e;
+    };
+    auto scatter = [&]() { return launch_scatter(h->a.x, h->xptrs, h->a.sys_row0, h->a.sys_n, S, maxn, h->stream); };
+    if (h->persistent && h->opt.use_graph) {
+      // the whole batch solve is one graph: gather, the persistent kernel, scatter
+      if (!h->pexec) {
+        hipGraph_t g = nullptr;
+        hip_check(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = gather();
+        if (e == hipSuccess) e = launch_batch_persistent(h->a, h->order, h->counter, h->stream);
+        if (e == hipSuccess) e = scatter();
+        const hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          throw Fail{GMRES_EHIP};
+        }
+        e = hipGraphInstantiate(&h->pexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hip_check(e);
+      }
+      hip_check(hipGraphLaunch(h->pexec, h->stream));
+      hip_check(hipMemcpyAsync(h->st_host, h->a.st, sizeof(SysState) * S, hipMemcpyDeviceToHost, h->stream));
+    } else {
+      hip_check(gather());
+      run_cycles(h);
+      hip_check(scatter());
+    }
     hip_check(hipStreamSynchronize(h->stream));
     const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (res) finish(h, res, S, sec);
@@ -874,6 +944,7 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
     gmres_ctx* h = get(hh);
     const KArgs& a = h->a;
     if (j < 0 || j >= a.m || reps < 1 || !avg_ms) return GMRES_EINVAL;
+    if (h->persistent) return GMRES_ESTATE;  // the harness times the device-wide kernels
     const int prec = a.prec;
     const double n = (double)h->nrows, nnz = (double)h->nnz;
     const double sv = (double)vbytes(prec), sw = (double)wbytes(prec), sa = prec == P64 ? 8.0 : 4.0;

@@ -16,6 +16,8 @@ constexpr int kMaxM = 256;
 constexpr int kFinBlock = 1024;  // threads of the per-system finalise kernels
 constexpr int kHistCap = 4096;
 constexpr int kMaxOcc = 8;       // persistent grids of ncu * k workgroups, k = 1..kMaxOcc
+constexpr int kMaxPM = 64;       // persistent batch schedule: restart length limit
+constexpr int kMaxPR = 64;       //   and rows per thread (systems up to 1024 * 64 rows)
 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
 enum Status { RUNNING = 0, CONVERGED = 1, MAXITER = 2, STALLED = 3 };
@@ -76,6 +78,8 @@ struct KArgs {
   int32_t spmv_budget;  // nnz per SpMV row block (streaming mode)
   int32_t xcd_remap;    // map consecutive blocks onto one XCD
   int32_t ncu;          // compute units of the device
+  int32_t vsys;         // basis layout: 0 = column stride ld over all systems,
+                        // 1 = one block of (m+1) padded columns per system (persistent batch)
   // matrix: concatenated systems, global row and column numbering
   const int32_t* rp;
   const int32_t* ci;
@@ -158,6 +162,9 @@ hipError_t launch_gather(const double* const* src, double* dst, const int64_t* r
                          const int32_t* n, int S, int64_t maxn, hipStream_t st);
 hipError_t launch_scatter(const double* src, double* const* dst, const int64_t* row0,
                           const int32_t* n, int S, int64_t maxn, hipStream_t st);
+// One workgroup per system, systems taken from `order` through `counter`
+// (cleared by this call), float32 MGS Arnoldi; basis in layout vsys = 1.
+hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, hipStream_t st);
 // Queries, once per process, how many workgroups of each persistent basis
 // pass of `prec` fit on one CU.  Must run before any graph capture.
 hipError_t prepare_occupancy(int prec);

@@ -1130,6 +1130,14 @@ template <typename TV>
 __global__ void k_decode_column(KArgs a, int sys, int col, double* out) {
   const int64_t row0 = a.sys_row0[sys];
   const int n = a.sys_n[sys];
+  if (a.vsys) {  // normalised float32 columns, one block per system
+    const float* v = static_cast<const float*>(a.V) + (int64_t)(a.m + 1) * row0 +
+                     (int64_t)col * a.sys_nt[sys] * kTile;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+      out[i] = (double)v[i];
+    return;
+  }
   const double sc = a.sc[(int64_t)sys * (a.m + 1) + col];
   const TV* v = col_ptr<TV>(a, col);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;

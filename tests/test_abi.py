@@ -40,6 +40,7 @@ def test_default_options(lib):
     assert (o.m, o.tol, o.max_iters) == (50, 1e-10, 100000)
     assert o.ortho == L.CGSR and o.precision == L.MIXED_FP32 and o.precond == L.PRECOND_NONE
     assert o.restart_improve == 0.0 and o.stall_cycles == 3 and o.use_graph == 1 and o.autotune == 1
+    assert o.batch_schedule == L.SCHEDULE_AUTO
 
 
 def test_strerror(lib):
@@ -56,7 +57,8 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.gmres_create(C.byref(h), 10, 5, None, None, None, C.byref(o), None) == L.EINVAL
     assert lib.gmres_create(None, 10, 5, 1, 1, 1, C.byref(o), None) == L.EINVAL
     for field, bad in [("m", 0), ("m", 257), ("tol", -1.0), ("ortho", 7), ("precision", 9),
-                       ("precond", 5), ("stall_cycles", 0), ("restart_improve", -0.5)]:
+                       ("precond", 5), ("stall_cycles", 0), ("restart_improve", -0.5), ("batch_schedule", 3),
+                       ("batch_schedule", -1)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field

@@ -260,7 +260,7 @@ def test_batch_equals_single_solves_bitwise(precision):
                                                     (45, (1.0, 90.0))]]
     rhs = [P.manufactured_rhs(A, 95, i)[1] for i, A in enumerate(systems)]
     bs = BatchSolver([(A.row_ptr, A.col_idx, A.vals) for A in systems], m=20, ortho="mgs",
-                     precision=precision, autotune=False)
+                     precision=precision, autotune=False, schedule="device_wide")
     xb, infos = bs.solve(rhs)
     bs.close()
     for A, b, x, info in zip(systems, rhs, xb, infos):

@@ -7,8 +7,8 @@
 // update, Hessenberg matrix and rotations): the work vector w lives in
 // registers, R = ceil(n / 1024) rows per thread (n <= 65,536), and each
 // basis vector is kept in LDS between its dot product and its axpy (up to
-// 24 rows per thread), so an MGS step reads v_i once from memory (for n up
-// to 24,576; larger systems re-read the rest) and never streams w; H, the rotations
+// 28 rows per thread), so an MGS step reads v_i once from memory (for n up
+// to 28,672; larger systems re-read the rest) and never streams w; H, the rotations
 // and the least-squares right-hand side live in LDS; the basis lives in
 // HBM in one contiguous block per system.  Every reduction is a fixed-order
 // block sum (per-thread float32 partials, float64 across threads), so a
@@ -25,7 +25,8 @@ namespace {
 
 constexpr int kPB = 1024;        // threads per system
 constexpr int kPW = kPB / 64;    // waves per system
-constexpr int kStage = 24;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
+constexpr int kStage = 28;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
+constexpr int kStageLd = kStage + 1;  // odd row stride: lanes hit distinct banks, one base address
 
 struct PShared {
   double red[2][kPW][2];               // double-buffered wave partials (two sums each)
@@ -34,7 +35,7 @@ struct PShared {
   int ctl[4];
   double dctl[2];
   int sys;
-  float vst[kStage][kPB];              // staged rows of v_i (thread t owns column t)
+  float vst[kPB][kStageLd];            // staged rows of v_i (thread t owns row t)
 };
 
 __device__ __forceinline__ double wsum(double v) {
@@ -264,7 +265,7 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const float v = ldf(vi, t4, (uint32_t)q * kPB * 4u);
-          if (q < kStage) sh.vst[q][t] = v;  // read back by this thread only: no barrier
+          if (q < kStage) sh.vst[t][q] = v;  // read back by this thread only: no barrier
           d += w[q] * v;
           if ((q & 15) == 15) __builtin_amdgcn_sched_barrier(0);  // at most 16 loads in flight
         }
@@ -282,7 +283,7 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
         const float hf = (float)h;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-          w[q] -= hf * (q < kStage ? sh.vst[q][t] : ldf(vi, t4, (uint32_t)q * kPB * 4u));
+          w[q] -= hf * (q < kStage ? sh.vst[t][q] : ldf(vi, t4, (uint32_t)q * kPB * 4u));
           if ((q & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
       }

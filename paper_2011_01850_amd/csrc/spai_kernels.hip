@@ -574,14 +574,24 @@ __global__ void k_enc_bwd_edge(Net a) {
   }
 }
 
-// grad[dst + c] (=, or +=) sum over rows b in order of part[b * stride + src + c]
+// grad[dst + c] (=, or +=) the sum over rows b of part[b * stride + src + c]:
+// a block covers 32 columns with 8 row groups; group g sums the rows
+// b = g mod 8 in order, then the 8 group sums are added in order.
 __global__ void k_reduce(const float* __restrict__ part, int rows, int stride, int src, int count,
                          float* __restrict__ grad, int dst, int accumulate) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= count) return;
+  __shared__ double sh[8][33];
+  const int cl = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const int c = blockIdx.x * 32 + cl;
   double s = 0.0;
-  for (int b = 0; b < rows; ++b) s += (double)part[(size_t)b * stride + src + c];
-  grad[dst + c] = accumulate ? grad[dst + c] + (float)s : (float)s;
+  if (c < count)
+    for (int b = g; b < rows; b += 8) s += (double)part[(size_t)b * stride + src + c];
+  sh[g][cl] = s;
+  __syncthreads();
+  if (g == 0 && c < count) {
+    double t = 0.0;
+    for (int q = 0; q < 8; ++q) t += sh[q][cl];
+    grad[dst + c] = accumulate ? grad[dst + c] + (float)t : (float)t;
+  }
 }
 
 __global__ void k_flag_clear(int32_t* flag) { flag[0] = 0; }
@@ -672,7 +682,7 @@ hipError_t launch_backward(const Net& a, const uint16_t* prm, const float* dm, f
   const int gm = mfma_blocks(a, ncu);
   const int acc = accumulate ? 1 : 0;
   auto reduce = [&](int rows, int stride, int src, int count, int dst) {
-    hipLaunchKernelGGL(k_reduce, dim3(grid_for(count)), dim3(256), 0, st, a.part, rows, stride, src, count, grad,
+    hipLaunchKernelGGL(k_reduce, dim3((count + 31) / 32), dim3(256), 0, st, a.part, rows, stride, src, count, grad,
                        dst, acc);
   };
   hipLaunchKernelGGL(k_ds, dim3(grid_for(a.nnz)), dim3(256), 0, st, a, dm);

@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by what it reads
 # for a plain 1 GiB device copy: x2.0 and x1.0), averaged over the roofline
 # launches.  Valid only for the kernel source they were taken from.
-TRAFFIC = {"bytes_per_launch": 346204006, "kernel_source_sha256": "06cb5d35e01ada360755015aa7968f1beb9fceb7ec9f8a3392699412cca2ca0a"}
+TRAFFIC = {"bytes_per_launch": 347550366, "kernel_source_sha256": "49130a9db5dbdd05415d348ca241c2ff4736334144f72ee11f8254b4e9a528b6"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 

@@ -95,6 +95,10 @@ typedef struct {
   int32_t use_graph;        /* 1: capture one restart cycle as a hipGraph and replay it */
   int32_t autotune;         /* 1: time SpMV tile variants at create time and keep the fastest */
   int32_t batch_schedule;   /* GMRES_SCHEDULE_*: how the systems of a handle share the GPU */
+  int32_t spmv_block_nnz;   /* 0: SpMV row blocks chosen by the autotuner (autotune = 1) or 2048;
+                               else a fixed non-zero budget per row block, a multiple of 64 in
+                               [64, 8192].  Results do not depend on it: every row is summed in
+                               one order fixed by its length. */
 } gmres_options;
 
 typedef struct {
@@ -110,7 +114,7 @@ typedef struct {
 
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 3,
- * use_graph = 1, autotune = 1, batch_schedule = AUTO. */
+ * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).

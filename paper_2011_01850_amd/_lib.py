@@ -34,6 +34,7 @@ class Options(C.Structure):
         ("use_graph", C.c_int32),
         ("autotune", C.c_int32),
         ("batch_schedule", C.c_int32),
+        ("spmv_block_nnz", C.c_int32),
     ]
 
 

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "gmres.h"
@@ -36,7 +37,20 @@ struct System {
   int64_t n = 0, nnz = 0;
   int64_t row0 = 0;  // first global row
   int64_t nz0 = 0;   // first global non-zero
-  int32_t nt = 0, t0 = 0, nrb = 0, rb0 = 0;  // tiles, first tile, SpMV row blocks
+  int32_t nt = 0, t0 = 0;  // tiles, first tile
+};
+
+// non-zero budgets per SpMV row block that the autotuner times
+constexpr int kTuneBudgets[] = {1024, 2048, 4096};
+
+// SpMV row blocks for one non-zero budget: host tables, uploaded on first use.
+struct RowBlocks {
+  int budget = 0;
+  std::vector<int32_t> rb;     // first row of each block, then the sentinel ld
+  std::vector<int32_t> sys;    // system of each block
+  std::vector<int32_t> lanes;  // max row_lanes over the block's rows
+  std::vector<int32_t> rb0, nrb;  // per system: first block, block count
+  int32_t *d_rb = nullptr, *d_sys = nullptr, *d_lanes = nullptr, *d_rb0 = nullptr, *d_nrb = nullptr;
 };
 
 }  // namespace
@@ -49,6 +63,7 @@ struct gmres_ctx {
   int64_t ld = 0, nnz = 0, nrows = 0;
   int32_t ntile = 0, nrb = 0;
   std::vector<int32_t> rp_host;  // global row pointer (ld + 1)
+  std::vector<std::unique_ptr<RowBlocks>> rbt;  // row-block tables built so far
   std::vector<void*> allocs;
   size_t bytes = 0;
   KArgs a{};
@@ -142,6 +157,8 @@ bool valid_options(const gmres_options* o) {
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
+  if (o->spmv_block_nnz != 0 && (o->spmv_block_nnz < 64 || o->spmv_block_nnz > 8192 || o->spmv_block_nnz % 64))
+    return false;
   return true;
 }
 
@@ -156,21 +173,25 @@ bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64
 }
 
 // Adaptive-CSR row blocks over global rows [r_begin, r_end): up to kBlock
-// rows whose non-zeros fit `budget`, or a single longer row.
+// rows whose non-zeros fit `budget`, or a single longer row.  `lanes` gets
+// the lane-group width of each block: row_lanes of its longest row
+// (row_lanes grows with the length).
 void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r_end, int budget,
-                      std::vector<int32_t>& rb) {
+                      std::vector<int32_t>& rb, std::vector<int32_t>* lanes) {
   int64_t r = r_begin;
   while (r < r_end) {
     rb.push_back((int32_t)r);
-    int64_t nz = 0, rows = 0;
+    int64_t nz = 0, rows = 0, maxlen = 0;
     while (r < r_end && rows < kBlock) {
       const int64_t len = (int64_t)rp[r + 1] - rp[r];
       if (rows > 0 && nz + len > budget) break;
       nz += len;
+      maxlen = std::max(maxlen, len);
       ++rows;
       ++r;
       if (nz > budget) break;
     }
+    if (lanes) lanes->push_back(row_lanes((int)std::min<int64_t>(maxlen, INT32_MAX)));
   }
 }
 
@@ -180,37 +201,82 @@ int32_t* upload32(gmres_ctx* h, const std::vector<int32_t>& v) {
   return d;
 }
 
+// Host part only (reads h->rp_host and h->sys): safe to run for several
+// budgets at once.
+void fill_row_blocks(const gmres_ctx* h, RowBlocks& t) {
+  t.rb.clear();
+  for (size_t k = 0; k < h->sys.size(); ++k) {
+    const System& s = h->sys[k];
+    const size_t before = t.rb.size();
+    build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, t.budget, t.rb, &t.lanes);
+    t.rb0.push_back((int32_t)before);
+    t.nrb.push_back((int32_t)(t.rb.size() - before));
+    t.sys.insert(t.sys.end(), t.rb.size() - before, (int32_t)k);
+  }
+  // sentinel; no block starts in the padding.  The last block of each system
+  // ends at the next block start (or ld): pad rows are empty, so that is exact.
+  t.rb.push_back((int32_t)h->ld);
+}
+
+// Builds the tables of every budget in `budgets` not built yet, in parallel.
+void prepare_row_blocks(gmres_ctx* h, const std::vector<int>& budgets) {
+  std::vector<RowBlocks*> todo;
+  for (int b : budgets) {
+    bool have = false;
+    for (const auto& t : h->rbt) have = have || t->budget == b;
+    for (const RowBlocks* t : todo) have = have || t->budget == b;
+    if (have) continue;
+    h->rbt.push_back(std::make_unique<RowBlocks>());
+    h->rbt.back()->budget = b;
+    todo.push_back(h->rbt.back().get());
+  }
+  std::vector<std::thread> th;
+  std::vector<char> failed(todo.size(), 0);
+  for (size_t i = 1; i < todo.size(); ++i)
+    th.emplace_back([h, &todo, &failed, i] {
+      try {
+        fill_row_blocks(h, *todo[i]);
+      } catch (...) {
+        failed[i] = 1;
+      }
+    });
+  if (!todo.empty()) {
+    try {
+      fill_row_blocks(h, *todo[0]);
+    } catch (...) {
+      failed[0] = 1;
+    }
+  }
+  for (auto& t : th) t.join();
+  for (char f : failed)
+    if (f) throw Fail{GMRES_ENOMEM};
+}
+
+const RowBlocks& row_blocks(gmres_ctx* h, int budget) {
+  prepare_row_blocks(h, {budget});
+  for (const auto& t : h->rbt)
+    if (t->budget == budget) return *t;
+  throw Fail{GMRES_EINVAL};
+}
+
 void set_row_blocks(gmres_ctx* h, int budget) {
-  std::vector<int32_t> rb, rb_sys;
-  for (size_t k = 0; k < h->sys.size(); ++k) {
-    System& s = h->sys[k];
-    const size_t before = rb.size();
-    build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, budget, rb);
-    s.rb0 = (int32_t)before;
-    s.nrb = (int32_t)(rb.size() - before);
-    rb_sys.insert(rb_sys.end(), rb.size() - before, (int32_t)k);
+  prepare_row_blocks(h, {budget});
+  RowBlocks* t = nullptr;
+  for (const auto& p : h->rbt)
+    if (p->budget == budget) t = p.get();
+  if (!t->d_rb) {
+    t->d_rb = upload32(h, t->rb);
+    t->d_sys = upload32(h, t->sys);
+    t->d_lanes = upload32(h, t->lanes);
+    t->d_rb0 = upload32(h, t->rb0);
+    t->d_nrb = upload32(h, t->nrb);
   }
-  rb.push_back((int32_t)h->ld);  // sentinel; no block starts in the padding
-  // the last block of each system must end at that system's last real row:
-  // pad rows are empty, so ending at the next block start (or ld) is exact.
-  h->nrb = (int32_t)rb_sys.size();
-  int32_t* d_rb = h->alloc<int32_t>(rb.size());
-  int32_t* d_rbs = h->alloc<int32_t>(std::max<size_t>(rb_sys.size(), 1));
-  hip_check(hipMemcpy(d_rb, rb.data(), rb.size() * 4, hipMemcpyHostToDevice));
-  if (!rb_sys.empty()) hip_check(hipMemcpy(d_rbs, rb_sys.data(), rb_sys.size() * 4, hipMemcpyHostToDevice));
-  std::vector<int32_t> rb0(h->sys.size()), nrb(h->sys.size());
-  for (size_t k = 0; k < h->sys.size(); ++k) {
-    rb0[k] = h->sys[k].rb0;
-    nrb[k] = h->sys[k].nrb;
-  }
-  int32_t* d_rb0 = h->alloc<int32_t>(rb0.size());
-  int32_t* d_nrb = h->alloc<int32_t>(nrb.size());
-  hip_check(hipMemcpy(d_rb0, rb0.data(), rb0.size() * 4, hipMemcpyHostToDevice));
-  hip_check(hipMemcpy(d_nrb, nrb.data(), nrb.size() * 4, hipMemcpyHostToDevice));
-  h->a.rb = d_rb;
-  h->a.rb_sys = d_rbs;
-  h->a.sys_rb0 = d_rb0;
-  h->a.sys_nrb = d_nrb;
+  h->nrb = (int32_t)t->sys.size();
+  h->a.rb = t->d_rb;
+  h->a.rb_sys = t->d_sys;
+  h->a.rb_lanes = t->d_lanes;
+  h->a.sys_rb0 = t->d_rb0;
+  h->a.sys_nrb = t->d_nrb;
   h->a.nrb = h->nrb;
   h->a.spmv_budget = budget;
 }
@@ -299,13 +365,12 @@ void build_graph(gmres_ctx* h) {
 
 // Times the Arnoldi SpMV for a few row-block budgets and keeps the fastest.
 void autotune_spmv(gmres_ctx* h) {
-  const int cands[] = {1024, 2048, 4096};
   float best = 1e30f;
   int best_budget = h->a.spmv_budget, best_remap = h->a.xcd_remap;
   // exercise with a column of the zero-initialised basis; force the kernel on
   hip_check(launch_set_force(h->a, 1, h->stream));
   const int reps = 5;
-  for (int budget : cands) {
+  for (int budget : kTuneBudgets) {
     set_row_blocks(h, budget);
     for (int remap = 0; remap <= 1; ++remap) {
       h->a.xcd_remap = remap;
@@ -457,8 +522,10 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   }
   a.x = h->alloc<double>(h->ld);
   a.b = h->alloc<double>(h->ld);
+  a.zres = h->alloc<double>(h->ld);  // padding rows stay zero
   hip_check(hipMemsetAsync(a.x, 0, h->ld * 8, h->stream));
   hip_check(hipMemsetAsync(a.b, 0, h->ld * 8, h->stream));
+  hip_check(hipMemsetAsync(a.zres, 0, h->ld * 8, h->stream));
   a.st = h->alloc<SysState>(nsys);
   a.H = h->alloc<double>(nsys * M1 * m);
   a.Hbar = h->alloc<double>(nsys * M1 * m);
@@ -490,11 +557,17 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     hip_check(hipMemsetAsync(d, 0, (h->nnz + 4) * 4, h->stream));
     a.mval = d;
   }
-  // ---- partials sized for the largest grid any budget candidate can give
+  // ---- SpMV row blocks of every budget this handle may use (the autotuner's
+  // candidates, else the fixed one), built in parallel on the host
+  const bool tune = !h->persistent && opt->autotune && opt->spmv_block_nnz == 0;
+  const int fixed_budget = opt->spmv_block_nnz > 0 ? opt->spmv_block_nnz : 2048;
+  const std::vector<int> budgets = tune ? std::vector<int>(std::begin(kTuneBudgets), std::end(kTuneBudgets))
+                                        : std::vector<int>{fixed_budget};
+  prepare_row_blocks(h, budgets);
+  // ---- partials sized for the largest grid any of those budgets gives
   {
-    std::vector<int32_t> rbtmp;
-    for (const System& s : h->sys) build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, 1024, rbtmp);
-    int64_t maxrows = std::max<int64_t>((int64_t)rbtmp.size(), h->ntile);
+    int64_t maxrows = h->ntile;
+    for (int b : budgets) maxrows = std::max<int64_t>(maxrows, (int64_t)row_blocks(h, b).sys.size());
     for (int k = 1; k <= kMaxOcc; ++k) {
       a.seg[k - 1] = make_split(h, (int)std::min<int64_t>((int64_t)k * a.ncu, h->ntile));
       maxrows = std::max<int64_t>(maxrows, a.seg[k - 1].nseg);
@@ -511,7 +584,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     hip_check(hipStreamSynchronize(h->stream));
     if (hb) throw Fail{GMRES_EINVAL};
   }
-  set_row_blocks(h, 2048);
+  set_row_blocks(h, tune ? 2048 : fixed_budget);
   hip_check(prepare_occupancy(prec));
   hip_check(launch_init_state(a, h->stream));
   if (h->persistent) {
@@ -522,7 +595,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     h->order = h->alloc<int32_t>(nsys);
     hip_check(hipMemcpy(h->order, ord.data(), nsys * 4, hipMemcpyHostToDevice));
     h->counter = h->alloc<int32_t>(1);
-  } else if (opt->autotune) {
+  } else if (tune) {
     autotune_spmv(h);
   }
   h->xs = h->alloc<double>(h->ld);
@@ -602,6 +675,7 @@ void gmres_default_options(gmres_options* o) {
   o->use_graph = 1;
   o->autotune = 1;
   o->batch_schedule = GMRES_SCHEDULE_AUTO;
+  o->spmv_block_nnz = 0;
 }
 
 const char* gmres_strerror(int code) {

@@ -19,6 +19,19 @@ constexpr int kMaxOcc = 8;       // persistent grids of ncu * k workgroups, k = 
 constexpr int kMaxPM = 64;       // persistent batch schedule: restart length limit
 constexpr int kMaxPR = 64;       //   and rows per thread (systems up to 1024 * 64 rows)
 
+// SpMV row sums follow one canonical order that depends only on the row's
+// length len: T = row_lanes(len) partial sums, partial l adding products
+// l, l + T, l + 2T, ... in turn, then the T partials combined by a fixed
+// butterfly.  T doubles from 1 while it stays <= 16 and every partial still
+// gets at least kRowLanePer products.
+constexpr int kRowLaneMax = 16;
+constexpr int kRowLanePer = 4;
+__host__ __device__ inline int row_lanes(int len) {
+  int T = 1;
+  while (T < kRowLaneMax && 2 * T * kRowLanePer <= len) T *= 2;
+  return T;
+}
+
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
 enum Status { RUNNING = 0, CONVERGED = 1, MAXITER = 2, STALLED = 3 };
 
@@ -89,6 +102,7 @@ struct KArgs {
   const float* dinv;   // Jacobi: 1 / a_ii
   const int32_t* rb;       // row-block first rows [nrb + 1]
   const int32_t* rb_sys;   // system of each row block
+  const int32_t* rb_lanes; // lanes per row of each row block: max row_lanes over its rows
   const int32_t* sys_rb0;  // first row block of each system
   const int32_t* sys_nrb;
   const int32_t* tile_sys;  // system of each tile
@@ -103,6 +117,7 @@ struct KArgs {
   void* w;        // work vector: double (P64) or float
   double* x;      // iterate
   double* b;      // right-hand side
+  double* zres;   // float64 restart residual (ld rows)
   // scratch: column-major partial tables (quantity q of row k at q * rows + k)
   double* part;
   double* part2;  // second table: MGS alternates between the two

@@ -363,7 +363,12 @@ enum SpmvMode { SM_ARNOLDI = 0, SM_PRECOND = 1, SM_AZ = 2, SM_RESID = 3, SM_PLAI
 
 // Adaptive CSR: a row block is either up to 256 rows whose non-zeros fit
 // the streaming budget (products staged in LDS, each row reduced by a
-// power-of-two group of lanes) or one long row reduced by the whole block.
+// power-of-two group of lanes) or one long row staged by the whole block.
+//
+// Every row is summed in the canonical order of row_lanes (lane l of T adds
+// the products l, l + T, ... in turn, then a fixed butterfly), so the
+// row-block layout (which the autotuner picks) never changes a result.
+
 template <typename TA, typename TX, typename TY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__ vals,
                                                  const TX* __restrict__ x, TY* __restrict__ y,
@@ -396,15 +401,26 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
       zsq += z * z;
       zmax = fmax(zmax, fabs(z));
       y[r] = (TY)z;
+      if (MODE == SM_RESID) a.zres[r] = z;
     } else {
       y[r] = (TY)(acc * scale);
     }
   };
-  if (p1 - p0 > a.spmv_budget) {  // one long row
+  if (p1 - p0 > a.spmv_budget) {  // one long row: staged chunk by chunk, lanes 0..T-1 of wave 0 add
+    const int T = row_lanes(p1 - p0);
     ACC acc = (ACC)0;
-    for (int k = p0 + t; k < p1; k += kBlock) acc += (ACC)vals[k] * (ACC)ldv(x[a.ci[k]]);
-    acc = block_sum(acc);
-    if (t == 0) emit(r0, acc);
+    for (int c0 = p0; c0 < p1; c0 += a.spmv_budget) {  // chunks are multiples of T long
+      const int c1 = min(p1, c0 + a.spmv_budget);
+      for (int k = c0 + t; k < c1; k += kBlock) prod[k - c0] = (ACC)vals[k] * (ACC)ldv(x[a.ci[k]]);
+      __syncthreads();
+      if (t < T)
+        for (int k = c0 + t; k < c1; k += T) acc += prod[k - c0];
+      __syncthreads();
+    }
+    if (t < 64) {
+      for (int o = T >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (t == 0) emit(r0, acc);
+    }
   } else {
     // products staged in LDS; indices and values are read as aligned groups
     // of four (16-byte index loads; the matrix arrays carry a zero pad of
@@ -429,26 +445,38 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
       }
     }
     __syncthreads();
-    const int nr = r1 - r0;
-    int tpr = 1;
-    while (tpr < 64 && tpr * 2 * nr <= kBlock) tpr *= 2;
+    // groups of tpr lanes, tpr = the widest canonical row of the block; lanes
+    // past a row's own T hold zero, which the first butterfly steps add
+    const int tpr = a.rb_lanes[blk];
     const int g = t / tpr, l = t % tpr, ng = kBlock / tpr;
     for (int r = r0 + g; r < r1; r += ng) {
       ACC acc = (ACC)0;
-      const int e = a.rp[r + 1];
-      for (int k = a.rp[r] + l; k < e; k += tpr) acc += prod[k - p0];
+      const int b = a.rp[r], e = a.rp[r + 1];
+      const int T = row_lanes(e - b);
+      if (l < T)
+        for (int k = b + l; k < e; k += T) acc += prod[k - p0];
       for (int o = tpr >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
       if (l == 0) emit(r, acc);
     }
   }
-  if (MODE == SM_RESID || MODE == SM_RESID_PLAIN) {
+  if (MODE == SM_RESID_PLAIN) {
     zsq = block_sum(zsq);
-    if (MODE == SM_RESID) zmax = block_max(zmax);
-    if (t == 0) {
-      a.part[blk] = zsq;
-      if (MODE == SM_RESID) a.part[(int64_t)a.nrb + blk] = zmax;
-    }
+    if (t == 0) a.part[blk] = zsq;
+  }
+}
 
+// ||z||^2 and max|z| of the float64 restart residual per 256-row tile (a
+// fixed tree per tile, so the norm does not depend on the row blocks).
+__global__ __launch_bounds__(kBlock) void k_tile_norm(KArgs a) {
+  const int s = a.tile_sys[blockIdx.x];
+  const SysState& S = a.st[s];
+  if (S.status != RUNNING && !S.force) return;
+  const double z = a.zres[(int64_t)blockIdx.x * kTile + threadIdx.x];
+  const double sq = block_sum(z * z);
+  const double mx = block_max(fabs(z));
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = sq;
+    a.part[(int64_t)a.ntile + blockIdx.x] = mx;
   }
 }
 
@@ -1264,8 +1292,9 @@ hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {
                        a.a64, a.x, (float*)a.w, a.b, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !with_fin) return e;
-  hipLaunchKernelGGL((k_fin<FIN_RESID>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.nrb, a.sys_rb0,
-                     a.sys_nrb, 0);
+  hipLaunchKernelGGL(k_tile_norm, dim3(a.ntile), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_fin<FIN_RESID>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.ntile, a.sys_t0,
+                     a.sys_nt, 0);
   return hipGetLastError();
 }
 

@@ -254,6 +254,32 @@ def test_deterministic_and_graph_equals_stream():
     assert all(np.array_equal(xs[0][0], x) and xs[0][1] == it for x, it in xs[1:])
 
 
+@pytest.mark.parametrize("case", ["convdiff2d", "powerlaw"])
+def test_results_do_not_depend_on_spmv_row_blocks(case):
+    # every row is summed in one order fixed by its length, whichever row
+    # blocks the SpMV uses (short rows inside a block, long rows split across
+    # chunks of the block budget), and the residual norm is reduced per
+    # fixed tile: solves with different budgets agree bit for bit.
+    if case == "convdiff2d":
+        pr = P.c1_convdiff2d(40)
+        A, b, kw = pr.A, pr.b, dict(m=30, ortho="cgsr", precision="fp32")
+    else:
+        A = P.powerlaw(30_000, 3, 5)  # rows up to 2000 long: longer than most budgets
+        b = P.manufactured_rhs(A, 3, 5)[1]
+        kw = dict(m=30, ortho="cgsr", precision="fp16", tol=1e-9)
+    runs = []
+    for budget, tune in [(64, False), (256, False), (4096, False), (8192, False), (0, True), (0, False)]:
+        s = _solver(A, spmv_block_nnz=budget, autotune=tune, **kw)
+        x, info = s.solve(b)
+        s.close()
+        runs.append((budget, tune, x.cpu().numpy(), info["iters"], info["rel_residual"]))
+    x0, it0, rel0 = runs[0][2], runs[0][3], runs[0][4]
+    assert rel0 <= kw.get("tol", 1e-10)
+    for budget, tune, x, it, rel in runs[1:]:
+        assert it == it0 and rel == rel0, (budget, tune, it, it0)
+        assert np.array_equal(x, x0), (budget, tune)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
 def test_batch_equals_single_solves_bitwise(precision):
     systems = [P.convdiff(N, beta) for N, beta in [(33, (10.0, 3.0)), (20, (0.0, 0.0)), (64, (80.0, 40.0)),

@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by what it reads
 # for a plain 1 GiB device copy: x2.0 and x1.0), averaged over the roofline
 # launches.  Valid only for the kernel source they were taken from.
-TRAFFIC = {"bytes_per_launch": 347550366, "kernel_source_sha256": "49130a9db5dbdd05415d348ca241c2ff4736334144f72ee11f8254b4e9a528b6"}
+TRAFFIC = {"bytes_per_launch": 346213450, "kernel_source_sha256": "aad90474fcdaaa4835483112dc6a5459922b704ae122df20bc831ab0bbe942ce"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 
@@ -82,13 +82,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps, warmup):
+def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps, warmup, stall_cycles=10):
     rp, ci, va = A_dev
     times, infos = [], []
     for it in range(warmup + steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s = Solver(rp, ci, va, m=m, ortho=ortho, precision=precision, tol=1e-10, max_iters=100_000)
+        s = Solver(rp, ci, va, m=m, ortho=ortho, precision=precision, tol=1e-10, max_iters=100_000,
+                   stall_cycles=stall_cycles)
         x, info = s.solve(b_dev)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -261,7 +262,7 @@ def bench_powerlaw(args):
     import problems as P
     from paper_2011_01850_amd import Solver
 
-    value_mode = args.precision or "bf16"
+    value_mode = args.precision or "fp16"
     m = 30
     log("generating the power-law system n = 1e6 ...")
     pr = P.c3_powerlaw()
@@ -271,9 +272,13 @@ def bench_powerlaw(args):
     torch.cuda.synchronize()
     log(f"n = {A.n:,}, nnz = {A.nnz:,}; CGSR GMRES({m})")
     modes, kern = {}, {}
+    # the bfloat16 basis makes the per-cycle progress noisy on this matrix
+    # (dozens of cycles can pass between new lowest residuals), so the
+    # no-progress stop is set far out for every mode
+    stall = 1000
     for mode in ["fp64", "fp32", "bf16", "fp16"]:
         t, inf, (s, x) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, mode,
-                                          args.steps, args.warmup)
+                                          args.steps, args.warmup, stall_cycles=stall)
         xs = x.cpu().numpy()
         fwd = float(np.linalg.norm(xs - pr.x_true) / np.linalg.norm(pr.x_true))
         modes[mode] = _mode_summary(t, inf, fwd, s.memory_bytes())
@@ -294,7 +299,8 @@ def bench_powerlaw(args):
         "data": "synthetic",
         "config": {"workload": f"power-law random sparse n={A.n}, nnz={A.nnz} (row lengths alpha=2.1, mean 20, "
                                f"max 2000, a_ii = 1.2 sum|a_ij|), GMRES({m}) {args.ortho.upper()}, {value_mode} "
-                               f"basis, fp32 arithmetic, fp64 residual/update, tol 1e-10, time incl. setup",
+                               f"basis, fp32 arithmetic, fp64 residual/update, tol 1e-10, time incl. setup, "
+                               f"stall stop after {stall} cycles without a new lowest residual",
                    "n": A.n, "nnz": A.nnz, "m": m, "ortho": args.ortho, "precision": value_mode},
         "modes": modes,
         "kernels_at_j_last": kern,

@@ -91,7 +91,8 @@ typedef struct {
   int32_t precond;          /* GMRES_PRECOND_* */
   double restart_improve;   /* 0 = off; else end a cycle once |s_{j+1}| <= restart_improve * beta
                                (the improvement trigger of the restart-strategy study) */
-  int32_t stall_cycles;     /* STALLED after this many cycles in a row that do not lower beta */
+  int32_t stall_cycles;     /* STALLED after this many cycles in a row that do not lower the best
+                               restart residual so far (a 2-byte basis makes single cycles noisy) */
   int32_t use_graph;        /* 1: capture one restart cycle as a hipGraph and replay it */
   int32_t autotune;         /* 1: time SpMV tile variants at create time and keep the fastest */
   int32_t batch_schedule;   /* GMRES_SCHEDULE_*: how the systems of a handle share the GPU */
@@ -113,7 +114,7 @@ typedef struct {
 } gmres_result;
 
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
- * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 3,
+ * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0. */
 void gmres_default_options(gmres_options* opt);
 

@@ -216,7 +216,7 @@ def _cast(v, precision):
 
 
 def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
-          precision="fp64", precond=None, restart_improve=0.0, stall_cycles=3,
+          precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
           fallback=True, record=False, residual_fp32=False, update_fp32=False):
     """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
 

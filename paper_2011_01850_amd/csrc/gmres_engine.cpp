@@ -671,7 +671,7 @@ void gmres_default_options(gmres_options* o) {
   o->precision = GMRES_MIXED_FP32;
   o->precond = GMRES_PRECOND_NONE;
   o->restart_improve = 0.0;
-  o->stall_cycles = 3;
+  o->stall_cycles = 10;
   o->use_graph = 1;
   o->autotune = 1;
   o->batch_schedule = GMRES_SCHEDULE_AUTO;

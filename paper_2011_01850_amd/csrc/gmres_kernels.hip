@@ -507,6 +507,29 @@ template <>
 __device__ __forceinline__ f16_t bload<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
 }
+// The same loads with the non-temporal hint (cache policy bit 1 on gfx950):
+// used by the last pass of a CGSR step, whose basis columns are not read
+// again before the next step's first pass, so they need not displace the
+// rows the next passes will re-read from the memory-side cache.
+template <typename T>
+__device__ __forceinline__ T bload_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff);
+template <>
+__device__ __forceinline__ float bload_nt<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 2));
+}
+template <>
+__device__ __forceinline__ double bload_nt<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, 2);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
+template <>
+__device__ __forceinline__ bf16_t bload_nt<bf16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return bf16_t{(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, 0, 2)};
+}
+template <>
+__device__ __forceinline__ f16_t bload_nt<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, 0, 2));
+}
 // Resource over basis columns [0, ncols): a tile load of a column >= ncols
 // is pointed at column ncols, which lies past the range and reads zero, so
 // tiles of L >= ncols columns need no per-column guards.
@@ -726,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
       uint32_t so = 0;
 #pragma unroll
       for (int q = 0; q < L; ++q) {
-        v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
+        v[q] = (ACC)ldv(bload_nt<TV>(rs, voff + so));
         if (q < ncol) so += cs;
       }
       ACC wr = (ACC)w[r];

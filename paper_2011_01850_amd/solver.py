@@ -53,7 +53,7 @@ class Solver:
     """Restarted GMRES(m) for one sparse system A x = b on the current GPU."""
 
     def __init__(self, row_ptr, col_idx, vals, m=50, tol=1e-10, ortho="cgsr", precision="fp32",
-                 precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=3,
+                 precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0):
         torch = _torch()
         self._torch = torch
@@ -189,7 +189,7 @@ class BatchSolver:
     """Many independent systems advanced together by every kernel launch."""
 
     def __init__(self, systems, m=40, tol=1e-10, ortho="mgs", precision="fp32", precond="none",
-                 max_iters=100_000, restart_improve=0.0, stall_cycles=3, use_graph=True, autotune=True,
+                 max_iters=100_000, restart_improve=0.0, stall_cycles=10, use_graph=True, autotune=True,
                  schedule="auto", spmv_block_nnz=0):
         torch = _torch()
         self._torch = torch

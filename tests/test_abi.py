@@ -39,7 +39,7 @@ def test_default_options(lib):
     o = L.default_options()
     assert (o.m, o.tol, o.max_iters) == (50, 1e-10, 100000)
     assert o.ortho == L.CGSR and o.precision == L.MIXED_FP32 and o.precond == L.PRECOND_NONE
-    assert o.restart_improve == 0.0 and o.stall_cycles == 3 and o.use_graph == 1 and o.autotune == 1
+    assert o.restart_improve == 0.0 and o.stall_cycles == 10 and o.use_graph == 1 and o.autotune == 1
     assert o.batch_schedule == L.SCHEDULE_AUTO and o.spmv_block_nnz == 0
 
 

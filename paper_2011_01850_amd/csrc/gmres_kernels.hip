@@ -530,6 +530,35 @@ template <>
 __device__ __forceinline__ f16_t bload_nt<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, 0, 2));
 }
+// Memory-side cache policy of the first two CGSR passes.  Each workgroup
+// walks its own tile range, and the next pass walks it the other way, so
+// only the last tiles a pass touches are still cached when the next pass
+// starts.  A pass over B bytes of basis keeps (with ordinary loads) the last
+// kMallKeep / B of every range; the tiles before them would be evicted
+// before the next pass reaches them, so they are read non-temporally.
+constexpr uint64_t kMallKeep = 192ull << 20;
+
+// (2-byte bases: never split, which keeps their 64-column tile free of
+// spills under the 128-register cap.)
+template <typename TV>
+__device__ __forceinline__ int nt_tiles(int nt, uint64_t pass_bytes) {
+  if (sizeof(TV) == 2 || pass_bytes <= kMallKeep) return 0;
+  return nt - (int)(((uint64_t)nt * kMallKeep + pass_bytes - 1) / pass_bytes);
+}
+
+// One tile of basis loads: column q at byte offset voff + q * cs (columns
+// past ncol repeat the last offset step, reading zero past the resource).
+template <typename TV, int L, bool kNT, typename ACC>
+__device__ __forceinline__ void load_tile(ACC (&v)[L], __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t cs,
+                                          int ncol) {
+  uint32_t so = 0;
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    v[q] = (ACC)ldv(kNT ? bload_nt<TV>(rs, voff + so) : bload<TV>(rs, voff + so, 0));
+    if (q < ncol) so += cs;
+  }
+}
+
 // Resource over basis columns [0, ncols): a tile load of a column >= ncols
 // is pointed at column ncols, which lies past the range and reads zero, so
 // tiles of L >= ncols columns need no per-column guards.
@@ -597,6 +626,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
   for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
     if (!gated(a, sg.seg_sys[k])) continue;
     const int nt = sg.seg_nt[k];
+    const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0, ww = (ACC)0;
 #pragma unroll 1
     for (int u = 0; u < nt; ++u) {
@@ -608,12 +638,12 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
       const ACC wr = (ACC)w[r];
       ww += wr * wr;
       ACC p[L];
-      uint32_t so = 0;
+      if (sizeof(TV) != 2 && u < nfirst)
+        load_tile<TV, L, true>(p, rs, voff, cs, ncol);
+      else
+        load_tile<TV, L, false>(p, rs, voff, cs, ncol);
 #pragma unroll
-      for (int q = 0; q < L; ++q) {
-        p[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0)) * wr;
-        if (q < ncol) so += cs;
-      }
+      for (int q = 0; q < L; ++q) p[q] *= wr;
       colsum += reduce_scatter<L>(p, lane);
     }
     store_colsums<L>(a.part, sg.nseg, k, col0, ncol, colsum);
@@ -644,6 +674,7 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
     __syncthreads();
     const int nt = sg.seg_nt[k];
+    const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0;
 #pragma unroll 1
     for (int u = 0; u < nt; ++u) {
@@ -651,12 +682,10 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
       const int64_t r = tile_row(sg, k, u, rev);
       const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
       ACC v[L];
-      uint32_t so = 0;
-#pragma unroll
-      for (int q = 0; q < L; ++q) {
-        v[q] = (ACC)ldv(bload<TV>(rs, voff + so, 0));
-        if (q < ncol) so += cs;
-      }
+      if (sizeof(TV) != 2 && u < nfirst)
+        load_tile<TV, L, true>(v, rs, voff, cs, ncol);
+      else
+        load_tile<TV, L, false>(v, rs, voff, cs, ncol);
       ACC wr = (ACC)w[r];
 #pragma unroll
       for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];

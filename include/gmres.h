@@ -55,6 +55,20 @@ enum {
   GMRES_MIXED_FP16 = 3  /* float32 arithmetic, basis stored as IEEE half */
 };
 
+/* gmres_options.a_storage: how the handle keeps A's values.
+ * COPY:  the float64 values plus a float32 copy for the Arnoldi SpMV
+ *        (12 bytes per non-zero in the mixed modes, as in the numerics
+ *        section of the paper, which notes that the matrix is stored twice).
+ * SPLIT: the float64 values split into two arrays of 32-bit words, high
+ *        words and low words (8 bytes per non-zero; the storage the paper
+ *        suggests as an improvement, after the modular-precision format it
+ *        cites).  The float64 residual SpMV reads both; the Arnoldi SpMV of
+ *        the mixed modes reads the high words only, i.e. each value truncated
+ *        to 20 significand bits (relative error below 2^-20), converted
+ *        exactly to float32.  Not available with the persistent batch
+ *        schedule. */
+enum { GMRES_A_COPY = 0, GMRES_A_SPLIT = 1 };
+
 /* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y) */
 enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2 };
 
@@ -100,6 +114,7 @@ typedef struct {
                                else a fixed non-zero budget per row block, a multiple of 64 in
                                [64, 8192].  Results do not depend on it: every row is summed in
                                one order fixed by its length. */
+  int32_t a_storage;        /* GMRES_A_COPY or GMRES_A_SPLIT */
 } gmres_options;
 
 typedef struct {
@@ -115,7 +130,7 @@ typedef struct {
 
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
- * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0. */
+ * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).

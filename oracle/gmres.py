@@ -80,9 +80,13 @@ class Matrix:
         x = np.asarray(x, dtype=np.float64)
         return np.bincount(self.rows, weights=self.vals * x[self.col_idx], minlength=self.n)
 
-    def matvec32(self, x32):
-        """Emulated single-precision product: float32 products, result rounded to float32."""
-        prod = (self.vals32 * np.asarray(x32, dtype=np.float32)[self.col_idx]).astype(np.float64)
+    def matvec32(self, x32, vals32=None):
+        """Emulated single-precision product: float32 products, result rounded to float32.
+
+        ``vals32`` replaces the float32 copy of the values (the split-storage
+        form passes the high-word values)."""
+        v = self.vals32 if vals32 is None else vals32
+        prod = (v * np.asarray(x32, dtype=np.float32)[self.col_idx]).astype(np.float64)
         return np.bincount(self.rows, weights=prod, minlength=self.n).astype(np.float32)
 
     def diagonal(self):
@@ -95,6 +99,19 @@ class Matrix:
         D = np.zeros((self.n, self.n))
         np.add.at(D, (self.rows, self.col_idx), self.vals)
         return D
+
+
+# ---------------------------------------------------------------------------
+# Split storage of the float64 matrix values (the alternative organisation
+# the paper suggests for the matrix it otherwise stores twice): the high and
+# low 32-bit words of each value in two arrays.  Reading the high words only
+# gives each value with its significand cut after 20 bits (towards zero).
+
+def high_word_value(vals):
+    """float64 values keeping only their high 32-bit word (sign, exponent and
+    the first 20 significand bits; the low word set to zero)."""
+    bits = np.ascontiguousarray(vals, dtype=np.float64).view(np.uint64)
+    return (bits & np.uint64(0xFFFFFFFF00000000)).view(np.float64)
 
 
 # ---------------------------------------------------------------------------
@@ -217,18 +234,26 @@ def _cast(v, precision):
 
 def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
           precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
-          fallback=True, record=False, residual_fp32=False, update_fp32=False):
+          fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy"):
     """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
 
     ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> z applied
     on the right: z_j = M v_j, w = A z_j, and the correction is Z y
     (flexible GMRES).  The paper itself preconditions on the left; the
     right-preconditioned form is what the learned preconditioner uses.
+    ``a_storage="split"`` emulates the split storage of A: the float32
+    Arnoldi product uses the high-word values (the float64 residual is
+    unchanged, as both words together are the float64 value).
     """
     if ortho not in ("mgs", "cgsr"):
         raise ValueError(ortho)
     if precision not in ("fp64", "fp32", "bf16", "fp16"):
         raise ValueError(precision)
+    if a_storage not in ("copy", "split"):
+        raise ValueError(a_storage)
+    # the Arnoldi product's copy of A in the reduced-precision modes: float32
+    # rounding of the values, or (split storage) the high-word values
+    a32 = A.vals32 if a_storage == "copy" else high_word_value(A.vals).astype(np.float32)
     b = np.asarray(b, dtype=np.float64)
     n = A.n
     bn = float(np.linalg.norm(b))
@@ -315,7 +340,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 src = Z[j]
             else:
                 src = vj
-            w = A.matvec32(src) if lowp else A.matvec(src)
+            w = A.matvec32(src, a32) if lowp else A.matvec(src)
             # orthogonalize(w, V_j)
             hcol = np.zeros(j + 1)
             if ortho == "mgs":

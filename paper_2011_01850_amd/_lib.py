@@ -19,6 +19,8 @@ ORTHOS = {"mgs": MGS, "cgsr": CGSR}
 PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "spai": PRECOND_SPAI}
 SCHEDULE_AUTO, SCHEDULE_DEVICE_WIDE, SCHEDULE_PERSISTENT = 0, 1, 2
 SCHEDULES = {"auto": SCHEDULE_AUTO, "device_wide": SCHEDULE_DEVICE_WIDE, "persistent": SCHEDULE_PERSISTENT}
+A_COPY, A_SPLIT = 0, 1
+A_STORAGES = {"copy": A_COPY, "split": A_SPLIT}
 
 
 class Options(C.Structure):
@@ -35,6 +37,7 @@ class Options(C.Structure):
         ("autotune", C.c_int32),
         ("batch_schedule", C.c_int32),
         ("spmv_block_nnz", C.c_int32),
+        ("a_storage", C.c_int32),
     ]
 
 

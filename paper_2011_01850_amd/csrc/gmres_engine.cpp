@@ -86,6 +86,9 @@ struct gmres_ctx {
   // staging for the plain SpMV / residual entry points (ld rows each)
   double* xs = nullptr;
   double* ys = nullptr;
+  // SPLIT storage: the float64 values reassembled for the network inputs
+  // (allocated on the first inference)
+  double* a64_merged = nullptr;
 
   template <typename T>
   T* alloc(size_t count) {
@@ -159,6 +162,7 @@ bool valid_options(const gmres_options* o) {
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
   if (o->spmv_block_nnz != 0 && (o->spmv_block_nnz < 64 || o->spmv_block_nnz > 8192 || o->spmv_block_nnz % 64))
     return false;
+  if (o->a_storage != GMRES_A_COPY && o->a_storage != GMRES_A_SPLIT) return false;
   return true;
 }
 
@@ -166,6 +170,7 @@ bool valid_options(const gmres_options* o) {
 // system, up to kMaxPR rows per thread, H in LDS, 32-bit buffer offsets).
 bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64_t nnz_total, int64_t ld) {
   if (o->precision != GMRES_MIXED_FP32 || o->precond != GMRES_PRECOND_NONE || o->ortho != GMRES_MGS) return false;
+  if (o->a_storage != GMRES_A_COPY) return false;
   if (o->m > kMaxPM) return false;
   for (int k = 0; k < nsys; ++k)
     if (n[k] > (int64_t)1024 * kMaxPR) return false;
@@ -466,22 +471,42 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   hip_check(hipMemcpy(d_rp, h->rp_host.data(), (h->ld + 1) * 4, hipMemcpyHostToDevice));
   // index and value arrays carry a zero pad of 4 entries (SpMV reads aligned groups of 4)
   int32_t* d_ci = h->alloc<int32_t>(h->nnz + 4);
-  double* d_a64 = h->alloc<double>(h->nnz + 4);
   hip_check(hipMemsetAsync(d_ci + h->nnz, 0, 16, h->stream));
-  hip_check(hipMemsetAsync(d_a64 + h->nnz, 0, 32, h->stream));
   for (int k = 0; k < nsys; ++k) {
     const System& s = h->sys[k];
     if (s.nnz == 0) continue;
     hip_check(launch_shift_cols(ci[k], d_ci + s.nz0, s.nnz, (int32_t)s.row0, h->stream));
-    hip_check(hipMemcpyAsync(d_a64 + s.nz0, vals[k], s.nnz * 8, hipMemcpyDeviceToDevice, h->stream));
   }
   a.rp = d_rp;
   a.ci = d_ci;
-  a.a64 = d_a64;
-  if (prec != P64) {
-    float* d_a32 = h->alloc<float>(h->nnz + 4);
-    hip_check(launch_convert_f32(d_a64, d_a32, h->nnz + 4, h->stream));
-    a.a32 = d_a32;
+  if (opt->a_storage == GMRES_A_SPLIT) {
+    // high and low 32-bit words of the float64 values, in two arrays
+    uint32_t* d_hi = h->alloc<uint32_t>(h->nnz + 4);
+    uint32_t* d_lo = h->alloc<uint32_t>(h->nnz + 4);
+    hip_check(hipMemsetAsync(d_hi + h->nnz, 0, 16, h->stream));
+    hip_check(hipMemsetAsync(d_lo + h->nnz, 0, 16, h->stream));
+    for (int k = 0; k < nsys; ++k) {
+      const System& s = h->sys[k];
+      if (s.nnz == 0) continue;
+      hip_check(launch_split_words(vals[k], d_hi + s.nz0, d_lo + s.nz0, s.nnz, h->stream));
+    }
+    a.ahi = d_hi;
+    a.alo = d_lo;
+    a.asplit = 1;
+  } else {
+    double* d_a64 = h->alloc<double>(h->nnz + 4);
+    hip_check(hipMemsetAsync(d_a64 + h->nnz, 0, 32, h->stream));
+    for (int k = 0; k < nsys; ++k) {
+      const System& s = h->sys[k];
+      if (s.nnz == 0) continue;
+      hip_check(hipMemcpyAsync(d_a64 + s.nz0, vals[k], s.nnz * 8, hipMemcpyDeviceToDevice, h->stream));
+    }
+    a.a64 = d_a64;
+    if (prec != P64) {
+      float* d_a32 = h->alloc<float>(h->nnz + 4);
+      hip_check(launch_convert_f32(d_a64, d_a32, h->nnz + 4, h->stream));
+      a.a32 = d_a32;
+    }
   }
   // ---- per-system tables
   std::vector<int32_t> tile_sys(h->ntile), t0(nsys), nt(nsys), sn(nsys);
@@ -656,6 +681,15 @@ gmres_ctx* get(gmres_handle h) {
   return h;
 }
 
+// A's float64 values as one array (merged from the two word arrays in SPLIT
+// storage); enqueued on the handle's stream.
+const double* a64_values(gmres_ctx* h) {
+  if (!h->a.asplit) return h->a.a64;
+  if (!h->a64_merged) h->a64_merged = h->alloc<double>(h->nnz + 4);
+  hip_check(launch_merge_words(h->a.ahi, h->a.alo, h->a64_merged, h->nnz, h->stream));
+  return h->a64_merged;
+}
+
 }  // namespace
 
 // ===================================================================== C ABI
@@ -676,6 +710,7 @@ void gmres_default_options(gmres_options* o) {
   o->autotune = 1;
   o->batch_schedule = GMRES_SCHEDULE_AUTO;
   o->spmv_block_nnz = 0;
+  o->a_storage = GMRES_A_COPY;
 }
 
 const char* gmres_strerror(int code) {
@@ -748,7 +783,7 @@ int gmres_spai_infer(gmres_handle hh, const void* params, size_t param_bytes, fl
       const int rc = spai_create(&h->spai, h->sys[0].n, h->nnz, h->a.rp, h->a.ci, 1, h->stream);
       if (rc != GMRES_OK) return rc;
     }
-    int rc = spai_set_values(h->spai, h->a.a64);
+    int rc = spai_set_values(h->spai, a64_values(h));
     if (rc == GMRES_OK) rc = spai_forward(h->spai, (const uint16_t*)params, (float*)h->a.mval);
     if (rc != GMRES_OK) return rc;
     if (m_out) {
@@ -774,7 +809,7 @@ int gmres_spai_infer_with(gmres_handle hh, spai_handle net, const void* params, 
     int rc = spai_same_pattern(net, h->sys[0].n, h->nnz, h->a.rp, h->a.ci, &same);
     if (rc != GMRES_OK) return rc;
     if (!same) return GMRES_ESTATE;
-    rc = spai_set_values(net, h->a.a64);
+    rc = spai_set_values(net, a64_values(h));
     if (rc == GMRES_OK) rc = spai_forward(net, (const uint16_t*)params, (float*)h->a.mval);
     if (rc != GMRES_OK) return rc;
     if (m_out) {
@@ -909,7 +944,7 @@ int gmres_spmv(gmres_handle hh, int32_t precision, const void* x, void* y) {
     gmres_ctx* h = get(hh);
     if (!x || !y) return GMRES_EINVAL;
     if (precision != GMRES_FP64 && precision != GMRES_MIXED_FP32) return GMRES_EINVAL;
-    if (precision == GMRES_MIXED_FP32 && !h->a.a32) return GMRES_ESTATE;
+    if (precision == GMRES_MIXED_FP32 && !h->a.a32 && !h->a.asplit) return GMRES_ESTATE;
     if (h->sys.size() != 1) return GMRES_ESTATE;
     const int64_t n = h->sys[0].n;
     const size_t eb = precision == GMRES_FP64 ? 8 : 4;

@@ -96,8 +96,11 @@ struct KArgs {
   // matrix: concatenated systems, global row and column numbering
   const int32_t* rp;
   const int32_t* ci;
-  const double* a64;
-  const float* a32;
+  const double* a64;    // float64 values (COPY storage), else null
+  const float* a32;     // float32 copy (COPY storage, mixed modes), else null
+  const uint32_t* ahi;  // SPLIT storage: high and low 32-bit words of the float64 values
+  const uint32_t* alo;
+  int32_t asplit;       // 1: SPLIT storage
   const float* mval;   // SPAI values (float32, A's pattern)
   const float* dinv;   // Jacobi: 1 / a_ii
   const int32_t* rb;       // row-block first rows [nrb + 1]
@@ -163,6 +166,9 @@ hipError_t launch_init_state(const KArgs& a, hipStream_t st);
 hipError_t launch_set_force(const KArgs& a, int on, hipStream_t st);
 hipError_t launch_check_cols(const KArgs& a, int32_t* bad, hipStream_t st);
 hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+// float64 values -> high and low 32-bit words (SPLIT storage), and back
+hipError_t launch_split_words(const double* src, uint32_t* hi, uint32_t* lo, int64_t n, hipStream_t st);
+hipError_t launch_merge_words(const uint32_t* hi, const uint32_t* lo, double* dst, int64_t n, hipStream_t st);
 hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st);
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,

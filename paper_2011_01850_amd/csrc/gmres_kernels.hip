@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "gmres_internal.hpp"
 
@@ -39,6 +40,34 @@ template <>
 struct AccOf<double> {
   using type = double;
 };
+
+// A's values in SPLIT storage: HiW reads the high 32-bit word of each
+// float64 value (the value truncated to 20 significand bits) as float32;
+// HiLoW reads the high word and the low word at the same index of the
+// separate low-word array, i.e. the float64 value itself.
+struct HiW {
+  uint32_t w;
+};
+struct HiLoW {
+  uint32_t w;
+};
+template <>
+struct AccOf<HiLoW> {
+  using type = double;
+};
+__device__ __forceinline__ float hi_value(uint32_t h) { return (float)__hiloint2double((int)h, 0); }
+__device__ __forceinline__ double hilo_value(uint32_t h, uint32_t l) { return __hiloint2double((int)h, (int)l); }
+
+// Value k of A for the SpMV (element type TA, see above).
+template <typename TA>
+__device__ __forceinline__ typename AccOf<TA>::type a_value(const KArgs& a, const TA* vals, int k) {
+  if constexpr (std::is_same<TA, HiW>::value)
+    return hi_value(vals[k].w);
+  else if constexpr (std::is_same<TA, HiLoW>::value)
+    return hilo_value(vals[k].w, a.alo[k]);
+  else
+    return (typename AccOf<TA>::type)vals[k];
+}
 
 __device__ __forceinline__ float ldv(float v) { return v; }
 __device__ __forceinline__ double ldv(double v) { return v; }
@@ -411,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
     ACC acc = (ACC)0;
     for (int c0 = p0; c0 < p1; c0 += a.spmv_budget) {  // chunks are multiples of T long
       const int c1 = min(p1, c0 + a.spmv_budget);
-      for (int k = c0 + t; k < c1; k += kBlock) prod[k - c0] = (ACC)vals[k] * (ACC)ldv(x[a.ci[k]]);
+      for (int k = c0 + t; k < c1; k += kBlock) prod[k - c0] = a_value(a, vals, k) * (ACC)ldv(x[a.ci[k]]);
       __syncthreads();
       if (t < T)
         for (int k = c0 + t; k < c1; k += T) acc += prod[k - c0];
@@ -428,20 +457,29 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
     const int q0 = p0 & ~3;
     for (int k4 = q0 + 4 * t; k4 < p1; k4 += 4 * kBlock) {
       const int4 c4 = *reinterpret_cast<const int4*>(a.ci + k4);
-      TA v4[4];
-      if constexpr (sizeof(TA) == 4) {
+      ACC v4[4];
+      if constexpr (std::is_same<TA, float>::value) {
         const float4 f = *reinterpret_cast<const float4*>(vals + k4);
         v4[0] = f.x; v4[1] = f.y; v4[2] = f.z; v4[3] = f.w;
-      } else {
+      } else if constexpr (std::is_same<TA, double>::value) {
         const double2 f0 = *reinterpret_cast<const double2*>(vals + k4);
         const double2 f1 = *reinterpret_cast<const double2*>(vals + k4 + 2);
         v4[0] = f0.x; v4[1] = f0.y; v4[2] = f1.x; v4[3] = f1.y;
+      } else {
+        const uint4 h = *reinterpret_cast<const uint4*>(vals + k4);
+        if constexpr (std::is_same<TA, HiW>::value) {
+          v4[0] = hi_value(h.x); v4[1] = hi_value(h.y); v4[2] = hi_value(h.z); v4[3] = hi_value(h.w);
+        } else {
+          const uint4 l = *reinterpret_cast<const uint4*>(a.alo + k4);
+          v4[0] = hilo_value(h.x, l.x); v4[1] = hilo_value(h.y, l.y);
+          v4[2] = hilo_value(h.z, l.z); v4[3] = hilo_value(h.w, l.w);
+        }
       }
       const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int k = k4 + e;
-        if (k >= p0 && k < p1) prod[k - p0] = (ACC)v4[e] * (ACC)ldv(x[cc[e]]);
+        if (k >= p0 && k < p1) prod[k - p0] = v4[e] * (ACC)ldv(x[cc[e]]);
       }
     }
     __syncthreads();
@@ -1147,6 +1185,21 @@ __global__ void k_check_cols(KArgs a, int32_t* bad) {
   }
 }
 
+__global__ void k_split_words(const double* __restrict__ src, uint32_t* __restrict__ hi,
+                              uint32_t* __restrict__ lo, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = src[i];
+    hi[i] = (uint32_t)__double2hiint(v);
+    lo[i] = (uint32_t)__double2loint(v);
+  }
+}
+
+__global__ void k_merge_words(const uint32_t* __restrict__ hi, const uint32_t* __restrict__ lo,
+                              double* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = hilo_value(hi[i], lo[i]);
+}
+
 __global__ void k_convert_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1160,7 +1213,7 @@ __global__ void k_jacobi_setup(KArgs a, float* dinv) {
   const int p0 = a.rp[r], p1 = a.rp[r + 1];
   double d = 0.0;
   for (int k = p0; k < p1; ++k)
-    if (a.ci[k] == r) d += a.a64[k];
+    if (a.ci[k] == r) d += a.asplit ? hilo_value(a.ahi[k], a.alo[k]) : a.a64[k];
   dinv[r] = (p1 > p0 && d != 0.0) ? (float)(1.0 / d) : 0.0f;
 }
 
@@ -1297,9 +1350,16 @@ static hipError_t launch_fin_cols(const KArgs& a, const SegTab& sg, int j, hipSt
 
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
   const size_t sh = (size_t)a.spmv_budget * (a.prec == P64 ? 8 : 4);
+  const HiW* hw = reinterpret_cast<const HiW*>(a.ahi);
+  const HiLoW* hlw = reinterpret_cast<const HiLoW*>(a.ahi);
   if (a.precond != 0) {  // w = A z_j
-    hipLaunchKernelGGL((k_spmv<float, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a,
-                       a.a32, a.Z + (int64_t)j * a.ld, (float*)a.w, nullptr, j);
+    const float* z = a.Z + (int64_t)j * a.ld;
+    if (a.asplit)
+      hipLaunchKernelGGL((k_spmv<HiW, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, z,
+                         (float*)a.w, nullptr, j);
+    else
+      hipLaunchKernelGGL((k_spmv<float, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a32, z,
+                         (float*)a.w, nullptr, j);
     return hipGetLastError();
   }
   return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
@@ -1307,11 +1367,19 @@ hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
     using TW = decltype(tw);
     const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
     if constexpr (sizeof(TW) == 8) {
-      hipLaunchKernelGGL((k_spmv<double, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a,
-                         a.a64, x, (TW*)a.w, nullptr, j);
+      if (a.asplit)
+        hipLaunchKernelGGL((k_spmv<HiLoW, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, hlw, x,
+                           (TW*)a.w, nullptr, j);
+      else
+        hipLaunchKernelGGL((k_spmv<double, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a64, x,
+                           (TW*)a.w, nullptr, j);
     } else {
-      hipLaunchKernelGGL((k_spmv<float, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a,
-                         a.a32, x, (TW*)a.w, nullptr, j);
+      if (a.asplit)
+        hipLaunchKernelGGL((k_spmv<HiW, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, x,
+                           (TW*)a.w, nullptr, j);
+      else
+        hipLaunchKernelGGL((k_spmv<float, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a32, x,
+                           (TW*)a.w, nullptr, j);
     }
     return hipGetLastError();
   });
@@ -1336,12 +1404,22 @@ hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {
   // z goes to w; the cycle's first basis column is written from it only
   // once the stop test has decided that a cycle starts (launch_encode)
   const size_t sh = (size_t)a.spmv_budget * 8;
-  if (a.prec == P64)
-    hipLaunchKernelGGL((k_spmv<double, double, double, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
-                       a.a64, a.x, (double*)a.w, a.b, 0);
-  else
-    hipLaunchKernelGGL((k_spmv<double, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
-                       a.a64, a.x, (float*)a.w, a.b, 0);
+  const HiLoW* hlw = reinterpret_cast<const HiLoW*>(a.ahi);
+  if (a.prec == P64) {
+    if (a.asplit)
+      hipLaunchKernelGGL((k_spmv<HiLoW, double, double, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a, hlw,
+                         a.x, (double*)a.w, a.b, 0);
+    else
+      hipLaunchKernelGGL((k_spmv<double, double, double, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                         a.a64, a.x, (double*)a.w, a.b, 0);
+  } else {
+    if (a.asplit)
+      hipLaunchKernelGGL((k_spmv<HiLoW, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a, hlw,
+                         a.x, (float*)a.w, a.b, 0);
+    else
+      hipLaunchKernelGGL((k_spmv<double, double, float, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                         a.a64, a.x, (float*)a.w, a.b, 0);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !with_fin) return e;
   hipLaunchKernelGGL(k_tile_norm, dim3(a.ntile), dim3(kBlock), 0, st, a);
@@ -1555,6 +1633,18 @@ hipError_t launch_check_cols(const KArgs& a, int32_t* bad, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_split_words(const double* src, uint32_t* hi, uint32_t* lo, int64_t n, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  if (blocks > 0) hipLaunchKernelGGL(k_split_words, dim3((unsigned)blocks), dim3(256), 0, st, src, hi, lo, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_words(const uint32_t* hi, const uint32_t* lo, double* dst, int64_t n, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  if (blocks > 0) hipLaunchKernelGGL(k_merge_words, dim3((unsigned)blocks), dim3(256), 0, st, hi, lo, dst, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
   if (blocks > 0) hipLaunchKernelGGL(k_convert_f32, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
@@ -1567,20 +1657,34 @@ hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st) {
 }
 
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st) {
+  const size_t sh8 = (size_t)a.spmv_budget * 8, sh4 = (size_t)a.spmv_budget * 4;
   if (prec == P64) {
-    hipLaunchKernelGGL((k_spmv<double, double, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock),
-                       (size_t)a.spmv_budget * 8, st, a, a.a64, (const double*)x, (double*)y, nullptr, 0);
+    if (a.asplit)
+      hipLaunchKernelGGL((k_spmv<HiLoW, double, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh8, st, a,
+                         reinterpret_cast<const HiLoW*>(a.ahi), (const double*)x, (double*)y, nullptr, 0);
+    else
+      hipLaunchKernelGGL((k_spmv<double, double, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh8, st, a,
+                         a.a64, (const double*)x, (double*)y, nullptr, 0);
   } else {
-    hipLaunchKernelGGL((k_spmv<float, float, float, SM_PLAIN>), dim3(a.nrb), dim3(kBlock),
-                       (size_t)a.spmv_budget * 4, st, a, a.a32, (const float*)x, (float*)y, nullptr, 0);
+    if (a.asplit)
+      hipLaunchKernelGGL((k_spmv<HiW, float, float, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh4, st, a,
+                         reinterpret_cast<const HiW*>(a.ahi), (const float*)x, (float*)y, nullptr, 0);
+    else
+      hipLaunchKernelGGL((k_spmv<float, float, float, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh4, st, a,
+                         a.a32, (const float*)x, (float*)y, nullptr, 0);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st) {
-  hipLaunchKernelGGL((k_spmv<double, double, double, SM_RESID_PLAIN>), dim3(a.nrb), dim3(kBlock),
-                     (size_t)a.spmv_budget * 8, st, a, a.a64, x, r, b, 0);
+  const size_t sh = (size_t)a.spmv_budget * 8;
+  if (a.asplit)
+    hipLaunchKernelGGL((k_spmv<HiLoW, double, double, SM_RESID_PLAIN>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                       reinterpret_cast<const HiLoW*>(a.ahi), x, r, b, 0);
+  else
+    hipLaunchKernelGGL((k_spmv<double, double, double, SM_RESID_PLAIN>), dim3(a.nrb), dim3(kBlock), sh, st, a,
+                       a.a64, x, r, b, 0);
   return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ def _dev(t, dtype, torch):
 
 
 def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
-             autotune, schedule="auto", spmv_block_nnz=0) -> L.Options:
+             autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy") -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -46,6 +46,7 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.autotune = int(bool(autotune))
     o.batch_schedule = L.SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.spmv_block_nnz = int(spmv_block_nnz)
+    o.a_storage = L.A_STORAGES[a_storage] if isinstance(a_storage, str) else int(a_storage)
     return o
 
 
@@ -54,7 +55,8 @@ class Solver:
 
     def __init__(self, row_ptr, col_idx, vals, m=50, tol=1e-10, ortho="cgsr", precision="fp32",
                  precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
-                 use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0):
+                 use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
+                 a_storage="copy"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -65,7 +67,7 @@ class Solver:
         self.nnz = int(ci.numel())
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
-                            use_graph, autotune, schedule, spmv_block_nnz)
+                            use_graph, autotune, schedule, spmv_block_nnz, a_storage)
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         torch.cuda.synchronize()
@@ -190,7 +192,7 @@ class BatchSolver:
 
     def __init__(self, systems, m=40, tol=1e-10, ortho="mgs", precision="fp32", precond="none",
                  max_iters=100_000, restart_improve=0.0, stall_cycles=10, use_graph=True, autotune=True,
-                 schedule="auto", spmv_block_nnz=0):
+                 schedule="auto", spmv_block_nnz=0, a_storage="copy"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -211,7 +213,7 @@ class BatchSolver:
         self.ns = ns
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
-                            use_graph, autotune, schedule, spmv_block_nnz)
+                            use_graph, autotune, schedule, spmv_block_nnz, a_storage)
         arr64 = C.c_int64 * S
         arrp = C.c_void_p * S
         h = C.c_void_p()

@@ -40,7 +40,7 @@ def test_default_options(lib):
     assert (o.m, o.tol, o.max_iters) == (50, 1e-10, 100000)
     assert o.ortho == L.CGSR and o.precision == L.MIXED_FP32 and o.precond == L.PRECOND_NONE
     assert o.restart_improve == 0.0 and o.stall_cycles == 10 and o.use_graph == 1 and o.autotune == 1
-    assert o.batch_schedule == L.SCHEDULE_AUTO and o.spmv_block_nnz == 0
+    assert o.batch_schedule == L.SCHEDULE_AUTO and o.spmv_block_nnz == 0 and o.a_storage == L.A_COPY
 
 
 def test_strerror(lib):
@@ -59,7 +59,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     for field, bad in [("m", 0), ("m", 257), ("tol", -1.0), ("ortho", 7), ("precision", 9),
                        ("precond", 5), ("stall_cycles", 0), ("restart_improve", -0.5), ("batch_schedule", 3),
                        ("batch_schedule", -1), ("spmv_block_nnz", 32), ("spmv_block_nnz", 100),
-                       ("spmv_block_nnz", 8256)]:
+                       ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -89,6 +89,7 @@ def test_struct_layouts_match_header():
     assert L.Options.tol.offset == 8 and L.Options.max_iters.offset == 16
     assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
     assert L.Options.batch_schedule.offset == 60 and L.Options.spmv_block_nnz.offset == 64
+    assert L.Options.a_storage.offset == 68
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 

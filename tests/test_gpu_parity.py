@@ -70,6 +70,77 @@ def test_spmv_integer_inputs_bitwise(n, long_rows):
     s.close()
 
 
+@pytest.mark.parametrize("n,long_rows", [(5000, ()), (7001, (3, 4000))])
+def test_split_storage_spmv_and_residual(n, long_rows):
+    # split storage of A: the float64 product and the residual read both
+    # words (bitwise equal to the exact sums on integer data); the float32
+    # product reads the high words: on values with long significands it
+    # equals the oracle's product with the high-word values
+    A = _int_csr(n, n, long_rows)
+    g = np.random.default_rng(3)
+    x = g.integers(-16, 17, n).astype(np.float64)
+    s = _solver(A, precision="fp32", m=4, a_storage="split")
+    M = O.Matrix.from_csr(A)
+    ref = M.matvec(x)
+    assert np.array_equal(s.spmv(x, "fp64").cpu().numpy(), ref)
+    assert np.array_equal(s.spmv(x.astype(np.float32), "fp32").cpu().numpy(), ref.astype(np.float32))
+    b = g.integers(-100, 101, n).astype(np.float64)
+    r, nrm = s.residual(b, x)
+    assert np.array_equal(r.cpu().numpy(), b - ref)
+    s.close()
+    # values with more than 20 significand bits: the float32 product of the
+    # split storage follows the high-word values (truncated after 20 bits),
+    # not the float32 rounding of the values that the copy storage uses
+    A2 = P.CSR(A.n, A.row_ptr, A.col_idx, A.vals * (1.0 + g.uniform(0.0, 2.0 ** -18, A.nnz)))
+    M2 = O.Matrix.from_csr(A2)
+    xs = g.integers(-8, 9, n).astype(np.float64)
+    head = O.high_word_value(M2.vals)
+    y_head = np.bincount(M2.rows, weights=head * xs[M2.col_idx], minlength=n)
+    bound = 16 * 2.0 ** -24 * np.bincount(M2.rows, weights=np.abs(head * xs[M2.col_idx]), minlength=n)
+    s_split = _solver(A2, precision="fp32", m=4, a_storage="split")
+    s_copy = _solver(A2, precision="fp32", m=4)
+    y_split = s_split.spmv(xs.astype(np.float32), "fp32").cpu().numpy().astype(np.float64)
+    y_copy = s_copy.spmv(xs.astype(np.float32), "fp32").cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(y_split - y_head) <= bound)
+    # on average over the rows, far closer to the high-word product than the
+    # copy storage's float32 product is
+    scale = np.maximum(bound, 1e-300)
+    assert np.mean(np.abs(y_split - y_head) / scale) < 0.25 * np.mean(np.abs(y_copy - y_head) / scale)
+    # the float64 product reads both words: the same as the copy storage, bit for bit
+    assert np.array_equal(s_split.spmv(xs, "fp64").cpu().numpy(), s_copy.spmv(xs, "fp64").cpu().numpy())
+    s_split.close()
+    s_copy.close()
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_split_storage_solves(ortho):
+    pr, m = _case("3d17_ragged")
+    # float64 mode reads both words: the same solve as the copy storage, bit for bit
+    outs = []
+    for st in ("copy", "split"):
+        sv = _solver(pr.A, m=m, ortho=ortho, precision="fp64", tol=1e-12, autotune=False, a_storage=st)
+        x, info = sv.solve(pr.b)
+        outs.append((x.cpu().numpy(), info["iters"], sv.memory_bytes()))
+        sv.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    # mixed mode: the float32 Arnoldi reads the high words; parity with the
+    # oracle's solution and with its emulation of the same storage
+    ref = _oracle_x("3d17_ragged", ortho)
+    x, info = _parity_case(pr.A, pr.b, m, ortho, "fp32", a_storage="split")
+    assert info["status"] == "CONVERGED" and _relres(pr.A, pr.b, x) <= 1e-13 * 1.01
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    emu = O.gmres(O.Matrix.from_csr(pr.A), pr.b, m=m, tol=1e-13, ortho=ortho, precision="fp32",
+                  a_storage="split", max_iters=20000)
+    assert emu.status == O.CONVERGED
+    assert abs(_cycles_to(info["history"], 1e-10) - _cycles_to(emu.history, 1e-10)) <= 1
+    # footprint: the float32 copy (4 bytes per non-zero) is gone
+    s_copy = _solver(pr.A, m=m, ortho=ortho, precision="fp32", autotune=False)
+    s_split = _solver(pr.A, m=m, ortho=ortho, precision="fp32", autotune=False, a_storage="split")
+    assert s_copy.memory_bytes() - s_split.memory_bytes() >= 4 * pr.A.nnz
+    s_copy.close()
+    s_split.close()
+
+
 @pytest.mark.parametrize("fmt", ["fp16", "bf16"])
 def test_encode_bitwise_against_oracle(fmt):
     g = np.random.default_rng(2)
@@ -318,6 +389,12 @@ def test_jacobi_fgmres_matches_oracle():
     s2.close()
     assert info2["status"] == "CONVERGED" and info2["iters"] == info["iters"]
     assert np.array_equal(x2.cpu().numpy(), x.cpu().numpy())
+    # split storage: D^-1 from both words, the Arnoldi product from the high words
+    s3 = _solver(A0, m=30, precision="fp32", precond="jacobi", tol=1e-11, a_storage="split")
+    x3, info3 = s3.solve(b)
+    s3.close()
+    assert info3["status"] == "CONVERGED" and _relres(A0, b, x3.cpu().numpy()) <= 1.01e-11
+    assert abs(info3["iters"] - ref.iters) <= 30
 
 
 def test_spai_nonfinite_values_fall_back_to_plain_gmres():

@@ -260,6 +260,12 @@ def test_infer_with_shared_network(lib):
         m_shared = s.spai_infer(params, net=net)
         assert torch.equal(m_own, m_shared)
         s.close()
+        # split storage of A: the network reads the same float64 values
+        s = Solver(A.row_ptr, A.col_idx, A.vals, m=20, precision="fp32", precond="spai", autotune=False,
+                   a_storage="split")
+        assert torch.equal(s.spai_infer(params), m_own)
+        assert torch.equal(s.spai_infer(params, net=net), m_own)
+        s.close()
     other = P.convdiff(10, (1.0, 2.0))
     s = Solver(other.row_ptr, other.col_idx, other.vals, m=20, precision="fp32", precond="spai", autotune=False)
     with pytest.raises(GmresError):

@@ -320,6 +320,48 @@ def test_two_byte_basis_still_reaches_double_accuracy(fmt):
 
 
 # --------------------------------------------------------------------------
+# split storage of A (high and low 32-bit words of each float64 value)
+
+def test_high_word_value_hand_cases():
+    # the high word holds sign, exponent and the first 20 significand bits
+    vals = np.array([1.0 + 2.0 ** -20, 1.0 + 2.0 ** -21, -(1.0 + 2.0 ** -21), 3.0, 0.0, -0.0,
+                     2.0 ** -1000 * (1.0 + 2.0 ** -30), 1.5 * 2.0 ** 300])
+    want = np.array([1.0 + 2.0 ** -20, 1.0, -1.0, 3.0, 0.0, -0.0, 2.0 ** -1000, 1.5 * 2.0 ** 300])
+    got = O.high_word_value(vals)
+    assert np.array_equal(got, want) and np.array_equal(np.signbit(got), np.signbit(want))
+
+
+def test_high_word_value_is_a_truncation_exact_in_float32():
+    g = np.random.default_rng(7)
+    v = g.standard_normal(20000) * np.exp(g.uniform(-30, 30, 20000))
+    h = O.high_word_value(v)
+    # never larger in magnitude, same sign, relative error below 2^-20
+    assert np.all(np.abs(h) <= np.abs(v)) and np.all(np.sign(h) == np.sign(v))
+    assert np.all(np.abs(v - h) < 2.0 ** -20 * np.abs(v))
+    # 20 significand bits fit float32's 23: the conversion is exact in range
+    assert np.array_equal(h.astype(np.float32).astype(np.float64), h)
+    # the low word is what was dropped: high word + low word = the value
+    lo = (v.view(np.uint64) & np.uint64(0xFFFFFFFF)).astype(np.uint64)
+    assert np.array_equal((h.view(np.uint64) | lo).view(np.float64), v)
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_split_storage_mixed_reaches_double_accuracy(ortho):
+    # the Arnoldi copy of A is perturbed by up to 2^-20 relative; the float64
+    # residual (both words) still drives the solve to 1e-10
+    pr = P.c1_convdiff2d(32)
+    A = _mat(pr.A)
+    r32 = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho, precision="fp32")
+    rs = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho, precision="fp32", a_storage="split")
+    assert rs.status == O.CONVERGED and O.relative_residual(A, pr.b, rs.x) <= 1e-10
+    assert abs(rs.iters - r32.iters) <= 30
+    # float64 mode reads both words: identical to the copy storage
+    r64 = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho)
+    r64s = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho, a_storage="split")
+    assert np.array_equal(r64.x, r64s.x) and r64.iters == r64s.iters
+
+
+# --------------------------------------------------------------------------
 # flexible (right-preconditioned) form
 
 def test_fgmres_with_identity_is_plain_gmres_bitwise():

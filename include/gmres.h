@@ -115,7 +115,29 @@ typedef struct {
                                [64, 8192].  Results do not depend on it: every row is summed in
                                one order fixed by its length. */
   int32_t a_storage;        /* GMRES_A_COPY or GMRES_A_SPLIT */
+  /* Restart strategies of the restart study (section 3), each optional and
+   * combinable with j = m and the improvement trigger above:
+   * restart_repeat   1: the first cycle ends as usual (m, or restart_improve);
+   *                  every later cycle ends after as many inner iterations as
+   *                  the first one took (the two-stage strategy; the
+   *                  improvement trigger applies to the first cycle only).
+   * restart_on_stall 1: end a cycle once the Arnoldi residual stalls, i.e.
+   *                  |s_{j+1}| > |s_{j+1-w}| / 1.001 with w = max(1, ceil(0.05 m))
+   *                  (the third strategy; the same window as first_stall).
+   * orth_restart     > 0: end a cycle once ||S_k|| >= orth_restart, where
+   *                  S_k = (I + U_k)^-1 U_k and U_k is the strictly upper part
+   *                  of V_k^T V_k (the loss-of-orthogonality strategy; ||S_k|| = 1
+   *                  exactly when the basis is linearly dependent).  Costs one
+   *                  more pass over the basis per step.
+   * orth_norm        GMRES_ORTH_SPECTRAL (10 power iterations on S_k^T S_k from
+   *                  the all-ones vector) or GMRES_ORTH_FROBENIUS. */
+  int32_t restart_repeat;
+  int32_t restart_on_stall;
+  double orth_restart;
+  int32_t orth_norm;
 } gmres_options;
+
+enum { GMRES_ORTH_SPECTRAL = 0, GMRES_ORTH_FROBENIUS = 1 };
 
 typedef struct {
   int32_t status;        /* GMRES_CONVERGED / MAXITER / STALLED */
@@ -130,7 +152,8 @@ typedef struct {
 
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
- * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY. */
+ * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
+ * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).

@@ -234,7 +234,8 @@ def _cast(v, precision):
 
 def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
           precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
-          fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy"):
+          fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy",
+          restart_repeat=False, restart_on_stall=False):
     """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
 
     ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> z applied
@@ -244,6 +245,13 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     ``a_storage="split"`` emulates the split storage of A: the float32
     Arnoldi product uses the high-word values (the float64 residual is
     unchanged, as both words together are the float64 value).
+
+    Restart strategies of the restart study (section 3), on top of j = m and
+    the improvement threshold ``restart_improve``: ``restart_repeat`` is the
+    two-stage strategy (the first cycle ends as usual; every later one after
+    as many inner iterations as the first took; the improvement threshold
+    only applies to the first cycle); ``restart_on_stall`` ends a cycle once
+    the Arnoldi residual has stalled over the window of ``stall_window``.
     """
     if ortho not in ("mgs", "cgsr"):
         raise ValueError(ortho)
@@ -273,6 +281,8 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     no_progress = 0
     prev_beta = math.inf
     use_pc = precond is not None
+    klimit = 0  # two-stage strategy: length of the first cycle once it has ended
+    win = stall_window(m)
     while True:
         # Alg. 1: residual, in full precision unless the negative control asks otherwise
         if residual_fp32:
@@ -332,6 +342,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
 
         k = 0
         cycle_arn = []
+        ares = [beta]  # |s_1| .. |s_{j+1}| of this cycle
         for j in range(m):
             vj = basis(j)
             # w <- A v_j (flexible form: z_j = M v_j, w <- A z_j)
@@ -373,6 +384,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
             H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
             H[j + 1, j] = 0.0
             cycle_arn.append(abs(s[j + 1]) / bn)
+            ares.append(abs(s[j + 1]))
             if hnext == 0.0 or not math.isfinite(hnext):
                 if not math.isfinite(hnext):
                     k = j  # drop the non-finite column
@@ -387,8 +399,15 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 scale[j + 1] = 1.0
             if abs(s[j + 1]) / bn <= tol or total >= max_iters:
                 break
-            if restart_improve > 0.0 and abs(s[j + 1]) <= restart_improve * beta:
+            first_stage = not restart_repeat or klimit == 0
+            if restart_improve > 0.0 and first_stage and abs(s[j + 1]) <= restart_improve * beta:
                 break
+            if not first_stage and j + 1 >= klimit:
+                break
+            if restart_on_stall and j + 1 - win >= 0 and ares[j + 1] > ares[j + 1 - win] / 1.001:
+                break
+        if restart_repeat and klimit == 0 and k > 0:
+            klimit = k
         # correction u = V_j H^-1 s (Z y in the flexible form), applied in full precision
         y, kk = back_solve(H, s, k, U32 if lowp else U64)
         u = np.zeros(n)

@@ -21,6 +21,8 @@ SCHEDULE_AUTO, SCHEDULE_DEVICE_WIDE, SCHEDULE_PERSISTENT = 0, 1, 2
 SCHEDULES = {"auto": SCHEDULE_AUTO, "device_wide": SCHEDULE_DEVICE_WIDE, "persistent": SCHEDULE_PERSISTENT}
 A_COPY, A_SPLIT = 0, 1
 A_STORAGES = {"copy": A_COPY, "split": A_SPLIT}
+ORTH_SPECTRAL, ORTH_FROBENIUS = 0, 1
+ORTH_NORMS = {"spectral": ORTH_SPECTRAL, "frobenius": ORTH_FROBENIUS}
 
 
 class Options(C.Structure):
@@ -38,6 +40,10 @@ class Options(C.Structure):
         ("batch_schedule", C.c_int32),
         ("spmv_block_nnz", C.c_int32),
         ("a_storage", C.c_int32),
+        ("restart_repeat", C.c_int32),
+        ("restart_on_stall", C.c_int32),
+        ("orth_restart", C.c_double),
+        ("orth_norm", C.c_int32),
     ]
 
 

@@ -155,7 +155,7 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
   bsum2(sh, buf, bb, dummy);
   const double bnorm = sqrt(bb);
 
-  int status = RUNNING, nhist = 0, cycle = 0, no_progress = 0, first_stall = -1, klast = 0;
+  int status = RUNNING, nhist = 0, cycle = 0, no_progress = 0, first_stall = -1, klast = 0, klimit = 0;
   int64_t iters = 0, restarts = 0;
   double best = INFINITY, beta = 0.0, rel = 0.0;
   if (bnorm == 0.0) {
@@ -320,8 +320,14 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
         }
         const double bd = 16.0 * (double)(j + 1) * bd_u;
         const bool fin = isfinite(hn) && isfinite(cur);
+        const bool first_stage = !a.restart_repeat || klimit == 0;
+        const int Js = j + 1 - a.stall_win;
         const bool end = !fin || (j + 1 >= m) || !(hn > bd * wnorm_pre) || res <= a.tol * bnorm ||
-                         iters >= a.max_iters || (a.restart_improve > 0.0 && res <= a.restart_improve * beta);
+                         iters >= a.max_iters ||
+                         (a.restart_improve > 0.0 && first_stage && res <= a.restart_improve * beta) ||
+                         (!first_stage && j + 1 >= klimit) ||
+                         (a.restart_on_stall && Js >= 0 && res > sh.ar[Js] / 1.001);
+        if (end && a.restart_repeat && klimit == 0) klimit = fin ? j + 1 : j;
         sh.ctl[0] = end ? 1 : 0;
         sh.ctl[1] = fin ? 1 : 0;
       }

@@ -163,6 +163,11 @@ bool valid_options(const gmres_options* o) {
   if (o->spmv_block_nnz != 0 && (o->spmv_block_nnz < 64 || o->spmv_block_nnz > 8192 || o->spmv_block_nnz % 64))
     return false;
   if (o->a_storage != GMRES_A_COPY && o->a_storage != GMRES_A_SPLIT) return false;
+  if (o->restart_repeat != 0 && o->restart_repeat != 1) return false;
+  if (o->restart_on_stall != 0 && o->restart_on_stall != 1) return false;
+  if (!(o->orth_restart >= 0.0) || !std::isfinite(o->orth_restart)) return false;
+  if (o->orth_norm != GMRES_ORTH_SPECTRAL && o->orth_norm != GMRES_ORTH_FROBENIUS) return false;
+  if (o->orth_restart > 0.0) return false;  // loss-of-orthogonality monitor: not available yet
   return true;
 }
 
@@ -170,7 +175,7 @@ bool valid_options(const gmres_options* o) {
 // system, up to kMaxPR rows per thread, H in LDS, 32-bit buffer offsets).
 bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64_t nnz_total, int64_t ld) {
   if (o->precision != GMRES_MIXED_FP32 || o->precond != GMRES_PRECOND_NONE || o->ortho != GMRES_MGS) return false;
-  if (o->a_storage != GMRES_A_COPY) return false;
+  if (o->a_storage != GMRES_A_COPY || o->orth_restart > 0.0) return false;
   if (o->m > kMaxPM) return false;
   for (int k = 0; k < nsys; ++k)
     if (n[k] > (int64_t)1024 * kMaxPR) return false;
@@ -568,6 +573,10 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.hist = h->alloc<double>((size_t)nsys * kHistCap);
   a.tol = opt->tol;
   a.restart_improve = opt->restart_improve;
+  a.restart_repeat = opt->restart_repeat;
+  a.restart_on_stall = opt->restart_on_stall;
+  a.orth_restart = opt->orth_restart;
+  a.orth_norm = opt->orth_norm;
   a.max_iters = opt->max_iters;
   a.stall_cycles = opt->stall_cycles;
   a.stall_win = std::max(1, (int)std::ceil(0.05 * m));
@@ -711,6 +720,10 @@ void gmres_default_options(gmres_options* o) {
   o->batch_schedule = GMRES_SCHEDULE_AUTO;
   o->spmv_block_nnz = 0;
   o->a_storage = GMRES_A_COPY;
+  o->restart_repeat = 0;
+  o->restart_on_stall = 0;
+  o->orth_restart = 0.0;
+  o->orth_norm = GMRES_ORTH_SPECTRAL;
 }
 
 const char* gmres_strerror(int code) {

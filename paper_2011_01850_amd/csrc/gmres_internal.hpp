@@ -60,7 +60,7 @@ struct SysState {
   int32_t cycle;        // cycles started
   int32_t force;        // timing harness: run gated kernels regardless of state
   float enc_f;          // encode factor of the next 2-byte basis vector
-  float pad_;
+  int32_t klimit;       // two-stage restarts: the first cycle's length (0 until it ends)
 };
 
 // Work split of a persistent basis pass with G workgroups: workgroup b owns
@@ -140,6 +140,10 @@ struct KArgs {
   // options
   double tol;
   double restart_improve;
+  double orth_restart;      // loss-of-orthogonality trigger (0 = off)
+  int32_t orth_norm;        // 0 spectral, 1 Frobenius
+  int32_t restart_repeat;   // two-stage strategy
+  int32_t restart_on_stall; // stall-triggered restarts
   int64_t max_iters;
   int32_t stall_cycles;
   int32_t stall_win;  // max(1, ceil(0.05 m))

@@ -273,6 +273,7 @@ __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax
   if (t == 0) {
     if (!finite) {
       // drop the column; the cycle ends with the finite part of the basis
+      if (a.restart_repeat && S.klimit == 0 && j > 0) S.klimit = j;
       S.k = j;
       S.need_update = j > 0 ? 1 : 0;
       S.active = 0;
@@ -310,9 +311,17 @@ __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax
         if (J >= 0 && res > ar[J] / 1.001) S.first_stall = J;
       }
       const double bd = 16.0 * (double)(j + 1) * unit_roundoff(a.prec);
+      // restart triggers: the improvement threshold (first cycle only under
+      // the two-stage strategy), the first cycle's length (two-stage), a
+      // stalled Arnoldi residual
+      const bool first_stage = !a.restart_repeat || S.klimit == 0;
+      const int Js = j + 1 - a.stall_win;
       const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
                        S.iters >= a.max_iters ||
-                       (a.restart_improve > 0.0 && res <= a.restart_improve * S.beta);
+                       (a.restart_improve > 0.0 && first_stage && res <= a.restart_improve * S.beta) ||
+                       (!first_stage && j + 1 >= S.klimit) ||
+                       (a.restart_on_stall && Js >= 0 && res > ar[Js] / 1.001);
+      if (end && a.restart_repeat && S.klimit == 0) S.klimit = j + 1;
       if (a.prec == PBF16 || a.prec == PF16) {
         if (!end) {
           const int e = scale_exp(wmax / hn, a.prec);
@@ -1162,6 +1171,7 @@ __global__ void k_init_state(KArgs a) {
   S.prev_beta = INFINITY;
   S.precond_on = a.precond != 0 ? 1 : 0;
   S.first_stall = -1;
+  S.klimit = 0;
   a.st[s] = S;
 }
 

@@ -32,7 +32,8 @@ def _dev(t, dtype, torch):
 
 
 def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
-             autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy") -> L.Options:
+             autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
+             restart_on_stall=False, orth_restart=0.0, orth_norm="spectral") -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -47,6 +48,10 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.batch_schedule = L.SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
     o.spmv_block_nnz = int(spmv_block_nnz)
     o.a_storage = L.A_STORAGES[a_storage] if isinstance(a_storage, str) else int(a_storage)
+    o.restart_repeat = int(bool(restart_repeat))
+    o.restart_on_stall = int(bool(restart_on_stall))
+    o.orth_restart = float(orth_restart)
+    o.orth_norm = L.ORTH_NORMS[orth_norm] if isinstance(orth_norm, str) else int(orth_norm)
     return o
 
 
@@ -56,7 +61,8 @@ class Solver:
     def __init__(self, row_ptr, col_idx, vals, m=50, tol=1e-10, ortho="cgsr", precision="fp32",
                  precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
-                 a_storage="copy"):
+                 a_storage="copy", restart_repeat=False, restart_on_stall=False, orth_restart=0.0,
+                 orth_norm="spectral"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -67,7 +73,8 @@ class Solver:
         self.nnz = int(ci.numel())
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
-                            use_graph, autotune, schedule, spmv_block_nnz, a_storage)
+                            use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
+                            restart_on_stall, orth_restart, orth_norm)
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         torch.cuda.synchronize()
@@ -192,7 +199,8 @@ class BatchSolver:
 
     def __init__(self, systems, m=40, tol=1e-10, ortho="mgs", precision="fp32", precond="none",
                  max_iters=100_000, restart_improve=0.0, stall_cycles=10, use_graph=True, autotune=True,
-                 schedule="auto", spmv_block_nnz=0, a_storage="copy"):
+                 schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
+                 restart_on_stall=False, orth_restart=0.0, orth_norm="spectral"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -213,7 +221,8 @@ class BatchSolver:
         self.ns = ns
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
-                            use_graph, autotune, schedule, spmv_block_nnz, a_storage)
+                            use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
+                            restart_on_stall, orth_restart, orth_norm)
         arr64 = C.c_int64 * S
         arrp = C.c_void_p * S
         h = C.c_void_p()

@@ -41,6 +41,7 @@ def test_default_options(lib):
     assert o.ortho == L.CGSR and o.precision == L.MIXED_FP32 and o.precond == L.PRECOND_NONE
     assert o.restart_improve == 0.0 and o.stall_cycles == 10 and o.use_graph == 1 and o.autotune == 1
     assert o.batch_schedule == L.SCHEDULE_AUTO and o.spmv_block_nnz == 0 and o.a_storage == L.A_COPY
+    assert o.restart_repeat == 0 and o.restart_on_stall == 0 and o.orth_restart == 0.0 and o.orth_norm == 0
 
 
 def test_strerror(lib):
@@ -59,7 +60,9 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     for field, bad in [("m", 0), ("m", 257), ("tol", -1.0), ("ortho", 7), ("precision", 9),
                        ("precond", 5), ("stall_cycles", 0), ("restart_improve", -0.5), ("batch_schedule", 3),
                        ("batch_schedule", -1), ("spmv_block_nnz", 32), ("spmv_block_nnz", 100),
-                       ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1)]:
+                       ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1), ("restart_repeat", 2),
+                       ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
+                       ("orth_norm", 2)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -85,11 +88,13 @@ def test_handle_checks(lib):
 
 def test_struct_layouts_match_header():
     # offsets that C gives the two structs on x86-64
-    assert C.sizeof(L.Options) == 72
+    assert C.sizeof(L.Options) == 96
     assert L.Options.tol.offset == 8 and L.Options.max_iters.offset == 16
     assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
     assert L.Options.batch_schedule.offset == 60 and L.Options.spmv_block_nnz.offset == 64
-    assert L.Options.a_storage.offset == 68
+    assert L.Options.a_storage.offset == 68 and L.Options.restart_repeat.offset == 72
+    assert L.Options.restart_on_stall.offset == 76 and L.Options.orth_restart.offset == 80
+    assert L.Options.orth_norm.offset == 88
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 

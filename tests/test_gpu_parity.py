@@ -112,6 +112,39 @@ def test_split_storage_spmv_and_residual(n, long_rows):
     s_copy.close()
 
 
+@pytest.mark.parametrize("schedule", ["device_wide", "persistent"])
+def test_restart_strategies_match_oracle(schedule):
+    # float32 MGS GMRES(64) on a system float64 GMRES solves in one 42-step
+    # cycle: without a trigger the first float32 cycle runs on to m; the stall
+    # trigger and the two-stage strategy end cycles where the oracle's
+    # emulation of the same arithmetic ends them
+    A0 = P.convdiff(12, (5.0, 5.0))
+    b = P.manufactured_rhs(A0, 7, 12)[1]
+    M = O.Matrix.from_csr(A0)
+    m = 64
+    cases = [dict(), dict(restart_on_stall=True), dict(restart_improve=1e-5, restart_repeat=True)]
+    its = []
+    for kw in cases:
+        emu = O.gmres(M, b, m=m, tol=1e-10, ortho="mgs", precision="fp32", **kw)
+        assert emu.status == O.CONVERGED
+        if schedule == "persistent":
+            bs = BatchSolver([(A0.row_ptr, A0.col_idx, A0.vals)] * 2, m=m, ortho="mgs", precision="fp32",
+                             schedule="persistent", **kw)
+            xs, infos = bs.solve([b, b])
+            bs.close()
+            x, info = xs[0], infos[0]
+            assert infos[1]["iters"] == info["iters"]
+        else:
+            s = _solver(A0, m=m, ortho="mgs", precision="fp32", tol=1e-10, autotune=False, **kw)
+            x, info = s.solve(b)
+            s.close()
+        assert info["status"] == "CONVERGED" and _relres(A0, b, x.cpu().numpy()) <= 1e-10
+        assert info["restarts"] == emu.restarts, (kw, info, emu.iters, emu.restarts)
+        assert abs(info["iters"] - emu.iters) <= max(3, 0.1 * emu.iters), (kw, info["iters"], emu.iters)
+        its.append(info["iters"])
+    assert its[1] < 0.8 * its[0] and its[2] < 0.8 * its[0]
+
+
 @pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
 def test_split_storage_solves(ortho):
     pr, m = _case("3d17_ragged")

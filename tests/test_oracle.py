@@ -320,6 +320,57 @@ def test_two_byte_basis_still_reaches_double_accuracy(fmt):
 
 
 # --------------------------------------------------------------------------
+# restart strategies of the restart study (section 3)
+
+def _stall_case():
+    A0 = P.convdiff(24, (5.0, 5.0))
+    xt, b = P.manufactured_rhs(A0, 7, 24)
+    return O.Matrix.from_csr(A0), b
+
+
+def test_restart_on_stall_ends_each_cycle_at_its_stall_point():
+    # float32 MGS with a long restart length: the Arnoldi residual stops
+    # improving long before j = m; the trigger ends the cycle there
+    A, b = _stall_case()
+    m = 200
+    base = O.gmres(A, b, m=m, tol=1e-10, ortho="mgs", precision="fp32", record=True)
+    st = O.gmres(A, b, m=m, tol=1e-10, ortho="mgs", precision="fp32", record=True, restart_on_stall=True)
+    assert base.status == O.CONVERGED and st.status == O.CONVERGED
+    assert len(base.arnoldi[0]) == m  # without the trigger the first cycle runs to m
+    w = O.stall_window(m)
+    for c, arn in enumerate(st.arnoldi[:-1]):  # every cycle but the converging one
+        res = [st.history[c]] + list(arn)  # |s_1| .. |s_{k+1}|, relative to ||b||
+        J = O.stall_point(res, m)
+        assert J is not None and len(arn) == J + w
+    assert st.iters < 0.6 * base.iters
+    # where nothing stalls (float64) the trigger changes nothing
+    r64 = O.gmres(A, b, m=m, tol=1e-10, ortho="mgs")
+    s64 = O.gmres(A, b, m=m, tol=1e-10, ortho="mgs", restart_on_stall=True)
+    assert np.array_equal(r64.x, s64.x) and r64.iters == s64.iters
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_two_stage_restart_repeats_the_first_cycle_length(precision):
+    A, b = _stall_case()
+    delta = 1e-5
+    r = O.gmres(A, b, m=200, tol=1e-10, ortho="cgsr", precision=precision, record=True,
+                restart_improve=delta, restart_repeat=True)
+    assert r.status == O.CONVERGED and r.restarts >= 2
+    lens = [len(a) for a in r.arnoldi]
+    # the first cycle ends at the first step with |s_{j+1}| <= delta beta
+    first = r.arnoldi[0]
+    k1 = next(j + 1 for j, v in enumerate(first) if v <= delta * r.history[0])
+    assert lens[0] == k1
+    # every later cycle but the last has the same length (the threshold no
+    # longer applies: those cycles improve by less or more than delta)
+    assert all(L == k1 for L in lens[1:-1]) and lens[-1] <= k1
+    # without a threshold the first cycle runs to m: plain GMRES(m), bit for bit
+    p = O.gmres(A, b, m=60, tol=1e-10, ortho="cgsr", precision=precision)
+    q = O.gmres(A, b, m=60, tol=1e-10, ortho="cgsr", precision=precision, restart_repeat=True)
+    assert np.array_equal(p.x, q.x) and p.iters == q.iters
+
+
+# --------------------------------------------------------------------------
 # split storage of A (high and low 32-bit words of each float64 value)
 
 def test_high_word_value_hand_cases():

@@ -228,6 +228,41 @@ class Result:
         return STATUS_NAMES[self.status]
 
 
+# ---------------------------------------------------------------------------
+# Loss of orthogonality of the basis (the last restart strategy of section 3):
+# S_k = (I + U_k)^-1 U_k with U_k the strictly upper part of V_k^T V_k; the
+# basis is linearly dependent exactly when ||S_k||_2 = 1.
+
+def orth_s_append(OU, OS, c, u):
+    """Column c of U and S from u = V_{0..c-1}^T v_c.
+
+    Because S_{c+1} = [[S_c, (I + U_c)^-1 u], [0, 0]], only the new column
+    needs computing: the unit upper triangular system (I + U_c) s = u, solved
+    from the last row up.  OU and OS are square arrays updated in place;
+    returns s."""
+    OU[:c, c] = u
+    sv = np.array(u, dtype=np.float64)
+    for r in range(c - 1, -1, -1):
+        for l in range(r + 1, c):
+            sv[r] -= OU[r, l] * sv[l]
+    OS[:c, c] = sv
+    return sv
+
+
+def power_norm(S, iters=10):
+    """||S||_2 estimated by `iters` power iterations on S^T S from the
+    all-ones vector (normalised), then ||S x||."""
+    k = S.shape[0]
+    x = np.full(k, 1.0 / math.sqrt(k))
+    for _ in range(iters):
+        z = S.T @ (S @ x)
+        nz = float(np.linalg.norm(z))
+        if not nz > 0.0:
+            return 0.0
+        x = z / nz
+    return float(np.linalg.norm(S @ x))
+
+
 def _cast(v, precision):
     return np.asarray(v, dtype=np.float64 if precision == "fp64" else np.float32)
 
@@ -235,7 +270,7 @@ def _cast(v, precision):
 def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
           precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
           fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy",
-          restart_repeat=False, restart_on_stall=False):
+          restart_repeat=False, restart_on_stall=False, orth_restart=0.0, orth_norm="spectral"):
     """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
 
     ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> z applied
@@ -251,7 +286,10 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     two-stage strategy (the first cycle ends as usual; every later one after
     as many inner iterations as the first took; the improvement threshold
     only applies to the first cycle); ``restart_on_stall`` ends a cycle once
-    the Arnoldi residual has stalled over the window of ``stall_window``.
+    the Arnoldi residual has stalled over the window of ``stall_window``;
+    ``orth_restart`` > 0 ends a cycle once ||S_k|| (``orth_norm``: the
+    10-step power estimate of the 2-norm, or the Frobenius norm) of the basis
+    built so far reaches it.
     """
     if ortho not in ("mgs", "cgsr"):
         raise ValueError(ortho)
@@ -343,6 +381,10 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         k = 0
         cycle_arn = []
         ares = [beta]  # |s_1| .. |s_{j+1}| of this cycle
+        if orth_restart > 0.0:
+            OU = np.zeros((m + 1, m + 1))
+            OS = np.zeros((m + 1, m + 1))
+            fro2 = 0.0
         for j in range(m):
             vj = basis(j)
             # w <- A v_j (flexible form: z_j = M v_j, w <- A z_j)
@@ -406,6 +448,14 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 break
             if restart_on_stall and j + 1 - win >= 0 and ares[j + 1] > ares[j + 1 - win] / 1.001:
                 break
+            if orth_restart > 0.0:
+                vn = basis(j + 1).astype(np.float64)
+                u = np.array([float(np.dot(basis(i).astype(np.float64), vn)) for i in range(j + 1)])
+                sv = orth_s_append(OU, OS, j + 1, u)
+                fro2 += float(sv @ sv)
+                nrm = math.sqrt(fro2) if orth_norm == "frobenius" else power_norm(OS[: j + 2, : j + 2])
+                if nrm >= orth_restart:
+                    break
         if restart_repeat and klimit == 0 and k > 0:
             klimit = k
         # correction u = V_j H^-1 s (Z y in the flexible form), applied in full precision

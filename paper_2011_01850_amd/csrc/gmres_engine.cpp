@@ -167,7 +167,7 @@ bool valid_options(const gmres_options* o) {
   if (o->restart_on_stall != 0 && o->restart_on_stall != 1) return false;
   if (!(o->orth_restart >= 0.0) || !std::isfinite(o->orth_restart)) return false;
   if (o->orth_norm != GMRES_ORTH_SPECTRAL && o->orth_norm != GMRES_ORTH_FROBENIUS) return false;
-  if (o->orth_restart > 0.0) return false;  // loss-of-orthogonality monitor: not available yet
+  if (o->orth_restart > 0.0 && o->m > kMaxOrthM) return false;  // U and S of the monitor sit in LDS
   return true;
 }
 
@@ -349,6 +349,7 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
       if (e == hipSuccess) e = launch_final_pass(a, j, st);
     }
     if (e == hipSuccess && two && j + 1 <= a.m) e = launch_encode(a, j + 1, st);
+    if (e == hipSuccess && a.orth_restart > 0.0) e = launch_orth_check(a, j, st);
   }
   if (e == hipSuccess) e = launch_backsolve(a, st);
   if (e == hipSuccess) e = launch_update(a, st);
@@ -567,6 +568,11 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.sc = h->alloc<double>(nsys * M1);
   hip_check(hipMemsetAsync(a.sc, 0, nsys * M1 * 8, h->stream));
   a.hacc = h->alloc<double>(nsys * M2);
+  if (opt->orth_restart > 0.0) {
+    a.ou = h->alloc<double>((size_t)nsys * M1 * M1);
+    a.os = h->alloc<double>((size_t)nsys * M1 * M1);
+    a.ocol = h->alloc<double>((size_t)nsys * M1);
+  }
   a.h1 = h->alloc<double>(nsys * M2);
   a.coef = h->alloc<double>(nsys * M2);
   a.ares = h->alloc<double>(nsys * M1);

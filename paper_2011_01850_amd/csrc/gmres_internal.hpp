@@ -18,6 +18,7 @@ constexpr int kHistCap = 4096;
 constexpr int kMaxOcc = 8;       // persistent grids of ncu * k workgroups, k = 1..kMaxOcc
 constexpr int kMaxPM = 64;       // persistent batch schedule: restart length limit
 constexpr int kMaxPR = 64;       //   and rows per thread (systems up to 1024 * 64 rows)
+constexpr int kMaxOrthM = 64;    // loss-of-orthogonality monitor: restart length limit
 
 // SpMV row sums follow one canonical order that depends only on the row's
 // length len: T = row_lanes(len) partial sums, partial l adding products
@@ -61,6 +62,8 @@ struct SysState {
   int32_t force;        // timing harness: run gated kernels regardless of state
   float enc_f;          // encode factor of the next 2-byte basis vector
   int32_t klimit;       // two-stage restarts: the first cycle's length (0 until it ends)
+  double orth_fro2;     // loss-of-orthogonality monitor: ||S_k||_F^2 of the current cycle
+  double orth_norm;     //   and the last norm it compared with the threshold
 };
 
 // Work split of a persistent basis pass with G workgroups: workgroup b owns
@@ -139,6 +142,9 @@ struct KArgs {
   double* hist;   // restart residual history, kHistCap per system
   // options
   double tol;
+  double* ou;      // loss-of-orthogonality monitor, per system (m+1)^2 each: U = strictly upper
+  double* os;      //   part of V^T V and S = (I + U)^-1 U, column-major
+  double* ocol;    //   the new column of U, (m+1) per system
   double restart_improve;
   double orth_restart;      // loss-of-orthogonality trigger (0 = off)
   int32_t orth_norm;        // 0 spectral, 1 Frobenius
@@ -161,6 +167,9 @@ hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin
 hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
 hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
 hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st);
+// Loss-of-orthogonality monitor after step j: column j+1 of U and S, the
+// norm of S, and the end of the cycle when it reaches the threshold.
+hipError_t launch_orth_check(const KArgs& a, int j, hipStream_t st);
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st);
 // the kernel that completes CGS projection 2 at column j (timing)
 hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st);

@@ -659,6 +659,8 @@ __device__ __forceinline__ void store_colsums(double* part, int nrows, int k, in
 // CGSR projection, first half: quantities col0 .. of V^T w for the columns
 // [col0, col0 + L) below j + 1, plus ||w||^2 (quantity j + 1) when col0 = 0
 // and mode = 1.  mode 2: the second projection's dots when j + 1 > 64.
+// mode 3: the loss-of-orthogonality monitor's dots, with basis column j + 1
+// (as stored, before its decode scale) in place of w.
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int col0, int mode, int rev) {
   using ACC = typename AccOf<TV>::type;
@@ -666,6 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
   const int lane = threadIdx.x & 63;
   const int ncol = min(L, j + 1 - col0);
   const TW* w = reinterpret_cast<const TW*>(a.w);
+  const TV* wv = reinterpret_cast<const TV*>(a.V) + (int64_t)(j + 1) * a.ld;
   const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, col0 + ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
   const uint32_t c0off = (uint32_t)col0 * cstride;
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
       asm volatile("" : "+s"(cs));
       const int64_t r = tile_row(sg, k, u, rev);
       const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV)) + c0off;
-      const ACC wr = (ACC)w[r];
+      const ACC wr = mode == 3 ? (ACC)ldv(wv[r]) : (ACC)w[r];
       ww += wr * wr;
       ACC p[L];
       if (sizeof(TV) != 2 && u < nfirst)
@@ -1055,6 +1058,111 @@ __global__ __launch_bounds__(kBlock) void k_fin_cols(KArgs a, SegTab sg, int j) 
   a.coef[(int64_t)s * M2 + q] = h * scq;
 }
 
+// Loss-of-orthogonality monitor (the last restart strategy of section 3).
+// u = V_j^T v_{j+1} with the decoded columns: workgroup (s, q) reduces
+// quantity q of system s.
+__global__ __launch_bounds__(kBlock) void k_orth_cols(KArgs a, SegTab sg, int j) {
+  const int s = blockIdx.x, q = blockIdx.y;
+  const SysState& S = a.st[s];
+  if (!S.active && !S.force) return;
+  const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + sg.sys_sg0[s], sg.sys_nsg[s]);
+  if (threadIdx.x != 0) return;
+  const int M1 = a.m + 1;
+  a.ocol[(int64_t)s * M1 + q] = v * a.sc[(int64_t)s * M1 + q] * a.sc[(int64_t)s * M1 + j + 1];
+}
+
+// Column c = j + 1 of U and of S = (I + U)^-1 U (S_{k+1} = [S_k, (I + U_k)^-1 u;
+// 0, 0], a back-substitution with the unit upper triangular I + U_k), then
+// ||S||_F (running sum) or ||S||_2 (10 power iterations on S^T S from the
+// all-ones vector, then ||S x||); the cycle ends once it reaches the
+// threshold.  One workgroup per system; U, then S, staged in LDS.
+__global__ __launch_bounds__(kBlock) void k_orth_fin(KArgs a, int j) {
+  __shared__ double mat[(kMaxOrthM + 1) * (kMaxOrthM + 1)];
+  __shared__ double sv[kMaxOrthM + 2], xv[kMaxOrthM + 2], yv[kMaxOrthM + 2];
+  __shared__ double red[kBlock / 64];
+  const int s = blockIdx.x, t = threadIdx.x;
+  SysState& S = a.st[s];
+  if (!S.active && !S.force) return;
+  const int M1 = a.m + 1, c = j + 1, k = j + 2;  // S is k x k; new column c
+  double* OU = a.ou + (int64_t)s * M1 * M1;
+  double* OS = a.os + (int64_t)s * M1 * M1;
+  const double* u = a.ocol + (int64_t)s * M1;
+  // U's leading c x c block (columns 1..c-1 hold data; column-major, stride M1)
+  for (int i = t; i < c * c; i += kBlock) {
+    const int col = i / c, row = i % c;
+    mat[col * c + row] = row < col ? OU[(int64_t)col * M1 + row] : 0.0;
+  }
+  for (int i = t; i < c; i += kBlock) {
+    sv[i] = u[i];
+    OU[(int64_t)c * M1 + i] = u[i];
+  }
+  __syncthreads();
+  if (t == 0) {  // (I + U) s = u, rows c-1 .. 0
+    for (int r = c - 1; r >= 0; --r) {
+      double acc = sv[r];
+      for (int l = r + 1; l < c; ++l) acc -= mat[l * c + r] * sv[l];
+      sv[r] = acc;
+    }
+  }
+  __syncthreads();
+  double f2 = 0.0;
+  for (int i = t; i < c; i += kBlock) {
+    OS[(int64_t)c * M1 + i] = sv[i];
+    f2 += sv[i] * sv[i];
+  }
+  f2 = block_sum(f2);
+  const double fro2 = (j == 0 ? 0.0 : S.orth_fro2) + f2;
+  double nrm = sqrt(fro2);
+  if (a.orth_norm == 0) {
+    // S in LDS (k x k, column-major, zero on and below the diagonal)
+    __syncthreads();
+    for (int i = t; i < k * k; i += kBlock) {
+      const int col = i / k, row = i % k;
+      mat[col * k + row] = (row < col && col >= 1) ? (col == c ? sv[row] : OS[(int64_t)col * M1 + row]) : 0.0;
+    }
+    const double x0 = 1.0 / sqrt((double)k);
+    for (int i = t; i < k; i += kBlock) xv[i] = x0;
+    __syncthreads();
+    bool zero = false;
+    for (int it = 0; it < 10 && !zero; ++it) {
+      for (int i = t; i < k; i += kBlock) {  // y = S x
+        double acc = 0.0;
+        for (int l = i + 1; l < k; ++l) acc += mat[l * k + i] * xv[l];
+        yv[i] = acc;
+      }
+      __syncthreads();
+      double z2 = 0.0;
+      double zi = 0.0;
+      if (t < k) {  // z = S^T y, thread t owns column t
+        for (int l = 0; l < t; ++l) zi += mat[t * k + l] * yv[l];
+        z2 = zi * zi;
+      }
+      z2 = block_sum(z2);
+      if (!(z2 > 0.0)) {
+        zero = true;
+      } else if (t < k) {
+        xv[t] = zi / sqrt(z2);
+      }
+      __syncthreads();
+    }
+    double y2 = 0.0;
+    if (!zero) {
+      if (t < k) {  // ||S x|| with the final x
+        double acc = 0.0;
+        for (int l = t + 1; l < k; ++l) acc += mat[l * k + t] * xv[l];
+        y2 = acc * acc;
+      }
+    }
+    y2 = block_sum(y2);
+    nrm = zero ? 0.0 : sqrt(y2);
+  }
+  if (t == 0) {
+    S.orth_fro2 = fro2;
+    S.orth_norm = nrm;
+    if (!S.force && nrm >= a.orth_restart) S.active = 0;  // end the cycle after this step
+  }
+}
+
 // ------------------------------------------------------------ tile kernels
 // One workgroup per 256-row tile, one row per thread.
 
@@ -1172,6 +1280,8 @@ __global__ void k_init_state(KArgs a) {
   S.precond_on = a.precond != 0 ? 1 : 0;
   S.first_stall = -1;
   S.klimit = 0;
+  S.orth_fro2 = 0.0;
+  S.orth_norm = 0.0;
   a.st[s] = S;
 }
 
@@ -1573,6 +1683,25 @@ hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fi
   if (e0 != hipSuccess || !with_fin) return e0;
   hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, src, used->nseg, used->sys_sg0,
                      used->sys_nsg, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_orth_check(const KArgs& a, int j, hipStream_t st) {
+  const SegTab* used = nullptr;
+  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const int ncol = j + 1;
+    if (ncol <= 64) return launch_mdot_window<TV, TW>(a, j, 0, 3, lanes_for(ncol), st, &used);
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+      hipError_t e2 = launch_mdot_window<TV, TW>(a, j, c0, 3, 64, st, &used);
+      if (e2 != hipSuccess) return e2;
+    }
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_orth_cols, dim3(a.S, j + 1), dim3(kBlock), 0, st, a, *used, j);
+  hipLaunchKernelGGL(k_orth_fin, dim3(a.S), dim3(kBlock), 0, st, a, j);
   return hipGetLastError();
 }
 

@@ -66,6 +66,11 @@ def test_invalid_arguments_rejected_before_device_work(lib):
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
+    # the loss-of-orthogonality monitor keeps U and S in LDS: m <= 64
+    ob = L.default_options()
+    ob.orth_restart = 0.5
+    ob.m = 65
+    assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL
     # preconditioning is defined for the mixed modes only
     ob = L.default_options()
     ob.precision = L.FP64

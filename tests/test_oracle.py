@@ -370,6 +370,68 @@ def test_two_stage_restart_repeats_the_first_cycle_length(precision):
     assert np.array_equal(p.x, q.x) and p.iters == q.iters
 
 
+def _s_from_basis(V):
+    k = V.shape[1]
+    OU = np.zeros((k, k))
+    OS = np.zeros((k, k))
+    for c in range(1, k):
+        O.orth_s_append(OU, OS, c, V[:, :c].T @ V[:, c])
+    return OU, OS
+
+
+def test_orth_s_matrix_properties():
+    g = np.random.default_rng(11)
+    # orthonormal basis: U = 0, so S = 0
+    Q, _ = np.linalg.qr(g.standard_normal((50, 8)))
+    _, S = _s_from_basis(Q)
+    assert np.max(np.abs(S)) < 1e-14
+    # two unit vectors with cosine c: S = U = [[0, c], [0, 0]], ||S||_2 = |c|
+    v1 = np.array([1.0, 0.0, 0.0])
+    v2 = np.array([0.6, 0.8, 0.0])
+    _, S = _s_from_basis(np.stack([v1, v2], 1))
+    assert np.allclose(S, [[0.0, 0.6], [0.0, 0.0]], atol=1e-15)
+    # unit columns that are linearly dependent: ||S||_2 = 1 (the criterion)
+    v3 = (Q[:, 0] + Q[:, 1]) / np.sqrt(2.0)
+    V = np.concatenate([Q[:, :3], v3[:, None], Q[:, 3:5]], axis=1)
+    _, S = _s_from_basis(V)
+    assert abs(np.linalg.norm(S, 2) - 1.0) < 1e-12
+    # ... and independent but non-orthogonal unit columns: below 1, and the
+    # leading blocks (earlier steps) never have a larger norm
+    W = g.standard_normal((40, 7))
+    W /= np.linalg.norm(W, axis=0)
+    _, S = _s_from_basis(W)
+    norms = [np.linalg.norm(S[:c, :c], 2) for c in range(1, 8)]
+    assert norms[-1] < 1.0 and all(a <= b + 1e-15 for a, b in zip(norms, norms[1:]))
+    # the appended columns reproduce the definition (I + U)^-1 U
+    U = np.triu(W.T @ W, 1)
+    assert np.allclose(S, np.linalg.solve(np.eye(7) + U, U), atol=1e-13)
+
+
+def test_power_norm_estimate():
+    g = np.random.default_rng(12)
+    S = np.triu(g.standard_normal((9, 9)), 1)
+    est = O.power_norm(S)
+    true = np.linalg.norm(S, 2)
+    assert est <= true * (1 + 1e-12)  # a Rayleigh-quotient estimate never exceeds the norm
+    assert est >= 0.9 * true
+    assert O.power_norm(np.zeros((4, 4))) == 0.0
+    assert O.power_norm(S, iters=200) == pytest.approx(true, rel=1e-9)
+
+
+@pytest.mark.parametrize("norm,tau", [("spectral", 0.5), ("frobenius", 0.5)])
+def test_orth_restart_ends_cycles_when_the_basis_loses_orthogonality(norm, tau):
+    A, b = (lambda A0: (O.Matrix.from_csr(A0), P.manufactured_rhs(A0, 7, 12)[1]))(P.convdiff(12, (5.0, 5.0)))
+    base = O.gmres(A, b, m=64, tol=1e-10, ortho="mgs", precision="fp32", record=True)
+    r = O.gmres(A, b, m=64, tol=1e-10, ortho="mgs", precision="fp32", record=True, orth_restart=tau,
+                orth_norm=norm)
+    assert r.status == O.CONVERGED and r.iters < base.iters
+    assert len(r.arnoldi[0]) < 64 == len(base.arnoldi[0])
+    # float64 CGSR keeps the basis orthogonal to working accuracy: never fires
+    p = O.gmres(A, b, m=64, tol=1e-10, ortho="cgsr")
+    q = O.gmres(A, b, m=64, tol=1e-10, ortho="cgsr", orth_restart=tau, orth_norm=norm)
+    assert np.array_equal(p.x, q.x) and p.iters == q.iters
+
+
 # --------------------------------------------------------------------------
 # split storage of A (high and low 32-bit words of each float64 value)
 

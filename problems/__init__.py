@@ -241,6 +241,21 @@ def c2_convdiff3d(N: int = 128) -> Problem:
     return Problem(f"convdiff3d_N{N}", A, b, xt, 50, 1e-10, "cgsr")
 
 
+def restart_study_3d(N: int = 128, shift: float = 1.0) -> Problem:
+    """The 3-D convection-diffusion operator of C2 plus shift * 6/h^2 on the
+    diagonal: well conditioned, so float64 GMRES converges within one short
+    cycle and a float32 Arnoldi process stalls well before a long restart
+    length (the regime of the restart-strategy study)."""
+    A = convdiff(N, (50.0, 20.0, 10.0))
+    h = 1.0 / (N + 1)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    vals = A.vals.copy()
+    vals[rows == A.col_idx] += shift * 6.0 / h ** 2
+    A = CSR(A.n, A.row_ptr, A.col_idx, vals, {"family": "convdiff_shifted", "N": N, "shift": shift})
+    xt, b = manufactured_rhs(A, 8, N)
+    return Problem(f"convdiff3d_shifted_N{N}", A, b, xt, 64, 1e-10, "mgs")
+
+
 def c3_powerlaw(n: int = 1_000_000) -> Problem:
     """Power-law random sparse system, GMRES(30) with CGSR and a 2-byte basis."""
     A = powerlaw(n, 3, 0)

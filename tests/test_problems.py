@@ -83,3 +83,14 @@ def test_rhs_and_batch_specs_are_seeded():
     Ns = [s[0] for s in specs]
     assert min(Ns) >= 32 and max(Ns) <= 256
     assert all(0 <= b <= 100 for s in specs for b in s[1])
+
+
+def test_restart_study_system_is_c2_plus_a_diagonal_shift():
+    a = P.convdiff(12, (50.0, 20.0, 10.0))
+    pr = P.restart_study_3d(12, shift=1.0)
+    assert np.array_equal(pr.A.row_ptr, a.row_ptr) and np.array_equal(pr.A.col_idx, a.col_idx)
+    rows = np.repeat(np.arange(a.n), np.diff(a.row_ptr))
+    d = rows == a.col_idx
+    h = 1.0 / 13
+    assert np.allclose(pr.A.vals[d] - a.vals[d], 6.0 / h ** 2, rtol=1e-14)
+    assert np.array_equal(pr.A.vals[~d], a.vals[~d])

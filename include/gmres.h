@@ -69,8 +69,15 @@ enum {
  *        schedule. */
 enum { GMRES_A_COPY = 0, GMRES_A_SPLIT = 1 };
 
-/* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y) */
-enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2 };
+/* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y).
+ * ILU0: incomplete LU without fill (the preconditioner of the paper's
+ * experiments), factored on the GPU in float64 at create time (rows in
+ * dependency levels; every row must store its diagonal) and applied in
+ * float32 as z = U^-1 L^-1 v by ilu_sweeps Jacobi sweeps per triangle from a
+ * zero start, or exactly (ilu_sweeps = 0: as many sweeps as the triangle has
+ * levels).  The paper applies ILU(0) on the left; here it is applied on the
+ * right, so GMRES keeps minimising the true residual. */
+enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2, GMRES_PRECOND_ILU0 = 3 };
 
 /* gmres_options.batch_schedule.
  * DEVICE_WIDE: every kernel launch covers all systems of the handle (any
@@ -135,6 +142,7 @@ typedef struct {
   int32_t restart_on_stall;
   double orth_restart;
   int32_t orth_norm;
+  int32_t ilu_sweeps;       /* GMRES_PRECOND_ILU0: Jacobi sweeps per triangle (0 = exact), 0..4096 */
 } gmres_options;
 
 enum { GMRES_ORTH_SPECTRAL = 0, GMRES_ORTH_FROBENIUS = 1 };
@@ -153,7 +161,7 @@ typedef struct {
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
- * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL. */
+ * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).
@@ -208,10 +216,18 @@ const char* gmres_strerror(int code);
 int gmres_residual(gmres_handle h, const double* b, const double* x, double* r, double* norm_out);
 
 /* y = A x with the stored float64 values (precision = GMRES_FP64, x and y
- * float64) or the stored float32 copy (GMRES_MIXED_FP32, float32 x, y).
- * The mixed copy exists only on mixed-precision handles (else ESTATE);
+ * float64) or the float32 values of the Arnoldi product (GMRES_MIXED_FP32,
+ * float32 x, y: the float32 copy, or the high words under SPLIT storage).
+ * The float32 values exist only on mixed-precision handles (else ESTATE);
  * single-system handles only (ESTATE on a batch handle). */
 int gmres_spmv(gmres_handle h, int32_t precision, const void* x, void* y);
+
+/* z = M^-1 v for a single-system handle created with
+ * precond = GMRES_PRECOND_ILU0: the ILU(0) application of the Arnoldi loop
+ * (float32 sweeps as configured by ilu_sweeps).  v and z are float32[n]
+ * device arrays.  Errors: EINVAL (null pointer), ESTATE (another
+ * preconditioner, or several systems). */
+int gmres_precond_apply(gmres_handle h, const float* v, float* z);
 
 /* Store v = w * inv_h in a 2-byte format (precision GMRES_MIXED_BF16 or
  * GMRES_MIXED_FP16) exactly as the solver stores a basis vector: with

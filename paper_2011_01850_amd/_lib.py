@@ -9,14 +9,14 @@ LIB_PATH = os.path.join(HERE, "libgmres.so")
 
 MGS, CGSR = 0, 1
 FP64, MIXED_FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
-PRECOND_NONE, PRECOND_JACOBI, PRECOND_SPAI = 0, 1, 2
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_SPAI, PRECOND_ILU0 = 0, 1, 2, 3
 RUNNING, CONVERGED, MAXITER, STALLED = 0, 1, 2, 3
 OK, EINVAL, EHIP, ENOMEM, EHANDLE, ESTATE = 0, -1, -2, -3, -4, -5
 
 STATUS_NAMES = {RUNNING: "RUNNING", CONVERGED: "CONVERGED", MAXITER: "MAXITER", STALLED: "STALLED"}
 PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
 ORTHOS = {"mgs": MGS, "cgsr": CGSR}
-PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "spai": PRECOND_SPAI}
+PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "spai": PRECOND_SPAI, "ilu0": PRECOND_ILU0}
 SCHEDULE_AUTO, SCHEDULE_DEVICE_WIDE, SCHEDULE_PERSISTENT = 0, 1, 2
 SCHEDULES = {"auto": SCHEDULE_AUTO, "device_wide": SCHEDULE_DEVICE_WIDE, "persistent": SCHEDULE_PERSISTENT}
 A_COPY, A_SPLIT = 0, 1
@@ -44,6 +44,7 @@ class Options(C.Structure):
         ("restart_on_stall", C.c_int32),
         ("orth_restart", C.c_double),
         ("orth_norm", C.c_int32),
+        ("ilu_sweeps", C.c_int32),
     ]
 
 
@@ -83,6 +84,7 @@ _SIGS = {
     "gmres_destroy": (C.c_int, [_vp]),
     "gmres_residual": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
     "gmres_spmv": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
+    "gmres_precond_apply": (C.c_int, [_vp, _vp, _vp]),
     "gmres_encode": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_double, _vp, C.POINTER(C.c_double), _vp]),
     "gmres_last_cycle": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _vp, _vp]),
     "gmres_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, C.POINTER(C.c_int32)]),

@@ -155,7 +155,8 @@ bool valid_options(const gmres_options* o) {
   if (o->max_iters < 0) return false;
   if (o->ortho != GMRES_MGS && o->ortho != GMRES_CGSR) return false;
   if (o->precision < GMRES_FP64 || o->precision > GMRES_MIXED_FP16) return false;
-  if (o->precond < GMRES_PRECOND_NONE || o->precond > GMRES_PRECOND_SPAI) return false;
+  if (o->precond < GMRES_PRECOND_NONE || o->precond > GMRES_PRECOND_ILU0) return false;
+  if (o->ilu_sweeps < 0 || o->ilu_sweeps > 4096) return false;
   if (o->precond != GMRES_PRECOND_NONE && o->precision == GMRES_FP64) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
@@ -405,6 +406,8 @@ void autotune_spmv(gmres_ctx* h) {
   hip_check(hipStreamSynchronize(h->stream));
 }
 
+void setup_ilu0(gmres_ctx* h, int32_t sweeps);
+
 void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, const int32_t* const* rp,
            const int32_t* const* ci, const double* const* vals, const gmres_options* opt, void* user_stream) {
   h->opt = *opt;
@@ -597,6 +600,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     hip_check(hipMemsetAsync(d, 0, (h->nnz + 4) * 4, h->stream));
     a.mval = d;
   }
+  if (opt->precond == GMRES_PRECOND_ILU0) setup_ilu0(h, opt->ilu_sweeps);
   // ---- SpMV row blocks of every budget this handle may use (the autotuner's
   // candidates, else the fixed one), built in parallel on the host
   const bool tune = !h->persistent && opt->autotune && opt->spmv_block_nnz == 0;
@@ -696,6 +700,76 @@ gmres_ctx* get(gmres_handle h) {
   return h;
 }
 
+// ILU(0) at create time: diagonal positions and dependency levels of the
+// lower triangle on the host, the factorisation level by level on the device
+// (float64, on a copy of A's values), then float32 factors for the sweeps.
+// Every row must store its diagonal entry.
+void setup_ilu0(gmres_ctx* h, int32_t sweeps) {
+  KArgs& a = h->a;
+  const int64_t ld = h->ld;
+  std::vector<int32_t> ci(h->nnz);
+  if (h->nnz) hip_check(hipMemcpy(ci.data(), a.ci, h->nnz * 4, hipMemcpyDeviceToHost));
+  const std::vector<int32_t>& rp = h->rp_host;
+  std::vector<int32_t> diag(ld);
+  for (int64_t r = 0; r < ld; ++r) {
+    diag[r] = -1;
+    for (int p = rp[r]; p < rp[r + 1]; ++p)
+      if (ci[p] == r) diag[r] = p;
+    if (diag[r] < 0) {
+      if (rp[r] != rp[r + 1]) throw Fail{GMRES_EINVAL};  // a real row without its diagonal
+      diag[r] = rp[r];  // padding row: empty ranges
+    }
+  }
+  // levels: lower triangle (factorisation and L sweeps), upper triangle (U sweeps)
+  std::vector<int32_t> lvl(ld, 0), ulv(ld, 0);
+  int32_t depth_l = 0, depth_u = 0;
+  for (int64_t r = 0; r < ld; ++r) {
+    int32_t v = 0;
+    for (int p = rp[r]; p < diag[r]; ++p) v = std::max(v, lvl[ci[p]] + 1);
+    lvl[r] = v;
+    depth_l = std::max(depth_l, v + 1);
+  }
+  for (int64_t r = ld - 1; r >= 0; --r) {
+    int32_t v = 0;
+    for (int p = diag[r] + 1; p < rp[r + 1]; ++p) v = std::max(v, ulv[ci[p]] + 1);
+    ulv[r] = v;
+    depth_u = std::max(depth_u, v + 1);
+  }
+  std::vector<int32_t> count(depth_l + 1, 0), order(ld);
+  for (int64_t r = 0; r < ld; ++r) ++count[lvl[r] + 1];
+  for (int l = 0; l < depth_l; ++l) count[l + 1] += count[l];
+  {
+    std::vector<int32_t> fill(count.begin(), count.end() - 1);
+    for (int64_t r = 0; r < ld; ++r) order[fill[lvl[r]]++] = (int32_t)r;
+  }
+  int32_t* d_diag = upload32(h, diag);
+  int32_t* d_order = upload32(h, order);
+  a.diagpos = d_diag;
+  double* lu = h->alloc<double>(h->nnz + 4);
+  const double* vals = a.asplit ? nullptr : a.a64;
+  if (a.asplit) {
+    hip_check(launch_merge_words(a.ahi, a.alo, lu, h->nnz, h->stream));
+  } else if (h->nnz) {
+    hip_check(hipMemcpyAsync(lu, vals, h->nnz * 8, hipMemcpyDeviceToDevice, h->stream));
+  }
+  for (int l = 0; l < depth_l; ++l)
+    hip_check(launch_ilu_factor(a, lu, d_order + count[l], count[l + 1] - count[l], h->stream));
+  float* lu32 = h->alloc<float>(h->nnz + 4);
+  float* dinv = h->alloc<float>(ld);
+  hip_check(launch_ilu_finish(a, lu, lu32, dinv, h->stream));
+  a.ilu32 = lu32;
+  a.iludinv = dinv;
+  a.ilu_v = h->alloc<float>(ld);
+  for (int k = 0; k < 3; ++k) {
+    a.ilu_b[k] = h->alloc<float>(ld);
+    hip_check(hipMemsetAsync(a.ilu_b[k], 0, ld * 4, h->stream));
+  }
+  hip_check(hipMemsetAsync(a.ilu_v, 0, ld * 4, h->stream));
+  a.ilu_sl = sweeps > 0 ? sweeps : std::max(1, depth_l);
+  a.ilu_su = sweeps > 0 ? sweeps : std::max(1, depth_u);
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
 // A's float64 values as one array (merged from the two word arrays in SPLIT
 // storage); enqueued on the handle's stream.
 const double* a64_values(gmres_ctx* h) {
@@ -730,6 +804,7 @@ void gmres_default_options(gmres_options* o) {
   o->restart_on_stall = 0;
   o->orth_restart = 0.0;
   o->orth_norm = GMRES_ORTH_SPECTRAL;
+  o->ilu_sweeps = 4;
 }
 
 const char* gmres_strerror(int code) {
@@ -951,6 +1026,28 @@ int gmres_residual(gmres_handle hh, const double* b, const double* x, double* r,
     double sq = 0.0;
     for (int i = 0; i < h->nrb; ++i) sq += part[(size_t)i];
     if (norm_out) *norm_out = std::sqrt(sq);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_precond_apply(gmres_handle hh, const float* v, float* z) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!v || !z) return GMRES_EINVAL;
+    if (h->opt.precond != GMRES_PRECOND_ILU0 || h->sys.size() != 1) return GMRES_ESTATE;
+    const int64_t n = h->sys[0].n;
+    after_caller(h);
+    hip_check(hipMemsetAsync(h->a.ilu_v, 0, h->ld * 4, h->stream));
+    hip_check(hipMemcpyAsync(h->a.ilu_v, v, n * 4, hipMemcpyDeviceToDevice, h->stream));
+    float* out = reinterpret_cast<float*>(h->ys);  // ld doubles of staging, used as float32 here
+    hip_check(launch_set_force(h->a, 1, h->stream));
+    hip_check(launch_ilu_apply(h->a, out, h->stream));
+    hip_check(launch_set_force(h->a, 0, h->stream));
+    hip_check(hipMemcpyAsync(z, out, n * 4, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
     return GMRES_OK;
   } catch (const Fail& f) {
     (void)hipGetLastError();

@@ -106,6 +106,12 @@ struct KArgs {
   int32_t asplit;       // 1: SPLIT storage
   const float* mval;   // SPAI values (float32, A's pattern)
   const float* dinv;   // Jacobi: 1 / a_ii
+  const float* ilu32;  // ILU(0) factors on A's pattern (float32): L below the diagonal, U the rest
+  const float* iludinv;  // 1 / u_ii
+  const int32_t* diagpos;  // index of each row's diagonal entry (padding rows: their empty start)
+  float* ilu_v;        // ILU application: the scaled v_j and three work vectors (ld rows each)
+  float* ilu_b[3];
+  int32_t ilu_sl, ilu_su;  // sweeps on L and on U
   const int32_t* rb;       // row-block first rows [nrb + 1]
   const int32_t* rb_sys;   // system of each row block
   const int32_t* rb_lanes; // lanes per row of each row block: max row_lanes over its rows
@@ -183,6 +189,12 @@ hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStrea
 hipError_t launch_split_words(const double* src, uint32_t* hi, uint32_t* lo, int64_t n, hipStream_t st);
 hipError_t launch_merge_words(const uint32_t* hi, const uint32_t* lo, double* dst, int64_t n, hipStream_t st);
 hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st);
+// ILU(0) factorisation of the rows rows[0, count) (one dependency level), in place on lu
+hipError_t launch_ilu_factor(const KArgs& a, double* lu, const int32_t* rows, int32_t count, hipStream_t st);
+// z = U^-1 L^-1 ilu_v by the configured sweeps, the result in dst
+hipError_t launch_ilu_apply(const KArgs& a, float* dst, hipStream_t st);
+// float32 factors and 1/u_ii from the float64 factors
+hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, hipStream_t st);
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st);

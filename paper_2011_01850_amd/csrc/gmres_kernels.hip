@@ -1195,6 +1195,87 @@ __global__ __launch_bounds__(kBlock) void k_jacobi(KArgs a, int j) {
   a.Z[(int64_t)j * a.ld + r] = on ? (a.dinv[r] * vr) * scale : vr * scale;
 }
 
+// ---------------------------------------------------------- ILU(0)
+// Factorisation of one dependency level (every row whose lower-triangle
+// columns lie in earlier levels), one thread per row, in place on A's float64
+// values: for each stored a_ik, k < i, ascending, l_ik = a_ik / u_kk, then
+// every later entry a_ij of the row that row k also stores loses l_ik u_kj
+// (a merge of the two sorted column lists).
+__global__ __launch_bounds__(kBlock) void k_ilu_factor(KArgs a, double* __restrict__ lu,
+                                                       const int32_t* __restrict__ rows, int32_t count) {
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= count) return;
+  const int i = rows[idx];
+  const int end_i = a.rp[i + 1], di = a.diagpos[i];
+  for (int p = a.rp[i]; p < di; ++p) {
+    const int k = a.ci[p];
+    const double lik = lu[p] / lu[a.diagpos[k]];
+    lu[p] = lik;
+    int q = a.diagpos[k] + 1;
+    const int q_end = a.rp[k + 1];
+    int p2 = p + 1;
+    while (q < q_end && p2 < end_i) {
+      const int cq = a.ci[q], cp = a.ci[p2];
+      if (cq == cp) {
+        lu[p2] -= lik * lu[q];
+        ++q;
+        ++p2;
+      } else if (cq < cp) {
+        ++q;
+      } else {
+        ++p2;
+      }
+    }
+  }
+}
+
+__global__ void k_ilu_finish(KArgs a, const double* __restrict__ lu, float* __restrict__ lu32,
+                             float* __restrict__ dinv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.ld) return;
+  const int b = a.rp[r], e = a.rp[r + 1];
+  for (int p = b; p < e; ++p) lu32[p] = (float)lu[p];
+  dinv[r] = b < e ? (float)(1.0 / lu[a.diagpos[r]]) : 0.0f;  // padding rows: zero
+}
+
+// Application z_j = U^-1 L^-1 (scale_j v_j): the scaled v_j, then sweeps
+// y <- v - L' y and x <- D^-1 (y - U' x) from zero starts (src = null), one
+// thread per row, each row's strictly lower / upper entries in storage order.
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_ilu_begin(KArgs a, int j) {
+  const int s = a.tile_sys[blockIdx.x];
+  if (!gated(a, s)) return;
+  const float scale = (float)a.sc[(int64_t)s * (a.m + 1) + j];
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  const float v = (float)ldv(col_ptr<TV>(a, j)[r]) * scale;
+  if (a.st[s].precond_on)
+    a.ilu_v[r] = v;
+  else
+    a.Z[(int64_t)j * a.ld + r] = v;  // preconditioner switched off: z_j = v_j
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_lsweep(KArgs a, const float* __restrict__ src,
+                                                       float* __restrict__ dst) {
+  const int s = a.tile_sys[blockIdx.x];
+  if (!gated(a, s) || (!a.st[s].precond_on && !a.st[s].force)) return;
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  float acc = 0.0f;
+  if (src)
+    for (int p = a.rp[r]; p < a.diagpos[r]; ++p) acc += a.ilu32[p] * src[a.ci[p]];
+  dst[r] = a.ilu_v[r] - acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ilu_usweep(KArgs a, const float* __restrict__ y,
+                                                       const float* __restrict__ src, float* __restrict__ dst) {
+  const int s = a.tile_sys[blockIdx.x];
+  if (!gated(a, s) || (!a.st[s].precond_on && !a.st[s].force)) return;
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  float acc = 0.0f;
+  if (src)
+    for (int p = a.diagpos[r] + 1; p < a.rp[r + 1]; ++p) acc += a.ilu32[p] * src[a.ci[p]];
+  dst[r] = (y[r] - acc) * a.iludinv[r];
+}
+
 // y = H^-1 s by back-substitution, one wave per system, with truncation of
 // a singular leading block.  Also turns y into update coefficients.
 __global__ __launch_bounds__(64) void k_backsolve(KArgs a) {
@@ -1505,8 +1586,48 @@ hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
   });
 }
 
+hipError_t launch_ilu_factor(const KArgs& a, double* lu, const int32_t* rows, int32_t count, hipStream_t st) {
+  if (count > 0)
+    hipLaunchKernelGGL(k_ilu_factor, dim3((unsigned)((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a, lu,
+                       rows, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, hipStream_t st) {
+  hipLaunchKernelGGL(k_ilu_finish, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, lu, lu32, dinv);
+  return hipGetLastError();
+}
+
+// ILU(0) sweeps on ilu_v (L sweeps ping-pong in b0/b1, U sweeps in b2 and
+// whichever of b0/b1 does not hold the L result); the last U sweep writes dst.
+hipError_t launch_ilu_apply(const KArgs& a, float* dst_final, hipStream_t st) {
+  const float* src = nullptr;
+  for (int t = 0; t < a.ilu_sl; ++t) {
+    float* dst = a.ilu_b[t & 1];
+    hipLaunchKernelGGL(k_ilu_lsweep, dim3(a.ntile), dim3(kBlock), 0, st, a, src, dst);
+    src = dst;
+  }
+  const float* y = src;
+  float* const ub[2] = {a.ilu_b[2], a.ilu_b[(a.ilu_sl & 1) ? 1 : 0]};
+  const float* usrc = nullptr;
+  for (int t = 0; t < a.ilu_su; ++t) {
+    float* dst = t + 1 == a.ilu_su ? dst_final : ub[t & 1];
+    hipLaunchKernelGGL(k_ilu_usweep, dim3(a.ntile), dim3(kBlock), 0, st, a, y, usrc, dst);
+    usrc = dst;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
   if (a.precond == 0) return hipSuccess;
+  if (a.precond == 3) {
+    launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
+      using TV = decltype(tv);
+      hipLaunchKernelGGL((k_ilu_begin<TV>), dim3(a.ntile), dim3(kBlock), 0, st, a, j);
+      return hipSuccess;
+    });
+    return launch_ilu_apply(a, a.Z + (int64_t)j * a.ld, st);
+  }
   return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
     using TV = decltype(tv);
     if (a.precond == 1) {

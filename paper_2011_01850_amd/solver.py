@@ -33,7 +33,7 @@ def _dev(t, dtype, torch):
 
 def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
              autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
-             restart_on_stall=False, orth_restart=0.0, orth_norm="spectral") -> L.Options:
+             restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4) -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -52,6 +52,7 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.restart_on_stall = int(bool(restart_on_stall))
     o.orth_restart = float(orth_restart)
     o.orth_norm = L.ORTH_NORMS[orth_norm] if isinstance(orth_norm, str) else int(orth_norm)
+    o.ilu_sweeps = int(ilu_sweeps)
     return o
 
 
@@ -62,7 +63,7 @@ class Solver:
                  precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
                  a_storage="copy", restart_repeat=False, restart_on_stall=False, orth_restart=0.0,
-                 orth_norm="spectral"):
+                 orth_norm="spectral", ilu_sweeps=4):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -74,7 +75,7 @@ class Solver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps)
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         torch.cuda.synchronize()
@@ -151,6 +152,15 @@ class Solver:
                 "gmres_residual")
         return r, nrm.value
 
+    def precond_apply(self, v):
+        """z = M^-1 v (float32 tensors) with the handle's ILU(0) preconditioner."""
+        torch = self._torch
+        vt = _dev(v, torch.float32, torch)
+        z = torch.empty_like(vt)
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_precond_apply(self.h, vt.data_ptr(), z.data_ptr()), "gmres_precond_apply")
+        return z
+
     def spmv(self, x, precision="fp64"):
         torch = self._torch
         dt = torch.float64 if precision == "fp64" else torch.float32
@@ -200,7 +210,7 @@ class BatchSolver:
     def __init__(self, systems, m=40, tol=1e-10, ortho="mgs", precision="fp32", precond="none",
                  max_iters=100_000, restart_improve=0.0, stall_cycles=10, use_graph=True, autotune=True,
                  schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
-                 restart_on_stall=False, orth_restart=0.0, orth_norm="spectral"):
+                 restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -222,7 +232,7 @@ class BatchSolver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps)
         arr64 = C.c_int64 * S
         arrp = C.c_void_p * S
         h = C.c_void_p()

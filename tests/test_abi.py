@@ -42,6 +42,7 @@ def test_default_options(lib):
     assert o.restart_improve == 0.0 and o.stall_cycles == 10 and o.use_graph == 1 and o.autotune == 1
     assert o.batch_schedule == L.SCHEDULE_AUTO and o.spmv_block_nnz == 0 and o.a_storage == L.A_COPY
     assert o.restart_repeat == 0 and o.restart_on_stall == 0 and o.orth_restart == 0.0 and o.orth_norm == 0
+    assert o.ilu_sweeps == 4
 
 
 def test_strerror(lib):
@@ -62,7 +63,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                        ("batch_schedule", -1), ("spmv_block_nnz", 32), ("spmv_block_nnz", 100),
                        ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1), ("restart_repeat", 2),
                        ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
-                       ("orth_norm", 2)]:
+                       ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -86,6 +87,7 @@ def test_handle_checks(lib):
     assert lib.gmres_solve(None, 1, 1, C.byref(r)) == L.EHANDLE
     v = C.c_size_t()
     assert lib.gmres_memory_bytes(None, C.byref(v)) == L.EHANDLE
+    assert lib.gmres_precond_apply(None, None, None) == L.EHANDLE
     # a pointer to something that is not a handle
     junk = (C.c_uint32 * 64)()
     assert lib.gmres_memory_bytes(C.cast(junk, C.c_void_p), C.byref(v)) == L.EHANDLE
@@ -99,7 +101,7 @@ def test_struct_layouts_match_header():
     assert L.Options.batch_schedule.offset == 60 and L.Options.spmv_block_nnz.offset == 64
     assert L.Options.a_storage.offset == 68 and L.Options.restart_repeat.offset == 72
     assert L.Options.restart_on_stall.offset == 76 and L.Options.orth_restart.offset == 80
-    assert L.Options.orth_norm.offset == 88
+    assert L.Options.orth_norm.offset == 88 and L.Options.ilu_sweeps.offset == 92
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 

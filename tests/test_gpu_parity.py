@@ -403,6 +403,53 @@ def test_batch_equals_single_solves_bitwise(precision):
         assert np.array_equal(x.cpu().numpy(), x1.cpu().numpy())
 
 
+def test_ilu0_application_matches_oracle():
+    # the float64 factorisation on the GPU, then the float32 sweeps (or the
+    # exact substitutions, ilu_sweeps = 0), against the oracle's ILU(0)
+    A0 = P.varcoef3d(10, family=94, index=1)
+    M = O.Matrix.from_csr(A0)
+    lu, diag = O.ilu0(M)
+    dl, du = O.triangle_depths(M, diag)
+    assert dl == du == 3 * 10 - 2
+    g = np.random.default_rng(8)
+    v = g.standard_normal(A0.n).astype(np.float32)
+    outs = {}
+    for sweeps in (1, 3, 0):
+        ref = O.ilu_apply(M, lu, diag, v.astype(np.float64), sweeps=sweeps)
+        for st in ("copy", "split"):
+            s = _solver(A0, m=10, precision="fp32", precond="ilu0", ilu_sweeps=sweeps, a_storage=st)
+            z = s.precond_apply(v).cpu().numpy()
+            s.close()
+            assert np.linalg.norm(z - ref) <= 2e-5 * np.linalg.norm(ref), (sweeps, st)
+            outs[(sweeps, st)] = z
+        # both storages reach the same float64 values: the same factors, bit for bit
+        assert np.array_equal(outs[(sweeps, "copy")], outs[(sweeps, "split")])
+    # one sweep per triangle is D^-1 v (D the diagonal of U)
+    assert np.allclose(outs[(1, "copy")], v / lu[diag], rtol=1e-6)
+    emu = O.ilu_apply(M, lu, diag, v, sweeps=3, dtype=np.float32)
+    assert np.linalg.norm(outs[(3, "copy")] - emu) <= 1e-5 * np.linalg.norm(emu)
+
+
+@pytest.mark.parametrize("sweeps", [4, 0])
+def test_ilu0_fgmres_matches_oracle(sweeps):
+    A0 = P.varcoef3d(16, family=94, index=0)
+    M = O.Matrix.from_csr(A0)
+    xt, b = P.manufactured_rhs(A0, 94, 0)
+    lu, diag = O.ilu0(M)
+    ref = O.gmres(M, b, m=30, tol=1e-11, fallback=False,
+                  precond=lambda v: O.ilu_apply(M, lu, diag, v, sweeps=sweeps))
+    s = _solver(A0, m=30, precision="fp32", precond="ilu0", ilu_sweeps=sweeps, tol=1e-11)
+    x, info = s.solve(b)
+    s.close()
+    assert info["status"] == "CONVERGED" and not info["fallback_used"]
+    assert _relres(A0, b, x.cpu().numpy()) <= 1.01e-11
+    assert abs(info["iters"] - ref.iters) <= max(10, 0.1 * ref.iters)
+    sj = _solver(A0, m=30, precision="fp32", precond="jacobi", tol=1e-11)
+    _, ij = sj.solve(b)
+    sj.close()
+    assert info["iters"] < 0.8 * ij["iters"]
+
+
 def test_jacobi_fgmres_matches_oracle():
     A0 = P.varcoef3d(16, family=94, index=0)
     M = O.Matrix.from_csr(A0)

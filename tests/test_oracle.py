@@ -433,6 +433,73 @@ def test_orth_restart_ends_cycles_when_the_basis_loses_orthogonality(norm, tau):
 
 
 # --------------------------------------------------------------------------
+# ILU(0)
+
+def _lu_dense(A, lu, diag):
+    n = A.n
+    L = np.eye(n)
+    U = np.zeros((n, n))
+    for i in range(n):
+        for p in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            j = A.col_idx[p]
+            if j < i:
+                L[i, j] = lu[p]
+            else:
+                U[i, j] = lu[p]
+    return L, U
+
+
+def test_ilu0_reproduces_a_on_its_pattern():
+    # the defining property of ILU(0): (L U)_ij = a_ij wherever A stores an entry
+    A = O.Matrix.from_csr(P.convdiff(7, (20.0, 5.0)))
+    lu, diag = O.ilu0(A)
+    L, U = _lu_dense(A, lu, diag)
+    LU = L @ U
+    D = A.dense()
+    on = np.zeros_like(D, dtype=bool)
+    on[A.rows, A.col_idx] = True
+    assert np.allclose(LU[on], D[on], rtol=1e-13, atol=1e-12 * np.abs(D).max())
+    assert np.max(np.abs(LU[~on] - D[~on])) > 1e-3  # and it is incomplete: fill is dropped
+
+
+def test_ilu0_of_a_tridiagonal_matrix_is_exact_lu():
+    n = 30
+    g = np.random.default_rng(5)
+    D = np.diag(4.0 + g.random(n)) + np.diag(g.random(n - 1) - 0.5, 1) + np.diag(g.random(n - 1) - 0.5, -1)
+    A = O.Matrix.from_csr(P.dense_to_csr(D))
+    lu, diag = O.ilu0(A)
+    L, U = _lu_dense(A, lu, diag)
+    assert np.allclose(L @ U, D, rtol=0, atol=1e-14)
+    v = g.standard_normal(n)
+    assert np.allclose(D @ O.ilu_apply(A, lu, diag, v), v, atol=1e-12)
+
+
+def test_ilu_sweeps_reach_the_substitution_at_the_triangle_depth():
+    A = O.Matrix.from_csr(P.convdiff(6, (10.0, 3.0)))
+    lu, diag = O.ilu0(A)
+    dl, du = O.triangle_depths(A, diag)
+    assert dl == 2 * 6 - 1 and du == 2 * 6 - 1  # 5-point stencil, natural order
+    v = np.random.default_rng(6).standard_normal(A.n)
+    exact = O.ilu_apply(A, lu, diag, v)
+    deep = O.ilu_apply(A, lu, diag, v, sweeps=max(dl, du))
+    shallow = O.ilu_apply(A, lu, diag, v, sweeps=3)
+    assert np.allclose(deep, exact, rtol=1e-13, atol=1e-13)
+    assert np.linalg.norm(shallow - exact) > 1e-6 * np.linalg.norm(exact)
+
+
+def test_ilu_preconditioned_gmres_beats_jacobi():
+    A0 = P.varcoef3d(8, family=94, index=0)
+    A = O.Matrix.from_csr(A0)
+    b = P.manufactured_rhs(A0, 94, 0)[1]
+    lu, diag = O.ilu0(A)
+    d = A.diagonal()
+    rj = O.gmres(A, b, m=30, tol=1e-10, ortho="cgsr", precond=lambda v: v / d)
+    ri = O.gmres(A, b, m=30, tol=1e-10, ortho="cgsr", precond=lambda v: O.ilu_apply(A, lu, diag, v))
+    assert ri.status == O.CONVERGED and rj.status == O.CONVERGED
+    assert ri.iters < 0.8 * rj.iters
+
+
+# --------------------------------------------------------------------------
 # split storage of A (high and low 32-bit words of each float64 value)
 
 def test_high_word_value_hand_cases():

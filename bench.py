@@ -537,7 +537,7 @@ def bench_learned(args, pool):
             net = S.SpaiNet(dev[0], dev[1], kmax=1)
             torch.cuda.synchronize()
             t_net = time.perf_counter() - t0
-        kinds = ["jacobi", "learned"] + (["none", "fp64"] if q < nb else [])
+        kinds = ["jacobi", "ilu0", "learned"] + (["none", "fp64"] if q < nb else [])
         row = {"instance": test_ids[q]}
         for kind in kinds:
             _, row[kind] = T.solve_once(dev, bt, kind, params=res["params"], m=m, net=net)
@@ -557,8 +557,8 @@ def bench_learned(args, pool):
                 "fallback_used": sum(bool(r["fallback_used"]) for r in rs),
                 "max_rel_residual": float(max(r["rel_residual"] for r in rs))}
 
-    kinds_all = {k: summary(k, rows) for k in ("jacobi", "learned")}
-    kinds_sub = {k: summary(k, rows[:nb]) for k in ("fp64", "none", "jacobi", "learned")}
+    kinds_all = {k: summary(k, rows) for k in ("jacobi", "ilu0", "learned")}
+    kinds_sub = {k: summary(k, rows[:nb]) for k in ("fp64", "none", "jacobi", "ilu0", "learned")}
     v = kinds_all["learned"]["seconds_mean"]
     n_a = N ** 3
     rec = {
@@ -575,6 +575,7 @@ def bench_learned(args, pool):
         "held_out_baseline_subset": kinds_sub,
         "speedup_learned_vs_fp64": round(kinds_sub["fp64"]["seconds_mean"] / kinds_sub["learned"]["seconds_mean"], 3),
         "speedup_learned_vs_jacobi": round(kinds_all["jacobi"]["seconds_mean"] / v, 3),
+        "speedup_learned_vs_ilu0": round(kinds_all["ilu0"]["seconds_mean"] / v, 3),
         "iteration_gain_vs_none": round(kinds_sub["none"]["iters_mean"] / kinds_sub["learned"]["iters_mean"], 3),
         "learned_one_off": {"network_instance_seconds": t_net,
                             "first_instance_seconds_own_instance": rows[0]["learned_own_instance"]["seconds_total"],

@@ -133,14 +133,14 @@ def train(train_ids, N=64, steps=100, lr=3e-3, seed=0, pairs_per_instance=4, bat
 
 def solve_once(A, b, kind, params=None, m=30, tol=1e-10, ortho="cgsr", max_iters=100_000, net=None):
     """Time to tol including setup for one preconditioning kind:
-    fp64 (no preconditioner), none, jacobi, learned (float32 Arnoldi).
+    fp64 (no preconditioner), none, jacobi, ilu0 (4 sweeps), learned (float32 Arnoldi).
     For `learned`, `net` is an optional network instance shared by the
     family's sparsity pattern (else the solver builds its own)."""
     torch = _torch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     prec = "fp64" if kind == "fp64" else "fp32"
-    pc = {"fp64": "none", "none": "none", "jacobi": "jacobi", "learned": "spai"}[kind]
+    pc = {"fp64": "none", "none": "none", "jacobi": "jacobi", "learned": "spai", "ilu0": "ilu0"}[kind]
     s = Solver(A[0], A[1], A[2], m=m, tol=tol, ortho=ortho, precision=prec, precond=pc, max_iters=max_iters)
     if kind == "learned":
         s.spai_infer(params, net=net, return_m=False)

@@ -430,6 +430,33 @@ def test_ilu0_application_matches_oracle():
     assert np.linalg.norm(outs[(3, "copy")] - emu) <= 1e-5 * np.linalg.norm(emu)
 
 
+def test_ilu0_edge_cases():
+    from paper_2011_01850_amd import GmresError
+    # a row without its diagonal entry has no ILU(0): refused at create
+    D = np.array([[0.0, 1.0, 0.0], [1.0, 2.0, 0.0], [0.0, 1.0, 3.0]])
+    rp = np.array([0, 1, 3, 5], dtype=np.int32)
+    ci = np.array([1, 0, 1, 1, 2], dtype=np.int32)
+    va = np.array([1.0, 1.0, 2.0, 1.0, 3.0])
+    assert np.allclose(O.Matrix(rp, ci, va).dense(), D)
+    with pytest.raises(GmresError):
+        Solver(rp, ci, va, m=3, precision="fp32", precond="ilu0")
+    # the application entry point needs an ILU(0) handle
+    A0 = P.convdiff(8, (1.0, 1.0))
+    s = _solver(A0, m=5, precision="fp32", precond="jacobi")
+    with pytest.raises(GmresError):
+        s.precond_apply(np.ones(A0.n, dtype=np.float32))
+    s.close()
+    # a diagonal matrix: ILU(0) is exact, one iteration of the flexible solver
+    n = 300
+    d = np.linspace(1.0, 5.0, n)
+    Ad = P.dense_to_csr(np.diag(d))
+    s = _solver(Ad, m=5, precision="fp32", precond="ilu0", tol=1e-12)
+    x, info = s.solve(d)
+    s.close()
+    assert info["status"] == "CONVERGED" and info["iters"] <= 2
+    assert np.allclose(x.cpu().numpy(), 1.0, atol=1e-12)
+
+
 @pytest.mark.parametrize("sweeps", [4, 0])
 def test_ilu0_fgmres_matches_oracle(sweeps):
     A0 = P.varcoef3d(16, family=94, index=0)

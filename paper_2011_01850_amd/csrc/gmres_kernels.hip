@@ -245,31 +245,51 @@ __device__ __forceinline__ void givens(double a, double b, double& c, double& s)
 // earlier rotations are staged in LDS in parallel, one lane runs the
 // sequential rotation chain in registers, and the column is written back in
 // parallel.
-__device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax) {
-  __shared__ double hcol[kMaxM + 2], rc[kMaxM], rsn[kMaxM];
-  __shared__ int ok;
+// Staged inputs of the per-step finaliser (LDS): the unrotated column of H,
+// the earlier rotations, and the two history values the tests need.
+struct FinShared {
+  double hcol[kMaxM + 2], rc[kMaxM], rsn[kMaxM];
+  double svj, arJ;
+  int ok;
+};
+
+// Givens update of column j, restart / stop decisions (one lane), on S, a
+// copy of the system's state in LDS that the caller writes back.  The column
+// and the rotations are staged (fin_stage) before the partial sums are
+// reduced, so their loads overlap; one lane runs the sequential rotation
+// chain in registers; the column is written back in parallel.
+__device__ void fin_stage(const KArgs& a, int s, int j, FinShared& sh) {
   const int t = threadIdx.x, NT = blockDim.x;
-  SysState& S = a.st[s];
   const int m = a.m, M1 = m + 1, M2 = m + 2;
+  const double* hc = a.hacc + (int64_t)s * M2;
+  const double* cs = a.cs + (int64_t)s * m;
+  const double* sn = a.sn + (int64_t)s * m;
+  for (int i = t; i <= j; i += NT) sh.hcol[i] = hc[i];
+  for (int i = t; i < j; i += NT) {
+    sh.rc[i] = cs[i];
+    sh.rsn[i] = sn[i];
+  }
+  if (t == 0) sh.svj = a.s[(int64_t)s * M1 + j];
+  if (t == 1) {
+    const int J = j + 1 - a.stall_win;
+    sh.arJ = J >= 0 ? a.ares[(int64_t)s * M1 + J] : 0.0;
+  }
+}
+
+__device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax, SysState& S, FinShared& sh) {
+  const int t = threadIdx.x, NT = blockDim.x;
+  const int m = a.m, M1 = m + 1;
   double* col = a.H + (int64_t)s * M1 * m + (int64_t)j * M1;
   double* bcol = a.Hbar + (int64_t)s * M1 * m + (int64_t)j * M1;
-  const double* hc = a.hacc + (int64_t)s * M2;
   double* cs = a.cs + (int64_t)s * m;
   double* sn = a.sn + (int64_t)s * m;
   const double hn = sqrt(sumsq);
-  if (t == 0) ok = isfinite(hn) ? 1 : 0;
+  if (t == 0) sh.ok = isfinite(hn) ? 1 : 0;
   __syncthreads();
-  for (int i = t; i <= j; i += NT) {
-    const double v = hc[i];
-    hcol[i] = v;
-    if (!isfinite(v)) ok = 0;
-  }
-  for (int i = t; i < j; i += NT) {
-    rc[i] = cs[i];
-    rsn[i] = sn[i];
-  }
+  for (int i = t; i <= j; i += NT)
+    if (!isfinite(sh.hcol[i])) sh.ok = 0;
   __syncthreads();
-  const bool finite = ok != 0;
+  const bool finite = sh.ok != 0;
   if (t == 0) {
     if (!finite) {
       // drop the column; the cycle ends with the finite part of the basis
@@ -286,41 +306,40 @@ __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax
       double* sc = a.sc + (int64_t)s * M1;
       double* ar = a.ares + (int64_t)s * M1;
       // apply the previous rotations; only the running entry is carried
-      double cur = hcol[0];
+      double cur = sh.hcol[0];
       for (int i = 0; i < j; ++i) {
-        const double nxt = hcol[i + 1];
-        hcol[i] = rc[i] * cur + rsn[i] * nxt;
-        cur = -rsn[i] * cur + rc[i] * nxt;
+        const double nxt = sh.hcol[i + 1];
+        sh.hcol[i] = sh.rc[i] * cur + sh.rsn[i] * nxt;
+        cur = -sh.rsn[i] * cur + sh.rc[i] * nxt;
       }
       double c, sg;
       givens(cur, hn, c, sg);
       cs[j] = c;
       sn[j] = sg;
-      const double sj = sv[j];
+      const double sj = sh.svj;
       sv[j + 1] = -sg * sj;
       sv[j] = c * sj;
-      hcol[j] = c * cur + sg * hn;
-      hcol[j + 1] = 0.0;
+      sh.hcol[j] = c * cur + sg * hn;
+      sh.hcol[j + 1] = 0.0;
       S.iters += 1;
       S.k = j + 1;
       S.need_update = 1;
       const double res = fabs(sg * sj);
       ar[j + 1] = res;
+      const int J = j + 1 - a.stall_win;  // the stall window's start (sh.arJ = |s_{J+1}|)
       if (S.cycle == 1 && S.first_stall < 0) {
-        const int J = j + 1 - a.stall_win;
-        if (J >= 0 && res > ar[J] / 1.001) S.first_stall = J;
+        if (J >= 0 && res > sh.arJ / 1.001) S.first_stall = J;
       }
       const double bd = 16.0 * (double)(j + 1) * unit_roundoff(a.prec);
       // restart triggers: the improvement threshold (first cycle only under
       // the two-stage strategy), the first cycle's length (two-stage), a
       // stalled Arnoldi residual
       const bool first_stage = !a.restart_repeat || S.klimit == 0;
-      const int Js = j + 1 - a.stall_win;
       const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
                        S.iters >= a.max_iters ||
                        (a.restart_improve > 0.0 && first_stage && res <= a.restart_improve * S.beta) ||
                        (!first_stage && j + 1 >= S.klimit) ||
-                       (a.restart_on_stall && Js >= 0 && res > ar[Js] / 1.001);
+                       (a.restart_on_stall && J >= 0 && res > sh.arJ / 1.001);
       if (end && a.restart_repeat && S.klimit == 0) S.klimit = j + 1;
       if (a.prec == PBF16 || a.prec == PF16) {
         if (!end) {
@@ -338,9 +357,10 @@ __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax
   }
   __syncthreads();
   if (finite) {
+    const double* hc = a.hacc + (int64_t)s * (m + 2);
     for (int i = t; i <= j; i += NT) bcol[i] = hc[i];
     if (t == 0) bcol[j + 1] = hn;
-    for (int i = t; i <= j + 1; i += NT) col[i] = hcol[i];
+    for (int i = t; i <= j + 1; i += NT) col[i] = sh.hcol[i];
   }
 }
 
@@ -1026,11 +1046,59 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, const double* src, i
     return;
   }
   const double mx = reduce_col<true>(src + rows + b0, n);
-  if (MODE == FIN_RESID) {
-    if (threadIdx.x == 0) fin_residual(a, s, sq, mx);
-  } else {
-    fin_step(a, s, j, sq, mx);
+  if (threadIdx.x == 0) fin_residual(a, s, sq, mx);
+}
+
+// Sum of p[0, n) and maximum of q[0, n), both in a fixed order, in one pass
+// (every thread of the block returns both).
+__device__ void reduce_sum_max(const double* p, const double* q, int n, double& sum, double& mx) {
+  __shared__ double sh[2][kBlock / 64];
+  const int t = threadIdx.x, NT = blockDim.x;
+  double s0 = 0.0, s1 = 0.0, m0 = 0.0, m1 = 0.0;
+  int r = t;
+  for (; r + NT < n; r += 2 * NT) {
+    s0 += p[r];
+    s1 += p[r + NT];
+    m0 = fmax(m0, q[r]);
+    m1 = fmax(m1, q[r + NT]);
   }
+  if (r < n) {
+    s0 += p[r];
+    m0 = fmax(m0, q[r]);
+  }
+  double v = wave_sum(s0 + s1), w = wave_max(fmax(m0, m1));
+  if ((t & 63) == 0) {
+    sh[0][t >> 6] = v;
+    sh[1][t >> 6] = w;
+  }
+  __syncthreads();
+  sum = sh[0][0];
+  mx = sh[1][0];
+  for (int k = 1; k < NT / 64; ++k) {
+    sum += sh[0][k];
+    mx = fmax(mx, sh[1][k]);
+  }
+}
+
+// The per-step finaliser: column j of H from the float64 partials of the
+// last pass (||w''||^2 in the first column of src, max|w''| in the second),
+// the Givens step and the restart decisions, on an LDS copy of the state.
+__global__ __launch_bounds__(kBlock) void k_fin_step(KArgs a, const double* src, int rows, const int32_t* r0,
+                                                     const int32_t* nr, int j) {
+  __shared__ FinShared sh;
+  __shared__ SysState S;
+  const int s = blockIdx.x, t = threadIdx.x;
+  const SysState& G = a.st[s];
+  if (!G.active && !G.force) return;
+  constexpr int kWords = (int)(sizeof(SysState) / 8);
+  static_assert(sizeof(SysState) % 8 == 0, "SysState is copied as 8-byte words");
+  if (t < kWords) reinterpret_cast<uint64_t*>(&S)[t] = reinterpret_cast<const uint64_t*>(&G)[t];
+  fin_stage(a, s, j, sh);
+  double sq, mx;
+  reduce_sum_max(src + r0[s], src + rows + r0[s], nr[s], sq, mx);
+  fin_step(a, s, j, sq, mx, S, sh);
+  __syncthreads();
+  if (t < kWords) reinterpret_cast<uint64_t*>(&a.st[s])[t] = reinterpret_cast<const uint64_t*>(&S)[t];
 }
 
 // The CGS projections complete column by column: workgroup (s, q) reduces
@@ -1802,8 +1870,7 @@ hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fi
     return hipGetLastError();
   });
   if (e0 != hipSuccess || !with_fin) return e0;
-  hipLaunchKernelGGL((k_fin<FIN_STEP>), dim3(a.S), dim3(kFinBlock), 0, st, a, src, used->nseg, used->sys_sg0,
-                     used->sys_nsg, j);
+  hipLaunchKernelGGL(k_fin_step, dim3(a.S), dim3(kBlock), 0, st, a, src, used->nseg, used->sys_sg0, used->sys_nsg, j);
   return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by what it reads
 # for a plain 1 GiB device copy: x2.0 and x1.0), averaged over the roofline
 # launches.  Valid only for the kernel source they were taken from.
-TRAFFIC = {"bytes_per_launch": 346235136, "kernel_source_sha256": "ed8244b5e8892dc640e9cc33569d940437621ae6ec521439b0a847da57bbad73"}
+TRAFFIC = {"bytes_per_launch": 346235867, "kernel_source_sha256": "e85cd22d499b991ed0b770363725a87afd7b29f9553feb1871daf2e8ec1d16dc"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 

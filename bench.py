@@ -217,6 +217,18 @@ def bench_convdiff3d(args):
                  "forward_error": float(np.linalg.norm(x_sp.cpu().numpy() - pr.x_true) / np.linalg.norm(pr.x_true)),
                  "memory_bytes": s_sp.memory_bytes()}
     s_sp.close()
+    # the limited mixed solver of the convergence study: float32 storage of
+    # the Arnoldi copy of A and of the basis only, w and its dots float64
+    log("limited mixed precision ...")
+    t_li, i_li, (s_li, x_li) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, "limited",
+                                                args.steps, min(args.warmup, 1))
+    out_limited = {"seconds_mean": statistics.mean(t_li), "seconds_median": statistics.median(t_li),
+                   "solve_seconds": i_li[-1]["seconds"], "iters": i_li[-1]["iters"],
+                   "restarts": i_li[-1]["restarts"], "rel_residual": i_li[-1]["rel_residual"],
+                   "forward_error": float(np.linalg.norm(x_li.cpu().numpy() - pr.x_true)
+                                          / np.linalg.norm(pr.x_true)),
+                   "memory_bytes": s_li.memory_bytes()}
+    s_li.close()
     value = statistics.mean(t_mix)
     rec = {
         "metric": METRIC,
@@ -245,6 +257,7 @@ def bench_convdiff3d(args):
                   "memory_bytes": mem_mixed},
         "fp64": out_fp64,
         "split_storage": out_split,
+        "limited": out_limited,
         "speedup_vs_fp64": (round(out_fp64["seconds"] / value, 3) if out_fp64 else None),
         "paper_context": "paper (2x10-core Haswell, Kokkos/MKL, ILU(0), SuiteSparse): mixed vs FP64 "
                          "geo-mean speedup +19% (MGS), +24% (CGSR) when restarted at least once",
@@ -356,6 +369,9 @@ def bench_restart(args):
         ("fp32_improve", "fp32", {"restart_improve": 1e-6}),
         ("fp32_orth_spectral", "fp32", {"orth_restart": 0.5, "orth_norm": "spectral"}),
         ("fp32_orth_frobenius", "fp32", {"orth_restart": 0.5, "orth_norm": "frobenius"}),
+        # the limited mixed solver (float32 storage of A, M and the basis only)
+        ("limited", "limited", {}),
+        ("limited_stall", "limited", {"restart_on_stall": True}),
     ]
     modes = {}
     rp, ci, va = A_dev

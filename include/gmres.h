@@ -52,7 +52,14 @@ enum {
   GMRES_FP64 = 0,       /* everything float64 (the baseline) */
   GMRES_MIXED_FP32 = 1, /* float32 A copy, basis, w and dot products */
   GMRES_MIXED_BF16 = 2, /* float32 arithmetic, basis stored as bfloat16 */
-  GMRES_MIXED_FP16 = 3  /* float32 arithmetic, basis stored as IEEE half */
+  GMRES_MIXED_FP16 = 3, /* float32 arithmetic, basis stored as IEEE half */
+  /* the limited mixed solver of the convergence study (section 4.1): only
+   * the storage of A for the Arnoldi product, of the preconditioner and of
+   * the basis is float32; w, its dot products and the Arnoldi product's
+   * sums are float64 (float32 values widened exactly).  Basis traffic as in
+   * GMRES_MIXED_FP32, w traffic as in GMRES_FP64.  Not available with the
+   * persistent batch schedule. */
+  GMRES_MIXED_LIMITED = 4
 };
 
 /* gmres_options.a_storage: how the handle keeps A's values.
@@ -108,7 +115,7 @@ typedef struct {
   double tol;               /* stop when ||b - A x||_2 / ||b||_2 <= tol (float64 residual) */
   int64_t max_iters;        /* budget of inner (Arnoldi) iterations over all cycles */
   int32_t ortho;            /* GMRES_MGS or GMRES_CGSR */
-  int32_t precision;        /* GMRES_FP64 ... GMRES_MIXED_FP16 */
+  int32_t precision;        /* GMRES_FP64 ... GMRES_MIXED_LIMITED */
   int32_t precond;          /* GMRES_PRECOND_* */
   double restart_improve;   /* 0 = off; else end a cycle once |s_{j+1}| <= restart_improve * beta
                                (the improvement trigger of the restart-strategy study) */
@@ -217,9 +224,10 @@ int gmres_residual(gmres_handle h, const double* b, const double* x, double* r, 
 
 /* y = A x with the stored float64 values (precision = GMRES_FP64, x and y
  * float64) or the float32 values of the Arnoldi product (GMRES_MIXED_FP32,
- * float32 x, y: the float32 copy, or the high words under SPLIT storage).
- * The float32 values exist only on mixed-precision handles (else ESTATE);
- * single-system handles only (ESTATE on a batch handle). */
+ * float32 x, y: the float32 copy, or the high words under SPLIT storage;
+ * GMRES_MIXED_LIMITED: the same values and float32 x, summed in float64,
+ * float64 y).  The float32 values exist only on mixed-precision handles
+ * (else ESTATE); single-system handles only (ESTATE on a batch handle). */
 int gmres_spmv(gmres_handle h, int32_t precision, const void* x, void* y);
 
 /* z = M^-1 v for a single-system handle created with

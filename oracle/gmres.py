@@ -40,9 +40,13 @@ float32 while the residual, the update, H, the rotations and the
 back-solve stay float64 (the precision split of the numerics section);
 ``bf16`` / ``fp16`` additionally store each basis vector rounded to nearest
 even in the 2-byte format after multiplying by a per-vector power-of-two
-scale.  Two debug switches reproduce the negative control of the
-per-variable study (section 4.1): ``residual_fp32`` computes the restart
-residual in float32 and ``update_fp32`` keeps x in float32.
+scale; ``limited`` is the second, limited mixed solver of the convergence
+study (section 4.1): only the Arnoldi copy of A, the preconditioner's output
+and the basis are stored in float32, while w, the dot products and the sums
+of the Arnoldi product are float64.  Two debug switches reproduce the
+negative control of the per-variable study (section 4.1): ``residual_fp32``
+computes the restart residual in float32 and ``update_fp32`` keeps x in
+float32.
 
 Parity pins for this module live in tests/test_oracle.py.
 """
@@ -88,6 +92,13 @@ class Matrix:
         v = self.vals32 if vals32 is None else vals32
         prod = (v * np.asarray(x32, dtype=np.float32)[self.col_idx]).astype(np.float64)
         return np.bincount(self.rows, weights=prod, minlength=self.n).astype(np.float32)
+
+    def matvec_wide(self, x32, vals32=None):
+        """The limited mode's product: float32-stored values and x, widened to
+        float64 (each product is then exact) and summed in float64."""
+        v = (self.vals32 if vals32 is None else vals32).astype(np.float64)
+        prod = v * np.asarray(x32, dtype=np.float32).astype(np.float64)[self.col_idx]
+        return np.bincount(self.rows, weights=prod, minlength=self.n)
 
     def diagonal(self):
         d = np.zeros(self.n)
@@ -394,7 +405,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     """
     if ortho not in ("mgs", "cgsr"):
         raise ValueError(ortho)
-    if precision not in ("fp64", "fp32", "bf16", "fp16"):
+    if precision not in ("fp64", "fp32", "bf16", "fp16", "limited"):
         raise ValueError(precision)
     if a_storage not in ("copy", "split"):
         raise ValueError(a_storage)
@@ -409,7 +420,11 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     if update_fp32:
         x = x.astype(np.float32).astype(np.float64)
-    lowp = precision != "fp64"
+    lowp = precision != "fp64"  # reduced-precision storage of the basis (and of A's Arnoldi copy)
+    # the limited solver of the convergence study (section 4.1): only A's
+    # Arnoldi copy, M and the basis are stored in float32; w, the dot
+    # products and the product's sums stay float64
+    limited = precision == "limited"
     two_byte = precision in ("bf16", "fp16")
     total = 0
     restarts = 0
@@ -479,7 +494,11 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 return (V[i] * np.float32(scale[i])).astype(np.float32)
             return V[i]
 
+        def operand(i):  # basis vector i as the orthogonalisation reads it
+            return V[i].astype(np.float64) if limited else basis(i)
+
         k = 0
+        W = []  # (record) w after orthogonalisation, before normalisation, per step
         cycle_arn = []
         ares = [beta]  # |s_1| .. |s_{j+1}| of this cycle
         if orth_restart > 0.0:
@@ -494,22 +513,27 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 src = Z[j]
             else:
                 src = vj
-            w = A.matvec32(src, a32) if lowp else A.matvec(src)
+            if limited:
+                w = A.matvec_wide(src, a32)
+            else:
+                w = A.matvec32(src, a32) if lowp else A.matvec(src)
             # orthogonalize(w, V_j)
             hcol = np.zeros(j + 1)
             if ortho == "mgs":
                 for i in range(j + 1):
-                    vi = basis(i)
+                    vi = operand(i)
                     hij = float(np.dot(w, vi))
                     hcol[i] = hij
-                    w = (w - (np.float32(hij) if lowp else hij) * vi).astype(w.dtype)
+                    w = (w - (np.float32(hij) if lowp and not limited else hij) * vi).astype(w.dtype)
             else:
-                Vj = np.stack([basis(i) for i in range(j + 1)], axis=1)
+                Vj = np.stack([operand(i) for i in range(j + 1)], axis=1)
                 for _ in range(2):  # classical Gram-Schmidt, then its re-orthogonalisation pass
                     hp = Vj.T @ w
                     w = (w - Vj @ hp.astype(w.dtype)).astype(w.dtype)
                     hcol += hp.astype(np.float64)
             hnext = float(np.linalg.norm(w.astype(np.float64)))
+            if record:
+                W.append(w.astype(np.float64))
             H[: j + 1, j] = hcol
             H[j + 1, j] = hnext
             Hbar[: j + 2, j] = H[: j + 2, j]
@@ -574,7 +598,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         if record:
             cyc.append({"V": [basis(i).astype(np.float64) for i in range(k + 1) if V[i] is not None],
                         "Hbar": Hbar[: k + 1, :k].copy(), "H": H[:k, :k].copy(), "s": s[: k + 1].copy(),
-                        "k": k, "beta": beta, "y": y, "cs": cs[:k].copy(), "sn": sn[:k].copy()})
+                        "k": k, "beta": beta, "y": y, "cs": cs[:k].copy(), "sn": sn[:k].copy(), "W": W})
     return Result(x, status, total, restarts, hist[-1], hist, arn, cyc, fallback_used)
 
 

@@ -8,13 +8,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgmres.so")
 
 MGS, CGSR = 0, 1
-FP64, MIXED_FP32, MIXED_BF16, MIXED_FP16 = 0, 1, 2, 3
+FP64, MIXED_FP32, MIXED_BF16, MIXED_FP16, MIXED_LIMITED = 0, 1, 2, 3, 4
 PRECOND_NONE, PRECOND_JACOBI, PRECOND_SPAI, PRECOND_ILU0 = 0, 1, 2, 3
 RUNNING, CONVERGED, MAXITER, STALLED = 0, 1, 2, 3
 OK, EINVAL, EHIP, ENOMEM, EHANDLE, ESTATE = 0, -1, -2, -3, -4, -5
 
 STATUS_NAMES = {RUNNING: "RUNNING", CONVERGED: "CONVERGED", MAXITER: "MAXITER", STALLED: "STALLED"}
-PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16}
+PRECISIONS = {"fp64": FP64, "fp32": MIXED_FP32, "bf16": MIXED_BF16, "fp16": MIXED_FP16,
+              "limited": MIXED_LIMITED}
 ORTHOS = {"mgs": MGS, "cgsr": CGSR}
 PRECONDS = {"none": PRECOND_NONE, "jacobi": PRECOND_JACOBI, "spai": PRECOND_SPAI, "ilu0": PRECOND_ILU0}
 SCHEDULE_AUTO, SCHEDULE_DEVICE_WIDE, SCHEDULE_PERSISTENT = 0, 1, 2

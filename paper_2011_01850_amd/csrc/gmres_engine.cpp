@@ -154,7 +154,7 @@ bool valid_options(const gmres_options* o) {
   if (!(o->tol >= 0.0)) return false;
   if (o->max_iters < 0) return false;
   if (o->ortho != GMRES_MGS && o->ortho != GMRES_CGSR) return false;
-  if (o->precision < GMRES_FP64 || o->precision > GMRES_MIXED_FP16) return false;
+  if (o->precision < GMRES_FP64 || o->precision > GMRES_MIXED_LIMITED) return false;
   if (o->precond < GMRES_PRECOND_NONE || o->precond > GMRES_PRECOND_ILU0) return false;
   if (o->ilu_sweeps < 0 || o->ilu_sweeps > 4096) return false;
   if (o->precond != GMRES_PRECOND_NONE && o->precision == GMRES_FP64) return false;
@@ -327,8 +327,8 @@ SegTab make_split(gmres_ctx* h, int G) {
   return sg;
 }
 
-int64_t vbytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
-int64_t wbytes(int prec) { return prec == P64 ? 8 : 4; }
+int64_t vbytes(int prec) { return prec == P64 ? 8 : ((prec == P32 || prec == PL32) ? 4 : 2); }
+int64_t wbytes(int prec) { return wide_w(prec) ? 8 : 4; }
 
 // Enqueue one restart cycle: residual and stop test, m Arnoldi steps,
 // back-solve and update.  Every kernel is gated on the device.
@@ -1059,17 +1059,19 @@ int gmres_spmv(gmres_handle hh, int32_t precision, const void* x, void* y) {
   try {
     gmres_ctx* h = get(hh);
     if (!x || !y) return GMRES_EINVAL;
-    if (precision != GMRES_FP64 && precision != GMRES_MIXED_FP32) return GMRES_EINVAL;
-    if (precision == GMRES_MIXED_FP32 && !h->a.a32 && !h->a.asplit) return GMRES_ESTATE;
+    if (precision != GMRES_FP64 && precision != GMRES_MIXED_FP32 && precision != GMRES_MIXED_LIMITED)
+      return GMRES_EINVAL;
+    if (precision != GMRES_FP64 && !h->a.a32 && !h->a.asplit) return GMRES_ESTATE;
     if (h->sys.size() != 1) return GMRES_ESTATE;
     const int64_t n = h->sys[0].n;
-    const size_t eb = precision == GMRES_FP64 ? 8 : 4;
+    const size_t xb = precision == GMRES_FP64 ? 8 : 4, yb = precision == GMRES_MIXED_FP32 ? 4 : 8;
     // padded staging so that the kernel's global indexing is valid
     after_caller(h);
     hip_check(hipMemsetAsync(h->xs, 0, h->ld * 8, h->stream));
-    hip_check(hipMemcpyAsync(h->xs, x, n * eb, hipMemcpyDeviceToDevice, h->stream));
-    hip_check(launch_spmv_plain(h->a, precision == GMRES_FP64 ? P64 : P32, h->xs, h->ys, h->stream));
-    hip_check(hipMemcpyAsync(y, h->ys, n * eb, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipMemcpyAsync(h->xs, x, n * xb, hipMemcpyDeviceToDevice, h->stream));
+    const int prec = precision == GMRES_FP64 ? P64 : (precision == GMRES_MIXED_FP32 ? P32 : PL32);
+    hip_check(launch_spmv_plain(h->a, prec, h->xs, h->ys, h->stream));
+    hip_check(hipMemcpyAsync(y, h->ys, n * yb, hipMemcpyDeviceToDevice, h->stream));
     hip_check(hipStreamSynchronize(h->stream));
     return GMRES_OK;
   } catch (const Fail& f) {

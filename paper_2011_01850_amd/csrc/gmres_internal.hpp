@@ -33,7 +33,11 @@ __host__ __device__ inline int row_lanes(int len) {
   return T;
 }
 
-enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3 };
+// Storage of the basis / of w: P64 float64 / float64, P32 float32 / float32,
+// PBF16 and PF16 2-byte / float32, PL32 (the limited mode) float32 / float64.
+enum Prec { P64 = 0, P32 = 1, PBF16 = 2, PF16 = 3, PL32 = 4 };
+// w, its dot products and the Arnoldi product are float64
+inline bool wide_w(int prec) { return prec == P64 || prec == PL32; }
 enum Status { RUNNING = 0, CONVERGED = 1, MAXITER = 2, STALLED = 3 };
 
 // Per-system scalar state, device resident.  Written only by one lane of a
@@ -126,7 +130,7 @@ struct KArgs {
   // vectors (ld rows each)
   void* V;        // m+1 basis columns, storage per prec
   float* Z;       // m preconditioned columns (flexible form)
-  void* w;        // work vector: double (P64) or float
+  void* w;        // work vector: double (P64, PL32) or float
   double* x;      // iterate
   double* b;      // right-hand side
   double* zres;   // float64 restart residual (ld rows)

@@ -55,6 +55,12 @@ template <>
 struct AccOf<HiLoW> {
   using type = double;
 };
+// Accumulation type of a kernel that reads TIn and writes TOut: float64
+// whenever the written vector is float64 (the limited precision mode keeps
+// w, its dot products and the Arnoldi product's sums in float64 over a
+// float32 basis and a float32 copy of A), else that of what it reads.
+template <typename TIn, typename TOut>
+using AccFor = typename std::conditional<sizeof(TOut) == 8, double, typename AccOf<TIn>::type>::type;
 __device__ __forceinline__ float hi_value(uint32_t h) { return (float)__hiloint2double((int)h, 0); }
 __device__ __forceinline__ double hilo_value(uint32_t h, uint32_t l) { return __hiloint2double((int)h, (int)l); }
 
@@ -431,7 +437,7 @@ template <typename TA, typename TX, typename TY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__ vals,
                                                  const TX* __restrict__ x, TY* __restrict__ y,
                                                  const double* __restrict__ bvec, int j) {
-  using ACC = typename AccOf<TA>::type;
+  using ACC = AccFor<TA, TY>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   ACC* prod = reinterpret_cast<ACC*>(smem_raw);
   const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
@@ -683,7 +689,7 @@ __device__ __forceinline__ void store_colsums(double* part, int nrows, int k, in
 // (as stored, before its decode scale) in place of w.
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int col0, int mode, int rev) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   const int b = pass_block(a, sg, rev);
   const int lane = threadIdx.x & 63;
   const int ncol = min(L, j + 1 - col0);
@@ -728,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
 // V^T w' from the same register tile of V.  Requires j + 1 <= L <= 64.
 template <typename TV, typename TW, int L>
 __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg, int j, int rev) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   const int b = pass_block(a, sg, rev);
   const int t = threadIdx.x, lane = t & 63;
   const int ncol = j + 1;
@@ -768,8 +774,9 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
   }
 }
 
-// 4-byte and 2-byte bases: capped at 128 registers so four workgroups fit on
-// a CU; the float64 tile needs more registers than that.
+// float32 w (4-byte and 2-byte bases): capped at 128 registers so four
+// workgroups fit on a CU; with float64 w the tile is held in float64 and
+// needs more registers than that (k_axpy_mdot64).
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_axpy_mdot(KArgs a, SegTab sg, int j, int rev) {
@@ -784,7 +791,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_mdot64(KArgs a, SegTab sg, int 
 // when j + 1 > 64.
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, SegTab sg, int j, int col0) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   const int b = pass_block(a, sg, 0);
   const int ncol = min(L, j + 1 - col0);
   TW* w = reinterpret_cast<TW*>(a.w);
@@ -820,7 +827,7 @@ __device__ __forceinline__ void store_norm_partials(double* part, int nrows, int
 // decode scale 1/h_{j+1,j}) or stays in w (2-byte basis, encoded later).
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j, int rev) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   constexpr bool kTwoByte = sizeof(TV) == 2;
   const int b = pass_block(a, sg, rev);
   const int t = threadIdx.x;
@@ -868,7 +875,7 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
 // The same last pass for j + 1 > 64 (column loop instead of a register tile).
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kBlock) void k_final(KArgs a, SegTab sg, int j) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   constexpr bool kTwoByte = sizeof(TV) == 2;
   const int b = pass_block(a, sg, 0);
   TW* w = reinterpret_cast<TW*>(a.w);
@@ -925,7 +932,7 @@ __device__ __forceinline__ double mgs_complete(const KArgs& a, const SegTab& sgp
 
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   const int b = pass_block(a, sg, i & 1);
   double* pout = (i & 1) ? a.part2 : a.part;
   const double* pin = (i & 1) ? a.part : a.part2;  // dot i-1
@@ -976,7 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
 // split sgp), w'' = w - h_j v_j, and the partials of ||w''||^2, max|w''|.
 template <typename TV, typename TW>
 __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab sgp, int j) {
-  using ACC = typename AccOf<TV>::type;
+  using ACC = AccFor<TV, TW>;
   constexpr bool kTwoByte = sizeof(TV) == 2;
   const int b = pass_block(a, sg, (j + 1) & 1);
   const double* pin = (j & 1) ? a.part2 : a.part;
@@ -1562,6 +1569,7 @@ static hipError_t launch_by_prec(int prec, F&& f) {
     case P32: return f(float{}, float{});
     case PBF16: return f(bf16_t{}, float{});
     case PF16: return f(f16_t{}, float{});
+    case PL32: return f(float{}, double{});
   }
   return hipErrorInvalidValue;
 }
@@ -1618,11 +1626,20 @@ static hipError_t launch_fin_cols(const KArgs& a, const SegTab& sg, int j, hipSt
 }
 
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
-  const size_t sh = (size_t)a.spmv_budget * (a.prec == P64 ? 8 : 4);
+  const size_t sh = (size_t)a.spmv_budget * (wide_w(a.prec) ? 8 : 4);
   const HiW* hw = reinterpret_cast<const HiW*>(a.ahi);
   const HiLoW* hlw = reinterpret_cast<const HiLoW*>(a.ahi);
   if (a.precond != 0) {  // w = A z_j
     const float* z = a.Z + (int64_t)j * a.ld;
+    if (wide_w(a.prec)) {
+      if (a.asplit)
+        hipLaunchKernelGGL((k_spmv<HiW, float, double, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, z,
+                           (double*)a.w, nullptr, j);
+      else
+        hipLaunchKernelGGL((k_spmv<float, float, double, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a32, z,
+                           (double*)a.w, nullptr, j);
+      return hipGetLastError();
+    }
     if (a.asplit)
       hipLaunchKernelGGL((k_spmv<HiW, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, z,
                          (float*)a.w, nullptr, j);
@@ -1635,14 +1652,14 @@ hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
     using TV = decltype(tv);
     using TW = decltype(tw);
     const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
-    if constexpr (sizeof(TW) == 8) {
+    if constexpr (sizeof(TW) == 8 && sizeof(TV) == 8) {
       if (a.asplit)
         hipLaunchKernelGGL((k_spmv<HiLoW, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, hlw, x,
                            (TW*)a.w, nullptr, j);
       else
         hipLaunchKernelGGL((k_spmv<double, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a64, x,
                            (TW*)a.w, nullptr, j);
-    } else {
+    } else {  // float32 copy of A (or its high words); float64 sums when w is float64
       if (a.asplit)
         hipLaunchKernelGGL((k_spmv<HiW, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, x,
                            (TW*)a.w, nullptr, j);
@@ -1714,7 +1731,7 @@ hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {
   // once the stop test has decided that a cycle starts (launch_encode)
   const size_t sh = (size_t)a.spmv_budget * 8;
   const HiLoW* hlw = reinterpret_cast<const HiLoW*>(a.ahi);
-  if (a.prec == P64) {
+  if (wide_w(a.prec)) {
     if (a.asplit)
       hipLaunchKernelGGL((k_spmv<HiLoW, double, double, SM_RESID>), dim3(a.nrb), dim3(kBlock), sh, st, a, hlw,
                          a.x, (double*)a.w, a.b, 0);
@@ -1765,7 +1782,7 @@ hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin
 
 template <typename TV, typename TW, int L>
 static hipError_t launch_axpy_mdot_L(const KArgs& a, int j, hipStream_t st, const SegTab** used) {
-  if constexpr (sizeof(TV) == 8) {
+  if constexpr (sizeof(TW) == 8) {
     auto kern = k_axpy_mdot64<TV, TW, L>;
     const SegTab& sg = split_for(a, kern);
     hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass2);
@@ -1818,7 +1835,7 @@ hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st) {
     if (j + 1 <= 64) {
       const int L = lanes_for(j + 1);
       const void* k = nullptr;
-      if constexpr (sizeof(TV) == 8) {
+      if constexpr (sizeof(TW) == 8) {
         k = L == 8 ? (const void*)k_axpy_mdot64<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64<TV, TW, 16>
           : L == 32 ? (const void*)k_axpy_mdot64<TV, TW, 32> : (const void*)k_axpy_mdot64<TV, TW, 64>;
       } else {
@@ -1911,15 +1928,21 @@ hipError_t prepare_occupancy(int prec) {
     using TW = decltype(tw);
     const void* ks[] = {
         (const void*)k_mdot<TV, TW, 8>, (const void*)k_mdot<TV, TW, 16>, (const void*)k_mdot<TV, TW, 32>,
-        (const void*)k_mdot<TV, TW, 64>, (const void*)k_axpy_mdot<TV, TW, 8>,
-        (const void*)k_axpy_mdot<TV, TW, 16>, (const void*)k_axpy_mdot<TV, TW, 32>,
-        (const void*)k_axpy_mdot<TV, TW, 64>, (const void*)k_axpy_mdot64<TV, TW, 8>,
-        (const void*)k_axpy_mdot64<TV, TW, 16>, (const void*)k_axpy_mdot64<TV, TW, 32>,
-        (const void*)k_axpy_mdot64<TV, TW, 64>, (const void*)k_axpy<TV, TW, 64>,
+        (const void*)k_mdot<TV, TW, 64>, (const void*)k_axpy<TV, TW, 64>,
         (const void*)k_final_tile<TV, TW, 8>, (const void*)k_final_tile<TV, TW, 16>,
         (const void*)k_final_tile<TV, TW, 32>, (const void*)k_final_tile<TV, TW, 64>,
         (const void*)k_final<TV, TW>, (const void*)k_mgs<TV, TW>, (const void*)k_mgs_final<TV, TW>};
     for (const void* k : ks) occupancy_of(k);
+    // the fused projection-2 kernel in the variant that is launched
+    if constexpr (sizeof(TW) == 8) {
+      const void* kf[] = {(const void*)k_axpy_mdot64<TV, TW, 8>, (const void*)k_axpy_mdot64<TV, TW, 16>,
+                          (const void*)k_axpy_mdot64<TV, TW, 32>, (const void*)k_axpy_mdot64<TV, TW, 64>};
+      for (const void* k : kf) occupancy_of(k);
+    } else {
+      const void* kf[] = {(const void*)k_axpy_mdot<TV, TW, 8>, (const void*)k_axpy_mdot<TV, TW, 16>,
+                          (const void*)k_axpy_mdot<TV, TW, 32>, (const void*)k_axpy_mdot<TV, TW, 64>};
+      for (const void* k : kf) occupancy_of(k);
+    }
     return hipSuccess;
   });
 }
@@ -1992,6 +2015,13 @@ hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, h
     else
       hipLaunchKernelGGL((k_spmv<double, double, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh8, st, a,
                          a.a64, (const double*)x, (double*)y, nullptr, 0);
+  } else if (prec == PL32) {  // float32 values and x, float64 sums and y
+    if (a.asplit)
+      hipLaunchKernelGGL((k_spmv<HiW, float, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh8, st, a,
+                         reinterpret_cast<const HiW*>(a.ahi), (const float*)x, (double*)y, nullptr, 0);
+    else
+      hipLaunchKernelGGL((k_spmv<float, float, double, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh8, st, a,
+                         a.a32, (const float*)x, (double*)y, nullptr, 0);
   } else {
     if (a.asplit)
       hipLaunchKernelGGL((k_spmv<HiW, float, float, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh4, st, a,

@@ -165,7 +165,7 @@ class Solver:
         torch = self._torch
         dt = torch.float64 if precision == "fp64" else torch.float32
         xt = _dev(x, dt, torch)
-        y = torch.empty(self.n, dtype=dt, device="cuda")
+        y = torch.empty(self.n, dtype=torch.float32 if precision == "fp32" else torch.float64, device="cuda")
         torch.cuda.synchronize()
         L.check(self.lib.gmres_spmv(self.h, L.PRECISIONS[precision], xt.data_ptr(), y.data_ptr()), "gmres_spmv")
         return y

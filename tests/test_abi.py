@@ -58,7 +58,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.gmres_create(C.byref(h), 0, 0, None, None, None, C.byref(o), None) == L.EINVAL
     assert lib.gmres_create(C.byref(h), 10, 5, None, None, None, C.byref(o), None) == L.EINVAL
     assert lib.gmres_create(None, 10, 5, 1, 1, 1, C.byref(o), None) == L.EINVAL
-    for field, bad in [("m", 0), ("m", 257), ("tol", -1.0), ("ortho", 7), ("precision", 9),
+    for field, bad in [("m", 0), ("m", 257), ("tol", -1.0), ("ortho", 7), ("precision", 9), ("precision", 5), ("precision", -1),
                        ("precond", 5), ("stall_cycles", 0), ("restart_improve", -0.5), ("batch_schedule", 3),
                        ("batch_schedule", -1), ("spmv_block_nnz", 32), ("spmv_block_nnz", 100),
                        ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1), ("restart_repeat", 2),

@@ -63,11 +63,37 @@ def test_spmv_integer_inputs_bitwise(n, long_rows):
     ref = M.matvec(x)
     assert np.array_equal(y64, ref)
     assert np.array_equal(y32, ref.astype(np.float32))
+    s_lim = _solver(A, precision="limited", m=4)
+    assert np.array_equal(s_lim.spmv(x.astype(np.float32), "limited").cpu().numpy(), ref)
+    s_lim.close()
     b = g.integers(-100, 101, n).astype(np.float64)
     r, nrm = s.residual(b, x)
     assert np.array_equal(r.cpu().numpy(), b - ref)
     assert math.isclose(nrm, float(np.linalg.norm(b - ref)), rel_tol=1e-14)
     s.close()
+
+
+@pytest.mark.parametrize("n,long_rows", [(5000, ()), (7001, (3, 4000))])
+def test_limited_spmv_sums_in_float64(n, long_rows):
+    # the limited mode's product: float32 values and x, every product exact in
+    # float64 and summed in float64 (the oracle's matvec_wide up to summation
+    # order), far closer to it than the float32 product
+    A = _int_csr(n, n + 1, long_rows)
+    g = np.random.default_rng(4)
+    A = P.CSR(A.n, A.row_ptr, A.col_idx, A.vals * g.uniform(0.5, 1.5, A.nnz))
+    M = O.Matrix.from_csr(A)
+    x32 = g.standard_normal(n).astype(np.float32)
+    ref = M.matvec_wide(x32)
+    absum = np.bincount(M.rows, weights=np.abs(M.vals32.astype(np.float64) * x32.astype(np.float64)[M.col_idx]),
+                        minlength=n)
+    s = _solver(A, precision="limited", m=4)
+    y = s.spmv(x32, "limited").cpu().numpy()
+    y32 = s.spmv(x32, "fp32").cpu().numpy().astype(np.float64)
+    s.close()
+    assert y.dtype == np.float64
+    assert np.all(np.abs(y - ref) <= 16 * O.U64 * absum)
+    assert np.max(np.abs(y32 - ref) / np.maximum(absum, 1e-300)) > 1e3 * np.max(
+        np.abs(y - ref) / np.maximum(absum, 1e-300))
 
 
 @pytest.mark.parametrize("n,long_rows", [(5000, ()), (7001, (3, 4000))])
@@ -254,13 +280,13 @@ def _oracle_emulated(name, ortho, precision):
 
 @pytest.mark.parametrize("name", [c[0] for c in CASES])
 @pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp16", "limited"])
 def test_solver_matches_oracle(name, ortho, precision):
     pr, m = _case(name)
     ref = _oracle_x(name, ortho)
     x, info = _parity_case(pr.A, pr.b, m, ortho, precision)
     rr = _relres(pr.A, pr.b, x)
-    emu = _oracle_emulated(name, ortho, precision) if precision in ("bf16", "fp16") else None
+    emu = _oracle_emulated(name, ortho, precision) if precision in ("bf16", "fp16", "limited") else None
     print(f"{name} {ortho} {precision}: gpu {info['status']} iters {info['iters']} restarts "
           f"{info['restarts']} relres {rr:.3e} | oracle fp64 iters {ref.iters}"
           + (f" | oracle {precision} emulation {emu.status_name} iters {emu.iters} relres "
@@ -285,9 +311,12 @@ def test_solver_matches_oracle(name, ortho, precision):
         assert abs(_cycles_to(info["history"], 1e-10) - _cycles_to(ref.history, 1e-10)) <= 1
         if ref.iters < 1000:
             assert abs(info["iters"] - ref.iters) <= 2
+    if precision == "limited":
+        # the oracle's emulation of the same storage split reaches 1e-10 within a cycle of it
+        assert abs(_cycles_to(info["history"], 1e-10) - _cycles_to(emu.history, 1e-10)) <= 1
 
 
-@pytest.mark.parametrize("precision,u", [("fp64", O.U64), ("fp32", O.U32)])
+@pytest.mark.parametrize("precision,u", [("fp64", O.U64), ("fp32", O.U32), ("limited", O.U32)])
 @pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
 def test_gpu_basis_satisfies_arnoldi_relation(precision, u, ortho):
     A = P.convdiff(24, (20.0, 10.0))
@@ -303,12 +332,70 @@ def test_gpu_basis_satisfies_arnoldi_relation(precision, u, ortho):
     assert k == m
     R = D @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k]
     # the float32 basis is stored unnormalised; its decode scale is exact to u32
-    assert np.linalg.norm(R) <= 10 * k * u * np.linalg.norm(D) * (50 if precision == "fp32" else 1)
+    assert np.linalg.norm(R) <= 10 * k * u * np.linalg.norm(D) * (50 if precision != "fp64" else 1)
     orth = np.linalg.norm(np.eye(k + 1) - V.T @ V, 2)
     if ortho == "cgsr":
-        assert orth <= 10 * (k + 1) * u * (10 if precision == "fp32" else 1)
+        assert orth <= 10 * (k + 1) * u * (10 if precision != "fp64" else 1)
     else:
         assert orth < (1e-6 if precision == "fp64" else 1e-2)
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_limited_basis_is_float32_rounding_of_float64_w(ortho):
+    # limited mode: w'' = A32 v_j - V_j h_j is computed in float64 and only its
+    # storage as basis column j+1 is rounded, so that column is the float32
+    # rounding of w'' recomputed from the GPU's own basis and H (to within
+    # float64 noise).  In the fully float32 mode w'' carries float32
+    # arithmetic errors of many ulps.
+    A0 = P.convdiff(24, (20.0, 10.0))
+    g = np.random.default_rng(11)
+    A = P.CSR(A0.n, A0.row_ptr, A0.col_idx, A0.vals * (1.0 + g.uniform(0.0, 1e-3, A0.nnz)))
+    D32 = O.Matrix.from_csr(A).dense().astype(np.float32).astype(np.float64)
+    b = g.standard_normal(A.n)
+    m = 30
+    bad = {}
+    for prec in ("limited", "fp32"):
+        s = _solver(A, m=m, ortho=ortho, precision=prec, tol=0.0, max_iters=m)
+        s.solve(b)
+        k, Hb, V = s.last_cycle()
+        s.close()
+        V = V.cpu().numpy()
+        assert k == m
+        nb, tot = 0, 0
+        for j in range(k):
+            h = Hb[: j + 1, j]
+            R = D32 @ V[:, j] - V[:, : j + 1] @ h
+            stored = (V[:, j + 1] * Hb[j + 1, j]).astype(np.float32)  # exact: V is stored * (1 / h)
+            half_ulp = 0.5 * np.spacing(np.abs(stored)).astype(np.float64)
+            noise = 64 * (j + 2) * O.U64 * (np.abs(D32) @ np.abs(V[:, j]) + np.abs(V[:, : j + 1]) @ np.abs(h))
+            nb += int(np.count_nonzero(np.abs(R - stored.astype(np.float64)) > half_ulp + noise))
+            tot += A.n
+        bad[prec] = nb / tot
+    print(f"{ortho}: entries off the float32 rounding of float64 w'': limited {bad['limited']:.2e}, "
+          f"fp32 {bad['fp32']:.2e}", flush=True)
+    assert bad["limited"] == 0.0
+    assert bad["fp32"] > 0.05
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "ilu0"])
+def test_limited_mode_with_preconditioners(precond):
+    # float32 M (its output z_j) in the limited mode: w = A z_j summed in float64
+    A0 = P.varcoef3d(16, family=94, index=0)
+    M = O.Matrix.from_csr(A0)
+    xt, b = P.manufactured_rhs(A0, 94, 0)
+    if precond == "jacobi":
+        d = M.diagonal()
+        pc = lambda v: v / d  # noqa: E731
+    else:
+        lu, diag = O.ilu0(M)
+        pc = lambda v: O.ilu_apply(M, lu, diag, v, sweeps=4)  # noqa: E731
+    ref = O.gmres(M, b, m=30, tol=1e-11, fallback=False, precond=pc, precision="limited")
+    s = _solver(A0, m=30, precision="limited", precond=precond, tol=1e-11)
+    x, info = s.solve(b)
+    s.close()
+    assert info["status"] == "CONVERGED" and not info["fallback_used"]
+    assert _relres(A0, b, x.cpu().numpy()) <= 1.01e-11
+    assert abs(info["iters"] - ref.iters) <= max(10, 0.1 * ref.iters)
 
 
 def test_edge_cases():

@@ -319,6 +319,50 @@ def test_two_byte_basis_still_reaches_double_accuracy(fmt):
     assert r.status == O.CONVERGED
 
 
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_limited_mode_stores_float32_and_computes_w_in_float64(ortho):
+    # the limited solver of section 4.1 stores A's Arnoldi copy and the basis
+    # in float32 and nothing else: every stored basis vector is
+    # float32-representable, and w'' = A v_j - V_j h_j holds to float64
+    # rounding with the float32 values of A (only to about u32 with its
+    # float64 values, and only to about u32 in the fully float32 mode)
+    A0 = P.convdiff(12, (20.0, 10.0))
+    g = np.random.default_rng(9)
+    A = O.Matrix(A0.row_ptr, A0.col_idx, A0.vals * (1.0 + g.uniform(0.0, 1e-3, A0.nnz)), A0.n)
+    D64 = A.dense()
+    D32 = D64.astype(np.float32).astype(np.float64)
+    b = np.random.default_rng(3).standard_normal(A.n)
+    m = 30
+    rel = {}
+    for prec in ("limited", "fp32", "fp64"):
+        c = O.gmres(A, b, m=m, tol=0.0, max_iters=m, ortho=ortho, precision=prec, record=True).cycles[0]
+        k, V, Hb, W = c["k"], np.stack(c["V"], 1), c["Hbar"], c["W"]
+        assert k == m
+        stored32 = np.array_equal(V, V.astype(np.float32).astype(np.float64))
+        assert stored32 == (prec != "fp64")
+        r32, r64 = [], []
+        for j in range(k):
+            scale = np.linalg.norm(D32, 2) * np.linalg.norm(V[:, j]) + np.abs(Hb[: j + 1, j]).sum()
+            r32.append(np.linalg.norm(D32 @ V[:, j] - V[:, : j + 1] @ Hb[: j + 1, j] - W[j]) / scale)
+            r64.append(np.linalg.norm(D64 @ V[:, j] - V[:, : j + 1] @ Hb[: j + 1, j] - W[j]) / scale)
+        rel[prec] = (max(r32), min(r64), max(r64))
+    assert rel["limited"][0] <= 10 * m * O.U64  # float64 w over the float32 values of A
+    assert rel["limited"][1] >= 1e-3 * O.U32  # ... and not over its float64 values
+    assert rel["fp64"][2] <= 10 * m * O.U64
+    assert rel["fp32"][0] >= 1e-2 * O.U32  # float32 w: relation to about u32 only
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_limited_mode_reaches_double_accuracy(ortho):
+    # section 4.1: after restarting, both mixed solvers regain float64 accuracy
+    pr = P.c1_convdiff2d(32)
+    A = _mat(pr.A)
+    r64 = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho)
+    rl = O.gmres(A, pr.b, m=30, tol=1e-10, ortho=ortho, precision="limited")
+    assert rl.status == O.CONVERGED and rl.rel_residual <= 1e-10 and rl.restarts >= 2
+    assert abs(rl.iters - r64.iters) <= 30
+
+
 # --------------------------------------------------------------------------
 # restart strategies of the restart study (section 3)
 

@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16"],
                     help="mixed mode timed as `value` (default fp32; bf16 for powerlaw)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 baseline")
+    ap.add_argument("--modes", default="fp64,fp32,bf16,fp16",
+                    help="powerlaw: comma-separated precision modes to run (fp64 is always run first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=10)
     ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample: inner iterations")
@@ -302,7 +304,10 @@ def bench_powerlaw(args):
     # (dozens of cycles can pass between new lowest residuals), so the
     # no-progress stop is set far out for every mode
     stall = 1000
-    for mode in ["fp64", "fp32", "bf16", "fp16"]:
+    run_modes = ["fp64"] + [md for md in ["fp32", "bf16", "fp16"] if md in args.modes.split(",")]
+    if value_mode not in run_modes:
+        raise SystemExit(f"--precision {value_mode} is not among --modes {args.modes}")
+    for mode in run_modes:
         t, inf, (s, x) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, mode,
                                           args.steps, args.warmup, stall_cycles=stall)
         xs = x.cpu().numpy()

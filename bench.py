@@ -52,11 +52,13 @@ def measured_traffic():
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="convdiff3d", choices=["convdiff3d", "powerlaw", "batch", "learned", "restart"],
+    ap.add_argument("--workload", default="convdiff3d",
+                    choices=["convdiff3d", "powerlaw", "batch", "learned", "restart", "variables"],
                     help="convdiff3d: the headline time-to-solution (default); powerlaw: the n = 1e6 "
                          "power-law system in every precision mode; batch: 512 uneven 2-D systems in one handle; "
                          "learned: train the sparse-approximate-inverse network on the GPU, then FGMRES on "
-                         "held-out variable-coefficient systems")
+                         "held-out variable-coefficient systems; restart: restart strategies; variables: "
+                         "the per-variable precision study (one correction variable in float32 at a time)")
     ap.add_argument("--train-instances", type=int, default=2000)
     ap.add_argument("--test-instances", type=int, default=200)
     ap.add_argument("--baseline-instances", type=int, default=20,
@@ -348,6 +350,65 @@ def bench_powerlaw(args):
     return rec
 
 
+def bench_variables(args):
+    """Per-variable precision study (section 4.1): a 2-D convection-diffusion
+    system of the size of the paper's airfoil_2d matrix, GMRES(256) (the
+    longest cycle the library takes; the paper restarts every 300), with the
+    correction's variables in float32 one at a time, then together."""
+    import numpy as np
+    import torch
+
+    import problems as P
+    from paper_2011_01850_amd import Solver
+
+    N, m = 119, 256
+    A = P.convdiff(N, (100.0, 50.0))
+    x_true, b = P.manufactured_rhs(A, 21, 0)
+    A_dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
+    b_dev = torch.as_tensor(b, device="cuda")
+    torch.cuda.synchronize()
+    cases = [("none", "fp64", "default"), ("A (Krylov product)", "fp64", "fp32"),
+             ("basis V", "limited", "fp64"), ("A, M, V (limited solver)", "limited", "default"),
+             ("every correction variable", "fp32", "default")]
+    rows = {}
+    rp, ci, va = A_dev
+    for ortho in ("mgs", "cgsr"):
+        for label, prec, arnoldi_a in cases:
+            times, info, hist = [], None, None
+            for it in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = Solver(rp, ci, va, m=m, ortho=ortho, precision=prec, tol=1e-10, max_iters=100_000,
+                           arnoldi_a=arnoldi_a)
+                x, info = s.solve(b_dev)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                hist = s.history()
+                s.close()
+                if it >= args.warmup:
+                    times.append(dt)
+            fwd = float(np.linalg.norm(x.cpu().numpy() - x_true) / np.linalg.norm(x_true))
+            key = f"{ortho}:{label}"
+            rows[key] = {"precision": prec, "arnoldi_a": arnoldi_a, "seconds_mean": statistics.mean(times),
+                         "iters": info["iters"], "restarts": info["restarts"], "status": info["status"],
+                         "first_stall": info["first_stall"], "rel_residual": info["rel_residual"],
+                         "restart_residuals": [float(h) for h in hist], "forward_error": fwd}
+            log(f"  {key:40s} {statistics.mean(times) * 1e3:8.2f} ms iters {info['iters']} restarts "
+                f"{info['restarts']} first stall {info['first_stall']} residuals "
+                + " ".join(f"{h:.1e}" for h in hist))
+    v = rows["cgsr:A, M, V (limited solver)"]["seconds_mean"]
+    return {
+        "metric": METRIC, "value": round(v, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(v * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"2-D convection-diffusion {N}^2 (n={A.n}, nnz={A.nnz}), beta=(100,50), "
+                               f"GMRES({m}) MGS and CGSR with one correction variable in float32 at a time "
+                               f"(value: the limited solver, CGSR), tol 1e-10, time incl. setup",
+                   "n": A.n, "nnz": A.nnz, "m": m},
+        "cases": rows, "roofline": None, "cpu_baseline": None,
+    }
+
+
 def bench_restart(args):
     """Restart strategies on a well-conditioned 3-D convection-diffusion
     system (the C2 operator plus a diagonal shift), MGS GMRES(64): float64
@@ -632,7 +693,7 @@ def main():
             rec = bench_learned(args, pool)
     else:
         rec = {"convdiff3d": bench_convdiff3d, "powerlaw": bench_powerlaw,
-               "batch": bench_batch, "restart": bench_restart}[args.workload](args)
+               "batch": bench_batch, "restart": bench_restart, "variables": bench_variables}[args.workload](args)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

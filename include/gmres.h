@@ -150,9 +150,23 @@ typedef struct {
   double orth_restart;
   int32_t orth_norm;
   int32_t ilu_sweeps;       /* GMRES_PRECOND_ILU0: Jacobi sweeps per triangle (0 = exact), 0..4096 */
+  int32_t arnoldi_a;        /* GMRES_ARNOLDI_A_*: which values of A the Arnoldi product reads */
 } gmres_options;
 
 enum { GMRES_ORTH_SPECTRAL = 0, GMRES_ORTH_FROBENIUS = 1 };
+
+/* gmres_options.arnoldi_a, for the per-variable study of section 4.1 (one
+ * variable of the correction in single precision, the rest unchanged):
+ * DEFAULT  float64 values with GMRES_FP64, float32 values (the float32 copy,
+ *          or the high words under SPLIT storage) in every mixed mode.
+ * FP64     the float64 values in any mode (no float32 copy is kept); with
+ *          GMRES_MIXED_LIMITED this leaves the basis (and M) as the only
+ *          float32 variables.
+ * FP32     the float32 values in any mode; with GMRES_FP64 this makes A for
+ *          the next Krylov vector the only float32 variable.
+ * The product's sums are float64 whenever w or the values are float64.
+ * FP32 is the only choice with the persistent batch schedule. */
+enum { GMRES_ARNOLDI_A_DEFAULT = 0, GMRES_ARNOLDI_A_FP64 = 1, GMRES_ARNOLDI_A_FP32 = 2 };
 
 typedef struct {
   int32_t status;        /* GMRES_CONVERGED / MAXITER / STALLED */
@@ -168,7 +182,8 @@ typedef struct {
 /* Fill *opt with defaults: m = 50, tol = 1e-10, max_iters = 100000, CGSR,
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
- * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4. */
+ * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4,
+ * arnoldi_a = DEFAULT. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).

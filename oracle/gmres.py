@@ -96,8 +96,13 @@ class Matrix:
     def matvec_wide(self, x32, vals32=None):
         """The limited mode's product: float32-stored values and x, widened to
         float64 (each product is then exact) and summed in float64."""
-        v = (self.vals32 if vals32 is None else vals32).astype(np.float64)
-        prod = v * np.asarray(x32, dtype=np.float32).astype(np.float64)[self.col_idx]
+        v = self.vals32 if vals32 is None else vals32
+        return self.matvec_values(v, np.asarray(x32, dtype=np.float32))
+
+    def matvec_values(self, vals, x):
+        """Product with the given values (any precision, widened to float64)
+        and x widened to float64, summed in float64."""
+        prod = np.asarray(vals).astype(np.float64) * np.asarray(x).astype(np.float64)[self.col_idx]
         return np.bincount(self.rows, weights=prod, minlength=self.n)
 
     def diagonal(self):
@@ -382,7 +387,8 @@ def _cast(v, precision):
 def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
           precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
           fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy",
-          restart_repeat=False, restart_on_stall=False, orth_restart=0.0, orth_norm="spectral"):
+          restart_repeat=False, restart_on_stall=False, orth_restart=0.0, orth_norm="spectral",
+          arnoldi_a="default"):
     """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
 
     ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> z applied
@@ -402,6 +408,11 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     ``orth_restart`` > 0 ends a cycle once ||S_k|| (``orth_norm``: the
     10-step power estimate of the 2-norm, or the Frobenius norm) of the basis
     built so far reaches it.
+
+    ``arnoldi_a`` picks the values of A the Arnoldi product reads, for the
+    per-variable study of section 4.1: "default" (float64 in the fp64 mode,
+    the float32 copy otherwise), "fp64" or "fp32" in any mode.  The sums are
+    float64 whenever w or the values are float64.
     """
     if ortho not in ("mgs", "cgsr"):
         raise ValueError(ortho)
@@ -409,6 +420,8 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         raise ValueError(precision)
     if a_storage not in ("copy", "split"):
         raise ValueError(a_storage)
+    if arnoldi_a not in ("default", "fp64", "fp32"):
+        raise ValueError(arnoldi_a)
     # the Arnoldi product's copy of A in the reduced-precision modes: float32
     # rounding of the values, or (split storage) the high-word values
     a32 = A.vals32 if a_storage == "copy" else high_word_value(A.vals).astype(np.float32)
@@ -426,6 +439,8 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     # products and the product's sums stay float64
     limited = precision == "limited"
     two_byte = precision in ("bf16", "fp16")
+    wide_w = precision in ("fp64", "limited")  # w, its dots and the product's sums in float64
+    a64_arnoldi = arnoldi_a == "fp64" or (arnoldi_a == "default" and precision == "fp64")
     total = 0
     restarts = 0
     hist, arn, cyc = [], [], []
@@ -513,10 +528,14 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 src = Z[j]
             else:
                 src = vj
-            if limited:
-                w = A.matvec_wide(src, a32)
+            if a64_arnoldi:  # float64 values: float64 sums, rounded once where w is float32
+                w = A.matvec(np.asarray(src).astype(np.float64))
+                if not wide_w:
+                    w = w.astype(np.float32)
+            elif wide_w:  # float32 values widened, float64 sums
+                w = A.matvec_values(a32, src)
             else:
-                w = A.matvec32(src, a32) if lowp else A.matvec(src)
+                w = A.matvec32(src, a32)
             # orthogonalize(w, V_j)
             hcol = np.zeros(j + 1)
             if ortho == "mgs":

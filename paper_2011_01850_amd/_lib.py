@@ -24,6 +24,8 @@ A_COPY, A_SPLIT = 0, 1
 A_STORAGES = {"copy": A_COPY, "split": A_SPLIT}
 ORTH_SPECTRAL, ORTH_FROBENIUS = 0, 1
 ORTH_NORMS = {"spectral": ORTH_SPECTRAL, "frobenius": ORTH_FROBENIUS}
+ARNOLDI_A_DEFAULT, ARNOLDI_A_FP64, ARNOLDI_A_FP32 = 0, 1, 2
+ARNOLDI_AS = {"default": ARNOLDI_A_DEFAULT, "fp64": ARNOLDI_A_FP64, "fp32": ARNOLDI_A_FP32}
 
 
 class Options(C.Structure):
@@ -46,6 +48,7 @@ class Options(C.Structure):
         ("orth_restart", C.c_double),
         ("orth_norm", C.c_int32),
         ("ilu_sweeps", C.c_int32),
+        ("arnoldi_a", C.c_int32),
     ]
 
 

@@ -157,6 +157,7 @@ bool valid_options(const gmres_options* o) {
   if (o->precision < GMRES_FP64 || o->precision > GMRES_MIXED_LIMITED) return false;
   if (o->precond < GMRES_PRECOND_NONE || o->precond > GMRES_PRECOND_ILU0) return false;
   if (o->ilu_sweeps < 0 || o->ilu_sweeps > 4096) return false;
+  if (o->arnoldi_a < GMRES_ARNOLDI_A_DEFAULT || o->arnoldi_a > GMRES_ARNOLDI_A_FP32) return false;
   if (o->precond != GMRES_PRECOND_NONE && o->precision == GMRES_FP64) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
@@ -177,6 +178,7 @@ bool valid_options(const gmres_options* o) {
 bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64_t nnz_total, int64_t ld) {
   if (o->precision != GMRES_MIXED_FP32 || o->precond != GMRES_PRECOND_NONE || o->ortho != GMRES_MGS) return false;
   if (o->a_storage != GMRES_A_COPY || o->orth_restart > 0.0) return false;
+  if (o->arnoldi_a == GMRES_ARNOLDI_A_FP64) return false;
   if (o->m > kMaxPM) return false;
   for (int k = 0; k < nsys; ++k)
     if (n[k] > (int64_t)1024 * kMaxPR) return false;
@@ -475,6 +477,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.prec = prec;
   a.precond = opt->precond;
   a.ortho = opt->ortho;
+  a.arn64 = opt->arnoldi_a == GMRES_ARNOLDI_A_FP64 || (opt->arnoldi_a == GMRES_ARNOLDI_A_DEFAULT && prec == P64) ? 1 : 0;
   a.xcd_remap = 1;
   int32_t* d_rp = h->alloc<int32_t>(h->ld + 1);
   hip_check(hipMemcpy(d_rp, h->rp_host.data(), (h->ld + 1) * 4, hipMemcpyHostToDevice));
@@ -511,7 +514,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
       hip_check(hipMemcpyAsync(d_a64 + s.nz0, vals[k], s.nnz * 8, hipMemcpyDeviceToDevice, h->stream));
     }
     a.a64 = d_a64;
-    if (prec != P64) {
+    if (!a.arn64) {
       float* d_a32 = h->alloc<float>(h->nnz + 4);
       hip_check(launch_convert_f32(d_a64, d_a32, h->nnz + 4, h->stream));
       a.a32 = d_a32;
@@ -805,6 +808,7 @@ void gmres_default_options(gmres_options* o) {
   o->orth_restart = 0.0;
   o->orth_norm = GMRES_ORTH_SPECTRAL;
   o->ilu_sweeps = 4;
+  o->arnoldi_a = GMRES_ARNOLDI_A_DEFAULT;
 }
 
 const char* gmres_strerror(int code) {
@@ -1174,7 +1178,7 @@ int gmres_time_kernel(gmres_handle hh, int32_t kernel, int32_t j, int32_t reps, 
     if (h->persistent) return GMRES_ESTATE;  // the harness times the device-wide kernels
     const int prec = a.prec;
     const double n = (double)h->nrows, nnz = (double)h->nnz;
-    const double sv = (double)vbytes(prec), sw = (double)wbytes(prec), sa = prec == P64 ? 8.0 : 4.0;
+    const double sv = (double)vbytes(prec), sw = (double)wbytes(prec), sa = a.arn64 ? 8.0 : 4.0;
     double bts = 0.0;
     auto run = [&]() -> hipError_t {
       switch (kernel) {

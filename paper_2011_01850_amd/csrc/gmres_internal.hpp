@@ -104,7 +104,8 @@ struct KArgs {
   const int32_t* rp;
   const int32_t* ci;
   const double* a64;    // float64 values (COPY storage), else null
-  const float* a32;     // float32 copy (COPY storage, mixed modes), else null
+  const float* a32;     // float32 copy (COPY storage, when the Arnoldi product reads float32 values)
+  int32_t arn64;        // 1: the Arnoldi product reads the float64 values (else the float32 ones)
   const uint32_t* ahi;  // SPLIT storage: high and low 32-bit words of the float64 values
   const uint32_t* alo;
   int32_t asplit;       // 1: SPLIT storage

@@ -1625,49 +1625,41 @@ static hipError_t launch_fin_cols(const KArgs& a, const SegTab& sg, int j, hipSt
   return hipGetLastError();
 }
 
+// Arnoldi product with the values the handle chose for it: the float64
+// values (or both words of the split storage) when arn64 is set, else the
+// float32 copy (or the high words); LDS holds one product per non-zero of a
+// row block in the kernel's accumulation type.
+template <typename TX, typename TY, int MODE>
+static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStream_t st) {
+  auto go = [&](auto kern, const auto* vals, size_t acc_bytes) {
+    hipLaunchKernelGGL(kern, dim3(a.nrb), dim3(kBlock), (size_t)a.spmv_budget * acc_bytes, st, a, vals, x, y,
+                       nullptr, j);
+  };
+  if (a.arn64) {
+    if (a.asplit)
+      go(k_spmv<HiLoW, TX, TY, MODE>, reinterpret_cast<const HiLoW*>(a.ahi), sizeof(AccFor<HiLoW, TY>));
+    else
+      go(k_spmv<double, TX, TY, MODE>, a.a64, sizeof(AccFor<double, TY>));
+  } else {
+    if (a.asplit)
+      go(k_spmv<HiW, TX, TY, MODE>, reinterpret_cast<const HiW*>(a.ahi), sizeof(AccFor<HiW, TY>));
+    else
+      go(k_spmv<float, TX, TY, MODE>, a.a32, sizeof(AccFor<float, TY>));
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
-  const size_t sh = (size_t)a.spmv_budget * (wide_w(a.prec) ? 8 : 4);
-  const HiW* hw = reinterpret_cast<const HiW*>(a.ahi);
-  const HiLoW* hlw = reinterpret_cast<const HiLoW*>(a.ahi);
   if (a.precond != 0) {  // w = A z_j
     const float* z = a.Z + (int64_t)j * a.ld;
-    if (wide_w(a.prec)) {
-      if (a.asplit)
-        hipLaunchKernelGGL((k_spmv<HiW, float, double, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, z,
-                           (double*)a.w, nullptr, j);
-      else
-        hipLaunchKernelGGL((k_spmv<float, float, double, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a32, z,
-                           (double*)a.w, nullptr, j);
-      return hipGetLastError();
-    }
-    if (a.asplit)
-      hipLaunchKernelGGL((k_spmv<HiW, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, z,
-                         (float*)a.w, nullptr, j);
-    else
-      hipLaunchKernelGGL((k_spmv<float, float, float, SM_AZ>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a32, z,
-                         (float*)a.w, nullptr, j);
-    return hipGetLastError();
+    if (wide_w(a.prec)) return spmv_values<float, double, SM_AZ>(a, z, (double*)a.w, j, st);
+    return spmv_values<float, float, SM_AZ>(a, z, (float*)a.w, j, st);
   }
   return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
     const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
-    if constexpr (sizeof(TW) == 8 && sizeof(TV) == 8) {
-      if (a.asplit)
-        hipLaunchKernelGGL((k_spmv<HiLoW, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, hlw, x,
-                           (TW*)a.w, nullptr, j);
-      else
-        hipLaunchKernelGGL((k_spmv<double, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a64, x,
-                           (TW*)a.w, nullptr, j);
-    } else {  // float32 copy of A (or its high words); float64 sums when w is float64
-      if (a.asplit)
-        hipLaunchKernelGGL((k_spmv<HiW, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, hw, x,
-                           (TW*)a.w, nullptr, j);
-      else
-        hipLaunchKernelGGL((k_spmv<float, TV, TW, SM_ARNOLDI>), dim3(a.nrb), dim3(kBlock), sh, st, a, a.a32, x,
-                           (TW*)a.w, nullptr, j);
-    }
-    return hipGetLastError();
+    return spmv_values<TV, TW, SM_ARNOLDI>(a, x, (TW*)a.w, j, st);
   });
 }
 

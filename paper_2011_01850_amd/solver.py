@@ -33,7 +33,8 @@ def _dev(t, dtype, torch):
 
 def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
              autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
-             restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4) -> L.Options:
+             restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4,
+             arnoldi_a="default") -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -53,6 +54,7 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.orth_restart = float(orth_restart)
     o.orth_norm = L.ORTH_NORMS[orth_norm] if isinstance(orth_norm, str) else int(orth_norm)
     o.ilu_sweeps = int(ilu_sweeps)
+    o.arnoldi_a = L.ARNOLDI_AS[arnoldi_a] if isinstance(arnoldi_a, str) else int(arnoldi_a)
     return o
 
 
@@ -63,7 +65,7 @@ class Solver:
                  precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
                  a_storage="copy", restart_repeat=False, restart_on_stall=False, orth_restart=0.0,
-                 orth_norm="spectral", ilu_sweeps=4):
+                 orth_norm="spectral", ilu_sweeps=4, arnoldi_a="default"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -75,7 +77,7 @@ class Solver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a)
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         torch.cuda.synchronize()
@@ -210,7 +212,8 @@ class BatchSolver:
     def __init__(self, systems, m=40, tol=1e-10, ortho="mgs", precision="fp32", precond="none",
                  max_iters=100_000, restart_improve=0.0, stall_cycles=10, use_graph=True, autotune=True,
                  schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
-                 restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4):
+                 restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4,
+                 arnoldi_a="default"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -232,7 +235,7 @@ class BatchSolver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a)
         arr64 = C.c_int64 * S
         arrp = C.c_void_p * S
         h = C.c_void_p()

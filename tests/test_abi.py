@@ -42,7 +42,7 @@ def test_default_options(lib):
     assert o.restart_improve == 0.0 and o.stall_cycles == 10 and o.use_graph == 1 and o.autotune == 1
     assert o.batch_schedule == L.SCHEDULE_AUTO and o.spmv_block_nnz == 0 and o.a_storage == L.A_COPY
     assert o.restart_repeat == 0 and o.restart_on_stall == 0 and o.orth_restart == 0.0 and o.orth_norm == 0
-    assert o.ilu_sweeps == 4
+    assert o.ilu_sweeps == 4 and o.arnoldi_a == L.ARNOLDI_A_DEFAULT
 
 
 def test_strerror(lib):
@@ -63,7 +63,8 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                        ("batch_schedule", -1), ("spmv_block_nnz", 32), ("spmv_block_nnz", 100),
                        ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1), ("restart_repeat", 2),
                        ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
-                       ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097)]:
+                       ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097),
+                       ("arnoldi_a", 3), ("arnoldi_a", -1)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -95,13 +96,14 @@ def test_handle_checks(lib):
 
 def test_struct_layouts_match_header():
     # offsets that C gives the two structs on x86-64
-    assert C.sizeof(L.Options) == 96
+    assert C.sizeof(L.Options) == 104
     assert L.Options.tol.offset == 8 and L.Options.max_iters.offset == 16
     assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
     assert L.Options.batch_schedule.offset == 60 and L.Options.spmv_block_nnz.offset == 64
     assert L.Options.a_storage.offset == 68 and L.Options.restart_repeat.offset == 72
     assert L.Options.restart_on_stall.offset == 76 and L.Options.orth_restart.offset == 80
     assert L.Options.orth_norm.offset == 88 and L.Options.ilu_sweeps.offset == 92
+    assert L.Options.arnoldi_a.offset == 96
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 
@@ -126,3 +128,30 @@ def test_spai_layout_matches_oracle():
     from paper_2011_01850_amd import spai as S
     assert S.NPARAMS == N.NPARAMS == L.SPAI_NPARAMS
     assert S.offsets() == N.OFFSETS
+
+
+def test_struct_layouts_match_compiled_header(tmp_path):
+    # the ctypes mirrors against what a C compiler makes of include/gmres.h
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gmres.h"', "int main(void) {"]
+    for cname, ct in (("gmres_options", L.Options), ("gmres_result", L.Result)):
+        lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in ct._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, ct in (("gmres_options", L.Options), ("gmres_result", L.Result)):
+        assert got[(cname, "sizeof")] == C.sizeof(ct), cname
+        for fname, _ in ct._fields_:
+            assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)

@@ -143,7 +143,8 @@ def test_persistent_requires_its_conditions(mods):
     BatchSolver, Solver, GmresError = mods
     A = P.convdiff(20, (1.0, 1.0))
     for kw in (dict(precision="fp64"), dict(ortho="cgsr"), dict(precond="jacobi"), dict(m=65),
-               dict(a_storage="split"), dict(orth_restart=0.5), dict(precision="limited")):
+               dict(a_storage="split"), dict(orth_restart=0.5), dict(precision="limited"),
+               dict(arnoldi_a="fp64")):
         opts = dict(m=20, ortho="mgs", precision="fp32", schedule="persistent")
         opts.update(kw)
         with pytest.raises(GmresError):

@@ -345,17 +345,19 @@ def test_limited_basis_is_float32_rounding_of_float64_w(ortho):
     # limited mode: w'' = A32 v_j - V_j h_j is computed in float64 and only its
     # storage as basis column j+1 is rounded, so that column is the float32
     # rounding of w'' recomputed from the GPU's own basis and H (to within
-    # float64 noise).  In the fully float32 mode w'' carries float32
-    # arithmetic errors of many ulps.
+    # float64 noise); with the float64 values for the product (the basis as
+    # the only float32 variable) the same holds with A's float64 values.  In
+    # the fully float32 mode w'' carries float32 arithmetic errors of many ulps.
     A0 = P.convdiff(24, (20.0, 10.0))
     g = np.random.default_rng(11)
     A = P.CSR(A0.n, A0.row_ptr, A0.col_idx, A0.vals * (1.0 + g.uniform(0.0, 1e-3, A0.nnz)))
-    D32 = O.Matrix.from_csr(A).dense().astype(np.float32).astype(np.float64)
+    D64 = O.Matrix.from_csr(A).dense()
+    D32 = D64.astype(np.float32).astype(np.float64)
     b = g.standard_normal(A.n)
     m = 30
     bad = {}
-    for prec in ("limited", "fp32"):
-        s = _solver(A, m=m, ortho=ortho, precision=prec, tol=0.0, max_iters=m)
+    for prec, arnoldi_a, D in (("limited", "default", D32), ("limited", "fp64", D64), ("fp32", "default", D32)):
+        s = _solver(A, m=m, ortho=ortho, precision=prec, tol=0.0, max_iters=m, arnoldi_a=arnoldi_a)
         s.solve(b)
         k, Hb, V = s.last_cycle()
         s.close()
@@ -364,17 +366,78 @@ def test_limited_basis_is_float32_rounding_of_float64_w(ortho):
         nb, tot = 0, 0
         for j in range(k):
             h = Hb[: j + 1, j]
-            R = D32 @ V[:, j] - V[:, : j + 1] @ h
+            R = D @ V[:, j] - V[:, : j + 1] @ h
             stored = (V[:, j + 1] * Hb[j + 1, j]).astype(np.float32)  # exact: V is stored * (1 / h)
             half_ulp = 0.5 * np.spacing(np.abs(stored)).astype(np.float64)
-            noise = 64 * (j + 2) * O.U64 * (np.abs(D32) @ np.abs(V[:, j]) + np.abs(V[:, : j + 1]) @ np.abs(h))
+            noise = 64 * (j + 2) * O.U64 * (np.abs(D) @ np.abs(V[:, j]) + np.abs(V[:, : j + 1]) @ np.abs(h))
             nb += int(np.count_nonzero(np.abs(R - stored.astype(np.float64)) > half_ulp + noise))
             tot += A.n
-        bad[prec] = nb / tot
-    print(f"{ortho}: entries off the float32 rounding of float64 w'': limited {bad['limited']:.2e}, "
-          f"fp32 {bad['fp32']:.2e}", flush=True)
-    assert bad["limited"] == 0.0
-    assert bad["fp32"] > 0.05
+        bad[(prec, arnoldi_a)] = nb / tot
+    print(f"{ortho}: entries off the float32 rounding of float64 w'': {bad}", flush=True)
+    assert bad[("limited", "default")] == 0.0
+    assert bad[("limited", "fp64")] == 0.0
+    assert bad[("fp32", "default")] > 0.05
+
+
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_float32_a_alone_in_float64_solver(ortho):
+    # A for the next Krylov vector as the only float32 variable (float64
+    # basis, w and H): the GPU's Arnoldi relation holds to float64 rounding
+    # with the float32 values of A and only to about u32 with its float64
+    # values; the float64 handle without the float32 copy refuses the float32
+    # product
+    A0 = P.convdiff(24, (20.0, 10.0))
+    g = np.random.default_rng(12)
+    A = P.CSR(A0.n, A0.row_ptr, A0.col_idx, A0.vals * (1.0 + g.uniform(0.0, 1e-3, A0.nnz)))
+    D64 = O.Matrix.from_csr(A).dense()
+    D32 = D64.astype(np.float32).astype(np.float64)
+    b = g.standard_normal(A.n)
+    m = 30
+    s = _solver(A, m=m, ortho=ortho, precision="fp64", tol=0.0, max_iters=m, arnoldi_a="fp32")
+    s.solve(b)
+    k, Hb, V = s.last_cycle()
+    x32 = g.standard_normal(A.n).astype(np.float32)
+    y = s.spmv(x32, "fp32").cpu().numpy()  # the float32 copy exists on this handle
+    assert np.allclose(y, (D32 @ x32.astype(np.float64)).astype(np.float32), rtol=1e-5, atol=1e-5 * np.abs(y).max())
+    s.close()
+    V = V.cpu().numpy()
+    assert k == m
+    r32 = np.linalg.norm(D32 @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k])
+    r64 = np.linalg.norm(D64 @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k])
+    assert r32 <= 10 * k * O.U64 * np.linalg.norm(D32)
+    assert r64 >= 1e-3 * O.U32 * np.linalg.norm(D64)
+    # the float64 solver's default: the float64 values
+    s = _solver(A, m=m, ortho=ortho, precision="fp64", tol=0.0, max_iters=m)
+    s.solve(b)
+    k, Hb, V = s.last_cycle()
+    s.close()
+    V = V.cpu().numpy()
+    assert np.linalg.norm(D64 @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k]) <= 10 * k * O.U64 * np.linalg.norm(D64)
+    assert np.linalg.norm(D32 @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k]) >= 1e-3 * O.U32 * np.linalg.norm(D32)
+    s64 = _solver(A, m=4, precision="fp32", arnoldi_a="fp64")
+    with pytest.raises(L.GmresError):
+        s64.spmv(x32, "fp32")
+    s64.close()
+
+
+@pytest.mark.parametrize("precision,arnoldi_a", [("limited", "fp64"), ("fp64", "fp32"), ("fp32", "fp64")])
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_per_variable_solves_match_oracle(precision, arnoldi_a, ortho):
+    # the single-variable runs of section 4.1 (and float64 values under a float32 w):
+    # every one reaches 1e-13 and the oracle's solution, the restart residuals
+    # reaching 1e-10 within a cycle of the oracle's emulation of the same split
+    name = "3d17_ragged"
+    pr, m = _case(name)
+    ref = _oracle_x(name, ortho)
+    x, info = _parity_case(pr.A, pr.b, m, ortho, precision, arnoldi_a=arnoldi_a)
+    emu = O.gmres(O.Matrix.from_csr(pr.A), pr.b, m=m, tol=1e-13, ortho=ortho, precision=precision,
+                  arnoldi_a=arnoldi_a, max_iters=20000)
+    rr = _relres(pr.A, pr.b, x)
+    print(f"{precision}/{arnoldi_a} {ortho}: gpu {info['status']} iters {info['iters']} relres {rr:.2e} | "
+          f"oracle {emu.status_name} iters {emu.iters}", flush=True)
+    assert info["status"] == "CONVERGED" and rr <= 1e-13 * 1.01
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    assert abs(_cycles_to(info["history"], 1e-10) - _cycles_to(emu.history, 1e-10)) <= 1
 
 
 @pytest.mark.parametrize("precond", ["jacobi", "ilu0"])
@@ -396,6 +459,45 @@ def test_limited_mode_with_preconditioners(precond):
     assert info["status"] == "CONVERGED" and not info["fallback_used"]
     assert _relres(A0, b, x.cpu().numpy()) <= 1.01e-11
     assert abs(info["iters"] - ref.iters) <= max(10, 0.1 * ref.iters)
+
+
+@pytest.mark.parametrize("precision,u", [("fp64", O.U64), ("fp32", O.U32), ("limited", O.U32)])
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_long_cycle_column_windows(precision, u, ortho):
+    # a cycle longer than the 64-column register tile: from j + 1 = 65 on,
+    # CGSR runs its projections over 64-column windows and its last pass as a
+    # column loop; the relation and CGS2's orthogonality hold there as well
+    A = P.convdiff(32, (20.0, 10.0))
+    M = O.Matrix.from_csr(A)
+    D = M.dense()
+    b = np.random.default_rng(8).standard_normal(A.n)
+    m = 150
+    s = _solver(A, m=m, ortho=ortho, precision=precision, tol=0.0, max_iters=m)
+    s.solve(b)
+    k, Hb, V = s.last_cycle()
+    s.close()
+    V = V.cpu().numpy()
+    assert k == m
+    R = D @ V[:, :k] - V[:, : k + 1] @ Hb[: k + 1, :k]
+    assert np.linalg.norm(R) <= 10 * k * u * np.linalg.norm(D) * (50 if precision != "fp64" else 1)
+    if ortho == "cgsr":
+        orth = np.linalg.norm(np.eye(k + 1) - V.T @ V, 2)
+        assert orth <= 10 * (k + 1) * u * (10 if precision != "fp64" else 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "limited"])
+def test_long_cycle_solves_match_oracle(precision):
+    name = "3d17_ragged"
+    pr, _ = _case(name)
+    m = 120
+    ref = O.gmres(O.Matrix.from_csr(pr.A), pr.b, m=m, tol=1e-13, ortho="cgsr")
+    x, info = _parity_case(pr.A, pr.b, m, "cgsr", precision)
+    rr = _relres(pr.A, pr.b, x)
+    print(f"m={m} {precision}: gpu {info['status']} iters {info['iters']} restarts {info['restarts']} "
+          f"relres {rr:.2e} | oracle fp64 iters {ref.iters}", flush=True)
+    assert info["status"] == "CONVERGED" and rr <= 1e-13 * 1.01
+    assert info["iters"] > 64  # the windowed kernels ran
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
 
 
 def test_edge_cases():

@@ -319,37 +319,54 @@ def test_two_byte_basis_still_reaches_double_accuracy(fmt):
     assert r.status == O.CONVERGED
 
 
+# (precision, arnoldi_a) -> (basis stored in float32, values of A the Arnoldi product reads)
+_VARIABLE_CASES = {
+    ("limited", "default"): (True, 32),  # the limited solver: A, M and V in float32
+    ("limited", "fp64"): (True, 64),  # the basis alone in float32
+    ("fp64", "fp32"): (False, 32),  # A for the next Krylov vector alone in float32
+    ("fp64", "default"): (False, 64),  # nothing in float32
+}
+
+
 @pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
-def test_limited_mode_stores_float32_and_computes_w_in_float64(ortho):
-    # the limited solver of section 4.1 stores A's Arnoldi copy and the basis
-    # in float32 and nothing else: every stored basis vector is
-    # float32-representable, and w'' = A v_j - V_j h_j holds to float64
-    # rounding with the float32 values of A (only to about u32 with its
-    # float64 values, and only to about u32 in the fully float32 mode)
+def test_per_variable_precision_storage_split(ortho):
+    # the limited solver and the single-variable runs of section 4.1 store
+    # only their chosen variables in float32 and keep w in float64: a stored
+    # basis vector is float32-representable exactly when the basis is a
+    # float32 variable, and w'' = A v_j - V_j h_j holds to float64 rounding
+    # with the values of A the product is meant to read, but only to about u32
+    # with the other ones; in the fully float32 mode (w in float32) it holds
+    # only to about u32 with either
     A0 = P.convdiff(12, (20.0, 10.0))
     g = np.random.default_rng(9)
     A = O.Matrix(A0.row_ptr, A0.col_idx, A0.vals * (1.0 + g.uniform(0.0, 1e-3, A0.nnz)), A0.n)
-    D64 = A.dense()
-    D32 = D64.astype(np.float32).astype(np.float64)
+    D = {64: A.dense()}
+    D[32] = D[64].astype(np.float32).astype(np.float64)
     b = np.random.default_rng(3).standard_normal(A.n)
     m = 30
-    rel = {}
-    for prec in ("limited", "fp32", "fp64"):
-        c = O.gmres(A, b, m=m, tol=0.0, max_iters=m, ortho=ortho, precision=prec, record=True).cycles[0]
+
+    def relation(prec, arnoldi_a):
+        c = O.gmres(A, b, m=m, tol=0.0, max_iters=m, ortho=ortho, precision=prec, record=True,
+                    arnoldi_a=arnoldi_a).cycles[0]
         k, V, Hb, W = c["k"], np.stack(c["V"], 1), c["Hbar"], c["W"]
         assert k == m
-        stored32 = np.array_equal(V, V.astype(np.float32).astype(np.float64))
-        assert stored32 == (prec != "fp64")
-        r32, r64 = [], []
-        for j in range(k):
-            scale = np.linalg.norm(D32, 2) * np.linalg.norm(V[:, j]) + np.abs(Hb[: j + 1, j]).sum()
-            r32.append(np.linalg.norm(D32 @ V[:, j] - V[:, : j + 1] @ Hb[: j + 1, j] - W[j]) / scale)
-            r64.append(np.linalg.norm(D64 @ V[:, j] - V[:, : j + 1] @ Hb[: j + 1, j] - W[j]) / scale)
-        rel[prec] = (max(r32), min(r64), max(r64))
-    assert rel["limited"][0] <= 10 * m * O.U64  # float64 w over the float32 values of A
-    assert rel["limited"][1] >= 1e-3 * O.U32  # ... and not over its float64 values
-    assert rel["fp64"][2] <= 10 * m * O.U64
-    assert rel["fp32"][0] >= 1e-2 * O.U32  # float32 w: relation to about u32 only
+        rel = {}
+        for bits in (32, 64):
+            r = []
+            for j in range(k):
+                scale = np.linalg.norm(D[32], 2) * np.linalg.norm(V[:, j]) + np.abs(Hb[: j + 1, j]).sum()
+                r.append(np.linalg.norm(D[bits] @ V[:, j] - V[:, : j + 1] @ Hb[: j + 1, j] - W[j]) / scale)
+            rel[bits] = (max(r), min(r))
+        return np.array_equal(V, V.astype(np.float32).astype(np.float64)), rel
+
+    for (prec, arnoldi_a), (basis32, bits) in _VARIABLE_CASES.items():
+        stored32, rel = relation(prec, arnoldi_a)
+        assert stored32 == basis32, (prec, arnoldi_a)
+        assert rel[bits][0] <= 10 * m * O.U64, (prec, arnoldi_a)  # float64 w over these values
+        assert rel[96 - bits][1] >= 1e-3 * O.U32, (prec, arnoldi_a)  # ... and not over the others
+    for arnoldi_a in ("default", "fp64"):
+        stored32, rel = relation("fp32", arnoldi_a)
+        assert stored32 and rel[32][0] >= 1e-2 * O.U32 and rel[64][0] >= 1e-2 * O.U32
 
 
 @pytest.mark.parametrize("ortho", ["mgs", "cgsr"])

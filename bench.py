@@ -36,7 +36,7 @@ PEAK_HBM_GBS = 8000.0
 # of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by what it reads
 # for a plain 1 GiB device copy: x2.0 and x1.0), averaged over the roofline
 # launches.  Valid only for the kernel source they were taken from.
-TRAFFIC = {"bytes_per_launch": 347247610, "kernel_source_sha256": "f8fcd321af7fac59cbd155c2a3c5b329c45cdb625052fd6b0ed7d67eb6ae1c16"}
+TRAFFIC = {"bytes_per_launch": 346543305, "kernel_source_sha256": "9f604e3b53c3b7acc9c068a9543cba3f9690106ff4882a681d85516800440d31"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 

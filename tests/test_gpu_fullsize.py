@@ -57,3 +57,58 @@ def test_fullsize_mixed_solve_reaches_1e10(c2, ortho):
     assert info["rel_residual"] == pytest.approx(rr, rel=1e-6)
     # restart residuals never increase (the convergence argument of the numerics section)
     assert np.all(np.diff(hist) <= 0)
+
+
+def test_fullsize_first_cycle_basis(c2):
+    # one full cycle of the benchmark solver at 128^3: CGS2 keeps the float32
+    # basis orthogonal to working accuracy, and A V_k = V_{k+1} Hbar_k holds
+    # (A applied by the float64 product, checked above row by row)
+    A = c2.A
+    m = 50
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=m, ortho="cgsr", precision="fp32", tol=0.0, max_iters=m)
+    s.solve(c2.b)
+    k, Hb, V = s.last_cycle()
+    assert k == m
+    G = V.T @ V
+    orth = torch.linalg.matrix_norm(torch.eye(k + 1, dtype=torch.float64, device="cuda") - G, ord=2).item()
+    AV = torch.stack([s.spmv(V[:, j], "fp64") for j in range(k)], dim=1)
+    R = AV - V @ torch.as_tensor(Hb[: k + 1, :k], device="cuda")
+    rel = (torch.linalg.norm(R) / np.linalg.norm(A.vals)).item()
+    s.close()
+    print(f"128^3 first cycle: ||I - V^T V||_2 = {orth:.2e}, ||A V - V Hbar||_F / ||A||_F = {rel:.2e}", flush=True)
+    assert orth <= 10 * (k + 1) * O.U32 * 10
+    assert rel <= 10 * k * O.U32 * 50
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return P.c3_powerlaw()
+
+
+def test_fullsize_powerlaw_rows_sampled(c3):
+    # the power-law workload at its full size: rows up to 2000 entries go
+    # through the chunked long-row path; sampled rows against dot products
+    A = c3.A
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=30, ortho="cgsr", precision="fp16")
+    g = np.random.default_rng(9)
+    x = g.standard_normal(A.n)
+    y64 = s.spmv(x, "fp64").cpu().numpy()
+    s.close()
+    lens = np.diff(A.row_ptr)
+    rows = np.concatenate([g.integers(0, A.n, 1000), np.argsort(lens)[-20:]])
+    assert lens[rows].max() >= 1000
+    for r in rows:
+        lo, hi = A.row_ptr[r], A.row_ptr[r + 1]
+        ref = float(np.dot(A.vals[lo:hi], x[A.col_idx[lo:hi]]))
+        scale = float(np.abs(A.vals[lo:hi]).dot(np.abs(x[A.col_idx[lo:hi]])))
+        assert abs(y64[r] - ref) <= 16 * O.U64 * scale
+
+
+def test_fullsize_powerlaw_half_basis_reaches_1e10(c3):
+    A = c3.A
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=30, ortho="cgsr", precision="fp16", tol=1e-10, stall_cycles=1000)
+    x, info = s.solve(c3.b)
+    s.close()
+    rr = O.relative_residual(O.Matrix.from_csr(A), c3.b, x.cpu().numpy())
+    print(f"power-law 1e6 fp16: {info['status']} iters {info['iters']} relres {rr:.3e}", flush=True)
+    assert info["status"] == "CONVERGED" and rr <= 1e-10 * 1.001

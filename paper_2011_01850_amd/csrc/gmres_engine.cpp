@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <memory>
 #include <new>
 #include <thread>
@@ -50,7 +51,7 @@ struct RowBlocks {
   std::vector<int32_t> sys;    // system of each block
   std::vector<int32_t> lanes;  // max row_lanes over the block's rows
   std::vector<int32_t> rb0, nrb;  // per system: first block, block count
-  int32_t *d_rb = nullptr, *d_sys = nullptr, *d_lanes = nullptr, *d_rb0 = nullptr, *d_nrb = nullptr;
+  const int32_t *d_rb = nullptr, *d_sys = nullptr, *d_lanes = nullptr, *d_rb0 = nullptr, *d_nrb = nullptr;
 };
 
 }  // namespace
@@ -208,10 +209,53 @@ void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r
   }
 }
 
+// Runs f(i) for i in [0, count) on up to `workers` host threads (plain loop
+// for small counts); an exception in any call fails the whole run.
+template <typename F>
+void parallel_for(int64_t count, int workers, F&& f) {
+  if (count <= 1 || workers <= 1) {
+    for (int64_t i = 0; i < count; ++i) f(i);
+    return;
+  }
+  const int nt = (int)std::min<int64_t>(workers, count);
+  std::vector<std::thread> th;
+  std::vector<char> failed(nt, 0);
+  for (int w = 0; w < nt; ++w)
+    th.emplace_back([&, w] {
+      try {
+        for (int64_t i = w; i < count; i += nt) f(i);
+      } catch (...) {
+        failed[w] = 1;
+      }
+    });
+  for (auto& t : th) t.join();
+  for (char c : failed)
+    if (c) throw Fail{GMRES_EINVAL};
+}
+
 int32_t* upload32(gmres_ctx* h, const std::vector<int32_t>& v) {
   int32_t* d = h->alloc<int32_t>(std::max<size_t>(v.size(), 1));
   if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * 4, hipMemcpyHostToDevice));
   return d;
+}
+
+// Several small tables in one allocation and one copy; out[i] points at
+// table i (each starts on a 64-entry boundary).
+void upload_pack(gmres_ctx* h, std::initializer_list<const std::vector<int32_t>*> tables,
+                 std::initializer_list<const int32_t**> out) {
+  std::vector<size_t> off;
+  size_t total = 0;
+  for (const auto* v : tables) {
+    off.push_back(total);
+    total += (std::max<size_t>(v->size(), 1) + 63) / 64 * 64;
+  }
+  std::vector<int32_t> host(total, 0);
+  size_t i = 0;
+  for (const auto* v : tables) std::copy(v->begin(), v->end(), host.begin() + (ptrdiff_t)off[i++]);
+  int32_t* d = h->alloc<int32_t>(total);
+  hip_check(hipMemcpy(d, host.data(), total * 4, hipMemcpyHostToDevice));
+  i = 0;
+  for (const int32_t** o : out) *o = d + off[i++];
 }
 
 // Host part only (reads h->rp_host and h->sys): safe to run for several
@@ -221,7 +265,23 @@ void fill_row_blocks(const gmres_ctx* h, RowBlocks& t) {
   for (size_t k = 0; k < h->sys.size(); ++k) {
     const System& s = h->sys[k];
     const size_t before = t.rb.size();
-    build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, t.budget, t.rb, &t.lanes);
+    constexpr int64_t kChunk = 1 << 19;
+    if (s.n <= kChunk) {
+      build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, t.budget, t.rb, &t.lanes);
+    } else {
+      // a large system in row chunks built in parallel (a block never spans
+      // two chunks; any blocking gives the same sums)
+      const int64_t nc = (s.n + kChunk - 1) / kChunk;
+      std::vector<std::vector<int32_t>> rbs(nc), lns(nc);
+      parallel_for(nc, 4, [&](int64_t c) {
+        build_row_blocks(h->rp_host, s.row0 + c * kChunk, s.row0 + std::min<int64_t>(s.n, (c + 1) * kChunk),
+                         t.budget, rbs[c], &lns[c]);
+      });
+      for (int64_t c = 0; c < nc; ++c) {
+        t.rb.insert(t.rb.end(), rbs[c].begin(), rbs[c].end());
+        t.lanes.insert(t.lanes.end(), lns[c].begin(), lns[c].end());
+      }
+    }
     t.rb0.push_back((int32_t)before);
     t.nrb.push_back((int32_t)(t.rb.size() - before));
     t.sys.insert(t.sys.end(), t.rb.size() - before, (int32_t)k);
@@ -277,13 +337,9 @@ void set_row_blocks(gmres_ctx* h, int budget) {
   RowBlocks* t = nullptr;
   for (const auto& p : h->rbt)
     if (p->budget == budget) t = p.get();
-  if (!t->d_rb) {
-    t->d_rb = upload32(h, t->rb);
-    t->d_sys = upload32(h, t->sys);
-    t->d_lanes = upload32(h, t->lanes);
-    t->d_rb0 = upload32(h, t->rb0);
-    t->d_nrb = upload32(h, t->nrb);
-  }
+  if (!t->d_rb)
+    upload_pack(h, {&t->rb, &t->sys, &t->lanes, &t->rb0, &t->nrb},
+                {&t->d_rb, &t->d_sys, &t->d_lanes, &t->d_rb0, &t->d_nrb});
   h->nrb = (int32_t)t->sys.size();
   h->a.rb = t->d_rb;
   h->a.rb_sys = t->d_sys;
@@ -320,12 +376,8 @@ SegTab make_split(gmres_ctx* h, int G) {
   SegTab sg{};
   sg.G = G;
   sg.nseg = (int32_t)seg_t0.size();
-  sg.bseg0 = upload32(h, bseg0);
-  sg.seg_t0 = upload32(h, seg_t0);
-  sg.seg_nt = upload32(h, seg_nt);
-  sg.seg_sys = upload32(h, seg_sys);
-  sg.sys_sg0 = upload32(h, sys_sg0);
-  sg.sys_nsg = upload32(h, sys_nsg);
+  upload_pack(h, {&bseg0, &seg_t0, &seg_nt, &seg_sys, &sys_sg0, &sys_nsg},
+              {&sg.bseg0, &sg.seg_t0, &sg.seg_nt, &sg.seg_sys, &sg.sys_sg0, &sg.sys_nsg});
   return sg;
 }
 
@@ -383,7 +435,7 @@ void autotune_spmv(gmres_ctx* h) {
   int best_budget = h->a.spmv_budget, best_remap = h->a.xcd_remap;
   // exercise with a column of the zero-initialised basis; force the kernel on
   hip_check(launch_set_force(h->a, 1, h->stream));
-  const int reps = 5;
+  const int reps = 3;
   for (int budget : kTuneBudgets) {
     set_row_blocks(h, budget);
     for (int remap = 0; remap <= 1; ++remap) {
@@ -447,20 +499,47 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
                            (opt->batch_schedule == GMRES_SCHEDULE_AUTO && nsys >= 2));
   }
 
-  // ---- global CSR (rows of padding are empty; columns shifted per system)
-  h->rp_host.assign(h->ld + 1, 0);
-  std::vector<int32_t> tmp;
+  // ---- global CSR (rows of padding are empty; columns shifted per system).
+  // Each system's row pointer is copied straight into place, checked (in
+  // parallel chunks, read-only), then shifted by its first non-zero and
+  // padded (disjoint ranges).
+  h->rp_host.resize(h->ld + 1);
   for (int k = 0; k < nsys; ++k) {
     const System& s = h->sys[k];
-    tmp.resize(s.n + 1);
-    hip_check(hipMemcpy(tmp.data(), rp[k], (s.n + 1) * 4, hipMemcpyDeviceToHost));
-    if (tmp[0] != 0 || tmp[s.n] != s.nnz) throw Fail{GMRES_EINVAL};
-    for (int64_t i = 0; i < s.n; ++i) {
-      if (tmp[i + 1] < tmp[i]) throw Fail{GMRES_EINVAL};
-      h->rp_host[s.row0 + i] = (int32_t)(s.nz0 + tmp[i]);
-    }
-    const int64_t end = s.row0 + (int64_t)s.nt * kTile;
-    for (int64_t i = s.row0 + s.n; i <= end; ++i) h->rp_host[i] = (int32_t)(s.nz0 + s.nnz);
+    int32_t* dst = h->rp_host.data() + s.row0;
+    hip_check(hipMemcpy(dst, rp[k], (s.n + 1) * 4, hipMemcpyDeviceToHost));
+    if (dst[0] != 0 || dst[s.n] != s.nnz) throw Fail{GMRES_EINVAL};
+  }
+  {
+    constexpr int64_t kChunk = 1 << 18;
+    struct Piece {
+      int k;
+      int64_t i0, i1;
+    };
+    std::vector<Piece> pieces;
+    for (int k = 0; k < nsys; ++k)
+      for (int64_t i0 = 0; i0 < h->sys[k].n; i0 += kChunk)
+        pieces.push_back({k, i0, std::min<int64_t>(h->sys[k].n, i0 + kChunk)});
+    const int workers = h->ld >= 4 * kChunk ? 8 : 1;
+    parallel_for((int64_t)pieces.size(), workers, [&](int64_t p) {
+      const System& s = h->sys[pieces[p].k];
+      const int32_t* v = h->rp_host.data() + s.row0;
+      // the entry after the last row may already hold the next system's first
+      // entry (n a multiple of the tile): its own value, nnz, was checked above
+      for (int64_t i = pieces[p].i0; i < pieces[p].i1; ++i)
+        if ((i + 1 < s.n ? v[i + 1] : (int32_t)s.nnz) < v[i]) throw Fail{GMRES_EINVAL};
+    });
+    parallel_for((int64_t)pieces.size(), workers, [&](int64_t p) {
+      const System& s = h->sys[pieces[p].k];
+      int32_t* v = h->rp_host.data() + s.row0;
+      const int32_t z0 = (int32_t)s.nz0;
+      if (z0 != 0)
+        for (int64_t i = pieces[p].i0; i < pieces[p].i1; ++i) v[i] += z0;
+      if (pieces[p].i1 == s.n) {  // the system's last piece: its end and its padding rows
+        const int64_t end = pieces[p].k + 1 < nsys ? h->sys[pieces[p].k + 1].row0 : h->ld + 1;
+        for (int64_t i = s.row0 + s.n; i < end; ++i) h->rp_host[i] = (int32_t)(s.nz0 + s.nnz);
+      }
+    });
   }
   KArgs& a = h->a;
   a.S = nsys;

@@ -152,3 +152,36 @@ def test_persistent_requires_its_conditions(mods):
     big = P.convdiff(257, (1.0, 1.0))  # n = 66,049 > 65,536
     with pytest.raises(GmresError):
         Solver(big.row_ptr, big.col_idx, big.vals, m=20, ortho="mgs", precision="fp32", schedule="persistent")
+
+
+def test_row_pointer_checks_and_large_batch_offsets(mods):
+    # the host checks of the row pointer run in parallel chunks on inputs of
+    # a million rows and more: every kind of broken row pointer is refused,
+    # and the shifted, padded global row pointer of a batch of large systems
+    # gives each system its single-system result (up to the float32 rounding
+    # order of the device-wide passes, whose partial sums are cut per batch)
+    BatchSolver, Solver, GmresError = mods
+    A = P.convdiff(102, (5.0, 2.0, 1.0))  # n = 1,061,208
+    n = A.n
+    for i, bad in [(0, 1), (n, A.nnz - 1), (500_000, int(A.row_ptr[500_001]) + 1)]:
+        rp = A.row_ptr.copy()
+        rp[i] = bad
+        with pytest.raises(GmresError):
+            Solver(rp, A.col_idx, A.vals, m=10, precision="fp32")
+    ci = A.col_idx.copy()
+    ci[777_777] = n  # a column past the matrix
+    with pytest.raises(GmresError):
+        Solver(A.row_ptr, ci, A.vals, m=10, precision="fp32")
+    systems = [P.convdiff(760, (1.0 + k, 0.5)) for k in range(3)]  # 577,600 rows each
+    bs = [P.manufactured_rhs(S, 5, k)[1] for k, S in enumerate(systems)]
+    kw = dict(m=20, ortho="cgsr", precision="fp32", tol=1e-12, max_iters=40, autotune=False)
+    batch = BatchSolver([(S.row_ptr, S.col_idx, S.vals) for S in systems], schedule="device_wide", **kw)
+    xs, infos = batch.solve(bs)
+    batch.close()
+    for k, S in enumerate(systems):
+        s = Solver(S.row_ptr, S.col_idx, S.vals, **kw)
+        x, info = s.solve(bs[k])
+        s.close()
+        assert info["iters"] == infos[k]["iters"] == 40
+        assert infos[k]["rel_residual"] == pytest.approx(info["rel_residual"], rel=1e-3)
+        assert (torch.linalg.norm(x - xs[k]) / torch.linalg.norm(x)).item() <= 1e-4, k

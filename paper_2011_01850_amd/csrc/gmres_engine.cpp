@@ -209,6 +209,23 @@ void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r
   }
 }
 
+// Pinned host memory for one download, freed when it goes out of scope.
+struct PinnedBuffer {
+  void* p = nullptr;
+  explicit PinnedBuffer(size_t bytes) {
+    if (hipHostMalloc(&p, std::max<size_t>(bytes, 4), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Fail{GMRES_ENOMEM};
+    }
+  }
+  ~PinnedBuffer() {
+    if (p) (void)hipHostFree(p);
+  }
+  PinnedBuffer(const PinnedBuffer&) = delete;
+  PinnedBuffer& operator=(const PinnedBuffer&) = delete;
+};
+
 // Runs f(i) for i in [0, count) on up to `workers` host threads (plain loop
 // for small counts); an exception in any call fails the whole run.
 template <typename F>
@@ -500,13 +517,15 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   }
 
   // ---- global CSR (rows of padding are empty; columns shifted per system).
-  // Each system's row pointer is copied straight into place, checked (in
-  // parallel chunks, read-only), then shifted by its first non-zero and
-  // padded (disjoint ranges).
+  // Each system's row pointer is downloaded into place in a pinned staging
+  // buffer, checked (in parallel chunks, read-only), then shifted by its
+  // first non-zero and padded (disjoint ranges) into the host copy.
+  PinnedBuffer stage((size_t)(h->ld + 1) * 4);
+  int32_t* const st = static_cast<int32_t*>(stage.p);
   h->rp_host.resize(h->ld + 1);
   for (int k = 0; k < nsys; ++k) {
     const System& s = h->sys[k];
-    int32_t* dst = h->rp_host.data() + s.row0;
+    int32_t* dst = st + s.row0;
     hip_check(hipMemcpy(dst, rp[k], (s.n + 1) * 4, hipMemcpyDeviceToHost));
     if (dst[0] != 0 || dst[s.n] != s.nnz) throw Fail{GMRES_EINVAL};
   }
@@ -523,7 +542,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     const int workers = h->ld >= 4 * kChunk ? 8 : 1;
     parallel_for((int64_t)pieces.size(), workers, [&](int64_t p) {
       const System& s = h->sys[pieces[p].k];
-      const int32_t* v = h->rp_host.data() + s.row0;
+      const int32_t* v = st + s.row0;
       // the entry after the last row may already hold the next system's first
       // entry (n a multiple of the tile): its own value, nnz, was checked above
       for (int64_t i = pieces[p].i0; i < pieces[p].i1; ++i)
@@ -531,10 +550,10 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     });
     parallel_for((int64_t)pieces.size(), workers, [&](int64_t p) {
       const System& s = h->sys[pieces[p].k];
-      int32_t* v = h->rp_host.data() + s.row0;
+      const int32_t* v = st + s.row0;
+      int32_t* g = h->rp_host.data() + s.row0;
       const int32_t z0 = (int32_t)s.nz0;
-      if (z0 != 0)
-        for (int64_t i = pieces[p].i0; i < pieces[p].i1; ++i) v[i] += z0;
+      for (int64_t i = pieces[p].i0; i < pieces[p].i1; ++i) g[i] = v[i] + z0;
       if (pieces[p].i1 == s.n) {  // the system's last piece: its end and its padding rows
         const int64_t end = pieces[p].k + 1 < nsys ? h->sys[pieces[p].k + 1].row0 : h->ld + 1;
         for (int64_t i = s.row0 + s.n; i < end; ++i) h->rp_host[i] = (int32_t)(s.nz0 + s.nnz);

@@ -500,6 +500,55 @@ def test_long_cycle_solves_match_oracle(precision):
     assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_initial_guess(precision):
+    # Algorithm 1 starts from x0: an exact x0 returns at once, unchanged;
+    # a nearby x0 converges from there like the oracle started at the same x0
+    A = P.convdiff(40, (20.0, 10.0))  # integer values (h = 1/41)
+    M = O.Matrix.from_csr(A)
+    assert np.array_equal(A.vals, np.round(A.vals))
+    g = np.random.default_rng(21)
+    xt = g.integers(-4, 5, A.n).astype(np.float64)
+    b = M.matvec(xt)  # integer sums: exact
+    s = _solver(A, m=20, ortho="cgsr", precision=precision, tol=1e-12)
+    x, info = s.solve(b, x0=xt)
+    assert info["iters"] == 0 and info["status"] == "CONVERGED" and info["rel_residual"] == 0.0
+    assert np.array_equal(x.cpu().numpy(), xt)
+    x0 = xt + 1e-3 * g.standard_normal(A.n)
+    x, info = s.solve(b, x0=x0)
+    xz, info_z = s.solve(b)
+    s.close()
+    ref = O.gmres(M, b, x0=x0, m=20, tol=1e-12, ortho="cgsr")
+    assert info["status"] == "CONVERGED" and _relres(A, b, x.cpu().numpy()) <= 1.01e-12
+    assert info["iters"] < info_z["iters"]
+    assert abs(info["iters"] - ref.iters) <= 20
+    assert np.linalg.norm(x.cpu().numpy() - xt) <= 1e-8 * np.linalg.norm(xt)
+
+
+def test_kernel_timing_harness():
+    # the roofline harness: positive durations, the documented algorithmic
+    # bytes per launch, and its argument checks
+    A = P.convdiff(64, (20.0, 10.0))
+    n, nnz = A.n, A.nnz
+    m = 30
+    s = _solver(A, m=m, ortho="cgsr", precision="fp32")
+    s.solve(P.manufactured_rhs(A, 3, 0)[1])
+    expect = {0: nnz * 8 + 4 * (n + 1) + 8 * n,  # SpMV: float32 values and indices, x and w
+              1: (m - 1 + 1) * n * 4 + n * 4,  # projection 1 at j = m - 1
+              2: (m - 1 + 1) * n * 4 + 2 * n * 4,  # projection 2
+              3: (m - 1 + 1) * n * 4 + 2 * n * 4,  # last pass: basis, w, v_{j+1}
+              5: nnz * 12 + 4 * (n + 1) + 16 * n + 4 * n}  # float64 residual
+    for k, by_expect in expect.items():
+        ms, by = s.time_kernel(k, m - 1, reps=3)
+        assert ms > 0.0 and by == pytest.approx(by_expect, rel=1e-12), k
+    for bad in [(2, m), (2, -1), (99, 0)]:
+        with pytest.raises(L.GmresError):
+            s.time_kernel(bad[0], bad[1], reps=3)
+    with pytest.raises(L.GmresError):
+        s.time_kernel(2, 0, reps=0)
+    s.close()
+
+
 def test_edge_cases():
     A = P.convdiff(20, (5.0, 1.0))
     n = A.n

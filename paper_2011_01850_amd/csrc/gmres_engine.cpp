@@ -209,18 +209,24 @@ void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r
   }
 }
 
-// Pinned host memory for one download, freed when it goes out of scope.
+// Host staging for one download, freed when it goes out of scope: pinned
+// memory (a faster copy), or ordinary memory when pinning that much fails.
 struct PinnedBuffer {
   void* p = nullptr;
+  bool pinned = false;
+  std::vector<uint8_t> fallback;
   explicit PinnedBuffer(size_t bytes) {
-    if (hipHostMalloc(&p, std::max<size_t>(bytes, 4), hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw Fail{GMRES_ENOMEM};
+    bytes = std::max<size_t>(bytes, 4);
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) == hipSuccess) {
+      pinned = true;
+      return;
     }
+    (void)hipGetLastError();
+    fallback.resize(bytes);  // std::bad_alloc here is reported as out of memory by the caller
+    p = fallback.data();
   }
   ~PinnedBuffer() {
-    if (p) (void)hipHostFree(p);
+    if (pinned) (void)hipHostFree(p);
   }
   PinnedBuffer(const PinnedBuffer&) = delete;
   PinnedBuffer& operator=(const PinnedBuffer&) = delete;
@@ -941,6 +947,10 @@ int gmres_batch_create(gmres_handle* out, int32_t nsys, const int64_t* n, const 
     return f.code;
   } catch (const std::bad_alloc&) {
     delete h;
+    return GMRES_ENOMEM;
+  } catch (...) {  // e.g. host threads that could not be started: a resource failure
+    delete h;
+    (void)hipGetLastError();
     return GMRES_ENOMEM;
   }
   *out = h;

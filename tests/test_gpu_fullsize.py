@@ -112,3 +112,74 @@ def test_fullsize_powerlaw_half_basis_reaches_1e10(c3):
     rr = O.relative_residual(O.Matrix.from_csr(A), c3.b, x.cpu().numpy())
     print(f"power-law 1e6 fp16: {info['status']} iters {info['iters']} relres {rr:.3e}", flush=True)
     assert info["status"] == "CONVERGED" and rr <= 1e-10 * 1.001
+
+
+def test_fullsize_batch_persistent():
+    # the 512-system batch exactly as the batch benchmark solves it (one
+    # persistent launch): every system reaches 1e-10 by its own float64
+    # residual, and sampled systems are bitwise their single-system solves
+    from paper_2011_01850_amd import BatchSolver
+
+    probs = P.c4_batch()
+    bs = BatchSolver([(p.A.row_ptr, p.A.col_idx, p.A.vals) for p in probs], m=40, ortho="mgs",
+                     precision="fp32", tol=1e-10, schedule="persistent")
+    xs, infos = bs.solve([p.b for p in probs])
+    bs.close()
+    assert all(i["status"] == "CONVERGED" for i in infos)
+    worst = 0.0
+    for p, x in zip(probs, xs):
+        rr = O.relative_residual(O.Matrix.from_csr(p.A), p.b, x.cpu().numpy())
+        worst = max(worst, rr)
+    its = [i["iters"] for i in infos]
+    print(f"batch of 512: iterations {min(its)} / {int(np.median(its))} / {max(its)}, worst relres {worst:.3e}",
+          flush=True)
+    assert worst <= 1e-10 * 1.001
+    g = np.random.default_rng(4)
+    for k in list(g.choice(512, 3, replace=False)) + [int(np.argmax(its))]:
+        p = probs[k]
+        s = Solver(p.A.row_ptr, p.A.col_idx, p.A.vals, m=40, ortho="mgs", precision="fp32", tol=1e-10,
+                   schedule="persistent")
+        x1, i1 = s.solve(p.b)
+        s.close()
+        assert i1["iters"] == infos[k]["iters"]
+        assert torch.equal(x1, xs[k]), k
+
+
+def _spai_theta(seed):
+    from oracle import mpnn as N
+
+    g = np.random.default_rng(seed)
+    th = N.init_params(seed)
+    o, _ = N.OFFSETS["wo"]
+    th[o:o + N.U] = g.normal(0, 0.05, N.U)
+    th[N.OFFSETS["bo"][0]] = 0.01
+    for name in ("bn", "be", "b1", "b2", "b3"):
+        o, shape = N.OFFSETS[name]
+        th[o:o + shape[0]] = g.normal(0, 0.1, shape[0])
+    return th
+
+
+def test_fullsize_spai_forward():
+    # the learned preconditioner's inference on a held-out 64^3
+    # variable-coefficient instance against the float64 network oracle on the
+    # same bfloat16-rounded parameters (the learned part of M: M minus its
+    # Jacobi start)
+    from oracle import mpnn as N
+    from paper_2011_01850_amd import spai
+
+    A = P.c5_varcoef(2000).A
+    G = N.graph(A.n, A.row_ptr, A.col_idx, A.vals)
+    th = _spai_theta(1)
+    M_or = N.forward(torch.as_tensor(N.round_bf16(th)), G).numpy()
+    net = spai.SpaiNet(A.row_ptr, A.col_idx, kmax=4)
+    net.set_values(A.vals)
+    M_gpu = net.forward(torch.as_tensor(spai.params_to_bf16(th)).cuda()).cpu().numpy().astype(np.float64)
+    net.close()
+    diag = (G.rows == G.cols).numpy()
+    J = np.where(diag, G.sigma.numpy()[G.rows.numpy()] / np.sqrt(G.d.numpy()[G.rows.numpy()] ** 2), 0.0)
+    a, b = M_gpu - J, M_or - J
+    cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+    rel = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    print(f"64^3 inference: learned part cos {cos:.7f} rel {rel:.2e}", flush=True)
+    assert np.all(np.isfinite(M_gpu))
+    assert cos >= 0.99999 and rel <= 1e-3

@@ -90,7 +90,11 @@ def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps,
                      a_storage="copy"):
     rp, ci, va = A_dev
     times, infos = [], []
+    last = None
     for it in range(warmup + steps):
+        if last is not None:  # the previous step's handle is released before this step starts
+            last[0].close()
+            last = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = Solver(rp, ci, va, m=m, ortho=ortho, precision=precision, tol=1e-10, max_iters=100_000,

@@ -126,7 +126,8 @@ typedef struct {
   int32_t batch_schedule;   /* GMRES_SCHEDULE_*: how the systems of a handle share the GPU */
   int32_t spmv_block_nnz;   /* 0: SpMV row blocks chosen by the autotuner (autotune = 1) or 2048;
                                else a fixed non-zero budget per row block, a multiple of 64 in
-                               [64, 8192].  Results do not depend on it: every row is summed in
+                               [64, 8192]; a block holds up to 256 rows (512 with budgets of 4096
+                               and more).  Results do not depend on it: every row is summed in
                                one order fixed by its length. */
   int32_t a_storage;        /* GMRES_A_COPY or GMRES_A_SPLIT */
   /* Restart strategies of the restart study (section 3), each optional and

@@ -187,16 +187,18 @@ bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64
 }
 
 // Adaptive-CSR row blocks over global rows [r_begin, r_end): up to kBlock
-// rows whose non-zeros fit `budget`, or a single longer row.  `lanes` gets
+// rows (2 kBlock with budgets of 4096 and more: fewer, longer blocks for
+// short rows) whose non-zeros fit `budget`, or a single longer row.  `lanes` gets
 // the lane-group width of each block: row_lanes of its longest row
 // (row_lanes grows with the length).
 void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r_end, int budget,
                       std::vector<int32_t>& rb, std::vector<int32_t>* lanes) {
   int64_t r = r_begin;
+  const int64_t max_rows = budget >= 4096 ? 2 * kBlock : kBlock;
   while (r < r_end) {
     rb.push_back((int32_t)r);
     int64_t nz = 0, rows = 0, maxlen = 0;
-    while (r < r_end && rows < kBlock) {
+    while (r < r_end && rows < max_rows) {
       const int64_t len = (int64_t)rp[r + 1] - rp[r];
       if (rows > 0 && nz + len > budget) break;
       nz += len;

@@ -180,7 +180,20 @@ def cpu_baseline(pr, m, ortho, iters_ref, sample_iters):
                    f"{iters_ref} iterations the GPU float64 solve needed (a lower bound: later iterations "
                    f"of a cycle orthogonalise against more vectors)"),
         "host_cpus": len(os.sched_getaffinity(0)),
+        "cpu_model": _cpu_model(),
+        "threads_note": "the oracle is NumPy: single-threaded except the BLAS calls of the CGS projections",
     }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def bench_convdiff3d(args):

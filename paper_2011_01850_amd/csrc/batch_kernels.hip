@@ -7,8 +7,8 @@
 // update, Hessenberg matrix and rotations): the work vector w lives in
 // registers, R = ceil(n / 1024) rows per thread (n <= 65,536), and each
 // basis vector is kept in LDS between its dot product and its axpy (up to
-// 28 rows per thread), so an MGS step reads v_i once from memory (for n up
-// to 28,672; larger systems re-read the rest) and never streams w; H, the rotations
+// 30 rows per thread), so an MGS step reads v_i once from memory (for n up
+// to 30,720; larger systems re-read the rest) and never streams w; H, the rotations
 // and the least-squares right-hand side live in LDS; the basis lives in
 // HBM in one contiguous block per system.  Every reduction is a fixed-order
 // block sum (per-thread float32 partials, float64 across threads), so a
@@ -25,7 +25,7 @@ namespace {
 
 constexpr int kPB = 1024;        // threads per system
 constexpr int kPW = kPB / 64;    // waves per system
-constexpr int kStage = 28;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
+constexpr int kStage = 30;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
 constexpr int kStageLd = kStage + 1;  // odd row stride: lanes hit distinct banks, one base address
 
 struct PShared {

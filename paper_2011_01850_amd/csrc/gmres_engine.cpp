@@ -528,14 +528,24 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   // Each system's row pointer is downloaded into place in a pinned staging
   // buffer, checked (in parallel chunks, read-only), then shifted by its
   // first non-zero and padded (disjoint ranges) into the host copy.
-  PinnedBuffer stage((size_t)(h->ld + 1) * 4);
+  PinnedBuffer stage((size_t)(h->ld + 1 + nsys) * 4);
   int32_t* const st = static_cast<int32_t*>(stage.p);
+  int32_t* const ends = st + h->ld + 1;  // each system's last row-pointer entry
   h->rp_host.resize(h->ld + 1);
+  // every system's download is queued on the handle's stream, then one wait
+  // (pinned staging: the copies run asynchronously).  Copies land in system
+  // order; a system whose row count is a multiple of the tile shares its end
+  // entry with the next system's first, so each end entry is also copied on
+  // its own.
   for (int k = 0; k < nsys; ++k) {
     const System& s = h->sys[k];
-    int32_t* dst = st + s.row0;
-    hip_check(hipMemcpy(dst, rp[k], (s.n + 1) * 4, hipMemcpyDeviceToHost));
-    if (dst[0] != 0 || dst[s.n] != s.nnz) throw Fail{GMRES_EINVAL};
+    hip_check(hipMemcpyAsync(st + s.row0, rp[k], (s.n + 1) * 4, hipMemcpyDeviceToHost, h->stream));
+    hip_check(hipMemcpyAsync(&ends[k], rp[k] + s.n, 4, hipMemcpyDeviceToHost, h->stream));
+  }
+  hip_check(hipStreamSynchronize(h->stream));
+  for (int k = 0; k < nsys; ++k) {
+    const System& s = h->sys[k];
+    if (st[s.row0] != 0 || ends[k] != s.nnz) throw Fail{GMRES_EINVAL};
   }
   {
     constexpr int64_t kChunk = 1 << 18;

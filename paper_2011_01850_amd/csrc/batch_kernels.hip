@@ -7,8 +7,8 @@
 // update, Hessenberg matrix and rotations): the work vector w lives in
 // registers, R = ceil(n / 1024) rows per thread (n <= 65,536), and each
 // basis vector is kept in LDS between its dot product and its axpy (up to
-// 30 rows per thread), so an MGS step reads v_i once from memory (for n up
-// to 30,720; larger systems re-read the rest) and never streams w; H, the rotations
+// 34 rows per thread), so an MGS step reads v_i once from memory (for n up
+// to 34,816; larger systems re-read the rest) and never streams w; H, the rotations
 // and the least-squares right-hand side live in LDS; the basis lives in
 // HBM in one contiguous block per system.  Every reduction is a fixed-order
 // block sum (per-thread float32 partials, float64 across threads), so a
@@ -25,18 +25,21 @@ namespace {
 
 constexpr int kPB = 1024;        // threads per system
 constexpr int kPW = kPB / 64;    // waves per system
-constexpr int kStage = 30;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
+constexpr int kStage = 34;       // rows per thread of v_i kept in LDS between an MGS dot and its axpy
 constexpr int kStageLd = kStage + 1;  // odd row stride: lanes hit distinct banks, one base address
 
 struct PShared {
   double red[2][kPW][2];               // double-buffered wave partials (two sums each)
-  double H[(kMaxPM + 1) * kMaxPM];     // rotated Hessenberg matrix, column-major
+  double H[kMaxPM * (kMaxPM + 1) / 2];  // rotated Hessenberg matrix, packed upper triangle by columns
   double cs[kMaxPM], sn[kMaxPM], sv[kMaxPM + 1], y[kMaxPM], ar[kMaxPM + 1];
   int ctl[4];
   double dctl[2];
   int sys;
   float vst[kPB][kStageLd];            // staged rows of v_i (thread t owns row t)
 };
+
+// column j of the rotated H (rows 0..j) starts at j (j + 1) / 2
+__device__ __forceinline__ int hoff(int j) { return j * (j + 1) / 2; }
 
 __device__ __forceinline__ double wsum(double v) {
 #pragma unroll
@@ -277,7 +280,7 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
           h = bsum(sh, buf, h);
         }
         if (t == 0) {
-          sh.H[j * M1 + i] = h;
+          sh.H[hoff(j) + i] = h;
           hbar[(int64_t)j * M1 + i] = h;
         }
         const float hf = (float)h;
@@ -296,7 +299,7 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
       // ---- Givens rotations of column j, stop decisions (one lane)
       if (t == 0) {
         hbar[(int64_t)j * M1 + j + 1] = hn;
-        double* hc = sh.H + j * M1;
+        double* hc = sh.H + hoff(j);
         double cur = hc[0];
         for (int i = 0; i < j; ++i) {
           const double nxt = hc[i + 1];
@@ -311,7 +314,6 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
         sh.sv[j + 1] = -sg * sjv;
         sh.sv[j] = c * sjv;
         hc[j] = c * cur + sg * hn;
-        hc[j + 1] = 0.0;
         const double res = fabs(sg * sjv);
         sh.ar[j + 1] = res;
         if (cycle == 1 && first_stall < 0) {
@@ -351,14 +353,14 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
     if (t == 0) {
       double hm = 0.0;
       for (int jj = 0; jj < k; ++jj)
-        for (int i = 0; i <= jj; ++i) hm = fmax(hm, fabs(sh.H[jj * M1 + i]));
+        for (int i = 0; i <= jj; ++i) hm = fmax(hm, fabs(sh.H[hoff(jj) + i]));
       const double thr = 16.0 * (double)k * bd_u * hm;
       int kk = 0;
-      while (kk < k && fabs(sh.H[kk * M1 + kk]) > thr) ++kk;
+      while (kk < k && fabs(sh.H[hoff(kk) + kk]) > thr) ++kk;
       for (int i = 0; i < kk; ++i) sh.y[i] = sh.sv[i];
       for (int i = kk - 1; i >= 0; --i) {
-        sh.y[i] /= sh.H[i * M1 + i];
-        for (int l = 0; l < i; ++l) sh.y[l] -= sh.H[i * M1 + l] * sh.y[i];
+        sh.y[i] /= sh.H[hoff(i) + i];
+        for (int l = 0; l < i; ++l) sh.y[l] -= sh.H[hoff(i) + l] * sh.y[i];
       }
       sh.ctl[2] = kk;
     }

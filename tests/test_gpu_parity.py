@@ -461,17 +461,18 @@ def test_limited_mode_with_preconditioners(precond):
     assert abs(info["iters"] - ref.iters) <= max(10, 0.1 * ref.iters)
 
 
+@pytest.mark.parametrize("m", [150, 256])
 @pytest.mark.parametrize("precision,u", [("fp64", O.U64), ("fp32", O.U32), ("limited", O.U32)])
 @pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
-def test_long_cycle_column_windows(precision, u, ortho):
-    # a cycle longer than the 64-column register tile: from j + 1 = 65 on,
-    # CGSR runs its projections over 64-column windows and its last pass as a
-    # column loop; the relation and CGS2's orthogonality hold there as well
+def test_long_cycle_column_windows(precision, u, ortho, m):
+    # a cycle longer than the 64-column register tile (up to the largest
+    # restart length the library takes): from j + 1 = 65 on, CGSR runs its
+    # projections over 64-column windows and its last pass as a column loop;
+    # the relation and CGS2's orthogonality hold there as well
     A = P.convdiff(32, (20.0, 10.0))
     M = O.Matrix.from_csr(A)
     D = M.dense()
     b = np.random.default_rng(8).standard_normal(A.n)
-    m = 150
     s = _solver(A, m=m, ortho=ortho, precision=precision, tol=0.0, max_iters=m)
     s.solve(b)
     k, Hb, V = s.last_cycle()

@@ -250,6 +250,19 @@ def bench_convdiff3d(args):
                                           / np.linalg.norm(pr.x_true)),
                    "memory_bytes": s_li.memory_bytes()}
     s_li.close()
+    # the 2-byte basis (IEEE half plus a power-of-two scale per vector) on the same system
+    out_half = None
+    if args.precision == "fp32":
+        log("half-precision basis ...")
+        t_h, i_h, (s_h, x_h) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, "fp16",
+                                                  args.steps, min(args.warmup, 1))
+        out_half = {"seconds_mean": statistics.mean(t_h), "seconds_median": statistics.median(t_h),
+                    "solve_seconds": i_h[-1]["seconds"], "iters": i_h[-1]["iters"],
+                    "restarts": i_h[-1]["restarts"], "rel_residual": i_h[-1]["rel_residual"],
+                    "forward_error": float(np.linalg.norm(x_h.cpu().numpy() - pr.x_true)
+                                           / np.linalg.norm(pr.x_true)),
+                    "memory_bytes": s_h.memory_bytes()}
+        s_h.close()
     value = statistics.mean(t_mix)
     rec = {
         "metric": METRIC,
@@ -279,6 +292,7 @@ def bench_convdiff3d(args):
         "fp64": out_fp64,
         "split_storage": out_split,
         "limited": out_limited,
+        "half_basis": out_half,
         "speedup_vs_fp64": (round(out_fp64["seconds"] / value, 3) if out_fp64 else None),
         "paper_context": "paper (2x10-core Haswell, Kokkos/MKL, ILU(0), SuiteSparse): mixed vs FP64 "
                          "geo-mean speedup +19% (MGS), +24% (CGSR) when restarted at least once",

@@ -97,13 +97,27 @@ enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2,
  * conditions, DEVICE_WIDE otherwise. */
 enum { GMRES_SCHEDULE_AUTO = 0, GMRES_SCHEDULE_DEVICE_WIDE = 1, GMRES_SCHEDULE_PERSISTENT = 2 };
 
-/* gmres_result.status */
+/* gmres_result.status.  Breakdown of the Arnoldi process (h_{j+1,j} = 0 in
+ * Algorithm 1, detected here as h_{j+1,j} <= 16 (j+1) u ||A v_j|| with u the
+ * unit roundoff of the Arnoldi arithmetic) has no status of its own: it ends
+ * the cycle like j = m does, the correction from the columns formed so far
+ * is applied, and the float64 restart residual decides what follows.  A
+ * "lucky" breakdown (the Krylov space holds the solution) therefore ends as
+ * CONVERGED.  A breakdown whose least-squares problem keeps no column (every
+ * leading pivot of H below 16 k u max|H|, e.g. A v_1 = 0 for a singular A)
+ * applies no correction, so the restart residual does not move and the solve
+ * ends as STALLED after stall_cycles such cycles. */
 enum { GMRES_RUNNING = 0, GMRES_CONVERGED = 1, GMRES_MAXITER = 2, GMRES_STALLED = 3 };
 
 /* error codes */
 enum {
   GMRES_OK = 0,
-  GMRES_EINVAL = -1,  /* invalid argument: n <= 0, m < 1 or m > 256, tol < 0, bad CSR, NULL pointer */
+  GMRES_EINVAL = -1,  /* invalid argument: n <= 0, m < 1 or m > 256, tol < 0, bad CSR, NULL pointer,
+                         or sizes the kernels cannot address (checked before any device work):
+                         padded rows (each system's n rounded up to a multiple of 256, summed)
+                         >= 2^31 - 1, non-zeros > 2^31 - 1029, or a basis of (m + 1) x padded
+                         rows x element bytes (8 float64, 4 float32 / limited, 2 bfloat16 / half)
+                         >= 2^32 bytes, since the basis is read through 32-bit buffer offsets */
   GMRES_EHIP = -2,    /* a HIP runtime call failed */
   GMRES_ENOMEM = -3,  /* device allocation failed */
   GMRES_EHANDLE = -4, /* NULL or destroyed handle */
@@ -212,16 +226,21 @@ int gmres_batch_create(gmres_handle* out, int32_t nsys, const int64_t* n, const 
                        const int32_t* const* row_ptr, const int32_t* const* col_idx,
                        const double* const* vals, const gmres_options* opt, void* hip_stream);
 
-/* Values of a sparse approximate inverse M on the sparsity pattern of A
+/* The preconditioner M^-1 of Algorithm 1's inputs, given explicitly:
+ * values of a sparse approximate inverse M on the sparsity pattern of A
  * (float32, device, one value per stored entry of A in A's storage order,
  * systems concatenated for a batch handle).  Used as z = M v in the
  * flexible (right-preconditioned) solve.  Errors: ESTATE unless the handle
  * was created with precond = GMRES_PRECOND_SPAI. */
 int gmres_set_preconditioner(gmres_handle h, const float* spai_vals);
 
-/* Solve A x = b.  b: float64[n], read only.  x: float64[n], in: x0, out:
- * the final iterate.  b = 0 gives x = 0 with 0 iterations.  Synchronises
- * the stream and fills *res (res may be NULL). */
+/* Solve A x = b by Algorithm 1: restart cycles of float64 residual
+ * z = b - A x and stop test, m Arnoldi steps (SpMV, MGS or CGSR, Givens
+ * update of H), back-solve and float64 correction x += V y (x += Z y in the
+ * flexible form), with the precision split of the numerics section.
+ * b: float64[n], read only.  x: float64[n], in: x0, out: the final iterate.
+ * b = 0 gives x = 0 with 0 iterations.  Synchronises the stream and fills
+ * *res (res may be NULL). */
 int gmres_solve(gmres_handle h, const double* b, double* x, gmres_result* res);
 
 /* Batch solve: b[k], x[k] are device pointers of system k (host arrays of

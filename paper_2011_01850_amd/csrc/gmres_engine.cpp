@@ -174,6 +174,26 @@ bool valid_options(const gmres_options* o) {
   return true;
 }
 
+// Sizes the kernels can address, checked before any device work: row
+// pointers and column indices are int32 (padded rows and non-zeros, with the
+// 4-entry pad and a workgroup's worth of index slack, stay below 2^31), and
+// the basis is read through buffer resources whose byte ranges and offsets
+// are 32-bit, so (m + 1) padded columns of the basis must stay below 4 GiB.
+int64_t basis_elem_bytes(int precision) {
+  return precision == GMRES_FP64 ? 8 : (precision == GMRES_MIXED_BF16 || precision == GMRES_MIXED_FP16) ? 2 : 4;
+}
+
+bool sizes_ok(int32_t nsys, const int64_t* n, const int64_t* nnz, const gmres_options* o) {
+  int64_t ld = 0, nz = 0;
+  for (int k = 0; k < nsys; ++k) {
+    if (n[k] > (int64_t)INT32_MAX || nnz[k] > (int64_t)INT32_MAX) return false;
+    ld += (n[k] + kTile - 1) / kTile * kTile;
+    nz += nnz[k];
+    if (ld >= (int64_t)INT32_MAX || nz > (int64_t)INT32_MAX - 4 * kBlock - 4) return false;
+  }
+  return (int64_t)(o->m + 1) * ld * basis_elem_bytes(o->precision) < ((int64_t)1 << 32);
+}
+
 // Conditions of the persistent schedule (one workgroup of 1024 threads per
 // system, up to kMaxPR rows per thread, H in LDS, 32-bit buffer offsets).
 bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64_t nnz_total, int64_t ld) {
@@ -513,7 +533,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     tl += s.nt;
     h->nrows += s.n;
   }
-  if (row >= (int64_t)INT32_MAX || nz >= (int64_t)INT32_MAX) throw Fail{GMRES_EINVAL};
+  if (row >= (int64_t)INT32_MAX || nz >= (int64_t)INT32_MAX) throw Fail{GMRES_EINVAL};  // (sizes_ok)
   h->ld = row;
   h->nnz = nz;
   h->ntile = (int32_t)tl;
@@ -663,8 +683,8 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   }
   // ---- workspace
   const int64_t M1 = m + 1, M2 = m + 2;
-  // the basis is addressed through 32-bit buffer offsets
-  if (M1 * h->ld * vbytes(prec) >= (int64_t)1 << 32) throw Fail{GMRES_ENOMEM};
+  // the basis is addressed through 32-bit buffer offsets (checked by sizes_ok)
+  if (M1 * h->ld * vbytes(prec) >= (int64_t)1 << 32) throw Fail{GMRES_EINVAL};
   a.V = h->alloc<uint8_t>((size_t)(M1 * h->ld * vbytes(prec)));
   hip_check(hipMemsetAsync(a.V, 0, (size_t)(M1 * h->ld * vbytes(prec)), h->stream));
   a.w = h->alloc<uint8_t>((size_t)(h->ld * wbytes(prec)));
@@ -949,6 +969,7 @@ int gmres_batch_create(gmres_handle* out, int32_t nsys, const int64_t* n, const 
     if (n[k] <= 0 || nnz[k] < 0 || !row_ptr[k] || (nnz[k] > 0 && (!col_idx[k] || !vals[k])))
       return GMRES_EINVAL;
   }
+  if (!sizes_ok(nsys, n, nnz, opt)) return GMRES_EINVAL;
   gmres_ctx* h = new (std::nothrow) gmres_ctx();
   if (!h) return GMRES_ENOMEM;
   try {

@@ -82,6 +82,35 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.gmres_encode(L.MIXED_FP16, 10, 1, 0.0, 1, None, None) == L.EINVAL
 
 
+def test_unaddressable_sizes_rejected_before_device_work(lib):
+    # the basis is read through 32-bit buffer offsets: (m + 1) padded columns
+    # must stay below 4 GiB; row pointers and column indices are int32.  The
+    # pointers below are never dereferenced: the sizes are refused first.
+    h = C.c_void_p()
+    n128 = 128 ** 3  # 2,097,152 rows, a multiple of the 256-row tile
+    # (accepted sizes are not tried here: the call would go on to read the fake pointers)
+    for prec, m in [(L.FP64, 255), (L.FP64, 256)]:  # 256 x 2^21 x 8 = 2^32 bytes
+        o = L.default_options()
+        o.precision, o.m = prec, m
+        assert lib.gmres_create(C.byref(h), n128, 7 * n128, 16, 16, 16, C.byref(o), None) == L.EINVAL, m
+    # float32 / half bases of the same system fit: 257 x 2^21 x 4 < 2^32
+    assert 257 * n128 * 4 < 2 ** 32
+    # float32 basis of 4 GiB: 2^23 + 256 rows pad to 2^23 + 256, (m + 1) = 128 columns
+    o = L.default_options()
+    o.precision, o.m = L.MIXED_FP32, 127
+    assert lib.gmres_create(C.byref(h), 2 ** 23 + 1, 10, 16, 16, 16, C.byref(o), None) == L.EINVAL
+    # rows and non-zeros beyond int32
+    o = L.default_options()
+    o.m = 1
+    assert lib.gmres_create(C.byref(h), 2 ** 31, 10, 16, 16, 16, C.byref(o), None) == L.EINVAL
+    assert lib.gmres_create(C.byref(h), 1000, 2 ** 31 - 1028, 16, 16, 16, C.byref(o), None) == L.EINVAL
+    # a batch whose padded rows add up past int32
+    ns = (C.c_int64 * 2)(2 ** 30, 2 ** 30)
+    zs = (C.c_int64 * 2)(10, 10)
+    ptrs = (C.c_void_p * 2)(16, 16)
+    assert lib.gmres_batch_create(C.byref(h), 2, ns, zs, ptrs, ptrs, ptrs, C.byref(o), None) == L.EINVAL
+
+
 def test_handle_checks(lib):
     assert lib.gmres_destroy(None) == L.OK
     r = L.Result()

@@ -625,3 +625,112 @@ def test_fgmres_with_jacobi_equals_right_preconditioned_gmres():
     r2 = O.gmres(AD, b, m=20, tol=1e-11)
     assert r1.iters == r2.iters and r1.restarts == r2.restarts
     assert np.linalg.norm(r1.x - r2.x / d) <= 1e-9 * np.linalg.norm(r1.x)
+
+
+# --------------------------------------------------------------------------
+# normwise backward error (the stopping metric the paper's experiments use)
+
+def test_backward_error_closed_form_2x2():
+    # A = [[2, 1], [0, 3]], x = [1, 1], b = [3, 2]: r = [0, -1], ||A||_F = sqrt(14)
+    A = O.Matrix(np.array([0, 2, 3]), np.array([0, 1, 1]), np.array([2.0, 1.0, 3.0]))
+    eta = O.backward_error(A, np.array([3.0, 2.0]), np.array([1.0, 1.0]))
+    assert eta == pytest.approx(1.0 / (math.sqrt(14.0) * math.sqrt(2.0) + math.sqrt(13.0)), rel=1e-15)
+
+
+def test_backward_error_is_the_size_of_an_exact_perturbation():
+    # Rigal-Gaches: with dA = t ||A|| r x^T / ||x||^2 and db = -(1 - t) r,
+    # t = ||A|| ||x|| / (||A|| ||x|| + ||b||), (A + dA) x = b + db holds exactly
+    # and ||dA||_F / ||A||_F = ||db|| / ||b|| = eta (a rank-one dA has equal
+    # Frobenius and 2-norms); eta never exceeds the relative residual, is
+    # zero at the solution and does not change when A and b are scaled together
+    g = np.random.default_rng(5)
+    D = g.standard_normal((7, 7)) + 4 * np.eye(7)
+    A = O.Matrix.from_csr(P.dense_to_csr(D))
+    b = g.standard_normal(7)
+    x = np.linalg.solve(D, b) + 1e-3 * g.standard_normal(7)
+    eta = O.backward_error(A, b, x)
+    r = b - D @ x
+    nA, nx, nb = np.linalg.norm(D), np.linalg.norm(x), np.linalg.norm(b)
+    t = nA * nx / (nA * nx + nb)
+    dA = (t / nx ** 2) * np.outer(r, x)
+    db = -(1.0 - t) * r
+    assert np.allclose((D + dA) @ x, b + db, rtol=0, atol=1e-13)
+    assert np.linalg.norm(dA) / nA == pytest.approx(eta, rel=1e-12)
+    assert np.linalg.norm(db) / nb == pytest.approx(eta, rel=1e-12)
+    assert eta <= O.relative_residual(A, b, x)
+    xs = np.linalg.solve(D, b)
+    assert O.backward_error(A, b, xs) <= 1e-15
+    A3 = O.Matrix.from_csr(P.dense_to_csr(3.0 * D))
+    assert O.backward_error(A3, 3.0 * b, x) == pytest.approx(eta, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# ILU(0) sweeps in float32: every operation rounded, checked against exact
+# rational arithmetic with an explicit round-to-nearest-even to float32
+
+def _rne32(q):
+    """The float32 nearest to the rational q (ties to even), as a Fraction."""
+    from fractions import Fraction
+
+    if q == 0:
+        return Fraction(0)
+    sign = -1 if q < 0 else 1
+    q = abs(q)
+    e = 0  # q * 2^-e in [2^23, 2^24): 24 significand bits
+    while q / Fraction(2) ** e >= 2 ** 24:
+        e += 1
+    while q / Fraction(2) ** e < 2 ** 23:
+        e -= 1
+    e = max(e, -149)  # subnormals: fixed quantum 2^-149
+    m = q / Fraction(2) ** e
+    f = m.numerator // m.denominator
+    rem = m - f
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and f % 2 == 1):
+        f += 1
+    return sign * Fraction(f) * Fraction(2) ** e
+
+
+def test_ilu_float32_sweeps_round_every_operation():
+    from fractions import Fraction
+
+    # a 4x4 matrix with full lower and upper triangles and values that are
+    # not float32-exact, so every product, difference and quotient rounds
+    D = np.array([[3.0, 0.1, 0.0, 0.7],
+                  [0.3, 2.5, 0.2, 0.0],
+                  [0.0, 0.9, 4.1, 0.6],
+                  [0.2, 0.0, 0.4, 1.9]])
+    A = O.Matrix.from_csr(P.dense_to_csr(D))
+    lu, diag = O.ilu0(A)
+    v = np.array([1.0, -2.0 / 3.0, 0.1, 5.0 / 7.0], dtype=np.float32)
+    n, rp, ci = A.n, A.row_ptr, A.col_idx
+    lu32 = [Fraction(float(np.float32(t))) for t in lu]
+    vq = [Fraction(float(t)) for t in v]
+    dinv = [_rne32(1 / lu32[diag[i]]) for i in range(n)]
+    for sweeps in (1, 2, 3, 4):
+        y = [Fraction(0)] * n
+        for _ in range(sweeps):  # y <- v - L' y, the row sum in storage order
+            new = []
+            for i in range(n):
+                acc = Fraction(0)
+                for p in range(rp[i], rp[i + 1]):
+                    if ci[p] < i:
+                        acc = _rne32(acc + _rne32(lu32[p] * y[ci[p]]))
+                new.append(_rne32(vq[i] - acc))
+            y = new
+        x = [Fraction(0)] * n
+        for _ in range(sweeps):  # x <- D^-1 (y - U' x)
+            new = []
+            for i in range(n):
+                acc = Fraction(0)
+                for p in range(rp[i], rp[i + 1]):
+                    if ci[p] > i:
+                        acc = _rne32(acc + _rne32(lu32[p] * x[ci[p]]))
+                new.append(_rne32(_rne32(y[i] - acc) * dinv[i]))
+            x = new
+        got = O.ilu_apply(A, lu, diag, v, sweeps=sweeps, dtype=np.float32)
+        assert got.dtype == np.float32
+        assert [Fraction(float(t)) for t in got] == x, sweeps
+    # the float32 result differs from the float64 one (rounding is really emulated)
+    z64 = O.ilu_apply(A, lu, diag, v.astype(np.float64), sweeps=4)
+    assert not np.array_equal(got.astype(np.float64), z64)
+    assert np.allclose(got, z64, rtol=1e-6)

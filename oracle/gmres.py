@@ -513,6 +513,9 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
             return V[i].astype(np.float64) if limited else basis(i)
 
         k = 0
+        # CGSR reads the stored basis as one matrix [v_1 .. v_j]: its columns
+        # are filled in as they are formed (a view, not a fresh copy per step)
+        Vmat = None
         W = []  # (record) w after orthogonalisation, before normalisation, per step
         cycle_arn = []
         ares = [beta]  # |s_1| .. |s_{j+1}| of this cycle
@@ -545,7 +548,11 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                     hcol[i] = hij
                     w = (w - (np.float32(hij) if lowp and not limited else hij) * vi).astype(w.dtype)
             else:
-                Vj = np.stack([operand(i) for i in range(j + 1)], axis=1)
+                col = operand(j)
+                if Vmat is None:
+                    Vmat = np.empty((n, m + 1), dtype=col.dtype)
+                Vmat[:, j] = col
+                Vj = Vmat[:, : j + 1]
                 for _ in range(2):  # classical Gram-Schmidt, then its re-orthogonalisation pass
                     hp = Vj.T @ w
                     w = (w - Vj @ hp.astype(w.dtype)).astype(w.dtype)

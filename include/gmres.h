@@ -281,6 +281,20 @@ int gmres_precond_apply(gmres_handle h, const float* v, float* z);
 int gmres_encode(int32_t precision, int64_t n, const float* w, double inv_h, void* out,
                  double* scale_out, void* hip_stream);
 
+/* gmres_encode without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same arguments, result and scale as
+ * gmres_encode, bit for bit.  The per-tile partial maxima live in a static
+ * device array of 262,400 bytes (one float per 256-element tile of at most
+ * 2^24 elements, plus the reduced maximum) that each GPU the library runs on
+ * holds until the process ends.  n > 2^24 is refused with GMRES_EINVAL
+ * before any device work.  Every call on one GPU uses that GPU's array, so
+ * calls that overlap in time on one GPU (other host threads, other streams)
+ * race; calls in sequence do not (each call writes every slot it reads).
+ * Runs on hip_stream and synchronises it. */
+int gmres_encode_noalloc(int32_t precision, int64_t n, const float* w, double inv_h, void* out,
+                         double* scale_out, void* hip_stream);
+
 /* After a solve, the last cycle of system sys: *k_out = number of Arnoldi
  * steps, Hbar_out (HOST, float64, (m+1) x m column-major, may be NULL) =
  * the unrotated Hessenberg matrix, V_out (DEVICE, float64, n x (k+1)

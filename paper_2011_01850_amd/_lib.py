@@ -90,6 +90,7 @@ _SIGS = {
     "gmres_spmv": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
     "gmres_precond_apply": (C.c_int, [_vp, _vp, _vp]),
     "gmres_encode": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_double, _vp, C.POINTER(C.c_double), _vp]),
+    "gmres_encode_noalloc": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_double, _vp, C.POINTER(C.c_double), _vp]),
     "gmres_last_cycle": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _vp, _vp]),
     "gmres_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, C.POINTER(C.c_int32)]),
     "gmres_memory_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),

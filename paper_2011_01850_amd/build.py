@@ -15,7 +15,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgmres.so")
 ARCH = os.environ.get("GMRES_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["gmres_kernels.hip", "gmres_engine.cpp", "batch_kernels.hip", "spai_kernels.hip", "spai_engine.cpp"]
+SOURCES = ["gmres_kernels.hip", "gmres_engine.cpp", "batch_kernels.hip", "spai_kernels.hip", "spai_engine.cpp",
+           "encode_noalloc.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

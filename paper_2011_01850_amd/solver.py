@@ -277,14 +277,21 @@ class BatchSolver:
         return out[: min(cnt.value, cap)].copy()
 
 
-def encode(w, inv_h, fmt="fp16"):
-    """2-byte basis storage of v = w * inv_h exactly as the solver does it: (uint16 tensor, scale)."""
+def encode(w, inv_h, fmt="fp16", out=None, noalloc=False):
+    """2-byte basis storage of v = w * inv_h exactly as the solver does it: (uint16 tensor, scale).
+
+    noalloc=True calls gmres_encode_noalloc (no device allocation inside the
+    library; `out` may be given so that the binding allocates nothing either)."""
     torch = _torch()
     lib = L.load()
     wt = _dev(w, torch.float32, torch)
-    out = torch.empty(wt.numel(), dtype=torch.int16, device="cuda")
+    if out is None:
+        out = torch.empty(wt.numel(), dtype=torch.int16, device="cuda")
+    elif out.numel() < wt.numel() or out.element_size() != 2 or not out.is_cuda:
+        raise ValueError("out must be a 2-byte CUDA tensor of at least len(w) elements")
     sc = C.c_double()
     torch.cuda.synchronize()
-    L.check(lib.gmres_encode(L.PRECISIONS[fmt], wt.numel(), wt.data_ptr(), float(inv_h), out.data_ptr(),
-                             C.byref(sc), C.c_void_p(torch.cuda.current_stream().cuda_stream)), "gmres_encode")
+    fn, name = (lib.gmres_encode_noalloc, "gmres_encode_noalloc") if noalloc else (lib.gmres_encode, "gmres_encode")
+    L.check(fn(L.PRECISIONS[fmt], wt.numel(), wt.data_ptr(), float(inv_h), out.data_ptr(),
+               C.byref(sc), C.c_void_p(torch.cuda.current_stream().cuda_stream)), name)
     return out, sc.value

@@ -80,6 +80,11 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL
     assert lib.gmres_encode(L.FP64, 10, 1, 1.0, 1, None, None) == L.EINVAL
     assert lib.gmres_encode(L.MIXED_FP16, 10, 1, 0.0, 1, None, None) == L.EINVAL
+    # the no-allocation variant: the same checks, and no more than 2^24 elements
+    assert lib.gmres_encode_noalloc(L.FP64, 10, 1, 1.0, 1, None, None) == L.EINVAL
+    assert lib.gmres_encode_noalloc(L.MIXED_FP16, 10, 1, 0.0, 1, None, None) == L.EINVAL
+    assert lib.gmres_encode_noalloc(L.MIXED_BF16, 10, None, 1.0, 1, None, None) == L.EINVAL
+    assert lib.gmres_encode_noalloc(L.MIXED_BF16, 2 ** 24 + 1, 1, 1.0, 1, None, None) == L.EINVAL
 
 
 def test_unaddressable_sizes_rejected_before_device_work(lib):

@@ -3,18 +3,27 @@
 
 Workload: 3-D convection-diffusion on a 128^3 grid (n = 2,097,152 rows,
 14,581,760 non-zeros, 7-point first-order upwind stencil, beta = (50, 20,
-10)), b = A x_true with x_true ~ U[-1, 1], x0 = 0, GMRES(50) with CGSR (or
+10)), b = A x_true with x_true ~ U[-1, 1], x0 = 0, GMRES(50) with CGSR (and
 MGS), float32 Arnoldi with float64 residual and update.  One step = one
 time-to-solution: gmres_create (matrix copies, float32 copy, SpMV row
 blocks and autotuning, workspace) + gmres_solve to 1e-10, inputs already
 resident in HBM.  The float64 solver is timed the same way for the speedup.
 
 Also reported, on the same JSON line:
-  roofline      achieved HBM bandwidth of the dominant kernel (the fused
-                second CGS projection at its 64-column tile width, launches
-                j = 31..49 of a cycle, timed with HIP events on the solver's
-                stream) against the 8 TB/s peak;
-  cpu_baseline  the CPU oracle on a bounded sample of the same system.
+  roofline      achieved HBM bandwidth of the dominant kernel family (the
+                one with the most kernel time inside a solve), measured
+                inside one more solve of the same handle in which every
+                launch sits between two HIP events on the solver's stream,
+                against the 8 TB/s peak; the back-to-back harness time of
+                its 64-column instantiation and its launch configuration are
+                printed beside it;
+  cpu_baseline  the CPU oracle on a bounded sample of the same system (two
+                whole restart cycles, scaled to the float64 cycle count);
+  mgs           the same system with MGS, mixed and float64, and the MGS
+                step kernel's in-solve bandwidth;
+  powerlaw, batch, learned
+                compact results of the other workloads (--legs selects
+                them; each has its own --workload for the full report).
 """
 from __future__ import annotations
 
@@ -32,16 +41,17 @@ sys.path.insert(0, ROOT)
 METRIC = "time to 1e-10 rel. residual: mixed/learned vs FP64 GMRES; HBM GB/s"
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the roofline kernel, from two rocprofv3 counter runs
-# of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by what it reads
-# for a plain 1 GiB device copy: x2.0 and x1.0), averaged over the roofline
-# launches.  Valid only for the kernel source they were taken from.
-TRAFFIC = {"bytes_per_launch": 346543305, "kernel_source_sha256": "9f604e3b53c3b7acc9c068a9543cba3f9690106ff4882a681d85516800440d31"}
+# HBM bytes per launch of the roofline kernel family, from two rocprofv3
+# counter runs of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by
+# what it reads for a plain 1 GiB device copy: x2.0 and x1.0), averaged over
+# the family's launches that did work.  Valid only for the family they were
+# taken for and the kernel source they were taken from.
+TRAFFIC = {"family": None, "bytes_per_launch": None, "kernel_source_sha256": None}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 
-def measured_traffic():
-    if TRAFFIC["bytes_per_launch"] is None:
+def measured_traffic(family):
+    if TRAFFIC["bytes_per_launch"] is None or TRAFFIC["family"] != family:
         return None
     with open(KERNEL_SOURCE, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["kernel_source_sha256"]:
@@ -76,7 +86,16 @@ def parse():
                     help="powerlaw: comma-separated precision modes to run (fp64 is always run first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=10)
-    ap.add_argument("--cpu-iters", type=int, default=20, help="oracle sample: inner iterations")
+    ap.add_argument("--cpu-cycles", type=int, default=2,
+                    help="oracle sample: whole restart cycles of the float64 oracle (default 2)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the whole float64 oracle solve instead of a sample (minutes)")
+    ap.add_argument("--mgs-steps", type=int, default=3, help="timed steps of each MGS mode (default workload)")
+    ap.add_argument("--legs", default="c3,c4,c5",
+                    help="default workload: comma-separated extra legs to run after the headline system "
+                         "(c3 = power-law, c4 = batch, c5 = learned preconditioner), or 'none'")
+    ap.add_argument("--c5-train", type=int, default=2000, help="c5 leg: training instances")
+    ap.add_argument("--c5-test", type=int, default=200, help="c5 leg: held-out instances")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (reference kernel for HBM byte counters)")
     return ap.parse_args()
@@ -113,49 +132,84 @@ def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps,
     return times, infos, last
 
 
-def roofline(solver, m, reps):
-    """Dominant kernel: fused CGS projection 2 at its 64-column tile (j = 31..m-1).
+# kernel families of the in-solve profile and the kernels each one launches
+FAMILY_KERNELS = {
+    "spmv": "k_spmv<A,x,w,ARNOLDI> (Arnoldi SpMV w = A v_j, adaptive CSR row blocks)",
+    "pass1": "k_mdot<V,w,L> (CGS projection 1: V^T w; L = 8/16/32/64 columns by j)",
+    "pass2": "k_axpy_mdot<V,w,L> (CGS projection 2 fused: w -= V h1, then V^T w)",
+    "final": "k_final_tile<V,w,L> / k_mgs_final (last pass: w -= V h2, ||w||, v_{j+1})",
+    "mgs": "k_mgs<V,w> (MGS step: completes dot i-1, w -= h v_{i-1}, partial w . v_i)",
+    "residual": "k_spmv<double,double,w,RESID> (float64 restart residual z = b - A x)",
+    "update": "k_update<V> (float64 update x += V y)",
+    "precond": "preconditioner application z_j = M v_j",
+}
+HBM_FAMILIES = ("spmv", "pass1", "pass2", "final", "mgs", "residual", "update", "precond")
+# gmres_time_kernel's numbering of the same kernels (the back-to-back harness)
+HARNESS_KERNEL = {"spmv": 0, "pass1": 1, "pass2": 2, "final": 3, "mgs": 4, "residual": 5, "update": 6}
 
-    For each column j the library launches the kernel once untimed, then
-    `reps` times back to back between two HIP events on the solver's stream;
-    the timed launches sit in a ROCTx range named "timed:k_axpy_mdot(cgs pass
-    2)", which `rocprofv3 --marker-trace --kernel-rename` reports as one row.
-    """
-    js = list(range(min(31, m - 1), m))
-    t_ms, byts = [], []
-    for j in js:
-        ms, by = solver.time_kernel(2, j, reps)
-        t_ms.append(ms)
-        byts.append(by)
-    avg_ms = sum(t_ms) / len(t_ms)
-    avg_bytes = sum(byts) / len(byts)
-    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
-    # the rest of the step's kernels at the last column, for the report
-    other = {}
-    for k, name in [(0, "spmv_arnoldi"), (1, "cgs_pass1"), (3, "final_pass"), (5, "residual64"), (6, "update64"),
-                    (7, "finalize_pass2")]:
-        ms, by = solver.time_kernel(k, m - 1, reps)
-        other[name] = {"ms": round(ms, 5), "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
+
+def in_solve_profile(solver, b_dev):
+    """One more solve on the same handle, every launch between two HIP events
+    (gmres_solve_profiled): per kernel family, time per solve, launches, and
+    the time, launches and algorithmic bytes of the launches that did work."""
+    x, info, prof = solver.solve_profiled(b_dev)
+    fam = {}
+    for name, p in prof.items():
+        if p["launches"] == 0:
+            continue
+        e = {"ms_per_solve": round(p["ms"], 4), "launches": p["launches"], "ms_active": round(p["ms_active"], 4),
+             "active_launches": p["active"], "alg_bytes": p["bytes"]}
+        if p["active"] and p["bytes"] > 0:
+            e["avg_launch_ms"] = round(p["ms_active"] / p["active"], 5)
+            e["GB/s"] = round(p["bytes"] / (p["ms_active"] * 1e-3) / 1e9, 1)
+        fam[name] = e
+    return x, info, fam
+
+
+def roofline_from_profile(solver, fam, m, reps, families=HBM_FAMILIES):
+    """The dominant family by in-solve time among the HBM-bound ones; achieved =
+    its algorithmic bytes over its summed in-solve launch time.  Beside it: the
+    back-to-back harness time of the same kernel at the last column of its
+    widest instantiation, and the launch configuration."""
+    cands = [k for k in families if k in fam and fam[k]["alg_bytes"] > 0]
+    dom = max(cands, key=lambda k: fam[k]["ms_active"])
+    f = fam[dom]
+    avg_ms = f["ms_active"] / f["active_launches"]
+    per_launch = f["alg_bytes"] / f["active_launches"]
+    achieved = f["alg_bytes"] / (f["ms_active"] * 1e-3) / 1e9
+    traffic = measured_traffic(dom)
+    j_last = m - 1
+    harness = None
+    if dom in HARNESS_KERNEL:
+        ms, by = solver.time_kernel(HARNESS_KERNEL[dom], j_last, reps)
+        harness = {"j": j_last, "reps": reps, "avg_launch_ms": round(ms, 5), "alg_bytes": by,
+                   "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
+    cfg = solver.launch_config(dom, j_last) if dom in HARNESS_KERNEL else None
     return {
         "bound": "hbm",
-        "kernel": "k_axpy_mdot<float,float,64> (CGS projection 2, fused w -= V h1 and V^T w)",
+        "kernel": FAMILY_KERNELS.get(dom, dom),
+        "family": dom,
         "achieved": round(achieved, 1),
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
-        "traffic": traffic,
-        "traffic_over_alg": (round(traffic / avg_bytes, 4) if traffic else None),
+        "traffic": (round(traffic) if traffic else None),
+        "traffic_over_alg": (round(traffic / per_launch, 4) if traffic else None),
         "avg_launch_ms": round(avg_ms, 5),
-        "alg_bytes_per_launch": avg_bytes,
-        "launches": f"j = {js[0]}..{js[-1]}, {reps} timed back-to-back launches each (after 1 untimed)",
-        "other_kernels_at_j_last": other,
+        "alg_bytes_per_launch": round(per_launch),
+        "launches": (f"{f['active_launches']} launches that did work inside one solve (of {f['launches']}; "
+                     f"the rest are gated off after the last cycle converged), each between two HIP events "
+                     f"on the solver's stream"),
+        "avg_launch_ms_all_launches": round(f["ms_per_solve"] / f["launches"], 5),
+        "harness_back_to_back": harness,
+        "launch_config_at_j_last": cfg,
+        "in_solve_families": fam,
     }
 
 
-def cpu_baseline(pr, m, ortho, iters_ref, sample_iters):
-    import numpy as np  # noqa: F401
-
+def cpu_baseline(pr, m, ortho, ref_iters, ref_cycles, cycles, full=False):
+    """The float64 oracle on the host: `cycles` whole restart cycles (or the
+    whole solve), scaled to the float64 GPU solve's cycle count."""
     from oracle import gmres as O
 
     try:
@@ -167,18 +221,25 @@ def cpu_baseline(pr, m, ortho, iters_ref, sample_iters):
         threads = 1
     A = O.Matrix.from_csr(pr.A)
     t0 = time.perf_counter()
-    r = O.gmres(A, pr.b, m=m, tol=1e-10, max_iters=sample_iters, ortho=ortho)
+    r = O.gmres(A, pr.b, m=m, tol=1e-10, max_iters=(10 ** 7 if full else cycles * m), ortho=ortho)
     dt = time.perf_counter() - t0
-    per_iter = dt / max(1, r.iters)
+    if full:
+        value = dt
+        sample = (f"the whole float64 {ortho.upper()} oracle solve on the same system: {r.iters} iterations, "
+                  f"{r.restarts} cycles, relres {r.rel_residual:.2e}, {dt:.1f} s")
+    else:
+        per_cycle = dt / max(1, r.restarts)
+        value = per_cycle * ref_cycles
+        sample = (f"{r.restarts} whole restart cycles ({r.iters} inner iterations and their float64 residuals) "
+                  f"of the float64 {ortho.upper()} oracle on the same system took {dt:.2f} s; value = that time "
+                  f"per cycle x the {ref_cycles} cycles ({ref_iters} iterations) the GPU float64 solve needed "
+                  f"(its last cycle is shorter, so this slightly over-states the whole solve)")
     return {
-        "value": round(per_iter * iters_ref, 3),
+        "value": round(value, 3),
         "unit": "s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": (f"first {r.iters} inner iterations (+2 float64 residuals) of the float64 {ortho.upper()} "
-                   f"oracle on the same system took {dt:.2f} s; value = that per-iteration cost x the "
-                   f"{iters_ref} iterations the GPU float64 solve needed (a lower bound: later iterations "
-                   f"of a cycle orthogonalise against more vectors)"),
+        "sample": sample,
         "host_cpus": len(os.sched_getaffinity(0)),
         "cpu_model": _cpu_model(),
         "threads_note": "the oracle is NumPy: single-threaded except the BLAS calls of the CGS projections",
@@ -194,6 +255,19 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def _summary(times, infos, solver, x, pr, b_dev, np):
+    """Time-to-solution statistics of one mode, with the errors of its last solution."""
+    eta, rel = solver.backward_error(b_dev, x)
+    xs = x.cpu().numpy()
+    return {"seconds_mean": statistics.mean(times), "seconds_median": statistics.median(times),
+            "seconds_min": min(times), "seconds_max": max(times),
+            "solve_seconds": infos[-1]["seconds"], "setup_seconds": infos[-1]["setup_seconds"],
+            "iters": infos[-1]["iters"], "restarts": infos[-1]["restarts"], "status": infos[-1]["status"],
+            "rel_residual": infos[-1]["rel_residual"], "backward_error": eta,
+            "forward_error": float(np.linalg.norm(xs - pr.x_true) / np.linalg.norm(pr.x_true)),
+            "memory_bytes": solver.memory_bytes()}, xs
 
 
 def bench_convdiff3d(args):
@@ -212,58 +286,66 @@ def bench_convdiff3d(args):
     b_dev = torch.as_tensor(pr.b, device="cuda")
     torch.cuda.synchronize()
     log(f"n = {A.n:,}, nnz = {A.nnz:,}; mixed {args.precision} {args.ortho}")
-    t_mix, i_mix, (solver, x) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, args.precision,
-                                                 args.steps, args.warmup)
-    xs = x.cpu().numpy()
-    fwd = float(np.linalg.norm(xs - pr.x_true) / np.linalg.norm(pr.x_true))
-    rf = roofline(solver, m, args.roofline_reps) if args.ortho == "cgsr" else None
-    mem_mixed = solver.memory_bytes()
+
+    def mode(ortho, precision, steps, warmup, **kw):
+        t, inf, (s, x) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, ortho, precision, steps, warmup,
+                                          **kw)
+        out, xs = _summary(t, inf, s, x, pr, b_dev, np)
+        return out, xs, s
+
+    mixed, x_mix, solver = mode(args.ortho, args.precision, args.steps, args.warmup)
+    value = mixed["seconds_mean"]
+    log("in-solve kernel profile (one more solve, every launch between HIP events) ...")
+    _, pinfo, fam = in_solve_profile(solver, b_dev)
+    rf = roofline_from_profile(solver, fam, m, args.roofline_reps)
+    log(f"  dominant family {rf['family']}: {rf['avg_launch_ms'] * 1e3:.1f} us per launch, "
+        f"{rf['achieved']:.0f} GB/s ({rf['frac']:.3f} of peak); harness "
+        f"{(rf['harness_back_to_back'] or {}).get('avg_launch_ms', 0) * 1e3:.1f} us at j = {m - 1}")
     solver.close()
-    out_fp64 = None
+    out_fp64, x64 = None, None
     if not args.no_fp64:
-        t64, i64, (s64, _) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, "fp64",
-                                              args.steps, max(0, min(args.warmup, 1)))
-        out_fp64 = {"seconds": statistics.mean(t64), "median": statistics.median(t64), "iters": i64[-1]["iters"],
-                    "restarts": i64[-1]["restarts"], "rel_residual": i64[-1]["rel_residual"],
-                    "memory_bytes": s64.memory_bytes()}
+        out_fp64, x64, s64 = mode(args.ortho, "fp64", args.steps, max(0, min(args.warmup, 1)))
         s64.close()
+    # the error of each mode against the float64 solution, next to its iterations
+    if x64 is not None:
+        mixed["error_vs_fp64_solution"] = float(np.linalg.norm(x_mix - x64) / np.linalg.norm(x64))
     # split storage of A (high and low words; the Arnoldi product reads the
     # high words): the same solve without the float32 copy of the matrix
     log("split storage of A ...")
-    t_sp, i_sp, (s_sp, x_sp) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, args.precision,
-                                                args.steps, min(args.warmup, 1), a_storage="split")
-    out_split = {"seconds_mean": statistics.mean(t_sp), "seconds_median": statistics.median(t_sp),
-                 "solve_seconds": i_sp[-1]["seconds"], "iters": i_sp[-1]["iters"],
-                 "restarts": i_sp[-1]["restarts"], "rel_residual": i_sp[-1]["rel_residual"],
-                 "forward_error": float(np.linalg.norm(x_sp.cpu().numpy() - pr.x_true) / np.linalg.norm(pr.x_true)),
-                 "memory_bytes": s_sp.memory_bytes()}
-    s_sp.close()
+    out_split, xs_, s_ = mode(args.ortho, args.precision, args.steps, min(args.warmup, 1), a_storage="split")
+    s_.close()
     # the limited mixed solver of the convergence study: float32 storage of
     # the Arnoldi copy of A and of the basis only, w and its dots float64
     log("limited mixed precision ...")
-    t_li, i_li, (s_li, x_li) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, "limited",
-                                                args.steps, min(args.warmup, 1))
-    out_limited = {"seconds_mean": statistics.mean(t_li), "seconds_median": statistics.median(t_li),
-                   "solve_seconds": i_li[-1]["seconds"], "iters": i_li[-1]["iters"],
-                   "restarts": i_li[-1]["restarts"], "rel_residual": i_li[-1]["rel_residual"],
-                   "forward_error": float(np.linalg.norm(x_li.cpu().numpy() - pr.x_true)
-                                          / np.linalg.norm(pr.x_true)),
-                   "memory_bytes": s_li.memory_bytes()}
-    s_li.close()
+    out_limited, xl_, s_ = mode(args.ortho, "limited", args.steps, min(args.warmup, 1))
+    s_.close()
     # the 2-byte basis (IEEE half plus a power-of-two scale per vector) on the same system
-    out_half = None
+    out_half, xh_ = None, None
     if args.precision == "fp32":
         log("half-precision basis ...")
-        t_h, i_h, (s_h, x_h) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, args.ortho, "fp16",
-                                                  args.steps, min(args.warmup, 1))
-        out_half = {"seconds_mean": statistics.mean(t_h), "seconds_median": statistics.median(t_h),
-                    "solve_seconds": i_h[-1]["seconds"], "iters": i_h[-1]["iters"],
-                    "restarts": i_h[-1]["restarts"], "rel_residual": i_h[-1]["rel_residual"],
-                    "forward_error": float(np.linalg.norm(x_h.cpu().numpy() - pr.x_true)
-                                           / np.linalg.norm(pr.x_true)),
-                    "memory_bytes": s_h.memory_bytes()}
-        s_h.close()
-    value = statistics.mean(t_mix)
+        out_half, xh_, s_ = mode(args.ortho, "fp16", args.steps, min(args.warmup, 1))
+        s_.close()
+    if x64 is not None:
+        for o, xo in ((out_split, xs_), (out_limited, xl_), (out_half, xh_)):
+            if o is not None:
+                o["error_vs_fp64_solution"] = float(np.linalg.norm(xo - x64) / np.linalg.norm(x64))
+    # MGS, the other orthogonalisation the configuration names: mixed and
+    # float64, and the MGS step kernel's in-solve bandwidth
+    out_mgs = None
+    if args.ortho == "cgsr" and args.mgs_steps > 0:
+        log("MGS ...")
+        mg, xm, sm = mode("mgs", args.precision, args.mgs_steps, min(args.warmup, 1))
+        _, _, fam_m = in_solve_profile(sm, b_dev)
+        rf_m = roofline_from_profile(sm, fam_m, m, args.roofline_reps, families=("mgs",))
+        rf_m.pop("in_solve_families")
+        sm.close()
+        out_mgs = {"mixed": mg, "roofline_mgs_step": rf_m, "in_solve_families": fam_m}
+        if not args.no_fp64:
+            m64, xm64, sm64 = mode("mgs", "fp64", args.mgs_steps, min(args.warmup, 1))
+            sm64.close()
+            out_mgs["fp64"] = m64
+            out_mgs["speedup_vs_fp64"] = round(m64["seconds_mean"] / mg["seconds_mean"], 3)
+            mg["error_vs_fp64_solution"] = float(np.linalg.norm(xm - xm64) / np.linalg.norm(xm64))
     rec = {
         "metric": METRIC,
         "value": round(value, 6),
@@ -283,28 +365,111 @@ def bench_convdiff3d(args):
                         f"tol 1e-10, time incl. setup",
             "n": A.n, "nnz": A.nnz, "m": m, "ortho": args.ortho, "precision": args.precision,
         },
-        "mixed": {"seconds_mean": value, "seconds_median": statistics.median(t_mix),
-                  "seconds_min": min(t_mix), "seconds_max": max(t_mix),
-                  "solve_seconds": i_mix[-1]["seconds"], "setup_seconds": i_mix[-1]["setup_seconds"],
-                  "iters": i_mix[-1]["iters"], "restarts": i_mix[-1]["restarts"],
-                  "rel_residual": i_mix[-1]["rel_residual"], "forward_error": fwd,
-                  "memory_bytes": mem_mixed},
+        "mixed": mixed,
         "fp64": out_fp64,
         "split_storage": out_split,
         "limited": out_limited,
         "half_basis": out_half,
-        "speedup_vs_fp64": (round(out_fp64["seconds"] / value, 3) if out_fp64 else None),
+        "mgs": out_mgs,
+        "speedup_vs_fp64": (round(out_fp64["seconds_mean"] / value, 3) if out_fp64 else None),
         "paper_context": "paper (2x10-core Haswell, Kokkos/MKL, ILU(0), SuiteSparse): mixed vs FP64 "
                          "geo-mean speedup +19% (MGS), +24% (CGSR) when restarted at least once",
         "roofline": rf,
+        "profiled_solve": {"iters": pinfo["iters"], "restarts": pinfo["restarts"], "status": pinfo["status"],
+                           "seconds": pinfo["seconds"]},
     }
     if not args.no_cpu:
-        iters_ref = out_fp64["iters"] if out_fp64 else i_mix[-1]["iters"]
+        ref = out_fp64 or mixed
         log("CPU oracle sample ...")
-        rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, iters_ref, args.cpu_iters)
+        rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, ref["iters"], ref["restarts"], args.cpu_cycles,
+                                           full=args.cpu_full)
     else:
         rec["cpu_baseline"] = None
+    del A_dev, b_dev
+    torch.cuda.empty_cache()
+    legs = [] if args.legs in ("", "none") else args.legs.split(",")
+    for leg in legs:
+        log(f"leg {leg} ...")
+        if leg == "c3":
+            rec["powerlaw"] = leg_powerlaw(args)
+        elif leg == "c4":
+            rec["batch"] = leg_batch(args)
+        elif leg == "c5":
+            rec["learned"] = leg_learned(args)
+        else:
+            raise SystemExit(f"unknown leg {leg}")
     return rec
+
+
+def leg_powerlaw(args):
+    """C3 in brief: one time-to-solution per basis format (after one untimed fp16 solve)."""
+    import numpy as np
+    import torch
+
+    import problems as P
+    from paper_2011_01850_amd import Solver
+
+    m, stall = 30, 1000
+    pr = P.c3_powerlaw()
+    A = pr.A
+    A_dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
+    b_dev = torch.as_tensor(pr.b, device="cuda")
+    out = {"workload": f"power-law random sparse n={A.n}, nnz={A.nnz}, GMRES({m}) CGSR, tol 1e-10, "
+                       f"one time-to-solution per mode incl. setup", "modes": {}}
+    for k, mode in enumerate(["fp64", "fp32", "fp16", "bf16"]):
+        t, inf, (s, x) = time_to_solution(torch, Solver, A_dev, b_dev, A.n, m, "cgsr", mode, 1,
+                                          1 if k == 0 else 0, stall_cycles=stall)
+        o, _ = _summary(t, inf, s, x, pr, b_dev, np)
+        if mode in ("fp32", "fp16"):
+            _, _, fam = in_solve_profile(s, b_dev)
+            o["spmv_in_solve"] = fam.get("spmv")
+        s.close()
+        out["modes"][mode] = o
+    for mode, o in out["modes"].items():
+        o["speedup_vs_fp64"] = round(out["modes"]["fp64"]["seconds_mean"] / o["seconds_mean"], 3)
+    return out
+
+
+def leg_batch(args):
+    """C4 in brief: the 512-system batch, one untimed and one timed solve (create + solve)."""
+    import numpy as np
+    import torch
+
+    import problems as P
+    from paper_2011_01850_amd import BatchSolver
+
+    m = 40
+    probs = P.c4_batch()
+    systems = [tuple(torch.as_tensor(v, device="cuda") for v in (p.A.row_ptr, p.A.col_idx, p.A.vals))
+               for p in probs]
+    bs = [torch.as_tensor(p.b, device="cuda") for p in probs]
+    ns = [p.A.n for p in probs]
+    nnzs = [p.A.nnz for p in probs]
+    times, infos, tune = [], None, None
+    for it in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bsol = BatchSolver(systems, m=m, tol=1e-10, ortho="mgs", precision="fp32", max_iters=100_000)
+        xs, infos = bsol.solve(bs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tune = bsol.tuning() if hasattr(bsol, "tuning") else None
+        bsol.close()
+        if it > 0:
+            times.append(dt)
+    alg = sum(batch_alg_bytes(n, z, i["iters"], i["restarts"], m) for n, z, i in zip(ns, nnzs, infos))
+    iters = [i["iters"] for i in infos]
+    v = times[0]
+    fwd = max(float(np.linalg.norm(x.cpu().numpy() - p.x_true) / np.linalg.norm(p.x_true))
+              for x, p in zip(xs, probs))
+    return {"workload": f"{len(probs)} 2-D convection-diffusion systems (sum n={sum(ns)}), GMRES({m}) MGS "
+                        f"float32 Arnoldi, one persistent launch, create + solve timed",
+            "systems_per_s": round(len(probs) / v, 2), "seconds": v,
+            "iterations": {"min": min(iters), "median": float(np.median(iters)), "max": max(iters)},
+            "converged": sum(i["status"] == "CONVERGED" for i in infos),
+            "max_rel_residual": max(i["rel_residual"] for i in infos), "max_forward_error": fwd,
+            "effective_GBps": round(alg / v / 1e9, 1), "frac_of_peak": round(alg / v / 1e9 / PEAK_HBM_GBS, 4),
+            "tuning": tune}
 
 
 def _mode_summary(times, infos, fwd, mem):
@@ -346,16 +511,15 @@ def bench_powerlaw(args):
         xs = x.cpu().numpy()
         fwd = float(np.linalg.norm(xs - pr.x_true) / np.linalg.norm(pr.x_true))
         modes[mode] = _mode_summary(t, inf, fwd, s.memory_bytes())
-        ks = {}
-        for k, name in [(0, "spmv_arnoldi"), (1, "cgs_pass1"), (2, "cgs_pass2"), (3, "final_pass")]:
-            ms, by = s.time_kernel(k, m - 1, args.roofline_reps)
-            ks[name] = {"ms": round(ms, 5), "alg_bytes": by, "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
-        kern[mode] = ks
+        modes[mode]["backward_error"] = s.backward_error(b_dev, x)[0]
+        _, _, fam = in_solve_profile(s, b_dev)
+        kern[mode] = {"in_solve_families": fam,
+                      "spmv_roofline": roofline_from_profile(s, fam, m, args.roofline_reps, families=("spmv",))}
+        kern[mode]["spmv_roofline"].pop("in_solve_families")
         s.close()
     for mode in modes:
         modes[mode]["speedup_vs_fp64"] = round(modes["fp64"]["seconds_mean"] / modes[mode]["seconds_mean"], 3)
     v = modes[value_mode]["seconds_mean"]
-    sp = kern[value_mode]["spmv_arnoldi"]
     rec = {
         "metric": METRIC, "value": round(v, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(v * 1e3, 3), "higher_is_better": False, "scaling": "weak",
@@ -367,15 +531,13 @@ def bench_powerlaw(args):
                                f"stall stop after {stall} cycles without a new lowest residual",
                    "n": A.n, "nnz": A.nnz, "m": m, "ortho": args.ortho, "precision": value_mode},
         "modes": modes,
-        "kernels_at_j_last": kern,
-        "roofline": {"bound": "hbm", "kernel": f"k_spmv (Arnoldi SpMV, float32 A, {value_mode} x)",
-                     "achieved": sp["GB/s"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(sp["GB/s"] / PEAK_HBM_GBS, 4), "traffic": None,
-                     "avg_launch_ms": sp["ms"], "alg_bytes_per_launch": sp["alg_bytes"]},
+        "kernels_in_solve": kern,
+        "roofline": kern[value_mode]["spmv_roofline"],
     }
     if not args.no_cpu:
         log("CPU oracle sample ...")
-        rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, modes["fp64"]["iters"], args.cpu_iters)
+        rec["cpu_baseline"] = cpu_baseline(pr, m, args.ortho, modes["fp64"]["iters"], modes["fp64"]["restarts"],
+                                           args.cpu_cycles, full=args.cpu_full)
     else:
         rec["cpu_baseline"] = None
     return rec
@@ -597,51 +759,78 @@ def bench_batch(args):
     return rec
 
 
-def _gen_varcoef(job):
-    """Values and right-hand side of one variable-coefficient instance (host worker)."""
-    i, N = job
-    import problems as P
-
-    pr = P.c5_varcoef(i, N=N)
-    return pr.A.vals, pr.b
-
-
-def _varcoef_stream(ids, N, pool):
-    """(A, b) in order of ids, generated by the worker pool; the pattern is shared."""
+def _varcoef_stream(ids, N, workers=None, window=32):
+    """(A, b) in order of ids, generated by host threads (the generator's NumPy
+    work releases the GIL), at most `window` instances in flight; the pattern
+    is shared."""
+    from collections import deque
+    from concurrent.futures import ThreadPoolExecutor
     from types import SimpleNamespace
 
     import problems as P
 
+    workers = workers or max(1, min(8, len(os.sched_getaffinity(0)) - 1))
     pat = P.varcoef3d(N, 5, ids[0])
-    for vals, b in pool.imap(_gen_varcoef, [(i, N) for i in ids], chunksize=4):
-        yield SimpleNamespace(n=pat.n, nnz=pat.nnz, row_ptr=pat.row_ptr, col_idx=pat.col_idx, vals=vals), b
+
+    def gen(i):
+        pr = P.c5_varcoef(i, N=N)
+        return pr.A.vals, pr.b
+
+    with ThreadPoolExecutor(workers) as ex:
+        pending = deque()
+        it = iter(ids)
+        for i in it:
+            pending.append(ex.submit(gen, i))
+            if len(pending) >= window:
+                break
+        while pending:
+            vals, b = pending.popleft().result()
+            nxt = next(it, None)
+            if nxt is not None:
+                pending.append(ex.submit(gen, nxt))
+            yield SimpleNamespace(n=pat.n, nnz=pat.nnz, row_ptr=pat.row_ptr, col_idx=pat.col_idx, vals=vals), b
 
 
-def bench_learned(args, pool):
+def leg_learned(args):
+    """C5 in brief: train on the GPU, then FGMRES on held-out instances
+    (learned, Jacobi, ILU(0)); none and float64 on the first few."""
+    res = learned_run(args.c5_train, args.c5_test, 5, args.epochs, args.learned_N)
+    keep = ("held_out_all", "held_out_baseline_subset", "speedup_learned_vs_fp64", "speedup_learned_vs_jacobi",
+            "speedup_learned_vs_ilu0", "iteration_gain_vs_none", "iteration_gain_vs_jacobi", "training")
+    out = {k: res[k] for k in keep}
+    out["workload"] = res["config"]["workload"]
+    return out
+
+
+def bench_learned(args):
     """Train the SPAI network on GPU-generated residual pairs, then time FGMRES(30) to 1e-10 on held-out
     instances: learned vs Jacobi (float32 Arnoldi), and plain float32 / float64 GMRES on a subset."""
+    return learned_run(args.train_instances, args.test_instances, args.baseline_instances, args.epochs,
+                       args.learned_N)
+
+
+def learned_run(n_train, n_test, n_baseline, epochs, N):
     import numpy as np
     import torch
 
     from paper_2011_01850_amd import train as T
 
-    N = args.learned_N
     m = 30
-    train_ids = list(range(args.train_instances))
-    test_ids = list(range(2000, 2000 + args.test_instances))
+    train_ids = list(range(n_train))
+    test_ids = list(range(2000, 2000 + n_test))
     log(f"training data: {len(train_ids)} instances of the 3-D variable-coefficient family, N = {N} ...")
-    data = T.prepare(_varcoef_stream(train_ids, N, pool), K=4, m=m, log=log)
-    log(f"  data ready in {data.seconds:.1f} s; training {args.epochs} epochs")
-    res = T.train_on(data, epochs=args.epochs, lr=1e-3, batch=4, seed=0, log=log)
+    data = T.prepare(_varcoef_stream(train_ids, N), K=4, m=m, log=log)
+    log(f"  data ready in {data.seconds:.1f} s; training {epochs} epochs")
+    res = T.train_on(data, epochs=epochs, lr=1e-3, batch=4, seed=0, log=log)
     del data
     torch.cuda.empty_cache()
     log(f"  loss {res['loss_first']:.4f} (Jacobi start) -> {res['loss_last']:.4f} in {res['seconds_train']:.1f} s")
     from paper_2011_01850_amd import spai as S
 
     rows = []
-    nb = min(args.baseline_instances, len(test_ids))
+    nb = min(n_baseline, len(test_ids))
     net, t_net = None, None
-    for q, (A, b) in enumerate(_varcoef_stream(test_ids, N, pool)):
+    for q, (A, b) in enumerate(_varcoef_stream(test_ids, N)):
         dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
         bt = torch.as_tensor(b, device="cuda")
         if net is None:  # one network instance for the family's pattern, built once
@@ -690,6 +879,7 @@ def bench_learned(args, pool):
         "speedup_learned_vs_jacobi": round(kinds_all["jacobi"]["seconds_mean"] / v, 3),
         "speedup_learned_vs_ilu0": round(kinds_all["ilu0"]["seconds_mean"] / v, 3),
         "iteration_gain_vs_none": round(kinds_sub["none"]["iters_mean"] / kinds_sub["learned"]["iters_mean"], 3),
+        "iteration_gain_vs_jacobi": round(kinds_all["jacobi"]["iters_mean"] / kinds_all["learned"]["iters_mean"], 3),
         "learned_one_off": {"network_instance_seconds": t_net,
                             "first_instance_seconds_own_instance": rows[0]["learned_own_instance"]["seconds_total"],
                             "first_instance_seconds_shared_instance": rows[0]["learned"]["seconds_total"]},
@@ -707,24 +897,13 @@ def main():
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU row partitioning is described in the design notes only)", file=sys.stderr)
         sys.exit(2)
-    pool = None
-    if args.workload == "learned":
-        # host workers for the instance generator, started before the GPU is touched
-        import multiprocessing as mp
-
-        workers = max(1, min(16, len(os.sched_getaffinity(0)) - 1))
-        pool = mp.get_context("spawn").Pool(workers)
     import torch
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if pool is not None:
-        with pool:
-            rec = bench_learned(args, pool)
-    else:
-        rec = {"convdiff3d": bench_convdiff3d, "powerlaw": bench_powerlaw,
-               "batch": bench_batch, "restart": bench_restart, "variables": bench_variables}[args.workload](args)
+    rec = {"convdiff3d": bench_convdiff3d, "powerlaw": bench_powerlaw, "learned": bench_learned,
+           "batch": bench_batch, "restart": bench_restart, "variables": bench_variables}[args.workload](args)
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -79,11 +79,19 @@ enum { GMRES_A_COPY = 0, GMRES_A_SPLIT = 1 };
 /* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y).
  * ILU0: incomplete LU without fill (the preconditioner of the paper's
  * experiments), factored on the GPU in float64 at create time (rows in
- * dependency levels; every row must store its diagonal) and applied in
- * float32 as z = U^-1 L^-1 v by ilu_sweeps Jacobi sweeps per triangle from a
- * zero start, or exactly (ilu_sweeps = 0: as many sweeps as the triangle has
+ * dependency levels; every row must store its diagonal) and applied as
+ * z = U^-1 L^-1 v by ilu_sweeps Jacobi sweeps per triangle from a zero
+ * start, or exactly (ilu_sweeps = 0: as many sweeps as the triangle has
  * levels).  The paper applies ILU(0) on the left; here it is applied on the
- * right, so GMRES keeps minimising the true residual. */
+ * right, so GMRES keeps minimising the true residual.
+ * Precision (Algorithm 1's M^-1 and the paper's split of Section 4.2): the
+ * mixed modes store and apply the preconditioner in float32 and keep Z in
+ * float32.  GMRES_FP64 keeps Z in float64 and applies the preconditioner in
+ * float64 (Jacobi d^-1, the ILU factors and sweeps), or, with
+ * precond_precision = GMRES_PRECOND_FP32, in float32 (the paper's "FP32
+ * ILU only" solver: v_j rounded to float32, float32 factors and sweeps, the
+ * result widened to float64).  The learned M (float32 values) is summed in
+ * the precision of Z. */
 enum { GMRES_PRECOND_NONE = 0, GMRES_PRECOND_JACOBI = 1, GMRES_PRECOND_SPAI = 2, GMRES_PRECOND_ILU0 = 3 };
 
 /* gmres_options.batch_schedule.
@@ -166,7 +174,11 @@ typedef struct {
   int32_t orth_norm;
   int32_t ilu_sweeps;       /* GMRES_PRECOND_ILU0: Jacobi sweeps per triangle (0 = exact), 0..4096 */
   int32_t arnoldi_a;        /* GMRES_ARNOLDI_A_*: which values of A the Arnoldi product reads */
+  int32_t precond_precision; /* GMRES_PRECOND_NATIVE (the solver's precision) or GMRES_PRECOND_FP32
+                                (a float32 preconditioner in the float64 solver) */
 } gmres_options;
+
+enum { GMRES_PRECOND_NATIVE = 0, GMRES_PRECOND_FP32 = 1 };
 
 enum { GMRES_ORTH_SPECTRAL = 0, GMRES_ORTH_FROBENIUS = 1 };
 
@@ -198,7 +210,7 @@ typedef struct {
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
  * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4,
- * arnoldi_a = DEFAULT. */
+ * arnoldi_a = DEFAULT, precond_precision = NATIVE. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).
@@ -257,6 +269,24 @@ const char* gmres_strerror(int code);
  * float64[n] device.  Single-system handles only (ESTATE on a batch handle). */
 int gmres_residual(gmres_handle h, const double* b, const double* x, double* r, double* norm_out);
 
+/* The stopping metric of the paper's experiments (Section 4.2): the
+ * normwise backward error eta = ||b - A x||_2 / (||A|| ||x||_2 + ||b||_2),
+ * with the Frobenius norm ||A||_F standing in for ||A||_2 (which it bounds
+ * from above, so eta is at most sqrt(n) times too small), all in float64
+ * with the stored A.  *eta and *rel_residual (= ||b - A x||_2 / ||b||_2)
+ * are host outputs, either may be NULL.  b, x: float64[n] device.
+ * Single-system handles only (ESTATE on a batch handle). */
+int gmres_backward_error(gmres_handle h, const double* b, const double* x, double* eta, double* rel_residual);
+
+/* The unit restart residual of Algorithm 1 in float32: r_out = float32(z /
+ * ||z||_2) with z = b - A x computed in float64 (the first basis vector of
+ * a cycle before its storage format is applied), and *norm_out = ||z||_2
+ * (host, may be NULL).  Used to collect the residuals the learned
+ * preconditioner trains on.  b, x: float64[n] device; r_out: float32[n]
+ * device.  EINVAL when ||z|| is 0 or not finite (r_out untouched).
+ * Single-system handles only. */
+int gmres_residual_unit(gmres_handle h, const double* b, const double* x, float* r_out, double* norm_out);
+
 /* y = A x with the stored float64 values (precision = GMRES_FP64, x and y
  * float64) or the float32 values of the Arnoldi product (GMRES_MIXED_FP32,
  * float32 x, y: the float32 copy, or the high words under SPLIT storage;
@@ -267,10 +297,15 @@ int gmres_spmv(gmres_handle h, int32_t precision, const void* x, void* y);
 
 /* z = M^-1 v for a single-system handle created with
  * precond = GMRES_PRECOND_ILU0: the ILU(0) application of the Arnoldi loop
- * (float32 sweeps as configured by ilu_sweeps).  v and z are float32[n]
- * device arrays.  Errors: EINVAL (null pointer), ESTATE (another
- * preconditioner, or several systems). */
+ * (sweeps as configured by ilu_sweeps).  gmres_precond_apply: v and z are
+ * float32[n] device arrays, for handles whose preconditioner computes in
+ * float32 (the mixed modes; GMRES_FP64 with GMRES_PRECOND_FP32, whose z is
+ * then float32 before widening).  gmres_precond_apply_f64: float64[n], for
+ * GMRES_FP64 handles with a float64 preconditioner.  Errors: EINVAL (null
+ * pointer), ESTATE (another preconditioner, the other precision, or
+ * several systems). */
 int gmres_precond_apply(gmres_handle h, const float* v, float* z);
+int gmres_precond_apply_f64(gmres_handle h, const double* v, double* z);
 
 /* Store v = w * inv_h in a 2-byte format (precision GMRES_MIXED_BF16 or
  * GMRES_MIXED_FP16) exactly as the solver stores a basis vector: with
@@ -328,6 +363,55 @@ int gmres_memory_bytes(gmres_handle h, size_t* bytes);
 int gmres_time_kernel(gmres_handle h, int32_t kernel, int32_t j, int32_t reps, double* avg_ms,
                       double* bytes);
 /* (ESTATE on a handle that runs the persistent batch schedule.) */
+
+/* In-solve kernel profile (measurement of Algorithm 1's steps inside a real
+ * solve).  gmres_solve_profiled runs the same solve as gmres_solve, the same
+ * kernels in the same order with the same launch configurations (so x, the
+ * iteration count and the history are bitwise those of gmres_solve), but
+ * launches every kernel directly instead of through the per-cycle graph and
+ * brackets each group of launches with a pair of HIP events on the handle's
+ * stream.  prof (HOST, GMRES_PK_COUNT entries) receives per kernel family:
+ * the summed event-timed durations of all its launches (ms, launches) and
+ * of the launches that did work (ms_active, active: a step j >= k of a
+ * cycle that ended after k steps is gated off on the device and returns at
+ * once), and the algorithmic bytes the active launches move (the formulas
+ * of the design notes: e.g. projection 1 at column j reads j+1 basis
+ * columns and w).  Single-system handles on the device-wide schedule only
+ * (ESTATE otherwise).  Families: */
+enum {
+  GMRES_PK_SPMV = 0,      /* Arnoldi product w = A v_j (or A z_j) */
+  GMRES_PK_PASS1 = 1,     /* CGSR projection 1: V^T w */
+  GMRES_PK_PASS2 = 2,     /* CGSR projection 2: w -= V h1, then V^T w */
+  GMRES_PK_FINAL = 3,     /* last pass of a step: w -= V h2 (CGSR) or the last MGS axpy; ||w||, v_{j+1} */
+  GMRES_PK_MGS = 4,       /* one MGS step h_ij = w . v_i, w -= h_ij v_i */
+  GMRES_PK_RESIDUAL = 5,  /* float64 restart residual z = b - A x */
+  GMRES_PK_UPDATE = 6,    /* float64 update x += V y (Z y) */
+  GMRES_PK_REDUCE = 7,    /* per-system reductions, Givens step, back-solve (latency-bound) */
+  GMRES_PK_PRECOND = 8,   /* z_j = M v_j */
+  GMRES_PK_ENCODE = 9,    /* 2-byte encoding of a basis vector; orthogonality monitor */
+  GMRES_PK_COUNT = 10
+};
+typedef struct {
+  double ms;          /* all launches */
+  double ms_active;   /* launches that did work */
+  double bytes;       /* algorithmic bytes of the launches that did work */
+  int64_t launches;
+  int64_t active;
+} gmres_kernel_profile;
+int gmres_solve_profiled(gmres_handle h, const double* b, double* x, gmres_result* res,
+                         gmres_kernel_profile* prof);
+
+/* Launch configuration the solver uses for kernel family `family`
+ * (GMRES_PK_SPMV .. GMRES_PK_UPDATE) at Arnoldi column j (0 <= j < m), for
+ * the measurement report: *grid workgroups of *block threads; *per_cu = the
+ * resident workgroups per compute unit the persistent basis passes size
+ * their grid for (grid = per_cu x compute units, capped at the row tiles),
+ * 0 for kernels with one workgroup per row block or tile; *basis_align =
+ * the largest power of two (up to 2 MiB) dividing the basis allocation's
+ * device address.  Any output may be NULL.  ESTATE on the persistent batch
+ * schedule. */
+int gmres_launch_config(gmres_handle h, int32_t family, int32_t j, int32_t* grid, int32_t* block,
+                        int32_t* per_cu, int64_t* basis_align);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,8 @@ ORTH_SPECTRAL, ORTH_FROBENIUS = 0, 1
 ORTH_NORMS = {"spectral": ORTH_SPECTRAL, "frobenius": ORTH_FROBENIUS}
 ARNOLDI_A_DEFAULT, ARNOLDI_A_FP64, ARNOLDI_A_FP32 = 0, 1, 2
 ARNOLDI_AS = {"default": ARNOLDI_A_DEFAULT, "fp64": ARNOLDI_A_FP64, "fp32": ARNOLDI_A_FP32}
+PRECOND_NATIVE, PRECOND_FP32 = 0, 1
+PRECOND_PRECISIONS = {"native": PRECOND_NATIVE, "fp32": PRECOND_FP32}
 
 
 class Options(C.Structure):
@@ -49,6 +51,7 @@ class Options(C.Structure):
         ("orth_norm", C.c_int32),
         ("ilu_sweeps", C.c_int32),
         ("arnoldi_a", C.c_int32),
+        ("precond_precision", C.c_int32),
     ]
 
 
@@ -75,6 +78,19 @@ class Result(C.Structure):
         }
 
 
+class KernelProfile(C.Structure):
+    _fields_ = [
+        ("ms", C.c_double),
+        ("ms_active", C.c_double),
+        ("bytes", C.c_double),
+        ("launches", C.c_int64),
+        ("active", C.c_int64),
+    ]
+
+
+# kernel families of gmres_solve_profiled (GMRES_PK_* in gmres.h)
+PROFILE_KINDS = ["spmv", "pass1", "pass2", "final", "mgs", "residual", "update", "reduce", "precond", "encode"]
+
 _vp = C.c_void_p
 _SIGS = {
     "gmres_default_options": (None, [C.POINTER(Options)]),
@@ -87,8 +103,11 @@ _SIGS = {
     "gmres_batch_solve": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(Result)]),
     "gmres_destroy": (C.c_int, [_vp]),
     "gmres_residual": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
+    "gmres_backward_error": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "gmres_residual_unit": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
     "gmres_spmv": (C.c_int, [_vp, C.c_int32, _vp, _vp]),
     "gmres_precond_apply": (C.c_int, [_vp, _vp, _vp]),
+    "gmres_precond_apply_f64": (C.c_int, [_vp, _vp, _vp]),
     "gmres_encode": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_double, _vp, C.POINTER(C.c_double), _vp]),
     "gmres_encode_noalloc": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_double, _vp, C.POINTER(C.c_double), _vp]),
     "gmres_last_cycle": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _vp, _vp]),
@@ -96,6 +115,9 @@ _SIGS = {
     "gmres_memory_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "gmres_time_kernel": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
+    "gmres_solve_profiled": (C.c_int, [_vp, _vp, _vp, C.POINTER(Result), C.POINTER(KernelProfile)]),
+    "gmres_launch_config": (C.c_int, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "gmres_spai_infer": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "spai_create": (C.c_int, [C.POINTER(_vp), C.c_int64, C.c_int64, _vp, _vp, C.c_int32, _vp]),
     "spai_set_values": (C.c_int, [_vp, _vp]),

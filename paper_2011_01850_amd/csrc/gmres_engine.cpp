@@ -90,6 +90,10 @@ struct gmres_ctx {
   // SPLIT storage: the float64 values reassembled for the network inputs
   // (allocated on the first inference)
   double* a64_merged = nullptr;
+  // sums of squares: kSumsqBlocks partials (allocated on first use); ||A||_F
+  // once computed (negative until then)
+  double* sq_part = nullptr;
+  double afro = -1.0;
 
   template <typename T>
   T* alloc(size_t count) {
@@ -159,7 +163,7 @@ bool valid_options(const gmres_options* o) {
   if (o->precond < GMRES_PRECOND_NONE || o->precond > GMRES_PRECOND_ILU0) return false;
   if (o->ilu_sweeps < 0 || o->ilu_sweeps > 4096) return false;
   if (o->arnoldi_a < GMRES_ARNOLDI_A_DEFAULT || o->arnoldi_a > GMRES_ARNOLDI_A_FP32) return false;
-  if (o->precond != GMRES_PRECOND_NONE && o->precision == GMRES_FP64) return false;
+  if (o->precond_precision != GMRES_PRECOND_NATIVE && o->precond_precision != GMRES_PRECOND_FP32) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
@@ -456,6 +460,87 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
   return e;
 }
 
+// In-solve kernel profile: the launches of one cycle in the order
+// enqueue_cycle issues them, each group between two HIP events on the
+// handle's stream.  A group records its family, its Arnoldi column (-1 for
+// the launches of the cycle's start and end) and the algorithmic bytes it
+// moves when it does work; whether it did work is only known once the cycle
+// has ended (steps j >= k of a cycle that ended early are gated off on the
+// device).
+struct ProfRec {
+  int kind;
+  int j;        // Arnoldi column, -1: residual / encode of v_1, -2: back-solve / update
+  double bytes;
+  hipEvent_t e0, e1;
+};
+
+struct ProfPool {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == ev.size()) {
+      hipEvent_t e = nullptr;
+      hip_check(hipEventCreate(&e));
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+  ~ProfPool() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+void enqueue_cycle_profiled(gmres_ctx* h, hipStream_t st, ProfPool& pool, std::vector<ProfRec>& recs) {
+  const KArgs& a = h->a;
+  const bool two = a.prec == PBF16 || a.prec == PF16;
+  const double n = (double)h->nrows, nnz = (double)h->nnz;
+  const double sv = (double)vbytes(a.prec), sw = (double)wbytes(a.prec), sa = a.arn64 ? 8.0 : 4.0;
+  auto timed = [&](int kind, int j, double bytes, auto&& launch) {
+    ProfRec r{kind, j, bytes, pool.get(), pool.get()};
+    hip_check(hipEventRecord(r.e0, st));
+    hip_check(launch());
+    hip_check(hipEventRecord(r.e1, st));
+    recs.push_back(r);
+  };
+  timed(GMRES_PK_RESIDUAL, -1, nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * sw,
+        [&] { return launch_residual(a, st, false); });
+  timed(GMRES_PK_REDUCE, -1, 0.0, [&] { return launch_residual_finish(a, st); });
+  timed(GMRES_PK_ENCODE, -1, n * sw + n * sv, [&] { return launch_encode(a, 0, st); });
+  for (int j = 0; j < a.m; ++j) {
+    const double ncol = j + 1;
+    if (a.precond != 0) {
+      const double sz = a.z64 ? 8.0 : 4.0, sd = a.pc64 ? 8.0 : 4.0;
+      const double pb = a.precond == 1 ? n * sv + n * sd + n * sz
+                      : a.precond == 2 ? nnz * 8.0 + 4.0 * (n + 1) + n * sv + n * sz : 0.0;
+      timed(GMRES_PK_PRECOND, j, pb, [&] { return launch_precond(a, j, st); });
+    }
+    const double sx = a.precond != 0 ? (a.z64 ? 8.0 : 4.0) : sv;
+    timed(GMRES_PK_SPMV, j, nnz * (sa + 4.0) + 4.0 * (n + 1) + n * sx + n * sw,
+          [&] { return launch_spmv_arnoldi(a, j, st); });
+    if (h->opt.ortho == GMRES_CGSR) {
+      const double win = std::ceil(ncol / 64.0);
+      timed(GMRES_PK_PASS1, j, ncol * n * sv + win * n * sw, [&] { return launch_cgs_pass1(a, j, st, false); });
+      timed(GMRES_PK_REDUCE, j, 0.0, [&] { return launch_finalize_pass1(a, j, st); });
+      const double p2 = ncol <= 64 ? ncol * n * sv + 2.0 * n * sw : 2.0 * ncol * n * sv + 3.0 * win * n * sw;
+      timed(GMRES_PK_PASS2, j, p2, [&] { return launch_cgs_pass2(a, j, st, false); });
+      timed(GMRES_PK_REDUCE, j, 0.0, [&] { return launch_finalize_pass2(a, j, st); });
+    } else {
+      for (int i = 0; i <= j; ++i)
+        timed(GMRES_PK_MGS, j, i > 0 ? 2.0 * n * sv + 2.0 * n * sw : n * sv + n * sw,
+              [&] { return launch_mgs_dot(a, j, i, st); });
+    }
+    timed(GMRES_PK_FINAL, j,
+          (h->opt.ortho == GMRES_CGSR ? ncol * n * sv : n * sv) + n * sw + n * (two ? sw : sv),
+          [&] { return launch_final_pass(a, j, st, false); });
+    timed(GMRES_PK_REDUCE, j, 0.0, [&] { return launch_finalize_final(a, j, st); });
+    if (two && j + 1 <= a.m) timed(GMRES_PK_ENCODE, j, n * sw + n * sv, [&] { return launch_encode(a, j + 1, st); });
+    if (a.orth_restart > 0.0) timed(GMRES_PK_ENCODE, j, 0.0, [&] { return launch_orth_check(a, j, st); });
+  }
+  timed(GMRES_PK_REDUCE, -2, 0.0, [&] { return launch_backsolve(a, st); });
+  // the update reads k basis (or preconditioned) columns: its bytes are set once k is known
+  timed(GMRES_PK_UPDATE, -2, 16.0 * n, [&] { return launch_update(a, st); });
+}
+
 void build_graph(gmres_ctx* h) {
   if (h->gexec) return;
   hipGraph_t g = nullptr;
@@ -689,9 +774,14 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   hip_check(hipMemsetAsync(a.V, 0, (size_t)(M1 * h->ld * vbytes(prec)), h->stream));
   a.w = h->alloc<uint8_t>((size_t)(h->ld * wbytes(prec)));
   hip_check(hipMemsetAsync(a.w, 0, (size_t)(h->ld * wbytes(prec)), h->stream));
+  // the preconditioner's output Z is float64 in the float64 solver, and so is
+  // its arithmetic unless a float32 preconditioner was asked for
+  a.z64 = (opt->precond != GMRES_PRECOND_NONE && prec == P64) ? 1 : 0;
+  a.pc64 = (a.z64 && opt->precond_precision == GMRES_PRECOND_NATIVE) ? 1 : 0;
   if (opt->precond != GMRES_PRECOND_NONE) {
-    a.Z = h->alloc<float>((size_t)(m * h->ld));
-    hip_check(hipMemsetAsync(a.Z, 0, (size_t)(m * h->ld * 4), h->stream));
+    const size_t zb = a.z64 ? 8 : 4;
+    a.Z = h->alloc<uint8_t>((size_t)(m * h->ld) * zb);
+    hip_check(hipMemsetAsync(a.Z, 0, (size_t)(m * h->ld) * zb, h->stream));
   }
   a.x = h->alloc<double>(h->ld);
   a.b = h->alloc<double>(h->ld);
@@ -730,9 +820,15 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.stall_win = std::max(1, (int)std::ceil(0.05 * m));
   hip_check(hipHostMalloc((void**)&h->st_host, sizeof(SysState) * nsys, hipHostMallocDefault));
   if (opt->precond == GMRES_PRECOND_JACOBI) {
-    float* d = h->alloc<float>(h->ld);
-    hip_check(launch_jacobi_setup(a, d, h->stream));
-    a.dinv = d;
+    if (a.pc64) {
+      double* d = h->alloc<double>(h->ld);
+      hip_check(launch_jacobi_setup(a, nullptr, d, h->stream));
+      a.dinv64 = d;
+    } else {
+      float* d = h->alloc<float>(h->ld);
+      hip_check(launch_jacobi_setup(a, d, nullptr, h->stream));
+      a.dinv = d;
+    }
   }
   if (opt->precond == GMRES_PRECOND_SPAI) {
     float* d = h->alloc<float>(h->nnz + 4);
@@ -893,17 +989,26 @@ void setup_ilu0(gmres_ctx* h, int32_t sweeps) {
   }
   for (int l = 0; l < depth_l; ++l)
     hip_check(launch_ilu_factor(a, lu, d_order + count[l], count[l + 1] - count[l], h->stream));
-  float* lu32 = h->alloc<float>(h->nnz + 4);
-  float* dinv = h->alloc<float>(ld);
-  hip_check(launch_ilu_finish(a, lu, lu32, dinv, h->stream));
-  a.ilu32 = lu32;
-  a.iludinv = dinv;
-  a.ilu_v = h->alloc<float>(ld);
-  for (int k = 0; k < 3; ++k) {
-    a.ilu_b[k] = h->alloc<float>(ld);
-    hip_check(hipMemsetAsync(a.ilu_b[k], 0, ld * 4, h->stream));
+  // the factors the sweeps read: float64 as factored, or their float32 rounding
+  if (a.pc64) {
+    double* dinv = h->alloc<double>(ld);
+    hip_check(launch_ilu_finish(a, lu, nullptr, nullptr, dinv, h->stream));
+    a.ilu64 = lu;
+    a.iludinv64 = dinv;
+  } else {
+    float* lu32 = h->alloc<float>(h->nnz + 4);
+    float* dinv = h->alloc<float>(ld);
+    hip_check(launch_ilu_finish(a, lu, lu32, dinv, nullptr, h->stream));
+    a.ilu32 = lu32;
+    a.iludinv = dinv;
   }
-  hip_check(hipMemsetAsync(a.ilu_v, 0, ld * 4, h->stream));
+  const size_t eb = a.pc64 ? 8 : 4;
+  a.ilu_v = h->alloc<uint8_t>(ld * eb);
+  for (int k = 0; k < 3; ++k) {
+    a.ilu_b[k] = h->alloc<uint8_t>(ld * eb);
+    hip_check(hipMemsetAsync(a.ilu_b[k], 0, ld * eb, h->stream));
+  }
+  hip_check(hipMemsetAsync(a.ilu_v, 0, ld * eb, h->stream));
   a.ilu_sl = sweeps > 0 ? sweeps : std::max(1, depth_l);
   a.ilu_su = sweeps > 0 ? sweeps : std::max(1, depth_u);
   hip_check(hipStreamSynchronize(h->stream));
@@ -945,6 +1050,7 @@ void gmres_default_options(gmres_options* o) {
   o->orth_norm = GMRES_ORTH_SPECTRAL;
   o->ilu_sweeps = 4;
   o->arnoldi_a = GMRES_ARNOLDI_A_DEFAULT;
+  o->precond_precision = GMRES_PRECOND_NATIVE;
 }
 
 const char* gmres_strerror(int code) {
@@ -1178,21 +1284,113 @@ int gmres_residual(gmres_handle hh, const double* b, const double* x, double* r,
   }
 }
 
+namespace {
+
+// ||v||_2 of a device vector, float64: fixed-grid partials, summed on the host in order.
+double norm2(gmres_ctx* h, const double* v, int64_t n) {
+  if (!h->sq_part) h->sq_part = h->alloc<double>(kSumsqBlocks);
+  const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kSumsqBlocks, (n + kBlock - 1) / kBlock));
+  hip_check(launch_sumsq(v, n, h->sq_part, nblk, h->stream));
+  std::vector<double> part(nblk);
+  hip_check(hipMemcpyAsync(part.data(), h->sq_part, nblk * 8, hipMemcpyDeviceToHost, h->stream));
+  hip_check(hipStreamSynchronize(h->stream));
+  double sq = 0.0;
+  for (double p : part) sq += p;
+  return std::sqrt(sq);
+}
+
+// r = b - A x (float64) into h->ys for system 0, and its norm
+double residual_into_ys(gmres_ctx* h, const double* b, const double* x) {
+  const int64_t n = h->sys[0].n;
+  after_caller(h);
+  hip_check(hipMemsetAsync(h->xs, 0, h->ld * 8, h->stream));
+  hip_check(hipMemsetAsync(h->ys, 0, h->ld * 8, h->stream));
+  hip_check(hipMemcpyAsync(h->ys, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
+  hip_check(hipMemcpyAsync(h->xs, x, n * 8, hipMemcpyDeviceToDevice, h->stream));
+  hip_check(launch_residual_plain(h->a, h->ys, h->xs, h->ys, h->stream));
+  return norm2(h, h->ys, n);
+}
+
+}  // namespace
+
+int gmres_backward_error(gmres_handle hh, const double* b, const double* x, double* eta, double* rel_residual) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!b || !x) return GMRES_EINVAL;
+    if (h->sys.size() != 1) return GMRES_ESTATE;
+    const int64_t n = h->sys[0].n;
+    const double rn = residual_into_ys(h, b, x);
+    const double bn = norm2(h, b, n);
+    const double xn = norm2(h, x, n);
+    if (h->afro < 0.0) h->afro = norm2(h, a64_values(h), h->nnz);
+    const double den = h->afro * xn + bn;
+    if (eta) *eta = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+    if (rel_residual) *rel_residual = bn > 0.0 ? rn / bn : (rn > 0.0 ? INFINITY : 0.0);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_residual_unit(gmres_handle hh, const double* b, const double* x, float* r_out, double* norm_out) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!b || !x || !r_out) return GMRES_EINVAL;
+    if (h->sys.size() != 1) return GMRES_ESTATE;
+    const int64_t n = h->sys[0].n;
+    const double rn = residual_into_ys(h, b, x);
+    if (norm_out) *norm_out = rn;
+    if (!(rn > 0.0) || !std::isfinite(rn)) return GMRES_EINVAL;
+    hip_check(launch_scale_f32(h->ys, n, 1.0 / rn, r_out, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+namespace {
+
+// z = M^-1 v through the ILU application of the Arnoldi loop, with elements
+// of eb bytes (4: the float32 sweeps, 8: the float64 ones)
+void ilu_apply_staged(gmres_ctx* h, const void* v, void* z, size_t eb) {
+  const int64_t n = h->sys[0].n;
+  KArgs t = h->a;
+  t.z64 = eb == 8 ? 1 : 0;  // the output in the sweeps' own precision
+  after_caller(h);
+  hip_check(hipMemsetAsync(t.ilu_v, 0, h->ld * eb, h->stream));
+  hip_check(hipMemcpyAsync(t.ilu_v, v, n * eb, hipMemcpyDeviceToDevice, h->stream));
+  void* out = h->ys;  // ld doubles of staging
+  hip_check(launch_set_force(t, 1, h->stream));
+  hip_check(launch_ilu_apply(t, out, h->stream));
+  hip_check(launch_set_force(t, 0, h->stream));
+  hip_check(hipMemcpyAsync(z, out, n * eb, hipMemcpyDeviceToDevice, h->stream));
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
+}  // namespace
+
 int gmres_precond_apply(gmres_handle hh, const float* v, float* z) {
   try {
     gmres_ctx* h = get(hh);
     if (!v || !z) return GMRES_EINVAL;
-    if (h->opt.precond != GMRES_PRECOND_ILU0 || h->sys.size() != 1) return GMRES_ESTATE;
-    const int64_t n = h->sys[0].n;
-    after_caller(h);
-    hip_check(hipMemsetAsync(h->a.ilu_v, 0, h->ld * 4, h->stream));
-    hip_check(hipMemcpyAsync(h->a.ilu_v, v, n * 4, hipMemcpyDeviceToDevice, h->stream));
-    float* out = reinterpret_cast<float*>(h->ys);  // ld doubles of staging, used as float32 here
-    hip_check(launch_set_force(h->a, 1, h->stream));
-    hip_check(launch_ilu_apply(h->a, out, h->stream));
-    hip_check(launch_set_force(h->a, 0, h->stream));
-    hip_check(hipMemcpyAsync(z, out, n * 4, hipMemcpyDeviceToDevice, h->stream));
-    hip_check(hipStreamSynchronize(h->stream));
+    if (h->opt.precond != GMRES_PRECOND_ILU0 || h->sys.size() != 1 || h->a.pc64) return GMRES_ESTATE;
+    ilu_apply_staged(h, v, z, 4);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_precond_apply_f64(gmres_handle hh, const double* v, double* z) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!v || !z) return GMRES_EINVAL;
+    if (h->opt.precond != GMRES_PRECOND_ILU0 || h->sys.size() != 1 || !h->a.pc64) return GMRES_ESTATE;
+    ilu_apply_staged(h, v, z, 8);
     return GMRES_OK;
   } catch (const Fail& f) {
     (void)hipGetLastError();
@@ -1307,6 +1505,84 @@ int gmres_memory_bytes(gmres_handle hh, size_t* bytes) {
     *bytes = h->bytes;
     return GMRES_OK;
   } catch (const Fail& f) {
+    return f.code;
+  }
+}
+
+int gmres_solve_profiled(gmres_handle hh, const double* b, double* x, gmres_result* res,
+                         gmres_kernel_profile* prof) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (h->a.S != 1 || h->persistent) return GMRES_ESTATE;
+    if (!b || !x || !prof) return GMRES_EINVAL;
+    for (int k = 0; k < GMRES_PK_COUNT; ++k) prof[k] = gmres_kernel_profile{};
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = h->sys[0].n;
+    KArgs& a = h->a;
+    const double sv_upd = a.precond != 0 ? (a.z64 ? 8.0 : 4.0) : (double)vbytes(a.prec);
+    after_caller(h);
+    hip_check(hipMemcpyAsync(a.b, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipMemcpyAsync(a.x, x, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(launch_init_state(a, h->stream));
+    hip_check(launch_bnorm(a, h->stream));
+    ProfPool pool;
+    std::vector<ProfRec> recs;
+    const int64_t cap = h->opt.max_iters + 8;
+    int64_t restarts_before = 0;
+    for (int64_t cyc = 0; cyc <= cap; ++cyc) {
+      pool.used = 0;
+      recs.clear();
+      enqueue_cycle_profiled(h, h->stream, pool, recs);
+      hip_check(hipMemcpyAsync(h->st_host, a.st, sizeof(SysState), hipMemcpyDeviceToHost, h->stream));
+      hip_check(hipStreamSynchronize(h->stream));
+      const SysState& S = h->st_host[0];
+      // the cycle did work past its residual iff it applied a correction
+      // (the residual may have ended the solve); then S.k is its step count
+      const bool ran = S.restarts > restarts_before;
+      const int k = ran ? S.k : 0;
+      restarts_before = S.restarts;
+      for (const ProfRec& r : recs) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, r.e0, r.e1));
+        const bool active = r.j == -1 ? (r.kind != GMRES_PK_ENCODE || ran) : r.j == -2 ? ran : r.j < k;
+        gmres_kernel_profile& p = prof[r.kind];
+        p.ms += ms;
+        p.launches += 1;
+        if (active) {
+          p.ms_active += ms;
+          p.active += 1;
+          p.bytes += r.kind == GMRES_PK_UPDATE ? r.bytes + (double)S.kk * (double)h->nrows * sv_upd : r.bytes;
+        }
+      }
+      if (S.status != RUNNING) break;
+    }
+    hip_check(hipMemcpyAsync(x, a.x, n * 8, hipMemcpyDeviceToDevice, h->stream));
+    hip_check(hipStreamSynchronize(h->stream));
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (res) finish(h, res, 1, sec);
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_launch_config(gmres_handle hh, int32_t family, int32_t j, int32_t* grid, int32_t* block,
+                        int32_t* per_cu, int64_t* basis_align) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (family < 0 || family > GMRES_PK_UPDATE || j < 0 || j >= h->a.m) return GMRES_EINVAL;
+    if (h->persistent) return GMRES_ESTATE;
+    hip_check(launch_config(h->a, family, j, grid, block, per_cu));
+    if (basis_align) {
+      const uint64_t addr = (uint64_t)(uintptr_t)h->a.V;
+      int64_t al = 1;
+      while (al < (int64_t(1) << 21) && (addr & (uint64_t)al) == 0) al <<= 1;
+      *basis_align = al;
+    }
+    return GMRES_OK;
+  } catch (const Fail& f) {
+    (void)hipGetLastError();
     return f.code;
   }
 }

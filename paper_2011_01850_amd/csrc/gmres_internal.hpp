@@ -110,12 +110,21 @@ struct KArgs {
   const uint32_t* alo;
   int32_t asplit;       // 1: SPLIT storage
   const float* mval;   // SPAI values (float32, A's pattern)
-  const float* dinv;   // Jacobi: 1 / a_ii
+  // The preconditioner computes in float32 (pc64 = 0: the mixed modes, and
+  // the float64 solver with a float32 preconditioner) or float64 (pc64 = 1:
+  // the float64 solver); its output Z is float64 in the float64 solver
+  // (z64 = 1), else float32.
+  int32_t pc64;
+  int32_t z64;
+  const float* dinv;   // Jacobi: 1 / a_ii (float32)
+  const double* dinv64;  //   (float64)
   const float* ilu32;  // ILU(0) factors on A's pattern (float32): L below the diagonal, U the rest
   const float* iludinv;  // 1 / u_ii
+  const double* ilu64;   // the same factors and 1 / u_ii in float64
+  const double* iludinv64;
   const int32_t* diagpos;  // index of each row's diagonal entry (padding rows: their empty start)
-  float* ilu_v;        // ILU application: the scaled v_j and three work vectors (ld rows each)
-  float* ilu_b[3];
+  void* ilu_v;         // ILU application: the scaled v_j and three work vectors (ld rows each,
+  void* ilu_b[3];      //   float64 when pc64, else float32)
   int32_t ilu_sl, ilu_su;  // sweeps on L and on U
   const int32_t* rb;       // row-block first rows [nrb + 1]
   const int32_t* rb_sys;   // system of each row block
@@ -130,7 +139,7 @@ struct KArgs {
   SegTab seg[kMaxOcc];      // seg[k - 1]: the split for G = k * ncu workgroups
   // vectors (ld rows each)
   void* V;        // m+1 basis columns, storage per prec
-  float* Z;       // m preconditioned columns (flexible form)
+  void* Z;        // m preconditioned columns (flexible form): double when z64, else float
   void* w;        // work vector: double (P64, PL32) or float
   double* x;      // iterate
   double* b;      // right-hand side
@@ -184,6 +193,16 @@ hipError_t launch_orth_check(const KArgs& a, int j, hipStream_t st);
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st);
 // the kernel that completes CGS projection 2 at column j (timing)
 hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st);
+// The completing reductions on their own (the in-solve profile launches each
+// pass without its reduction, then these): the residual's norm and stop
+// test, projection 1's coefficients, and the end-of-step finaliser.
+// Launch configuration of a kernel family (GMRES_PK_* numbering, 0-6) at
+// column j: workgroups, threads per workgroup, and for the persistent
+// passes the resident workgroups per CU their grid is sized for (else 0).
+hipError_t launch_config(const KArgs& a, int family, int j, int32_t* grid, int32_t* block, int32_t* per_cu);
+hipError_t launch_residual_finish(const KArgs& a, hipStream_t st);
+hipError_t launch_finalize_pass1(const KArgs& a, int j, hipStream_t st);
+hipError_t launch_finalize_final(const KArgs& a, int j, hipStream_t st);
 hipError_t launch_update(const KArgs& a, hipStream_t st);
 hipError_t launch_bnorm(const KArgs& a, hipStream_t st);
 hipError_t launch_init_state(const KArgs& a, hipStream_t st);
@@ -193,13 +212,18 @@ hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStrea
 // float64 values -> high and low 32-bit words (SPLIT storage), and back
 hipError_t launch_split_words(const double* src, uint32_t* hi, uint32_t* lo, int64_t n, hipStream_t st);
 hipError_t launch_merge_words(const uint32_t* hi, const uint32_t* lo, double* dst, int64_t n, hipStream_t st);
-hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st);
+// sum of squares of v[0, n) as nblk partials (part[0, nblk)); out = float32(r * f)
+constexpr int kSumsqBlocks = 1024;
+hipError_t launch_sumsq(const double* v, int64_t n, double* part, int nblk, hipStream_t st);
+hipError_t launch_scale_f32(const double* r, int64_t n, double f, float* out, hipStream_t st);
+hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, double* dinv64, hipStream_t st);
 // ILU(0) factorisation of the rows rows[0, count) (one dependency level), in place on lu
 hipError_t launch_ilu_factor(const KArgs& a, double* lu, const int32_t* rows, int32_t count, hipStream_t st);
 // z = U^-1 L^-1 ilu_v by the configured sweeps, the result in dst
-hipError_t launch_ilu_apply(const KArgs& a, float* dst, hipStream_t st);
+hipError_t launch_ilu_apply(const KArgs& a, void* dst, hipStream_t st);
 // float32 factors and 1/u_ii from the float64 factors
-hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, hipStream_t st);
+hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, double* dinv64,
+                             hipStream_t st);
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st);

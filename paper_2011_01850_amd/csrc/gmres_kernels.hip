@@ -1257,17 +1257,39 @@ __global__ __launch_bounds__(kBlock) void k_encode(KArgs a, int col) {
     out[r] = (TV)w[r];
 }
 
+// The preconditioner's arithmetic (TP) and output (TZ) types: float32 /
+// float32 in the mixed modes; float64 / float64 in the float64 solver, or
+// float32 / float64 when it runs with a float32 preconditioner.
+template <typename TP>
+__device__ __forceinline__ const TP* jacobi_dinv(const KArgs& a);
+template <>
+__device__ __forceinline__ const float* jacobi_dinv<float>(const KArgs& a) { return a.dinv; }
+template <>
+__device__ __forceinline__ const double* jacobi_dinv<double>(const KArgs& a) { return a.dinv64; }
+template <typename TP>
+__device__ __forceinline__ const TP* ilu_factors(const KArgs& a);
+template <>
+__device__ __forceinline__ const float* ilu_factors<float>(const KArgs& a) { return a.ilu32; }
+template <>
+__device__ __forceinline__ const double* ilu_factors<double>(const KArgs& a) { return a.ilu64; }
+template <typename TP>
+__device__ __forceinline__ const TP* ilu_udinv(const KArgs& a);
+template <>
+__device__ __forceinline__ const float* ilu_udinv<float>(const KArgs& a) { return a.iludinv; }
+template <>
+__device__ __forceinline__ const double* ilu_udinv<double>(const KArgs& a) { return a.iludinv64; }
+
 // Jacobi: z_j = D^-1 v_j (or v_j once the preconditioner is switched off).
-template <typename TV>
+template <typename TV, typename TP, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_jacobi(KArgs a, int j) {
   const int s = a.tile_sys[blockIdx.x];
   if (!gated(a, s)) return;
-  const float scale = (float)a.sc[(int64_t)s * (a.m + 1) + j];
+  const TP scale = (TP)a.sc[(int64_t)s * (a.m + 1) + j];
   const bool on = a.st[s].precond_on != 0;
   const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
   // (d^-1 v) * scale: the same rounding as a sparse M = D^-1 applied by the SpMV
-  const float vr = (float)ldv(col_ptr<TV>(a, j)[r]);
-  a.Z[(int64_t)j * a.ld + r] = on ? (a.dinv[r] * vr) * scale : vr * scale;
+  const TP vr = (TP)ldv(col_ptr<TV>(a, j)[r]);
+  static_cast<TZ*>(a.Z)[(int64_t)j * a.ld + r] = (TZ)(on ? (jacobi_dinv<TP>(a)[r] * vr) * scale : vr * scale);
 }
 
 // ---------------------------------------------------------- ILU(0)
@@ -1305,50 +1327,56 @@ __global__ __launch_bounds__(kBlock) void k_ilu_factor(KArgs a, double* __restri
 }
 
 __global__ void k_ilu_finish(KArgs a, const double* __restrict__ lu, float* __restrict__ lu32,
-                             float* __restrict__ dinv) {
+                             float* __restrict__ dinv, double* __restrict__ dinv64) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
   const int b = a.rp[r], e = a.rp[r + 1];
-  for (int p = b; p < e; ++p) lu32[p] = (float)lu[p];
-  dinv[r] = b < e ? (float)(1.0 / lu[a.diagpos[r]]) : 0.0f;  // padding rows: zero
+  if (lu32)
+    for (int p = b; p < e; ++p) lu32[p] = (float)lu[p];
+  const double di = b < e ? 1.0 / lu[a.diagpos[r]] : 0.0;  // padding rows: zero
+  if (dinv) dinv[r] = (float)di;
+  if (dinv64) dinv64[r] = di;
 }
 
 // Application z_j = U^-1 L^-1 (scale_j v_j): the scaled v_j, then sweeps
 // y <- v - L' y and x <- D^-1 (y - U' x) from zero starts (src = null), one
 // thread per row, each row's strictly lower / upper entries in storage order.
-template <typename TV>
+template <typename TV, typename TP, typename TZ>
 __global__ __launch_bounds__(kBlock) void k_ilu_begin(KArgs a, int j) {
   const int s = a.tile_sys[blockIdx.x];
   if (!gated(a, s)) return;
-  const float scale = (float)a.sc[(int64_t)s * (a.m + 1) + j];
+  const TP scale = (TP)a.sc[(int64_t)s * (a.m + 1) + j];
   const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
-  const float v = (float)ldv(col_ptr<TV>(a, j)[r]) * scale;
+  const TP v = (TP)ldv(col_ptr<TV>(a, j)[r]) * scale;
   if (a.st[s].precond_on)
-    a.ilu_v[r] = v;
+    static_cast<TP*>(a.ilu_v)[r] = v;
   else
-    a.Z[(int64_t)j * a.ld + r] = v;  // preconditioner switched off: z_j = v_j
+    static_cast<TZ*>(a.Z)[(int64_t)j * a.ld + r] = (TZ)v;  // preconditioner switched off: z_j = v_j
 }
 
-__global__ __launch_bounds__(kBlock) void k_ilu_lsweep(KArgs a, const float* __restrict__ src,
-                                                       float* __restrict__ dst) {
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_ilu_lsweep(KArgs a, const TP* __restrict__ src, TP* __restrict__ dst) {
   const int s = a.tile_sys[blockIdx.x];
   if (!gated(a, s) || (!a.st[s].precond_on && !a.st[s].force)) return;
   const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
-  float acc = 0.0f;
+  const TP* lu = ilu_factors<TP>(a);
+  TP acc = (TP)0;
   if (src)
-    for (int p = a.rp[r]; p < a.diagpos[r]; ++p) acc += a.ilu32[p] * src[a.ci[p]];
-  dst[r] = a.ilu_v[r] - acc;
+    for (int p = a.rp[r]; p < a.diagpos[r]; ++p) acc += lu[p] * src[a.ci[p]];
+  dst[r] = static_cast<const TP*>(a.ilu_v)[r] - acc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_ilu_usweep(KArgs a, const float* __restrict__ y,
-                                                       const float* __restrict__ src, float* __restrict__ dst) {
+template <typename TP, typename TO>
+__global__ __launch_bounds__(kBlock) void k_ilu_usweep(KArgs a, const TP* __restrict__ y, const TP* __restrict__ src,
+                                                       TO* __restrict__ dst) {
   const int s = a.tile_sys[blockIdx.x];
   if (!gated(a, s) || (!a.st[s].precond_on && !a.st[s].force)) return;
   const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
-  float acc = 0.0f;
+  const TP* lu = ilu_factors<TP>(a);
+  TP acc = (TP)0;
   if (src)
-    for (int p = a.diagpos[r] + 1; p < a.rp[r + 1]; ++p) acc += a.ilu32[p] * src[a.ci[p]];
-  dst[r] = (y[r] - acc) * a.iludinv[r];
+    for (int p = a.diagpos[r] + 1; p < a.rp[r + 1]; ++p) acc += lu[p] * src[a.ci[p]];
+  dst[r] = (TO)((y[r] - acc) * ilu_udinv<TP>(a)[r]);
 }
 
 // y = H^-1 s by back-substitution, one wave per system, with truncation of
@@ -1404,8 +1432,10 @@ __global__ __launch_bounds__(kBlock) void k_update(KArgs a) {
   const double* yv = a.y + (int64_t)s * a.m;
   const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
   double acc = a.x[r];
-  if (a.precond != 0) {
-    for (int i = 0; i < kk; ++i) acc += yv[i] * (double)a.Z[(int64_t)i * a.ld + r];
+  if (a.precond != 0 && a.z64) {
+    for (int i = 0; i < kk; ++i) acc += yv[i] * static_cast<const double*>(a.Z)[(int64_t)i * a.ld + r];
+  } else if (a.precond != 0) {
+    for (int i = 0; i < kk; ++i) acc += yv[i] * (double)static_cast<const float*>(a.Z)[(int64_t)i * a.ld + r];
   } else {
     for (int i = 0; i < kk; ++i) acc += yv[i] * (double)ldv(col_ptr<TV>(a, i)[r]);
   }
@@ -1482,7 +1512,23 @@ __global__ void k_convert_f32(const double* __restrict__ src, float* __restrict_
   for (int64_t k = i; k < n; k += stride) dst[k] = (float)src[k];
 }
 
-__global__ void k_jacobi_setup(KArgs a, float* dinv) {
+// Sum of squares of v[0, n): one partial per workgroup (grid-stride rows,
+// then the fixed block tree); the host adds the partials in order.
+__global__ __launch_bounds__(kBlock) void k_sumsq(const double* __restrict__ v, int64_t n, double* part) {
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  double acc = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) acc += v[k] * v[k];
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// out = float32(r * f)
+__global__ void k_scale_f32(const double* __restrict__ r, int64_t n, double f, float* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) out[k] = (float)(r[k] * f);
+}
+
+__global__ void k_jacobi_setup(KArgs a, float* dinv, double* dinv64) {
   // one thread per row; padding rows (empty) get 0
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
@@ -1490,7 +1536,9 @@ __global__ void k_jacobi_setup(KArgs a, float* dinv) {
   double d = 0.0;
   for (int k = p0; k < p1; ++k)
     if (a.ci[k] == r) d += a.asplit ? hilo_value(a.ahi[k], a.alo[k]) : a.a64[k];
-  dinv[r] = (p1 > p0 && d != 0.0) ? (float)(1.0 / d) : 0.0f;
+  const double di = (p1 > p0 && d != 0.0) ? 1.0 / d : 0.0;
+  if (dinv) dinv[r] = (float)di;
+  if (dinv64) dinv64[r] = di;
 }
 
 __global__ void k_shift_i32(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int64_t n,
@@ -1651,7 +1699,10 @@ static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStre
 
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
   if (a.precond != 0) {  // w = A z_j
-    const float* z = a.Z + (int64_t)j * a.ld;
+    if (a.z64)
+      return spmv_values<double, double, SM_AZ>(a, static_cast<const double*>(a.Z) + (int64_t)j * a.ld,
+                                                (double*)a.w, j, st);
+    const float* z = static_cast<const float*>(a.Z) + (int64_t)j * a.ld;
     if (wide_w(a.prec)) return spmv_values<float, double, SM_AZ>(a, z, (double*)a.w, j, st);
     return spmv_values<float, float, SM_AZ>(a, z, (float*)a.w, j, st);
   }
@@ -1670,51 +1721,76 @@ hipError_t launch_ilu_factor(const KArgs& a, double* lu, const int32_t* rows, in
   return hipGetLastError();
 }
 
-hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, hipStream_t st) {
-  hipLaunchKernelGGL(k_ilu_finish, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, lu, lu32, dinv);
+hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, double* dinv64,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_ilu_finish, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, lu, lu32, dinv,
+                     dinv64);
   return hipGetLastError();
 }
 
 // ILU(0) sweeps on ilu_v (L sweeps ping-pong in b0/b1, U sweeps in b2 and
 // whichever of b0/b1 does not hold the L result); the last U sweep writes dst.
-hipError_t launch_ilu_apply(const KArgs& a, float* dst_final, hipStream_t st) {
-  const float* src = nullptr;
+template <typename TP, typename TZ>
+static hipError_t ilu_apply_t(const KArgs& a, TZ* dst_final, hipStream_t st) {
+  TP* const b[3] = {static_cast<TP*>(a.ilu_b[0]), static_cast<TP*>(a.ilu_b[1]), static_cast<TP*>(a.ilu_b[2])};
+  const TP* src = nullptr;
   for (int t = 0; t < a.ilu_sl; ++t) {
-    float* dst = a.ilu_b[t & 1];
-    hipLaunchKernelGGL(k_ilu_lsweep, dim3(a.ntile), dim3(kBlock), 0, st, a, src, dst);
+    TP* dst = b[t & 1];
+    hipLaunchKernelGGL((k_ilu_lsweep<TP>), dim3(a.ntile), dim3(kBlock), 0, st, a, src, dst);
     src = dst;
   }
-  const float* y = src;
-  float* const ub[2] = {a.ilu_b[2], a.ilu_b[(a.ilu_sl & 1) ? 1 : 0]};
-  const float* usrc = nullptr;
+  const TP* y = src;
+  TP* const ub[2] = {b[2], b[(a.ilu_sl & 1) ? 1 : 0]};
+  const TP* usrc = nullptr;
   for (int t = 0; t < a.ilu_su; ++t) {
-    float* dst = t + 1 == a.ilu_su ? dst_final : ub[t & 1];
-    hipLaunchKernelGGL(k_ilu_usweep, dim3(a.ntile), dim3(kBlock), 0, st, a, y, usrc, dst);
-    usrc = dst;
+    if (t + 1 == a.ilu_su) {
+      hipLaunchKernelGGL((k_ilu_usweep<TP, TZ>), dim3(a.ntile), dim3(kBlock), 0, st, a, y, usrc, dst_final);
+    } else {
+      TP* dst = ub[t & 1];
+      hipLaunchKernelGGL((k_ilu_usweep<TP, TP>), dim3(a.ntile), dim3(kBlock), 0, st, a, y, usrc, dst);
+      usrc = dst;
+    }
   }
   return hipGetLastError();
 }
 
+// z = U^-1 L^-1 ilu_v into dst (float64 when z64, else float32)
+hipError_t launch_ilu_apply(const KArgs& a, void* dst_final, hipStream_t st) {
+  if (a.pc64) return ilu_apply_t<double, double>(a, static_cast<double*>(dst_final), st);
+  if (a.z64) return ilu_apply_t<float, double>(a, static_cast<double*>(dst_final), st);
+  return ilu_apply_t<float, float>(a, static_cast<float*>(dst_final), st);
+}
+
+// the preconditioner's (arithmetic, output) types for the handle
+template <typename F>
+static hipError_t launch_by_pc(const KArgs& a, F&& f) {
+  if (a.pc64) return f(double{}, double{});
+  if (a.z64) return f(float{}, double{});
+  return f(float{}, float{});
+}
+
 hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
   if (a.precond == 0) return hipSuccess;
-  if (a.precond == 3) {
-    launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
-      using TV = decltype(tv);
-      hipLaunchKernelGGL((k_ilu_begin<TV>), dim3(a.ntile), dim3(kBlock), 0, st, a, j);
-      return hipSuccess;
-    });
-    return launch_ilu_apply(a, a.Z + (int64_t)j * a.ld, st);
-  }
   return launch_by_prec(a.prec, [&](auto tv, auto) -> hipError_t {
     using TV = decltype(tv);
-    if (a.precond == 1) {
-      hipLaunchKernelGGL((k_jacobi<TV>), dim3(a.ntile), dim3(kBlock), 0, st, a, j);
-    } else {
-      const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
-      hipLaunchKernelGGL((k_spmv<float, TV, float, SM_PRECOND>), dim3(a.nrb), dim3(kBlock),
-                         (size_t)a.spmv_budget * 4, st, a, a.mval, x, a.Z + (int64_t)j * a.ld, nullptr, j);
-    }
-    return hipGetLastError();
+    return launch_by_pc(a, [&](auto tp, auto tz) -> hipError_t {
+      using TP = decltype(tp);
+      using TZ = decltype(tz);
+      TZ* zj = static_cast<TZ*>(a.Z) + (int64_t)j * a.ld;
+      if (a.precond == 3) {
+        hipLaunchKernelGGL((k_ilu_begin<TV, TP, TZ>), dim3(a.ntile), dim3(kBlock), 0, st, a, j);
+        return ilu_apply_t<TP, TZ>(a, zj, st);
+      }
+      if (a.precond == 1) {
+        hipLaunchKernelGGL((k_jacobi<TV, TP, TZ>), dim3(a.ntile), dim3(kBlock), 0, st, a, j);
+      } else {
+        // the learned M (float32 values) applied with the accumulation of the output's type
+        const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
+        hipLaunchKernelGGL((k_spmv<float, TV, TZ, SM_PRECOND>), dim3(a.nrb), dim3(kBlock),
+                           (size_t)a.spmv_budget * sizeof(AccFor<float, TZ>), st, a, a.mval, x, zj, nullptr, j);
+      }
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1844,6 +1920,64 @@ hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st) {
   return launch_fin_cols<2>(a, *used, j, st);
 }
 
+// The split the projection-1 kernel at column j runs with (the layout of its
+// partial rows, which the completing reduction reads).
+static const SegTab* pass1_split(const KArgs& a, int j) {
+  const SegTab* used = nullptr;
+  launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const int L = j + 1 <= 64 ? lanes_for(j + 1) : 64;
+    const void* k = L == 8 ? (const void*)k_mdot<TV, TW, 8> : L == 16 ? (const void*)k_mdot<TV, TW, 16>
+                  : L == 32 ? (const void*)k_mdot<TV, TW, 32> : (const void*)k_mdot<TV, TW, 64>;
+    used = &a.seg[occupancy_of(k) - 1];
+    return hipSuccess;
+  });
+  return used;
+}
+
+hipError_t launch_finalize_pass1(const KArgs& a, int j, hipStream_t st) {
+  const SegTab* used = pass1_split(a, j);
+  if (!used) return hipErrorInvalidValue;
+  return launch_fin_cols<1>(a, *used, j, st);
+}
+
+hipError_t launch_residual_finish(const KArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_tile_norm, dim3(a.ntile), dim3(kBlock), 0, st, a);
+  hipLaunchKernelGGL((k_fin<FIN_RESID>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.ntile, a.sys_t0,
+                     a.sys_nt, 0);
+  return hipGetLastError();
+}
+
+// The per-step finaliser after the last pass of step j (k_fin_step), on the
+// partial rows that pass wrote.
+hipError_t launch_finalize_final(const KArgs& a, int j, hipStream_t st) {
+  const SegTab* used = nullptr;
+  const double* src = a.part;
+  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    if (a.ortho == 0) {
+      used = &a.seg[kMgsOcc - 1];
+      src = (j & 1) ? a.part : a.part2;
+      return hipSuccess;
+    }
+    const void* k = nullptr;
+    if (j + 1 <= 64) {
+      const int L = lanes_for(j + 1);
+      k = L == 8 ? (const void*)k_final_tile<TV, TW, 8> : L == 16 ? (const void*)k_final_tile<TV, TW, 16>
+        : L == 32 ? (const void*)k_final_tile<TV, TW, 32> : (const void*)k_final_tile<TV, TW, 64>;
+    } else {
+      k = (const void*)k_final<TV, TW>;
+    }
+    used = &a.seg[occupancy_of(k) - 1];
+    return hipSuccess;
+  });
+  if (e != hipSuccess || !used) return e != hipSuccess ? e : hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fin_step, dim3(a.S), dim3(kBlock), 0, st, a, src, used->nseg, used->sys_sg0, used->sys_nsg, j);
+  return hipGetLastError();
+}
+
 hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fin) {
   const SegTab* used = nullptr;
   const double* src = a.part;
@@ -1881,6 +2015,65 @@ hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fi
   if (e0 != hipSuccess || !with_fin) return e0;
   hipLaunchKernelGGL(k_fin_step, dim3(a.S), dim3(kBlock), 0, st, a, src, used->nseg, used->sys_sg0, used->sys_nsg, j);
   return hipGetLastError();
+}
+
+hipError_t launch_config(const KArgs& a, int family, int j, int32_t* grid, int32_t* block, int32_t* per_cu) {
+  const void* k = nullptr;
+  int G = 0, B = kBlock;
+  hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const int L = j + 1 <= 64 ? lanes_for(j + 1) : 64;
+    switch (family) {
+      case 0:  // Arnoldi SpMV: one workgroup per row block
+        G = a.nrb;
+        return hipSuccess;
+      case 1:
+        k = L == 8 ? (const void*)k_mdot<TV, TW, 8> : L == 16 ? (const void*)k_mdot<TV, TW, 16>
+          : L == 32 ? (const void*)k_mdot<TV, TW, 32> : (const void*)k_mdot<TV, TW, 64>;
+        return hipSuccess;
+      case 2:
+        if (j + 1 > 64) {
+          k = (const void*)k_mdot<TV, TW, 64>;
+        } else if constexpr (sizeof(TW) == 8) {
+          k = L == 8 ? (const void*)k_axpy_mdot64<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64<TV, TW, 16>
+            : L == 32 ? (const void*)k_axpy_mdot64<TV, TW, 32> : (const void*)k_axpy_mdot64<TV, TW, 64>;
+        } else {
+          k = L == 8 ? (const void*)k_axpy_mdot<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot<TV, TW, 16>
+            : L == 32 ? (const void*)k_axpy_mdot<TV, TW, 32> : (const void*)k_axpy_mdot<TV, TW, 64>;
+        }
+        return hipSuccess;
+      case 3:
+        if (a.ortho == 0) {
+          G = a.seg[kMgsOcc - 1].G;
+          return hipSuccess;
+        }
+        k = j + 1 > 64 ? (const void*)k_final<TV, TW>
+          : L == 8 ? (const void*)k_final_tile<TV, TW, 8> : L == 16 ? (const void*)k_final_tile<TV, TW, 16>
+          : L == 32 ? (const void*)k_final_tile<TV, TW, 32> : (const void*)k_final_tile<TV, TW, 64>;
+        return hipSuccess;
+      case 4:
+        G = a.seg[kMgsOcc - 1].G;
+        return hipSuccess;
+      case 5:
+        G = a.nrb;
+        return hipSuccess;
+      case 6:
+        G = a.ntile;
+        return hipSuccess;
+    }
+    return hipErrorInvalidValue;
+  });
+  if (e != hipSuccess) return e;
+  int occ = 0;
+  if (k) {
+    occ = occupancy_of(k);
+    G = a.seg[occ - 1].G;
+  }
+  if (grid) *grid = G;
+  if (block) *block = B;
+  if (per_cu) *per_cu = occ;
+  return hipSuccess;
 }
 
 hipError_t launch_orth_check(const KArgs& a, int j, hipStream_t st) {
@@ -1993,8 +2186,19 @@ hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, hipStream_t st) {
-  hipLaunchKernelGGL(k_jacobi_setup, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, dinv);
+hipError_t launch_sumsq(const double* v, int64_t n, double* part, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_sumsq, dim3(nblk), dim3(kBlock), 0, st, v, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_f32(const double* r, int64_t n, double f, float* out, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+  if (blocks > 0) hipLaunchKernelGGL(k_scale_f32, dim3(blocks), dim3(256), 0, st, r, n, f, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_setup(const KArgs& a, float* dinv, double* dinv64, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_setup, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, dinv, dinv64);
   return hipGetLastError();
 }
 

@@ -55,6 +55,8 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.orth_norm = L.ORTH_NORMS[orth_norm] if isinstance(orth_norm, str) else int(orth_norm)
     o.ilu_sweeps = int(ilu_sweeps)
     o.arnoldi_a = L.ARNOLDI_AS[arnoldi_a] if isinstance(arnoldi_a, str) else int(arnoldi_a)
+    o.precond_precision = (L.PRECOND_PRECISIONS[precond_precision] if isinstance(precond_precision, str)
+                           else int(precond_precision))
     return o
 
 
@@ -65,7 +67,7 @@ class Solver:
                  precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
                  a_storage="copy", restart_repeat=False, restart_on_stall=False, orth_restart=0.0,
-                 orth_norm="spectral", ilu_sweeps=4, arnoldi_a="default"):
+                 orth_norm="spectral", ilu_sweeps=4, arnoldi_a="default", precond_precision="native"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -77,7 +79,8 @@ class Solver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a, precond_precision)
+        self.precision = precision
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         torch.cuda.synchronize()
@@ -115,6 +118,26 @@ class Solver:
         res = L.Result()
         L.check(self.lib.gmres_solve(self.h, bt.data_ptr(), x.data_ptr(), C.byref(res)), "gmres_solve")
         return x, res.as_dict()
+
+    def solve_profiled(self, b, x0=None):
+        """The same solve with every kernel launched directly between HIP events.
+
+        Returns (x, info, profile): profile maps each kernel family to its
+        summed milliseconds, launches, and the milliseconds, launches and
+        algorithmic bytes of the launches that did work."""
+        torch = self._torch
+        bt = _dev(b, torch.float64, torch)
+        x = torch.zeros(self.n, dtype=torch.float64, device="cuda") if x0 is None else \
+            _dev(x0, torch.float64, torch).clone()
+        torch.cuda.synchronize()
+        res = L.Result()
+        prof = (L.KernelProfile * len(L.PROFILE_KINDS))()
+        L.check(self.lib.gmres_solve_profiled(self.h, bt.data_ptr(), x.data_ptr(), C.byref(res), prof),
+                "gmres_solve_profiled")
+        out = {name: {"ms": p.ms, "launches": int(p.launches), "ms_active": p.ms_active,
+                      "active": int(p.active), "bytes": p.bytes}
+               for name, p in zip(L.PROFILE_KINDS, prof)}
+        return x, res.as_dict(), out
 
     def set_preconditioner(self, spai_vals):
         torch = self._torch
@@ -154,13 +177,42 @@ class Solver:
                 "gmres_residual")
         return r, nrm.value
 
-    def precond_apply(self, v):
-        """z = M^-1 v (float32 tensors) with the handle's ILU(0) preconditioner."""
+    def backward_error(self, b, x):
+        """(eta, relres): normwise backward error ||r|| / (||A||_F ||x|| + ||b||) and ||r|| / ||b||, float64."""
         torch = self._torch
-        vt = _dev(v, torch.float32, torch)
+        bt = _dev(b, torch.float64, torch)
+        xt = _dev(x, torch.float64, torch)
+        eta, rel = C.c_double(), C.c_double()
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_backward_error(self.h, bt.data_ptr(), xt.data_ptr(), C.byref(eta), C.byref(rel)),
+                "gmres_backward_error")
+        return eta.value, rel.value
+
+    def residual_unit(self, b, x, out=None):
+        """(float32 z / ||z||, ||z||) with z = b - A x in float64; `out` is an optional float32 device tensor."""
+        torch = self._torch
+        bt = _dev(b, torch.float64, torch)
+        xt = _dev(x, torch.float64, torch)
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        elif out.dtype != torch.float32 or out.numel() != self.n or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor of n elements")
+        nrm = C.c_double()
+        torch.cuda.synchronize()
+        L.check(self.lib.gmres_residual_unit(self.h, bt.data_ptr(), xt.data_ptr(), out.data_ptr(), C.byref(nrm)),
+                "gmres_residual_unit")
+        return out, nrm.value
+
+    def precond_apply(self, v, f64=False):
+        """z = M^-1 v with the handle's ILU(0) preconditioner: float32 tensors, or
+        float64 ones (f64=True) for a float64 solver with a float64 preconditioner."""
+        torch = self._torch
+        vt = _dev(v, torch.float64 if f64 else torch.float32, torch)
         z = torch.empty_like(vt)
         torch.cuda.synchronize()
-        L.check(self.lib.gmres_precond_apply(self.h, vt.data_ptr(), z.data_ptr()), "gmres_precond_apply")
+        fn, name = (self.lib.gmres_precond_apply_f64, "gmres_precond_apply_f64") if f64 else \
+            (self.lib.gmres_precond_apply, "gmres_precond_apply")
+        L.check(fn(self.h, vt.data_ptr(), z.data_ptr()), name)
         return z
 
     def spmv(self, x, precision="fp64"):
@@ -196,6 +248,14 @@ class Solver:
         v = C.c_size_t()
         L.check(self.lib.gmres_memory_bytes(self.h, C.byref(v)), "gmres_memory_bytes")
         return int(v.value)
+
+    def launch_config(self, family, j):
+        """Launch configuration of a kernel family at column j: dict(grid, block, per_cu, basis_align)."""
+        fam = L.PROFILE_KINDS.index(family) if isinstance(family, str) else int(family)
+        g, b, o, al = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        L.check(self.lib.gmres_launch_config(self.h, fam, int(j), C.byref(g), C.byref(b), C.byref(o), C.byref(al)),
+                "gmres_launch_config")
+        return {"grid": g.value, "block": b.value, "per_cu": o.value, "basis_align": al.value}
 
     def time_kernel(self, kernel, j, reps=20):
         """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""

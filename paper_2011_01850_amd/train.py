@@ -28,10 +28,10 @@ def collect_pairs(row_ptr, col_idx, vals, b, K=4, m=30):
     x = torch.zeros(s.n, dtype=torch.float64, device="cuda")
     Z = torch.empty((K, s.n), dtype=torch.float32, device="cuda")
     for k in range(K):
-        r, nrm = s.residual(b, x)
-        if not nrm > 0.0:
-            raise ValueError("zero residual: the system is already solved")
-        Z[k] = (r / nrm).to(torch.float32)
+        try:
+            s.residual_unit(b, x, out=Z[k])
+        except Exception as e:
+            raise ValueError("zero or non-finite residual: the system is already solved or broken") from e
         if k + 1 < K:
             x, _ = s.solve(b, x0=x)
     s.close()

@@ -73,11 +73,13 @@ def test_invalid_arguments_rejected_before_device_work(lib):
     ob.orth_restart = 0.5
     ob.m = 65
     assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL
-    # preconditioning is defined for the mixed modes only
-    ob = L.default_options()
-    ob.precision = L.FP64
-    ob.precond = L.PRECOND_JACOBI
-    assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL
+    # the preconditioner's precision: the solver's own, or float32
+    for bad in (2, -1):
+        ob = L.default_options()
+        ob.precision = L.FP64
+        ob.precond = L.PRECOND_JACOBI
+        ob.precond_precision = bad
+        assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL
     assert lib.gmres_encode(L.FP64, 10, 1, 1.0, 1, None, None) == L.EINVAL
     assert lib.gmres_encode(L.MIXED_FP16, 10, 1, 0.0, 1, None, None) == L.EINVAL
     # the no-allocation variant: the same checks, and no more than 2^24 elements
@@ -123,6 +125,9 @@ def test_handle_checks(lib):
     v = C.c_size_t()
     assert lib.gmres_memory_bytes(None, C.byref(v)) == L.EHANDLE
     assert lib.gmres_precond_apply(None, None, None) == L.EHANDLE
+    assert lib.gmres_precond_apply_f64(None, 1, 1) == L.EHANDLE
+    prof = (L.KernelProfile * len(L.PROFILE_KINDS))()
+    assert lib.gmres_solve_profiled(None, 1, 1, None, prof) == L.EHANDLE
     # a pointer to something that is not a handle
     junk = (C.c_uint32 * 64)()
     assert lib.gmres_memory_bytes(C.cast(junk, C.c_void_p), C.byref(v)) == L.EHANDLE
@@ -137,7 +142,7 @@ def test_struct_layouts_match_header():
     assert L.Options.a_storage.offset == 68 and L.Options.restart_repeat.offset == 72
     assert L.Options.restart_on_stall.offset == 76 and L.Options.orth_restart.offset == 80
     assert L.Options.orth_norm.offset == 88 and L.Options.ilu_sweeps.offset == 92
-    assert L.Options.arnoldi_a.offset == 96
+    assert L.Options.arnoldi_a.offset == 96 and L.Options.precond_precision.offset == 100
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 
@@ -174,10 +179,12 @@ def test_struct_layouts_match_compiled_header(tmp_path):
         pytest.skip("no C compiler")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gmres.h"', "int main(void) {"]
-    for cname, ct in (("gmres_options", L.Options), ("gmres_result", L.Result)):
+    structs = (("gmres_options", L.Options), ("gmres_result", L.Result), ("gmres_kernel_profile", L.KernelProfile))
+    for cname, ct in structs:
         lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
         for fname, _ in ct._fields_:
             lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append('  printf("GMRES_PK_COUNT value %d\\n", (int)GMRES_PK_COUNT);')
     lines += ["  return 0;", "}"]
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines) + "\n")
@@ -185,7 +192,8 @@ def test_struct_layouts_match_compiled_header(tmp_path):
     subprocess.run([cc, "-std=c99", "-I", inc, str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
-    for cname, ct in (("gmres_options", L.Options), ("gmres_result", L.Result)):
+    for cname, ct in structs:
         assert got[(cname, "sizeof")] == C.sizeof(ct), cname
         for fname, _ in ct._fields_:
             assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)
+    assert got[("GMRES_PK_COUNT", "value")] == len(L.PROFILE_KINDS)

@@ -1,6 +1,8 @@
 """The benchmark workload at full size (128^3 convection-diffusion, n = 2,097,152)
 in the launch configuration bench.py times, checked by properties that hold at
 any size and by outputs the oracle computes one by one."""
+import time
+
 import numpy as np
 import pytest
 
@@ -57,6 +59,57 @@ def test_fullsize_mixed_solve_reaches_1e10(c2, ortho):
     assert info["rel_residual"] == pytest.approx(rr, rel=1e-6)
     # restart residuals never increase (the convergence argument of the numerics section)
     assert np.all(np.diff(hist) <= 0)
+
+
+@pytest.fixture(scope="module")
+def c2_oracle(c2):
+    # the float64 oracle (CGSR) at full size to 1e-13: the solution every
+    # mode is compared with (several minutes on the host's cores)
+    # Run cycle by cycle (each call: the residual of the current x, then one
+    # GMRES(50) cycle from it), which is restarted GMRES itself, so that every
+    # cycle reports its progress
+    t0 = time.perf_counter()
+    A = O.Matrix.from_csr(c2.A)
+    m, x, iters, restarts = 50, None, 0, 0
+    while True:
+        r = O.gmres(A, c2.b, x0=x, m=m, tol=1e-13, ortho="cgsr", max_iters=m)
+        iters += r.iters
+        restarts += r.restarts
+        x = r.x
+        print(f"  oracle cycle {restarts}: relres {r.history[-1]:.2e} after {iters} iterations "
+              f"({time.perf_counter() - t0:.0f} s)", flush=True)
+        if r.status != O.MAXITER:
+            break
+    print(f"128^3 float64 oracle: {r.status_name} iters {iters} restarts {restarts} relres "
+          f"{r.rel_residual:.2e} in {time.perf_counter() - t0:.1f} s", flush=True)
+    assert r.status == O.CONVERGED
+    r.iters, r.restarts = iters, restarts
+    return r
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("ortho,precision", [("cgsr", "fp32"), ("mgs", "fp32"), ("cgsr", "fp64"),
+                                             ("mgs", "fp64"), ("cgsr", "fp16"), ("cgsr", "limited")])
+def test_fullsize_solution_matches_oracle(c2, c2_oracle, ortho, precision):
+    # the benchmark system at full size, each mode to 1e-13 (the launch
+    # configuration the benchmark times, autotuned): the solution agrees
+    # element by element with the float64 oracle's to 1e-8 relative
+    A = c2.A
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=50, ortho=ortho, precision=precision, tol=1e-13)
+    x, info = s.solve(c2.b)
+    s.close()
+    x = x.cpu().numpy()
+    rr = O.relative_residual(O.Matrix.from_csr(A), c2.b, x)
+    err = float(np.linalg.norm(x - c2_oracle.x) / np.linalg.norm(c2_oracle.x))
+    fwd = float(np.linalg.norm(x - c2.x_true) / np.linalg.norm(c2.x_true))
+    print(f"128^3 {ortho} {precision}: {info['status']} iters {info['iters']} restarts {info['restarts']} "
+          f"relres {rr:.2e} | vs oracle x {err:.2e} (oracle iters {c2_oracle.iters}) | vs x_true {fwd:.2e}",
+          flush=True)
+    assert info["status"] == "CONVERGED" and rr <= 1.01e-13
+    assert err <= 1e-8
+    # mixed and float64 need about the same number of cycles (the paper finds
+    # equal iteration counts on most of its matrices)
+    assert abs(info["restarts"] - c2_oracle.restarts) <= 2
 
 
 def test_fullsize_first_cycle_basis(c2):
@@ -183,3 +236,49 @@ def test_fullsize_spai_forward():
     print(f"64^3 inference: learned part cos {cos:.7f} rel {rel:.2e}", flush=True)
     assert np.all(np.isfinite(M_gpu))
     assert cos >= 0.99999 and rel <= 1e-3
+
+
+@pytest.fixture(scope="module")
+def c5():
+    return P.c5_varcoef(2000)  # the first held-out instance of the learned-preconditioner workload
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("kind", ["jacobi", "learned"])
+def test_fullsize_varcoef_fgmres_matches_oracle(c5, kind):
+    # FGMRES(30) on a held-out 64^3 variable-coefficient instance, to 1e-13:
+    # Jacobi, and the network's M (GPU inference on bfloat16 weights; the
+    # oracle applies the float64 network's M to the same weights), against the
+    # float64 FGMRES oracle element by element
+    from oracle import mpnn as N
+    from paper_2011_01850_amd import spai
+
+    A = c5.A
+    M = O.Matrix.from_csr(A)
+    if kind == "jacobi":
+        d = M.diagonal()
+        pc = lambda v: v / d  # noqa: E731
+    else:
+        th = _spai_theta(1)
+        G = N.graph(A.n, A.row_ptr, A.col_idx, A.vals)
+        Mo = O.Matrix(A.row_ptr, A.col_idx, N.forward(torch.as_tensor(N.round_bf16(th)), G).numpy(), A.n)
+        pc = Mo.matvec
+    t0 = time.perf_counter()
+    ref = O.gmres(M, c5.b, m=30, tol=1e-13, ortho="cgsr", precond=pc, fallback=False)
+    t_or = time.perf_counter() - t0
+    s = Solver(A.row_ptr, A.col_idx, A.vals, m=30, ortho="cgsr", precision="fp32",
+               precond="jacobi" if kind == "jacobi" else "spai", tol=1e-13)
+    if kind == "learned":
+        s.spai_infer(torch.as_tensor(spai.params_to_bf16(th)).cuda(), return_m=False)
+    x, info = s.solve(c5.b)
+    s.close()
+    x = x.cpu().numpy()
+    rr = O.relative_residual(M, c5.b, x)
+    err = float(np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x))
+    print(f"64^3 FGMRES {kind}: gpu {info['status']} iters {info['iters']} relres {rr:.2e} fallback "
+          f"{info['fallback_used']} | oracle {ref.status_name} iters {ref.iters} ({t_or:.1f} s) | "
+          f"vs oracle x {err:.2e}", flush=True)
+    assert ref.status == O.CONVERGED
+    assert info["status"] == "CONVERGED" and not info["fallback_used"] and rr <= 1.01e-13
+    assert err <= 1e-8
+    assert abs(info["iters"] - ref.iters) <= max(30, 0.1 * ref.iters)

@@ -229,11 +229,11 @@ def test_infer_installs_jacobi_for_zero_decoder(lib):
     assert res <= 1e-10 * 1.01
 
 
-def test_training_gains_over_no_preconditioner(lib):
+def test_training_gains_over_jacobi_and_no_preconditioner(lib):
     """A short GPU training run on residuals the solver produces lowers the
     loss below its Jacobi start, and FGMRES with the trained network needs
-    far fewer iterations than plain GMRES on held-out instances; the
-    iterations with Jacobi are reported beside it."""
+    fewer iterations than Jacobi (the network's own starting point) and far
+    fewer than plain GMRES on held-out instances."""
     from paper_2011_01850_amd.train import collect_pairs, evaluate, train
     Nside = 12
     train_ids = list(range(6))
@@ -242,9 +242,11 @@ def test_training_gains_over_no_preconditioner(lib):
     assert res["loss_last"] < 0.9 * res["loss_first"], res
     ev = evaluate(res["params"], test_ids, N=Nside)
     for r in ev:
-        print(r)
-        assert r["learned"]["status"] == "CONVERGED"
+        print({k: (v["iters"], v["status"]) if isinstance(v, dict) else v for k, v in r.items()}, flush=True)
+        assert r["learned"]["status"] == "CONVERGED" and r["jacobi"]["status"] == "CONVERGED"
         assert r["learned"]["iters"] < 0.5 * r["none"]["iters"]
+        # the network starts as Jacobi (zero decoder): training has to beat its own start
+        assert r["learned"]["iters"] < r["jacobi"]["iters"]
 
 
 def test_infer_with_shared_network(lib):

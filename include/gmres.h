@@ -176,7 +176,19 @@ typedef struct {
   int32_t arnoldi_a;        /* GMRES_ARNOLDI_A_*: which values of A the Arnoldi product reads */
   int32_t precond_precision; /* GMRES_PRECOND_NATIVE (the solver's precision) or GMRES_PRECOND_FP32
                                 (a float32 preconditioner in the float64 solver) */
+  int32_t persistent_spmv;   /* persistent batch schedule: 0 = the Arnoldi SpMV variant of each size
+                                class chosen by the create-time tuner (autotune = 1; else CSR8);
+                                1 + GMRES_PSPMV_* forces one variant for every class */
 } gmres_options;
+
+/* Arnoldi SpMV variants of the persistent batch kernel (all sum each row's
+ * products in storage order, so the choice never changes a result bit):
+ * CSR8 / CSR4: the CSR arrays, a row's entries loaded in groups of 8 / 4;
+ * ELL16: an ELL copy made at create (entry k of every row of a system in one
+ * contiguous slice, 16-bit columns local to the system, a byte of row
+ * length; systems up to 65,536 rows with rows of at most 255 entries, others
+ * fall back to CSR8). */
+enum { GMRES_PSPMV_CSR8 = 0, GMRES_PSPMV_CSR4 = 1, GMRES_PSPMV_ELL16 = 2 };
 
 enum { GMRES_PRECOND_NATIVE = 0, GMRES_PRECOND_FP32 = 1 };
 
@@ -210,7 +222,7 @@ typedef struct {
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
  * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4,
- * arnoldi_a = DEFAULT, precond_precision = NATIVE. */
+ * arnoldi_a = DEFAULT, precond_precision = NATIVE, persistent_spmv = 0. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).
@@ -400,6 +412,22 @@ typedef struct {
 } gmres_kernel_profile;
 int gmres_solve_profiled(gmres_handle h, const double* b, double* x, gmres_result* res,
                          gmres_kernel_profile* prof);
+
+/* The persistent batch schedule's SpMV tuner, one entry per size class
+ * (systems with the same rows per thread of the persistent kernel, n <=
+ * 1024 x rows_per_thread): how many systems, the largest n, the probe time
+ * of each variant on the largest system in microseconds per SpMV (-1: not
+ * timed), and the variant every system of the class runs (GMRES_PSPMV_*).
+ * Copies at most cap entries to out (HOST); *count = the number of classes.
+ * ESTATE on a handle that does not run the persistent schedule. */
+typedef struct {
+  int32_t rows_per_thread;
+  int32_t systems;
+  int32_t largest_n;
+  int32_t variant;
+  double probe_us[3];
+} gmres_tune_class;
+int gmres_batch_tuning(gmres_handle h, gmres_tune_class* out, int32_t cap, int32_t* count);
 
 /* Launch configuration the solver uses for kernel family `family`
  * (GMRES_PK_SPMV .. GMRES_PK_UPDATE) at Arnoldi column j (0 <= j < m), for

@@ -28,6 +28,9 @@ ARNOLDI_A_DEFAULT, ARNOLDI_A_FP64, ARNOLDI_A_FP32 = 0, 1, 2
 ARNOLDI_AS = {"default": ARNOLDI_A_DEFAULT, "fp64": ARNOLDI_A_FP64, "fp32": ARNOLDI_A_FP32}
 PRECOND_NATIVE, PRECOND_FP32 = 0, 1
 PRECOND_PRECISIONS = {"native": PRECOND_NATIVE, "fp32": PRECOND_FP32}
+PSPMV_CSR8, PSPMV_CSR4, PSPMV_ELL16 = 0, 1, 2
+PERSISTENT_SPMV_NAMES = {PSPMV_CSR8: "csr8", PSPMV_CSR4: "csr4", PSPMV_ELL16: "ell16"}
+PERSISTENT_SPMVS = {"tuned": 0, "csr8": 1 + PSPMV_CSR8, "csr4": 1 + PSPMV_CSR4, "ell16": 1 + PSPMV_ELL16}
 
 
 class Options(C.Structure):
@@ -52,6 +55,7 @@ class Options(C.Structure):
         ("ilu_sweeps", C.c_int32),
         ("arnoldi_a", C.c_int32),
         ("precond_precision", C.c_int32),
+        ("persistent_spmv", C.c_int32),
     ]
 
 
@@ -88,6 +92,16 @@ class KernelProfile(C.Structure):
     ]
 
 
+class TuneClass(C.Structure):
+    _fields_ = [
+        ("rows_per_thread", C.c_int32),
+        ("systems", C.c_int32),
+        ("largest_n", C.c_int32),
+        ("variant", C.c_int32),
+        ("probe_us", C.c_double * 3),
+    ]
+
+
 # kernel families of gmres_solve_profiled (GMRES_PK_* in gmres.h)
 PROFILE_KINDS = ["spmv", "pass1", "pass2", "final", "mgs", "residual", "update", "reduce", "precond", "encode"]
 
@@ -113,6 +127,7 @@ _SIGS = {
     "gmres_last_cycle": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _vp, _vp]),
     "gmres_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, C.POINTER(C.c_int32)]),
     "gmres_memory_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "gmres_batch_tuning": (C.c_int, [_vp, C.POINTER(TuneClass), C.c_int32, C.POINTER(C.c_int32)]),
     "gmres_time_kernel": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
     "gmres_solve_profiled": (C.c_int, [_vp, _vp, _vp, C.POINTER(Result), C.POINTER(KernelProfile)]),

@@ -104,6 +104,12 @@ __device__ __forceinline__ double ldd(rsrc_t r, uint32_t vo, uint32_t so) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
   return __hiloint2double((int)v[1], (int)v[0]);
 }
+__device__ __forceinline__ int ldu8(rsrc_t r, uint32_t vo, uint32_t so) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b8(r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ int ldu16(rsrc_t r, uint32_t vo, uint32_t so) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0);
+}
 __device__ __forceinline__ void stf(float x, rsrc_t r, uint32_t vo, uint32_t so) {
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, (int)vo, (int)so, 0);
 }
@@ -122,6 +128,108 @@ __device__ __forceinline__ int64_t uni64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// The descriptors of one system's Arnoldi SpMV.
+struct SpmvSys {
+  rsrc_t rpr, cir, a32r;  // CSR: row pointers of the system, all columns and values up to it
+  rsrc_t ev, ec, el;      // ELL: values, local columns, row lengths
+  int col0;               // global column of the system's first row
+  int ew;                 // ELL width
+  uint32_t pn;            // padded rows (ELL slice stride)
+};
+
+// w = A x over the system's rows (row q of thread t is t + 1024 q), entries in
+// groups of G, each row's products added in storage order; entries past a
+// row are masked (their gathers may fall anywhere, or past x).
+template <int R, int G>
+__device__ __forceinline__ void spmv_csr(const SpmvSys& m, rsrc_t x, float (&w)[R]) {
+  const uint32_t t4 = threadIdx.x * 4u;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const uint32_t so = (uint32_t)q * kPB * 4u;
+    const int k0 = ldi(m.rpr, t4, so), k1 = ldi(m.rpr, t4, so + 4u);
+    float acc = 0.f;
+    for (int kb = k0; kb < k1; kb += G) {
+      float av[G];
+      int cv[G];
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        av[e] = ldf(m.a32r, (uint32_t)(kb + e) * 4u, 0);
+        cv[e] = ldi(m.cir, (uint32_t)(kb + e) * 4u, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < G; ++e) {
+        const float xv = ldf(x, (uint32_t)(cv[e] - m.col0) * 4u, 0);
+        if (kb + e < k1) acc += av[e] * xv;
+      }
+    }
+    w[q] = acc;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// The same products from the ELL copy: slice k holds entry k of every row,
+// so each load of the workgroup is contiguous; slices are read in groups of
+// 8 (a group reaching past the last slice reads zeros through the bounded
+// descriptor, and the row length masks them).
+template <int R>
+__device__ __forceinline__ void spmv_ell(const SpmvSys& m, rsrc_t x, float (&w)[R]) {
+  const uint32_t t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const uint32_t r = (uint32_t)q * kPB;
+    const int len = ldu8(m.el, t, r);  // rows past n: zero
+    float acc = 0.f;
+    for (int kb = 0; kb < m.ew; kb += 8) {
+      float av[8];
+      int cv[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t so = (uint32_t)(kb + e) * m.pn + r;
+        av[e] = ldf(m.ev, t * 4u, so * 4u);
+        cv[e] = ldu16(m.ec, t * 2u, so * 2u);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float xv = ldf(x, (uint32_t)cv[e] * 4u, 0);
+        if (kb + e < len) acc += av[e] * xv;
+      }
+    }
+    w[q] = acc;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void spmv_sys(const SpmvSys& m, int pv, rsrc_t x, float (&w)[R]) {
+  if (pv == PV_ELL16)
+    spmv_ell<R>(m, x, w);
+  else if (pv == PV_CSR4)
+    spmv_csr<R, 4>(m, x, w);
+  else
+    spmv_csr<R, 8>(m, x, w);
+}
+
+__device__ __forceinline__ SpmvSys spmv_sys_of(const KArgs& a, int s, int64_t row0, int n, uint32_t pn,
+                                              uint32_t nz_end, int pv) {
+  SpmvSys m;
+  m.rpr = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
+  m.cir = mkr(a.ci, (uint64_t)nz_end * 4);
+  m.a32r = mkr(a.a32, (uint64_t)nz_end * 4);
+  m.col0 = (int)row0;
+  m.pn = pn;
+  m.ew = 0;
+  if (pv == PV_ELL16) {
+    const int64_t off = uni64(a.ell_off[s]);
+    m.ew = uni(a.ell_w[s]);
+    m.ev = mkr(a.ell_val + off, (uint64_t)m.ew * pn * 4);
+    m.ec = mkr(a.ell_col + off, (uint64_t)m.ew * pn * 2);
+    m.el = mkr(a.ell_len + row0, (uint64_t)n);
+  } else {
+    m.ev = m.ec = m.el = m.rpr;
+  }
+  return m;
+}
+
 // Row q of thread t is r = t + 1024 q.  Every vector of the system is read
 // and written through a descriptor bounded to its n rows: loads past the end
 // return zero and stores past it are dropped, so the row loops need no
@@ -138,8 +246,9 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
   auto col = [&](int i) { return mkr(Vs + (size_t)i * pn, (uint64_t)n * 4); };
   const rsrc_t rpr = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
   const rsrc_t cir = mkr(a.ci, (uint64_t)nz_end * 4);
-  const rsrc_t a32r = mkr(a.a32, (uint64_t)nz_end * 4);
   const rsrc_t a64r = mkr(a.a64, (uint64_t)nz_end * 8);
+  const int pv = a.sys_pv ? uni((int)a.sys_pv[s]) : (int)PV_CSR8;
+  const SpmvSys sm = spmv_sys_of(a, s, row0, n, pn, nz_end, pv);
   const rsrc_t xall = mkr(a.x, (uint64_t)a.ld * 8);         // gathers by global column
   const rsrc_t xs = mkr(a.x + row0, (uint64_t)n * 8);       // this system's rows
   const rsrc_t br = mkr(a.b + row0, (uint64_t)n * 8);
@@ -232,30 +341,8 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
     for (int j = 0; j < m; ++j) {
       __syncthreads();  // v_j complete (stores of every thread)
       const rsrc_t vj = col(j);
-      // ---- w = A v_j (float32); entries are read in groups of 8, the ones
-      // past the row masked (their gathers may fall anywhere, or past v_j)
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const uint32_t so = (uint32_t)q * kPB * 4u;
-        const int k0 = ldi(rpr, t4, so), k1 = ldi(rpr, t4, so + 4u);
-        float acc = 0.f;
-        for (int kb = k0; kb < k1; kb += 8) {
-          float av[8];
-          int cv[8];
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            av[e] = ldf(a32r, (uint32_t)(kb + e) * 4u, 0);
-            cv[e] = ldi(cir, (uint32_t)(kb + e) * 4u, 0);
-          }
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float xv = ldf(vj, (uint32_t)(cv[e] - col0) * 4u, 0);
-            if (kb + e < k1) acc += av[e] * xv;
-          }
-        }
-        w[q] = acc;
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      // ---- w = A v_j (float32), in the system's tuned SpMV variant
+      spmv_sys<R>(sm, pv, vj, w);
       float wp = 0.f;
 #pragma unroll
       for (int q = 0; q < R; ++q) wp += w[q] * w[q];
@@ -419,9 +506,65 @@ __global__ __launch_bounds__(kPB) void k_batch_persistent(KArgs a, const int32_t
   }
 }
 
+template <int R>
+__device__ void probe_system(const KArgs& a, int s, int pv, int reps, float* sink) {
+  const int64_t row0 = uni64(a.sys_row0[s]);
+  const int n = uni(a.sys_n[s]);
+  const int m1 = a.m + 1;
+  const uint32_t pn = (uint32_t)uni(a.sys_nt[s]) * kTile;
+  const uint32_t nz_end = (uint32_t)uni(a.rp[row0 + n]);
+  const SpmvSys sm = spmv_sys_of(a, s, row0, n, pn, nz_end, pv);
+  const rsrc_t x = mkr(static_cast<const float*>(a.V) + (int64_t)m1 * row0, (uint64_t)n * 4);
+  float w[R];
+  float keep = 0.f;
+  for (int it = 0; it < reps; ++it) {
+    spmv_sys<R>(sm, pv, x, w);
+#pragma unroll
+    for (int q = 0; q < R; ++q) keep += w[q];
+  }
+  sink[threadIdx.x] = keep;
+}
+
+__global__ __launch_bounds__(kPB) void k_persistent_probe(KArgs a, int s, int pv, int reps, float* sink) {
+  const int rows = (a.sys_n[s] + kPB - 1) / kPB;
+  if (rows <= 1) probe_system<1>(a, s, pv, reps, sink);
+  else if (rows <= 2) probe_system<2>(a, s, pv, reps, sink);
+  else if (rows <= 4) probe_system<4>(a, s, pv, reps, sink);
+  else if (rows <= 8) probe_system<8>(a, s, pv, reps, sink);
+  else if (rows <= 16) probe_system<16>(a, s, pv, reps, sink);
+  else if (rows <= 32) probe_system<32>(a, s, pv, reps, sink);
+  else probe_system<kMaxPR>(a, s, pv, reps, sink);
+}
+
+__global__ void k_build_ell(KArgs a, int64_t row0, int n, int w, int pn, float* __restrict__ val,
+                            uint16_t* __restrict__ col, uint8_t* __restrict__ len) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= pn) return;
+  const int p0 = r < n ? a.rp[row0 + r] : 0, p1 = r < n ? a.rp[row0 + r + 1] : 0;
+  for (int k = 0; k < w; ++k) {
+    const int p = p0 + k;
+    val[(int64_t)k * pn + r] = p < p1 ? a.a32[p] : 0.0f;
+    col[(int64_t)k * pn + r] = p < p1 ? (uint16_t)(a.ci[p] - row0) : (uint16_t)0;
+  }
+  if (r < n) len[row0 + r] = (uint8_t)(p1 - p0);
+}
+
 __global__ void k_counter_clear(int32_t* counter) { counter[0] = 0; }
 
 }  // namespace
+
+hipError_t launch_persistent_probe(const KArgs& a, int s, int pv, int reps, float* sink, hipStream_t st) {
+  hipLaunchKernelGGL(k_persistent_probe, dim3(1), dim3(kPB), 0, st, a, s, pv, reps, sink);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_ell(const KArgs& a, int s, int64_t row0, int n, int w, int64_t off, int pn,
+                            float* val, uint16_t* col, uint8_t* len, hipStream_t st) {
+  (void)s;
+  hipLaunchKernelGGL(k_build_ell, dim3((pn + 255) / 256), dim3(256), 0, st, a, row0, n, w, pn, val + off,
+                     col + off, len);
+  return hipGetLastError();
+}
 
 hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, hipStream_t st) {
   const int grid = std::max(1, std::min(a.S, a.ncu));

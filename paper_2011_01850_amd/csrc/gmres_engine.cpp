@@ -78,6 +78,7 @@ struct gmres_ctx {
   spai_handle spai = nullptr;    // network instance on this handle's pattern (gmres_spai_infer)
   // persistent schedule: one workgroup per system, one launch per solve
   bool persistent = false;
+  std::vector<gmres_tune_class> tune;  // the SpMV tuner's choice per size class
   int32_t* order = nullptr;      // systems, largest first
   int32_t* counter = nullptr;    // queue position
   hipGraphExec_t pexec = nullptr;
@@ -164,6 +165,7 @@ bool valid_options(const gmres_options* o) {
   if (o->ilu_sweeps < 0 || o->ilu_sweeps > 4096) return false;
   if (o->arnoldi_a < GMRES_ARNOLDI_A_DEFAULT || o->arnoldi_a > GMRES_ARNOLDI_A_FP32) return false;
   if (o->precond_precision != GMRES_PRECOND_NATIVE && o->precond_precision != GMRES_PRECOND_FP32) return false;
+  if (o->persistent_spmv < 0 || o->persistent_spmv > PV_COUNT) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
@@ -559,6 +561,111 @@ void build_graph(gmres_ctx* h) {
   h->gexec = ex;
 }
 
+// Arnoldi SpMV of the persistent batch schedule: ELL copies where a system
+// allows one (n <= 65,536, rows of at most 255 entries), then one variant per
+// size class (rows per thread of the persistent kernel): the one forced by
+// persistent_spmv, else the fastest on the class's largest system by the
+// probe kernel (a few launches of its SpMV alone, between HIP events), else
+// CSR with groups of 8.  Every variant gives bitwise the same products.
+void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
+  KArgs& a = h->a;
+  const int S = a.S;
+  std::vector<int32_t> width(S, 0);
+  std::vector<int64_t> off(S, 0);
+  int64_t total = 0;
+  for (int k = 0; k < S; ++k) {
+    const System& sy = h->sys[k];
+    int wmax = 0;
+    for (int64_t r = sy.row0; r < sy.row0 + sy.n; ++r)
+      wmax = std::max(wmax, h->rp_host[r + 1] - h->rp_host[r]);
+    if (sy.n <= 65536 && wmax <= 255 && wmax > 0) {
+      width[k] = wmax;
+      off[k] = total;
+      total += (int64_t)wmax * sy.nt * kTile;
+    }
+  }
+  const int forced = opt->persistent_spmv;  // 0: tuned, else 1 + PersistentSpmv
+  const bool want_ell = total > 0 && (forced == 0 || forced == 1 + PV_ELL16);
+  if (want_ell) {
+    float* val = h->alloc<float>((size_t)total);
+    uint16_t* col = h->alloc<uint16_t>((size_t)total);
+    uint8_t* len = h->alloc<uint8_t>((size_t)h->ld);
+    hip_check(hipMemsetAsync(len, 0, (size_t)h->ld, h->stream));
+    for (int k = 0; k < S; ++k)
+      if (width[k] > 0)
+        hip_check(launch_build_ell(a, k, h->sys[k].row0, (int)h->sys[k].n, width[k], off[k], h->sys[k].nt * kTile,
+                                   val, col, len, h->stream));
+    a.ell_val = val;
+    a.ell_col = col;
+    a.ell_len = len;
+    int64_t* d_off = h->alloc<int64_t>(S);
+    hip_check(hipMemcpyAsync(d_off, off.data(), S * 8, hipMemcpyHostToDevice, h->stream));
+    a.ell_off = d_off;
+    a.ell_w = upload32(h, width);
+  }
+  // size classes: the rows-per-thread tier of the persistent kernel
+  auto tier = [](int64_t n) {
+    const int64_t rows = (n + 1023) / 1024;
+    int t = 1;
+    while (t < rows && t < kMaxPR) t *= 2;
+    return t;
+  };
+  std::vector<int> classes;
+  for (int k = 0; k < S; ++k)
+    if (std::find(classes.begin(), classes.end(), tier(h->sys[k].n)) == classes.end())
+      classes.push_back(tier(h->sys[k].n));
+  std::sort(classes.begin(), classes.end());
+  std::vector<int8_t> pv(S, PV_CSR8);
+  h->tune.clear();
+  float* sink = opt->autotune && forced == 0 ? h->alloc<float>(1024) : nullptr;
+  for (int c : classes) {
+    gmres_tune_class tc{};
+    tc.rows_per_thread = c;
+    int big = -1;
+    for (int k = 0; k < S; ++k)
+      if (tier(h->sys[k].n) == c) {
+        tc.systems += 1;
+        if (big < 0 || h->sys[k].n > h->sys[big].n) big = k;
+      }
+    tc.largest_n = (int32_t)h->sys[big].n;
+    int choice = PV_CSR8;
+    for (int v = 0; v < PV_COUNT; ++v) tc.probe_us[v] = -1.0;
+    bool all_ell = a.ell_w != nullptr;
+    for (int k = 0; k < S && all_ell; ++k)
+      if (tier(h->sys[k].n) == c) all_ell = width[k] > 0;
+    if (forced > 0) {
+      choice = forced - 1;
+      if (choice == PV_ELL16 && !all_ell) choice = PV_CSR8;  // a system of the class has no ELL copy
+    } else if (sink) {
+      constexpr int kReps = 8;
+      float best = 1e30f;
+      for (int v = 0; v < PV_COUNT; ++v) {
+        if (v == PV_ELL16 && !all_ell) continue;
+        hip_check(launch_persistent_probe(a, big, v, 1, sink, h->stream));
+        hip_check(hipEventRecord(h->ev0, h->stream));
+        hip_check(launch_persistent_probe(a, big, v, kReps, sink, h->stream));
+        hip_check(hipEventRecord(h->ev1, h->stream));
+        hip_check(hipEventSynchronize(h->ev1));
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+        tc.probe_us[v] = 1000.0 * ms / kReps;
+        if (ms < best) {
+          best = ms;
+          choice = v;
+        }
+      }
+    }
+    tc.variant = choice;
+    for (int k = 0; k < S; ++k)
+      if (tier(h->sys[k].n) == c) pv[k] = (int8_t)choice;
+    h->tune.push_back(tc);
+  }
+  int8_t* d_pv = h->alloc<int8_t>(S);
+  hip_check(hipMemcpyAsync(d_pv, pv.data(), S, hipMemcpyHostToDevice, h->stream));
+  a.sys_pv = d_pv;
+  hip_check(hipStreamSynchronize(h->stream));
+}
+
 // Times the Arnoldi SpMV for a few row-block budgets and keeps the fastest.
 void autotune_spmv(gmres_ctx* h) {
   float best = 1e30f;
@@ -874,6 +981,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     h->order = h->alloc<int32_t>(nsys);
     hip_check(hipMemcpy(h->order, ord.data(), nsys * 4, hipMemcpyHostToDevice));
     h->counter = h->alloc<int32_t>(1);
+    setup_persistent_spmv(h, opt);
   } else if (tune) {
     autotune_spmv(h);
   }
@@ -1051,6 +1159,7 @@ void gmres_default_options(gmres_options* o) {
   o->ilu_sweeps = 4;
   o->arnoldi_a = GMRES_ARNOLDI_A_DEFAULT;
   o->precond_precision = GMRES_PRECOND_NATIVE;
+  o->persistent_spmv = 0;
 }
 
 const char* gmres_strerror(int code) {
@@ -1583,6 +1692,19 @@ int gmres_launch_config(gmres_handle hh, int32_t family, int32_t j, int32_t* gri
     return GMRES_OK;
   } catch (const Fail& f) {
     (void)hipGetLastError();
+    return f.code;
+  }
+}
+
+int gmres_batch_tuning(gmres_handle hh, gmres_tune_class* out, int32_t cap, int32_t* count) {
+  try {
+    gmres_ctx* h = get(hh);
+    if (!count || cap < 0 || (cap > 0 && !out)) return GMRES_EINVAL;
+    if (!h->persistent) return GMRES_ESTATE;
+    *count = (int32_t)h->tune.size();
+    for (int32_t k = 0; k < cap && k < (int32_t)h->tune.size(); ++k) out[k] = h->tune[k];
+    return GMRES_OK;
+  } catch (const Fail& f) {
     return f.code;
   }
 }

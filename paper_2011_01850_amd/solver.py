@@ -34,7 +34,7 @@ def _dev(t, dtype, torch):
 def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
              autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
              restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4,
-             arnoldi_a="default") -> L.Options:
+             arnoldi_a="default", precond_precision="native", persistent_spmv="tuned") -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -57,6 +57,8 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.arnoldi_a = L.ARNOLDI_AS[arnoldi_a] if isinstance(arnoldi_a, str) else int(arnoldi_a)
     o.precond_precision = (L.PRECOND_PRECISIONS[precond_precision] if isinstance(precond_precision, str)
                            else int(precond_precision))
+    o.persistent_spmv = (L.PERSISTENT_SPMVS[persistent_spmv] if isinstance(persistent_spmv, str)
+                         else int(persistent_spmv))
     return o
 
 
@@ -273,7 +275,7 @@ class BatchSolver:
                  max_iters=100_000, restart_improve=0.0, stall_cycles=10, use_graph=True, autotune=True,
                  schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
                  restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4,
-                 arnoldi_a="default"):
+                 arnoldi_a="default", persistent_spmv="tuned"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -295,7 +297,8 @@ class BatchSolver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a,
+                            persistent_spmv=persistent_spmv)
         arr64 = C.c_int64 * S
         arrp = C.c_void_p * S
         h = C.c_void_p()
@@ -335,6 +338,20 @@ class BatchSolver:
         cnt = C.c_int32()
         L.check(self.lib.gmres_history(self.h, int(sys), out.ctypes.data, cap, C.byref(cnt)), "gmres_history")
         return out[: min(cnt.value, cap)].copy()
+
+    def tuning(self):
+        """The persistent schedule's SpMV choice per size class (list of dicts), or None."""
+        cnt = C.c_int32()
+        out = (L.TuneClass * 16)()
+        rc = self.lib.gmres_batch_tuning(self.h, out, 16, C.byref(cnt))
+        if rc == L.ESTATE:
+            return None
+        L.check(rc, "gmres_batch_tuning")
+        return [{"rows_per_thread": c.rows_per_thread, "systems": c.systems, "largest_n": c.largest_n,
+                 "variant": L.PERSISTENT_SPMV_NAMES[c.variant],
+                 "probe_us": {L.PERSISTENT_SPMV_NAMES[v]: round(c.probe_us[v], 3) for v in range(3)
+                              if c.probe_us[v] >= 0}}
+                for c in out[: min(cnt.value, 16)]]
 
 
 def encode(w, inv_h, fmt="fp16", out=None, noalloc=False):

@@ -64,7 +64,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                        ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1), ("restart_repeat", 2),
                        ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
                        ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097),
-                       ("arnoldi_a", 3), ("arnoldi_a", -1)]:
+                       ("arnoldi_a", 3), ("arnoldi_a", -1), ("persistent_spmv", -1), ("persistent_spmv", 4)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -135,7 +135,7 @@ def test_handle_checks(lib):
 
 def test_struct_layouts_match_header():
     # offsets that C gives the two structs on x86-64
-    assert C.sizeof(L.Options) == 104
+    assert C.sizeof(L.Options) == 112
     assert L.Options.tol.offset == 8 and L.Options.max_iters.offset == 16
     assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
     assert L.Options.batch_schedule.offset == 60 and L.Options.spmv_block_nnz.offset == 64
@@ -143,6 +143,7 @@ def test_struct_layouts_match_header():
     assert L.Options.restart_on_stall.offset == 76 and L.Options.orth_restart.offset == 80
     assert L.Options.orth_norm.offset == 88 and L.Options.ilu_sweeps.offset == 92
     assert L.Options.arnoldi_a.offset == 96 and L.Options.precond_precision.offset == 100
+    assert L.Options.persistent_spmv.offset == 104
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 
@@ -179,7 +180,8 @@ def test_struct_layouts_match_compiled_header(tmp_path):
         pytest.skip("no C compiler")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "gmres.h"', "int main(void) {"]
-    structs = (("gmres_options", L.Options), ("gmres_result", L.Result), ("gmres_kernel_profile", L.KernelProfile))
+    structs = (("gmres_options", L.Options), ("gmres_result", L.Result), ("gmres_kernel_profile", L.KernelProfile),
+               ("gmres_tune_class", L.TuneClass))
     for cname, ct in structs:
         lines.append(f'  printf("{cname} sizeof %zu\\n", sizeof({cname}));')
         for fname, _ in ct._fields_:
@@ -197,3 +199,25 @@ def test_struct_layouts_match_compiled_header(tmp_path):
         for fname, _ in ct._fields_:
             assert got[(cname, fname)] == getattr(ct, fname).offset, (cname, fname)
     assert got[("GMRES_PK_COUNT", "value")] == len(L.PROFILE_KINDS)
+
+
+def test_binding_forwards_every_solver_option(lib):
+    # every keyword of the Python front end reaches a field of gmres_options
+    import inspect
+
+    from paper_2011_01850_amd import solver as S
+
+    params = inspect.signature(S._options).parameters
+    for cls in (S.Solver, S.BatchSolver):
+        for name in inspect.signature(cls.__init__).parameters:
+            if name in ("self", "row_ptr", "col_idx", "vals", "systems"):
+                continue
+            assert name in params, (cls.__name__, name)
+    o = S._options(30, 1e-9, 500, "mgs", "fp64", "ilu0", 1e-6, 7, False, False, "persistent", 1024, "split",
+                   True, True, 0.5, "frobenius", 0, "fp32", "fp32", "ell16")
+    assert (o.m, o.max_iters, o.ortho, o.precision, o.precond) == (30, 500, L.MGS, L.FP64, L.PRECOND_ILU0)
+    assert (o.stall_cycles, o.use_graph, o.autotune, o.batch_schedule) == (7, 0, 0, L.SCHEDULE_PERSISTENT)
+    assert (o.spmv_block_nnz, o.a_storage, o.restart_repeat, o.restart_on_stall) == (1024, L.A_SPLIT, 1, 1)
+    assert (o.orth_norm, o.ilu_sweeps, o.arnoldi_a) == (L.ORTH_FROBENIUS, 0, L.ARNOLDI_A_FP32)
+    assert (o.precond_precision, o.persistent_spmv) == (L.PRECOND_FP32, 1 + L.PSPMV_ELL16)
+    assert o.tol == 1e-9 and o.restart_improve == 1e-6 and o.orth_restart == 0.5

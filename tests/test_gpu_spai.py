@@ -235,10 +235,10 @@ def test_training_gains_over_jacobi_and_no_preconditioner(lib):
     fewer iterations than Jacobi (the network's own starting point) and far
     fewer than plain GMRES on held-out instances."""
     from paper_2011_01850_amd.train import collect_pairs, evaluate, train
-    Nside = 12
-    train_ids = list(range(6))
+    Nside = 16
+    train_ids = list(range(64))
     test_ids = [2000, 2001]
-    res = train(train_ids, N=Nside, steps=60, lr=3e-3, seed=0, pairs_per_instance=4, log=print)
+    res = train(train_ids, N=Nside, steps=300, lr=3e-3, seed=0, pairs_per_instance=4, batch=4, log=print)
     assert res["loss_last"] < 0.9 * res["loss_first"], res
     ev = evaluate(res["params"], test_ids, N=Nside)
     for r in ev:

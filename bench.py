@@ -45,13 +45,14 @@ PEAK_HBM_GBS = 8000.0
 # counter runs of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by
 # what it reads for a plain 1 GiB device copy: x2.0 and x1.0), averaged over
 # the family's launches that did work.  Valid only for the family they were
-# taken for and the kernel source they were taken from.
-TRAFFIC = {"family": None, "bytes_per_launch": None, "kernel_source_sha256": None}
+# taken for (the kernel instantiation's name) and the kernel source they were
+# taken from.
+TRAFFIC = {"kernel": None, "bytes_per_launch": None, "kernel_source_sha256": None}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 
-def measured_traffic(family):
-    if TRAFFIC["bytes_per_launch"] is None or TRAFFIC["family"] != family:
+def measured_traffic(kernel):
+    if TRAFFIC["bytes_per_launch"] is None or TRAFFIC["kernel"] != kernel:
         return None
     with open(KERNEL_SOURCE, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["kernel_source_sha256"]:
@@ -134,31 +135,60 @@ def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps,
 
 # kernel families of the in-solve profile and the kernels each one launches
 FAMILY_KERNELS = {
-    "spmv": "k_spmv<A,x,w,ARNOLDI> (Arnoldi SpMV w = A v_j, adaptive CSR row blocks)",
-    "pass1": "k_mdot<V,w,L> (CGS projection 1: V^T w; L = 8/16/32/64 columns by j)",
-    "pass2": "k_axpy_mdot<V,w,L> (CGS projection 2 fused: w -= V h1, then V^T w)",
-    "final": "k_final_tile<V,w,L> / k_mgs_final (last pass: w -= V h2, ||w||, v_{j+1})",
-    "mgs": "k_mgs<V,w> (MGS step: completes dot i-1, w -= h v_{i-1}, partial w . v_i)",
-    "residual": "k_spmv<double,double,w,RESID> (float64 restart residual z = b - A x)",
-    "update": "k_update<V> (float64 update x += V y)",
+    "spmv": "k_spmv (Arnoldi SpMV w = A v_j, adaptive CSR row blocks)",
+    "pass1": "k_mdot (CGS projection 1: V^T w)",
+    "pass2": "k_axpy_mdot (CGS projection 2 fused: w -= V h1, then V^T w)",
+    "final": "k_final_tile / k_mgs_final (last pass: w -= V h2 or the last MGS axpy, ||w||, v_{j+1})",
+    "mgs": "k_mgs (MGS step: completes dot i-1, w -= h v_{i-1}, partial w . v_i)",
+    "residual": "k_spmv RESID (float64 restart residual z = b - A x)",
+    "update": "k_update (float64 update x += V y)",
     "precond": "preconditioner application z_j = M v_j",
 }
 HBM_FAMILIES = ("spmv", "pass1", "pass2", "final", "mgs", "residual", "update", "precond")
 # gmres_time_kernel's numbering of the same kernels (the back-to-back harness)
 HARNESS_KERNEL = {"spmv": 0, "pass1": 1, "pass2": 2, "final": 3, "mgs": 4, "residual": 5, "update": 6}
+# template arguments (basis, w) of the basis kernels per precision mode
+TYPES = {"fp32": "float, float", "fp64": "double, double", "fp16": "_Float16, float", "bf16": "gm::bf16_t, float",
+         "limited": "float, double"}
+
+
+def tile_width(j):
+    """Columns of the register tile the CGS passes use at Arnoldi column j (8, 16, 32 or 64)."""
+    L = 8
+    while L < j + 1 and L < 64:
+        L *= 2
+    return L
+
+
+def kernel_units(fam, m, precision, ortho):
+    """The kernels (template instantiations) of one family: (name, columns)."""
+    ty = TYPES.get(precision, "?")
+    if fam in ("pass1", "pass2") or (fam == "final" and ortho == "cgsr"):
+        base = {"pass1": "k_mdot", "pass2": "k_axpy_mdot64" if precision in ("fp64", "limited") else "k_axpy_mdot",
+                "final": "k_final_tile"}[fam]
+        units = {}
+        for j in range(m):
+            units.setdefault(tile_width(j), []).append(j)
+        return [(f"{base}<{ty}, {L}>", cols) for L, cols in sorted(units.items())]
+    if fam == "final":
+        return [(f"k_mgs_final<{ty}>", list(range(m)))]
+    if fam == "mgs":
+        return [(f"k_mgs<{ty}>", list(range(m)))]
+    return [(FAMILY_KERNELS.get(fam, fam), list(range(m)))]
 
 
 def in_solve_profile(solver, b_dev):
     """One more solve on the same handle, every launch between two HIP events
     (gmres_solve_profiled): per kernel family, time per solve, launches, and
-    the time, launches and algorithmic bytes of the launches that did work."""
+    the time, launches and algorithmic bytes of the launches that did work,
+    with the per-column breakdown."""
     x, info, prof = solver.solve_profiled(b_dev)
     fam = {}
     for name, p in prof.items():
         if p["launches"] == 0:
             continue
         e = {"ms_per_solve": round(p["ms"], 4), "launches": p["launches"], "ms_active": round(p["ms_active"], 4),
-             "active_launches": p["active"], "alg_bytes": p["bytes"]}
+             "active_launches": p["active"], "alg_bytes": p["bytes"], "by_col": p["by_col"]}
         if p["active"] and p["bytes"] > 0:
             e["avg_launch_ms"] = round(p["ms_active"] / p["active"], 5)
             e["GB/s"] = round(p["bytes"] / (p["ms_active"] * 1e-3) / 1e9, 1)
@@ -166,44 +196,65 @@ def in_solve_profile(solver, b_dev):
     return x, info, fam
 
 
-def roofline_from_profile(solver, fam, m, reps, families=HBM_FAMILIES):
-    """The dominant family by in-solve time among the HBM-bound ones; achieved =
-    its algorithmic bytes over its summed in-solve launch time.  Beside it: the
-    back-to-back harness time of the same kernel at the last column of its
-    widest instantiation, and the launch configuration."""
-    cands = [k for k in families if k in fam and fam[k]["alg_bytes"] > 0]
-    dom = max(cands, key=lambda k: fam[k]["ms_active"])
-    f = fam[dom]
-    avg_ms = f["ms_active"] / f["active_launches"]
-    per_launch = f["alg_bytes"] / f["active_launches"]
-    achieved = f["alg_bytes"] / (f["ms_active"] * 1e-3) / 1e9
-    traffic = measured_traffic(dom)
-    j_last = m - 1
+def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", families=HBM_FAMILIES):
+    """The dominant kernel: the template instantiation with the most in-solve
+    time among the HBM-bound families; achieved = its algorithmic bytes over
+    its summed in-solve launch time (launches that did work).  Beside it: every
+    instantiation and family, the back-to-back harness time of the same kernel
+    at the last column, and its launch configuration."""
+    units = []
+    for f in families:
+        if f not in fam or fam[f]["alg_bytes"] <= 0:
+            continue
+        for name, cols in kernel_units(f, m, precision, ortho):
+            rows = [fam[f]["by_col"][j] for j in cols]
+            ms_act = sum(r["ms_active"] for r in rows)
+            act = sum(r["active"] for r in rows)
+            if f in ("residual", "update"):  # launched at a cycle's start or end: no column
+                ms_act, act = fam[f]["ms_active"], fam[f]["active_launches"]
+                ms_all, launches, byts = fam[f]["ms_per_solve"], fam[f]["launches"], fam[f]["alg_bytes"]
+            else:
+                ms_all = sum(r["ms"] for r in rows)
+                launches = sum(r["launches"] for r in rows)
+                byts = sum(r["bytes"] for r in rows)
+            if act == 0 or byts <= 0:
+                continue
+            units.append({"kernel": name, "family": f, "columns": f"{cols[0]}..{cols[-1]}", "ms_active": ms_act,
+                          "active_launches": act, "ms_all": ms_all, "launches": launches, "alg_bytes": byts,
+                          "avg_launch_ms": ms_act / act, "GB/s": byts / (ms_act * 1e-3) / 1e9})
+    dom = max(units, key=lambda u: u["ms_active"])
+    achieved = dom["GB/s"]
+    per_launch = dom["alg_bytes"] / dom["active_launches"]
+    traffic = measured_traffic(dom["kernel"])
+    j_last = int(dom["columns"].split("..")[1])
     harness = None
-    if dom in HARNESS_KERNEL:
-        ms, by = solver.time_kernel(HARNESS_KERNEL[dom], j_last, reps)
+    if dom["family"] in HARNESS_KERNEL:
+        ms, by = solver.time_kernel(HARNESS_KERNEL[dom["family"]], j_last, reps)
         harness = {"j": j_last, "reps": reps, "avg_launch_ms": round(ms, 5), "alg_bytes": by,
                    "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
-    cfg = solver.launch_config(dom, j_last) if dom in HARNESS_KERNEL else None
+    cfg = solver.launch_config(dom["family"], j_last) if dom["family"] in HARNESS_KERNEL else None
+    fams = {k: {kk: vv for kk, vv in v.items() if kk != "by_col"} for k, v in fam.items()}
     return {
         "bound": "hbm",
-        "kernel": FAMILY_KERNELS.get(dom, dom),
-        "family": dom,
+        "kernel": dom["kernel"],
+        "family": dom["family"],
+        "family_role": FAMILY_KERNELS.get(dom["family"], dom["family"]),
         "achieved": round(achieved, 1),
         "peak": PEAK_HBM_GBS,
         "unit": "GB/s",
         "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": (round(traffic) if traffic else None),
         "traffic_over_alg": (round(traffic / per_launch, 4) if traffic else None),
-        "avg_launch_ms": round(avg_ms, 5),
+        "avg_launch_ms": round(dom["avg_launch_ms"], 5),
         "alg_bytes_per_launch": round(per_launch),
-        "launches": (f"{f['active_launches']} launches that did work inside one solve (of {f['launches']}; "
-                     f"the rest are gated off after the last cycle converged), each between two HIP events "
-                     f"on the solver's stream"),
-        "avg_launch_ms_all_launches": round(f["ms_per_solve"] / f["launches"], 5),
+        "launches": (f"{dom['active_launches']} launches that did work inside one solve, columns j = "
+                     f"{dom['columns']} of every cycle (of {dom['launches']}; the rest are gated off after the "
+                     f"last cycle converged), each between two HIP events on the solver's stream"),
+        "avg_launch_ms_all_launches": round(dom["ms_all"] / dom["launches"], 5),
         "harness_back_to_back": harness,
         "launch_config_at_j_last": cfg,
-        "in_solve_families": fam,
+        "in_solve_kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in u.items()} for u in units],
+        "in_solve_families": fams,
     }
 
 
@@ -297,7 +348,7 @@ def bench_convdiff3d(args):
     value = mixed["seconds_mean"]
     log("in-solve kernel profile (one more solve, every launch between HIP events) ...")
     _, pinfo, fam = in_solve_profile(solver, b_dev)
-    rf = roofline_from_profile(solver, fam, m, args.roofline_reps)
+    rf = roofline_from_profile(solver, fam, m, args.roofline_reps, args.precision, args.ortho)
     log(f"  dominant family {rf['family']}: {rf['avg_launch_ms'] * 1e3:.1f} us per launch, "
         f"{rf['achieved']:.0f} GB/s ({rf['frac']:.3f} of peak); harness "
         f"{(rf['harness_back_to_back'] or {}).get('avg_launch_ms', 0) * 1e3:.1f} us at j = {m - 1}")
@@ -336,10 +387,9 @@ def bench_convdiff3d(args):
         log("MGS ...")
         mg, xm, sm = mode("mgs", args.precision, args.mgs_steps, min(args.warmup, 1))
         _, _, fam_m = in_solve_profile(sm, b_dev)
-        rf_m = roofline_from_profile(sm, fam_m, m, args.roofline_reps, families=("mgs",))
-        rf_m.pop("in_solve_families")
+        rf_m = roofline_from_profile(sm, fam_m, m, args.roofline_reps, args.precision, "mgs", families=("mgs",))
         sm.close()
-        out_mgs = {"mixed": mg, "roofline_mgs_step": rf_m, "in_solve_families": fam_m}
+        out_mgs = {"mixed": mg, "roofline_mgs_step": rf_m}
         if not args.no_fp64:
             m64, xm64, sm64 = mode("mgs", "fp64", args.mgs_steps, min(args.warmup, 1))
             sm64.close()
@@ -422,7 +472,7 @@ def leg_powerlaw(args):
         o, _ = _summary(t, inf, s, x, pr, b_dev, np)
         if mode in ("fp32", "fp16"):
             _, _, fam = in_solve_profile(s, b_dev)
-            o["spmv_in_solve"] = fam.get("spmv")
+            o["spmv_in_solve"] = {k: v for k, v in fam["spmv"].items() if k != "by_col"}
         s.close()
         out["modes"][mode] = o
     for mode, o in out["modes"].items():
@@ -513,9 +563,8 @@ def bench_powerlaw(args):
         modes[mode] = _mode_summary(t, inf, fwd, s.memory_bytes())
         modes[mode]["backward_error"] = s.backward_error(b_dev, x)[0]
         _, _, fam = in_solve_profile(s, b_dev)
-        kern[mode] = {"in_solve_families": fam,
-                      "spmv_roofline": roofline_from_profile(s, fam, m, args.roofline_reps, families=("spmv",))}
-        kern[mode]["spmv_roofline"].pop("in_solve_families")
+        kern[mode] = {"spmv_roofline": roofline_from_profile(s, fam, m, args.roofline_reps, mode, args.ortho,
+                                                             families=("spmv",))}
         s.close()
     for mode in modes:
         modes[mode]["speedup_vs_fp64"] = round(modes["fp64"]["seconds_mean"] / modes[mode]["seconds_mean"], 3)
@@ -705,6 +754,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     log(f"{len(probs)} systems, sum n = {sum(ns):,}, sum nnz = {sum(nnzs):,}; MGS GMRES({m}) {mode}")
 
+    tuning = []
+
     def run(prec, steps, warmup):
         times, last = [], None
         for it in range(warmup + steps):
@@ -714,6 +765,9 @@ def bench_batch(args):
             xs, infos = bsol.solve(bs)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+            if prec == mode and not tuning:
+                tuning.append(bsol.tuning())
+                log(f"  SpMV tuner: {tuning[0]['variant']} (probe us {tuning[0]['probe_us']})")
             bsol.close()
             if it >= warmup:
                 times.append(dt)
@@ -751,6 +805,7 @@ def bench_batch(args):
         "effective_GBps": round(alg / v / 1e9, 1),
         "alg_bytes": alg,
         "fp64": out64,
+        "spmv_tuning": tuning[0] if tuning else None,
         "roofline": {"bound": "hbm", "kernel": "whole batch solve (algorithmic bytes, MGS with w on chip)",
                      "achieved": round(alg / v / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(alg / v / 1e9 / PEAK_HBM_GBS, 4), "traffic": None},

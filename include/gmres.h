@@ -176,9 +176,9 @@ typedef struct {
   int32_t arnoldi_a;        /* GMRES_ARNOLDI_A_*: which values of A the Arnoldi product reads */
   int32_t precond_precision; /* GMRES_PRECOND_NATIVE (the solver's precision) or GMRES_PRECOND_FP32
                                 (a float32 preconditioner in the float64 solver) */
-  int32_t persistent_spmv;   /* persistent batch schedule: 0 = the Arnoldi SpMV variant of each size
-                                class chosen by the create-time tuner (autotune = 1; else CSR8);
-                                1 + GMRES_PSPMV_* forces one variant for every class */
+  int32_t persistent_spmv;   /* persistent batch schedule: 0 = the Arnoldi SpMV variant chosen by the
+                                create-time tuner (autotune = 1; else CSR8); 1 + GMRES_PSPMV_* forces
+                                one */
 } gmres_options;
 
 /* Arnoldi SpMV variants of the persistent batch kernel (all sum each row's
@@ -186,8 +186,9 @@ typedef struct {
  * CSR8 / CSR4: the CSR arrays, a row's entries loaded in groups of 8 / 4;
  * ELL16: an ELL copy made at create (entry k of every row of a system in one
  * contiguous slice, 16-bit columns local to the system, a byte of row
- * length; systems up to 65,536 rows with rows of at most 255 entries, others
- * fall back to CSR8). */
+ * length; only when every system of the batch has at most 65,536 rows with
+ * at most 255 entries each, else CSR8 runs instead).  One variant runs for
+ * the whole batch (one persistent kernel per variant). */
 enum { GMRES_PSPMV_CSR8 = 0, GMRES_PSPMV_CSR4 = 1, GMRES_PSPMV_ELL16 = 2 };
 
 enum { GMRES_PRECOND_NATIVE = 0, GMRES_PRECOND_FP32 = 1 };
@@ -411,23 +412,29 @@ typedef struct {
   int64_t active;
 } gmres_kernel_profile;
 int gmres_solve_profiled(gmres_handle h, const double* b, double* x, gmres_result* res,
-                         gmres_kernel_profile* prof);
+                         gmres_kernel_profile* prof, gmres_kernel_profile* by_col);
+/* by_col (HOST, may be NULL): GMRES_PK_COUNT x m entries, entry f * m + j
+ * holding family f's launches at Arnoldi column j (the launches of a
+ * cycle's start and end, column -1, are in prof only). */
 
-/* The persistent batch schedule's SpMV tuner, one entry per size class
- * (systems with the same rows per thread of the persistent kernel, n <=
- * 1024 x rows_per_thread): how many systems, the largest n, the probe time
- * of each variant on the largest system in microseconds per SpMV (-1: not
- * timed), and the variant every system of the class runs (GMRES_PSPMV_*).
- * Copies at most cap entries to out (HOST); *count = the number of classes.
- * ESTATE on a handle that does not run the persistent schedule. */
+/* The persistent batch schedule's SpMV tuner.  *variant = the SpMV variant
+ * the handle's persistent kernel runs (GMRES_PSPMV_*); probe_us (HOST, 3
+ * entries, may be NULL) = the tuner's probe time of each variant in
+ * microseconds (-1: not probed): one launch of the real kernel over the
+ * largest system of each size class for a few Arnoldi steps.  out (HOST, at
+ * most cap entries) = the size classes (systems with the same rows per thread
+ * of the persistent kernel, n <= 1024 x rows_per_thread): how many systems,
+ * the largest n, and the system the probe ran for the class; *count = the
+ * number of classes.  ESTATE on a handle that does not run the persistent
+ * schedule. */
 typedef struct {
   int32_t rows_per_thread;
   int32_t systems;
   int32_t largest_n;
-  int32_t variant;
-  double probe_us[3];
+  int32_t probe_system;
 } gmres_tune_class;
-int gmres_batch_tuning(gmres_handle h, gmres_tune_class* out, int32_t cap, int32_t* count);
+int gmres_batch_tuning(gmres_handle h, int32_t* variant, double* probe_us, gmres_tune_class* out, int32_t cap,
+                       int32_t* count);
 
 /* Launch configuration the solver uses for kernel family `family`
  * (GMRES_PK_SPMV .. GMRES_PK_UPDATE) at Arnoldi column j (0 <= j < m), for

@@ -384,6 +384,125 @@ def _cast(v, precision):
     return np.asarray(v, dtype=np.float64 if precision == "fp64" else np.float32)
 
 
+# ---------------------------------------------------------------------------
+# The steps of one restart cycle of Algorithm 1, each on its own.  Precision
+# modes: "fp64"; "fp32" (basis, w and A's Arnoldi copy in float32); "bf16" /
+# "fp16" (the float32 mode with each basis vector stored in a 2-byte format);
+# "limited" (basis, A's Arnoldi copy and M in float32, w and its sums in
+# float64).
+
+class _Basis:
+    """The stored Krylov basis of one cycle: v_i as stored (float64, float32
+    or 2-byte values) with a decode scale each."""
+
+    def __init__(self, m, n, precision):
+        self.precision = precision
+        self.two_byte = precision in ("bf16", "fp16")
+        self.lowp = precision != "fp64"
+        self.limited = precision == "limited"
+        self.V = [None] * (m + 1)
+        self.scale = np.zeros(m + 1)
+        self.n, self.m = n, m
+        self.Vmat = None  # [v_1 .. v_j] as one matrix for CGSR, filled column by column
+
+    def store(self, i, vec, h):
+        """v_i = vec / h in the mode's storage.  For the float32 modes vec is
+        already what the mode holds (float32 w, or the float64 w of the
+        limited mode) and is multiplied by float32(1/h)."""
+        if self.two_byte:
+            self.V[i], self.scale[i] = encode(np.asarray(vec).astype(np.float32), 1.0 / h, self.precision)
+        elif self.lowp:
+            self.V[i], self.scale[i] = (vec * np.float32(1.0 / h)).astype(np.float32), 1.0
+        else:
+            self.V[i], self.scale[i] = vec / h, 1.0
+
+    def vec(self, i):
+        """v_i decoded (float32 in the reduced modes)."""
+        if self.two_byte:
+            return (self.V[i] * np.float32(self.scale[i])).astype(np.float32)
+        return self.V[i]
+
+    def operand(self, i):
+        """v_i as the orthogonalisation reads it (widened in the limited mode)."""
+        return self.V[i].astype(np.float64) if self.limited else self.vec(i)
+
+    def matrix(self, j):
+        """[v_1 .. v_{j+1}] for the CGSR projections (column j added now)."""
+        col = self.operand(j)
+        if self.Vmat is None:
+            self.Vmat = np.empty((self.n, self.m + 1), dtype=col.dtype)
+        self.Vmat[:, j] = col
+        return self.Vmat[:, : j + 1]
+
+
+def _arnoldi_product(A: Matrix, src, a32, a64_values, wide_w):
+    """w = A src: float64 values summed in float64 (rounded once to float32
+    unless w is float64); float32 values widened and summed in float64 (w
+    float64); or the float32 product."""
+    if a64_values:
+        w = A.matvec(np.asarray(src).astype(np.float64))
+        return w if wide_w else w.astype(np.float32)
+    if wide_w:
+        return A.matvec_values(a32, src)
+    return A.matvec32(src, a32)
+
+
+def _mgs(w, basis: _Basis, j):
+    """Modified Gram-Schmidt: for i = 1..j, h_ij = w . v_i, w -= h_ij v_i
+    (h_ij rounded to float32 where w is float32)."""
+    hcol = np.zeros(j + 1)
+    single = basis.lowp and not basis.limited
+    for i in range(j + 1):
+        vi = basis.operand(i)
+        hij = float(np.dot(w, vi))
+        hcol[i] = hij
+        w = (w - (np.float32(hij) if single else hij) * vi).astype(w.dtype)
+    return w, hcol
+
+
+def _cgsr(w, basis: _Basis, j):
+    """CGSR: classical Gram-Schmidt, then its re-orthogonalisation pass, each
+    one matrix-vector product with the stored basis; h = h1 + h2."""
+    hcol = np.zeros(j + 1)
+    Vj = basis.matrix(j)
+    for _ in range(2):
+        hp = Vj.T @ w
+        w = (w - Vj @ hp.astype(w.dtype)).astype(w.dtype)
+        hcol += hp.astype(np.float64)
+    return w, hcol
+
+
+def _givens_step(H, cs, sn, s, j):
+    """Column j of H: apply the earlier rotations, form rotation j, update
+    (s_j, s_{j+1}) and zero h_{j+1,j}."""
+    for i in range(j):
+        a, c = H[i, j], H[i + 1, j]
+        H[i, j] = cs[i] * a + sn[i] * c
+        H[i + 1, j] = -sn[i] * a + cs[i] * c
+    cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
+    s[j + 1] = -sn[j] * s[j]
+    s[j] = cs[j] * s[j]
+    H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+    H[j + 1, j] = 0.0
+
+
+class _OrthMonitor:
+    """Loss of orthogonality of the cycle's basis: ||S_k|| after each new vector."""
+
+    def __init__(self, m, norm):
+        self.OU = np.zeros((m + 1, m + 1))
+        self.OS = np.zeros((m + 1, m + 1))
+        self.fro2 = 0.0
+        self.norm = norm
+
+    def add(self, basis: _Basis, c):
+        vn = basis.vec(c).astype(np.float64)
+        u = np.array([float(np.dot(basis.vec(i).astype(np.float64), vn)) for i in range(c)])
+        sv = orth_s_append(self.OU, self.OS, c, u)
+        self.fro2 += float(sv @ sv)
+        return math.sqrt(self.fro2) if self.norm == "frobenius" else power_norm(self.OS[: c + 1, : c + 1])
+
+
 def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs",
           precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
           fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy",
@@ -433,14 +552,10 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     if update_fp32:
         x = x.astype(np.float32).astype(np.float64)
-    lowp = precision != "fp64"  # reduced-precision storage of the basis (and of A's Arnoldi copy)
-    # the limited solver of the convergence study (section 4.1): only A's
-    # Arnoldi copy, M and the basis are stored in float32; w, the dot
-    # products and the product's sums stay float64
-    limited = precision == "limited"
-    two_byte = precision in ("bf16", "fp16")
+    lowp = precision != "fp64"
     wide_w = precision in ("fp64", "limited")  # w, its dots and the product's sums in float64
     a64_arnoldi = arnoldi_a == "fp64" or (arnoldi_a == "default" and precision == "fp64")
+    orthogonalize = _mgs if ortho == "mgs" else _cgsr
     total = 0
     restarts = 0
     hist, arn, cyc = [], [], []
@@ -486,8 +601,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
             fallback_used = True
         prev_beta = beta
 
-        V = [None] * (m + 1)  # stored basis entries (float32 / float64)
-        scale = np.zeros(m + 1)  # decode scale per vector
+        basis = _Basis(m, n, precision)
         Z = [None] * m
         H = np.zeros((m + 1, m))
         Hbar = np.zeros((m + 1, m))
@@ -495,68 +609,19 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         sn = np.zeros(m)
         s = np.zeros(m + 1)
         s[0] = beta  # s_1 = beta
-        if two_byte:
-            V[0], scale[0] = encode(z.astype(np.float32), 1.0 / beta, precision)
-        elif lowp:
-            V[0] = (z.astype(np.float32) * np.float32(1.0 / beta)).astype(np.float32)
-            scale[0] = 1.0
-        else:
-            V[0] = z / beta
-            scale[0] = 1.0
-
-        def basis(i):
-            if two_byte:
-                return (V[i] * np.float32(scale[i])).astype(np.float32)
-            return V[i]
-
-        def operand(i):  # basis vector i as the orthogonalisation reads it
-            return V[i].astype(np.float64) if limited else basis(i)
-
+        basis.store(0, z.astype(np.float32) if lowp else z, beta)
+        monitor = _OrthMonitor(m, orth_norm) if orth_restart > 0.0 else None
         k = 0
-        # CGSR reads the stored basis as one matrix [v_1 .. v_j]: its columns
-        # are filled in as they are formed (a view, not a fresh copy per step)
-        Vmat = None
         W = []  # (record) w after orthogonalisation, before normalisation, per step
         cycle_arn = []
         ares = [beta]  # |s_1| .. |s_{j+1}| of this cycle
-        if orth_restart > 0.0:
-            OU = np.zeros((m + 1, m + 1))
-            OS = np.zeros((m + 1, m + 1))
-            fro2 = 0.0
         for j in range(m):
-            vj = basis(j)
             # w <- A v_j (flexible form: z_j = M v_j, w <- A z_j)
+            vj = basis.vec(j)
             if use_pc:
                 Z[j] = _cast(precond(vj), precision)
-                src = Z[j]
-            else:
-                src = vj
-            if a64_arnoldi:  # float64 values: float64 sums, rounded once where w is float32
-                w = A.matvec(np.asarray(src).astype(np.float64))
-                if not wide_w:
-                    w = w.astype(np.float32)
-            elif wide_w:  # float32 values widened, float64 sums
-                w = A.matvec_values(a32, src)
-            else:
-                w = A.matvec32(src, a32)
-            # orthogonalize(w, V_j)
-            hcol = np.zeros(j + 1)
-            if ortho == "mgs":
-                for i in range(j + 1):
-                    vi = operand(i)
-                    hij = float(np.dot(w, vi))
-                    hcol[i] = hij
-                    w = (w - (np.float32(hij) if lowp and not limited else hij) * vi).astype(w.dtype)
-            else:
-                col = operand(j)
-                if Vmat is None:
-                    Vmat = np.empty((n, m + 1), dtype=col.dtype)
-                Vmat[:, j] = col
-                Vj = Vmat[:, : j + 1]
-                for _ in range(2):  # classical Gram-Schmidt, then its re-orthogonalisation pass
-                    hp = Vj.T @ w
-                    w = (w - Vj @ hp.astype(w.dtype)).astype(w.dtype)
-                    hcol += hp.astype(np.float64)
+            w = _arnoldi_product(A, Z[j] if use_pc else vj, a32, a64_arnoldi, wide_w)
+            w, hcol = orthogonalize(w, basis, j)
             hnext = float(np.linalg.norm(w.astype(np.float64)))
             if record:
                 W.append(w.astype(np.float64))
@@ -565,31 +630,15 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
             Hbar[: j + 2, j] = H[: j + 2, j]
             total += 1
             k = j + 1
-            # apply the previous rotations to the new column
-            for i in range(j):
-                a, c = H[i, j], H[i + 1, j]
-                H[i, j] = cs[i] * a + sn[i] * c
-                H[i + 1, j] = -sn[i] * a + cs[i] * c
-            # form rotation j and update (s_j, s_{j+1}) and (h_jj, h_{j+1,j})
-            cs[j], sn[j] = givens(H[j, j], H[j + 1, j])
-            s[j + 1] = -sn[j] * s[j]
-            s[j] = cs[j] * s[j]
-            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
-            H[j + 1, j] = 0.0
+            _givens_step(H, cs, sn, s, j)
             cycle_arn.append(abs(s[j + 1]) / bn)
             ares.append(abs(s[j + 1]))
             if hnext == 0.0 or not math.isfinite(hnext):
                 if not math.isfinite(hnext):
                     k = j  # drop the non-finite column
                 break
-            if two_byte:
-                V[j + 1], scale[j + 1] = encode(w.astype(np.float32), 1.0 / hnext, precision)
-            elif lowp:
-                V[j + 1] = (w * np.float32(1.0 / hnext)).astype(np.float32)
-                scale[j + 1] = 1.0
-            else:
-                V[j + 1] = w / hnext
-                scale[j + 1] = 1.0
+            basis.store(j + 1, w, hnext)
+            # restart conditions: the estimate, the budget, the triggers
             if abs(s[j + 1]) / bn <= tol or total >= max_iters:
                 break
             first_stage = not restart_repeat or klimit == 0
@@ -599,21 +648,15 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 break
             if restart_on_stall and j + 1 - win >= 0 and ares[j + 1] > ares[j + 1 - win] / 1.001:
                 break
-            if orth_restart > 0.0:
-                vn = basis(j + 1).astype(np.float64)
-                u = np.array([float(np.dot(basis(i).astype(np.float64), vn)) for i in range(j + 1)])
-                sv = orth_s_append(OU, OS, j + 1, u)
-                fro2 += float(sv @ sv)
-                nrm = math.sqrt(fro2) if orth_norm == "frobenius" else power_norm(OS[: j + 2, : j + 2])
-                if nrm >= orth_restart:
-                    break
+            if monitor is not None and monitor.add(basis, j + 1) >= orth_restart:
+                break
         if restart_repeat and klimit == 0 and k > 0:
             klimit = k
         # correction u = V_j H^-1 s (Z y in the flexible form), applied in full precision
         y, kk = back_solve(H, s, k, U32 if lowp else U64)
         u = np.zeros(n)
         for i in range(kk):
-            src = Z[i] if use_pc else basis(i)
+            src = Z[i] if use_pc else basis.vec(i)
             u += y[i] * src.astype(np.float64)
         if update_fp32:
             x = (x.astype(np.float32) + u.astype(np.float32)).astype(np.float64)
@@ -622,7 +665,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         restarts += 1
         arn.append(cycle_arn)
         if record:
-            cyc.append({"V": [basis(i).astype(np.float64) for i in range(k + 1) if V[i] is not None],
+            cyc.append({"V": [basis.vec(i).astype(np.float64) for i in range(k + 1) if basis.V[i] is not None],
                         "Hbar": Hbar[: k + 1, :k].copy(), "H": H[:k, :k].copy(), "s": s[: k + 1].copy(),
                         "k": k, "beta": beta, "y": y, "cs": cs[:k].copy(), "sn": sn[:k].copy(), "W": W})
     return Result(x, status, total, restarts, hist[-1], hist, arn, cyc, fallback_used)

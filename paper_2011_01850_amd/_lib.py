@@ -97,8 +97,7 @@ class TuneClass(C.Structure):
         ("rows_per_thread", C.c_int32),
         ("systems", C.c_int32),
         ("largest_n", C.c_int32),
-        ("variant", C.c_int32),
-        ("probe_us", C.c_double * 3),
+        ("probe_system", C.c_int32),
     ]
 
 
@@ -127,10 +126,12 @@ _SIGS = {
     "gmres_last_cycle": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), _vp, _vp]),
     "gmres_history": (C.c_int, [_vp, C.c_int32, _vp, C.c_int32, C.POINTER(C.c_int32)]),
     "gmres_memory_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
-    "gmres_batch_tuning": (C.c_int, [_vp, C.POINTER(TuneClass), C.c_int32, C.POINTER(C.c_int32)]),
+    "gmres_batch_tuning": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(TuneClass),
+                                     C.c_int32, C.POINTER(C.c_int32)]),
     "gmres_time_kernel": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]),
-    "gmres_solve_profiled": (C.c_int, [_vp, _vp, _vp, C.POINTER(Result), C.POINTER(KernelProfile)]),
+    "gmres_solve_profiled": (C.c_int, [_vp, _vp, _vp, C.POINTER(Result), C.POINTER(KernelProfile),
+                                       C.POINTER(KernelProfile)]),
     "gmres_launch_config": (C.c_int, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "gmres_spai_infer": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),

@@ -128,14 +128,101 @@ __device__ __forceinline__ int64_t uni64(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// The descriptors of one system's Arnoldi SpMV.
-struct SpmvSys {
-  rsrc_t rpr, cir, a32r;  // CSR: row pointers of the system, all columns and values up to it
-  rsrc_t ev, ec, el;      // ELL: values, local columns, row lengths
-  int col0;               // global column of the system's first row
-  int ew;                 // ELL width
-  uint32_t pn;            // padded rows (ELL slice stride)
+// What the persistent kernel reads, packed: the fields it uses of the
+// engine's argument block, in one small kernel-argument block (the full
+// block keeps more scalar registers live and spills them).
+struct PArgs {
+  const int32_t* rp;
+  const int32_t* ci;
+  const float* a32;
+  const double* a64;
+  float* V;
+  double* x;
+  const double* b;
+  double* Hbar;
+  double* hist;
+  SysState* st;
+  const int64_t* sys_row0;
+  const int32_t* sys_n;
+  const int32_t* sys_nt;
+  const float* ell_val;
+  const uint16_t* ell_col;
+  const uint8_t* ell_len;
+  const int64_t* ell_off;
+  const int32_t* ell_w;
+  double tol;
+  double restart_improve;
+  int64_t max_iters;
+  int64_t ld;
+  int32_t S;
+  int32_t m;
+  int32_t stall_cycles;
+  int32_t stall_win;
+  int32_t restart_repeat;
+  int32_t restart_on_stall;
 };
+
+PArgs pargs_of(const KArgs& k) {
+  PArgs p;
+  p.rp = k.rp;
+  p.ci = k.ci;
+  p.a32 = k.a32;
+  p.a64 = k.a64;
+  p.V = static_cast<float*>(k.V);
+  p.x = k.x;
+  p.b = k.b;
+  p.Hbar = k.Hbar;
+  p.hist = k.hist;
+  p.st = k.st;
+  p.sys_row0 = k.sys_row0;
+  p.sys_n = k.sys_n;
+  p.sys_nt = k.sys_nt;
+  p.ell_val = k.ell_val;
+  p.ell_col = k.ell_col;
+  p.ell_len = k.ell_len;
+  p.ell_off = k.ell_off;
+  p.ell_w = k.ell_w;
+  p.tol = k.tol;
+  p.restart_improve = k.restart_improve;
+  p.max_iters = k.max_iters;
+  p.ld = k.ld;
+  p.S = k.S;
+  p.m = k.m;
+  p.stall_cycles = k.stall_cycles;
+  p.stall_win = k.stall_win;
+  p.restart_repeat = k.restart_repeat;
+  p.restart_on_stall = k.restart_on_stall;
+  return p;
+}
+
+// The descriptors of one system's Arnoldi SpMV (the ones its variant reads).
+struct SpmvSys {
+  rsrc_t r0, r1, r2;  // CSR: row pointers of the system, columns, values; ELL: values, columns, lengths
+  int col0;           // global column of the system's first row
+  int ew;             // ELL width
+  uint32_t pn;        // padded rows (ELL slice stride)
+};
+
+template <int PV>
+__device__ __forceinline__ SpmvSys spmv_sys_of(const PArgs& a, int s, int64_t row0, int n, uint32_t pn,
+                                              uint32_t nz_end) {
+  SpmvSys m;
+  m.col0 = (int)row0;
+  m.pn = pn;
+  m.ew = 0;
+  if constexpr (PV == PV_ELL16) {
+    const int64_t off = uni64(a.ell_off[s]);
+    m.ew = uni(a.ell_w[s]);
+    m.r0 = mkr(a.ell_val + off, (uint64_t)m.ew * pn * 4);
+    m.r1 = mkr(a.ell_col + off, (uint64_t)m.ew * pn * 2);
+    m.r2 = mkr(a.ell_len + row0, (uint64_t)n);
+  } else {
+    m.r0 = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
+    m.r1 = mkr(a.ci, (uint64_t)nz_end * 4);
+    m.r2 = mkr(a.a32, (uint64_t)nz_end * 4);
+  }
+  return m;
+}
 
 // w = A x over the system's rows (row q of thread t is t + 1024 q), entries in
 // groups of G, each row's products added in storage order; entries past a
@@ -146,15 +233,15 @@ __device__ __forceinline__ void spmv_csr(const SpmvSys& m, rsrc_t x, float (&w)[
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const uint32_t so = (uint32_t)q * kPB * 4u;
-    const int k0 = ldi(m.rpr, t4, so), k1 = ldi(m.rpr, t4, so + 4u);
+    const int k0 = ldi(m.r0, t4, so), k1 = ldi(m.r0, t4, so + 4u);
     float acc = 0.f;
     for (int kb = k0; kb < k1; kb += G) {
       float av[G];
       int cv[G];
 #pragma unroll
       for (int e = 0; e < G; ++e) {
-        av[e] = ldf(m.a32r, (uint32_t)(kb + e) * 4u, 0);
-        cv[e] = ldi(m.cir, (uint32_t)(kb + e) * 4u, 0);
+        av[e] = ldf(m.r2, (uint32_t)(kb + e) * 4u, 0);
+        cv[e] = ldi(m.r1, (uint32_t)(kb + e) * 4u, 0);
       }
 #pragma unroll
       for (int e = 0; e < G; ++e) {
@@ -177,7 +264,7 @@ __device__ __forceinline__ void spmv_ell(const SpmvSys& m, rsrc_t x, float (&w)[
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const uint32_t r = (uint32_t)q * kPB;
-    const int len = ldu8(m.el, t, r);  // rows past n: zero
+    const int len = ldu8(m.r2, t, r);  // rows past n: zero
     float acc = 0.f;
     for (int kb = 0; kb < m.ew; kb += 8) {
       float av[8];
@@ -185,8 +272,8 @@ __device__ __forceinline__ void spmv_ell(const SpmvSys& m, rsrc_t x, float (&w)[
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const uint32_t so = (uint32_t)(kb + e) * m.pn + r;
-        av[e] = ldf(m.ev, t * 4u, so * 4u);
-        cv[e] = ldu16(m.ec, t * 2u, so * 2u);
+        av[e] = ldf(m.r0, t * 4u, so * 4u);
+        cv[e] = ldu16(m.r1, t * 2u, so * 2u);
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -199,56 +286,34 @@ __device__ __forceinline__ void spmv_ell(const SpmvSys& m, rsrc_t x, float (&w)[
   }
 }
 
-template <int R>
-__device__ __forceinline__ void spmv_sys(const SpmvSys& m, int pv, rsrc_t x, float (&w)[R]) {
-  if (pv == PV_ELL16)
+template <int R, int PV>
+__device__ __forceinline__ void spmv_sys(const SpmvSys& m, rsrc_t x, float (&w)[R]) {
+  if constexpr (PV == PV_ELL16)
     spmv_ell<R>(m, x, w);
-  else if (pv == PV_CSR4)
+  else if constexpr (PV == PV_CSR4)
     spmv_csr<R, 4>(m, x, w);
   else
     spmv_csr<R, 8>(m, x, w);
-}
-
-__device__ __forceinline__ SpmvSys spmv_sys_of(const KArgs& a, int s, int64_t row0, int n, uint32_t pn,
-                                              uint32_t nz_end, int pv) {
-  SpmvSys m;
-  m.rpr = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
-  m.cir = mkr(a.ci, (uint64_t)nz_end * 4);
-  m.a32r = mkr(a.a32, (uint64_t)nz_end * 4);
-  m.col0 = (int)row0;
-  m.pn = pn;
-  m.ew = 0;
-  if (pv == PV_ELL16) {
-    const int64_t off = uni64(a.ell_off[s]);
-    m.ew = uni(a.ell_w[s]);
-    m.ev = mkr(a.ell_val + off, (uint64_t)m.ew * pn * 4);
-    m.ec = mkr(a.ell_col + off, (uint64_t)m.ew * pn * 2);
-    m.el = mkr(a.ell_len + row0, (uint64_t)n);
-  } else {
-    m.ev = m.ec = m.el = m.rpr;
-  }
-  return m;
 }
 
 // Row q of thread t is r = t + 1024 q.  Every vector of the system is read
 // and written through a descriptor bounded to its n rows: loads past the end
 // return zero and stores past it are dropped, so the row loops need no
 // guards and a thread keeps up to 16 loads in flight.
-template <int R>
-__device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
+template <int R, int PV>
+__device__ __forceinline__ void p_system(const PArgs& a, int s, PShared& sh) {
   const int t = threadIdx.x;
   const int m = a.m, M1 = m + 1;
   const int64_t row0 = uni64(a.sys_row0[s]);
   const int n = uni(a.sys_n[s]);
   const uint32_t pn = (uint32_t)uni(a.sys_nt[s]) * kTile;  // column stride of this system's basis
   const uint32_t nz_end = (uint32_t)uni(a.rp[row0 + n]);    // entries of systems up to this one
-  float* Vs = static_cast<float*>(a.V) + (int64_t)M1 * row0;
+  float* Vs = a.V + (int64_t)M1 * row0;
   auto col = [&](int i) { return mkr(Vs + (size_t)i * pn, (uint64_t)n * 4); };
   const rsrc_t rpr = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
   const rsrc_t cir = mkr(a.ci, (uint64_t)nz_end * 4);
   const rsrc_t a64r = mkr(a.a64, (uint64_t)nz_end * 8);
-  const int pv = a.sys_pv ? uni((int)a.sys_pv[s]) : (int)PV_CSR8;
-  const SpmvSys sm = spmv_sys_of(a, s, row0, n, pn, nz_end, pv);
+  const SpmvSys sm = spmv_sys_of<PV>(a, s, row0, n, pn, nz_end);
   const rsrc_t xall = mkr(a.x, (uint64_t)a.ld * 8);         // gathers by global column
   const rsrc_t xs = mkr(a.x + row0, (uint64_t)n * 8);       // this system's rows
   const rsrc_t br = mkr(a.b + row0, (uint64_t)n * 8);
@@ -342,7 +407,7 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
       __syncthreads();  // v_j complete (stores of every thread)
       const rsrc_t vj = col(j);
       // ---- w = A v_j (float32), in the system's tuned SpMV variant
-      spmv_sys<R>(sm, pv, vj, w);
+      spmv_sys<R, PV>(sm, vj, w);
       float wp = 0.f;
 #pragma unroll
       for (int q = 0; q < R; ++q) wp += w[q] * w[q];
@@ -482,7 +547,8 @@ __device__ __forceinline__ void p_system(const KArgs& a, int s, PShared& sh) {
   __syncthreads();  // the next system reuses the shared state
 }
 
-__global__ __launch_bounds__(kPB) void k_batch_persistent(KArgs a, const int32_t* __restrict__ order,
+template <int PV>
+__global__ __launch_bounds__(kPB) void k_batch_persistent(PArgs a, const int32_t* __restrict__ order,
                                                           int32_t* counter) {
   __shared__ PShared sh;
   for (;;) {
@@ -496,44 +562,14 @@ __global__ __launch_bounds__(kPB) void k_batch_persistent(KArgs a, const int32_t
     if (q >= a.S) break;
     const int s = __builtin_amdgcn_readfirstlane(order[q]);
     const int rows = (a.sys_n[s] + kPB - 1) / kPB;
-    if (rows <= 1) p_system<1>(a, s, sh);
-    else if (rows <= 2) p_system<2>(a, s, sh);
-    else if (rows <= 4) p_system<4>(a, s, sh);
-    else if (rows <= 8) p_system<8>(a, s, sh);
-    else if (rows <= 16) p_system<16>(a, s, sh);
-    else if (rows <= 32) p_system<32>(a, s, sh);
-    else p_system<kMaxPR>(a, s, sh);
+    if (rows <= 1) p_system<1, PV>(a, s, sh);
+    else if (rows <= 2) p_system<2, PV>(a, s, sh);
+    else if (rows <= 4) p_system<4, PV>(a, s, sh);
+    else if (rows <= 8) p_system<8, PV>(a, s, sh);
+    else if (rows <= 16) p_system<16, PV>(a, s, sh);
+    else if (rows <= 32) p_system<32, PV>(a, s, sh);
+    else p_system<kMaxPR, PV>(a, s, sh);
   }
-}
-
-template <int R>
-__device__ void probe_system(const KArgs& a, int s, int pv, int reps, float* sink) {
-  const int64_t row0 = uni64(a.sys_row0[s]);
-  const int n = uni(a.sys_n[s]);
-  const int m1 = a.m + 1;
-  const uint32_t pn = (uint32_t)uni(a.sys_nt[s]) * kTile;
-  const uint32_t nz_end = (uint32_t)uni(a.rp[row0 + n]);
-  const SpmvSys sm = spmv_sys_of(a, s, row0, n, pn, nz_end, pv);
-  const rsrc_t x = mkr(static_cast<const float*>(a.V) + (int64_t)m1 * row0, (uint64_t)n * 4);
-  float w[R];
-  float keep = 0.f;
-  for (int it = 0; it < reps; ++it) {
-    spmv_sys<R>(sm, pv, x, w);
-#pragma unroll
-    for (int q = 0; q < R; ++q) keep += w[q];
-  }
-  sink[threadIdx.x] = keep;
-}
-
-__global__ __launch_bounds__(kPB) void k_persistent_probe(KArgs a, int s, int pv, int reps, float* sink) {
-  const int rows = (a.sys_n[s] + kPB - 1) / kPB;
-  if (rows <= 1) probe_system<1>(a, s, pv, reps, sink);
-  else if (rows <= 2) probe_system<2>(a, s, pv, reps, sink);
-  else if (rows <= 4) probe_system<4>(a, s, pv, reps, sink);
-  else if (rows <= 8) probe_system<8>(a, s, pv, reps, sink);
-  else if (rows <= 16) probe_system<16>(a, s, pv, reps, sink);
-  else if (rows <= 32) probe_system<32>(a, s, pv, reps, sink);
-  else probe_system<kMaxPR>(a, s, pv, reps, sink);
 }
 
 __global__ void k_build_ell(KArgs a, int64_t row0, int n, int w, int pn, float* __restrict__ val,
@@ -553,11 +589,6 @@ __global__ void k_counter_clear(int32_t* counter) { counter[0] = 0; }
 
 }  // namespace
 
-hipError_t launch_persistent_probe(const KArgs& a, int s, int pv, int reps, float* sink, hipStream_t st) {
-  hipLaunchKernelGGL(k_persistent_probe, dim3(1), dim3(kPB), 0, st, a, s, pv, reps, sink);
-  return hipGetLastError();
-}
-
 hipError_t launch_build_ell(const KArgs& a, int s, int64_t row0, int n, int w, int64_t off, int pn,
                             float* val, uint16_t* col, uint8_t* len, hipStream_t st) {
   (void)s;
@@ -566,10 +597,20 @@ hipError_t launch_build_ell(const KArgs& a, int s, int64_t row0, int n, int w, i
   return hipGetLastError();
 }
 
-hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, hipStream_t st) {
+hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, int pv, hipStream_t st) {
   const int grid = std::max(1, std::min(a.S, a.ncu));
+  const PArgs p = pargs_of(a);
   hipLaunchKernelGGL(k_counter_clear, dim3(1), dim3(1), 0, st, counter);
-  hipLaunchKernelGGL(k_batch_persistent, dim3(grid), dim3(kPB), 0, st, a, order, counter);
+  switch (pv) {
+    case PV_CSR4:
+      hipLaunchKernelGGL(k_batch_persistent<PV_CSR4>, dim3(grid), dim3(kPB), 0, st, p, order, counter);
+      break;
+    case PV_ELL16:
+      hipLaunchKernelGGL(k_batch_persistent<PV_ELL16>, dim3(grid), dim3(kPB), 0, st, p, order, counter);
+      break;
+    default:
+      hipLaunchKernelGGL(k_batch_persistent<PV_CSR8>, dim3(grid), dim3(kPB), 0, st, p, order, counter);
+  }
   return hipGetLastError();
 }
 

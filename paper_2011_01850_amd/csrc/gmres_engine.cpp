@@ -78,7 +78,9 @@ struct gmres_ctx {
   spai_handle spai = nullptr;    // network instance on this handle's pattern (gmres_spai_infer)
   // persistent schedule: one workgroup per system, one launch per solve
   bool persistent = false;
-  std::vector<gmres_tune_class> tune;  // the SpMV tuner's choice per size class
+  std::vector<gmres_tune_class> tune;  // size classes and their probe systems
+  double tune_probe_us[3] = {-1.0, -1.0, -1.0};  // probe time per SpMV variant
+  int pv = 0;                          // the persistent kernel's SpMV variant
   int32_t* order = nullptr;      // systems, largest first
   int32_t* counter = nullptr;    // queue position
   hipGraphExec_t pexec = nullptr;
@@ -482,7 +484,10 @@ struct ProfPool {
   hipEvent_t get() {
     if (used == ev.size()) {
       hipEvent_t e = nullptr;
-      hip_check(hipEventCreate(&e));
+      // timing only: no system-scope release (its cache write-back and
+      // invalidation would both inflate the bracketed time and evict what the
+      // next kernel of the solve reuses)
+      hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       ev.push_back(e);
     }
     return ev[used++];
@@ -561,18 +566,26 @@ void build_graph(gmres_ctx* h) {
   h->gexec = ex;
 }
 
-// Arnoldi SpMV of the persistent batch schedule: ELL copies where a system
-// allows one (n <= 65,536, rows of at most 255 entries), then one variant per
-// size class (rows per thread of the persistent kernel): the one forced by
-// persistent_spmv, else the fastest on the class's largest system by the
-// probe kernel (a few launches of its SpMV alone, between HIP events), else
-// CSR with groups of 8.  Every variant gives bitwise the same products.
+// Arnoldi SpMV of the persistent batch schedule, one kernel per variant: the
+// one forced by persistent_spmv, else (autotune) the fastest of CSR8, CSR4
+// and (when every system allows an ELL copy: n <= 65,536, rows of at most 255
+// entries) ELL16 on a probe of the real kernel: the largest system of each
+// size class (rows per thread), a few Arnoldi steps from b = const, x = 0,
+// one untimed and one timed launch per variant between HIP events; else CSR8.
+// Every variant gives bitwise the same results.
 void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
   KArgs& a = h->a;
   const int S = a.S;
+  auto tier = [](int64_t n) {
+    const int64_t rows = (n + 1023) / 1024;
+    int t = 1;
+    while (t < rows && t < kMaxPR) t *= 2;
+    return t;
+  };
   std::vector<int32_t> width(S, 0);
   std::vector<int64_t> off(S, 0);
   int64_t total = 0;
+  bool all_ell = true;
   for (int k = 0; k < S; ++k) {
     const System& sy = h->sys[k];
     int wmax = 0;
@@ -582,19 +595,21 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
       width[k] = wmax;
       off[k] = total;
       total += (int64_t)wmax * sy.nt * kTile;
+    } else {
+      all_ell = false;
     }
   }
   const int forced = opt->persistent_spmv;  // 0: tuned, else 1 + PersistentSpmv
-  const bool want_ell = total > 0 && (forced == 0 || forced == 1 + PV_ELL16);
-  if (want_ell) {
+  const bool tune = forced == 0 && opt->autotune;
+  const bool build_ell = all_ell && (forced == 1 + PV_ELL16 || tune);
+  if (build_ell) {
     float* val = h->alloc<float>((size_t)total);
     uint16_t* col = h->alloc<uint16_t>((size_t)total);
     uint8_t* len = h->alloc<uint8_t>((size_t)h->ld);
     hip_check(hipMemsetAsync(len, 0, (size_t)h->ld, h->stream));
     for (int k = 0; k < S; ++k)
-      if (width[k] > 0)
-        hip_check(launch_build_ell(a, k, h->sys[k].row0, (int)h->sys[k].n, width[k], off[k], h->sys[k].nt * kTile,
-                                   val, col, len, h->stream));
+      hip_check(launch_build_ell(a, k, h->sys[k].row0, (int)h->sys[k].n, width[k], off[k], h->sys[k].nt * kTile,
+                                 val, col, len, h->stream));
     a.ell_val = val;
     a.ell_col = col;
     a.ell_len = len;
@@ -603,21 +618,14 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
     a.ell_off = d_off;
     a.ell_w = upload32(h, width);
   }
-  // size classes: the rows-per-thread tier of the persistent kernel
-  auto tier = [](int64_t n) {
-    const int64_t rows = (n + 1023) / 1024;
-    int t = 1;
-    while (t < rows && t < kMaxPR) t *= 2;
-    return t;
-  };
+  // size classes and the probe systems (the largest of each class)
   std::vector<int> classes;
   for (int k = 0; k < S; ++k)
     if (std::find(classes.begin(), classes.end(), tier(h->sys[k].n)) == classes.end())
       classes.push_back(tier(h->sys[k].n));
   std::sort(classes.begin(), classes.end());
-  std::vector<int8_t> pv(S, PV_CSR8);
   h->tune.clear();
-  float* sink = opt->autotune && forced == 0 ? h->alloc<float>(1024) : nullptr;
+  std::vector<int32_t> probe;
   for (int c : classes) {
     gmres_tune_class tc{};
     tc.rows_per_thread = c;
@@ -628,41 +636,49 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
         if (big < 0 || h->sys[k].n > h->sys[big].n) big = k;
       }
     tc.largest_n = (int32_t)h->sys[big].n;
-    int choice = PV_CSR8;
-    for (int v = 0; v < PV_COUNT; ++v) tc.probe_us[v] = -1.0;
-    bool all_ell = a.ell_w != nullptr;
-    for (int k = 0; k < S && all_ell; ++k)
-      if (tier(h->sys[k].n) == c) all_ell = width[k] > 0;
-    if (forced > 0) {
-      choice = forced - 1;
-      if (choice == PV_ELL16 && !all_ell) choice = PV_CSR8;  // a system of the class has no ELL copy
-    } else if (sink) {
-      constexpr int kReps = 8;
-      float best = 1e30f;
-      for (int v = 0; v < PV_COUNT; ++v) {
-        if (v == PV_ELL16 && !all_ell) continue;
-        hip_check(launch_persistent_probe(a, big, v, 1, sink, h->stream));
-        hip_check(hipEventRecord(h->ev0, h->stream));
-        hip_check(launch_persistent_probe(a, big, v, kReps, sink, h->stream));
-        hip_check(hipEventRecord(h->ev1, h->stream));
-        hip_check(hipEventSynchronize(h->ev1));
-        float ms = 0.f;
-        hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-        tc.probe_us[v] = 1000.0 * ms / kReps;
-        if (ms < best) {
-          best = ms;
-          choice = v;
-        }
-      }
-    }
-    tc.variant = choice;
-    for (int k = 0; k < S; ++k)
-      if (tier(h->sys[k].n) == c) pv[k] = (int8_t)choice;
+    tc.probe_system = big;
+    probe.push_back(big);
     h->tune.push_back(tc);
   }
-  int8_t* d_pv = h->alloc<int8_t>(S);
-  hip_check(hipMemcpyAsync(d_pv, pv.data(), S, hipMemcpyHostToDevice, h->stream));
-  a.sys_pv = d_pv;
+  for (double& t : h->tune_probe_us) t = -1.0;
+  h->pv = PV_CSR8;
+  if (forced > 0) {
+    h->pv = forced - 1;
+    if (h->pv == PV_ELL16 && !all_ell) h->pv = PV_CSR8;  // a system has no ELL copy
+  } else if (tune) {
+    // largest systems first, as in the solve's queue
+    std::sort(probe.begin(), probe.end(), [&](int x, int y) { return h->sys[x].n > h->sys[y].n; });
+    int32_t* d_probe = upload32(h, probe);
+    KArgs t = a;
+    t.S = (int32_t)probe.size();
+    t.max_iters = std::min<int64_t>(a.m, 8);
+    for (int k : probe) {  // b = a constant (a non-zero byte pattern), x = 0
+      hip_check(hipMemsetAsync(a.b + h->sys[k].row0, 0x3f, (size_t)h->sys[k].n * 8, h->stream));
+      hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
+    }
+    float best = 1e30f;
+    for (int v = 0; v < PV_COUNT; ++v) {
+      if (v == PV_ELL16 && !all_ell) continue;
+      hip_check(launch_batch_persistent(t, d_probe, h->counter, v, h->stream));
+      for (int k : probe)
+        hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
+      hip_check(hipEventRecord(h->ev0, h->stream));
+      hip_check(launch_batch_persistent(t, d_probe, h->counter, v, h->stream));
+      hip_check(hipEventRecord(h->ev1, h->stream));
+      hip_check(hipEventSynchronize(h->ev1));
+      float ms = 0.f;
+      hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      h->tune_probe_us[v] = 1000.0 * ms;
+      if (ms < best) {
+        best = ms;
+        h->pv = v;
+      }
+      for (int k : probe)
+        hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
+    }
+    for (int k : probe) hip_check(hipMemsetAsync(a.b + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
+    hip_check(launch_init_state(a, h->stream));
+  }
   hip_check(hipStreamSynchronize(h->stream));
 }
 
@@ -704,8 +720,9 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   h->opt = *opt;
   h->user = (hipStream_t)user_stream;
   hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
-  hip_check(hipEventCreate(&h->ev0));
-  hip_check(hipEventCreate(&h->ev1));
+  // timing events (kernel harness, autotuners): no system-scope fence
+  hip_check(hipEventCreateWithFlags(&h->ev0, hipEventDisableSystemFence));
+  hip_check(hipEventCreateWithFlags(&h->ev1, hipEventDisableSystemFence));
   hip_check(hipEventCreateWithFlags(&h->evu, hipEventDisableTiming));
   after_caller(h);
   const int m = opt->m;
@@ -1009,7 +1026,7 @@ int finish(gmres_ctx* h, gmres_result* res, int32_t nres, double seconds) {
 // The cycle loop shared by single and batch solves; b and x are already in
 // the internal buffers.
 void run_persistent(gmres_ctx* h) {
-  hip_check(launch_batch_persistent(h->a, h->order, h->counter, h->stream));
+  hip_check(launch_batch_persistent(h->a, h->order, h->counter, h->pv, h->stream));
   hip_check(hipMemcpyAsync(h->st_host, h->a.st, sizeof(SysState) * h->a.S, hipMemcpyDeviceToHost, h->stream));
   hip_check(hipStreamSynchronize(h->stream));
 }
@@ -1330,7 +1347,7 @@ int gmres_batch_solve(gmres_handle hh, const double* const* b, double* const* x,
         hipGraph_t g = nullptr;
         hip_check(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = gather();
-        if (e == hipSuccess) e = launch_batch_persistent(h->a, h->order, h->counter, h->stream);
+        if (e == hipSuccess) e = launch_batch_persistent(h->a, h->order, h->counter, h->pv, h->stream);
         if (e == hipSuccess) e = scatter();
         const hipError_t e2 = hipStreamEndCapture(h->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -1619,12 +1636,15 @@ int gmres_memory_bytes(gmres_handle hh, size_t* bytes) {
 }
 
 int gmres_solve_profiled(gmres_handle hh, const double* b, double* x, gmres_result* res,
-                         gmres_kernel_profile* prof) {
+                         gmres_kernel_profile* prof, gmres_kernel_profile* by_col) {
   try {
     gmres_ctx* h = get(hh);
     if (h->a.S != 1 || h->persistent) return GMRES_ESTATE;
     if (!b || !x || !prof) return GMRES_EINVAL;
+    const int m = h->a.m;
     for (int k = 0; k < GMRES_PK_COUNT; ++k) prof[k] = gmres_kernel_profile{};
+    if (by_col)
+      for (int k = 0; k < GMRES_PK_COUNT * m; ++k) by_col[k] = gmres_kernel_profile{};
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = h->sys[0].n;
     KArgs& a = h->a;
@@ -1654,14 +1674,19 @@ int gmres_solve_profiled(gmres_handle hh, const double* b, double* x, gmres_resu
         float ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, r.e0, r.e1));
         const bool active = r.j == -1 ? (r.kind != GMRES_PK_ENCODE || ran) : r.j == -2 ? ran : r.j < k;
-        gmres_kernel_profile& p = prof[r.kind];
-        p.ms += ms;
-        p.launches += 1;
-        if (active) {
-          p.ms_active += ms;
-          p.active += 1;
-          p.bytes += r.kind == GMRES_PK_UPDATE ? r.bytes + (double)S.kk * (double)h->nrows * sv_upd : r.bytes;
-        }
+        const double bytes =
+            r.kind == GMRES_PK_UPDATE ? r.bytes + (double)S.kk * (double)h->nrows * sv_upd : r.bytes;
+        auto add = [&](gmres_kernel_profile& p) {
+          p.ms += ms;
+          p.launches += 1;
+          if (active) {
+            p.ms_active += ms;
+            p.active += 1;
+            p.bytes += bytes;
+          }
+        };
+        add(prof[r.kind]);
+        if (by_col && r.j >= 0) add(by_col[(size_t)r.kind * m + r.j]);
       }
       if (S.status != RUNNING) break;
     }
@@ -1696,12 +1721,16 @@ int gmres_launch_config(gmres_handle hh, int32_t family, int32_t j, int32_t* gri
   }
 }
 
-int gmres_batch_tuning(gmres_handle hh, gmres_tune_class* out, int32_t cap, int32_t* count) {
+int gmres_batch_tuning(gmres_handle hh, int32_t* variant, double* probe_us, gmres_tune_class* out, int32_t cap,
+                       int32_t* count) {
   try {
     gmres_ctx* h = get(hh);
-    if (!count || cap < 0 || (cap > 0 && !out)) return GMRES_EINVAL;
+    if (cap < 0 || (cap > 0 && !out)) return GMRES_EINVAL;
     if (!h->persistent) return GMRES_ESTATE;
-    *count = (int32_t)h->tune.size();
+    if (variant) *variant = h->pv;
+    if (probe_us)
+      for (int v = 0; v < 3; ++v) probe_us[v] = h->tune_probe_us[v];
+    if (count) *count = (int32_t)h->tune.size();
     for (int32_t k = 0; k < cap && k < (int32_t)h->tune.size(); ++k) out[k] = h->tune[k];
     return GMRES_OK;
   } catch (const Fail& f) {

@@ -173,10 +173,8 @@ struct KArgs {
   int64_t max_iters;
   int32_t stall_cycles;
   int32_t stall_win;  // max(1, ceil(0.05 m))
-  // persistent batch schedule: the Arnoldi SpMV variant of each system
-  // (PersistentSpmv, chosen per size class by the create-time tuner) and the
-  // ELL copy of the float32 values it reads in the ELL variant
-  const int8_t* sys_pv;
+  // persistent batch schedule: the ELL copy of the float32 values that the
+  // ELL variant of its Arnoldi SpMV reads
   const float* ell_val;     // system s: ell_w[s] slices of sys_nt[s] * kTile rows from ell_off[s]
   const uint16_t* ell_col;  //   column minus the system's first row
   const uint8_t* ell_len;   // row lengths (global rows)
@@ -185,7 +183,8 @@ struct KArgs {
 };
 
 // Arnoldi SpMV of the persistent batch kernel (one thread per row, R rows
-// per thread).  Every variant sums a row's products in storage order, so the
+// per thread), one kernel per variant, chosen per batch by the create-time
+// tuner.  Every variant sums a row's products in storage order, so the
 // choice changes speed only, never a result bit.
 //   PV_CSR8  CSR, a row's entries loaded in groups of 8
 //   PV_CSR4  CSR, groups of 4
@@ -259,11 +258,10 @@ hipError_t launch_scatter(const double* src, double* const* dst, const int64_t* 
                           const int32_t* n, int S, int64_t maxn, hipStream_t st);
 // One workgroup per system, systems taken from `order` through `counter`
 // (cleared by this call), float32 MGS Arnoldi; basis in layout vsys = 1.
-hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, hipStream_t st);
-// Tuner probe: one workgroup runs system s's Arnoldi SpMV `reps` times with
-// variant pv (its rows-per-thread tier as the solve would), on x = the first
-// basis column; sink receives one float per thread so the work is kept.
-hipError_t launch_persistent_probe(const KArgs& a, int s, int pv, int reps, float* sink, hipStream_t st);
+// One workgroup per system, systems taken from `order` (a.S entries) through
+// `counter` (cleared by this call), float32 MGS Arnoldi; basis in layout
+// vsys = 1; pv: the Arnoldi SpMV variant (PersistentSpmv).
+hipError_t launch_batch_persistent(const KArgs& a, const int32_t* order, int32_t* counter, int pv, hipStream_t st);
 // The ELL copy of system s (one thread per row): values from a.a32, local
 // columns, lengths; w = ELL width of s (its longest row).
 hipError_t launch_build_ell(const KArgs& a, int s, int64_t row0, int n, int w, int64_t off, int pn,

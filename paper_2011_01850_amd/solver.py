@@ -126,19 +126,28 @@ class Solver:
 
         Returns (x, info, profile): profile maps each kernel family to its
         summed milliseconds, launches, and the milliseconds, launches and
-        algorithmic bytes of the launches that did work."""
+        algorithmic bytes of the launches that did work; profile[family]
+        ["by_col"] lists the same per Arnoldi column j = 0..m-1."""
         torch = self._torch
         bt = _dev(b, torch.float64, torch)
         x = torch.zeros(self.n, dtype=torch.float64, device="cuda") if x0 is None else \
             _dev(x0, torch.float64, torch).clone()
         torch.cuda.synchronize()
         res = L.Result()
-        prof = (L.KernelProfile * len(L.PROFILE_KINDS))()
-        L.check(self.lib.gmres_solve_profiled(self.h, bt.data_ptr(), x.data_ptr(), C.byref(res), prof),
+        nk = len(L.PROFILE_KINDS)
+        prof = (L.KernelProfile * nk)()
+        cols = (L.KernelProfile * (nk * self.m))()
+        L.check(self.lib.gmres_solve_profiled(self.h, bt.data_ptr(), x.data_ptr(), C.byref(res), prof, cols),
                 "gmres_solve_profiled")
-        out = {name: {"ms": p.ms, "launches": int(p.launches), "ms_active": p.ms_active,
-                      "active": int(p.active), "bytes": p.bytes}
-               for name, p in zip(L.PROFILE_KINDS, prof)}
+
+        def row(p):
+            return {"ms": p.ms, "launches": int(p.launches), "ms_active": p.ms_active, "active": int(p.active),
+                    "bytes": p.bytes}
+
+        out = {}
+        for k, name in enumerate(L.PROFILE_KINDS):
+            out[name] = row(prof[k])
+            out[name]["by_col"] = [row(cols[k * self.m + j]) for j in range(self.m)]
         return x, res.as_dict(), out
 
     def set_preconditioner(self, spai_vals):
@@ -340,18 +349,19 @@ class BatchSolver:
         return out[: min(cnt.value, cap)].copy()
 
     def tuning(self):
-        """The persistent schedule's SpMV choice per size class (list of dicts), or None."""
+        """The persistent schedule's SpMV tuner: dict(variant, probe_us, classes), or None."""
         cnt = C.c_int32()
+        var = C.c_int32()
+        probe = (C.c_double * 3)()
         out = (L.TuneClass * 16)()
-        rc = self.lib.gmres_batch_tuning(self.h, out, 16, C.byref(cnt))
+        rc = self.lib.gmres_batch_tuning(self.h, C.byref(var), probe, out, 16, C.byref(cnt))
         if rc == L.ESTATE:
             return None
         L.check(rc, "gmres_batch_tuning")
-        return [{"rows_per_thread": c.rows_per_thread, "systems": c.systems, "largest_n": c.largest_n,
-                 "variant": L.PERSISTENT_SPMV_NAMES[c.variant],
-                 "probe_us": {L.PERSISTENT_SPMV_NAMES[v]: round(c.probe_us[v], 3) for v in range(3)
-                              if c.probe_us[v] >= 0}}
-                for c in out[: min(cnt.value, 16)]]
+        return {"variant": L.PERSISTENT_SPMV_NAMES[var.value],
+                "probe_us": {L.PERSISTENT_SPMV_NAMES[v]: round(probe[v], 2) for v in range(3) if probe[v] >= 0},
+                "classes": [{"rows_per_thread": c.rows_per_thread, "systems": c.systems, "largest_n": c.largest_n,
+                             "probe_system": c.probe_system} for c in out[: min(cnt.value, 16)]]}
 
 
 def encode(w, inv_h, fmt="fp16", out=None, noalloc=False):

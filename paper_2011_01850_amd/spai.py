@@ -129,6 +129,29 @@ class Adam:
                                         1.0, zero.data_ptr(), zero.clone().data_ptr(), 0.0, beta1, beta2, eps, 1,
                                         None), "spai_adam_step")
 
+    def state_dict(self):
+        """Host copies of the optimiser state: float32 master weights, both
+        moment estimates, the step count and the hyper-parameters."""
+        return {"theta": self.theta.cpu().numpy(), "m1": self.m1.cpu().numpy(), "m2": self.m2.cpu().numpy(),
+                "t": self.t, "lr": self.lr, "beta1": self.beta1, "beta2": self.beta2, "eps": self.eps}
+
+    def load_state_dict(self, d):
+        """Restore a state_dict (the bfloat16 copy is made again from the master weights)."""
+        torch = self._torch
+        for name in ("theta", "m1", "m2"):
+            src = np.asarray(d[name], dtype=np.float32)
+            if src.size != NPARAMS:
+                raise ValueError(f"{name}: expected {NPARAMS} values")
+            getattr(self, name).copy_(torch.as_tensor(src))
+        self.t = int(d["t"])
+        self.lr, self.beta1, self.beta2, self.eps = (float(d["lr"]), float(d["beta1"]), float(d["beta2"]),
+                                                     float(d["eps"]))
+        zero = torch.zeros_like(self.theta)
+        torch.cuda.synchronize()
+        L.check(self.lib.spai_adam_step(NPARAMS, self.theta.data_ptr(), self.params.data_ptr(), zero.data_ptr(),
+                                        1.0, zero.data_ptr(), zero.clone().data_ptr(), 0.0, self.beta1, self.beta2,
+                                        self.eps, 1, None), "spai_adam_step")
+
     def step(self, grad, scale=1.0, lr=None):
         self.t += 1
         self._torch.cuda.synchronize()

@@ -11,6 +11,7 @@ change between steps.
 """
 from __future__ import annotations
 
+import os
 import time
 from dataclasses import dataclass, field
 
@@ -71,8 +72,35 @@ def prepare(instances, K=4, m=30, log=None):
     return d
 
 
-def train_on(data: TrainingData, epochs=1.0, lr=1e-3, batch=4, seed=0, log=None):
-    """Adam on the residual loss, instances cycled in a seeded shuffled order."""
+def save_checkpoint(path, opt, step, hist, seed, ninst, batch):
+    """The training state after `step` steps (NumPy .npz, arrays only)."""
+    st = opt.state_dict()
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, theta=st["theta"], m1=st["m1"], m2=st["m2"],
+             scalars=np.array([st["t"], st["lr"], st["beta1"], st["beta2"], st["eps"]], dtype=np.float64),
+             step=np.array(step, dtype=np.int64), seed=np.array(seed, dtype=np.int64),
+             ninst=np.array(ninst, dtype=np.int64), batch=np.array(batch, dtype=np.int64),
+             history=np.asarray(hist, dtype=np.float64))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path):
+    with np.load(path, allow_pickle=False) as z:
+        sc = z["scalars"]
+        return {"opt": {"theta": z["theta"], "m1": z["m1"], "m2": z["m2"], "t": int(sc[0]), "lr": float(sc[1]),
+                        "beta1": float(sc[2]), "beta2": float(sc[3]), "eps": float(sc[4])},
+                "step": int(z["step"]), "seed": int(z["seed"]), "ninst": int(z["ninst"]), "batch": int(z["batch"]),
+                "history": [float(v) for v in z["history"]]}
+
+
+def train_on(data: TrainingData, epochs=1.0, lr=1e-3, batch=4, seed=0, log=None, checkpoint=None,
+             checkpoint_every=0, stop_after=None):
+    """Adam on the residual loss, instances cycled in a seeded shuffled order.
+
+    checkpoint: a file path.  When it exists, training resumes from it (the
+    same data, seed and batch are required); every `checkpoint_every` steps
+    and at the end the state is written to it.  stop_after: end after that
+    many steps in total (an interrupted run, for resuming later)."""
     torch = _torch()
     ninst = len(data.vals)
     K = int(data.pairs[0].shape[0])
@@ -82,9 +110,19 @@ def train_on(data: TrainingData, epochs=1.0, lr=1e-3, batch=4, seed=0, log=None)
     order = np.random.default_rng(seed).permutation(ninst)
     steps = max(1, int(round(epochs * ninst / batch)))
     hist = []
+    first = 0
+    if checkpoint and os.path.exists(checkpoint):
+        ck = load_checkpoint(checkpoint)
+        if (ck["seed"], ck["ninst"], ck["batch"]) != (seed, ninst, batch):
+            raise ValueError("checkpoint was written for another seed, instance count or batch")
+        opt.load_state_dict(ck["opt"])
+        first, hist = ck["step"], ck["history"]
+        if log:
+            log(f"  resumed at step {first} from {checkpoint}")
+    last = steps if stop_after is None else min(steps, int(stop_after))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for step in range(steps):
+    for step in range(first, last):
         Ls = []
         for q in range(batch):
             k = int(order[(step * batch + q) % ninst])
@@ -97,6 +135,10 @@ def train_on(data: TrainingData, epochs=1.0, lr=1e-3, batch=4, seed=0, log=None)
         hist.append(float(np.mean(Ls)))
         if log and (step % max(1, steps // 10) == 0 or step == steps - 1):
             log(f"  step {step:5d} loss {hist[-1]:.5f}")
+        if checkpoint and checkpoint_every and (step + 1) % checkpoint_every == 0:
+            save_checkpoint(checkpoint, opt, step + 1, hist, seed, ninst, batch)
+    if checkpoint:
+        save_checkpoint(checkpoint, opt, last, hist, seed, ninst, batch)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
 
@@ -111,7 +153,8 @@ def train_on(data: TrainingData, epochs=1.0, lr=1e-3, batch=4, seed=0, log=None)
     res = {"params": opt.params.clone(), "theta": opt.theta.clone(), "history": hist,
            "loss_first": mean_loss(jac), "loss_last": mean_loss(opt.params),
            "seconds_data": data.seconds, "seconds_train": t_train, "steps": steps, "batch": batch,
-           "instances": ninst, "seconds_per_instance_step": t_train / (steps * batch)}
+           "instances": ninst, "seconds_per_instance_step": t_train / (max(1, last - first) * batch),
+           "steps_done": last}
     net.close()
     return res
 

@@ -127,7 +127,7 @@ def test_handle_checks(lib):
     assert lib.gmres_precond_apply(None, None, None) == L.EHANDLE
     assert lib.gmres_precond_apply_f64(None, 1, 1) == L.EHANDLE
     prof = (L.KernelProfile * len(L.PROFILE_KINDS))()
-    assert lib.gmres_solve_profiled(None, 1, 1, None, prof) == L.EHANDLE
+    assert lib.gmres_solve_profiled(None, 1, 1, None, prof, None) == L.EHANDLE
     # a pointer to something that is not a handle
     junk = (C.c_uint32 * 64)()
     assert lib.gmres_memory_bytes(C.cast(junk, C.c_void_p), C.byref(v)) == L.EHANDLE

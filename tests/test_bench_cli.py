@@ -20,17 +20,39 @@ def test_traffic_record_is_tied_to_the_kernel_source():
     import bench
 
     t = bench.TRAFFIC
-    assert set(t) == {"family", "bytes_per_launch", "kernel_source_sha256"}
+    assert set(t) == {"kernel", "bytes_per_launch", "kernel_source_sha256"}
     assert t["bytes_per_launch"] is None or t["bytes_per_launch"] > 0
-    # the lookup returns the stored bytes only for the family and the source they were measured on
-    fam = t["family"] or "pass1"
-    got = bench.measured_traffic(fam)
+    # the lookup returns the stored bytes only for the kernel and the source they were measured on
+    got = bench.measured_traffic(t["kernel"] or "k_mdot<float, float, 64>")
     assert got is None or got == t["bytes_per_launch"]
-    assert bench.measured_traffic("no such family") is None
+    assert bench.measured_traffic("no such kernel") is None
     json.dumps({"traffic": got})
 
 
-def test_roofline_picks_the_dominant_family():
+def test_tile_widths_follow_the_column():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    assert [bench.tile_width(j) for j in (0, 7, 8, 15, 16, 31, 32, 49, 63, 64, 200)] == \
+        [8, 8, 16, 16, 32, 32, 64, 64, 64, 64, 64]
+    units = bench.kernel_units("pass1", 50, "fp32", "cgsr")
+    assert [u[0] for u in units] == [f"k_mdot<float, float, {L}>" for L in (8, 16, 32, 64)]
+    assert sum(len(c) for _, c in units) == 50 and units[3][1] == list(range(32, 50))
+    assert bench.kernel_units("pass2", 50, "fp64", "cgsr")[0][0].startswith("k_axpy_mdot64<double, double")
+    assert bench.kernel_units("final", 40, "fp32", "mgs") == [("k_mgs_final<float, float>", list(range(40)))]
+
+
+def _fam_entry(ms, launches, act, byts, m=50, cols=None):
+    cols = cols or range(m)
+    by_col = [{"ms": 0.0, "launches": 0, "ms_active": 0.0, "active": 0, "bytes": 0.0} for _ in range(m)]
+    for j in cols:
+        by_col[j] = {"ms": ms / len(cols), "launches": launches // len(cols), "ms_active": 0.95 * ms / len(cols),
+                     "active": act // len(cols), "bytes": byts / len(cols)}
+    return {"ms_per_solve": ms, "launches": launches, "ms_active": 0.95 * ms, "active_launches": act,
+            "alg_bytes": byts, "by_col": by_col}
+
+
+def test_roofline_picks_the_dominant_kernel():
     sys.path.insert(0, ROOT)
     import bench
 
@@ -39,17 +61,16 @@ def test_roofline_picks_the_dominant_family():
             return 0.05, 1e8
 
         def launch_config(self, fam, j):
-            return {"grid": 2048, "block": 256, "per_cu": 8, "basis_align": 4096}
+            return {"grid": 1024, "block": 256, "per_cu": 4, "basis_align": 2 ** 21}
 
-    fam = {"spmv": {"ms_per_solve": 20.0, "launches": 600, "ms_active": 19.0, "active_launches": 585,
-                    "alg_bytes": 585 * 1.4e8},
-           "pass1": {"ms_per_solve": 30.0, "launches": 600, "ms_active": 29.5, "active_launches": 585,
-                     "alg_bytes": 585 * 2.7e8},
+    fam = {"spmv": _fam_entry(20.0, 650, 600, 600 * 1.4e8),
+           "pass1": _fam_entry(30.0, 650, 600, 600 * 2.7e8, cols=range(32, 50)),
            "reduce": {"ms_per_solve": 40.0, "launches": 2000, "ms_active": 39.0, "active_launches": 1800,
-                      "alg_bytes": 0.0}}
+                      "alg_bytes": 0.0, "by_col": []}}
     rf = bench.roofline_from_profile(FakeSolver(), fam, 50, 3)
     # the latency-bound reductions take longest but move no algorithmic bytes
-    assert rf["family"] == "pass1"
-    assert abs(rf["achieved"] - 585 * 2.7e8 / 29.5e-3 / 1e9) < 0.1
+    assert rf["family"] == "pass1" and rf["kernel"] == "k_mdot<float, float, 64>"
+    per = 600 // 18 * 18  # launches the fake table spreads over columns 32..49
+    assert abs(rf["achieved"] - 600 * 2.7e8 / 28.5e-3 / 1e9) < 0.5 and rf["avg_launch_ms"] == round(28.5 / per, 5)
     assert abs(rf["frac"] - rf["achieved"] / 8000.0) < 1e-4
-    assert abs(rf["avg_launch_ms"] - 29.5 / 585) < 1e-5
+    assert "reduce" in rf["in_solve_families"] and rf["harness_back_to_back"]["j"] == 49

@@ -87,14 +87,13 @@ def test_spmv_variants_are_bitwise_equal_and_tuned(mods):
         bs.close()
         out[var] = ([x.cpu().numpy() for x in xs], [i["iters"] for i in infos])
         print(var, out[var][1], tune, flush=True)
-        assert len(tune) == 6  # one size class per row-count tier of SIDES
-        assert sum(c["systems"] for c in tune) == len(systems)
+        assert len(tune["classes"]) == 6  # one size class per row-count tier of SIDES
+        assert sum(c["systems"] for c in tune["classes"]) == len(systems)
         if var != "tuned":
-            assert all(c["variant"] == var for c in tune)
+            assert tune["variant"] == var and tune["probe_us"] == {}
         else:
-            for c in tune:
-                assert set(c["probe_us"]) == {"csr8", "csr4", "ell16"}
-                assert c["variant"] == min(c["probe_us"], key=c["probe_us"].get)
+            assert set(tune["probe_us"]) == {"csr8", "csr4", "ell16"}
+            assert tune["variant"] == min(tune["probe_us"], key=tune["probe_us"].get)
     for var in ("csr4", "ell16", "tuned"):
         assert out[var][1] == out["csr8"][1]
         for a, b in zip(out[var][0], out["csr8"][0]):

@@ -1,6 +1,7 @@
 """The benchmark workload at full size (128^3 convection-diffusion, n = 2,097,152)
 in the launch configuration bench.py times, checked by properties that hold at
 any size and by outputs the oracle computes one by one."""
+import math
 import time
 
 import numpy as np
@@ -281,14 +282,22 @@ def test_fullsize_varcoef_fgmres_matches_oracle(c5, kind):
     if kind == "learned":
         s.spai_infer(torch.as_tensor(spai.params_to_bf16(th)).cuda(), return_m=False)
     x, info = s.solve(c5.b)
+    hist = s.history()
     s.close()
     x = x.cpu().numpy()
     rr = O.relative_residual(M, c5.b, x)
     err = float(np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x))
+
+    def cycles_to(h, level):
+        return next(k for k, v in enumerate(h) if v <= level)
     print(f"64^3 FGMRES {kind}: gpu {info['status']} iters {info['iters']} relres {rr:.2e} fallback "
           f"{info['fallback_used']} | oracle {ref.status_name} iters {ref.iters} ({t_or:.1f} s), float32 "
-          f"emulation {emu.status_name} iters {emu.iters} | vs oracle x {err:.2e}", flush=True)
+          f"emulation {emu.status_name} iters {emu.iters} | cycles to 1e-10: gpu {cycles_to(hist, 1e-10)}, "
+          f"emulation {cycles_to(emu.history, 1e-10)} | vs oracle x {err:.2e}", flush=True)
     assert ref.status == O.CONVERGED and emu.status == O.CONVERGED
     assert info["status"] == "CONVERGED" and not info["fallback_used"] and rr <= 1.01e-13
     assert err <= 1e-8
-    assert abs(info["iters"] - emu.iters) <= max(30, 0.15 * emu.iters)
+    # below 1e-11 every cycle gains little and the count to 1e-13 is sensitive to
+    # rounding; down to 1e-10 the GPU follows the float32 emulation cycle for cycle
+    ce = cycles_to(emu.history, 1e-10)
+    assert abs(cycles_to(hist, 1e-10) - ce) <= max(1, math.ceil(0.15 * ce))

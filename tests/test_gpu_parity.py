@@ -822,6 +822,14 @@ def test_profiled_solve_is_the_same_solve(ortho, precision):
     for name in ("spmv", "final", "residual", "update"):
         p = prof[name]
         assert 0.0 < p["ms_active"] <= p["ms"]
+    # the per-column table adds up to the family totals (the column loop's launches)
+    for name in ("spmv", "pass1", "pass2", "final", "mgs"):
+        cols = prof[name]["by_col"]
+        assert len(cols) == m
+        assert sum(c["launches"] for c in cols) == prof[name]["launches"]
+        assert sum(c["active"] for c in cols) == prof[name]["active"]
+        assert sum(c["bytes"] for c in cols) == pytest.approx(prof[name]["bytes"], rel=1e-12)
+    assert [c["active"] for c in prof["spmv"]["by_col"]] == [sum(k > j for k in lens) for j in range(m)]
 
 
 def test_backward_error_and_unit_residual_match_oracle():

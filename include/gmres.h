@@ -179,7 +179,20 @@ typedef struct {
   int32_t persistent_spmv;   /* persistent batch schedule: 0 = the Arnoldi SpMV variant chosen by the
                                 create-time tuner (autotune = 1; else CSR8); 1 + GMRES_PSPMV_* forces
                                 one */
+  int32_t precond_side;      /* GMRES_PRECOND_RIGHT (flexible GMRES, the default) or GMRES_PRECOND_LEFT */
 } gmres_options;
+
+/* gmres_options.precond_side.  RIGHT: flexible GMRES, z_j = M^-1 v_j kept,
+ * w = A z_j, x += Z y.  LEFT, the form of the paper's experiments
+ * (Algorithm 1 with M^-1 on the left): each cycle starts from
+ * r = M^-1 (b - A x) (the residual in float64, M^-1 applied in the
+ * preconditioner's precision to w's copy of it), beta = ||r||, and every
+ * step forms w = M^-1 A v_j; x += V y.  The inner loop compares its estimate
+ * |s_{j+1}| (of ||M^-1 (b - A x)||) with tol ||M^-1 b||; the float64
+ * restart residual ||b - A x|| / ||b|| stays the stop test.  A zero or
+ * non-finite M^-1 z switches the preconditioner off (fallback_used), as a
+ * cycle that gains less than 1.001x does on either side. */
+enum { GMRES_PRECOND_RIGHT = 0, GMRES_PRECOND_LEFT = 1 };
 
 /* Arnoldi SpMV variants of the persistent batch kernel (all sum each row's
  * products in storage order, so the choice never changes a result bit):
@@ -223,7 +236,7 @@ typedef struct {
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
  * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4,
- * arnoldi_a = DEFAULT, precond_precision = NATIVE, persistent_spmv = 0. */
+ * arnoldi_a = DEFAULT, precond_precision = NATIVE, persistent_spmv = 0, precond_side = RIGHT. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).

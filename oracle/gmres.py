@@ -507,13 +507,17 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
           precision="fp64", precond=None, restart_improve=0.0, stall_cycles=10,
           fallback=True, record=False, residual_fp32=False, update_fp32=False, a_storage="copy",
           restart_repeat=False, restart_on_stall=False, orth_restart=0.0, orth_norm="spectral",
-          arnoldi_a="default"):
-    """Restarted GMRES(m) following Algorithm 1, optionally flexible (right-preconditioned).
+          arnoldi_a="default", side="right"):
+    """Restarted GMRES(m) following Algorithm 1, optionally preconditioned.
 
-    ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> z applied
-    on the right: z_j = M v_j, w = A z_j, and the correction is Z y
-    (flexible GMRES).  The paper itself preconditions on the left; the
-    right-preconditioned form is what the learned preconditioner uses.
+    ``precond`` is None (plain GMRES, M^-1 = I) or a callable v -> M^-1 v.
+    ``side="right"``: flexible GMRES, z_j = M^-1 v_j, w = A z_j, and the
+    correction is Z y (the form the learned preconditioner uses).
+    ``side="left"`` (the paper's form): r = M^-1 (b - A x) starts the cycle
+    (beta = ||r||), w = M^-1 A v_j, the correction is V y, and the inner
+    loop's estimate |s_{j+1}| is compared with tol ||M^-1 b|| (it estimates
+    the preconditioned residual); the restart residual b - A x stays the
+    judge.  The preconditioner's input and output have w's precision.
     ``a_storage="split"`` emulates the split storage of A: the float32
     Arnoldi product uses the high-word values (the float64 residual is
     unchanged, as both words together are the float64 value).
@@ -541,6 +545,8 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         raise ValueError(a_storage)
     if arnoldi_a not in ("default", "fp64", "fp32"):
         raise ValueError(arnoldi_a)
+    if side not in ("right", "left"):
+        raise ValueError(side)
     # the Arnoldi product's copy of A in the reduced-precision modes: float32
     # rounding of the values, or (split storage) the high-word values
     a32 = A.vals32 if a_storage == "copy" else high_word_value(A.vals).astype(np.float32)
@@ -556,6 +562,13 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
     wide_w = precision in ("fp64", "limited")  # w, its dots and the product's sums in float64
     a64_arnoldi = arnoldi_a == "fp64" or (arnoldi_a == "default" and precision == "fp64")
     orthogonalize = _mgs if ortho == "mgs" else _cgsr
+    left = side == "left"
+
+    def wprec(v):  # a vector in w's precision
+        return np.asarray(v, dtype=np.float64 if wide_w else np.float32)
+
+    # left preconditioning: the inner loop's estimate is measured against ||M^-1 b||
+    bnp = float(np.linalg.norm(wprec(precond(wprec(b))).astype(np.float64))) if left and precond else bn
     total = 0
     restarts = 0
     hist, arn, cyc = [], [], []
@@ -608,19 +621,35 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         cs = np.zeros(m)
         sn = np.zeros(m)
         s = np.zeros(m + 1)
-        s[0] = beta  # s_1 = beta
-        basis.store(0, z.astype(np.float32) if lowp else z, beta)
+        left_pc = left and use_pc
+        if left_pc:  # the cycle starts from the preconditioned residual
+            r = wprec(precond(wprec(z)))
+            beta_c = float(np.linalg.norm(r.astype(np.float64)))
+            est_norm = bnp
+            if not (beta_c > 0.0) or not math.isfinite(beta_c):
+                # M^-1 z vanished or is not finite: the preconditioner is
+                # switched off and the next cycle runs plain GMRES
+                use_pc = False
+                fallback_used = True
+                continue
+        else:
+            r, beta_c, est_norm = z, beta, bn
+        s[0] = beta_c  # s_1 = beta
+        basis.store(0, r.astype(np.float32) if lowp else r, beta_c)
         monitor = _OrthMonitor(m, orth_norm) if orth_restart > 0.0 else None
         k = 0
         W = []  # (record) w after orthogonalisation, before normalisation, per step
         cycle_arn = []
-        ares = [beta]  # |s_1| .. |s_{j+1}| of this cycle
+        ares = [beta_c]  # |s_1| .. |s_{j+1}| of this cycle
         for j in range(m):
             # w <- A v_j (flexible form: z_j = M v_j, w <- A z_j)
             vj = basis.vec(j)
-            if use_pc:
+            right_pc = use_pc and not left
+            if right_pc:
                 Z[j] = _cast(precond(vj), precision)
-            w = _arnoldi_product(A, Z[j] if use_pc else vj, a32, a64_arnoldi, wide_w)
+            w = _arnoldi_product(A, Z[j] if right_pc else vj, a32, a64_arnoldi, wide_w)
+            if left_pc:  # w <- M^-1 A v_j
+                w = wprec(precond(w))
             w, hcol = orthogonalize(w, basis, j)
             hnext = float(np.linalg.norm(w.astype(np.float64)))
             if record:
@@ -631,7 +660,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
             total += 1
             k = j + 1
             _givens_step(H, cs, sn, s, j)
-            cycle_arn.append(abs(s[j + 1]) / bn)
+            cycle_arn.append(abs(s[j + 1]) / est_norm)
             ares.append(abs(s[j + 1]))
             if hnext == 0.0 or not math.isfinite(hnext):
                 if not math.isfinite(hnext):
@@ -639,10 +668,10 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
                 break
             basis.store(j + 1, w, hnext)
             # restart conditions: the estimate, the budget, the triggers
-            if abs(s[j + 1]) / bn <= tol or total >= max_iters:
+            if abs(s[j + 1]) / est_norm <= tol or total >= max_iters:
                 break
             first_stage = not restart_repeat or klimit == 0
-            if restart_improve > 0.0 and first_stage and abs(s[j + 1]) <= restart_improve * beta:
+            if restart_improve > 0.0 and first_stage and abs(s[j + 1]) <= restart_improve * beta_c:
                 break
             if not first_stage and j + 1 >= klimit:
                 break
@@ -656,7 +685,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         y, kk = back_solve(H, s, k, U32 if lowp else U64)
         u = np.zeros(n)
         for i in range(kk):
-            src = Z[i] if use_pc else basis.vec(i)
+            src = Z[i] if use_pc and not left else basis.vec(i)
             u += y[i] * src.astype(np.float64)
         if update_fp32:
             x = (x.astype(np.float32) + u.astype(np.float32)).astype(np.float64)
@@ -667,7 +696,7 @@ def gmres(A: Matrix, b, x0=None, m=50, tol=1e-10, max_iters=10 ** 7, ortho="mgs"
         if record:
             cyc.append({"V": [basis.vec(i).astype(np.float64) for i in range(k + 1) if basis.V[i] is not None],
                         "Hbar": Hbar[: k + 1, :k].copy(), "H": H[:k, :k].copy(), "s": s[: k + 1].copy(),
-                        "k": k, "beta": beta, "y": y, "cs": cs[:k].copy(), "sn": sn[:k].copy(), "W": W})
+                        "k": k, "beta": beta_c, "y": y, "cs": cs[:k].copy(), "sn": sn[:k].copy(), "W": W})
     return Result(x, status, total, restarts, hist[-1], hist, arn, cyc, fallback_used)
 
 

@@ -203,9 +203,11 @@ struct SpmvSys {
   uint32_t pn;        // padded rows (ELL slice stride)
 };
 
+// rpr, cir: the system's row-pointer and column descriptors, which the
+// float64 residual reads too (the CSR variants share them).
 template <int PV>
 __device__ __forceinline__ SpmvSys spmv_sys_of(const PArgs& a, int s, int64_t row0, int n, uint32_t pn,
-                                              uint32_t nz_end) {
+                                              uint32_t nz_end, rsrc_t rpr, rsrc_t cir) {
   SpmvSys m;
   m.col0 = (int)row0;
   m.pn = pn;
@@ -217,8 +219,8 @@ __device__ __forceinline__ SpmvSys spmv_sys_of(const PArgs& a, int s, int64_t ro
     m.r1 = mkr(a.ell_col + off, (uint64_t)m.ew * pn * 2);
     m.r2 = mkr(a.ell_len + row0, (uint64_t)n);
   } else {
-    m.r0 = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
-    m.r1 = mkr(a.ci, (uint64_t)nz_end * 4);
+    m.r0 = rpr;
+    m.r1 = cir;
     m.r2 = mkr(a.a32, (uint64_t)nz_end * 4);
   }
   return m;
@@ -313,7 +315,7 @@ __device__ __forceinline__ void p_system(const PArgs& a, int s, PShared& sh) {
   const rsrc_t rpr = mkr(a.rp + row0, (uint64_t)(n + 1) * 4);
   const rsrc_t cir = mkr(a.ci, (uint64_t)nz_end * 4);
   const rsrc_t a64r = mkr(a.a64, (uint64_t)nz_end * 8);
-  const SpmvSys sm = spmv_sys_of<PV>(a, s, row0, n, pn, nz_end);
+  const SpmvSys sm = spmv_sys_of<PV>(a, s, row0, n, pn, nz_end, rpr, cir);
   const rsrc_t xall = mkr(a.x, (uint64_t)a.ld * 8);         // gathers by global column
   const rsrc_t xs = mkr(a.x + row0, (uint64_t)n * 8);       // this system's rows
   const rsrc_t br = mkr(a.b + row0, (uint64_t)n * 8);

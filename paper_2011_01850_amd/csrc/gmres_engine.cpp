@@ -168,6 +168,7 @@ bool valid_options(const gmres_options* o) {
   if (o->arnoldi_a < GMRES_ARNOLDI_A_DEFAULT || o->arnoldi_a > GMRES_ARNOLDI_A_FP32) return false;
   if (o->precond_precision != GMRES_PRECOND_NATIVE && o->precond_precision != GMRES_PRECOND_FP32) return false;
   if (o->persistent_spmv < 0 || o->persistent_spmv > PV_COUNT) return false;
+  if (o->precond_side != GMRES_PRECOND_RIGHT && o->precond_side != GMRES_PRECOND_LEFT) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
@@ -443,10 +444,12 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
   const KArgs& a = h->a;
   const bool two = a.prec == PBF16 || a.prec == PF16;
   hipError_t e = launch_residual(a, st);
+  if (e == hipSuccess) e = launch_left_start(a, st);  // left preconditioning: r = M^-1 z, beta = ||r||
   if (e == hipSuccess) e = launch_encode(a, 0, st);
   for (int j = 0; j < a.m && e == hipSuccess; ++j) {
-    if (a.precond != 0) e = launch_precond(a, j, st);
+    if (a.precond != 0 && !a.left) e = launch_precond(a, j, st);
     if (e == hipSuccess) e = launch_spmv_arnoldi(a, j, st);
+    if (e == hipSuccess) e = launch_left_apply(a, st);  // w = M^-1 A v_j
     if (e != hipSuccess) break;
     if (h->opt.ortho == GMRES_CGSR) {
       e = launch_cgs_pass1(a, j, st);
@@ -512,18 +515,20 @@ void enqueue_cycle_profiled(gmres_ctx* h, hipStream_t st, ProfPool& pool, std::v
   timed(GMRES_PK_RESIDUAL, -1, nnz * 12.0 + 4.0 * (n + 1) + 16.0 * n + n * sw,
         [&] { return launch_residual(a, st, false); });
   timed(GMRES_PK_REDUCE, -1, 0.0, [&] { return launch_residual_finish(a, st); });
+  if (a.left && a.precond != 0) timed(GMRES_PK_PRECOND, -1, 0.0, [&] { return launch_left_start(a, st); });
   timed(GMRES_PK_ENCODE, -1, n * sw + n * sv, [&] { return launch_encode(a, 0, st); });
   for (int j = 0; j < a.m; ++j) {
     const double ncol = j + 1;
-    if (a.precond != 0) {
+    if (a.precond != 0 && !a.left) {
       const double sz = a.z64 ? 8.0 : 4.0, sd = a.pc64 ? 8.0 : 4.0;
       const double pb = a.precond == 1 ? n * sv + n * sd + n * sz
                       : a.precond == 2 ? nnz * 8.0 + 4.0 * (n + 1) + n * sv + n * sz : 0.0;
       timed(GMRES_PK_PRECOND, j, pb, [&] { return launch_precond(a, j, st); });
     }
-    const double sx = a.precond != 0 ? (a.z64 ? 8.0 : 4.0) : sv;
+    const double sx = a.precond != 0 && !a.left ? (a.z64 ? 8.0 : 4.0) : sv;
     timed(GMRES_PK_SPMV, j, nnz * (sa + 4.0) + 4.0 * (n + 1) + n * sx + n * sw,
           [&] { return launch_spmv_arnoldi(a, j, st); });
+    if (a.left && a.precond != 0) timed(GMRES_PK_PRECOND, j, 0.0, [&] { return launch_left_apply(a, st); });
     if (h->opt.ortho == GMRES_CGSR) {
       const double win = std::ceil(ncol / 64.0);
       timed(GMRES_PK_PASS1, j, ncol * n * sv + win * n * sw, [&] { return launch_cgs_pass1(a, j, st, false); });
@@ -902,10 +907,15 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   // its arithmetic unless a float32 preconditioner was asked for
   a.z64 = (opt->precond != GMRES_PRECOND_NONE && prec == P64) ? 1 : 0;
   a.pc64 = (a.z64 && opt->precond_precision == GMRES_PRECOND_NATIVE) ? 1 : 0;
-  if (opt->precond != GMRES_PRECOND_NONE) {
+  a.left = (opt->precond != GMRES_PRECOND_NONE && opt->precond_side == GMRES_PRECOND_LEFT) ? 1 : 0;
+  if (opt->precond != GMRES_PRECOND_NONE && !a.left) {
     const size_t zb = a.z64 ? 8 : 4;
     a.Z = h->alloc<uint8_t>((size_t)(m * h->ld) * zb);
     hip_check(hipMemsetAsync(a.Z, 0, (size_t)(m * h->ld) * zb, h->stream));
+  }
+  if (a.left && opt->precond == GMRES_PRECOND_SPAI) {
+    a.ptmp = h->alloc<uint8_t>((size_t)h->ld * wbytes(prec));
+    hip_check(hipMemsetAsync(a.ptmp, 0, (size_t)h->ld * wbytes(prec), h->stream));
   }
   a.x = h->alloc<double>(h->ld);
   a.b = h->alloc<double>(h->ld);
@@ -1039,6 +1049,7 @@ void run_cycles(gmres_ctx* h) {
   KArgs& a = h->a;
   hip_check(launch_init_state(a, h->stream));
   hip_check(launch_bnorm(a, h->stream));
+  hip_check(launch_left_bnorm(a, h->stream));
   if (h->opt.use_graph) build_graph(h);
   const int S = a.S;
   const int64_t cap = h->opt.max_iters / 1 + 8;
@@ -1177,6 +1188,7 @@ void gmres_default_options(gmres_options* o) {
   o->arnoldi_a = GMRES_ARNOLDI_A_DEFAULT;
   o->precond_precision = GMRES_PRECOND_NATIVE;
   o->persistent_spmv = 0;
+  o->precond_side = GMRES_PRECOND_RIGHT;
 }
 
 const char* gmres_strerror(int code) {
@@ -1648,12 +1660,13 @@ int gmres_solve_profiled(gmres_handle hh, const double* b, double* x, gmres_resu
     const auto t0 = std::chrono::steady_clock::now();
     const int64_t n = h->sys[0].n;
     KArgs& a = h->a;
-    const double sv_upd = a.precond != 0 ? (a.z64 ? 8.0 : 4.0) : (double)vbytes(a.prec);
+    const double sv_upd = a.precond != 0 && !a.left ? (a.z64 ? 8.0 : 4.0) : (double)vbytes(a.prec);
     after_caller(h);
     hip_check(hipMemcpyAsync(a.b, b, n * 8, hipMemcpyDeviceToDevice, h->stream));
     hip_check(hipMemcpyAsync(a.x, x, n * 8, hipMemcpyDeviceToDevice, h->stream));
     hip_check(launch_init_state(a, h->stream));
     hip_check(launch_bnorm(a, h->stream));
+    hip_check(launch_left_bnorm(a, h->stream));
     ProfPool pool;
     std::vector<ProfRec> recs;
     const int64_t cap = h->opt.max_iters + 8;

@@ -68,6 +68,7 @@ struct SysState {
   int32_t klimit;       // two-stage restarts: the first cycle's length (0 until it ends)
   double orth_fro2;     // loss-of-orthogonality monitor: ||S_k||_F^2 of the current cycle
   double orth_norm;     //   and the last norm it compared with the threshold
+  double bnorm_p;       // ||M^-1 b||_2 (left preconditioning), else ||b||_2
 };
 
 // Work split of a persistent basis pass with G workgroups: workgroup b owns
@@ -116,6 +117,8 @@ struct KArgs {
   // (z64 = 1), else float32.
   int32_t pc64;
   int32_t z64;
+  int32_t left;        // 1: M^-1 applied on the left (r = M^-1 (b - A x), w = M^-1 A v_j); Z unused
+  void* ptmp;          // left preconditioning with the learned M: the product's output (ld rows of w's type)
   const float* dinv;   // Jacobi: 1 / a_ii (float32)
   const double* dinv64;  //   (float64)
   const float* ilu32;  // ILU(0) factors on A's pattern (float32): L below the diagonal, U the rest
@@ -212,6 +215,14 @@ hipError_t launch_orth_check(const KArgs& a, int j, hipStream_t st);
 hipError_t launch_backsolve(const KArgs& a, hipStream_t st);
 // the kernel that completes CGS projection 2 at column j (timing)
 hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st);
+// Left preconditioning: w <- M^-1 w on the systems whose cycle runs with the
+// preconditioner on (every system while the state's force flag is set);
+// launch_left_start: after the restart residual, M^-1 z, its norm and the
+// cycle's s_1 and first decode scale; launch_left_bnorm: ||M^-1 b|| at the
+// start of a solve (w is overwritten).
+hipError_t launch_left_apply(const KArgs& a, hipStream_t st);
+hipError_t launch_left_start(const KArgs& a, hipStream_t st);
+hipError_t launch_left_bnorm(const KArgs& a, hipStream_t st);
 // The completing reductions on their own (the in-solve profile launches each
 // pass without its reduction, then these): the residual's norm and stop
 // test, projection 1's coefficients, and the end-of-step finaliser.

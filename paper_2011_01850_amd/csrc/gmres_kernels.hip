@@ -341,7 +341,9 @@ __device__ void fin_step(const KArgs& a, int s, int j, double sumsq, double wmax
       // the two-stage strategy), the first cycle's length (two-stage), a
       // stalled Arnoldi residual
       const bool first_stage = !a.restart_repeat || S.klimit == 0;
-      const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * S.bnorm ||
+      // (left preconditioning: |s_{j+1}| estimates ||M^-1 (b - A x)||)
+      const double est_ref = a.left && S.precond_on ? S.bnorm_p : S.bnorm;
+      const bool end = (j + 1 >= m) || !(hn > bd * S.wnorm_pre) || res <= a.tol * est_ref ||
                        S.iters >= a.max_iters ||
                        (a.restart_improve > 0.0 && first_stage && res <= a.restart_improve * S.beta) ||
                        (!first_stage && j + 1 >= S.klimit) ||
@@ -423,7 +425,8 @@ __device__ void fin_residual(const KArgs& a, int s, double sumsq, double zmax) {
 
 // ------------------------------------------------------------------ SpMV
 
-enum SpmvMode { SM_ARNOLDI = 0, SM_PRECOND = 1, SM_AZ = 2, SM_RESID = 3, SM_PLAIN = 4, SM_RESID_PLAIN = 5 };
+enum SpmvMode { SM_ARNOLDI = 0, SM_PRECOND = 1, SM_AZ = 2, SM_RESID = 3, SM_PLAIN = 4, SM_RESID_PLAIN = 5,
+                SM_LEFT = 6 };
 
 // Adaptive CSR: a row block is either up to 256 rows whose non-zeros fit
 // the streaming budget (products staged in LDS, each row reduced by a
@@ -444,6 +447,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
   const int s = a.rb_sys[blk];
   if (MODE == SM_ARNOLDI || MODE == SM_PRECOND || MODE == SM_AZ) {
     if (!gated(a, s)) return;
+  } else if (MODE == SM_LEFT) {  // the learned M applied to w (left preconditioning), unscaled
+    if (!gated(a, s) || (!a.st[s].precond_on && !a.st[s].force)) return;
   } else if (MODE == SM_RESID) {
     const SysState& S = a.st[s];
     if (S.status != RUNNING && !S.force) return;
@@ -1026,7 +1031,34 @@ __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab
 // The per-system completions read the partial rows the preceding pass wrote
 // (the kernel boundary makes them visible) and run the system's scalar step.
 
-enum FinMode { FIN_STEP = 0, FIN_RESID = 1, FIN_BNORM = 2 };
+enum FinMode { FIN_STEP = 0, FIN_RESID = 1, FIN_BNORM = 2, FIN_LEFT = 3, FIN_BNORMP = 4 };
+
+// Left preconditioning, at the start of a cycle: beta = ||M^-1 z|| becomes
+// s_1 and the reference of the improvement trigger, and v_1 = M^-1 z / beta
+// gets its decode scale.  A zero or non-finite M^-1 z switches the
+// preconditioner off and ends the cycle without a correction (the next one
+// runs plain GMRES from the same x).
+__device__ void fin_left(const KArgs& a, int s, double sumsq, double wmax) {
+  SysState& S = a.st[s];
+  const int M1 = a.m + 1;
+  const double beta = sqrt(sumsq);
+  if (!(beta > 0.0) || !isfinite(beta)) {
+    S.active = 0;
+    S.precond_on = 0;
+    S.fallback_used = 1;
+    return;
+  }
+  S.beta = beta;
+  a.s[(int64_t)s * M1] = beta;
+  a.ares[(int64_t)s * M1] = beta;
+  if (a.prec == PBF16 || a.prec == PF16) {
+    const int e = scale_exp(wmax / beta, a.prec);
+    a.sc[(int64_t)s * M1] = ldexp(1.0, -e);
+    S.enc_f = (float)(ldexp(1.0, e) / beta);
+  } else {
+    a.sc[(int64_t)s * M1] = 1.0 / beta;
+  }
+}
 
 // `src` with column stride `rows`; system s owns rows [r0[s], r0[s] + nr[s]).
 template <int MODE>
@@ -1038,13 +1070,20 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, const double* src, i
     if (S.status != RUNNING && !S.force) return;
   } else if (MODE == FIN_STEP) {
     if (!S.active && !S.force) return;
+  } else if (MODE == FIN_LEFT) {
+    if (!S.active || !S.precond_on) return;
   }
   const int b0 = r0[s], n = nr[s];
   const double sq = reduce_col<false>(src + b0, n);
-  if (MODE == FIN_BNORM) {
+  if (MODE == FIN_BNORM || MODE == FIN_BNORMP) {
     if (threadIdx.x == 0) {
       SysState& W = a.st[s];
+      if (MODE == FIN_BNORMP) {
+        W.bnorm_p = sqrt(sq);
+        return;
+      }
       W.bnorm = sqrt(sq);
+      W.bnorm_p = W.bnorm;
       if (W.bnorm == 0.0) {
         W.status = CONVERGED;
         W.rel = 0.0;
@@ -1053,7 +1092,12 @@ __global__ __launch_bounds__(kFinBlock) void k_fin(KArgs a, const double* src, i
     return;
   }
   const double mx = reduce_col<true>(src + rows + b0, n);
-  if (threadIdx.x == 0) fin_residual(a, s, sq, mx);
+  if (threadIdx.x == 0) {
+    if (MODE == FIN_LEFT)
+      fin_left(a, s, sq, mx);
+    else
+      fin_residual(a, s, sq, mx);
+  }
 }
 
 // Sum of p[0, n) and maximum of q[0, n), both in a fixed order, in one pass
@@ -1379,6 +1423,61 @@ __global__ __launch_bounds__(kBlock) void k_ilu_usweep(KArgs a, const TP* __rest
   dst[r] = (TO)((y[r] - acc) * ilu_udinv<TP>(a)[r]);
 }
 
+// ---------------------------------------------------- left preconditioning
+// w <- M^-1 w where the system's cycle runs with the preconditioner on (or
+// the state's force flag is set).  TW: w's type; TP: the preconditioner's.
+__device__ __forceinline__ bool left_on(const KArgs& a, int s) {
+  return gated(a, s) && (a.st[s].precond_on || a.st[s].force);
+}
+
+template <typename TW, typename TP>
+__global__ __launch_bounds__(kBlock) void k_left_jacobi(KArgs a) {
+  const int s = a.tile_sys[blockIdx.x];
+  if (!left_on(a, s)) return;
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  TW* w = static_cast<TW*>(a.w);
+  w[r] = (TW)(jacobi_dinv<TP>(a)[r] * (TP)w[r]);
+}
+
+template <typename TW, typename TP>
+__global__ __launch_bounds__(kBlock) void k_left_ilu_begin(KArgs a) {
+  const int s = a.tile_sys[blockIdx.x];
+  if (!left_on(a, s)) return;
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  static_cast<TP*>(a.ilu_v)[r] = (TP)static_cast<const TW*>(a.w)[r];
+}
+
+template <typename TW>
+__global__ __launch_bounds__(kBlock) void k_left_copy(KArgs a) {
+  const int s = a.tile_sys[blockIdx.x];
+  if (!left_on(a, s)) return;
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  static_cast<TW*>(a.w)[r] = static_cast<const TW*>(a.ptmp)[r];
+}
+
+// ||w||^2 and max|w| per tile (the preconditioned residual at a cycle's start,
+// or M^-1 b): systems with a running cycle and the preconditioner on, or all
+// under the force flag
+template <typename TW>
+__global__ __launch_bounds__(kBlock) void k_left_norm(KArgs a) {
+  const int s = a.tile_sys[blockIdx.x];
+  const SysState& S = a.st[s];
+  if (!((S.active && S.precond_on) || S.force)) return;
+  const double v = (double)static_cast<const TW*>(a.w)[(int64_t)blockIdx.x * kTile + threadIdx.x];
+  const double sq = block_sum(v * v);
+  const double mx = block_max(fabs(v));
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = sq;
+    a.part[(int64_t)a.ntile + blockIdx.x] = mx;
+  }
+}
+
+template <typename TW>
+__global__ __launch_bounds__(kBlock) void k_b_to_w(KArgs a) {
+  const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
+  static_cast<TW*>(a.w)[r] = (TW)a.b[r];
+}
+
 // y = H^-1 s by back-substitution, one wave per system, with truncation of
 // a singular leading block.  Also turns y into update coefficients.
 __global__ __launch_bounds__(64) void k_backsolve(KArgs a) {
@@ -1432,9 +1531,9 @@ __global__ __launch_bounds__(kBlock) void k_update(KArgs a) {
   const double* yv = a.y + (int64_t)s * a.m;
   const int64_t r = (int64_t)blockIdx.x * kTile + threadIdx.x;
   double acc = a.x[r];
-  if (a.precond != 0 && a.z64) {
+  if (a.precond != 0 && !a.left && a.z64) {
     for (int i = 0; i < kk; ++i) acc += yv[i] * static_cast<const double*>(a.Z)[(int64_t)i * a.ld + r];
-  } else if (a.precond != 0) {
+  } else if (a.precond != 0 && !a.left) {
     for (int i = 0; i < kk; ++i) acc += yv[i] * (double)static_cast<const float*>(a.Z)[(int64_t)i * a.ld + r];
   } else {
     for (int i = 0; i < kk; ++i) acc += yv[i] * (double)ldv(col_ptr<TV>(a, i)[r]);
@@ -1698,7 +1797,7 @@ static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStre
 }
 
 hipError_t launch_spmv_arnoldi(const KArgs& a, int j, hipStream_t st) {
-  if (a.precond != 0) {  // w = A z_j
+  if (a.precond != 0 && !a.left) {  // w = A z_j
     if (a.z64)
       return spmv_values<double, double, SM_AZ>(a, static_cast<const double*>(a.Z) + (int64_t)j * a.ld,
                                                 (double*)a.w, j, st);
@@ -1792,6 +1891,74 @@ hipError_t launch_precond(const KArgs& a, int j, hipStream_t st) {
       return hipGetLastError();
     });
   });
+}
+
+// w's type for a precision mode
+template <typename F>
+static hipError_t launch_by_w(int prec, F&& f) {
+  if (wide_w(prec)) return f(double{});
+  return f(float{});
+}
+
+hipError_t launch_left_apply(const KArgs& a, hipStream_t st) {
+  if (a.precond == 0 || !a.left) return hipSuccess;
+  return launch_by_w(a.prec, [&](auto tw) -> hipError_t {
+    using TW = decltype(tw);
+    auto go = [&](auto tp) -> hipError_t {
+      using TP = decltype(tp);
+      if (a.precond == 1) {
+        hipLaunchKernelGGL((k_left_jacobi<TW, TP>), dim3(a.ntile), dim3(kBlock), 0, st, a);
+      } else if (a.precond == 3) {
+        hipLaunchKernelGGL((k_left_ilu_begin<TW, TP>), dim3(a.ntile), dim3(kBlock), 0, st, a);
+        return ilu_apply_t<TP, TW>(a, static_cast<TW*>(a.w), st);
+      } else {
+        hipLaunchKernelGGL((k_spmv<float, TW, TW, SM_LEFT>), dim3(a.nrb), dim3(kBlock),
+                           (size_t)a.spmv_budget * sizeof(AccFor<float, TW>), st, a, a.mval,
+                           static_cast<const TW*>(a.w), static_cast<TW*>(a.ptmp), nullptr, 0);
+        hipLaunchKernelGGL((k_left_copy<TW>), dim3(a.ntile), dim3(kBlock), 0, st, a);
+      }
+      return hipGetLastError();
+    };
+    if (a.pc64) return go(double{});
+    return go(float{});
+  });
+}
+
+hipError_t launch_left_start(const KArgs& a, hipStream_t st) {
+  if (a.precond == 0 || !a.left) return hipSuccess;
+  hipError_t e = launch_left_apply(a, st);
+  if (e != hipSuccess) return e;
+  e = launch_by_w(a.prec, [&](auto tw) -> hipError_t {
+    using TW = decltype(tw);
+    hipLaunchKernelGGL((k_left_norm<TW>), dim3(a.ntile), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fin<FIN_LEFT>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.ntile, a.sys_t0, a.sys_nt,
+                     0);
+  return hipGetLastError();
+}
+
+hipError_t launch_left_bnorm(const KArgs& a, hipStream_t st) {
+  if (a.precond == 0 || !a.left) return hipSuccess;
+  hipError_t e = launch_by_w(a.prec, [&](auto tw) -> hipError_t {
+    using TW = decltype(tw);
+    hipLaunchKernelGGL((k_b_to_w<TW>), dim3(a.ntile), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+  });
+  if (e == hipSuccess) e = launch_set_force(a, 1, st);
+  if (e == hipSuccess) e = launch_left_apply(a, st);
+  if (e == hipSuccess)
+    e = launch_by_w(a.prec, [&](auto tw) -> hipError_t {
+      using TW = decltype(tw);
+      hipLaunchKernelGGL((k_left_norm<TW>), dim3(a.ntile), dim3(kBlock), 0, st, a);
+      return hipGetLastError();
+    });
+  if (e == hipSuccess) e = launch_set_force(a, 0, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fin<FIN_BNORMP>), dim3(a.S), dim3(kFinBlock), 0, st, a, a.part, a.ntile, a.sys_t0, a.sys_nt,
+                     0);
+  return hipGetLastError();
 }
 
 hipError_t launch_residual(const KArgs& a, hipStream_t st, bool with_fin) {

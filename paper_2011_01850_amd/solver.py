@@ -34,7 +34,8 @@ def _dev(t, dtype, torch):
 def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles, use_graph,
              autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
              restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4,
-             arnoldi_a="default", precond_precision="native", persistent_spmv="tuned") -> L.Options:
+             arnoldi_a="default", precond_precision="native", persistent_spmv="tuned",
+             precond_side="right") -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -59,6 +60,7 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
                            else int(precond_precision))
     o.persistent_spmv = (L.PERSISTENT_SPMVS[persistent_spmv] if isinstance(persistent_spmv, str)
                          else int(persistent_spmv))
+    o.precond_side = L.PRECOND_SIDES[precond_side] if isinstance(precond_side, str) else int(precond_side)
     return o
 
 
@@ -69,7 +71,8 @@ class Solver:
                  precond="none", max_iters=100_000, restart_improve=0.0, stall_cycles=10,
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
                  a_storage="copy", restart_repeat=False, restart_on_stall=False, orth_restart=0.0,
-                 orth_norm="spectral", ilu_sweeps=4, arnoldi_a="default", precond_precision="native"):
+                 orth_norm="spectral", ilu_sweeps=4, arnoldi_a="default", precond_precision="native",
+                 precond_side="right"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -81,7 +84,8 @@ class Solver:
         self.m = int(m)
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
-                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a, precond_precision)
+                            restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a, precond_precision,
+                            precond_side=precond_side)
         self.precision = precision
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream

@@ -64,7 +64,8 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                        ("spmv_block_nnz", 8256), ("a_storage", 2), ("a_storage", -1), ("restart_repeat", 2),
                        ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
                        ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097),
-                       ("arnoldi_a", 3), ("arnoldi_a", -1), ("persistent_spmv", -1), ("persistent_spmv", 4)]:
+                       ("arnoldi_a", 3), ("arnoldi_a", -1), ("persistent_spmv", -1), ("persistent_spmv", 4), ("precond_side", 2),
+                       ("precond_side", -1)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -143,7 +144,7 @@ def test_struct_layouts_match_header():
     assert L.Options.restart_on_stall.offset == 76 and L.Options.orth_restart.offset == 80
     assert L.Options.orth_norm.offset == 88 and L.Options.ilu_sweeps.offset == 92
     assert L.Options.arnoldi_a.offset == 96 and L.Options.precond_precision.offset == 100
-    assert L.Options.persistent_spmv.offset == 104
+    assert L.Options.persistent_spmv.offset == 104 and L.Options.precond_side.offset == 108
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 
@@ -214,10 +215,11 @@ def test_binding_forwards_every_solver_option(lib):
                 continue
             assert name in params, (cls.__name__, name)
     o = S._options(30, 1e-9, 500, "mgs", "fp64", "ilu0", 1e-6, 7, False, False, "persistent", 1024, "split",
-                   True, True, 0.5, "frobenius", 0, "fp32", "fp32", "ell16")
+                   True, True, 0.5, "frobenius", 0, "fp32", "fp32", "ell16", "left")
     assert (o.m, o.max_iters, o.ortho, o.precision, o.precond) == (30, 500, L.MGS, L.FP64, L.PRECOND_ILU0)
     assert (o.stall_cycles, o.use_graph, o.autotune, o.batch_schedule) == (7, 0, 0, L.SCHEDULE_PERSISTENT)
     assert (o.spmv_block_nnz, o.a_storage, o.restart_repeat, o.restart_on_stall) == (1024, L.A_SPLIT, 1, 1)
     assert (o.orth_norm, o.ilu_sweeps, o.arnoldi_a) == (L.ORTH_FROBENIUS, 0, L.ARNOLDI_A_FP32)
     assert (o.precond_precision, o.persistent_spmv) == (L.PRECOND_FP32, 1 + L.PSPMV_ELL16)
+    assert o.precond_side == L.PRECOND_LEFT
     assert o.tol == 1e-9 and o.restart_improve == 1e-6 and o.orth_restart == 0.5

@@ -920,3 +920,65 @@ def test_fp64_preconditioned_solver_matches_oracle(kind):
     # the same precision and method: the iteration counts agree closely (the
     # float32 M of the learned path is the float32 rounding of D^-1)
     assert abs(info["iters"] - ref.iters) <= (2 if kind in ("jacobi", "ilu0_exact", "ilu0_sweeps") else 30)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "limited", "fp16"])
+@pytest.mark.parametrize("kind", ["jacobi", "ilu0_sweeps", "ilu0_exact", "spai_jacobi"])
+def test_left_preconditioned_solver_matches_oracle(kind, precision):
+    # Algorithm 1 with M^-1 on the left (the paper's form): r = M^-1 (b - A x),
+    # w = M^-1 A v_j, x += V y; the float64 restart residual decides
+    A0 = P.varcoef3d(16, family=94, index=0)
+    M = O.Matrix.from_csr(A0)
+    xt, b = P.manufactured_rhs(A0, 94, 0)
+    d = M.diagonal()
+    lu, diag = O.ilu0(M)
+    dt = np.float64 if precision == "fp64" else np.float32
+    kw = {}
+    if kind == "jacobi" or kind == "spai_jacobi":
+        pc, name = (lambda v: (v / d).astype(v.dtype)), ("jacobi" if kind == "jacobi" else "spai")
+    elif kind == "ilu0_sweeps":
+        pc, name, kw = (lambda v: O.ilu_apply(M, lu, diag, v, sweeps=4, dtype=dt)), "ilu0", {"ilu_sweeps": 4}
+    else:
+        pc, name, kw = (lambda v: O.ilu_apply(M, lu, diag, v, sweeps=0, dtype=dt)), "ilu0", {"ilu_sweeps": 0}
+    ref = O.gmres(M, b, m=30, tol=1e-13, ortho="cgsr", precond=pc, side="left", fallback=False)
+    emu = O.gmres(M, b, m=30, tol=1e-13, ortho="cgsr", precond=pc, side="left", fallback=False,
+                  precision=precision) if precision != "fp64" else ref
+    s = _solver(A0, m=30, precision=precision, precond=name, tol=1e-13, precond_side="left", **kw)
+    if kind == "spai_jacobi":
+        rows = np.repeat(np.arange(A0.n), np.diff(A0.row_ptr))
+        s.set_preconditioner(np.where(A0.col_idx == rows, 1.0 / d[rows], 0.0).astype(np.float32))
+    x, info = s.solve(b)
+    hist = s.history()
+    s.close()
+    x = x.cpu().numpy()
+    rr = _relres(A0, b, x)
+    err = float(np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x))
+    cg, ce = _cycles_to(hist, 1e-10), _cycles_to(emu.history, 1e-10)
+    print(f"left {kind} {precision}: gpu {info['status']} iters {info['iters']} cycles to 1e-10 {cg} relres "
+          f"{rr:.2e} | oracle iters {ref.iters}, emulation iters {emu.iters} cycles {ce} | vs oracle x {err:.2e}",
+          flush=True)
+    assert ref.status == O.CONVERGED and emu.status == O.CONVERGED
+    assert info["status"] == "CONVERGED" and not info["fallback_used"] and rr <= 1.01e-13
+    assert err <= 1e-8
+    assert abs(cg - ce) <= max(1, math.ceil(0.15 * ce))
+    if precision == "fp64" and kind in ("jacobi", "ilu0_exact", "ilu0_sweeps"):
+        assert abs(info["iters"] - ref.iters) <= 2
+
+
+def test_left_preconditioning_with_identity_follows_plain_gmres():
+    # M = I on A's pattern, applied on the left: the same cycles as plain GMRES
+    A0 = P.varcoef3d(12, family=94, index=3)
+    xt, b = P.manufactured_rhs(A0, 94, 3)
+    rows = np.repeat(np.arange(A0.n), np.diff(A0.row_ptr))
+    ident = (A0.col_idx == rows).astype(np.float32)
+    for precision in ("fp64", "fp32"):
+        s = _solver(A0, m=20, precision=precision, precond="spai", tol=1e-12, precond_side="left")
+        s.set_preconditioner(ident)
+        x1, i1 = s.solve(b)
+        s.close()
+        s0 = _solver(A0, m=20, precision=precision, tol=1e-12)
+        x0, i0 = s0.solve(b)
+        s0.close()
+        assert i1["status"] == i0["status"] == "CONVERGED" and not i1["fallback_used"]
+        assert abs(i1["iters"] - i0["iters"]) <= 2
+        assert np.linalg.norm((x1 - x0).cpu().numpy()) <= 1e-9 * np.linalg.norm(x0.cpu().numpy())

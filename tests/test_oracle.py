@@ -628,6 +628,68 @@ def test_fgmres_with_jacobi_equals_right_preconditioned_gmres():
 
 
 # --------------------------------------------------------------------------
+# left preconditioning (the form of the paper's experiments): r = M^-1 (b - A x),
+# w = M^-1 A v_j, x += V y
+
+def test_left_preconditioning_with_identity_is_plain_gmres_bitwise():
+    pr = P.c1_convdiff2d(20)
+    A = _mat(pr.A)
+    for ortho in ("mgs", "cgsr"):
+        r0 = O.gmres(A, pr.b, m=15, tol=1e-10, ortho=ortho)
+        r1 = O.gmres(A, pr.b, m=15, tol=1e-10, ortho=ortho, precond=lambda v: v.copy(), side="left")
+        assert r0.iters == r1.iters and np.array_equal(r0.x, r1.x) and r0.history == r1.history
+
+
+def test_left_preconditioning_with_the_exact_inverse_takes_one_step():
+    # M^-1 = A^-1: M^-1 A = I, so the first Arnoldi step spans the solution
+    D = np.array([[4.0, 1.0, 0.0], [2.0, 5.0, 1.0], [0.0, 3.0, 6.0]])
+    A = O.Matrix.from_csr(P.dense_to_csr(D))
+    Ainv = np.linalg.inv(D)
+    b = np.array([1.0, -2.0, 0.5])
+    r = O.gmres(A, b, m=3, tol=1e-13, precond=lambda v: Ainv @ v, side="left", fallback=False, record=True)
+    assert r.status == O.CONVERGED and r.iters == 1
+    assert np.allclose(r.x, np.linalg.solve(D, b), rtol=1e-14, atol=1e-15)
+
+
+def test_left_preconditioning_is_gmres_on_the_preconditioned_system():
+    # one cycle of left-preconditioned GMRES with M^-1 = D^-1 is GMRES on
+    # (D^-1 A) x = D^-1 b: the same iterate up to rounding, and its Arnoldi
+    # residual |s_{k+1}| is the preconditioned residual ||D^-1 (b - A x)||,
+    # the quantity it minimises
+    A0 = P.varcoef3d(8, family=90, index=2)
+    A = _mat(A0)
+    d = A.diagonal()
+    xt = np.random.default_rng(12).uniform(-1, 1, A.n)
+    b = A.matvec(xt)
+    m = 20
+    rl = O.gmres(A, b, m=m, tol=0.0, max_iters=m, precond=lambda v: v / d, side="left", fallback=False,
+                 record=True)
+    rows = np.repeat(np.arange(A.n), np.diff(A0.row_ptr))
+    DA = O.Matrix(A0.row_ptr, A0.col_idx, A0.vals / d[rows], A.n)
+    re = O.gmres(DA, b / d, m=m, tol=0.0, max_iters=m)
+    assert rl.iters == re.iters == m
+    assert np.linalg.norm(rl.x - re.x) <= 1e-12 * np.linalg.norm(re.x)
+    s_last = abs(rl.cycles[0]["s"][m])
+    pres = np.linalg.norm((b - A.matvec(rl.x)) / d)
+    assert s_last == pytest.approx(pres, rel=1e-8)
+
+
+def test_left_preconditioned_mixed_and_ilu_reach_double_accuracy():
+    # the restart residual b - A x judges convergence whatever the side
+    A0 = P.varcoef3d(10, family=90, index=3)
+    A = _mat(A0)
+    xt = np.random.default_rng(13).uniform(-1, 1, A.n)
+    b = A.matvec(xt)
+    lu, diag = O.ilu0(A)
+    for precision, dt in (("fp64", np.float64), ("fp32", np.float32)):
+        r = O.gmres(A, b, m=20, tol=1e-11, precision=precision, side="left",
+                    precond=lambda v: O.ilu_apply(A, lu, diag, v, sweeps=0, dtype=dt))
+        assert r.status == O.CONVERGED and O.relative_residual(A, b, r.x) <= 1e-11
+        plain = O.gmres(A, b, m=20, tol=1e-11, precision=precision)
+        assert r.iters < plain.iters
+
+
+# --------------------------------------------------------------------------
 # normwise backward error (the stopping metric the paper's experiments use)
 
 def test_backward_error_closed_form_2x2():

@@ -92,9 +92,10 @@ def parse():
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the whole float64 oracle solve instead of a sample (minutes)")
     ap.add_argument("--mgs-steps", type=int, default=3, help="timed steps of each MGS mode (default workload)")
-    ap.add_argument("--legs", default="c3,c4,c5",
+    ap.add_argument("--legs", default="ilu,c3,c4,c5",
                     help="default workload: comma-separated extra legs to run after the headline system "
-                         "(c3 = power-law, c4 = batch, c5 = learned preconditioner), or 'none'")
+                         "(ilu = the paper's ILU(0) precision study on the same system, c3 = power-law, "
+                         "c4 = batch, c5 = learned preconditioner), or 'none'")
     ap.add_argument("--c5-train", type=int, default=2000, help="c5 leg: training instances")
     ap.add_argument("--c5-test", type=int, default=200, help="c5 leg: held-out instances")
     ap.add_argument("--copy-probe", action="store_true",
@@ -196,7 +197,24 @@ def in_solve_profile(solver, b_dev):
     return x, info, fam
 
 
-def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", families=HBM_FAMILIES):
+def harness_times(solver, m, reps, families=("spmv", "pass1", "pass2", "final", "mgs")):
+    """gmres_time_kernel at the last column for each family (run before the
+    profiled solve: back-to-back launches on the solver's stream), with the
+    launch configuration."""
+    out = {}
+    for f in families:
+        try:
+            ms, by = solver.time_kernel(HARNESS_KERNEL[f], m - 1, reps)
+            cfg = solver.launch_config(f, m - 1)
+        except Exception:  # noqa: BLE001 - a family the handle does not run (MGS kernels on a CGSR handle)
+            continue
+        out[f] = {"j": m - 1, "reps": reps, "avg_launch_ms": round(ms, 5), "alg_bytes": by,
+                  "GB/s": round(by / (ms * 1e-3) / 1e9, 1), "launch_config": cfg}
+    return out
+
+
+def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", families=HBM_FAMILIES,
+                          harness=None):
     """The dominant kernel: the template instantiation with the most in-solve
     time among the HBM-bound families; achieved = its algorithmic bytes over
     its summed in-solve launch time (launches that did work).  Beside it: every
@@ -227,12 +245,10 @@ def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", 
     per_launch = dom["alg_bytes"] / dom["active_launches"]
     traffic = measured_traffic(dom["kernel"])
     j_last = int(dom["columns"].split("..")[1])
-    harness = None
-    if dom["family"] in HARNESS_KERNEL:
-        ms, by = solver.time_kernel(HARNESS_KERNEL[dom["family"]], j_last, reps)
-        harness = {"j": j_last, "reps": reps, "avg_launch_ms": round(ms, 5), "alg_bytes": by,
-                   "GB/s": round(by / (ms * 1e-3) / 1e9, 1)}
-    cfg = solver.launch_config(dom["family"], j_last) if dom["family"] in HARNESS_KERNEL else None
+    h = (harness or {}).get(dom["family"])
+    if h is not None and h["j"] != j_last:
+        h = None  # the harness timed another instantiation of the family
+    cfg = h["launch_config"] if h else None
     fams = {k: {kk: vv for kk, vv in v.items() if kk != "by_col"} for k, v in fam.items()}
     return {
         "bound": "hbm",
@@ -251,7 +267,7 @@ def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", 
                      f"{dom['columns']} of every cycle (of {dom['launches']}; the rest are gated off after the "
                      f"last cycle converged), each between two HIP events on the solver's stream"),
         "avg_launch_ms_all_launches": round(dom["ms_all"] / dom["launches"], 5),
-        "harness_back_to_back": harness,
+        "harness_back_to_back": ({k: v for k, v in h.items() if k != "launch_config"} if h else None),
         "launch_config_at_j_last": cfg,
         "in_solve_kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in u.items()} for u in units],
         "in_solve_families": fams,
@@ -346,9 +362,11 @@ def bench_convdiff3d(args):
 
     mixed, x_mix, solver = mode(args.ortho, args.precision, args.steps, args.warmup)
     value = mixed["seconds_mean"]
+    log("kernel harness (back-to-back launches at the last column) ...")
+    harness = harness_times(solver, m, args.roofline_reps)
     log("in-solve kernel profile (one more solve, every launch between HIP events) ...")
     _, pinfo, fam = in_solve_profile(solver, b_dev)
-    rf = roofline_from_profile(solver, fam, m, args.roofline_reps, args.precision, args.ortho)
+    rf = roofline_from_profile(solver, fam, m, args.roofline_reps, args.precision, args.ortho, harness=harness)
     log(f"  dominant family {rf['family']}: {rf['avg_launch_ms'] * 1e3:.1f} us per launch, "
         f"{rf['achieved']:.0f} GB/s ({rf['frac']:.3f} of peak); harness "
         f"{(rf['harness_back_to_back'] or {}).get('avg_launch_ms', 0) * 1e3:.1f} us at j = {m - 1}")
@@ -386,8 +404,10 @@ def bench_convdiff3d(args):
     if args.ortho == "cgsr" and args.mgs_steps > 0:
         log("MGS ...")
         mg, xm, sm = mode("mgs", args.precision, args.mgs_steps, min(args.warmup, 1))
+        hm = harness_times(sm, m, args.roofline_reps, families=("mgs",))
         _, _, fam_m = in_solve_profile(sm, b_dev)
-        rf_m = roofline_from_profile(sm, fam_m, m, args.roofline_reps, args.precision, "mgs", families=("mgs",))
+        rf_m = roofline_from_profile(sm, fam_m, m, args.roofline_reps, args.precision, "mgs", families=("mgs",),
+                                     harness=hm)
         sm.close()
         out_mgs = {"mixed": mg, "roofline_mgs_step": rf_m}
         if not args.no_fp64:
@@ -446,9 +466,62 @@ def bench_convdiff3d(args):
             rec["batch"] = leg_batch(args)
         elif leg == "c5":
             rec["learned"] = leg_learned(args)
+        elif leg == "ilu":
+            rec["ilu_precision_study"] = leg_ilu(args)
         else:
             raise SystemExit(f"unknown leg {leg}")
     return rec
+
+
+def leg_ilu(args):
+    """The precision study of the paper's experiments (Section 4.2) on the
+    headline system: left ILU(0)-preconditioned GMRES(50) (4 Jacobi sweeps per
+    triangle) with everything in float64, with only the preconditioner in
+    float32 ("FP32 ILU only"), and the mixed solver (float32 Arnoldi and
+    preconditioner); MGS and CGSR; time to 1e-10 including setup."""
+    import numpy as np
+    import torch
+
+    import problems as P
+    from paper_2011_01850_amd import Solver
+
+    m = 50
+    pr = P.c2_convdiff3d(args.N)
+    A = pr.A
+    A_dev = tuple(torch.as_tensor(v, device="cuda") for v in (A.row_ptr, A.col_idx, A.vals))
+    b_dev = torch.as_tensor(pr.b, device="cuda")
+    rp, ci, va = A_dev
+    cases = [("fp64", "fp64", "native"), ("fp32_ilu_only", "fp64", "fp32"), ("mixed", "fp32", "native")]
+    out = {"workload": f"3-D convection-diffusion {args.N}^3, left ILU(0) (4 sweeps per triangle), GMRES({m}), "
+                       f"tol 1e-10, time incl. setup (ILU factorisation included, as the paper times it)"}
+    for ortho in ("mgs", "cgsr"):
+        rows = {}
+        for name, prec, pcp in cases:
+            times, info, x = [], None, None
+            for it in range(1 + 3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s = Solver(rp, ci, va, m=m, ortho=ortho, precision=prec, tol=1e-10, precond="ilu0", ilu_sweeps=4,
+                           precond_side="left", precond_precision=pcp)
+                x, info = s.solve(b_dev)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                if it:
+                    times.append(dt)
+                    eta = s.backward_error(b_dev, x)[0] if it == 3 else None
+                s.close()
+            fwd = float(np.linalg.norm(x.cpu().numpy() - pr.x_true) / np.linalg.norm(pr.x_true))
+            rows[name] = {"seconds_mean": statistics.mean(times), "seconds_min": min(times), "iters": info["iters"],
+                          "restarts": info["restarts"], "status": info["status"],
+                          "rel_residual": info["rel_residual"], "backward_error": eta, "forward_error": fwd}
+            log(f"  ILU(0) {ortho} {name}: {statistics.mean(times) * 1e3:.1f} ms, iters {info['iters']}, "
+                f"{info['status']}")
+        for name in rows:
+            rows[name]["speedup_vs_fp64"] = round(rows["fp64"]["seconds_mean"] / rows[name]["seconds_mean"], 3)
+        out[ortho] = rows
+    out["paper_context"] = ("paper (2x10-core Haswell, SuiteSparse, left ILU(0)): mixed +19% (MGS) / +24% (CGSR), "
+                            "FP32 ILU only +2% / +2% over FP64 GMRES")
+    return out
 
 
 def leg_powerlaw(args):
@@ -562,9 +635,10 @@ def bench_powerlaw(args):
         fwd = float(np.linalg.norm(xs - pr.x_true) / np.linalg.norm(pr.x_true))
         modes[mode] = _mode_summary(t, inf, fwd, s.memory_bytes())
         modes[mode]["backward_error"] = s.backward_error(b_dev, x)[0]
+        hs = harness_times(s, m, args.roofline_reps, families=("spmv",))
         _, _, fam = in_solve_profile(s, b_dev)
         kern[mode] = {"spmv_roofline": roofline_from_profile(s, fam, m, args.roofline_reps, mode, args.ortho,
-                                                             families=("spmv",))}
+                                                             families=("spmv",), harness=hs)}
         s.close()
     for mode in modes:
         modes[mode]["speedup_vs_fp64"] = round(modes["fp64"]["seconds_mean"] / modes[mode]["seconds_mean"], 3)

@@ -180,7 +180,20 @@ typedef struct {
                                 create-time tuner (autotune = 1; else CSR8); 1 + GMRES_PSPMV_* forces
                                 one */
   int32_t precond_side;      /* GMRES_PRECOND_RIGHT (flexible GMRES, the default) or GMRES_PRECOND_LEFT */
+  int32_t spmv_format;       /* GMRES_SPMV_*: the Arnoldi product's layout (device-wide schedule) */
 } gmres_options;
+
+/* gmres_options.spmv_format.  CSR: the adaptive row blocks (spmv_block_nnz).
+ * SELL: a sliced ELL copy of the values the Arnoldi product reads (64-row
+ * slices, entry k of a slice's rows contiguous, so each load of a wave is
+ * coalesced; 4 bytes of column and 4 or 8 of value per entry, padded to the
+ * slice's longest row, plus a byte of length per row), built at create; only
+ * when every row has fewer than 8 entries (then each row's sum is the plain
+ * sum in storage order, so both layouts give the same bits) and split storage
+ * is off, else CSR.  AUTO: SELL competes with the row-block budgets in the
+ * autotuner (autotune = 1), else CSR.  The residual and preconditioner
+ * products always use the row blocks. */
+enum { GMRES_SPMV_AUTO = 0, GMRES_SPMV_CSR = 1, GMRES_SPMV_SELL = 2 };
 
 /* gmres_options.precond_side.  RIGHT: flexible GMRES, z_j = M^-1 v_j kept,
  * w = A z_j, x += Z y.  LEFT, the form of the paper's experiments
@@ -236,7 +249,8 @@ typedef struct {
  * MIXED_FP32, no preconditioner, restart_improve = 0, stall_cycles = 10,
  * use_graph = 1, autotune = 1, batch_schedule = AUTO, spmv_block_nnz = 0, a_storage = COPY,
  * restart_repeat = 0, restart_on_stall = 0, orth_restart = 0, orth_norm = SPECTRAL, ilu_sweeps = 4,
- * arnoldi_a = DEFAULT, precond_precision = NATIVE, persistent_spmv = 0, precond_side = RIGHT. */
+ * arnoldi_a = DEFAULT, precond_precision = NATIVE, persistent_spmv = 0, precond_side = RIGHT,
+ * spmv_format = AUTO. */
 void gmres_default_options(gmres_options* opt);
 
 /* Create a solver for one n x n system (Algorithm 1, inputs A, M^-1).

@@ -169,6 +169,7 @@ bool valid_options(const gmres_options* o) {
   if (o->precond_precision != GMRES_PRECOND_NATIVE && o->precond_precision != GMRES_PRECOND_FP32) return false;
   if (o->persistent_spmv < 0 || o->persistent_spmv > PV_COUNT) return false;
   if (o->precond_side != GMRES_PRECOND_RIGHT && o->precond_side != GMRES_PRECOND_LEFT) return false;
+  if (o->spmv_format < GMRES_SPMV_AUTO || o->spmv_format > GMRES_SPMV_SELL) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
@@ -575,8 +576,9 @@ void build_graph(gmres_ctx* h) {
 // one forced by persistent_spmv, else (autotune) the fastest of CSR8, CSR4
 // and (when every system allows an ELL copy: n <= 65,536, rows of at most 255
 // entries) ELL16 on a probe of the real kernel: the largest system of each
-// size class (rows per thread), a few Arnoldi steps from b = const, x = 0,
-// one untimed and one timed launch per variant between HIP events; else CSR8.
+// size class (rows per thread), four Arnoldi steps from b = const, x = 0, one
+// untimed launch, then one timed launch per variant between HIP events; else
+// CSR8.
 // Every variant gives bitwise the same results.
 void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
   KArgs& a = h->a;
@@ -656,15 +658,16 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
     int32_t* d_probe = upload32(h, probe);
     KArgs t = a;
     t.S = (int32_t)probe.size();
-    t.max_iters = std::min<int64_t>(a.m, 8);
+    t.max_iters = std::min<int64_t>(a.m, 4);
     for (int k : probe) {  // b = a constant (a non-zero byte pattern), x = 0
       hip_check(hipMemsetAsync(a.b + h->sys[k].row0, 0x3f, (size_t)h->sys[k].n * 8, h->stream));
       hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
     }
+    // one untimed launch brings the probe systems' data on chip for every variant alike
+    hip_check(launch_batch_persistent(t, d_probe, h->counter, PV_CSR8, h->stream));
     float best = 1e30f;
     for (int v = 0; v < PV_COUNT; ++v) {
       if (v == PV_ELL16 && !all_ell) continue;
-      hip_check(launch_batch_persistent(t, d_probe, h->counter, v, h->stream));
       for (int k : probe)
         hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
       hip_check(hipEventRecord(h->ev0, h->stream));
@@ -678,43 +681,106 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
         best = ms;
         h->pv = v;
       }
-      for (int k : probe)
-        hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
     }
+    for (int k : probe) hip_check(hipMemsetAsync(a.x + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
     for (int k : probe) hip_check(hipMemsetAsync(a.b + h->sys[k].row0, 0, (size_t)h->sys[k].n * 8, h->stream));
     hip_check(launch_init_state(a, h->stream));
   }
   hip_check(hipStreamSynchronize(h->stream));
 }
 
-// Times the Arnoldi SpMV for a few row-block budgets and keeps the fastest.
-void autotune_spmv(gmres_ctx* h) {
-  float best = 1e30f;
-  int best_budget = h->a.spmv_budget, best_remap = h->a.xcd_remap;
+// Sliced ELL copy of the Arnoldi product's values, when every row has fewer
+// than 2 kRowLanePer entries (each row's canonical sum is then its plain sum
+// in storage order, which the sliced kernel keeps) and the padded copy fits
+// 32-bit offsets.  Returns false (nothing built) otherwise.
+bool build_sell(gmres_ctx* h) {
+  KArgs& a = h->a;
+  if (a.asplit || h->persistent) return false;
+  const int64_t nslice = h->ld / 64;
+  std::vector<int32_t> off(nslice + 1, 0);
+  int64_t total = 0;
+  for (int64_t sl = 0; sl < nslice; ++sl) {
+    int w = 0;
+    for (int64_t r = sl * 64; r < sl * 64 + 64; ++r) w = std::max(w, h->rp_host[r + 1] - h->rp_host[r]);
+    if (w >= 2 * kRowLanePer) return false;
+    off[sl] = (int32_t)total;
+    total += (int64_t)w * 64;
+    if (total >= (int64_t)INT32_MAX) return false;
+  }
+  off[nslice] = (int32_t)total;
+  std::vector<uint8_t> len(h->ld);
+  for (int64_t r = 0; r < h->ld; ++r) len[r] = (uint8_t)(h->rp_host[r + 1] - h->rp_host[r]);
+  a.sell_off = upload32(h, off);
+  uint8_t* d_len = h->alloc<uint8_t>((size_t)h->ld);
+  hip_check(hipMemcpyAsync(d_len, len.data(), (size_t)h->ld, hipMemcpyHostToDevice, h->stream));
+  a.sell_len = d_len;
+  int32_t* col = h->alloc<int32_t>((size_t)total + 1);
+  void* val = a.arn64 ? (void*)h->alloc<double>((size_t)total + 1) : (void*)h->alloc<float>((size_t)total + 1);
+  hip_check(launch_build_sell(a, a.arn64 ? (const void*)a.a64 : (const void*)a.a32, a.arn64 ? 0 : 1, val, col,
+                              h->stream));
+  a.sell_val = val;
+  a.sell_col = col;
+  hip_check(hipStreamSynchronize(h->stream));  // the host tables are freed on return
+  return true;
+}
+
+// Times the Arnoldi SpMV for a few row-block budgets, each with and without
+// the XCD block mapping and the non-temporal matrix loads (and the sliced ELL
+// copy when there is one), and keeps the fastest.  The row blocks stay set to the fastest budget for the
+// other products (residual, preconditioner) either way.
+void autotune_spmv(gmres_ctx* h, bool sell) {
+  float best = 1e30f, best_csr = 1e30f;
+  int best_budget = h->a.spmv_budget, best_remap = h->a.xcd_remap, best_sell = 0, best_nt = 0;
   // exercise with a column of the zero-initialised basis; force the kernel on
   hip_check(launch_set_force(h->a, 1, h->stream));
   const int reps = 3;
+  auto timeit = [&]() {
+    hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));  // warm
+    hip_check(hipEventRecord(h->ev0, h->stream));
+    for (int r = 0; r < reps; ++r) hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));
+    hip_check(hipEventRecord(h->ev1, h->stream));
+    hip_check(hipEventSynchronize(h->ev1));
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    return ms;
+  };
   for (int budget : kTuneBudgets) {
     set_row_blocks(h, budget);
+    for (int remap = 0; remap <= 1; ++remap)
+      for (int nt = 0; nt <= 1; ++nt) {
+        h->a.xcd_remap = remap;
+        h->a.spmv_nt = nt;
+        const float ms = timeit();
+        if (ms < best_csr) {
+          best_csr = ms;
+          best_budget = budget;
+          if (ms < best) {
+            best = ms;
+            best_remap = remap;
+            best_nt = nt;
+          }
+        }
+      }
+  }
+  if (sell) {
+    h->a.use_sell = 1;
+    h->a.spmv_nt = 0;
     for (int remap = 0; remap <= 1; ++remap) {
       h->a.xcd_remap = remap;
-      hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));  // warm
-      hip_check(hipEventRecord(h->ev0, h->stream));
-      for (int r = 0; r < reps; ++r) hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));
-      hip_check(hipEventRecord(h->ev1, h->stream));
-      hip_check(hipEventSynchronize(h->ev1));
-      float ms = 0.f;
-      hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+      const float ms = timeit();
       if (ms < best) {
         best = ms;
-        best_budget = budget;
         best_remap = remap;
+        best_sell = 1;
+        best_nt = 0;
       }
     }
   }
   hip_check(launch_set_force(h->a, 0, h->stream));
   set_row_blocks(h, best_budget);
   h->a.xcd_remap = best_remap;
+  h->a.use_sell = best_sell;
+  h->a.spmv_nt = best_nt;
   hip_check(hipStreamSynchronize(h->stream));
 }
 
@@ -1009,8 +1075,14 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     hip_check(hipMemcpy(h->order, ord.data(), nsys * 4, hipMemcpyHostToDevice));
     h->counter = h->alloc<int32_t>(1);
     setup_persistent_spmv(h, opt);
-  } else if (tune) {
-    autotune_spmv(h);
+  } else {
+    // the sliced ELL copy: tuned against the row blocks, or forced
+    const bool sell = opt->spmv_format != GMRES_SPMV_CSR && (tune || opt->spmv_format == GMRES_SPMV_SELL) &&
+                      build_sell(h);
+    if (tune)
+      autotune_spmv(h, sell);
+    else
+      a.use_sell = sell ? 1 : 0;
   }
   h->xs = h->alloc<double>(h->ld);
   h->ys = h->alloc<double>(h->ld);
@@ -1189,6 +1261,7 @@ void gmres_default_options(gmres_options* o) {
   o->precond_precision = GMRES_PRECOND_NATIVE;
   o->persistent_spmv = 0;
   o->precond_side = GMRES_PRECOND_RIGHT;
+  o->spmv_format = GMRES_SPMV_AUTO;
 }
 
 const char* gmres_strerror(int code) {

@@ -98,6 +98,7 @@ struct KArgs {
   int32_t ortho;    // 0 MGS, 1 CGSR
   int32_t spmv_budget;  // nnz per SpMV row block (streaming mode)
   int32_t xcd_remap;    // map consecutive blocks onto one XCD
+  int32_t spmv_nt;      // the Arnoldi product's row blocks load the matrix with the non-temporal hint
   int32_t ncu;          // compute units of the device
   int32_t vsys;         // basis layout: 0 = column stride ld over all systems,
                         // 1 = one block of (m+1) padded columns per system (persistent batch)
@@ -129,6 +130,15 @@ struct KArgs {
   void* ilu_v;         // ILU application: the scaled v_j and three work vectors (ld rows each,
   void* ilu_b[3];      //   float64 when pc64, else float32)
   int32_t ilu_sl, ilu_su;  // sweeps on L and on U
+  // sliced ELL copy of the Arnoldi product's values (64-row slices, entry k
+  // of a slice's rows contiguous), used instead of the row blocks when every
+  // row has fewer than 2 kRowLanePer entries (so its canonical sum is the
+  // plain sum in storage order) and the autotuner or the option picks it
+  int32_t use_sell;
+  const void* sell_val;     // float32 or float64 (the values the Arnoldi product reads)
+  const int32_t* sell_col;
+  const int32_t* sell_off;  // first entry of each slice [ld / 64 + 1]
+  const uint8_t* sell_len;  // row lengths
   const int32_t* rb;       // row-block first rows [nrb + 1]
   const int32_t* rb_sys;   // system of each row block
   const int32_t* rb_lanes; // lanes per row of each row block: max row_lanes over its rows
@@ -255,6 +265,8 @@ hipError_t launch_ilu_apply(const KArgs& a, void* dst, hipStream_t st);
 hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, float* dinv, double* dinv64,
                              hipStream_t st);
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
+// The sliced ELL copy of A (values from `vals`, float32 when v32 else float64)
+hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st);
 hipError_t launch_encode_plain(int prec, int64_t n, const float* w, float f, void* out,

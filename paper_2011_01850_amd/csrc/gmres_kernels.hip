@@ -436,7 +436,22 @@ enum SpmvMode { SM_ARNOLDI = 0, SM_PRECOND = 1, SM_AZ = 2, SM_RESID = 3, SM_PLAI
 // the products l, l + T, ... in turn, then a fixed butterfly), so the
 // row-block layout (which the autotuner picks) never changes a result.
 
-template <typename TA, typename TX, typename TY, int MODE>
+// 16-byte loads of the matrix arrays, with the non-temporal hint when NT
+// (the arrays are streamed once per product; the hint keeps them from
+// displacing the gathered vector's lines in the L2).
+typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+template <bool NT, typename V>
+__device__ __forceinline__ V ld16(const void* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  else
+    return *reinterpret_cast<const V*>(p);
+}
+
+template <typename TA, typename TX, typename TY, int MODE, bool NT = false>
 __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__ vals,
                                                  const TX* __restrict__ x, TY* __restrict__ y,
                                                  const double* __restrict__ bvec, int j) {
@@ -496,21 +511,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
     // four entries so a group never leaves them)
     const int q0 = p0 & ~3;
     for (int k4 = q0 + 4 * t; k4 < p1; k4 += 4 * kBlock) {
-      const int4 c4 = *reinterpret_cast<const int4*>(a.ci + k4);
+      const i32x4_t c4 = ld16<NT, i32x4_t>(a.ci + k4);
       ACC v4[4];
       if constexpr (std::is_same<TA, float>::value) {
-        const float4 f = *reinterpret_cast<const float4*>(vals + k4);
+        const f32x4_t f = ld16<NT, f32x4_t>(vals + k4);
         v4[0] = f.x; v4[1] = f.y; v4[2] = f.z; v4[3] = f.w;
       } else if constexpr (std::is_same<TA, double>::value) {
-        const double2 f0 = *reinterpret_cast<const double2*>(vals + k4);
-        const double2 f1 = *reinterpret_cast<const double2*>(vals + k4 + 2);
+        const f64x2_t f0 = ld16<NT, f64x2_t>(vals + k4);
+        const f64x2_t f1 = ld16<NT, f64x2_t>(vals + k4 + 2);
         v4[0] = f0.x; v4[1] = f0.y; v4[2] = f1.x; v4[3] = f1.y;
       } else {
-        const uint4 h = *reinterpret_cast<const uint4*>(vals + k4);
+        const u32x4_t h = ld16<NT, u32x4_t>(vals + k4);
         if constexpr (std::is_same<TA, HiW>::value) {
           v4[0] = hi_value(h.x); v4[1] = hi_value(h.y); v4[2] = hi_value(h.z); v4[3] = hi_value(h.w);
         } else {
-          const uint4 l = *reinterpret_cast<const uint4*>(a.alo + k4);
+          const u32x4_t l = ld16<NT, u32x4_t>(a.alo + k4);
           v4[0] = hilo_value(h.x, l.x); v4[1] = hilo_value(h.y, l.y);
           v4[2] = hilo_value(h.z, l.z); v4[3] = hilo_value(h.w, l.w);
         }
@@ -540,6 +555,65 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
   if (MODE == SM_RESID_PLAIN) {
     zsq = block_sum(zsq);
     if (t == 0) a.part[blk] = zsq;
+  }
+}
+
+// Sliced ELL (64 rows per slice, one row per lane, entry k of the slice's
+// rows contiguous so every load of a wave is coalesced), for matrices whose
+// rows all have fewer than 2 kRowLanePer entries: their canonical sum is the
+// plain sum of the rounded products in storage order, which this kernel
+// keeps (no fused multiply-add), so it gives the row-block kernel's bits.
+template <typename TA, typename TX, typename TY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__ vals, const TX* __restrict__ x,
+                                                 TY* __restrict__ y, int j) {
+#pragma clang fp contract(off)
+  using ACC = AccFor<TA, TY>;
+  const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  const int lane = threadIdx.x & 63;
+  const int slice = blk * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t r = (int64_t)slice * 64 + lane;
+  const int s = a.tile_sys[blk];  // a block covers one 256-row tile
+  if (!gated(a, s)) return;
+  ACC scale = (ACC)1;
+  if (MODE == SM_ARNOLDI) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
+  const int off = a.sell_off[slice];
+  const int w = (a.sell_off[slice + 1] - off) >> 6;
+  const int len = a.sell_len[r];
+  ACC acc = (ACC)0;
+  for (int kb = 0; kb < w; kb += 8) {
+    ACC av[8];
+    int cv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int p = off + (kb + e) * 64 + lane;
+      av[e] = kb + e < w ? (ACC)vals[p] : (ACC)0;
+      cv[e] = kb + e < w ? a.sell_col[p] : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (kb + e < len) {
+        const ACC prod = av[e] * (ACC)ldv(x[cv[e]]);
+        acc = acc + prod;
+      }
+    }
+  }
+  y[r] = (TY)(acc * scale);
+}
+
+__global__ void k_build_sell(KArgs a, const void* __restrict__ vals, int v32, void* __restrict__ sv,
+                             int32_t* __restrict__ sc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.ld) return;
+  const int slice = (int)(r >> 6), lane = (int)(r & 63);
+  const int off = a.sell_off[slice], w = (a.sell_off[slice + 1] - off) >> 6;
+  const int p0 = a.rp[r], len = a.rp[r + 1] - p0;
+  for (int k = 0; k < w; ++k) {
+    const int p = off + k * 64 + lane;
+    if (v32)
+      static_cast<float*>(sv)[p] = k < len ? static_cast<const float*>(vals)[p0 + k] : 0.0f;
+    else
+      static_cast<double*>(sv)[p] = k < len ? static_cast<const double*>(vals)[p0 + k] : 0.0;
+    sc[p] = k < len ? a.ci[p0 + k] : (int32_t)r;
   }
 }
 
@@ -1511,7 +1585,7 @@ __global__ __launch_bounds__(64) void k_backsolve(KArgs a) {
     for (int l = lane; l < i; l += 64) ys[l] -= Hs[(int64_t)i * M1 + l] * yi;
     __syncthreads();
   }
-  const bool useZ = a.precond != 0;
+  const bool useZ = a.precond != 0 && !a.left;  // left preconditioning updates with V
   for (int i = lane; i < kk; i += 64)
     a.y[(int64_t)s * m + i] = useZ ? ys[i] : ys[i] * a.sc[(int64_t)s * M1 + i];
   if (lane == 0) {
@@ -1778,21 +1852,41 @@ static hipError_t launch_fin_cols(const KArgs& a, const SegTab& sg, int j, hipSt
 // row block in the kernel's accumulation type.
 template <typename TX, typename TY, int MODE>
 static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStream_t st) {
+  if constexpr (MODE == SM_ARNOLDI || MODE == SM_AZ) {
+    if (a.use_sell) {
+      const unsigned grid = (unsigned)(a.ld / kBlock);  // one block per 256-row tile (4 slices)
+      if (a.arn64)
+        hipLaunchKernelGGL((k_sell<double, TX, TY, MODE>), dim3(grid), dim3(kBlock), 0, st, a,
+                           static_cast<const double*>(a.sell_val), x, y, j);
+      else
+        hipLaunchKernelGGL((k_sell<float, TX, TY, MODE>), dim3(grid), dim3(kBlock), 0, st, a,
+                           static_cast<const float*>(a.sell_val), x, y, j);
+      return hipGetLastError();
+    }
+  }
   auto go = [&](auto kern, const auto* vals, size_t acc_bytes) {
     hipLaunchKernelGGL(kern, dim3(a.nrb), dim3(kBlock), (size_t)a.spmv_budget * acc_bytes, st, a, vals, x, y,
                        nullptr, j);
   };
-  if (a.arn64) {
-    if (a.asplit)
-      go(k_spmv<HiLoW, TX, TY, MODE>, reinterpret_cast<const HiLoW*>(a.ahi), sizeof(AccFor<HiLoW, TY>));
-    else
-      go(k_spmv<double, TX, TY, MODE>, a.a64, sizeof(AccFor<double, TY>));
-  } else {
-    if (a.asplit)
-      go(k_spmv<HiW, TX, TY, MODE>, reinterpret_cast<const HiW*>(a.ahi), sizeof(AccFor<HiW, TY>));
-    else
-      go(k_spmv<float, TX, TY, MODE>, a.a32, sizeof(AccFor<float, TY>));
-  }
+  auto by_values = [&](auto nt) {
+    constexpr bool NT = decltype(nt)::value;
+    if (a.arn64) {
+      if (a.asplit)
+        go(k_spmv<HiLoW, TX, TY, MODE, NT>, reinterpret_cast<const HiLoW*>(a.ahi), sizeof(AccFor<HiLoW, TY>));
+      else
+        go(k_spmv<double, TX, TY, MODE, NT>, a.a64, sizeof(AccFor<double, TY>));
+    } else {
+      if (a.asplit)
+        go(k_spmv<HiW, TX, TY, MODE, NT>, reinterpret_cast<const HiW*>(a.ahi), sizeof(AccFor<HiW, TY>));
+      else
+        go(k_spmv<float, TX, TY, MODE, NT>, a.a32, sizeof(AccFor<float, TY>));
+    }
+  };
+  // the non-temporal matrix loads are a tuning choice of the Arnoldi product only
+  if ((MODE == SM_ARNOLDI || MODE == SM_AZ) && a.spmv_nt)
+    by_values(std::true_type{});
+  else
+    by_values(std::false_type{});
   return hipGetLastError();
 }
 
@@ -2192,8 +2286,8 @@ hipError_t launch_config(const KArgs& a, int family, int j, int32_t* grid, int32
     using TW = decltype(tw);
     const int L = j + 1 <= 64 ? lanes_for(j + 1) : 64;
     switch (family) {
-      case 0:  // Arnoldi SpMV: one workgroup per row block
-        G = a.nrb;
+      case 0:  // Arnoldi SpMV: one workgroup per row block (per 256-row tile with the sliced ELL copy)
+        G = a.use_sell ? (int)(a.ld / kBlock) : a.nrb;
         return hipSuccess;
       case 1:
         k = L == 8 ? (const void*)k_mdot<TV, TW, 8> : L == 16 ? (const void*)k_mdot<TV, TW, 16>
@@ -2393,6 +2487,11 @@ hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, h
       hipLaunchKernelGGL((k_spmv<float, float, float, SM_PLAIN>), dim3(a.nrb), dim3(kBlock), sh4, st, a,
                          a.a32, (const float*)x, (float*)y, nullptr, 0);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_build_sell, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, vals, v32, sv, sc);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
              autotune, schedule="auto", spmv_block_nnz=0, a_storage="copy", restart_repeat=False,
              restart_on_stall=False, orth_restart=0.0, orth_norm="spectral", ilu_sweeps=4,
              arnoldi_a="default", precond_precision="native", persistent_spmv="tuned",
-             precond_side="right") -> L.Options:
+             precond_side="right", spmv_format="auto") -> L.Options:
     o = L.default_options()
     o.m = int(m)
     o.tol = float(tol)
@@ -61,6 +61,7 @@ def _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stal
     o.persistent_spmv = (L.PERSISTENT_SPMVS[persistent_spmv] if isinstance(persistent_spmv, str)
                          else int(persistent_spmv))
     o.precond_side = L.PRECOND_SIDES[precond_side] if isinstance(precond_side, str) else int(precond_side)
+    o.spmv_format = L.SPMV_FORMATS[spmv_format] if isinstance(spmv_format, str) else int(spmv_format)
     return o
 
 
@@ -72,7 +73,7 @@ class Solver:
                  use_graph=True, autotune=True, schedule="auto", spmv_block_nnz=0,
                  a_storage="copy", restart_repeat=False, restart_on_stall=False, orth_restart=0.0,
                  orth_norm="spectral", ilu_sweeps=4, arnoldi_a="default", precond_precision="native",
-                 precond_side="right"):
+                 precond_side="right", spmv_format="auto"):
         torch = _torch()
         self._torch = torch
         self.lib = L.load()
@@ -85,7 +86,7 @@ class Solver:
         self.opt = _options(m, tol, max_iters, ortho, precision, precond, restart_improve, stall_cycles,
                             use_graph, autotune, schedule, spmv_block_nnz, a_storage, restart_repeat,
                             restart_on_stall, orth_restart, orth_norm, ilu_sweeps, arnoldi_a, precond_precision,
-                            precond_side=precond_side)
+                            precond_side=precond_side, spmv_format=spmv_format)
         self.precision = precision
         h = C.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream

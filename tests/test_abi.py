@@ -65,7 +65,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                        ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
                        ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097),
                        ("arnoldi_a", 3), ("arnoldi_a", -1), ("persistent_spmv", -1), ("persistent_spmv", 4), ("precond_side", 2),
-                       ("precond_side", -1)]:
+                       ("precond_side", -1), ("spmv_format", 3), ("spmv_format", -1)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field
@@ -136,7 +136,7 @@ def test_handle_checks(lib):
 
 def test_struct_layouts_match_header():
     # offsets that C gives the two structs on x86-64
-    assert C.sizeof(L.Options) == 112
+    assert C.sizeof(L.Options) == 120
     assert L.Options.tol.offset == 8 and L.Options.max_iters.offset == 16
     assert L.Options.restart_improve.offset == 40 and L.Options.autotune.offset == 56
     assert L.Options.batch_schedule.offset == 60 and L.Options.spmv_block_nnz.offset == 64
@@ -145,6 +145,7 @@ def test_struct_layouts_match_header():
     assert L.Options.orth_norm.offset == 88 and L.Options.ilu_sweeps.offset == 92
     assert L.Options.arnoldi_a.offset == 96 and L.Options.precond_precision.offset == 100
     assert L.Options.persistent_spmv.offset == 104 and L.Options.precond_side.offset == 108
+    assert L.Options.spmv_format.offset == 112
     assert C.sizeof(L.Result) == 48
     assert L.Result.iters.offset == 8 and L.Result.first_stall.offset == 44
 
@@ -215,11 +216,11 @@ def test_binding_forwards_every_solver_option(lib):
                 continue
             assert name in params, (cls.__name__, name)
     o = S._options(30, 1e-9, 500, "mgs", "fp64", "ilu0", 1e-6, 7, False, False, "persistent", 1024, "split",
-                   True, True, 0.5, "frobenius", 0, "fp32", "fp32", "ell16", "left")
+                   True, True, 0.5, "frobenius", 0, "fp32", "fp32", "ell16", "left", "sell")
     assert (o.m, o.max_iters, o.ortho, o.precision, o.precond) == (30, 500, L.MGS, L.FP64, L.PRECOND_ILU0)
     assert (o.stall_cycles, o.use_graph, o.autotune, o.batch_schedule) == (7, 0, 0, L.SCHEDULE_PERSISTENT)
     assert (o.spmv_block_nnz, o.a_storage, o.restart_repeat, o.restart_on_stall) == (1024, L.A_SPLIT, 1, 1)
     assert (o.orth_norm, o.ilu_sweeps, o.arnoldi_a) == (L.ORTH_FROBENIUS, 0, L.ARNOLDI_A_FP32)
     assert (o.precond_precision, o.persistent_spmv) == (L.PRECOND_FP32, 1 + L.PSPMV_ELL16)
-    assert o.precond_side == L.PRECOND_LEFT
+    assert o.precond_side == L.PRECOND_LEFT and o.spmv_format == L.SPMV_SELL
     assert o.tol == 1e-9 and o.restart_improve == 1e-6 and o.orth_restart == 0.5

@@ -67,7 +67,8 @@ def test_roofline_picks_the_dominant_kernel():
            "pass1": _fam_entry(30.0, 650, 600, 600 * 2.7e8, cols=range(32, 50)),
            "reduce": {"ms_per_solve": 40.0, "launches": 2000, "ms_active": 39.0, "active_launches": 1800,
                       "alg_bytes": 0.0, "by_col": []}}
-    rf = bench.roofline_from_profile(FakeSolver(), fam, 50, 3)
+    harness = bench.harness_times(FakeSolver(), 50, 3, families=("spmv", "pass1"))
+    rf = bench.roofline_from_profile(FakeSolver(), fam, 50, 3, harness=harness)
     # the latency-bound reductions take longest but move no algorithmic bytes
     assert rf["family"] == "pass1" and rf["kernel"] == "k_mdot<float, float, 64>"
     per = 600 // 18 * 18  # launches the fake table spreads over columns 32..49

@@ -982,3 +982,38 @@ def test_left_preconditioning_with_identity_follows_plain_gmres():
         assert i1["status"] == i0["status"] == "CONVERGED" and not i1["fallback_used"]
         assert abs(i1["iters"] - i0["iters"]) <= 2
         assert np.linalg.norm((x1 - x0).cpu().numpy()) <= 1e-9 * np.linalg.norm(x0.cpu().numpy())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "limited"])
+@pytest.mark.parametrize("ortho", ["mgs", "cgsr"])
+def test_sliced_ell_gives_the_row_block_bits(precision, ortho):
+    # rows shorter than 8 entries are summed in storage order by both layouts
+    # of the Arnoldi product: the same solve bit for bit (plain and FGMRES)
+    for name, A, pc in [("3d17", P.convdiff(17, (50.0, 20.0, 10.0)), "none"),
+                        ("varcoef12", P.varcoef3d(12, family=94, index=4), "jacobi")]:
+        xt, b = P.manufactured_rhs(A, 95, 0)
+        out = {}
+        for fmt in ("csr", "sell"):
+            s = _solver(A, m=20, ortho=ortho, precision=precision, precond=pc, tol=1e-12, spmv_format=fmt,
+                        autotune=False)
+            x, info = s.solve(b)
+            cfg = s.launch_config("spmv", 0)
+            s.close()
+            out[fmt] = (x.cpu().numpy(), info["iters"], cfg["grid"])
+        assert out["sell"][2] == -(-A.n // 256)  # one workgroup per 256-row tile
+        assert out["sell"][1] == out["csr"][1], name
+        assert np.array_equal(out["sell"][0], out["csr"][0]), name
+
+
+def test_sliced_ell_is_refused_for_long_rows():
+    # a row of 8 or more entries: the option falls back to the row blocks
+    A = P.powerlaw(3000, family=93)
+    xt, b = P.manufactured_rhs(A, 95, 1)
+    s1 = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format="sell", autotune=False)
+    s2 = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format="csr", autotune=False)
+    assert s1.launch_config("spmv", 0)["grid"] == s2.launch_config("spmv", 0)["grid"]
+    x1, i1 = s1.solve(b)
+    x2, i2 = s2.solve(b)
+    s1.close()
+    s2.close()
+    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)

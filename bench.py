@@ -161,9 +161,25 @@ def tile_width(j):
     return L
 
 
-def kernel_units(fam, m, precision, ortho):
+def spmv_kernel(precision, spmv=None):
+    """The Arnoldi SpMV's template instantiation for the handle's SpMV choice
+    (Solver.spmv_config(): the sliced ELL kernel or the CSR row blocks, with or
+    without non-temporal matrix loads); the matrix values are float64 only in
+    the float64 solver."""
+    if not spmv:
+        return FAMILY_KERNELS["spmv"]
+    ta = "double" if precision == "fp64" else "float"
+    ty = TYPES.get(precision, "?")
+    if spmv["format"] == "sell":
+        return f"k_sell<{ta}, {ty}, 0>"
+    return f"k_spmv<{ta}, {ty}, 0, {'true' if spmv['nontemporal'] else 'false'}>"
+
+
+def kernel_units(fam, m, precision, ortho, spmv=None):
     """The kernels (template instantiations) of one family: (name, columns)."""
     ty = TYPES.get(precision, "?")
+    if fam == "spmv":
+        return [(spmv_kernel(precision, spmv), list(range(m)))]
     if fam in ("pass1", "pass2") or (fam == "final" and ortho == "cgsr"):
         base = {"pass1": "k_mdot", "pass2": "k_axpy_mdot64" if precision in ("fp64", "limited") else "k_axpy_mdot",
                 "final": "k_final_tile"}[fam]
@@ -220,11 +236,15 @@ def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", 
     its summed in-solve launch time (launches that did work).  Beside it: every
     instantiation and family, the back-to-back harness time of the same kernel
     at the last column, and its launch configuration."""
+    try:
+        spmv = solver.spmv_config()
+    except Exception:  # noqa: BLE001 - a handle without the query (older library, test double)
+        spmv = None
     units = []
     for f in families:
         if f not in fam or fam[f]["alg_bytes"] <= 0:
             continue
-        for name, cols in kernel_units(f, m, precision, ortho):
+        for name, cols in kernel_units(f, m, precision, ortho, spmv):
             rows = [fam[f]["by_col"][j] for j in cols]
             ms_act = sum(r["ms_active"] for r in rows)
             act = sum(r["active"] for r in rows)
@@ -269,6 +289,7 @@ def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", 
         "avg_launch_ms_all_launches": round(dom["ms_all"] / dom["launches"], 5),
         "harness_back_to_back": ({k: v for k, v in h.items() if k != "launch_config"} if h else None),
         "launch_config_at_j_last": cfg,
+        "spmv_config": spmv,
         "in_solve_kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in u.items()} for u in units],
         "in_solve_families": fams,
     }

@@ -475,6 +475,16 @@ int gmres_batch_tuning(gmres_handle h, int32_t* variant, double* probe_us, gmres
 int gmres_launch_config(gmres_handle h, int32_t family, int32_t j, int32_t* grid, int32_t* block,
                         int32_t* per_cu, int64_t* basis_align);
 
+/* The Arnoldi SpMV the handle runs, as the autotuner (or the options) left
+ * it, for the measurement report: *format = GMRES_SPMV_CSR or
+ * GMRES_SPMV_SELL; *block_nnz = the nonzeros per CSR row block (also used by
+ * the residual and preconditioner products); *xcd_remap = 1 when consecutive
+ * workgroups are mapped onto one XCD; *nontemporal = 1 when the matrix
+ * streams are loaded non-temporally.  Any output may be NULL.  ESTATE on the
+ * persistent batch schedule. */
+int gmres_spmv_config(gmres_handle h, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap,
+                      int32_t* nontemporal);
+
 #ifdef __cplusplus
 }
 #endif

@@ -140,6 +140,7 @@ struct KArgs {
   const int32_t* sell_off;  // first entry of each slice [ld / 64 + 1]
   const uint8_t* sell_len;  // row lengths
   const int32_t* rb;       // row-block first rows [nrb + 1]
+  const int32_t* rb_p;     // row pointer at each row-block start [nrb + 1]
   const int32_t* rb_sys;   // system of each row block
   const int32_t* rb_lanes; // lanes per row of each row block: max row_lanes over its rows
   const int32_t* sys_rb0;  // first row block of each system

@@ -220,6 +220,19 @@ __device__ __forceinline__ bool gated(const KArgs& a, int s) {
   return S.active != 0 || S.force != 0;
 }
 
+// The gate of system 0, read at a kernel's start from an address that needs
+// no other load (the single-system case).
+__device__ __forceinline__ int gate0(const KArgs& a) { return a.st[0].active | a.st[0].force; }
+
+// The gate test of a kernel whose first loads do not depend on it: `on0` is
+// gate0(), and `issued` (any non-negative value loaded beside it) ties those
+// loads to the test, so they are in flight together rather than each
+// waiting for the gate.
+__device__ __forceinline__ bool gated_now(const KArgs& a, int s, int on0, int issued) {
+  const bool on = a.S == 1 ? on0 != 0 : gated(a, s);
+  return on & (issued >= 0);
+}
+
 __device__ __forceinline__ double unit_roundoff(int prec) {
   return prec == P64 ? 0x1p-53 : 0x1p-24;
 }
@@ -459,18 +472,21 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
   extern __shared__ __align__(16) unsigned char smem_raw[];
   ACC* prod = reinterpret_cast<ACC*>(smem_raw);
   const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  const int s = a.rb_sys[blk];
+  const int t = threadIdx.x;
+  // the block's rows and non-zero range come from tables of their own, so
+  // they load together with the system's gate rather than after it
+  const int on0 = gate0(a);
+  const int s = a.S == 1 ? 0 : a.rb_sys[blk];
+  const int r0 = a.rb[blk], r1 = a.rb[blk + 1];
+  const int p0 = a.rb_p[blk], p1 = a.rb_p[blk + 1];
   if (MODE == SM_ARNOLDI || MODE == SM_PRECOND || MODE == SM_AZ) {
-    if (!gated(a, s)) return;
+    if (!gated_now(a, s, on0, p0 | r0)) return;
   } else if (MODE == SM_LEFT) {  // the learned M applied to w (left preconditioning), unscaled
     if (!gated(a, s) || (!a.st[s].precond_on && !a.st[s].force)) return;
   } else if (MODE == SM_RESID) {
     const SysState& S = a.st[s];
     if (S.status != RUNNING && !S.force) return;
   }
-  const int t = threadIdx.x;
-  const int r0 = a.rb[blk], r1 = a.rb[blk + 1];
-  const int p0 = a.rp[r0], p1 = a.rp[r1];
   ACC scale = (ACC)1;
   if (MODE == SM_ARNOLDI || MODE == SM_PRECOND) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
   if (MODE == SM_PRECOND && !a.st[s].precond_on) {
@@ -508,43 +524,73 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
   } else {
     // products staged in LDS; indices and values are read as aligned groups
     // of four (16-byte index loads; the matrix arrays carry a zero pad of
-    // four entries so a group never leaves them)
+    // four entries so a group never leaves them), two groups a thread in
+    // flight at once
+    const int tpr = a.rb_lanes[blk];
+    const int g = t / tpr, l = t % tpr, ng = kBlock / tpr;
+    // the first row of this lane group: its range loads beside the matrix
+    int rb_ = 0, re_ = 0;
+    if (r0 + g < r1) {
+      rb_ = a.rp[r0 + g];
+      re_ = a.rp[r0 + g + 1];
+    }
     const int q0 = p0 & ~3;
-    for (int k4 = q0 + 4 * t; k4 < p1; k4 += 4 * kBlock) {
-      const i32x4_t c4 = ld16<NT, i32x4_t>(a.ci + k4);
-      ACC v4[4];
-      if constexpr (std::is_same<TA, float>::value) {
-        const f32x4_t f = ld16<NT, f32x4_t>(vals + k4);
-        v4[0] = f.x; v4[1] = f.y; v4[2] = f.z; v4[3] = f.w;
-      } else if constexpr (std::is_same<TA, double>::value) {
-        const f64x2_t f0 = ld16<NT, f64x2_t>(vals + k4);
-        const f64x2_t f1 = ld16<NT, f64x2_t>(vals + k4 + 2);
-        v4[0] = f0.x; v4[1] = f0.y; v4[2] = f1.x; v4[3] = f1.y;
-      } else {
-        const u32x4_t h = ld16<NT, u32x4_t>(vals + k4);
-        if constexpr (std::is_same<TA, HiW>::value) {
-          v4[0] = hi_value(h.x); v4[1] = hi_value(h.y); v4[2] = hi_value(h.z); v4[3] = hi_value(h.w);
+    constexpr int kU = 2;
+    for (int base = q0 + 4 * t; base < p1; base += 4 * kBlock * kU) {
+      i32x4_t c4[kU];
+      ACC v4[kU][4];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int k4 = base + u * 4 * kBlock;
+        if (k4 >= p1) {
+          c4[u] = i32x4_t{0, 0, 0, 0};
+          v4[u][0] = v4[u][1] = v4[u][2] = v4[u][3] = (ACC)0;
+          continue;
+        }
+        c4[u] = ld16<NT, i32x4_t>(a.ci + k4);
+        if constexpr (std::is_same<TA, float>::value) {
+          const f32x4_t f = ld16<NT, f32x4_t>(vals + k4);
+          v4[u][0] = f.x; v4[u][1] = f.y; v4[u][2] = f.z; v4[u][3] = f.w;
+        } else if constexpr (std::is_same<TA, double>::value) {
+          const f64x2_t f0 = ld16<NT, f64x2_t>(vals + k4);
+          const f64x2_t f1 = ld16<NT, f64x2_t>(vals + k4 + 2);
+          v4[u][0] = f0.x; v4[u][1] = f0.y; v4[u][2] = f1.x; v4[u][3] = f1.y;
         } else {
-          const u32x4_t l = ld16<NT, u32x4_t>(a.alo + k4);
-          v4[0] = hilo_value(h.x, l.x); v4[1] = hilo_value(h.y, l.y);
-          v4[2] = hilo_value(h.z, l.z); v4[3] = hilo_value(h.w, l.w);
+          const u32x4_t h = ld16<NT, u32x4_t>(vals + k4);
+          if constexpr (std::is_same<TA, HiW>::value) {
+            v4[u][0] = hi_value(h.x); v4[u][1] = hi_value(h.y); v4[u][2] = hi_value(h.z); v4[u][3] = hi_value(h.w);
+          } else {
+            const u32x4_t lo = ld16<NT, u32x4_t>(a.alo + k4);
+            v4[u][0] = hilo_value(h.x, lo.x); v4[u][1] = hilo_value(h.y, lo.y);
+            v4[u][2] = hilo_value(h.z, lo.z); v4[u][3] = hilo_value(h.w, lo.w);
+          }
         }
       }
-      const int cc[4] = {c4.x, c4.y, c4.z, c4.w};
+      // every gather first (the entries outside the block's range, and the
+      // zero pad, hold valid column indices), so they are in flight together
+      ACC xv[kU][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int k = k4 + e;
-        if (k >= p0 && k < p1) prod[k - p0] = v4[e] * (ACC)ldv(x[cc[e]]);
+      for (int u = 0; u < kU; ++u) {
+        xv[u][0] = (ACC)ldv(x[c4[u].x]);
+        xv[u][1] = (ACC)ldv(x[c4[u].y]);
+        xv[u][2] = (ACC)ldv(x[c4[u].z]);
+        xv[u][3] = (ACC)ldv(x[c4[u].w]);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int k = base + u * 4 * kBlock + e;
+          if (k >= p0 && k < p1) prod[k - p0] = v4[u][e] * xv[u][e];
+        }
       }
     }
     __syncthreads();
     // groups of tpr lanes, tpr = the widest canonical row of the block; lanes
     // past a row's own T hold zero, which the first butterfly steps add
-    const int tpr = a.rb_lanes[blk];
-    const int g = t / tpr, l = t % tpr, ng = kBlock / tpr;
     for (int r = r0 + g; r < r1; r += ng) {
       ACC acc = (ACC)0;
-      const int b = a.rp[r], e = a.rp[r + 1];
+      const int b = r == r0 + g ? rb_ : a.rp[r], e = r == r0 + g ? re_ : a.rp[r + 1];
       const int T = row_lanes(e - b);
       if (l < T)
         for (int k = b + l; k < e; k += T) acc += prod[k - p0];
@@ -572,13 +618,17 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
   const int lane = threadIdx.x & 63;
   const int slice = blk * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t r = (int64_t)slice * 64 + lane;
-  const int s = a.tile_sys[blk];  // a block covers one 256-row tile
-  if (!gated(a, s)) return;
-  ACC scale = (ACC)1;
-  if (MODE == SM_ARNOLDI) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
+  // the slice's extent, the row's length, the system's gate and the column
+  // scale are independent loads: issue them together, before the gate test
+  // (a block covers one 256-row tile of one system)
+  const int on0 = gate0(a);
+  const int s = a.S == 1 ? 0 : a.tile_sys[blk];
   const int off = a.sell_off[slice];
   const int w = (a.sell_off[slice + 1] - off) >> 6;
   const int len = a.sell_len[r];
+  ACC scale = (ACC)1;
+  if (MODE == SM_ARNOLDI) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
+  if (!gated_now(a, s, on0, off)) return;
   ACC acc = (ACC)0;
   for (int kb = 0; kb < w; kb += 8) {
     ACC av[8];
@@ -589,10 +639,14 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
       av[e] = kb + e < w ? (ACC)vals[p] : (ACC)0;
       cv[e] = kb + e < w ? a.sell_col[p] : 0;
     }
+    // the gathers go out together (a pad entry's column is its own row)
+    ACC xv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xv[e] = (ACC)ldv(x[cv[e]]);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       if (kb + e < len) {
-        const ACC prod = av[e] * (ACC)ldv(x[cv[e]]);
+        const ACC prod = av[e] * xv[e];
         acc = acc + prod;
       }
     }

@@ -273,6 +273,14 @@ class Solver:
                 "gmres_launch_config")
         return {"grid": g.value, "block": b.value, "per_cu": o.value, "basis_align": al.value}
 
+    def spmv_config(self):
+        """The Arnoldi SpMV the handle runs: dict(format, block_nnz, xcd_remap, nontemporal)."""
+        f, bn, xr, nt = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self.lib.gmres_spmv_config(self.h, C.byref(f), C.byref(bn), C.byref(xr), C.byref(nt)),
+                "gmres_spmv_config")
+        fmt = {v: k for k, v in L.SPMV_FORMATS.items()}[f.value]
+        return {"format": fmt, "block_nnz": bn.value, "xcd_remap": bool(xr.value), "nontemporal": bool(nt.value)}
+
     def time_kernel(self, kernel, j, reps=20):
         """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""
         ms = C.c_double()

@@ -194,7 +194,8 @@ bool valid_options(const gmres_options* o) {
 // pointers and column indices are int32 (padded rows and non-zeros, with the
 // 4-entry pad and a workgroup's worth of index slack, stay below 2^31), and
 // the basis is read through buffer resources whose byte ranges and offsets
-// are 32-bit, so (m + 1) padded columns of the basis must stay below 4 GiB.
+// are 32-bit, so (m + 1) padded columns of the basis, and the 4 columns of
+// the half of the smallest register tile, must stay below 4 GiB.
 int64_t basis_elem_bytes(int precision) {
   return precision == GMRES_FP64 ? 8 : (precision == GMRES_MIXED_BF16 || precision == GMRES_MIXED_FP16) ? 2 : 4;
 }
@@ -207,7 +208,7 @@ bool sizes_ok(int32_t nsys, const int64_t* n, const int64_t* nnz, const gmres_op
     nz += nnz[k];
     if (ld >= (int64_t)INT32_MAX || nz > (int64_t)INT32_MAX - 4 * kBlock - 4) return false;
   }
-  return (int64_t)(o->m + 1) * ld * basis_elem_bytes(o->precision) < ((int64_t)1 << 32);
+  return (int64_t)std::max(o->m + 1, 4) * ld * basis_elem_bytes(o->precision) < ((int64_t)1 << 32);
 }
 
 // Conditions of the persistent schedule (one workgroup of 1024 threads per

@@ -752,25 +752,40 @@ __device__ __forceinline__ int nt_tiles(int nt, uint64_t pass_bytes) {
   return nt - (int)(((uint64_t)nt * kMallKeep + pass_bytes - 1) / pass_bytes);
 }
 
-// One tile of basis loads: column q at byte offset voff + q * cs (columns
-// past ncol repeat the last offset step, reading zero past the resource).
-template <typename TV, int L, bool kNT, typename ACC>
-__device__ __forceinline__ void load_tile(ACC (&v)[L], __amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t cs,
-                                          int ncol) {
-  uint32_t so = 0;
-#pragma unroll
-  for (int q = 0; q < L; ++q) {
-    v[q] = (ACC)ldv(kNT ? bload_nt<TV>(rs, voff + so) : bload<TV>(rs, voff + so, 0));
-    if (q < ncol) so += cs;
-  }
+// A register tile of L basis columns [col0, col0 + L) is read through two
+// resources, one per half: half h starts at column col0 + h L/2 and is
+// bounded to the columns below col0 + ncol, so columns past ncol read zero
+// with no per-column guard, and column q's offset within its half is the
+// plain (q mod L/2) * cs (below L/2 columns, which the create-time size
+// check keeps inside 32 bits).
+struct TileRsrc {
+  __amdgpu_buffer_rsrc_t half[2];
+};
+template <typename TV, int L>
+__device__ __forceinline__ TileRsrc tile_rsrc(const KArgs& a, int col0, int ncol) {
+  constexpr int H = L / 2;
+  const int64_t cb = a.ld * (int64_t)sizeof(TV);
+  const TV* base = reinterpret_cast<const TV*>(a.V) + (int64_t)col0 * a.ld;
+  TileRsrc t;
+  t.half[0] = make_rsrc(base, (uint32_t)((int64_t)min(ncol, H) * cb));
+  t.half[1] = make_rsrc(base + (int64_t)H * a.ld, (uint32_t)((int64_t)max(ncol - H, 0) * cb));
+  return t;
 }
 
-// Resource over basis columns [0, ncols): a tile load of a column >= ncols
-// is pointed at column ncols, which lies past the range and reads zero, so
-// tiles of L >= ncols columns need no per-column guards.
-template <typename TV>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t basis_rsrc(const KArgs& a, int ncols) {
-  return make_rsrc(a.V, (uint32_t)((int64_t)ncols * a.ld * (int64_t)sizeof(TV)));
+// One tile of basis loads: column q at byte offset voff + (q mod L/2) * cs
+// of its half's resource.
+template <typename TV, int L, bool kNT, typename ACC>
+__device__ __forceinline__ void load_tile(ACC (&v)[L], const TileRsrc& rs, uint32_t voff, uint32_t cs) {
+  constexpr int H = L / 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint32_t so = 0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      v[h * H + q] = (ACC)ldv(kNT ? bload_nt<TV>(rs.half[h], voff + so) : bload<TV>(rs.half[h], voff + so, 0));
+      so += cs;
+    }
+  }
 }
 
 
@@ -785,8 +800,10 @@ __device__ __forceinline__ int pass_block(const KArgs& a, const SegTab& sg, int 
   return rev ? sg.G - 1 - b : b;
 }
 
-__device__ __forceinline__ int64_t tile_row(const SegTab& sg, int k, int u, int rev) {
-  const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+// Row of tile u of a segment (first tile t0, nt tiles) for this thread; the
+// passes read t0 and nt once before their tile loop (a loop that re-read
+// them would wait for that load before every tile's addresses).
+__device__ __forceinline__ int64_t seg_row(int t0, int nt, int u, int rev) {
   const int tile = rev ? t0 + nt - 1 - u : t0 + u;
   return (int64_t)tile * kTile + threadIdx.x;
 }
@@ -828,29 +845,28 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
   const int ncol = min(L, j + 1 - col0);
   const TW* w = reinterpret_cast<const TW*>(a.w);
   const TV* wv = reinterpret_cast<const TV*>(a.V) + (int64_t)(j + 1) * a.ld;
-  const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, col0 + ncol);
+  const TileRsrc rs = tile_rsrc<TV, L>(a, col0, ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
-  const uint32_t c0off = (uint32_t)col0 * cstride;
   uint32_t cs = cstride;
   for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
     if (!gated(a, sg.seg_sys[k])) continue;
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0, ww = (ACC)0;
 #pragma unroll 1
     for (int u = 0; u < nt; ++u) {
       // column offsets are rebuilt per tile (a scalar add each) instead of
-      // being hoisted into L live scalar registers
+      // being hoisted into L/2 live scalar registers
       asm volatile("" : "+s"(cs));
-      const int64_t r = tile_row(sg, k, u, rev);
-      const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV)) + c0off;
+      const int64_t r = seg_row(t0, nt, u, rev);
+      const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
       const ACC wr = mode == 3 ? (ACC)ldv(wv[r]) : (ACC)w[r];
       ww += wr * wr;
       ACC p[L];
       if (sizeof(TV) != 2 && u < nfirst)
-        load_tile<TV, L, true>(p, rs, voff, cs, ncol);
+        load_tile<TV, L, true>(p, rs, voff, cs);
       else
-        load_tile<TV, L, false>(p, rs, voff, cs, ncol);
+        load_tile<TV, L, false>(p, rs, voff, cs);
 #pragma unroll
       for (int q = 0; q < L; ++q) p[q] *= wr;
       colsum += reduce_scatter<L>(p, lane);
@@ -872,7 +888,7 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
   const int t = threadIdx.x, lane = t & 63;
   const int ncol = j + 1;
   TW* w = reinterpret_cast<TW*>(a.w);
-  const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, ncol);
+  const TileRsrc rs = tile_rsrc<TV, L>(a, 0, ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
   uint32_t cs = cstride;
   __shared__ ACC cf[L];
@@ -882,19 +898,19 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
     __syncthreads();
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0;
 #pragma unroll 1
     for (int u = 0; u < nt; ++u) {
       asm volatile("" : "+s"(cs));
-      const int64_t r = tile_row(sg, k, u, rev);
+      const int64_t r = seg_row(t0, nt, u, rev);
       const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
       ACC v[L];
       if (sizeof(TV) != 2 && u < nfirst)
-        load_tile<TV, L, true>(v, rs, voff, cs, ncol);
+        load_tile<TV, L, true>(v, rs, voff, cs);
       else
-        load_tile<TV, L, false>(v, rs, voff, cs, ncol);
+        load_tile<TV, L, false>(v, rs, voff, cs);
       ACC wr = (ACC)w[r];
 #pragma unroll
       for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
@@ -933,9 +949,9 @@ __global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, SegTab sg, int j, int 
     const int s = sg.seg_sys[k];
     if (!gated(a, s)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2) + col0;
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     for (int u = 0; u < nt; ++u) {
-      const int64_t r = tile_row(sg, k, u, 0);
+      const int64_t r = seg_row(t0, nt, u, 0);
       ACC wr = (ACC)w[r];
       for (int q = 0; q < ncol; ++q) wr -= (ACC)coefd[q] * (ACC)ldv(V0[(int64_t)q * a.ld + r]);
       w[r] = (TW)wr;
@@ -966,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
   const int t = threadIdx.x;
   const int ncol = j + 1;
   TW* w = reinterpret_cast<TW*>(a.w);
-  const __amdgpu_buffer_rsrc_t rs = basis_rsrc<TV>(a, ncol);
+  const TileRsrc rs = tile_rsrc<TV, L>(a, 0, ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
   uint32_t cs = cstride;
   TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
@@ -977,20 +993,15 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
     __syncthreads();
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     ACC sq = (ACC)0, mx = (ACC)0;
 #pragma unroll 1
     for (int u = 0; u < nt; ++u) {
       asm volatile("" : "+s"(cs));
-      const int64_t r = tile_row(sg, k, u, rev);
+      const int64_t r = seg_row(t0, nt, u, rev);
       const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
       ACC v[L];
-      uint32_t so = 0;
-#pragma unroll
-      for (int q = 0; q < L; ++q) {
-        v[q] = (ACC)ldv(bload_nt<TV>(rs, voff + so));
-        if (q < ncol) so += cs;
-      }
+      load_tile<TV, L, true>(v, rs, voff, cs);
       ACC wr = (ACC)w[r];
 #pragma unroll
       for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
@@ -1017,10 +1028,10 @@ __global__ __launch_bounds__(kBlock) void k_final(KArgs a, SegTab sg, int j) {
     const int s = sg.seg_sys[k];
     if (!gated(a, s)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     ACC sq = (ACC)0, mx = (ACC)0;
     for (int u = 0; u < nt; ++u) {
-      const int64_t r = tile_row(sg, k, u, 0);
+      const int64_t r = seg_row(t0, nt, u, 0);
       ACC wr = (ACC)w[r];
       for (int i = 0; i <= j; ++i) wr -= (ACC)coefd[i] * (ACC)ldv(col_ptr<TV>(a, i)[r]);
       sq += wr * wr;
@@ -1076,7 +1087,7 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
     const int s = sg.seg_sys[k];
     if (!gated(a, s)) continue;
     const ACC cprev = i > 0 ? (ACC)mgs_complete(a, sg, s, k == sg.sys_sg0[s], i - 1, pin) : (ACC)0;
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     ACC d = (ACC)0, ww = (ACC)0;
     // kMgsUnroll tiles per iteration: all their loads are issued before use
     for (int u = 0; u < nt; u += kMgsUnroll) {
@@ -1084,7 +1095,7 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
       ACC wv[kMgsUnroll], pv[kMgsUnroll], iv[kMgsUnroll];
 #pragma unroll
       for (int q = 0; q < kMgsUnroll; ++q) {
-        r[q] = tile_row(sg, k, u + q < nt ? u + q : u, i & 1);
+        r[q] = seg_row(t0, nt, u + q < nt ? u + q : u, i & 1);
         wv[q] = (ACC)w[r[q]];
         pv[q] = i > 0 ? (ACC)ldv(vp[r[q]]) : (ACC)0;
         iv[q] = (ACC)ldv(vi[r[q]]);
@@ -1128,14 +1139,14 @@ __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab
     const int s = sg.seg_sys[k];
     if (!gated(a, s)) continue;
     const ACC cj = (ACC)mgs_complete(a, sgp, s, k == sg.sys_sg0[s], j, pin);
-    const int nt = sg.seg_nt[k];
+    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     ACC sq = (ACC)0, mx = (ACC)0;
     for (int u = 0; u < nt; u += kMgsUnroll) {
       int64_t r[kMgsUnroll];
       ACC wv[kMgsUnroll], jv[kMgsUnroll];
 #pragma unroll
       for (int q = 0; q < kMgsUnroll; ++q) {
-        r[q] = tile_row(sg, k, u + q < nt ? u + q : u, (j + 1) & 1);
+        r[q] = seg_row(t0, nt, u + q < nt ? u + q : u, (j + 1) & 1);
         wv[q] = (ACC)w[r[q]];
         jv[q] = (ACC)ldv(vj[r[q]]);
       }

@@ -47,7 +47,14 @@ PEAK_HBM_GBS = 8000.0
 # the family's launches that did work.  Valid only for the family they were
 # taken for (the kernel instantiation's name) and the kernel source they were
 # taken from.
-TRAFFIC = {"kernel": None, "bytes_per_launch": None, "kernel_source_sha256": None}
+# HBM bytes per launch of the roofline kernel from two rocprofv3 counter
+# passes (FETCH_SIZE, WRITE_SIZE; the 585 launches that did work inside the
+# profiled solve of `--legs none --mgs-steps 0 --no-cpu --no-fp64 --steps 1
+# --warmup 0 --spmv-format sell --copy-probe`), each scaled by what the same
+# counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
+# once the kernel source changes
+TRAFFIC = {"kernel": "k_sell<float, float, float, 0>", "bytes_per_launch": 145172446,
+           "kernel_source_sha256": "d9aedb56854270131b248c3cad449c59a0abe70af73640e2a916a194abd17480"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 
@@ -100,11 +107,85 @@ def parse():
     ap.add_argument("--c5-test", type=int, default=200, help="c5 leg: held-out instances")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (reference kernel for HBM byte counters)")
+    ap.add_argument("--spmv-format", default="auto", choices=["auto", "csr", "sell"],
+                    help="Arnoldi SpMV format of the time-to-solution handles (auto: the autotuner's choice; "
+                         "a fixed format keeps counter passes on one kernel)")
+    ap.add_argument("--trace-summary", metavar="DIR",
+                    help="no GPU: summarise the rocprofv3 CSV output in DIR (kernel trace and/or counter "
+                         "collection) for the last --last dispatches of --kernel, i.e. the launches of the "
+                         "profiled solve of a run with --legs none --mgs-steps 0")
+    ap.add_argument("--kernel", default="k_sell<float, float, float, 0>",
+                    help="--trace-summary: the kernel (template instantiation, without 'void gm::')")
+    ap.add_argument("--last", type=int, default=650, help="--trace-summary: dispatches of the profiled solve")
+    ap.add_argument("--floor-us", type=float, default=10.0,
+                    help="--trace-summary: dispatches shorter than this did no work (gated off)")
     return ap.parse_args()
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _short_kernel(name):
+    name = name[5:] if name.startswith("void ") else name
+    name = name[4:] if name.startswith("gm::") else name
+    return name.split("(")[0]
+
+
+def trace_summary(d, kernel, last, floor_us):
+    """Per-dispatch figures of one kernel from rocprofv3 CSV files: durations
+    from the kernel trace, and FETCH_SIZE / WRITE_SIZE (KiB) from the counter
+    collection, over the last `last` dispatches of that kernel, split into the
+    dispatches that did work and those the device gate switched off; with the
+    copy kernel's counters when the run ended with --copy-probe."""
+    out = {"kernel": kernel, "last": last}
+    tr = [r for r in _csv_rows(d, "kernel_trace.csv") if _short_kernel(r["Kernel_Name"]) == kernel]
+    if tr:
+        tr.sort(key=lambda r: int(r["Dispatch_Id"]))
+        sel = tr[-last:]
+        us = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+        act = [u for u in us if u >= floor_us]
+        out["trace"] = {"dispatches_of_kernel": len(tr), "selected": len(sel), "avg_us_all": sum(us) / len(us),
+                        "worked": len(act), "avg_us_worked": (sum(act) / len(act)) if act else None,
+                        "min_us_worked": min(act) if act else None, "max_us_worked": max(act) if act else None}
+    cc = _csv_rows(d, "counter_collection.csv")
+    if cc:
+        per = {}
+        for r in cc:
+            k = _short_kernel(r["Kernel_Name"])
+            per.setdefault(k, {}).setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        mine = [per[kernel][i] for i in sorted(per.get(kernel, {}))][-last:]
+        res = {}
+        for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = [v[cname] for v in mine if cname in v]
+            if not vals:
+                continue
+            top = max(vals)
+            act = [v for v in vals if v > 0.05 * top]
+            res[cname] = {"selected": len(vals), "worked": len(act), "avg_kib_worked": sum(act) / len(act)}
+        # the --copy-probe copies: the last three copy dispatches of the run
+        copy_ids = sorted(i for k, dd in per.items() if "copyBuffer" in k for i in dd)[-3:]
+        copy = [dd[i] for k, dd in per.items() if "copyBuffer" in k for i in dd if i in copy_ids]
+        for cname in ("FETCH_SIZE", "WRITE_SIZE"):
+            vals = [v[cname] for v in copy if cname in v]
+            if vals:
+                res.setdefault("copy_probe", {})[cname] = vals
+        out["counters"] = res
+    return out
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+SPMV_FORMAT = "auto"  # --spmv-format: the Arnoldi SpMV format of every time-to-solution handle
 
 
 def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps, warmup, stall_cycles=10,
@@ -119,7 +200,7 @@ def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps,
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = Solver(rp, ci, va, m=m, ortho=ortho, precision=precision, tol=1e-10, max_iters=100_000,
-                   stall_cycles=stall_cycles, a_storage=a_storage)
+                   stall_cycles=stall_cycles, a_storage=a_storage, spmv_format=SPMV_FORMAT)
         x, info = s.solve(b_dev)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -163,16 +244,14 @@ def tile_width(j):
 
 def spmv_kernel(precision, spmv=None):
     """The Arnoldi SpMV's template instantiation for the handle's SpMV choice
-    (Solver.spmv_config(): the sliced ELL kernel or the CSR row blocks, with or
-    without non-temporal matrix loads); the matrix values are float64 only in
-    the float64 solver."""
+    (Solver.spmv_config(): the sliced ELL kernel or the CSR row blocks); the
+    matrix values are float64 only in the float64 solver."""
     if not spmv:
         return FAMILY_KERNELS["spmv"]
     ta = "double" if precision == "fp64" else "float"
     ty = TYPES.get(precision, "?")
-    if spmv["format"] == "sell":
-        return f"k_sell<{ta}, {ty}, 0>"
-    return f"k_spmv<{ta}, {ty}, 0, {'true' if spmv['nontemporal'] else 'false'}>"
+    kern = "k_sell" if spmv["format"] == "sell" else "k_spmv"
+    return f"{kern}<{ta}, {ty}, 0>"
 
 
 def kernel_units(fam, m, precision, ortho, spmv=None):
@@ -1043,6 +1122,11 @@ def learned_run(n_train, n_test, n_baseline, epochs, N):
 
 def main():
     args = parse()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.kernel, args.last, args.floor_us), indent=1))
+        return
+    global SPMV_FORMAT
+    SPMV_FORMAT = args.spmv_format
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU row partitioning is described in the design notes only)", file=sys.stderr)

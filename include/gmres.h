@@ -299,8 +299,16 @@ int gmres_solve(gmres_handle h, const double* b, double* x, gmres_result* res);
  * nsys pointers); res is a host array of nsys results. */
 int gmres_batch_solve(gmres_handle h, const double* const* b, double* const* x, gmres_result* res);
 
-/* Free everything owned by the handle.  Safe on NULL. */
+/* Free everything owned by the handle.  Safe on NULL.  Waits for the
+ * handle's stream; its device blocks are kept by the library for the next
+ * handle created on the same device (up to 16 GiB per device; beyond that,
+ * and for any block when a new allocation fails, they are freed). */
 int gmres_destroy(gmres_handle h);
+
+/* Frees the device blocks destroyed handles left for reuse, on every device
+ * (live handles keep theirs); *bytes (HOST, may be NULL) = the bytes freed.
+ * Not to be called while another thread creates a handle. */
+int gmres_release_cached_memory(size_t* bytes);
 
 const char* gmres_strerror(int code);
 
@@ -479,11 +487,9 @@ int gmres_launch_config(gmres_handle h, int32_t family, int32_t j, int32_t* grid
  * it, for the measurement report: *format = GMRES_SPMV_CSR or
  * GMRES_SPMV_SELL; *block_nnz = the nonzeros per CSR row block (also used by
  * the residual and preconditioner products); *xcd_remap = 1 when consecutive
- * workgroups are mapped onto one XCD; *nontemporal = 1 when the matrix
- * streams are loaded non-temporally.  Any output may be NULL.  ESTATE on the
+ * workgroups are mapped onto one XCD.  Any output may be NULL.  ESTATE on the
  * persistent batch schedule. */
-int gmres_spmv_config(gmres_handle h, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap,
-                      int32_t* nontemporal);
+int gmres_spmv_config(gmres_handle h, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap);
 
 #ifdef __cplusplus
 }

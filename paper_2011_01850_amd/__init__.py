@@ -7,4 +7,4 @@ HIP sources in csrc/; this package only marshals arguments to it.
 """
 from ._lib import (CGSR, CONVERGED, FP64, MAXITER, MGS, MIXED_BF16, MIXED_FP16, MIXED_FP32,  # noqa: F401
                    STALLED, GmresError, load)
-from .solver import BatchSolver, Solver, encode  # noqa: F401
+from .solver import BatchSolver, Solver, encode, release_cached_memory  # noqa: F401

@@ -121,6 +121,7 @@ _SIGS = {
     "gmres_solve": (C.c_int, [_vp, _vp, _vp, C.POINTER(Result)]),
     "gmres_batch_solve": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(Result)]),
     "gmres_destroy": (C.c_int, [_vp]),
+    "gmres_release_cached_memory": (C.c_int, [C.POINTER(C.c_size_t)]),
     "gmres_residual": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
     "gmres_backward_error": (C.c_int, [_vp, _vp, _vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "gmres_residual_unit": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double)]),
@@ -140,8 +141,7 @@ _SIGS = {
                                        C.POINTER(KernelProfile)]),
     "gmres_launch_config": (C.c_int, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
-    "gmres_spmv_config": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                    C.POINTER(C.c_int32)]),
+    "gmres_spmv_config": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "gmres_spai_infer": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "spai_create": (C.c_int, [C.POINTER(_vp), C.c_int64, C.c_int64, _vp, _vp, C.c_int32, _vp]),
     "spai_set_values": (C.c_int, [_vp, _vp]),

@@ -68,6 +68,7 @@ struct gmres_ctx {
   std::vector<int32_t> rp_host;  // global row pointer (ld + 1)
   std::vector<std::unique_ptr<RowBlocks>> rbt;  // row-block tables built so far
   std::vector<void*> allocs;
+  std::vector<hipEvent_t> tune_ev;  // the SpMV autotuner's event pairs
   size_t bytes = 0;
   KArgs a{};
   // host mirror of per-system state
@@ -102,24 +103,24 @@ struct gmres_ctx {
 
   template <typename T>
   T* alloc(size_t count) {
-    void* p = nullptr;
-    const size_t nb = std::max<size_t>(count * sizeof(T), 256);
-    hipError_t e = hipMalloc(&p, nb);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Fail{GMRES_ENOMEM};
-    }
+    size_t nb = 0;
+    void* p = cache_alloc(count * sizeof(T), &nb);
+    if (!p) throw Fail{GMRES_ENOMEM};
     allocs.push_back(p);
     bytes += nb;
     return static_cast<T*>(p);
   }
 
+  // the stream is drained first, so no kernel still reads a block that goes
+  // back to the cache (also on a create that failed part way)
   ~gmres_ctx() {
+    if (stream) (void)hipStreamSynchronize(stream);
     if (spai) (void)spai_destroy(spai);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (pexec) (void)hipGraphExecDestroy(pexec);
-    for (void* p : allocs) (void)hipFree(p);
+    for (void* p : allocs) cache_free(p);
     if (st_host) (void)hipHostFree(st_host);
+    for (hipEvent_t e : tune_ev) (void)hipEventDestroy(e);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (evu) (void)hipEventDestroy(evu);
@@ -735,62 +736,58 @@ bool build_sell(gmres_ctx* h) {
 }
 
 // Times the Arnoldi SpMV for a few row-block budgets, each with and without
-// the XCD block mapping and the non-temporal matrix loads (and the sliced ELL
-// copy when there is one), and keeps the fastest.  The row blocks stay set to the fastest budget for the
-// other products (residual, preconditioner) either way.
-void autotune_spmv(gmres_ctx* h, bool sell) {
-  float best = 1e30f, best_csr = 1e30f;
-  int best_budget = h->a.spmv_budget, best_remap = h->a.xcd_remap, best_sell = 0, best_nt = 0;
+// the XCD block mapping (and the sliced ELL copy when there is one), and
+// keeps the fastest (of the sliced ELL candidates only, when that format was
+// asked for).  Every candidate runs between its own pair of events and the
+// host waits once, at the end.  The row blocks stay set to the fastest budget
+// for the other products (residual, preconditioner) either way.
+void autotune_spmv(gmres_ctx* h, bool sell, bool sell_only) {
+  struct Cand {
+    int budget, remap, sell;
+  };
+  std::vector<Cand> cands;
+  for (int budget : kTuneBudgets)
+    for (int remap = 0; remap <= 1; ++remap) cands.push_back({budget, remap, 0});
+  if (sell)
+    for (int remap = 0; remap <= 1; ++remap) cands.push_back({kTuneBudgets[0], remap, 1});
+  for (int budget : kTuneBudgets) set_row_blocks(h, budget);  // tables uploaded before the first launch
+  while (h->tune_ev.size() < 2 * cands.size()) {
+    hipEvent_t e;
+    hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    h->tune_ev.push_back(e);
+  }
   // exercise with a column of the zero-initialised basis; force the kernel on
   hip_check(launch_set_force(h->a, 1, h->stream));
-  const int reps = 3;
-  auto timeit = [&]() {
+  constexpr int reps = 3;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    const Cand& c = cands[i];
+    set_row_blocks(h, c.budget);
+    h->a.xcd_remap = c.remap;
+    h->a.use_sell = c.sell;
     hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));  // warm
-    hip_check(hipEventRecord(h->ev0, h->stream));
+    hip_check(hipEventRecord(h->tune_ev[2 * i], h->stream));
     for (int r = 0; r < reps; ++r) hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));
-    hip_check(hipEventRecord(h->ev1, h->stream));
-    hip_check(hipEventSynchronize(h->ev1));
-    float ms = 0.f;
-    hip_check(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    return ms;
-  };
-  for (int budget : kTuneBudgets) {
-    set_row_blocks(h, budget);
-    for (int remap = 0; remap <= 1; ++remap)
-      for (int nt = 0; nt <= 1; ++nt) {
-        h->a.xcd_remap = remap;
-        h->a.spmv_nt = nt;
-        const float ms = timeit();
-        if (ms < best_csr) {
-          best_csr = ms;
-          best_budget = budget;
-          if (ms < best) {
-            best = ms;
-            best_remap = remap;
-            best_nt = nt;
-          }
-        }
-      }
-  }
-  if (sell) {
-    h->a.use_sell = 1;
-    h->a.spmv_nt = 0;
-    for (int remap = 0; remap <= 1; ++remap) {
-      h->a.xcd_remap = remap;
-      const float ms = timeit();
-      if (ms < best) {
-        best = ms;
-        best_remap = remap;
-        best_sell = 1;
-        best_nt = 0;
-      }
-    }
+    hip_check(hipEventRecord(h->tune_ev[2 * i + 1], h->stream));
   }
   hip_check(launch_set_force(h->a, 0, h->stream));
-  set_row_blocks(h, best_budget);
-  h->a.xcd_remap = best_remap;
-  h->a.use_sell = best_sell;
-  h->a.spmv_nt = best_nt;
+  hip_check(hipEventSynchronize(h->tune_ev[2 * cands.size() - 1]));
+  float best = 1e30f, best_csr = 1e30f;
+  size_t bi = 0, bc = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, h->tune_ev[2 * i], h->tune_ev[2 * i + 1]));
+    if (!cands[i].sell && ms < best_csr) {
+      best_csr = ms;
+      bc = i;
+    }
+    if (ms < best && (cands[i].sell || !sell_only)) {
+      best = ms;
+      bi = i;
+    }
+  }
+  set_row_blocks(h, cands[bc].budget);
+  h->a.xcd_remap = cands[bi].remap;
+  h->a.use_sell = cands[bi].sell;
   hip_check(hipStreamSynchronize(h->stream));
 }
 
@@ -905,8 +902,17 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   a.ortho = opt->ortho;
   a.arn64 = opt->arnoldi_a == GMRES_ARNOLDI_A_FP64 || (opt->arnoldi_a == GMRES_ARNOLDI_A_DEFAULT && prec == P64) ? 1 : 0;
   a.xcd_remap = 1;
+  // the device copy of the global row pointer is built on the device from
+  // the caller's arrays (shifted by each system's first non-zero, padding
+  // rows empty), the same values as the host copy
   int32_t* d_rp = h->alloc<int32_t>(h->ld + 1);
-  hip_check(hipMemcpy(d_rp, h->rp_host.data(), (h->ld + 1) * 4, hipMemcpyHostToDevice));
+  for (int k = 0; k < nsys; ++k) {
+    const System& s = h->sys[k];
+    hip_check(launch_shift_cols(rp[k], d_rp + s.row0, s.n, (int32_t)s.nz0, h->stream));
+    const int64_t end = k + 1 < nsys ? h->sys[k + 1].row0 : h->ld + 1;
+    hip_check(hipMemsetD32Async((hipDeviceptr_t)(d_rp + s.row0 + s.n), (int)(s.nz0 + s.nnz),
+                                (size_t)(end - s.row0 - s.n), h->stream));
+  }
   // index and value arrays carry a zero pad of 4 entries (SpMV reads aligned groups of 4)
   int32_t* d_ci = h->alloc<int32_t>(h->nnz + 4);
   hip_check(hipMemsetAsync(d_ci + h->nnz, 0, 16, h->stream));
@@ -1090,7 +1096,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     const bool sell = opt->spmv_format != GMRES_SPMV_CSR && (tune || opt->spmv_format == GMRES_SPMV_SELL) &&
                       build_sell(h);
     if (tune)
-      autotune_spmv(h, sell);
+      autotune_spmv(h, sell, sell && opt->spmv_format == GMRES_SPMV_SELL);
     else
       a.use_sell = sell ? 1 : 0;
   }
@@ -1478,6 +1484,12 @@ int gmres_destroy(gmres_handle hh) {
   return GMRES_OK;
 }
 
+int gmres_release_cached_memory(size_t* bytes) {
+  const size_t n = cache_release_all();
+  if (bytes) *bytes = n;
+  return GMRES_OK;
+}
+
 int gmres_residual(gmres_handle hh, const double* b, const double* x, double* r, double* norm_out) {
   try {
     gmres_ctx* h = get(hh);
@@ -1817,15 +1829,13 @@ int gmres_launch_config(gmres_handle hh, int32_t family, int32_t j, int32_t* gri
   }
 }
 
-int gmres_spmv_config(gmres_handle hh, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap,
-                      int32_t* nontemporal) {
+int gmres_spmv_config(gmres_handle hh, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap) {
   try {
     gmres_ctx* h = get(hh);
     if (h->persistent) return GMRES_ESTATE;
     if (format) *format = h->a.use_sell ? GMRES_SPMV_SELL : GMRES_SPMV_CSR;
     if (block_nnz) *block_nnz = h->a.spmv_budget;
     if (xcd_remap) *xcd_remap = h->a.xcd_remap;
-    if (nontemporal) *nontemporal = h->a.spmv_nt;
     return GMRES_OK;
   } catch (const Fail& f) {
     return f.code;

@@ -98,7 +98,6 @@ struct KArgs {
   int32_t ortho;    // 0 MGS, 1 CGSR
   int32_t spmv_budget;  // nnz per SpMV row block (streaming mode)
   int32_t xcd_remap;    // map consecutive blocks onto one XCD
-  int32_t spmv_nt;      // the Arnoldi product's row blocks load the matrix with the non-temporal hint
   int32_t ncu;          // compute units of the device
   int32_t vsys;         // basis layout: 0 = column stride ld over all systems,
                         // 1 = one block of (m+1) padded columns per system (persistent batch)
@@ -293,5 +292,15 @@ hipError_t launch_build_ell(const KArgs& a, int s, int64_t row0, int n, int w, i
 // Queries, once per process, how many workgroups of each persistent basis
 // pass of `prec` fit on one CU.  Must run before any graph capture.
 hipError_t prepare_occupancy(int prec);
+
+// Device blocks of the handles (device_cache.cpp): cache_alloc takes a
+// block of at least `bytes` on the current device (a released block of the
+// same rounded size, else a new one; nullptr when out of memory) and stores
+// the rounded size in *rounded; cache_free returns it for reuse (all work
+// that reads it must be complete); cache_release_all frees every released
+// block and returns how many bytes that was.
+void* cache_alloc(size_t bytes, size_t* rounded);
+void cache_free(void* p);
+size_t cache_release_all();
 
 }  // namespace gm

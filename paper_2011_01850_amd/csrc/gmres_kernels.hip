@@ -449,22 +449,19 @@ enum SpmvMode { SM_ARNOLDI = 0, SM_PRECOND = 1, SM_AZ = 2, SM_RESID = 3, SM_PLAI
 // the products l, l + T, ... in turn, then a fixed butterfly), so the
 // row-block layout (which the autotuner picks) never changes a result.
 
-// 16-byte loads of the matrix arrays, with the non-temporal hint when NT
-// (the arrays are streamed once per product; the hint keeps them from
-// displacing the gathered vector's lines in the L2).
+// 16-byte loads of the matrix arrays.  (The non-temporal hint on these
+// streams was measured on the stencil and power-law matrices and never
+// gained: the gathers, not the streams, are what the L2 misses.)
 typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
-template <bool NT, typename V>
+template <typename V>
 __device__ __forceinline__ V ld16(const void* p) {
-  if constexpr (NT)
-    return __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
-  else
-    return *reinterpret_cast<const V*>(p);
+  return *reinterpret_cast<const V*>(p);
 }
 
-template <typename TA, typename TX, typename TY, int MODE, bool NT = false>
+template <typename TA, typename TX, typename TY, int MODE>
 __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__ vals,
                                                  const TX* __restrict__ x, TY* __restrict__ y,
                                                  const double* __restrict__ bvec, int j) {
@@ -547,20 +544,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
           v4[u][0] = v4[u][1] = v4[u][2] = v4[u][3] = (ACC)0;
           continue;
         }
-        c4[u] = ld16<NT, i32x4_t>(a.ci + k4);
+        c4[u] = ld16<i32x4_t>(a.ci + k4);
         if constexpr (std::is_same<TA, float>::value) {
-          const f32x4_t f = ld16<NT, f32x4_t>(vals + k4);
+          const f32x4_t f = ld16<f32x4_t>(vals + k4);
           v4[u][0] = f.x; v4[u][1] = f.y; v4[u][2] = f.z; v4[u][3] = f.w;
         } else if constexpr (std::is_same<TA, double>::value) {
-          const f64x2_t f0 = ld16<NT, f64x2_t>(vals + k4);
-          const f64x2_t f1 = ld16<NT, f64x2_t>(vals + k4 + 2);
+          const f64x2_t f0 = ld16<f64x2_t>(vals + k4);
+          const f64x2_t f1 = ld16<f64x2_t>(vals + k4 + 2);
           v4[u][0] = f0.x; v4[u][1] = f0.y; v4[u][2] = f1.x; v4[u][3] = f1.y;
         } else {
-          const u32x4_t h = ld16<NT, u32x4_t>(vals + k4);
+          const u32x4_t h = ld16<u32x4_t>(vals + k4);
           if constexpr (std::is_same<TA, HiW>::value) {
             v4[u][0] = hi_value(h.x); v4[u][1] = hi_value(h.y); v4[u][2] = hi_value(h.z); v4[u][3] = hi_value(h.w);
           } else {
-            const u32x4_t lo = ld16<NT, u32x4_t>(a.alo + k4);
+            const u32x4_t lo = ld16<u32x4_t>(a.alo + k4);
             v4[u][0] = hilo_value(h.x, lo.x); v4[u][1] = hilo_value(h.y, lo.y);
             v4[u][2] = hilo_value(h.z, lo.z); v4[u][3] = hilo_value(h.w, lo.w);
           }
@@ -853,23 +850,34 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
     const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0, ww = (ACC)0;
+    // narrow tiles move few bytes per load round: UT of them per iteration
+    // keep as many loads in flight as a wider tile (sums stay tile by tile)
+    constexpr int UT = L <= 16 ? 2 : 1;
 #pragma unroll 1
-    for (int u = 0; u < nt; ++u) {
+    for (int u = 0; u < nt; u += UT) {
       // column offsets are rebuilt per tile (a scalar add each) instead of
       // being hoisted into L/2 live scalar registers
       asm volatile("" : "+s"(cs));
-      const int64_t r = seg_row(t0, nt, u, rev);
-      const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
-      const ACC wr = mode == 3 ? (ACC)ldv(wv[r]) : (ACC)w[r];
-      ww += wr * wr;
-      ACC p[L];
-      if (sizeof(TV) != 2 && u < nfirst)
-        load_tile<TV, L, true>(p, rs, voff, cs);
-      else
-        load_tile<TV, L, false>(p, rs, voff, cs);
+      ACC p[UT][L], wr[UT];
 #pragma unroll
-      for (int q = 0; q < L; ++q) p[q] *= wr;
-      colsum += reduce_scatter<L>(p, lane);
+      for (int h = 0; h < UT; ++h) {
+        const int uu = u + h < nt ? u + h : u;
+        const int64_t r = seg_row(t0, nt, uu, rev);
+        const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
+        wr[h] = mode == 3 ? (ACC)ldv(wv[r]) : (ACC)w[r];
+        if (sizeof(TV) != 2 && uu < nfirst)
+          load_tile<TV, L, true>(p[h], rs, voff, cs);
+        else
+          load_tile<TV, L, false>(p[h], rs, voff, cs);
+      }
+#pragma unroll
+      for (int h = 0; h < UT; ++h) {
+        if (u + h >= nt) break;
+        ww += wr[h] * wr[h];
+#pragma unroll
+        for (int q = 0; q < L; ++q) p[h][q] *= wr[h];
+        colsum += reduce_scatter<L>(p[h], lane);
+      }
     }
     store_colsums<L>(a.part, sg.nseg, k, col0, ncol, colsum);
     if (col0 == 0 && mode == 1) {
@@ -1933,25 +1941,17 @@ static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStre
     hipLaunchKernelGGL(kern, dim3(a.nrb), dim3(kBlock), (size_t)a.spmv_budget * acc_bytes, st, a, vals, x, y,
                        nullptr, j);
   };
-  auto by_values = [&](auto nt) {
-    constexpr bool NT = decltype(nt)::value;
-    if (a.arn64) {
-      if (a.asplit)
-        go(k_spmv<HiLoW, TX, TY, MODE, NT>, reinterpret_cast<const HiLoW*>(a.ahi), sizeof(AccFor<HiLoW, TY>));
-      else
-        go(k_spmv<double, TX, TY, MODE, NT>, a.a64, sizeof(AccFor<double, TY>));
-    } else {
-      if (a.asplit)
-        go(k_spmv<HiW, TX, TY, MODE, NT>, reinterpret_cast<const HiW*>(a.ahi), sizeof(AccFor<HiW, TY>));
-      else
-        go(k_spmv<float, TX, TY, MODE, NT>, a.a32, sizeof(AccFor<float, TY>));
-    }
-  };
-  // the non-temporal matrix loads are a tuning choice of the Arnoldi product only
-  if ((MODE == SM_ARNOLDI || MODE == SM_AZ) && a.spmv_nt)
-    by_values(std::true_type{});
-  else
-    by_values(std::false_type{});
+  if (a.arn64) {
+    if (a.asplit)
+      go(k_spmv<HiLoW, TX, TY, MODE>, reinterpret_cast<const HiLoW*>(a.ahi), sizeof(AccFor<HiLoW, TY>));
+    else
+      go(k_spmv<double, TX, TY, MODE>, a.a64, sizeof(AccFor<double, TY>));
+  } else {
+    if (a.asplit)
+      go(k_spmv<HiW, TX, TY, MODE>, reinterpret_cast<const HiW*>(a.ahi), sizeof(AccFor<HiW, TY>));
+    else
+      go(k_spmv<float, TX, TY, MODE>, a.a32, sizeof(AccFor<float, TY>));
+  }
   return hipGetLastError();
 }
 

@@ -274,12 +274,11 @@ class Solver:
         return {"grid": g.value, "block": b.value, "per_cu": o.value, "basis_align": al.value}
 
     def spmv_config(self):
-        """The Arnoldi SpMV the handle runs: dict(format, block_nnz, xcd_remap, nontemporal)."""
-        f, bn, xr, nt = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        L.check(self.lib.gmres_spmv_config(self.h, C.byref(f), C.byref(bn), C.byref(xr), C.byref(nt)),
-                "gmres_spmv_config")
+        """The Arnoldi SpMV the handle runs: dict(format, block_nnz, xcd_remap)."""
+        f, bn, xr = C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self.lib.gmres_spmv_config(self.h, C.byref(f), C.byref(bn), C.byref(xr)), "gmres_spmv_config")
         fmt = {v: k for k, v in L.SPMV_FORMATS.items()}[f.value]
-        return {"format": fmt, "block_nnz": bn.value, "xcd_remap": bool(xr.value), "nontemporal": bool(nt.value)}
+        return {"format": fmt, "block_nnz": bn.value, "xcd_remap": bool(xr.value)}
 
     def time_kernel(self, kernel, j, reps=20):
         """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""
@@ -375,6 +374,13 @@ class BatchSolver:
                 "probe_us": {L.PERSISTENT_SPMV_NAMES[v]: round(probe[v], 2) for v in range(3) if probe[v] >= 0},
                 "classes": [{"rows_per_thread": c.rows_per_thread, "systems": c.systems, "largest_n": c.largest_n,
                              "probe_system": c.probe_system} for c in out[: min(cnt.value, 16)]]}
+
+
+def release_cached_memory():
+    """Free the device blocks destroyed handles left for reuse; returns the bytes freed."""
+    n = C.c_size_t()
+    L.check(L.load().gmres_release_cached_memory(C.byref(n)), "gmres_release_cached_memory")
+    return n.value
 
 
 def encode(w, inv_h, fmt="fp16", out=None, noalloc=False):

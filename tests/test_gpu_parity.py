@@ -194,10 +194,11 @@ def test_split_storage_solves(ortho):
                   a_storage="split", max_iters=20000)
     assert emu.status == O.CONVERGED
     assert abs(_cycles_to(info["history"], 1e-10) - _cycles_to(emu.history, 1e-10)) <= 1
-    # footprint: the float32 copy (4 bytes per non-zero) is gone
+    # footprint: the float32 copy (4 bytes per non-zero) is gone; the handle
+    # holds its blocks rounded up to 256 bytes, and three of them differ
     s_copy = _solver(pr.A, m=m, ortho=ortho, precision="fp32", autotune=False)
     s_split = _solver(pr.A, m=m, ortho=ortho, precision="fp32", autotune=False, a_storage="split")
-    assert s_copy.memory_bytes() - s_split.memory_bytes() >= 4 * pr.A.nnz
+    assert s_copy.memory_bytes() - s_split.memory_bytes() >= 4 * pr.A.nnz - 3 * 256
     s_copy.close()
     s_split.close()
 
@@ -628,6 +629,33 @@ def test_results_do_not_depend_on_spmv_row_blocks(case):
         assert np.array_equal(x, x0), (budget, tune)
 
 
+def test_reused_device_blocks_give_the_same_solve():
+    # a destroyed handle's device blocks go back to the library's cache and
+    # the next handle of the same shape takes them (not zeroed): its solve
+    # must match one on fresh blocks bit for bit
+    from paper_2011_01850_amd import release_cached_memory
+
+    pr = P.c1_convdiff2d(48)
+    kw = dict(m=30, ortho="cgsr", precision="fp32")
+    s = _solver(pr.A, **kw)
+    x0, info0 = s.solve(pr.b)
+    x0 = x0.cpu().numpy()
+    s.close()
+    assert release_cached_memory() > 0  # the handle's blocks were cached, then freed
+    assert release_cached_memory() == 0
+    s = _solver(pr.A, **kw)  # fresh blocks
+    x1, info1 = s.solve(pr.b)
+    x1 = x1.cpu().numpy()
+    s.close()
+    for _ in range(2):  # reused blocks, holding the previous handle's data
+        s = _solver(pr.A, **kw)
+        x2, info2 = s.solve(pr.b)
+        x2 = x2.cpu().numpy()
+        s.close()
+        assert info2["iters"] == info1["iters"] == info0["iters"]
+        assert np.array_equal(x2, x1) and np.array_equal(x1, x0)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
 def test_batch_equals_single_solves_bitwise(precision):
     systems = [P.convdiff(N, beta) for N, beta in [(33, (10.0, 3.0)), (20, (0.0, 0.0)), (64, (80.0, 40.0)),
@@ -1003,6 +1031,19 @@ def test_sliced_ell_gives_the_row_block_bits(precision, ortho):
         assert out["sell"][2] == -(-A.n // 256)  # one workgroup per 256-row tile
         assert out["sell"][1] == out["csr"][1], name
         assert np.array_equal(out["sell"][0], out["csr"][0]), name
+
+
+def test_forced_spmv_format_survives_the_autotuner():
+    # the autotuner still times row-block budgets (the residual's product),
+    # but a format asked for is the format the Arnoldi product runs
+    A = P.convdiff(24, (50.0, 20.0, 10.0))
+    for fmt in ("sell", "csr"):
+        s = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format=fmt, autotune=True)
+        assert s.spmv_config()["format"] == fmt
+        s.close()
+    s = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format="auto", autotune=True)
+    assert s.spmv_config()["format"] in ("sell", "csr")
+    s.close()
 
 
 def test_sliced_ell_is_refused_for_long_rows():

@@ -104,6 +104,14 @@ __device__ __forceinline__ double ldd(rsrc_t r, uint32_t vo, uint32_t so) {
   const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0);
   return __hiloint2double((int)v[1], (int)v[0]);
 }
+// The same load with the non-temporal hint, for a value read once.  Being a
+// different load, it is never merged with a later ordinary load of the same
+// address (the right-hand side read for ||b||, merged with every restart
+// residual's read of it, would keep R float64 values live for the solve).
+__device__ __forceinline__ double ldd_once(rsrc_t r, uint32_t vo, uint32_t so) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 2);
+  return __hiloint2double((int)v[1], (int)v[0]);
+}
 __device__ __forceinline__ int ldu8(rsrc_t r, uint32_t vo, uint32_t so) {
   return (int)__builtin_amdgcn_raw_buffer_load_b8(r, (int)vo, (int)so, 0);
 }
@@ -328,7 +336,7 @@ __device__ __forceinline__ void p_system(const PArgs& a, int s, PShared& sh) {
   double bb = 0.0, dummy = 0.0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const double bv = ldd(br, t8, (uint32_t)q * kPB * 8u);
+    const double bv = ldd_once(br, t8, (uint32_t)q * kPB * 8u);
     bb += bv * bv;
   }
   bsum2(sh, buf, bb, dummy);
@@ -368,7 +376,11 @@ __device__ __forceinline__ void p_system(const PArgs& a, int s, PShared& sh) {
       const double z = ldd(br, t8, (uint32_t)q * kPB * 8u) - acc;  // zero past n
       zz += z * z;
       w[q] = (float)z;
-      __builtin_amdgcn_sched_barrier(0);  // one row at a time: bounded registers
+      // one row at a time, bounded registers: the empty asm consumes zz here,
+      // so the subtraction is not sunk past the other rows' loops (which
+      // would keep every row's float64 sum live at once)
+      asm volatile("" : "+v"(zz));
+      __builtin_amdgcn_sched_barrier(0);
     }
     bsum2(sh, buf, zz, dummy);
     beta = sqrt(zz);

@@ -234,6 +234,28 @@ __device__ __forceinline__ SpmvSys spmv_sys_of(const PArgs& a, int s, int64_t ro
   return m;
 }
 
+// A batch of B loads of a basis column (rows q0 .. q0 + B - 1 of this
+// thread) issued together.  At the register ceiling the scheduler would
+// otherwise interleave each load with its use (one round trip per row); the
+// empty asm takes every loaded value as an input, so all B are complete
+// before the first is used and they go out back to back.
+template <int B>
+__device__ __forceinline__ void load_rows(float (&v)[B], rsrc_t r, uint32_t t4, int q0) {
+#pragma unroll
+  for (int e = 0; e < B; ++e) v[e] = ldf(r, t4, (uint32_t)(q0 + e) * kPB * 4u);
+  if constexpr (B == 16)
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]),
+                 "v"(v[8]), "v"(v[9]), "v"(v[10]), "v"(v[11]), "v"(v[12]), "v"(v[13]), "v"(v[14]), "v"(v[15]));
+  else if constexpr (B == 8)
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
+  else if constexpr (B == 4)
+    asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]));
+  else if constexpr (B == 2)
+    asm volatile("" ::"v"(v[0]), "v"(v[1]));
+  else
+    asm volatile("" ::"v"(v[0]));
+}
+
 // w = A x over the system's rows (row q of thread t is t + 1024 q), entries in
 // groups of G, each row's products added in storage order; entries past a
 // row are masked (their gathers may fall anywhere, or past x).
@@ -450,10 +472,21 @@ __device__ __forceinline__ void p_system(const PArgs& a, int s, PShared& sh) {
           hbar[(int64_t)j * M1 + i] = h;
         }
         const float hf = (float)h;
+        // rows staged in LDS, then the rest reloaded in batches of 16 (the
+        // last batch ends at row R - 1 and skips rows already updated)
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          w[q] -= hf * (q < kStage ? sh.vst[t][q] : ldf(vi, t4, (uint32_t)q * kPB * 4u));
-          if ((q & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        for (int q = 0; q < (R < kStage ? R : kStage); ++q) w[q] -= hf * sh.vst[t][q];
+        if constexpr (R > kStage) {
+#pragma unroll
+          for (int q0 = kStage; q0 < R; q0 += 16) {
+            const int base = q0 < R - 16 ? q0 : R - 16;
+            float vb[16];
+            load_rows<16>(vb, vi, t4, base);
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+              if (base + e >= q0) w[base + e] -= hf * vb[e];
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
       float ws = 0.f;

@@ -452,13 +452,25 @@ __device__ __forceinline__ void p_system(const PArgs& a, int s, PShared& sh) {
       double wnorm_pre = 0.0;
       for (int i = 0; i <= j; ++i) {
         const rsrc_t vi = col(i);
+        // w . v_i in batches of 16 rows: the batch's loads go out together,
+        // its products are summed in row order, then the rows kept for the
+        // update are staged in LDS (read back by this thread only: no
+        // barrier).  The staging stores come after the batch's products: with
+        // them interleaved the compiler reused store data registers a few
+        // instructions after each store, and the 64-row tier computed wrong
+        // sums (not seen in this order).
         float d = 0.f;
+        constexpr int B = R < 16 ? R : 16;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-          const float v = ldf(vi, t4, (uint32_t)q * kPB * 4u);
-          if (q < kStage) sh.vst[t][q] = v;  // read back by this thread only: no barrier
-          d += w[q] * v;
-          if ((q & 15) == 15) __builtin_amdgcn_sched_barrier(0);  // at most 16 loads in flight
+        for (int q0 = 0; q0 < R; q0 += B) {
+          float vb[B];
+          load_rows<B>(vb, vi, t4, q0);
+#pragma unroll
+          for (int e = 0; e < B; ++e) d += w[q0 + e] * vb[e];
+#pragma unroll
+          for (int e = 0; e < B; ++e)
+            if (q0 + e < kStage) sh.vst[t][q0 + e] = vb[e];
+          __builtin_amdgcn_sched_barrier(0);
         }
         double h = (double)d;
         if (i == 0) {

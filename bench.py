@@ -94,8 +94,8 @@ def parse():
                     help="powerlaw: comma-separated precision modes to run (fp64 is always run first)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--roofline-reps", type=int, default=10)
-    ap.add_argument("--cpu-cycles", type=int, default=2,
-                    help="oracle sample: whole restart cycles of the float64 oracle (default 2)")
+    ap.add_argument("--cpu-cycles", type=int, default=3,
+                    help="oracle sample: whole restart cycles of the float64 oracle (default 3, about 11 s)")
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the whole float64 oracle solve instead of a sample (minutes)")
     ap.add_argument("--mgs-steps", type=int, default=3, help="timed steps of each MGS mode (default workload)")

@@ -16,7 +16,8 @@
  *    are host structs.
  *  - CSR: row_ptr int32[n+1] (row_ptr[0] = 0, non-decreasing), col_idx
  *    int32[nnz] in [0, n), values float64[nnz].  Column order inside a row
- *    is free; duplicates are summed.
+ *    is free and duplicates are summed, except with GMRES_PRECOND_ILU0
+ *    (increasing columns, see below).
  *  - Return value: GMRES_OK (0) or a negative error code (gmres_strerror).
  *    Not converging is not an error: gmres_solve returns GMRES_OK and
  *    reports the outcome in gmres_result.status.
@@ -79,7 +80,8 @@ enum { GMRES_A_COPY = 0, GMRES_A_SPLIT = 1 };
 /* right preconditioning in flexible GMRES (z_j = M v_j, w = A z_j, x += Z y).
  * ILU0: incomplete LU without fill (the preconditioner of the paper's
  * experiments), factored on the GPU in float64 at create time (rows in
- * dependency levels; every row must store its diagonal) and applied as
+ * dependency levels; every row must store its diagonal and list its columns
+ * in increasing order, else gmres_create returns GMRES_EINVAL) and applied as
  * z = U^-1 L^-1 v by ilu_sweeps Jacobi sweeps per triangle from a zero
  * start, or exactly (ilu_sweeps = 0: as many sweeps as the triangle has
  * levels).  The paper applies ILU(0) on the left; here it is applied on the

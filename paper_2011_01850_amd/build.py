@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libgmres.so")
 ARCH = os.environ.get("GMRES_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["gmres_kernels.hip", "gmres_engine.cpp", "batch_kernels.hip", "spai_kernels.hip", "spai_engine.cpp",
-           "encode_noalloc.hip", "device_cache.cpp"]
+           "encode_noalloc.hip", "device_cache.cpp", "host_plan.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

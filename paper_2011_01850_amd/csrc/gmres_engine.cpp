@@ -202,14 +202,7 @@ int64_t basis_elem_bytes(int precision) {
 }
 
 bool sizes_ok(int32_t nsys, const int64_t* n, const int64_t* nnz, const gmres_options* o) {
-  int64_t ld = 0, nz = 0;
-  for (int k = 0; k < nsys; ++k) {
-    if (n[k] > (int64_t)INT32_MAX || nnz[k] > (int64_t)INT32_MAX) return false;
-    ld += (n[k] + kTile - 1) / kTile * kTile;
-    nz += nnz[k];
-    if (ld >= (int64_t)INT32_MAX || nz > (int64_t)INT32_MAX - 4 * kBlock - 4) return false;
-  }
-  return (int64_t)std::max(o->m + 1, 4) * ld * basis_elem_bytes(o->precision) < ((int64_t)1 << 32);
+  return plan::sizes_fit(nsys, n, nnz, o->m, basis_elem_bytes(o->precision));
 }
 
 // Conditions of the persistent schedule (one workgroup of 1024 threads per
@@ -222,31 +215,6 @@ bool persistent_ok(const gmres_options* o, const int64_t* n, int32_t nsys, int64
   for (int k = 0; k < nsys; ++k)
     if (n[k] > (int64_t)1024 * kMaxPR) return false;
   return nnz_total * 8 < ((int64_t)1 << 32) && ld * 8 < ((int64_t)1 << 32);
-}
-
-// Adaptive-CSR row blocks over global rows [r_begin, r_end): up to kBlock
-// rows (2 kBlock with budgets of 4096 and more: fewer, longer blocks for
-// short rows) whose non-zeros fit `budget`, or a single longer row.  `lanes` gets
-// the lane-group width of each block: row_lanes of its longest row
-// (row_lanes grows with the length).
-void build_row_blocks(const std::vector<int32_t>& rp, int64_t r_begin, int64_t r_end, int budget,
-                      std::vector<int32_t>& rb, std::vector<int32_t>* lanes) {
-  int64_t r = r_begin;
-  const int64_t max_rows = budget >= 4096 ? 2 * kBlock : kBlock;
-  while (r < r_end) {
-    rb.push_back((int32_t)r);
-    int64_t nz = 0, rows = 0, maxlen = 0;
-    while (r < r_end && rows < max_rows) {
-      const int64_t len = (int64_t)rp[r + 1] - rp[r];
-      if (rows > 0 && nz + len > budget) break;
-      nz += len;
-      maxlen = std::max(maxlen, len);
-      ++rows;
-      ++r;
-      if (nz > budget) break;
-    }
-    if (lanes) lanes->push_back(row_lanes((int)std::min<int64_t>(maxlen, INT32_MAX)));
-  }
 }
 
 // Host staging for one download, freed when it goes out of scope: pinned
@@ -330,15 +298,15 @@ void fill_row_blocks(const gmres_ctx* h, RowBlocks& t) {
     const size_t before = t.rb.size();
     constexpr int64_t kChunk = 1 << 19;
     if (s.n <= kChunk) {
-      build_row_blocks(h->rp_host, s.row0, s.row0 + s.n, t.budget, t.rb, &t.lanes);
+      plan::build_row_blocks(h->rp_host.data(), s.row0, s.row0 + s.n, t.budget, t.rb, &t.lanes);
     } else {
       // a large system in row chunks built in parallel (a block never spans
       // two chunks; any blocking gives the same sums)
       const int64_t nc = (s.n + kChunk - 1) / kChunk;
       std::vector<std::vector<int32_t>> rbs(nc), lns(nc);
       parallel_for(nc, 4, [&](int64_t c) {
-        build_row_blocks(h->rp_host, s.row0 + c * kChunk, s.row0 + std::min<int64_t>(s.n, (c + 1) * kChunk),
-                         t.budget, rbs[c], &lns[c]);
+        plan::build_row_blocks(h->rp_host.data(), s.row0 + c * kChunk,
+                               s.row0 + std::min<int64_t>(s.n, (c + 1) * kChunk), t.budget, rbs[c], &lns[c]);
       });
       for (int64_t c = 0; c < nc; ++c) {
         t.rb.insert(t.rb.end(), rbs[c].begin(), rbs[c].end());
@@ -419,30 +387,16 @@ void set_row_blocks(gmres_ctx* h, int budget) {
 // Work split of the persistent basis passes for G workgroups: workgroup b
 // owns tiles [b T / G, (b+1) T / G), cut at system boundaries into segments.
 SegTab make_split(gmres_ctx* h, int G) {
-  const int64_t T = h->ntile;
-  std::vector<int32_t> bseg0, seg_t0, seg_nt, seg_sys, sys_sg0(h->sys.size(), -1), sys_nsg(h->sys.size(), 0);
-  size_t sysk = 0;
-  for (int b = 0; b < G; ++b) {
-    bseg0.push_back((int32_t)seg_t0.size());
-    int64_t t = (int64_t)b * T / G;
-    const int64_t t1 = (int64_t)(b + 1) * T / G;
-    while (t < t1) {
-      while (h->sys[sysk].t0 + h->sys[sysk].nt <= t) ++sysk;
-      const System& s = h->sys[sysk];
-      const int64_t e = std::min<int64_t>(t1, s.t0 + s.nt);
-      if (sys_sg0[sysk] < 0) sys_sg0[sysk] = (int32_t)seg_t0.size();
-      sys_nsg[sysk] += 1;
-      seg_t0.push_back((int32_t)t);
-      seg_nt.push_back((int32_t)(e - t));
-      seg_sys.push_back((int32_t)sysk);
-      t = e;
-    }
+  std::vector<int32_t> t0, nt;
+  for (const System& s : h->sys) {
+    t0.push_back(s.t0);
+    nt.push_back(s.nt);
   }
-  bseg0.push_back((int32_t)seg_t0.size());
+  const plan::TileSplit sp = plan::split_tiles(t0.data(), nt.data(), (int32_t)h->sys.size(), G);
   SegTab sg{};
   sg.G = G;
-  sg.nseg = (int32_t)seg_t0.size();
-  upload_pack(h, {&bseg0, &seg_t0, &seg_nt, &seg_sys, &sys_sg0, &sys_nsg},
+  sg.nseg = (int32_t)sp.seg_t0.size();
+  upload_pack(h, {&sp.bseg0, &sp.seg_t0, &sp.seg_nt, &sp.seg_sys, &sp.sys_sg0, &sp.sys_nsg},
               {&sg.bseg0, &sg.seg_t0, &sg.seg_nt, &sg.seg_sys, &sg.sys_sg0, &sg.sys_nsg});
   return sg;
 }
@@ -594,12 +548,7 @@ void build_graph(gmres_ctx* h) {
 void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
   KArgs& a = h->a;
   const int S = a.S;
-  auto tier = [](int64_t n) {
-    const int64_t rows = (n + 1023) / 1024;
-    int t = 1;
-    while (t < rows && t < kMaxPR) t *= 2;
-    return t;
-  };
+  auto tier = [](int64_t n) { return plan::persistent_rows_per_thread(n, kMaxPR); };
   std::vector<int32_t> width(S, 0);
   std::vector<int64_t> off(S, 0);
   int64_t total = 0;
@@ -707,20 +656,10 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
 bool build_sell(gmres_ctx* h) {
   KArgs& a = h->a;
   if (a.asplit || h->persistent) return false;
-  const int64_t nslice = h->ld / 64;
-  std::vector<int32_t> off(nslice + 1, 0);
-  int64_t total = 0;
-  for (int64_t sl = 0; sl < nslice; ++sl) {
-    int w = 0;
-    for (int64_t r = sl * 64; r < sl * 64 + 64; ++r) w = std::max(w, h->rp_host[r + 1] - h->rp_host[r]);
-    if (w >= 2 * kRowLanePer) return false;
-    off[sl] = (int32_t)total;
-    total += (int64_t)w * 64;
-    if (total >= (int64_t)INT32_MAX) return false;
-  }
-  off[nslice] = (int32_t)total;
-  std::vector<uint8_t> len(h->ld);
-  for (int64_t r = 0; r < h->ld; ++r) len[r] = (uint8_t)(h->rp_host[r + 1] - h->rp_host[r]);
+  std::vector<int32_t> off;
+  std::vector<uint8_t> len;
+  if (!plan::sell_layout(h->rp_host.data(), h->ld, off, len)) return false;
+  const int64_t total = off.back();
   a.sell_off = upload32(h, off);
   uint8_t* d_len = h->alloc<uint8_t>((size_t)h->ld);
   hip_check(hipMemcpyAsync(d_len, len.data(), (size_t)h->ld, hipMemcpyHostToDevice, h->stream));
@@ -870,8 +809,7 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
       const int32_t* v = st + s.row0;
       // the entry after the last row may already hold the next system's first
       // entry (n a multiple of the tile): its own value, nnz, was checked above
-      for (int64_t i = pieces[p].i0; i < pieces[p].i1; ++i)
-        if ((i + 1 < s.n ? v[i + 1] : (int32_t)s.nnz) < v[i]) throw Fail{GMRES_EINVAL};
+      if (!plan::row_ptr_piece_ok(v, s.n, (int32_t)s.nnz, pieces[p].i0, pieces[p].i1)) throw Fail{GMRES_EINVAL};
     });
     parallel_for((int64_t)pieces.size(), workers, [&](int64_t p) {
       const System& s = h->sys[pieces[p].k];
@@ -1168,41 +1106,15 @@ void setup_ilu0(gmres_ctx* h, int32_t sweeps) {
   const int64_t ld = h->ld;
   std::vector<int32_t> ci(h->nnz);
   if (h->nnz) hip_check(hipMemcpy(ci.data(), a.ci, h->nnz * 4, hipMemcpyDeviceToHost));
-  const std::vector<int32_t>& rp = h->rp_host;
-  std::vector<int32_t> diag(ld);
-  for (int64_t r = 0; r < ld; ++r) {
-    diag[r] = -1;
-    for (int p = rp[r]; p < rp[r + 1]; ++p)
-      if (ci[p] == r) diag[r] = p;
-    if (diag[r] < 0) {
-      if (rp[r] != rp[r + 1]) throw Fail{GMRES_EINVAL};  // a real row without its diagonal
-      diag[r] = rp[r];  // padding row: empty ranges
-    }
-  }
-  // levels: lower triangle (factorisation and L sweeps), upper triangle (U sweeps)
-  std::vector<int32_t> lvl(ld, 0), ulv(ld, 0);
-  int32_t depth_l = 0, depth_u = 0;
-  for (int64_t r = 0; r < ld; ++r) {
-    int32_t v = 0;
-    for (int p = rp[r]; p < diag[r]; ++p) v = std::max(v, lvl[ci[p]] + 1);
-    lvl[r] = v;
-    depth_l = std::max(depth_l, v + 1);
-  }
-  for (int64_t r = ld - 1; r >= 0; --r) {
-    int32_t v = 0;
-    for (int p = diag[r] + 1; p < rp[r + 1]; ++p) v = std::max(v, ulv[ci[p]] + 1);
-    ulv[r] = v;
-    depth_u = std::max(depth_u, v + 1);
-  }
-  std::vector<int32_t> count(depth_l + 1, 0), order(ld);
-  for (int64_t r = 0; r < ld; ++r) ++count[lvl[r] + 1];
-  for (int l = 0; l < depth_l; ++l) count[l + 1] += count[l];
-  {
-    std::vector<int32_t> fill(count.begin(), count.end() - 1);
-    for (int64_t r = 0; r < ld; ++r) order[fill[lvl[r]]++] = (int32_t)r;
-  }
-  int32_t* d_diag = upload32(h, diag);
-  int32_t* d_order = upload32(h, order);
+  // diagonal positions and dependency levels (lower triangle: factorisation
+  // and L sweeps; upper triangle: U sweeps); every stored row needs its
+  // diagonal and its columns in increasing order
+  plan::IluPlan ip;
+  if (plan::ilu_plan(h->rp_host.data(), ci.data(), ld, ip) != plan::ILU_OK) throw Fail{GMRES_EINVAL};
+  const std::vector<int32_t>& count = ip.count;
+  const int32_t depth_l = ip.depth_l, depth_u = ip.depth_u;
+  int32_t* d_diag = upload32(h, ip.diag);
+  int32_t* d_order = upload32(h, ip.order);
   a.diagpos = d_diag;
   double* lu = h->alloc<double>(h->nnz + 4);
   const double* vals = a.asplit ? nullptr : a.a64;

@@ -4,14 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "host_plan.hpp"  // kBlock, kTile, row_lanes and the host planning tables
+
 namespace gm {
 
-// Rows are grouped in tiles of kTile rows: one row per thread of a kBlock
-// workgroup.  Every system is padded to a whole number of tiles (padding rows
-// of the basis, w, x and b are zero and stay zero), so no kernel needs tail
-// handling inside a tile.
-constexpr int kBlock = 256;
-constexpr int kTile = 256;
 constexpr int kMaxM = 256;
 constexpr int kFinBlock = 1024;  // threads of the per-system finalise kernels
 constexpr int kHistCap = 4096;
@@ -19,19 +15,6 @@ constexpr int kMaxOcc = 8;       // persistent grids of ncu * k workgroups, k = 
 constexpr int kMaxPM = 64;       // persistent batch schedule: restart length limit
 constexpr int kMaxPR = 64;       //   and rows per thread (systems up to 1024 * 64 rows)
 constexpr int kMaxOrthM = 64;    // loss-of-orthogonality monitor: restart length limit
-
-// SpMV row sums follow one canonical order that depends only on the row's
-// length len: T = row_lanes(len) partial sums, partial l adding products
-// l, l + T, l + 2T, ... in turn, then the T partials combined by a fixed
-// butterfly.  T doubles from 1 while it stays <= 16 and every partial still
-// gets at least kRowLanePer products.
-constexpr int kRowLaneMax = 16;
-constexpr int kRowLanePer = 4;
-__host__ __device__ inline int row_lanes(int len) {
-  int T = 1;
-  while (T < kRowLaneMax && 2 * T * kRowLanePer <= len) T *= 2;
-  return T;
-}
 
 // Storage of the basis / of w: P64 float64 / float64, P32 float32 / float32,
 // PBF16 and PF16 2-byte / float32, PL32 (the limited mode) float32 / float64.

@@ -710,6 +710,20 @@ def test_ilu0_edge_cases():
     assert np.allclose(O.Matrix(rp, ci, va).dense(), D)
     with pytest.raises(GmresError):
         Solver(rp, ci, va, m=3, precision="fp32", precond="ilu0")
+    # ILU(0) needs each row's columns in increasing order (the factorisation
+    # merges sorted column lists); without a preconditioner the order is free
+    B = P.convdiff(8, (1.0, 1.0))
+    ci2 = B.col_idx.copy()
+    r = 20
+    ci2[B.row_ptr[r]:B.row_ptr[r + 1]] = ci2[B.row_ptr[r]:B.row_ptr[r + 1]][::-1]
+    with pytest.raises(GmresError):
+        Solver(B.row_ptr, ci2, B.vals, m=5, precision="fp32", precond="ilu0")
+    va2 = B.vals.copy()
+    va2[B.row_ptr[r]:B.row_ptr[r + 1]] = va2[B.row_ptr[r]:B.row_ptr[r + 1]][::-1]
+    s = Solver(B.row_ptr, ci2, va2, m=20, precision="fp32", tol=1e-10)
+    x, info = s.solve(np.ones(B.n))
+    s.close()
+    assert info["status"] == "CONVERGED"
     # the application entry point needs an ILU(0) handle
     A0 = P.convdiff(8, (1.0, 1.0))
     s = _solver(A0, m=5, precision="fp32", precond="jacobi")

@@ -711,9 +711,8 @@ __device__ __forceinline__ f16_t bload<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t
   return __builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
 }
 // The same loads with the non-temporal hint (cache policy bit 1 on gfx950):
-// used by the last pass of a CGSR step, whose basis columns are not read
-// again before the next step's first pass, so they need not displace the
-// rows the next passes will re-read from the memory-side cache.
+// rows of a CGSR pass that the memory-side cache could not keep until the
+// next pass reaches them, so they need not displace the rows it can keep.
 template <typename T>
 __device__ __forceinline__ T bload_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff);
 template <>
@@ -733,20 +732,27 @@ template <>
 __device__ __forceinline__ f16_t bload_nt<f16_t>(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(f16_t, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, 0, 2));
 }
-// Memory-side cache policy of the first two CGSR passes.  Each workgroup
-// walks its own tile range, and the next pass walks it the other way, so
+// Memory-side cache policy of the CGSR passes.  Each workgroup walks its own
+// tile range, and the next pass over the basis walks it the other way, so
 // only the last tiles a pass touches are still cached when the next pass
 // starts.  A pass over B bytes of basis keeps (with ordinary loads) the last
-// kMallKeep / B of every range; the tiles before them would be evicted
-// before the next pass reaches them, so they are read non-temporally.
+// keep / B of every range; the tiles before them would be evicted before the
+// next pass reaches them, so they are read non-temporally.  The two
+// projections keep kMallKeep; the last pass keeps less (kMallKeepLast), for
+// the next step's projection 1, because the Arnoldi product between them
+// streams A and does better when part of A is still cached from the step
+// before (measured on the 128^3 stencil: 192 MB there made the product 7 %
+// slower, 48 MB made it 1 % faster, and saved 1.8 ms of projection 1 per
+// solve).
 constexpr uint64_t kMallKeep = 192ull << 20;
+constexpr uint64_t kMallKeepLast = 48ull << 20;
 
 // (2-byte bases: never split, which keeps their 64-column tile free of
 // spills under the 128-register cap.)
 template <typename TV>
-__device__ __forceinline__ int nt_tiles(int nt, uint64_t pass_bytes) {
-  if (sizeof(TV) == 2 || pass_bytes <= kMallKeep) return 0;
-  return nt - (int)(((uint64_t)nt * kMallKeep + pass_bytes - 1) / pass_bytes);
+__device__ __forceinline__ int nt_tiles(int nt, uint64_t pass_bytes, uint64_t keep = kMallKeep) {
+  if (sizeof(TV) == 2 || pass_bytes <= keep) return 0;
+  return nt - (int)(((uint64_t)nt * keep + pass_bytes - 1) / pass_bytes);
 }
 
 // A register tile of L basis columns [col0, col0 + L) is read through two
@@ -1002,6 +1008,7 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
     __syncthreads();
     const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+    const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride, kMallKeepLast);
     ACC sq = (ACC)0, mx = (ACC)0;
 #pragma unroll 1
     for (int u = 0; u < nt; ++u) {
@@ -1009,7 +1016,10 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
       const int64_t r = seg_row(t0, nt, u, rev);
       const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
       ACC v[L];
-      load_tile<TV, L, true>(v, rs, voff, cs);
+      if (sizeof(TV) == 2 || u < nfirst)
+        load_tile<TV, L, true>(v, rs, voff, cs);
+      else
+        load_tile<TV, L, false>(v, rs, voff, cs);
       ACC wr = (ACC)w[r];
 #pragma unroll
       for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
@@ -1287,13 +1297,19 @@ __global__ __launch_bounds__(kBlock) void k_fin_step(KArgs a, const double* src,
   __shared__ SysState S;
   const int s = blockIdx.x, t = threadIdx.x;
   const SysState& G = a.st[s];
-  if (!G.active && !G.force) return;
+  // the state copy, the staged column and rotations and the partial rows are
+  // loaded before the gate is tested (they do not depend on it), so they
+  // take one memory round trip together
+  const int on0 = gate0(a);
   constexpr int kWords = (int)(sizeof(SysState) / 8);
   static_assert(sizeof(SysState) % 8 == 0, "SysState is copied as 8-byte words");
   if (t < kWords) reinterpret_cast<uint64_t*>(&S)[t] = reinterpret_cast<const uint64_t*>(&G)[t];
   fin_stage(a, s, j, sh);
+  const int b0 = a.S == 1 ? 0 : r0[s];
+  const int n = a.S == 1 ? rows : nr[s];
   double sq, mx;
-  reduce_sum_max(src + r0[s], src + rows + r0[s], nr[s], sq, mx);
+  reduce_sum_max(src + b0, src + rows + b0, n, sq, mx);
+  if (!gated_now(a, s, on0, n)) return;
   fin_step(a, s, j, sq, mx, S, sh);
   __syncthreads();
   if (t < kWords) reinterpret_cast<uint64_t*>(&a.st[s])[t] = reinterpret_cast<const uint64_t*>(&S)[t];
@@ -1303,24 +1319,30 @@ __global__ __launch_bounds__(kBlock) void k_fin_step(KArgs a, const double* src,
 // quantity q of system s.  Pass 1: h1_q = sc_q * sum and the next axpy
 // coefficient h1_q * sc_q (quantity j+1 carries ||w||^2).  Pass 2: h2_q, the
 // column of H (h1 + h2) and the coefficient h2_q * sc_q.
+// A completion is a few dependent memory round trips on one CU, so every
+// load it needs (the gate, the column's scale and h1 entry, the partial
+// rows) is issued before the gate is tested; a gated-off system's block
+// reduces and drops the result.
 template <int PASS>
 __global__ __launch_bounds__(kBlock) void k_fin_cols(KArgs a, SegTab sg, int j) {
   const int s = blockIdx.x, q = blockIdx.y;
-  const SysState& S = a.st[s];
-  if (!S.active && !S.force) return;
-  const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + sg.sys_sg0[s], sg.sys_nsg[s]);
-  if (threadIdx.x != 0) return;
   const int M1 = a.m + 1, M2 = a.m + 2;
+  const int on0 = gate0(a);
+  const double scq = a.sc[(int64_t)s * M1 + q];
+  const double h1q = PASS == 2 ? a.h1[(int64_t)s * M2 + q] : 0.0;
+  const int g0 = a.S == 1 ? 0 : sg.sys_sg0[s];
+  const int ng = a.S == 1 ? sg.nseg : sg.sys_nsg[s];
+  const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + g0, ng);
+  if (!gated_now(a, s, on0, ng) || threadIdx.x != 0) return;
   if (PASS == 1 && q == j + 1) {
     a.st[s].wnorm_pre = sqrt(v);
     return;
   }
-  const double scq = a.sc[(int64_t)s * M1 + q];
   const double h = scq * v;
   if (PASS == 1)
     a.h1[(int64_t)s * M2 + q] = h;
   else
-    a.hacc[(int64_t)s * M2 + q] = a.h1[(int64_t)s * M2 + q] + h;
+    a.hacc[(int64_t)s * M2 + q] = h1q + h;
   a.coef[(int64_t)s * M2 + q] = h * scq;
 }
 
@@ -1888,16 +1910,19 @@ static const SegTab& split_for(const KArgs& a, K kernel) {
   return a.seg[occupancy_of(reinterpret_cast<const void*>(kernel)) - 1];
 }
 
-// direction of the CGS passes: projection 1 forward, projection 2 backward,
-// the last pass forward again
-constexpr int kRevPass1 = 0, kRevPass2 = 1, kRevPass3 = 0;
+// Direction of the CGS passes of step j: each pass walks the basis the other
+// way from the pass before it, across steps too (projection 1 of step j+1
+// starts on the rows the last pass of step j touched last).
+__host__ __device__ constexpr int rev_pass1(int j) { return j & 1; }
+__host__ __device__ constexpr int rev_pass2(int j) { return (j & 1) ^ 1; }
+__host__ __device__ constexpr int rev_pass3(int j) { return j & 1; }
 
 template <typename TV, typename TW, int L>
 static hipError_t launch_mdot_L(const KArgs& a, int j, int col0, int mode, hipStream_t st, const SegTab** used) {
   auto kern = k_mdot<TV, TW, L>;
   const SegTab& sg = split_for(a, kern);
   hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, col0, mode,
-                     mode == 1 ? kRevPass1 : kRevPass2);
+                     mode == 1 ? rev_pass1(j) : rev_pass2(j));
   if (used) *used = &sg;
   return hipGetLastError();
 }
@@ -2179,12 +2204,12 @@ static hipError_t launch_axpy_mdot_L(const KArgs& a, int j, hipStream_t st, cons
   if constexpr (sizeof(TW) == 8) {
     auto kern = k_axpy_mdot64<TV, TW, L>;
     const SegTab& sg = split_for(a, kern);
-    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass2);
+    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, rev_pass2(j));
     *used = &sg;
   } else {
     auto kern = k_axpy_mdot<TV, TW, L>;
     const SegTab& sg = split_for(a, kern);
-    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass2);
+    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, rev_pass2(j));
     *used = &sg;
   }
   return hipGetLastError();
@@ -2321,7 +2346,7 @@ hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fi
     if (j + 1 <= 64) {
       auto go = [&](auto kern) {
         const SegTab& sg = split_for(a, kern);
-        hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, kRevPass3);
+        hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, rev_pass3(j));
         used = &sg;
       };
       switch (lanes_for(j + 1)) {

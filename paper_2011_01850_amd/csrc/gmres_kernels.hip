@@ -811,6 +811,45 @@ __device__ __forceinline__ int64_t seg_row(int t0, int nt, int u, int rev) {
   return (int64_t)tile * kTile + threadIdx.x;
 }
 
+// Segments of a pass without table reads where they are known: with one
+// system every segment is system 0's, and when its tiles cover every
+// workgroup (nseg = G) workgroup b holds exactly segment b, tiles
+// [b T / G, (b + 1) T / G).  Passes start with these instead of dependent
+// loads of the split tables (which the streamed basis evicts from L2
+// between launches), and test the single system's gate, loaded at the
+// kernel's start, instead of loading it per segment.
+__device__ __forceinline__ bool seg_direct(const KArgs& a, const SegTab& sg) {
+  return a.S == 1 && sg.nseg == sg.G;
+}
+__device__ __forceinline__ int seg_k0(const KArgs& a, const SegTab& sg, int b) {
+  return seg_direct(a, sg) ? b : sg.bseg0[b];
+}
+__device__ __forceinline__ int seg_k1(const KArgs& a, const SegTab& sg, int b) {
+  return seg_direct(a, sg) ? b + 1 : sg.bseg0[b + 1];
+}
+__device__ __forceinline__ int seg_sys(const KArgs& a, const SegTab& sg, int k) {
+  return a.S == 1 ? 0 : sg.seg_sys[k];
+}
+__device__ __forceinline__ void seg_tiles(const KArgs& a, const SegTab& sg, int k, int& t0, int& nt) {
+  if (seg_direct(a, sg)) {
+    t0 = (int)((int64_t)k * a.ntile / sg.G);
+    nt = (int)((int64_t)(k + 1) * a.ntile / sg.G) - t0;
+  } else {
+    t0 = sg.seg_t0[k];
+    nt = sg.seg_nt[k];
+  }
+}
+__device__ __forceinline__ int sys_seg0(const KArgs& a, const SegTab& sg, int s) {
+  return a.S == 1 ? 0 : sg.sys_sg0[s];
+}
+__device__ __forceinline__ int sys_nseg(const KArgs& a, const SegTab& sg, int s) {
+  return a.S == 1 ? sg.nseg : sg.sys_nsg[s];
+}
+// gate of system s, with on0 = gate0() for a single system
+__device__ __forceinline__ bool gated_s(const KArgs& a, int s, int on0) {
+  return a.S == 1 ? on0 != 0 : gated(a, s);
+}
+
 template <typename T>
 __device__ __forceinline__ const T* col_ptr(const KArgs& a, int i) {
   return reinterpret_cast<const T*>(a.V) + (int64_t)i * a.ld;
@@ -851,9 +890,11 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
   const TileRsrc rs = tile_rsrc<TV, L>(a, col0, ncol);
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
   uint32_t cs = cstride;
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    if (!gated(a, sg.seg_sys[k])) continue;
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    if (!gated_s(a, seg_sys(a, sg, k), on0)) continue;
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0, ww = (ACC)0;
     // narrow tiles move few bytes per load round: UT of them per iteration
@@ -906,13 +947,15 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
   const uint32_t cstride = (uint32_t)(a.ld * (int64_t)sizeof(TV));
   uint32_t cs = cstride;
   __shared__ ACC cf[L];
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    const int s = sg.seg_sys[k];
-    if (!gated(a, s)) continue;
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
     __syncthreads();
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
     ACC colsum = (ACC)0;
 #pragma unroll 1
@@ -959,11 +1002,13 @@ __global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, SegTab sg, int j, int 
   const int ncol = min(L, j + 1 - col0);
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* V0 = col_ptr<TV>(a, col0);
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    const int s = sg.seg_sys[k];
-    if (!gated(a, s)) continue;
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2) + col0;
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     for (int u = 0; u < nt; ++u) {
       const int64_t r = seg_row(t0, nt, u, 0);
       ACC wr = (ACC)w[r];
@@ -1001,13 +1046,15 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
   uint32_t cs = cstride;
   TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
   __shared__ ACC cf[L];
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    const int s = sg.seg_sys[k];
-    if (!gated(a, s)) continue;
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
     __syncthreads();
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride, kMallKeepLast);
     ACC sq = (ACC)0, mx = (ACC)0;
 #pragma unroll 1
@@ -1042,11 +1089,13 @@ __global__ __launch_bounds__(kBlock) void k_final(KArgs a, SegTab sg, int j) {
   const int b = pass_block(a, sg, 0);
   TW* w = reinterpret_cast<TW*>(a.w);
   TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    const int s = sg.seg_sys[k];
-    if (!gated(a, s)) continue;
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     ACC sq = (ACC)0, mx = (ACC)0;
     for (int u = 0; u < nt; ++u) {
       const int64_t r = seg_row(t0, nt, u, 0);
@@ -1075,7 +1124,7 @@ constexpr int kMgsOcc = 4;
 
 __device__ __forceinline__ double mgs_complete(const KArgs& a, const SegTab& sgp, int s, bool first,
                                                int i, const double* pin) {
-  const int g0 = sgp.sys_sg0[s], ng = sgp.sys_nsg[s];
+  const int g0 = sys_seg0(a, sgp, s), ng = sys_nseg(a, sgp, s);
   const int M1 = a.m + 1, M2 = a.m + 2;
   const double d = reduce_col<false>(pin + g0, ng);
   const double sci = a.sc[(int64_t)s * M1 + i];
@@ -1101,11 +1150,13 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* vi = col_ptr<TV>(a, i);
   const TV* vp = col_ptr<TV>(a, i > 0 ? i - 1 : 0);
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    const int s = sg.seg_sys[k];
-    if (!gated(a, s)) continue;
-    const ACC cprev = i > 0 ? (ACC)mgs_complete(a, sg, s, k == sg.sys_sg0[s], i - 1, pin) : (ACC)0;
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
+    const ACC cprev = i > 0 ? (ACC)mgs_complete(a, sg, s, k == sys_seg0(a, sg, s), i - 1, pin) : (ACC)0;
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     ACC d = (ACC)0, ww = (ACC)0;
     // kMgsUnroll tiles per iteration: all their loads are issued before use
     for (int u = 0; u < nt; u += kMgsUnroll) {
@@ -1153,11 +1204,13 @@ __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab
   TW* w = reinterpret_cast<TW*>(a.w);
   const TV* vj = col_ptr<TV>(a, j);
   TV* vout = reinterpret_cast<TV*>(a.V) + (int64_t)(j + 1) * a.ld;
-  for (int k = sg.bseg0[b]; k < sg.bseg0[b + 1]; ++k) {
-    const int s = sg.seg_sys[k];
-    if (!gated(a, s)) continue;
-    const ACC cj = (ACC)mgs_complete(a, sgp, s, k == sg.sys_sg0[s], j, pin);
-    const int t0 = sg.seg_t0[k], nt = sg.seg_nt[k];
+  const int on0 = gate0(a);
+  for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
+    const ACC cj = (ACC)mgs_complete(a, sgp, s, k == sys_seg0(a, sg, s), j, pin);
+    int t0, nt;
+    seg_tiles(a, sg, k, t0, nt);
     ACC sq = (ACC)0, mx = (ACC)0;
     for (int u = 0; u < nt; u += kMgsUnroll) {
       int64_t r[kMgsUnroll];
@@ -1330,8 +1383,8 @@ __global__ __launch_bounds__(kBlock) void k_fin_cols(KArgs a, SegTab sg, int j) 
   const int on0 = gate0(a);
   const double scq = a.sc[(int64_t)s * M1 + q];
   const double h1q = PASS == 2 ? a.h1[(int64_t)s * M2 + q] : 0.0;
-  const int g0 = a.S == 1 ? 0 : sg.sys_sg0[s];
-  const int ng = a.S == 1 ? sg.nseg : sg.sys_nsg[s];
+  const int g0 = sys_seg0(a, sg, s);
+  const int ng = sys_nseg(a, sg, s);
   const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + g0, ng);
   if (!gated_now(a, s, on0, ng) || threadIdx.x != 0) return;
   if (PASS == 1 && q == j + 1) {
@@ -1353,7 +1406,7 @@ __global__ __launch_bounds__(kBlock) void k_orth_cols(KArgs a, SegTab sg, int j)
   const int s = blockIdx.x, q = blockIdx.y;
   const SysState& S = a.st[s];
   if (!S.active && !S.force) return;
-  const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + sg.sys_sg0[s], sg.sys_nsg[s]);
+  const double v = reduce_col<false>(a.part + (int64_t)q * sg.nseg + sys_seg0(a, sg, s), sys_nseg(a, sg, s));
   if (threadIdx.x != 0) return;
   const int M1 = a.m + 1;
   a.ocol[(int64_t)s * M1 + q] = v * a.sc[(int64_t)s * M1 + q] * a.sc[(int64_t)s * M1 + j + 1];

@@ -41,20 +41,14 @@ sys.path.insert(0, ROOT)
 METRIC = "time to 1e-10 rel. residual: mixed/learned vs FP64 GMRES; HBM GB/s"
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the roofline kernel family, from two rocprofv3
-# counter runs of this script (FETCH_SIZE, then WRITE_SIZE, each scaled by
-# what it reads for a plain 1 GiB device copy: x2.0 and x1.0), averaged over
-# the family's launches that did work.  Valid only for the family they were
-# taken for (the kernel instantiation's name) and the kernel source they were
-# taken from.
 # HBM bytes per launch of the roofline kernel from two rocprofv3 counter
 # passes (FETCH_SIZE, WRITE_SIZE; the 585 launches that did work inside the
 # profiled solve of `--legs none --mgs-steps 0 --no-cpu --no-fp64 --steps 1
-# --warmup 0 --spmv-format sell --copy-probe`), each scaled by what the same
-# counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
-# once the kernel source changes
-TRAFFIC = {"kernel": "k_sell<float, float, float, 0>", "bytes_per_launch": 145172820,
-           "kernel_source_sha256": "d7ba16875a4bb4d93112ee7e96f827a817ffa70c8a8072eab3bc0d9580a00447"}
+# --warmup 0 --spmv-format sell16 --copy-probe`), each scaled by what the
+# same counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
+# void once the kernel source changes
+TRAFFIC = {"kernel": "k_sell<float, float, float, 0, true>", "bytes_per_launch": 115907232,
+           "kernel_source_sha256": "d22ce096b45a17eb9f79479484791413576452b56d92e400ee2c607c600be2dc"}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 
@@ -107,14 +101,14 @@ def parse():
     ap.add_argument("--c5-test", type=int, default=200, help="c5 leg: held-out instances")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a plain 1 GiB device copy (reference kernel for HBM byte counters)")
-    ap.add_argument("--spmv-format", default="auto", choices=["auto", "csr", "sell"],
+    ap.add_argument("--spmv-format", default="auto", choices=["auto", "csr", "sell", "sell16"],
                     help="Arnoldi SpMV format of the time-to-solution handles (auto: the autotuner's choice; "
                          "a fixed format keeps counter passes on one kernel)")
     ap.add_argument("--trace-summary", metavar="DIR",
                     help="no GPU: summarise the rocprofv3 CSV output in DIR (kernel trace and/or counter "
                          "collection) for the last --last dispatches of --kernel, i.e. the launches of the "
                          "profiled solve of a run with --legs none --mgs-steps 0")
-    ap.add_argument("--kernel", default="k_sell<float, float, float, 0>",
+    ap.add_argument("--kernel", default="k_sell<float, float, float, 0, true>",
                     help="--trace-summary: the kernel (template instantiation, without 'void gm::')")
     ap.add_argument("--last", type=int, default=650, help="--trace-summary: dispatches of the profiled solve")
     ap.add_argument("--floor-us", type=float, default=10.0,
@@ -244,14 +238,16 @@ def tile_width(j):
 
 def spmv_kernel(precision, spmv=None):
     """The Arnoldi SpMV's template instantiation for the handle's SpMV choice
-    (Solver.spmv_config(): the sliced ELL kernel or the CSR row blocks); the
-    matrix values are float64 only in the float64 solver."""
+    (Solver.spmv_config(): the sliced ELL kernel, with 32-bit columns or
+    16-bit column offsets, or the CSR row blocks); the matrix values are
+    float64 only in the float64 solver."""
     if not spmv:
         return FAMILY_KERNELS["spmv"]
     ta = "double" if precision == "fp64" else "float"
     ty = TYPES.get(precision, "?")
-    kern = "k_sell" if spmv["format"] == "sell" else "k_spmv"
-    return f"{kern}<{ta}, {ty}, 0>"
+    if spmv["format"] in ("sell", "sell16"):
+        return f"k_sell<{ta}, {ty}, 0, {'true' if spmv['format'] == 'sell16' else 'false'}>"
+    return f"k_spmv<{ta}, {ty}, 0>"
 
 
 def kernel_units(fam, m, precision, ortho, spmv=None):

@@ -192,10 +192,13 @@ typedef struct {
  * slice's longest row, plus a byte of length per row), built at create; only
  * when every row has fewer than 8 entries (then each row's sum is the plain
  * sum in storage order, so both layouts give the same bits) and split storage
- * is off, else CSR.  AUTO: SELL competes with the row-block budgets in the
- * autotuner (autotune = 1), else CSR.  The residual and preconditioner
- * products always use the row blocks. */
-enum { GMRES_SPMV_AUTO = 0, GMRES_SPMV_CSR = 1, GMRES_SPMV_SELL = 2 };
+ * is off, else CSR.  SELL16: the same copy with each column stored as a
+ * 16-bit offset from its row (2 bytes instead of 4) when every column of the
+ * matrix is within 32767 of its row, else as SELL.  AUTO: the sliced copy
+ * (16-bit offsets when they fit) competes with the row-block budgets in the
+ * autotuner (autotune = 1), else CSR.  All layouts give the same bits.  The
+ * residual and preconditioner products always use the row blocks. */
+enum { GMRES_SPMV_AUTO = 0, GMRES_SPMV_CSR = 1, GMRES_SPMV_SELL = 2, GMRES_SPMV_SELL16 = 3 };
 
 /* gmres_options.precond_side.  RIGHT: flexible GMRES, z_j = M^-1 v_j kept,
  * w = A z_j, x += Z y.  LEFT, the form of the paper's experiments
@@ -486,8 +489,8 @@ int gmres_launch_config(gmres_handle h, int32_t family, int32_t j, int32_t* grid
                         int32_t* per_cu, int64_t* basis_align);
 
 /* The Arnoldi SpMV the handle runs, as the autotuner (or the options) left
- * it, for the measurement report: *format = GMRES_SPMV_CSR or
- * GMRES_SPMV_SELL; *block_nnz = the nonzeros per CSR row block (also used by
+ * it, for the measurement report: *format = GMRES_SPMV_CSR, GMRES_SPMV_SELL
+ * or GMRES_SPMV_SELL16; *block_nnz = the nonzeros per CSR row block (also used by
  * the residual and preconditioner products); *xcd_remap = 1 when consecutive
  * workgroups are mapped onto one XCD.  Any output may be NULL.  ESTATE on the
  * persistent batch schedule. */

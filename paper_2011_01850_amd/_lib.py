@@ -28,8 +28,8 @@ ARNOLDI_A_DEFAULT, ARNOLDI_A_FP64, ARNOLDI_A_FP32 = 0, 1, 2
 ARNOLDI_AS = {"default": ARNOLDI_A_DEFAULT, "fp64": ARNOLDI_A_FP64, "fp32": ARNOLDI_A_FP32}
 PRECOND_NATIVE, PRECOND_FP32 = 0, 1
 PRECOND_PRECISIONS = {"native": PRECOND_NATIVE, "fp32": PRECOND_FP32}
-SPMV_AUTO, SPMV_CSR, SPMV_SELL = 0, 1, 2
-SPMV_FORMATS = {"auto": SPMV_AUTO, "csr": SPMV_CSR, "sell": SPMV_SELL}
+SPMV_AUTO, SPMV_CSR, SPMV_SELL, SPMV_SELL16 = 0, 1, 2, 3
+SPMV_FORMATS = {"auto": SPMV_AUTO, "csr": SPMV_CSR, "sell": SPMV_SELL, "sell16": SPMV_SELL16}
 PRECOND_RIGHT, PRECOND_LEFT = 0, 1
 PRECOND_SIDES = {"right": PRECOND_RIGHT, "left": PRECOND_LEFT}
 PSPMV_CSR8, PSPMV_CSR4, PSPMV_ELL16 = 0, 1, 2

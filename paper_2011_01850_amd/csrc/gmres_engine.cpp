@@ -81,6 +81,7 @@ struct gmres_ctx {
   spai_handle spai = nullptr;    // network instance on this handle's pattern (gmres_spai_infer)
   // persistent schedule: one workgroup per system, one launch per solve
   bool persistent = false;
+  bool near_cols = false;  // every column within 32767 of its row (16-bit sliced ELL offsets)
   std::vector<gmres_tune_class> tune;  // size classes and their probe systems
   double tune_probe_us[3] = {-1.0, -1.0, -1.0};  // probe time per SpMV variant
   int pv = 0;                          // the persistent kernel's SpMV variant
@@ -176,7 +177,7 @@ bool valid_options(const gmres_options* o) {
   if (o->precond_precision != GMRES_PRECOND_NATIVE && o->precond_precision != GMRES_PRECOND_FP32) return false;
   if (o->persistent_spmv < 0 || o->persistent_spmv > PV_COUNT) return false;
   if (o->precond_side != GMRES_PRECOND_RIGHT && o->precond_side != GMRES_PRECOND_LEFT) return false;
-  if (o->spmv_format < GMRES_SPMV_AUTO || o->spmv_format > GMRES_SPMV_SELL) return false;
+  if (o->spmv_format < GMRES_SPMV_AUTO || o->spmv_format > GMRES_SPMV_SELL16) return false;
   if (!(o->restart_improve >= 0.0)) return false;
   if (o->stall_cycles < 1) return false;
   if (o->batch_schedule < GMRES_SCHEDULE_AUTO || o->batch_schedule > GMRES_SCHEDULE_PERSISTENT) return false;
@@ -652,8 +653,9 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
 // Sliced ELL copy of the Arnoldi product's values, when every row has fewer
 // than 2 kRowLanePer entries (each row's canonical sum is then its plain sum
 // in storage order, which the sliced kernel keeps) and the padded copy fits
-// 32-bit offsets.  Returns false (nothing built) otherwise.
-bool build_sell(gmres_ctx* h) {
+// 32-bit offsets; its columns as 16-bit offsets from the row when d16.
+// Returns false (nothing built) otherwise.
+bool build_sell(gmres_ctx* h, bool d16) {
   KArgs& a = h->a;
   if (a.asplit || h->persistent) return false;
   std::vector<int32_t> off;
@@ -664,12 +666,14 @@ bool build_sell(gmres_ctx* h) {
   uint8_t* d_len = h->alloc<uint8_t>((size_t)h->ld);
   hip_check(hipMemcpyAsync(d_len, len.data(), (size_t)h->ld, hipMemcpyHostToDevice, h->stream));
   a.sell_len = d_len;
-  int32_t* col = h->alloc<int32_t>((size_t)total + 1);
+  int32_t* col = d16 ? nullptr : h->alloc<int32_t>((size_t)total + 1);
+  int16_t* dcol = d16 ? h->alloc<int16_t>((size_t)total + 1) : nullptr;
   void* val = a.arn64 ? (void*)h->alloc<double>((size_t)total + 1) : (void*)h->alloc<float>((size_t)total + 1);
   hip_check(launch_build_sell(a, a.arn64 ? (const void*)a.a64 : (const void*)a.a32, a.arn64 ? 0 : 1, val, col,
-                              h->stream));
+                              dcol, h->stream));
   a.sell_val = val;
   a.sell_col = col;
+  a.sell_dcol = dcol;
   hip_check(hipStreamSynchronize(h->stream));  // the host tables are freed on return
   return true;
 }
@@ -1015,7 +1019,8 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     int32_t hb = 0;
     hip_check(hipMemcpyAsync(&hb, bad, 4, hipMemcpyDeviceToHost, h->stream));
     hip_check(hipStreamSynchronize(h->stream));
-    if (hb) throw Fail{GMRES_EINVAL};
+    if (hb & 1) throw Fail{GMRES_EINVAL};
+    h->near_cols = (hb & 2) == 0;
   }
   set_row_blocks(h, tune ? 2048 : fixed_budget);
   hip_check(prepare_occupancy(prec));
@@ -1030,11 +1035,15 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     h->counter = h->alloc<int32_t>(1);
     setup_persistent_spmv(h, opt);
   } else {
-    // the sliced ELL copy: tuned against the row blocks, or forced
-    const bool sell = opt->spmv_format != GMRES_SPMV_CSR && (tune || opt->spmv_format == GMRES_SPMV_SELL) &&
-                      build_sell(h);
+    // the sliced ELL copy (16-bit column offsets when every column is near
+    // its row, unless 32-bit columns were asked for): tuned against the row
+    // blocks, or forced
+    const int fmt = opt->spmv_format;
+    const bool forced = fmt == GMRES_SPMV_SELL || fmt == GMRES_SPMV_SELL16;
+    const bool sell = fmt != GMRES_SPMV_CSR && (tune || forced) &&
+                      build_sell(h, h->near_cols && fmt != GMRES_SPMV_SELL);
     if (tune)
-      autotune_spmv(h, sell, sell && opt->spmv_format == GMRES_SPMV_SELL);
+      autotune_spmv(h, sell, sell && forced);
     else
       a.use_sell = sell ? 1 : 0;
   }
@@ -1745,7 +1754,8 @@ int gmres_spmv_config(gmres_handle hh, int32_t* format, int32_t* block_nnz, int3
   try {
     gmres_ctx* h = get(hh);
     if (h->persistent) return GMRES_ESTATE;
-    if (format) *format = h->a.use_sell ? GMRES_SPMV_SELL : GMRES_SPMV_CSR;
+    if (format)
+      *format = !h->a.use_sell ? GMRES_SPMV_CSR : h->a.sell_dcol ? GMRES_SPMV_SELL16 : GMRES_SPMV_SELL;
     if (block_nnz) *block_nnz = h->a.spmv_budget;
     if (xcd_remap) *xcd_remap = h->a.xcd_remap;
     return GMRES_OK;

@@ -118,7 +118,8 @@ struct KArgs {
   // plain sum in storage order) and the autotuner or the option picks it
   int32_t use_sell;
   const void* sell_val;     // float32 or float64 (the values the Arnoldi product reads)
-  const int32_t* sell_col;
+  const int32_t* sell_col;  // 32-bit columns, or
+  const int16_t* sell_dcol; //   16-bit offsets from the row (the other is null)
   const int32_t* sell_off;  // first entry of each slice [ld / 64 + 1]
   const uint8_t* sell_len;  // row lengths
   const int32_t* rb;       // row-block first rows [nrb + 1]
@@ -249,7 +250,8 @@ hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, floa
                              hipStream_t st);
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
 // The sliced ELL copy of A (values from `vals`, float32 when v32 else float64)
-hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, hipStream_t st);
+hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, int16_t* sd,
+                             hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st);
 hipError_t launch_encode_plain(int prec, int64_t n, const float* w, float f, void* out,

@@ -606,7 +606,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
 // rows all have fewer than 2 kRowLanePer entries: their canonical sum is the
 // plain sum of the rounded products in storage order, which this kernel
 // keeps (no fused multiply-add), so it gives the row-block kernel's bits.
-template <typename TA, typename TX, typename TY, int MODE>
+// D16: the columns are stored as 16-bit offsets from the row (column r + d),
+// half the index bytes, when every entry of the matrix is within 32767 of
+// its row (banded and stencil matrices).
+template <typename TA, typename TX, typename TY, int MODE, bool D16>
 __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__ vals, const TX* __restrict__ x,
                                                  TY* __restrict__ y, int j) {
 #pragma clang fp contract(off)
@@ -634,7 +637,10 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
     for (int e = 0; e < 8; ++e) {
       const int p = off + (kb + e) * 64 + lane;
       av[e] = kb + e < w ? (ACC)vals[p] : (ACC)0;
-      cv[e] = kb + e < w ? a.sell_col[p] : 0;
+      if constexpr (D16)
+        cv[e] = (int)r + (kb + e < w ? (int)a.sell_dcol[p] : 0);
+      else
+        cv[e] = kb + e < w ? a.sell_col[p] : 0;
     }
     // the gathers go out together (a pad entry's column is its own row)
     ACC xv[8];
@@ -651,8 +657,9 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
   y[r] = (TY)(acc * scale);
 }
 
+// (sc: 32-bit columns, or sd: 16-bit offsets from the row; the other is null)
 __global__ void k_build_sell(KArgs a, const void* __restrict__ vals, int v32, void* __restrict__ sv,
-                             int32_t* __restrict__ sc) {
+                             int32_t* __restrict__ sc, int16_t* __restrict__ sd) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
   const int slice = (int)(r >> 6), lane = (int)(r & 63);
@@ -664,7 +671,10 @@ __global__ void k_build_sell(KArgs a, const void* __restrict__ vals, int v32, vo
       static_cast<float*>(sv)[p] = k < len ? static_cast<const float*>(vals)[p0 + k] : 0.0f;
     else
       static_cast<double*>(sv)[p] = k < len ? static_cast<const double*>(vals)[p0 + k] : 0.0;
-    sc[p] = k < len ? a.ci[p0 + k] : (int32_t)r;
+    if (sd)
+      sd[p] = k < len ? (int16_t)(a.ci[p0 + k] - r) : (int16_t)0;
+    else
+      sc[p] = k < len ? a.ci[p0 + k] : (int32_t)r;
   }
 }
 
@@ -1798,18 +1808,23 @@ __global__ void k_set_force(KArgs a, int on) {
 }
 
 // flags a column index outside its row's own system
+// bit 0 of *bad: a column outside its system; bit 1: a column more than
+// 32767 away from its row (no 16-bit offset layout)
 __global__ void k_check_cols(KArgs a, int32_t* bad) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
   const int s = a.tile_sys[r / kTile];
   const int64_t lo = a.sys_row0[s], hi = lo + a.sys_n[s];
+  bool far = false;
   for (int k = a.rp[r]; k < a.rp[r + 1]; ++k) {
     const int64_t c = a.ci[k];
     if (c < lo || c >= hi) {
       atomicOr(bad, 1);
       return;
     }
+    far = far || c - r > 32767 || r - c > 32767;
   }
+  if (far) atomicOr(bad, 2);
 }
 
 __global__ void k_split_words(const double* __restrict__ src, uint32_t* __restrict__ hi,
@@ -2006,11 +2021,18 @@ static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStre
   if constexpr (MODE == SM_ARNOLDI || MODE == SM_AZ) {
     if (a.use_sell) {
       const unsigned grid = (unsigned)(a.ld / kBlock);  // one block per 256-row tile (4 slices)
-      if (a.arn64)
-        hipLaunchKernelGGL((k_sell<double, TX, TY, MODE>), dim3(grid), dim3(kBlock), 0, st, a,
+      const bool d16 = a.sell_dcol != nullptr;
+      if (a.arn64 && d16)
+        hipLaunchKernelGGL((k_sell<double, TX, TY, MODE, true>), dim3(grid), dim3(kBlock), 0, st, a,
                            static_cast<const double*>(a.sell_val), x, y, j);
+      else if (a.arn64)
+        hipLaunchKernelGGL((k_sell<double, TX, TY, MODE, false>), dim3(grid), dim3(kBlock), 0, st, a,
+                           static_cast<const double*>(a.sell_val), x, y, j);
+      else if (d16)
+        hipLaunchKernelGGL((k_sell<float, TX, TY, MODE, true>), dim3(grid), dim3(kBlock), 0, st, a,
+                           static_cast<const float*>(a.sell_val), x, y, j);
       else
-        hipLaunchKernelGGL((k_sell<float, TX, TY, MODE>), dim3(grid), dim3(kBlock), 0, st, a,
+        hipLaunchKernelGGL((k_sell<float, TX, TY, MODE, false>), dim3(grid), dim3(kBlock), 0, st, a,
                            static_cast<const float*>(a.sell_val), x, y, j);
       return hipGetLastError();
     }
@@ -2633,8 +2655,10 @@ hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, h
   return hipGetLastError();
 }
 
-hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_build_sell, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, vals, v32, sv, sc);
+hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, int16_t* sd,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_build_sell, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, vals, v32, sv, sc,
+                     sd);
   return hipGetLastError();
 }
 

@@ -65,7 +65,7 @@ def test_invalid_arguments_rejected_before_device_work(lib):
                        ("restart_on_stall", -1), ("orth_restart", -1.0), ("orth_restart", float("inf")),
                        ("orth_norm", 2), ("ilu_sweeps", -1), ("ilu_sweeps", 4097),
                        ("arnoldi_a", 3), ("arnoldi_a", -1), ("persistent_spmv", -1), ("persistent_spmv", 4), ("precond_side", 2),
-                       ("precond_side", -1), ("spmv_format", 3), ("spmv_format", -1)]:
+                       ("precond_side", -1), ("spmv_format", 4), ("spmv_format", -1)]:
         ob = L.default_options()
         setattr(ob, field, bad)
         assert lib.gmres_create(C.byref(h), 10, 5, 1, 1, 1, C.byref(ob), None) == L.EINVAL, field

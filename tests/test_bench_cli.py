@@ -41,8 +41,10 @@ def test_tile_widths_follow_the_column():
     assert bench.kernel_units("pass2", 50, "fp64", "cgsr")[0][0].startswith("k_axpy_mdot64<double, double")
     assert bench.kernel_units("final", 40, "fp32", "mgs") == [("k_mgs_final<float, float>", list(range(40)))]
     sell = {"format": "sell", "block_nnz": 2048, "xcd_remap": True}
-    assert bench.kernel_units("spmv", 50, "fp32", "cgsr", sell) == [("k_sell<float, float, float, 0>",
+    assert bench.kernel_units("spmv", 50, "fp32", "cgsr", sell) == [("k_sell<float, float, float, 0, false>",
                                                                      list(range(50)))]
+    sell16 = dict(sell, format="sell16")
+    assert bench.kernel_units("spmv", 50, "fp32", "cgsr", sell16)[0][0] == "k_sell<float, float, float, 0, true>"
     csr = dict(sell, format="csr")
     assert bench.kernel_units("spmv", 50, "fp64", "cgsr", csr)[0][0] == "k_spmv<double, double, double, 0>"
     assert bench.kernel_units("spmv", 50, "limited", "cgsr", csr)[0][0] == "k_spmv<float, float, double, 0>"

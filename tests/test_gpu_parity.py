@@ -1035,26 +1035,56 @@ def test_sliced_ell_gives_the_row_block_bits(precision, ortho):
                         ("varcoef12", P.varcoef3d(12, family=94, index=4), "jacobi")]:
         xt, b = P.manufactured_rhs(A, 95, 0)
         out = {}
-        for fmt in ("csr", "sell"):
+        for fmt in ("csr", "sell", "sell16"):
             s = _solver(A, m=20, ortho=ortho, precision=precision, precond=pc, tol=1e-12, spmv_format=fmt,
                         autotune=False)
+            assert s.spmv_config()["format"] == fmt  # every column is within 32767 of its row
             x, info = s.solve(b)
             cfg = s.launch_config("spmv", 0)
             s.close()
             out[fmt] = (x.cpu().numpy(), info["iters"], cfg["grid"])
-        assert out["sell"][2] == -(-A.n // 256)  # one workgroup per 256-row tile
-        assert out["sell"][1] == out["csr"][1], name
-        assert np.array_equal(out["sell"][0], out["csr"][0]), name
+        for fmt in ("sell", "sell16"):
+            assert out[fmt][2] == -(-A.n // 256)  # one workgroup per 256-row tile
+            assert out[fmt][1] == out["csr"][1], (name, fmt)
+            assert np.array_equal(out[fmt][0], out["csr"][0]), (name, fmt)
 
 
 def test_forced_spmv_format_survives_the_autotuner():
     # the autotuner still times row-block budgets (the residual's product),
     # but a format asked for is the format the Arnoldi product runs
     A = P.convdiff(24, (50.0, 20.0, 10.0))
-    for fmt in ("sell", "csr"):
+    for fmt in ("sell", "sell16", "csr"):
         s = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format=fmt, autotune=True)
         assert s.spmv_config()["format"] == fmt
         s.close()
+    # the tuner's sliced candidate uses 16-bit offsets where they fit
+    s = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format="auto", autotune=True)
+    assert s.spmv_config()["format"] in ("sell16", "csr")
+    s.close()
+
+
+def test_sliced_ell_offsets_fall_back_to_32_bit_columns():
+    # one entry 39,999 columns from its row: no 16-bit offsets; "sell16" then
+    # builds the 32-bit copy, and every layout still gives the same bits
+    n = 40000
+    main = np.full(n, 4.0)
+    rows = np.concatenate([np.arange(n), np.arange(1, n), np.arange(n - 1), [0]])
+    cols = np.concatenate([np.arange(n), np.arange(n - 1), np.arange(1, n), [n - 1]])
+    vals = np.concatenate([main, np.full(n - 1, -1.0), np.full(n - 1, -1.5), [0.25]])
+    import scipy.sparse as sp
+    M = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    M.sort_indices()
+    A = P.CSR(n, M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64), {})
+    xt, b = P.manufactured_rhs(A, 95, 2)
+    out = {}
+    for fmt in ("csr", "sell", "sell16"):
+        s = _solver(A, m=20, precision="fp32", tol=1e-12, spmv_format=fmt, autotune=False)
+        out[fmt] = (s.spmv_config()["format"],) + tuple(s.solve(b))
+        s.close()
+    assert out["sell16"][0] == "sell" and out["sell"][0] == "sell" and out["csr"][0] == "csr"
+    for fmt in ("sell", "sell16"):
+        assert out[fmt][2]["iters"] == out["csr"][2]["iters"]
+        assert torch.equal(out[fmt][1], out["csr"][1])
     s = _solver(A, m=20, precision="fp32", tol=1e-10, spmv_format="auto", autotune=True)
     assert s.spmv_config()["format"] in ("sell", "csr")
     s.close()

@@ -356,6 +356,10 @@ def roofline_from_profile(solver, fam, m, reps, precision="fp32", ortho="cgsr", 
         "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": (round(traffic) if traffic else None),
         "traffic_over_alg": (round(traffic / per_launch, 4) if traffic else None),
+        # the measured bytes over the same launch time (the physical rate; a
+        # layout that moves fewer bytes than the algorithmic count shows here)
+        "traffic_GBps": (round(traffic / (dom["avg_launch_ms"] * 1e-3) / 1e9, 1) if traffic else None),
+        "traffic_frac": (round(traffic / (dom["avg_launch_ms"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if traffic else None),
         "avg_launch_ms": round(dom["avg_launch_ms"], 5),
         "alg_bytes_per_launch": round(per_launch),
         "launches": (f"{dom['active_launches']} launches that did work inside one solve, columns j = "

@@ -83,3 +83,15 @@ def test_roofline_picks_the_dominant_kernel():
     assert abs(rf["achieved"] - 600 * 2.7e8 / 28.5e-3 / 1e9) < 0.5 and rf["avg_launch_ms"] == round(28.5 / per, 5)
     assert abs(rf["frac"] - rf["achieved"] / 8000.0) < 1e-4
     assert "reduce" in rf["in_solve_families"] and rf["harness_back_to_back"]["j"] == 49
+    # no counter record for this kernel: no traffic, and no rate from it
+    assert rf["traffic"] is None and rf["traffic_GBps"] is None and rf["traffic_frac"] is None
+    # with one (the record of the roofline kernel it names), the measured rate
+    # is the measured bytes over the same launch time
+    original = bench.measured_traffic
+    try:
+        bench.measured_traffic = lambda k: 2.0e8 if k == "k_mdot<float, float, 64>" else None
+        rf = bench.roofline_from_profile(FakeSolver(), fam, 50, 3, harness=harness)
+        assert abs(rf["traffic_GBps"] - 2.0e8 / (rf["avg_launch_ms"] * 1e-3) / 1e9) < 0.1
+        assert abs(rf["traffic_frac"] - rf["traffic_GBps"] / 8000.0) < 1e-4
+    finally:
+        bench.measured_traffic = original

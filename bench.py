@@ -41,24 +41,34 @@ sys.path.insert(0, ROOT)
 METRIC = "time to 1e-10 rel. residual: mixed/learned vs FP64 GMRES; HBM GB/s"
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the roofline kernel from two rocprofv3 counter
-# passes (FETCH_SIZE, WRITE_SIZE; the 585 launches that did work inside the
+# HBM bytes per launch of the kernels that can be the roofline kernel (the
+# instantiations with the most in-solve time on the 128^3 workload; which one
+# leads varies from run to run), from two rocprofv3 counter passes
+# (FETCH_SIZE, WRITE_SIZE) over the launches that did work inside the
 # profiled solve of `--legs none --mgs-steps 0 --no-cpu --no-fp64 --steps 1
-# --warmup 0 --spmv-format sell16 --copy-probe`), each scaled by what the
-# same counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0);
-# void once the kernel source changes
-TRAFFIC = {"kernel": "k_sell<float, float, float, 0, true>", "bytes_per_launch": 115907232,
-           "kernel_source_sha256": "d22ce096b45a17eb9f79479484791413576452b56d92e400ee2c607c600be2dc"}
+# --warmup 0 --spmv-format sell16 --copy-probe`, each scaled by what the same
+# counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
+# once the kernel source changes
+TRAFFIC = {
+    "kernel_source_sha256": "62903cbd9aed72c6e8f8b012c2d259ed18b7537b30634aa40baa3262ef8abfd2",
+    "bytes_per_launch": {
+        "k_axpy_mdot<float, float, 64>": 364459809,
+        "k_mdot<float, float, 64>": 356080582,
+        "k_final_tile<float, float, 64>": 364089310,
+        "k_sell<float, float, float, 0, true>": 107667888,
+    },
+}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
 
 
 def measured_traffic(kernel):
-    if TRAFFIC["bytes_per_launch"] is None or TRAFFIC["kernel"] != kernel:
+    b = TRAFFIC["bytes_per_launch"].get(kernel)
+    if b is None:
         return None
     with open(KERNEL_SOURCE, "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["kernel_source_sha256"]:
             return None  # the kernels changed since the counters were taken
-    return TRAFFIC["bytes_per_launch"]
+    return b
 
 
 def parse():

@@ -608,7 +608,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
 // keeps (no fused multiply-add), so it gives the row-block kernel's bits.
 // D16: the columns are stored as 16-bit offsets from the row (column r + d),
 // half the index bytes, when every entry of the matrix is within 32767 of
-// its row (banded and stencil matrices).
+// its row (banded and stencil matrices).  Such a block then stages the part
+// of x around its own rows, [r0 - kSellHalo, r0 + 256 + kSellHalo), in LDS
+// with coalesced loads and reads the entries that fall in it from there
+// (a stencil's near neighbours: one global gather each otherwise); only the
+// far entries are gathered from memory.  The values summed are the same.
+constexpr int kSellHalo = 128;
 template <typename TA, typename TX, typename TY, int MODE, bool D16>
 __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__ vals, const TX* __restrict__ x,
                                                  TY* __restrict__ y, int j) {
@@ -629,29 +634,57 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
   ACC scale = (ACC)1;
   if (MODE == SM_ARNOLDI) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
   if (!gated_now(a, s, on0, off)) return;
-  ACC acc = (ACC)0;
-  for (int kb = 0; kb < w; kb += 8) {
-    ACC av[8];
-    int cv[8];
+  constexpr int kWin = D16 ? kBlock + 2 * kSellHalo : 1;
+  __shared__ TX xw[kWin];
+  const int64_t r0 = (int64_t)blk * kBlock;  // the block's first row
+  // a slice is at most 7 entries wide (the copy is built only for rows of
+  // fewer than 8), so one group of 8 covers it (entries past w are masked)
+  static_assert(2 * kRowLanePer == 8, "one group of 8 entries per row");
+  ACC av[8];
+  int cv[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int p = off + e * 64 + lane;
+    av[e] = e < w ? (ACC)vals[p] : (ACC)0;
+    if constexpr (D16)
+      cv[e] = e < w ? (int)a.sell_dcol[p] : 0;  // offset from the row
+    else
+      cv[e] = e < w ? a.sell_col[p] : 0;
+  }
+  // the gathers go out together (a pad entry's column is its own row)
+  ACC xv[8];
+  if constexpr (D16) {
+    // rows [r0 - halo, r0 + 256 + halo) of x, zero outside [0, ld)
+    TX xl[kWin / kBlock];
+#pragma unroll
+    for (int q = 0; q < kWin / kBlock; ++q) {
+      const int64_t c = r0 - kSellHalo + q * kBlock + threadIdx.x;
+      xl[q] = (c >= 0 && c < a.ld) ? x[c] : TX{};
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int p = off + (kb + e) * 64 + lane;
-      av[e] = kb + e < w ? (ACC)vals[p] : (ACC)0;
-      if constexpr (D16)
-        cv[e] = (int)r + (kb + e < w ? (int)a.sell_dcol[p] : 0);
-      else
-        cv[e] = kb + e < w ? a.sell_col[p] : 0;
+      const int d = cv[e];
+      if (d < -kSellHalo || d > kSellHalo) xv[e] = (ACC)ldv(x[(int)r + d]);
     }
-    // the gathers go out together (a pad entry's column is its own row)
-    ACC xv[8];
+#pragma unroll
+    for (int q = 0; q < kWin / kBlock; ++q) xw[q * kBlock + threadIdx.x] = xl[q];
+    __syncthreads();
+    const int base = (int)(r - r0) + kSellHalo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int d = cv[e];
+      if (d >= -kSellHalo && d <= kSellHalo) xv[e] = (ACC)ldv(xw[base + d]);
+    }
+  } else {
 #pragma unroll
     for (int e = 0; e < 8; ++e) xv[e] = (ACC)ldv(x[cv[e]]);
+  }
+  ACC acc = (ACC)0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (kb + e < len) {
-        const ACC prod = av[e] * xv[e];
-        acc = acc + prod;
-      }
+  for (int e = 0; e < 8; ++e) {
+    if (e < len) {
+      const ACC prod = av[e] * xv[e];
+      acc = acc + prod;
     }
   }
   y[r] = (TY)(acc * scale);

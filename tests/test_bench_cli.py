@@ -1,5 +1,6 @@
 """bench.py's command line on a host without a GPU: the single-GPU contract
 and the record fields that do not need a device."""
+import hashlib
 import json
 import os
 import subprocess
@@ -20,13 +21,15 @@ def test_traffic_record_is_tied_to_the_kernel_source():
     import bench
 
     t = bench.TRAFFIC
-    assert set(t) == {"kernel", "bytes_per_launch", "kernel_source_sha256"}
-    assert t["bytes_per_launch"] is None or t["bytes_per_launch"] > 0
-    # the lookup returns the stored bytes only for the kernel and the source they were measured on
-    got = bench.measured_traffic(t["kernel"] or "k_mdot<float, float, 64>")
-    assert got is None or got == t["bytes_per_launch"]
+    assert set(t) == {"bytes_per_launch", "kernel_source_sha256"}
+    assert all(b > 0 for b in t["bytes_per_launch"].values())
+    # the lookup returns the stored bytes only for a kernel measured on this source
+    with open(bench.KERNEL_SOURCE, "rb") as f:
+        current = hashlib.sha256(f.read()).hexdigest() == t["kernel_source_sha256"]
+    for k, b in t["bytes_per_launch"].items():
+        assert bench.measured_traffic(k) == (b if current else None)
     assert bench.measured_traffic("no such kernel") is None
-    json.dumps({"traffic": got})
+    json.dumps({"traffic": bench.measured_traffic("k_mdot<float, float, 64>")})
 
 
 def test_tile_widths_follow_the_column():
@@ -83,14 +86,16 @@ def test_roofline_picks_the_dominant_kernel():
     assert abs(rf["achieved"] - 600 * 2.7e8 / 28.5e-3 / 1e9) < 0.5 and rf["avg_launch_ms"] == round(28.5 / per, 5)
     assert abs(rf["frac"] - rf["achieved"] / 8000.0) < 1e-4
     assert "reduce" in rf["in_solve_families"] and rf["harness_back_to_back"]["j"] == 49
-    # no counter record for this kernel: no traffic, and no rate from it
-    assert rf["traffic"] is None and rf["traffic_GBps"] is None and rf["traffic_frac"] is None
-    # with one (the record of the roofline kernel it names), the measured rate
-    # is the measured bytes over the same launch time
     original = bench.measured_traffic
     try:
+        # no counter record for this kernel: no traffic, and no rate from it
+        bench.measured_traffic = lambda k: None
+        rf = bench.roofline_from_profile(FakeSolver(), fam, 50, 3, harness=harness)
+        assert rf["traffic"] is None and rf["traffic_GBps"] is None and rf["traffic_frac"] is None
+        # with one, the measured rate is the measured bytes over the same launch time
         bench.measured_traffic = lambda k: 2.0e8 if k == "k_mdot<float, float, 64>" else None
         rf = bench.roofline_from_profile(FakeSolver(), fam, 50, 3, harness=harness)
+        assert rf["traffic"] == 2.0e8 and abs(rf["traffic_over_alg"] - 2.0e8 / (600 * 2.7e8 / per)) < 1e-3
         assert abs(rf["traffic_GBps"] - 2.0e8 / (rf["avg_launch_ms"] * 1e-3) / 1e9) < 0.1
         assert abs(rf["traffic_frac"] - rf["traffic_GBps"] / 8000.0) < 1e-4
     finally:

@@ -82,6 +82,7 @@ struct gmres_ctx {
   // persistent schedule: one workgroup per system, one launch per solve
   bool persistent = false;
   bool near_cols = false;  // every column within 32767 of its row (16-bit sliced ELL offsets)
+  int64_t part_rows = 0;   // rows of the partial tables a.part, a.part2
   std::vector<gmres_tune_class> tune;  // size classes and their probe systems
   double tune_probe_us[3] = {-1.0, -1.0, -1.0};  // probe time per SpMV variant
   int pv = 0;                          // the persistent kernel's SpMV variant
@@ -678,59 +679,95 @@ bool build_sell(gmres_ctx* h, bool d16) {
   return true;
 }
 
+// Partial tables (two, for the passes that alternate) with a row for every
+// segment of any persistent split and every row block of any budget built so
+// far; reallocated (before any graph is captured) when a new budget needs
+// more rows.
+void ensure_partials(gmres_ctx* h) {
+  KArgs& a = h->a;
+  int64_t rows = h->ntile;
+  for (const auto& t : h->rbt) rows = std::max<int64_t>(rows, (int64_t)t->sys.size());
+  for (int k = 1; k <= kMaxOcc; ++k) rows = std::max<int64_t>(rows, a.seg[k - 1].nseg);
+  if (rows <= h->part_rows) return;
+  a.part = h->alloc<double>((size_t)rows * a.ps);
+  a.part2 = h->alloc<double>((size_t)rows * a.ps);
+  h->part_rows = rows;
+}
+
 // Times the Arnoldi SpMV for a few row-block budgets, each with and without
 // the XCD block mapping (and the sliced ELL copy when there is one), and
 // keeps the fastest (of the sliced ELL candidates only, when that format was
 // asked for).  Every candidate runs between its own pair of events and the
-// host waits once, at the end.  The row blocks stay set to the fastest budget
-// for the other products (residual, preconditioner) either way.
+// host waits once per round.  With a sliced copy the first round times it
+// against the middle budget only; the other budgets are built and timed only
+// if the copy is not clearly faster (kSellMargin).  The row blocks stay set
+// to the fastest budget timed for the other products (residual,
+// preconditioner) either way.
+constexpr float kSellMargin = 0.85f;
+
 void autotune_spmv(gmres_ctx* h, bool sell, bool sell_only) {
   struct Cand {
     int budget, remap, sell;
+    float ms;
   };
   std::vector<Cand> cands;
+  auto time_round = [&](size_t first) {
+    for (size_t i = first; i < cands.size(); ++i) set_row_blocks(h, cands[i].budget);  // tables uploaded first
+    while (h->tune_ev.size() < 2 * cands.size()) {
+      hipEvent_t e;
+      hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+      h->tune_ev.push_back(e);
+    }
+    // exercise with a column of the zero-initialised basis; force the kernel on
+    hip_check(launch_set_force(h->a, 1, h->stream));
+    constexpr int reps = 3;
+    for (size_t i = first; i < cands.size(); ++i) {
+      const Cand& c = cands[i];
+      set_row_blocks(h, c.budget);
+      h->a.xcd_remap = c.remap;
+      h->a.use_sell = c.sell;
+      hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));  // warm
+      hip_check(hipEventRecord(h->tune_ev[2 * i], h->stream));
+      for (int r = 0; r < reps; ++r) hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));
+      hip_check(hipEventRecord(h->tune_ev[2 * i + 1], h->stream));
+    }
+    hip_check(launch_set_force(h->a, 0, h->stream));
+    hip_check(hipEventSynchronize(h->tune_ev[2 * cands.size() - 1]));
+    for (size_t i = first; i < cands.size(); ++i)
+      hip_check(hipEventElapsedTime(&cands[i].ms, h->tune_ev[2 * i], h->tune_ev[2 * i + 1]));
+  };
+  auto best_of = [&](int want_sell) {  // -1: any
+    size_t bi = cands.size();
+    for (size_t i = 0; i < cands.size(); ++i)
+      if ((want_sell < 0 || cands[i].sell == want_sell) && (bi == cands.size() || cands[i].ms < cands[bi].ms))
+        bi = i;
+    return bi;
+  };
+  constexpr int kMid = 2048;
   for (int budget : kTuneBudgets)
-    for (int remap = 0; remap <= 1; ++remap) cands.push_back({budget, remap, 0});
+    if (!sell || budget == kMid)
+      for (int remap = 0; remap <= 1; ++remap) cands.push_back({budget, remap, 0, 0.f});
   if (sell)
-    for (int remap = 0; remap <= 1; ++remap) cands.push_back({kTuneBudgets[0], remap, 1});
-  for (int budget : kTuneBudgets) set_row_blocks(h, budget);  // tables uploaded before the first launch
-  while (h->tune_ev.size() < 2 * cands.size()) {
-    hipEvent_t e;
-    hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
-    h->tune_ev.push_back(e);
+    for (int remap = 0; remap <= 1; ++remap) cands.push_back({kMid, remap, 1, 0.f});
+  time_round(0);
+  if (sell && !(cands[best_of(1)].ms < kSellMargin * cands[best_of(0)].ms)) {
+    // the copy does not win clearly: the other budgets too
+    const size_t first = cands.size();
+    std::vector<int> more;
+    for (int budget : kTuneBudgets)
+      if (budget != kMid) {
+        more.push_back(budget);
+        for (int remap = 0; remap <= 1; ++remap) cands.push_back({budget, remap, 0, 0.f});
+      }
+    prepare_row_blocks(h, more);
+    ensure_partials(h);
+    time_round(first);
   }
-  // exercise with a column of the zero-initialised basis; force the kernel on
-  hip_check(launch_set_force(h->a, 1, h->stream));
-  constexpr int reps = 3;
-  for (size_t i = 0; i < cands.size(); ++i) {
-    const Cand& c = cands[i];
-    set_row_blocks(h, c.budget);
-    h->a.xcd_remap = c.remap;
-    h->a.use_sell = c.sell;
-    hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));  // warm
-    hip_check(hipEventRecord(h->tune_ev[2 * i], h->stream));
-    for (int r = 0; r < reps; ++r) hip_check(launch_spmv_arnoldi(h->a, 0, h->stream));
-    hip_check(hipEventRecord(h->tune_ev[2 * i + 1], h->stream));
-  }
-  hip_check(launch_set_force(h->a, 0, h->stream));
-  hip_check(hipEventSynchronize(h->tune_ev[2 * cands.size() - 1]));
-  float best = 1e30f, best_csr = 1e30f;
-  size_t bi = 0, bc = 0;
-  for (size_t i = 0; i < cands.size(); ++i) {
-    float ms = 0.f;
-    hip_check(hipEventElapsedTime(&ms, h->tune_ev[2 * i], h->tune_ev[2 * i + 1]));
-    if (!cands[i].sell && ms < best_csr) {
-      best_csr = ms;
-      bc = i;
-    }
-    if (ms < best && (cands[i].sell || !sell_only)) {
-      best = ms;
-      bi = i;
-    }
-  }
-  set_row_blocks(h, cands[bc].budget);
-  h->a.xcd_remap = cands[bi].remap;
-  h->a.use_sell = cands[bi].sell;
+  const Cand& bc = cands[best_of(0)];
+  const Cand& bi = cands[best_of(sell_only ? 1 : -1)];
+  set_row_blocks(h, bc.budget);
+  h->a.xcd_remap = bi.remap;
+  h->a.use_sell = bi.sell;
   hip_check(hipStreamSynchronize(h->stream));
 }
 
@@ -994,24 +1031,6 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     a.mval = d;
   }
   if (opt->precond == GMRES_PRECOND_ILU0) setup_ilu0(h, opt->ilu_sweeps);
-  // ---- SpMV row blocks of every budget this handle may use (the autotuner's
-  // candidates, else the fixed one), built in parallel on the host
-  const bool tune = !h->persistent && opt->autotune && opt->spmv_block_nnz == 0;
-  const int fixed_budget = opt->spmv_block_nnz > 0 ? opt->spmv_block_nnz : 2048;
-  const std::vector<int> budgets = tune ? std::vector<int>(std::begin(kTuneBudgets), std::end(kTuneBudgets))
-                                        : std::vector<int>{fixed_budget};
-  prepare_row_blocks(h, budgets);
-  // ---- partials sized for the largest grid any of those budgets gives
-  {
-    int64_t maxrows = h->ntile;
-    for (int b : budgets) maxrows = std::max<int64_t>(maxrows, (int64_t)row_blocks(h, b).sys.size());
-    for (int k = 1; k <= kMaxOcc; ++k) {
-      a.seg[k - 1] = make_split(h, (int)std::min<int64_t>((int64_t)k * a.ncu, h->ntile));
-      maxrows = std::max<int64_t>(maxrows, a.seg[k - 1].nseg);
-    }
-    a.part = h->alloc<double>((size_t)maxrows * a.ps);
-    a.part2 = h->alloc<double>((size_t)maxrows * a.ps);
-  }
   {
     int32_t* bad = h->alloc<int32_t>(1);
     hip_check(hipMemsetAsync(bad, 0, 4, h->stream));
@@ -1022,7 +1041,24 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     if (hb & 1) throw Fail{GMRES_EINVAL};
     h->near_cols = (hb & 2) == 0;
   }
-  set_row_blocks(h, tune ? 2048 : fixed_budget);
+  const bool tune = !h->persistent && opt->autotune && opt->spmv_block_nnz == 0;
+  const int fixed_budget = opt->spmv_block_nnz > 0 ? opt->spmv_block_nnz : 2048;
+  // the sliced ELL copy (16-bit column offsets when every column is near its
+  // row, unless 32-bit columns were asked for): tuned against the row
+  // blocks, or forced
+  const int fmt = opt->spmv_format;
+  const bool forced_sell = fmt == GMRES_SPMV_SELL || fmt == GMRES_SPMV_SELL16;
+  const bool sell = !h->persistent && fmt != GMRES_SPMV_CSR && (tune || forced_sell) &&
+                    build_sell(h, h->near_cols && fmt != GMRES_SPMV_SELL);
+  // ---- SpMV row blocks, built in parallel on the host: the fixed budget;
+  // for the autotuner every candidate budget, or only the middle one first
+  // when a sliced copy competes (the others are built if it does not win)
+  std::vector<int> budgets{fixed_budget};
+  if (tune && !sell) budgets.assign(std::begin(kTuneBudgets), std::end(kTuneBudgets));
+  prepare_row_blocks(h, budgets);
+  for (int k = 1; k <= kMaxOcc; ++k) a.seg[k - 1] = make_split(h, (int)std::min<int64_t>((int64_t)k * a.ncu, h->ntile));
+  ensure_partials(h);
+  set_row_blocks(h, fixed_budget);
   hip_check(prepare_occupancy(prec));
   hip_check(launch_init_state(a, h->stream));
   if (h->persistent) {
@@ -1034,18 +1070,10 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     hip_check(hipMemcpy(h->order, ord.data(), nsys * 4, hipMemcpyHostToDevice));
     h->counter = h->alloc<int32_t>(1);
     setup_persistent_spmv(h, opt);
+  } else if (tune) {
+    autotune_spmv(h, sell, sell && forced_sell);
   } else {
-    // the sliced ELL copy (16-bit column offsets when every column is near
-    // its row, unless 32-bit columns were asked for): tuned against the row
-    // blocks, or forced
-    const int fmt = opt->spmv_format;
-    const bool forced = fmt == GMRES_SPMV_SELL || fmt == GMRES_SPMV_SELL16;
-    const bool sell = fmt != GMRES_SPMV_CSR && (tune || forced) &&
-                      build_sell(h, h->near_cols && fmt != GMRES_SPMV_SELL);
-    if (tune)
-      autotune_spmv(h, sell, sell && forced);
-    else
-      a.use_sell = sell ? 1 : 0;
+    a.use_sell = sell ? 1 : 0;
   }
   h->xs = h->alloc<double>(h->ld);
   h->ys = h->alloc<double>(h->ld);

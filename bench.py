@@ -50,12 +50,12 @@ PEAK_HBM_GBS = 8000.0
 # counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
 # once the kernel source changes
 TRAFFIC = {
-    "kernel_source_sha256": "62903cbd9aed72c6e8f8b012c2d259ed18b7537b30634aa40baa3262ef8abfd2",
+    "kernel_source_sha256": "5f8a04ba7210680bf872a1c70e20335804f371d4d0e63b46d11737abdf282b0d",
     "bytes_per_launch": {
-        "k_axpy_mdot<float, float, 64>": 364459809,
-        "k_mdot<float, float, 64>": 356080582,
-        "k_final_tile<float, float, 64>": 364089310,
-        "k_sell<float, float, float, 0, true>": 107667888,
+        "k_axpy_mdot<float, float, 64>": 365526464,
+        "k_mdot<float, float, 64>": 357176884,
+        "k_final_tile<float, float, 64>": 364140366,
+        "k_sell<float, float, float, 0, true>": 107665816,
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")

@@ -298,7 +298,7 @@ void fill_row_blocks(const gmres_ctx* h, RowBlocks& t) {
   for (size_t k = 0; k < h->sys.size(); ++k) {
     const System& s = h->sys[k];
     const size_t before = t.rb.size();
-    constexpr int64_t kChunk = 1 << 19;
+    constexpr int64_t kChunk = 1 << 18;
     if (s.n <= kChunk) {
       plan::build_row_blocks(h->rp_host.data(), s.row0, s.row0 + s.n, t.budget, t.rb, &t.lanes);
     } else {
@@ -306,7 +306,7 @@ void fill_row_blocks(const gmres_ctx* h, RowBlocks& t) {
       // two chunks; any blocking gives the same sums)
       const int64_t nc = (s.n + kChunk - 1) / kChunk;
       std::vector<std::vector<int32_t>> rbs(nc), lns(nc);
-      parallel_for(nc, 4, [&](int64_t c) {
+      parallel_for(nc, 8, [&](int64_t c) {
         plan::build_row_blocks(h->rp_host.data(), s.row0 + c * kChunk,
                                s.row0 + std::min<int64_t>(s.n, (c + 1) * kChunk), t.budget, rbs[c], &lns[c]);
       });
@@ -659,19 +659,24 @@ void setup_persistent_spmv(gmres_ctx* h, const gmres_options* opt) {
 bool build_sell(gmres_ctx* h, bool d16) {
   KArgs& a = h->a;
   if (a.asplit || h->persistent) return false;
-  std::vector<int32_t> off;
-  std::vector<uint8_t> len;
-  if (!plan::sell_layout(h->rp_host.data(), h->ld, off, len)) return false;
+  // slice widths on host threads, the offsets from them; the row lengths are
+  // written on the device by the build kernel
+  const int64_t nslice = h->ld / 64;
+  std::vector<int32_t> wid(nslice), off;
+  constexpr int64_t kPiece = 1 << 12;  // slices per task
+  parallel_for((nslice + kPiece - 1) / kPiece, nslice >= 8 * kPiece ? 8 : 1, [&](int64_t p) {
+    plan::sell_widths(h->rp_host.data(), p * kPiece, std::min<int64_t>(nslice, (p + 1) * kPiece), wid.data());
+  });
+  if (!plan::sell_offsets(wid.data(), nslice, off)) return false;
   const int64_t total = off.back();
   a.sell_off = upload32(h, off);
   uint8_t* d_len = h->alloc<uint8_t>((size_t)h->ld);
-  hip_check(hipMemcpyAsync(d_len, len.data(), (size_t)h->ld, hipMemcpyHostToDevice, h->stream));
   a.sell_len = d_len;
   int32_t* col = d16 ? nullptr : h->alloc<int32_t>((size_t)total + 1);
   int16_t* dcol = d16 ? h->alloc<int16_t>((size_t)total + 1) : nullptr;
   void* val = a.arn64 ? (void*)h->alloc<double>((size_t)total + 1) : (void*)h->alloc<float>((size_t)total + 1);
   hip_check(launch_build_sell(a, a.arn64 ? (const void*)a.a64 : (const void*)a.a32, a.arn64 ? 0 : 1, val, col,
-                              dcol, h->stream));
+                              dcol, d_len, h->stream));
   a.sell_val = val;
   a.sell_col = col;
   a.sell_dcol = dcol;

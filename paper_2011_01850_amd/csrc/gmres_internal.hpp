@@ -251,7 +251,7 @@ hipError_t launch_ilu_finish(const KArgs& a, const double* lu, float* lu32, floa
 hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, hipStream_t st);
 // The sliced ELL copy of A (values from `vals`, float32 when v32 else float64)
 hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, int16_t* sd,
-                             hipStream_t st);
+                             uint8_t* sl, hipStream_t st);
 hipError_t launch_residual_plain(const KArgs& a, const double* b, const double* x, double* r,
                                  hipStream_t st);
 hipError_t launch_encode_plain(int prec, int64_t n, const float* w, float f, void* out,

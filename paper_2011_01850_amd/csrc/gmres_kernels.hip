@@ -690,14 +690,16 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
   y[r] = (TY)(acc * scale);
 }
 
-// (sc: 32-bit columns, or sd: 16-bit offsets from the row; the other is null)
+// (sc: 32-bit columns, or sd: 16-bit offsets from the row; the other is
+// null.  sl: each row's length.)
 __global__ void k_build_sell(KArgs a, const void* __restrict__ vals, int v32, void* __restrict__ sv,
-                             int32_t* __restrict__ sc, int16_t* __restrict__ sd) {
+                             int32_t* __restrict__ sc, int16_t* __restrict__ sd, uint8_t* __restrict__ sl) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= a.ld) return;
   const int slice = (int)(r >> 6), lane = (int)(r & 63);
   const int off = a.sell_off[slice], w = (a.sell_off[slice + 1] - off) >> 6;
   const int p0 = a.rp[r], len = a.rp[r + 1] - p0;
+  sl[r] = (uint8_t)len;
   for (int k = 0; k < w; ++k) {
     const int p = off + k * 64 + lane;
     if (v32)
@@ -2689,9 +2691,9 @@ hipError_t launch_spmv_plain(const KArgs& a, int prec, const void* x, void* y, h
 }
 
 hipError_t launch_build_sell(const KArgs& a, const void* vals, int v32, void* sv, int32_t* sc, int16_t* sd,
-                             hipStream_t st) {
+                             uint8_t* sl, hipStream_t st) {
   hipLaunchKernelGGL(k_build_sell, dim3((unsigned)((a.ld + 255) / 256)), dim3(256), 0, st, a, vals, v32, sv, sc,
-                     sd);
+                     sd, sl);
   return hipGetLastError();
 }
 

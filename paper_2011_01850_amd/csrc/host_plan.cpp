@@ -109,19 +109,32 @@ int ilu_plan(const int32_t* rp, const int32_t* ci, int64_t ld, IluPlan& out) {
   return ILU_OK;
 }
 
-bool sell_layout(const int32_t* rp, int64_t ld, std::vector<int32_t>& off, std::vector<uint8_t>& len) {
-  const int64_t nslice = ld / 64;
+void sell_widths(const int32_t* rp, int64_t s0, int64_t s1, int32_t* w) {
+  for (int64_t sl = s0; sl < s1; ++sl) {
+    int m = 0;
+    for (int64_t r = sl * 64; r < sl * 64 + 64; ++r) m = std::max(m, rp[r + 1] - rp[r]);
+    w[sl] = m;
+  }
+}
+
+bool sell_offsets(const int32_t* w, int64_t nslice, std::vector<int32_t>& off) {
   off.assign(nslice + 1, 0);
   int64_t total = 0;
   for (int64_t sl = 0; sl < nslice; ++sl) {
-    int w = 0;
-    for (int64_t r = sl * 64; r < sl * 64 + 64; ++r) w = std::max(w, rp[r + 1] - rp[r]);
-    if (w >= 2 * kRowLanePer) return false;
+    if (w[sl] >= 2 * kRowLanePer) return false;
     off[sl] = (int32_t)total;
-    total += (int64_t)w * 64;
+    total += (int64_t)w[sl] * 64;
     if (total >= (int64_t)INT32_MAX) return false;
   }
   off[nslice] = (int32_t)total;
+  return true;
+}
+
+bool sell_layout(const int32_t* rp, int64_t ld, std::vector<int32_t>& off, std::vector<uint8_t>& len) {
+  const int64_t nslice = ld / 64;
+  std::vector<int32_t> w(nslice);
+  sell_widths(rp, 0, nslice, w.data());
+  if (!sell_offsets(w.data(), nslice, off)) return false;
   len.resize(ld);
   for (int64_t r = 0; r < ld; ++r) len[r] = (uint8_t)(rp[r + 1] - rp[r]);
   return true;

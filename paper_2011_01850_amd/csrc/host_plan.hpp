@@ -91,6 +91,11 @@ int ilu_plan(const int32_t* rp, const int32_t* ci, int64_t ld, IluPlan& out);
 // unspecified) when a row has 2 kRowLanePer entries or more (its canonical
 // sum would not be its plain sum) or the padded copy reaches 2^31 entries.
 bool sell_layout(const int32_t* rp, int64_t ld, std::vector<int32_t>& off, std::vector<uint8_t>& len);
+// The same in two steps, for callers that split the rows: the widths of
+// slices [s0, s1) into w[s0 .. s1), then the offsets from all nslice widths
+// (false when a width reaches 2 kRowLanePer or the total 2^31).
+void sell_widths(const int32_t* rp, int64_t s0, int64_t s1, int32_t* w);
+bool sell_offsets(const int32_t* w, int64_t nslice, std::vector<int32_t>& off);
 
 // Rows per thread of a system of n rows in the persistent batch kernel
 // (1024 threads): the smallest power of two that covers n, at most kMaxPR.

@@ -295,6 +295,17 @@ void check_sell(Rng& g) {
       }
       CHECK(off[s + 1] - off[s] == 64 * w, "slice %lld width", (long long)s);
     }
+    // the two-step form over random pieces of slices gives the same offsets
+    {
+      const int64_t nslice = ld / 64;
+      std::vector<int32_t> wid(nslice, -1), off2;
+      for (int64_t s0 = 0; s0 < nslice;) {
+        const int64_t s1 = std::min<int64_t>(nslice, s0 + g.uniform(1, 9));
+        plan::sell_widths(rp.data(), s0, s1, wid.data());
+        s0 = s1;
+      }
+      CHECK(plan::sell_offsets(wid.data(), nslice, off2) && off2 == off, "piecewise offsets");
+    }
     if (ld > 0) {
       const int64_t r = g.uniform(0, ld - 1);
       for (int64_t q = r + 1; q <= ld; ++q) rp[q] += 2 * kRowLanePer - (rp[r + 1] - rp[r]) + (int32_t)g.uniform(0, 3);

@@ -50,12 +50,12 @@ PEAK_HBM_GBS = 8000.0
 # counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
 # once the kernel source changes
 TRAFFIC = {
-    "kernel_source_sha256": "5f8a04ba7210680bf872a1c70e20335804f371d4d0e63b46d11737abdf282b0d",
+    "kernel_source_sha256": "6ec416240159aa69bea8a76731b2740053424b7abe9818ed967afbda57a378e1",
     "bytes_per_launch": {
-        "k_axpy_mdot<float, float, 64>": 365526464,
-        "k_mdot<float, float, 64>": 357176884,
-        "k_final_tile<float, float, 64>": 364140366,
-        "k_sell<float, float, float, 0, true>": 107665816,
+        "k_axpy_mdot<float, float, 64>": 365529406,
+        "k_mdot<float, float, 64>": 357167583,
+        "k_final_tile<float, float, 64>": 364140137,
+        "k_sell<float, float, float, 0, true>": 107665790,
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")

@@ -112,6 +112,18 @@ __device__ __forceinline__ float stw<float>(double v) { return (float)v; }
 
 // ------------------------------------------------------------ block helpers
 
+// Stores of the streamed vectors (w, the new basis column, the product's
+// output) carry the non-temporal hint: the next kernel reads them from the
+// memory-side cache either way, and lines not left dirty in L2 make each
+// kernel's end (which writes L2 back) shorter.  2-byte types store plainly.
+template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) {
+  if constexpr (sizeof(T) == 2)
+    *p = v;
+  else
+    __builtin_nontemporal_store(v, p);
+}
+
 __device__ __forceinline__ int remap_block(int b, int G, int on) {
   // consecutive logical blocks on one XCD: dispatch is round-robin over 8 XCDs
   if (!on) return b;
@@ -500,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
       y[r] = (TY)z;
       if (MODE == SM_RESID) a.zres[r] = z;
     } else {
-      y[r] = (TY)(acc * scale);
+      st_nt(&y[r], (TY)(acc * scale));
     }
   };
   if (p1 - p0 > a.spmv_budget) {  // one long row: staged chunk by chunk, lanes 0..T-1 of wave 0 add
@@ -687,7 +699,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
       acc = acc + prod;
     }
   }
-  y[r] = (TY)(acc * scale);
+  st_nt(&y[r], (TY)(acc * scale));
 }
 
 // (sc: 32-bit columns, or sd: 16-bit offsets from the row; the other is
@@ -1016,7 +1028,7 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
       ACC wr = (ACC)w[r];
 #pragma unroll
       for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
-      w[r] = (TW)wr;
+      st_nt(&w[r], (TW)wr);
 #pragma unroll
       for (int q = 0; q < L; ++q) v[q] *= wr;
       colsum += reduce_scatter<L>(v, lane);
@@ -1058,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy(KArgs a, SegTab sg, int j, int 
       const int64_t r = seg_row(t0, nt, u, 0);
       ACC wr = (ACC)w[r];
       for (int q = 0; q < ncol; ++q) wr -= (ACC)coefd[q] * (ACC)ldv(V0[(int64_t)q * a.ld + r]);
-      w[r] = (TW)wr;
+      st_nt(&w[r], (TW)wr);
     }
   }
 }
@@ -1118,9 +1130,9 @@ __global__ __launch_bounds__(kBlock) void k_final_tile(KArgs a, SegTab sg, int j
       sq += wr * wr;
       mx = fmax(mx, fabs(wr));
       if constexpr (kTwoByte)
-        w[r] = (TW)wr;
+        st_nt(&w[r], (TW)wr);
       else
-        vout[r] = (TV)wr;
+        st_nt(&vout[r], (TV)wr);
     }
     store_norm_partials(a.part, sg.nseg, k, sq, mx);
   }
@@ -1149,9 +1161,9 @@ __global__ __launch_bounds__(kBlock) void k_final(KArgs a, SegTab sg, int j) {
       sq += wr * wr;
       mx = fmax(mx, fabs(wr));
       if constexpr (kTwoByte)
-        w[r] = (TW)wr;
+        st_nt(&w[r], (TW)wr);
       else
-        vout[r] = (TV)wr;
+        st_nt(&vout[r], (TV)wr);
     }
     store_norm_partials(a.part, sg.nseg, k, sq, mx);
   }
@@ -1220,7 +1232,7 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
         ACC wr = wv[q];
         if (i > 0) {
           wr -= cprev * pv[q];
-          w[r[q]] = (TW)wr;
+          st_nt(&w[r[q]], (TW)wr);
         } else {
           ww += wr * wr;
         }
@@ -1273,9 +1285,9 @@ __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab
         sq += wr * wr;
         mx = fmax(mx, fabs(wr));
         if constexpr (kTwoByte)
-          w[r[q]] = (TW)wr;
+          st_nt(&w[r[q]], (TW)wr);
         else
-          vout[r[q]] = (TV)wr;
+          st_nt(&vout[r[q]], (TV)wr);
       }
     }
     store_norm_partials(pout, sg.nseg, k, sq, mx);

@@ -1049,6 +1049,24 @@ def test_sliced_ell_gives_the_row_block_bits(precision, ortho):
             assert np.array_equal(out[fmt][0], out["csr"][0]), (name, fmt)
 
 
+def test_sliced_ell_window_edges_give_the_row_block_bits():
+    # 2-D stencils whose far neighbours sit exactly at the LDS window's edge
+    # (offset 128: read from LDS) and one past it (129: gathered from memory),
+    # over many tiles (the window clipped at both ends of x): the same solve
+    # bit for bit as the row blocks
+    for N in (128, 129):
+        A = P.convdiff(N, (20.0, 10.0))
+        xt, b = P.manufactured_rhs(A, 95, 3)
+        out = {}
+        for fmt in ("csr", "sell16"):
+            s = _solver(A, m=30, precision="fp32", tol=1e-11, spmv_format=fmt, autotune=False)
+            assert s.spmv_config()["format"] == fmt
+            out[fmt] = s.solve(b)
+            s.close()
+        assert out["sell16"][1]["iters"] == out["csr"][1]["iters"], N
+        assert torch.equal(out["sell16"][0], out["csr"][0]), N
+
+
 def test_forced_spmv_format_survives_the_autotuner():
     # the autotuner still times row-block budgets (the residual's product),
     # but a format asked for is the format the Arnoldi product runs

@@ -50,12 +50,12 @@ PEAK_HBM_GBS = 8000.0
 # counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
 # once the kernel source changes
 TRAFFIC = {
-    "kernel_source_sha256": "6ec416240159aa69bea8a76731b2740053424b7abe9818ed967afbda57a378e1",
+    "kernel_source_sha256": "676f263a22ec8ea9ce52fcdcf8d23381d10df79b18656f22b526ec79d146be4e",
     "bytes_per_launch": {
-        "k_axpy_mdot<float, float, 64>": 365529406,
-        "k_mdot<float, float, 64>": 357167583,
-        "k_final_tile<float, float, 64>": 364140137,
-        "k_sell<float, float, float, 0, true>": 107665790,
+        "k_axpy_mdot_ds<float, float, 64>": 365527707,
+        "k_mdot_ds<float, float, 64>": 357170679,
+        "k_final_tile<float, float, 64>": 364140129,
+        "k_sell<float, float, float, 0, true>": 107726658,
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")
@@ -222,8 +222,8 @@ def time_to_solution(torch, Solver, A_dev, b_dev, n, m, ortho, precision, steps,
 # kernel families of the in-solve profile and the kernels each one launches
 FAMILY_KERNELS = {
     "spmv": "k_spmv (Arnoldi SpMV w = A v_j, adaptive CSR row blocks)",
-    "pass1": "k_mdot (CGS projection 1: V^T w)",
-    "pass2": "k_axpy_mdot (CGS projection 2 fused: w -= V h1, then V^T w)",
+    "pass1": "k_mdot (CGS projection 1: V^T w; k_mdot_ds also scales w by v_j's decode scale)",
+    "pass2": "k_axpy_mdot (CGS projection 2 fused: w -= V h1, then V^T w; the _ds variant as pass 1)",
     "final": "k_final_tile / k_mgs_final (last pass: w -= V h2 or the last MGS axpy, ||w||, v_{j+1})",
     "mgs": "k_mgs (MGS step: completes dot i-1, w -= h v_{i-1}, partial w . v_i)",
     "residual": "k_spmv RESID (float64 restart residual z = b - A x)",
@@ -268,6 +268,10 @@ def kernel_units(fam, m, precision, ortho, spmv=None):
     if fam in ("pass1", "pass2") or (fam == "final" and ortho == "cgsr"):
         base = {"pass1": "k_mdot", "pass2": "k_axpy_mdot64" if precision in ("fp64", "limited") else "k_axpy_mdot",
                 "final": "k_final_tile"}[fam]
+        # with the finaliser merged into the product, the first two
+        # projections apply the decode scale of v_j (the _ds kernels)
+        if fam != "final" and spmv and spmv.get("fin_merged"):
+            base += "_ds"
         units = {}
         for j in range(m):
             units.setdefault(tile_width(j), []).append(j)

@@ -141,7 +141,8 @@ _SIGS = {
                                        C.POINTER(KernelProfile)]),
     "gmres_launch_config": (C.c_int, [_vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
-    "gmres_spmv_config": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gmres_spmv_config": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32)]),
     "gmres_spai_infer": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "spai_create": (C.c_int, [C.POINTER(_vp), C.c_int64, C.c_int64, _vp, _vp, C.c_int32, _vp]),
     "spai_set_values": (C.c_int, [_vp, _vp]),

@@ -414,15 +414,17 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
   hipError_t e = launch_residual(a, st);
   if (e == hipSuccess) e = launch_left_start(a, st);  // left preconditioning: r = M^-1 z, beta = ||r||
   if (e == hipSuccess) e = launch_encode(a, 0, st);
+  const bool ride = a.wsc_defer != 0;  // step j's finaliser launched with product j + 1
   for (int j = 0; j < a.m && e == hipSuccess; ++j) {
     if (a.precond != 0 && !a.left) e = launch_precond(a, j, st);
-    if (e == hipSuccess) e = launch_spmv_arnoldi(a, j, st);
+    if (e == hipSuccess && !(ride && j > 0)) e = launch_spmv_arnoldi(a, j, st);
     if (e == hipSuccess) e = launch_left_apply(a, st);  // w = M^-1 A v_j
     if (e != hipSuccess) break;
     if (h->opt.ortho == GMRES_CGSR) {
       e = launch_cgs_pass1(a, j, st);
       if (e == hipSuccess) e = launch_cgs_pass2(a, j, st);
-      if (e == hipSuccess) e = launch_final_pass(a, j, st);
+      if (e == hipSuccess) e = launch_final_pass(a, j, st, !ride);
+      if (e == hipSuccess && ride) e = j + 1 < a.m ? launch_spmv_fin(a, j, st) : launch_finalize_final(a, j, st);
     } else {
       for (int i = 0; i <= j && e == hipSuccess; ++i) e = launch_mgs_dot(a, j, i, st);
       if (e == hipSuccess) e = launch_final_pass(a, j, st);
@@ -473,6 +475,7 @@ void enqueue_cycle_profiled(gmres_ctx* h, hipStream_t st, ProfPool& pool, std::v
   const bool two = a.prec == PBF16 || a.prec == PF16;
   const double n = (double)h->nrows, nnz = (double)h->nnz;
   const double sv = (double)vbytes(a.prec), sw = (double)wbytes(a.prec), sa = a.arn64 ? 8.0 : 4.0;
+  const bool ride = a.wsc_defer != 0;
   auto timed = [&](int kind, int j, double bytes, auto&& launch) {
     ProfRec r{kind, j, bytes, pool.get(), pool.get()};
     hip_check(hipEventRecord(r.e0, st));
@@ -494,8 +497,8 @@ void enqueue_cycle_profiled(gmres_ctx* h, hipStream_t st, ProfPool& pool, std::v
       timed(GMRES_PK_PRECOND, j, pb, [&] { return launch_precond(a, j, st); });
     }
     const double sx = a.precond != 0 && !a.left ? (a.z64 ? 8.0 : 4.0) : sv;
-    timed(GMRES_PK_SPMV, j, nnz * (sa + 4.0) + 4.0 * (n + 1) + n * sx + n * sw,
-          [&] { return launch_spmv_arnoldi(a, j, st); });
+    const double spmv_bytes = nnz * (sa + 4.0) + 4.0 * (n + 1) + n * sx + n * sw;
+    if (!(ride && j > 0)) timed(GMRES_PK_SPMV, j, spmv_bytes, [&] { return launch_spmv_arnoldi(a, j, st); });
     if (a.left && a.precond != 0) timed(GMRES_PK_PRECOND, j, 0.0, [&] { return launch_left_apply(a, st); });
     if (h->opt.ortho == GMRES_CGSR) {
       const double win = std::ceil(ncol / 64.0);
@@ -512,7 +515,10 @@ void enqueue_cycle_profiled(gmres_ctx* h, hipStream_t st, ProfPool& pool, std::v
     timed(GMRES_PK_FINAL, j,
           (h->opt.ortho == GMRES_CGSR ? ncol * n * sv : n * sv) + n * sw + n * (two ? sw : sv),
           [&] { return launch_final_pass(a, j, st, false); });
-    timed(GMRES_PK_REDUCE, j, 0.0, [&] { return launch_finalize_final(a, j, st); });
+    if (ride && j + 1 < a.m)  // this finaliser runs beside product j + 1 (counted as that product)
+      timed(GMRES_PK_SPMV, j + 1, spmv_bytes, [&] { return launch_spmv_fin(a, j, st); });
+    else
+      timed(GMRES_PK_REDUCE, j, 0.0, [&] { return launch_finalize_final(a, j, st); });
     if (two && j + 1 <= a.m) timed(GMRES_PK_ENCODE, j, n * sw + n * sv, [&] { return launch_encode(a, j + 1, st); });
     if (a.orth_restart > 0.0) timed(GMRES_PK_ENCODE, j, 0.0, [&] { return launch_orth_check(a, j, st); });
   }
@@ -1080,6 +1086,14 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
   } else {
     a.use_sell = sell ? 1 : 0;
   }
+  // the finaliser of each step rides on the next step's sliced product
+  // (CGSR over register tiles, no preconditioner, a 4- or 8-byte basis, no
+  // orthogonality monitor); the product then leaves v_j's scale to the
+  // projections, which round the scaled w exactly as the product would
+  // have (not so for a float64 product into a float32 w: left out)
+  a.wsc_defer = !h->persistent && a.use_sell && opt->ortho == GMRES_CGSR && opt->precond == GMRES_PRECOND_NONE &&
+                (prec == P32 || prec == P64 || prec == PL32) && !(prec == P32 && a.arn64) && m <= 64 &&
+                opt->orth_restart <= 0.0;
   h->xs = h->alloc<double>(h->ld);
   h->ys = h->alloc<double>(h->ld);
   hip_check(hipStreamSynchronize(h->stream));
@@ -1783,7 +1797,8 @@ int gmres_launch_config(gmres_handle hh, int32_t family, int32_t j, int32_t* gri
   }
 }
 
-int gmres_spmv_config(gmres_handle hh, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap) {
+int gmres_spmv_config(gmres_handle hh, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap,
+                      int32_t* fin_merged) {
   try {
     gmres_ctx* h = get(hh);
     if (h->persistent) return GMRES_ESTATE;
@@ -1791,6 +1806,7 @@ int gmres_spmv_config(gmres_handle hh, int32_t* format, int32_t* block_nnz, int3
       *format = !h->a.use_sell ? GMRES_SPMV_CSR : h->a.sell_dcol ? GMRES_SPMV_SELL16 : GMRES_SPMV_SELL;
     if (block_nnz) *block_nnz = h->a.spmv_budget;
     if (xcd_remap) *xcd_remap = h->a.xcd_remap;
+    if (fin_merged) *fin_merged = h->a.wsc_defer;
     return GMRES_OK;
   } catch (const Fail& f) {
     return f.code;

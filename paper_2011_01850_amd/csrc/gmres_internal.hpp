@@ -117,6 +117,9 @@ struct KArgs {
   // row has fewer than 2 kRowLanePer entries (so its canonical sum is the
   // plain sum in storage order) and the autotuner or the option picks it
   int32_t use_sell;
+  int32_t wsc_defer;        // the Arnoldi product stores A v_j unscaled; projections 1 and 2 apply
+                            // v_j's decode scale as they load w (the product then runs beside the
+                            // finaliser of step j - 1, which computes that scale)
   const void* sell_val;     // float32 or float64 (the values the Arnoldi product reads)
   const int32_t* sell_col;  // 32-bit columns, or
   const int16_t* sell_dcol; //   16-bit offsets from the row (the other is null)
@@ -202,6 +205,9 @@ hipError_t launch_encode(const KArgs& a, int col, hipStream_t st);       // stor
 hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
 hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
 hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fin = true);
+// the finaliser of step j_fin and the Arnoldi product of column j_fin + 1 in
+// one launch (sliced ELL product, wsc_defer set)
+hipError_t launch_spmv_fin(const KArgs& a, int j_fin, hipStream_t st);
 hipError_t launch_mgs_dot(const KArgs& a, int j, int i, hipStream_t st);
 // Loss-of-orthogonality monitor after step j: column j+1 of U and S, the
 // norm of S, and the end of the cycle when it reaches the threshold.

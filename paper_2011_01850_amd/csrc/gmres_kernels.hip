@@ -102,6 +102,16 @@ __device__ __forceinline__ float mul_rn(float a, float b) {
   asm volatile("" : "+v"(t));
   return t;
 }
+// A product that is never fused into a following add (its multiply carries
+// no contraction flag; no scheduling fence either).
+__device__ __forceinline__ float mul_nofuse(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ __forceinline__ double mul_nofuse(double a, double b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
 
 template <typename T>
 __device__ __forceinline__ T stw(double v);
@@ -626,12 +636,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv(KArgs a, const TA* __restrict__
 // (a stencil's near neighbours: one global gather each otherwise); only the
 // far entries are gathered from memory.  The values summed are the same.
 constexpr int kSellHalo = 128;
+
+// The per-step finaliser of step j, run by the first n blocks of a sliced
+// product launch (n = 0: none; else a multiple of 8, so the product's blocks
+// keep their XCD placement): block s < S finalises system s.
+struct FinArgs {
+  int n = 0, j = -1;
+  const double* src = nullptr;
+  int rows = 0;
+  const int32_t* r0 = nullptr;
+  const int32_t* nr = nullptr;
+};
+__device__ void fin_step_block(const KArgs& a, const double* src, int rows, const int32_t* r0, const int32_t* nr,
+                               int j, int s);
+
 template <typename TA, typename TX, typename TY, int MODE, bool D16>
 __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__ vals, const TX* __restrict__ x,
-                                                 TY* __restrict__ y, int j) {
+                                                 TY* __restrict__ y, int j, FinArgs fa) {
 #pragma clang fp contract(off)
   using ACC = AccFor<TA, TY>;
-  const int blk = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  if ((int)blockIdx.x < fa.n) {
+    if ((int)blockIdx.x < a.S) fin_step_block(a, fa.src, fa.rows, fa.r0, fa.nr, fa.j, blockIdx.x);
+    return;
+  }
+  const int blk = remap_block(blockIdx.x - fa.n, gridDim.x - fa.n, a.xcd_remap);
   const int lane = threadIdx.x & 63;
   const int slice = blk * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t r = (int64_t)slice * 64 + lane;
@@ -644,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_sell(KArgs a, const TA* __restrict__
   const int w = (a.sell_off[slice + 1] - off) >> 6;
   const int len = a.sell_len[r];
   ACC scale = (ACC)1;
-  if (MODE == SM_ARNOLDI) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
+  if (MODE == SM_ARNOLDI && !a.wsc_defer) scale = (ACC)a.sc[(int64_t)s * (a.m + 1) + j];
   if (!gated_now(a, s, on0, off)) return;
   constexpr int kWin = D16 ? kBlock + 2 * kSellHalo : 1;
   __shared__ TX xw[kWin];
@@ -936,8 +964,11 @@ __device__ __forceinline__ void store_colsums(double* part, int nrows, int k, in
 // and mode = 1.  mode 2: the second projection's dots when j + 1 > 64.
 // mode 3: the loss-of-orthogonality monitor's dots, with basis column j + 1
 // (as stored, before its decode scale) in place of w.
-template <typename TV, typename TW, int L>
-__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int col0, int mode, int rev) {
+//
+// DS (the k_mdot_ds variant, 4- and 8-byte bases): projection 1 also applies
+// v_j's decode scale to w, which the Arnoldi product left out (wsc_defer).
+template <typename TV, typename TW, int L, bool DS>
+__device__ __forceinline__ void mdot_body(const KArgs& a, const SegTab& sg, int j, int col0, int mode, int rev) {
   using ACC = AccFor<TV, TW>;
   const int b = pass_block(a, sg, rev);
   const int lane = threadIdx.x & 63;
@@ -949,7 +980,12 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
   uint32_t cs = cstride;
   const int on0 = gate0(a);
   for (int k = seg_k0(a, sg, b), k1 = seg_k1(a, sg, b); k < k1; ++k) {
-    if (!gated_s(a, seg_sys(a, sg, k), on0)) continue;
+    const int s = seg_sys(a, sg, k);
+    if (!gated_s(a, s, on0)) continue;
+    // projection 1 applies v_j's decode scale to w when the product left it
+    // out: the product's own rounding, kept apart from the sums that follow
+    const bool defer = DS && mode == 1;
+    const ACC wsc = defer ? (ACC)a.sc[(int64_t)s * (a.m + 1) + j] : (ACC)1;
     int t0, nt;
     seg_tiles(a, sg, k, t0, nt);
     const int nfirst = nt_tiles<TV>(nt, (uint64_t)ncol * (uint64_t)cstride);
@@ -969,6 +1005,7 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
         const int64_t r = seg_row(t0, nt, uu, rev);
         const uint32_t voff = (uint32_t)(r * (int64_t)sizeof(TV));
         wr[h] = mode == 3 ? (ACC)ldv(wv[r]) : (ACC)w[r];
+        if (defer) wr[h] = mul_nofuse(wr[h], wsc);
         if (sizeof(TV) != 2 && uu < nfirst)
           load_tile<TV, L, true>(p[h], rs, voff, cs);
         else
@@ -990,10 +1027,20 @@ __global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int 
     }
   }
 }
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_mdot(KArgs a, SegTab sg, int j, int col0, int mode, int rev) {
+  mdot_body<TV, TW, L, false>(a, sg, j, col0, mode, rev);
+}
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_mdot_ds(KArgs a, SegTab sg, int j, int col0, int mode, int rev) {
+  mdot_body<TV, TW, L, true>(a, sg, j, col0, mode, rev);
+}
 
 // CGSR projection 2, fused: w' = w - V coef (coef from projection 1), then
-// V^T w' from the same register tile of V.  Requires j + 1 <= L <= 64.
-template <typename TV, typename TW, int L>
+// V^T w' from the same register tile of V.  Requires j + 1 <= L <= 64.  DS
+// (the _ds kernels): w is first scaled by v_j's decode scale, as in
+// projection 1.
+template <typename TV, typename TW, int L, bool DS>
 __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg, int j, int rev) {
   using ACC = AccFor<TV, TW>;
   const int b = pass_block(a, sg, rev);
@@ -1010,6 +1057,8 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
     if (!gated_s(a, s, on0)) continue;
     const double* coefd = a.coef + (int64_t)s * (a.m + 2);
     if (t < L) cf[t] = (t < ncol) ? (ACC)coefd[t] : (ACC)0;
+    // (the decode scale of v_j, when the product left it out of w)
+    const ACC wsc = DS ? (ACC)a.sc[(int64_t)s * (a.m + 1) + j] : (ACC)1;
     __syncthreads();
     int t0, nt;
     seg_tiles(a, sg, k, t0, nt);
@@ -1026,6 +1075,7 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
       else
         load_tile<TV, L, false>(v, rs, voff, cs);
       ACC wr = (ACC)w[r];
+      if (DS) wr = mul_nofuse(wr, wsc);  // (the product's rounding, as above)
 #pragma unroll
       for (int q = 0; q < L; ++q) wr -= cf[q] * v[q];
       st_nt(&w[r], (TW)wr);
@@ -1043,11 +1093,20 @@ __device__ __forceinline__ void axpy_mdot_body(const KArgs& a, const SegTab& sg,
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_axpy_mdot(KArgs a, SegTab sg, int j, int rev) {
-  axpy_mdot_body<TV, TW, L>(a, sg, j, rev);
+  axpy_mdot_body<TV, TW, L, false>(a, sg, j, rev);
+}
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_axpy_mdot_ds(KArgs a, SegTab sg, int j, int rev) {
+  axpy_mdot_body<TV, TW, L, true>(a, sg, j, rev);
 }
 template <typename TV, typename TW, int L>
 __global__ __launch_bounds__(kBlock) void k_axpy_mdot64(KArgs a, SegTab sg, int j, int rev) {
-  axpy_mdot_body<TV, TW, L>(a, sg, j, rev);
+  axpy_mdot_body<TV, TW, L, false>(a, sg, j, rev);
+}
+template <typename TV, typename TW, int L>
+__global__ __launch_bounds__(kBlock) void k_axpy_mdot64_ds(KArgs a, SegTab sg, int j, int rev) {
+  axpy_mdot_body<TV, TW, L, true>(a, sg, j, rev);
 }
 
 // w -= V[:, col0:col0+L] coef (no reduction): the first half of projection 2
@@ -1401,11 +1460,11 @@ __device__ void reduce_sum_max(const double* p, const double* q, int n, double& 
 // The per-step finaliser: column j of H from the float64 partials of the
 // last pass (||w''||^2 in the first column of src, max|w''| in the second),
 // the Givens step and the restart decisions, on an LDS copy of the state.
-__global__ __launch_bounds__(kBlock) void k_fin_step(KArgs a, const double* src, int rows, const int32_t* r0,
-                                                     const int32_t* nr, int j) {
+__device__ void fin_step_block(const KArgs& a, const double* src, int rows, const int32_t* r0, const int32_t* nr,
+                               int j, int s) {
   __shared__ FinShared sh;
   __shared__ SysState S;
-  const int s = blockIdx.x, t = threadIdx.x;
+  const int t = threadIdx.x;
   const SysState& G = a.st[s];
   // the state copy, the staged column and rotations and the partial rows are
   // loaded before the gate is tested (they do not depend on it), so they
@@ -1423,6 +1482,11 @@ __global__ __launch_bounds__(kBlock) void k_fin_step(KArgs a, const double* src,
   fin_step(a, s, j, sq, mx, S, sh);
   __syncthreads();
   if (t < kWords) reinterpret_cast<uint64_t*>(&a.st[s])[t] = reinterpret_cast<const uint64_t*>(&S)[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_fin_step(KArgs a, const double* src, int rows, const int32_t* r0,
+                                                     const int32_t* nr, int j) {
+  fin_step_block(a, src, rows, r0, nr, j, blockIdx.x);
 }
 
 // The CGS projections complete column by column: workgroup (s, q) reduces
@@ -2032,14 +2096,57 @@ __host__ __device__ constexpr int rev_pass1(int j) { return j & 1; }
 __host__ __device__ constexpr int rev_pass2(int j) { return (j & 1) ^ 1; }
 __host__ __device__ constexpr int rev_pass3(int j) { return j & 1; }
 
+// The projection kernels of a window of L columns (8, 16, 32 or 64): the
+// plain ones, or with ds the variants that apply v_j's decode scale to w as
+// they load it (KArgs::wsc_defer), which exist for 4- and 8-byte bases only
+// (null for 2-byte ones).
+template <typename TV, typename TW>
+static const void* mdot_fn(int L, bool ds) {
+  if (ds) {
+    if constexpr (sizeof(TV) >= 4)
+      return L == 8 ? (const void*)k_mdot_ds<TV, TW, 8> : L == 16 ? (const void*)k_mdot_ds<TV, TW, 16>
+           : L == 32 ? (const void*)k_mdot_ds<TV, TW, 32> : (const void*)k_mdot_ds<TV, TW, 64>;
+    return nullptr;
+  }
+  return L == 8 ? (const void*)k_mdot<TV, TW, 8> : L == 16 ? (const void*)k_mdot<TV, TW, 16>
+       : L == 32 ? (const void*)k_mdot<TV, TW, 32> : (const void*)k_mdot<TV, TW, 64>;
+}
+// (the fused projection 2: the float64-w variant for an 8-byte w)
+template <typename TV, typename TW>
+static const void* axpy_mdot_fn(int L, bool ds) {
+  if (ds) {
+    if constexpr (sizeof(TV) < 4) {
+      return nullptr;
+    } else if constexpr (sizeof(TW) == 8) {
+      return L == 8 ? (const void*)k_axpy_mdot64_ds<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64_ds<TV, TW, 16>
+           : L == 32 ? (const void*)k_axpy_mdot64_ds<TV, TW, 32> : (const void*)k_axpy_mdot64_ds<TV, TW, 64>;
+    } else {
+      return L == 8 ? (const void*)k_axpy_mdot_ds<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot_ds<TV, TW, 16>
+           : L == 32 ? (const void*)k_axpy_mdot_ds<TV, TW, 32> : (const void*)k_axpy_mdot_ds<TV, TW, 64>;
+    }
+  }
+  if constexpr (sizeof(TW) == 8)
+    return L == 8 ? (const void*)k_axpy_mdot64<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64<TV, TW, 16>
+         : L == 32 ? (const void*)k_axpy_mdot64<TV, TW, 32> : (const void*)k_axpy_mdot64<TV, TW, 64>;
+  else
+    return L == 8 ? (const void*)k_axpy_mdot<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot<TV, TW, 16>
+         : L == 32 ? (const void*)k_axpy_mdot<TV, TW, 32> : (const void*)k_axpy_mdot<TV, TW, 64>;
+}
+
 template <typename TV, typename TW, int L>
 static hipError_t launch_mdot_L(const KArgs& a, int j, int col0, int mode, hipStream_t st, const SegTab** used) {
-  auto kern = k_mdot<TV, TW, L>;
-  const SegTab& sg = split_for(a, kern);
-  hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, col0, mode,
-                     mode == 1 ? rev_pass1(j) : rev_pass2(j));
-  if (used) *used = &sg;
-  return hipGetLastError();
+  auto go = [&](auto kern) -> hipError_t {
+    const SegTab& sg = split_for(a, kern);
+    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, col0, mode,
+                       mode == 1 ? rev_pass1(j) : rev_pass2(j));
+    if (used) *used = &sg;
+    return hipGetLastError();
+  };
+  if (mode == 1 && a.wsc_defer) {
+    if constexpr (sizeof(TV) >= 4) return go(k_mdot_ds<TV, TW, L>);
+    else return hipErrorInvalidValue;
+  }
+  return go(k_mdot<TV, TW, L>);
 }
 
 template <typename TV, typename TW>
@@ -2064,26 +2171,28 @@ static hipError_t launch_fin_cols(const KArgs& a, const SegTab& sg, int j, hipSt
 // float32 copy (or the high words); LDS holds one product per non-zero of a
 // row block in the kernel's accumulation type.
 template <typename TX, typename TY, int MODE>
-static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStream_t st) {
+static hipError_t spmv_values(const KArgs& a, const TX* x, TY* y, int j, hipStream_t st, FinArgs fa = FinArgs{}) {
   if constexpr (MODE == SM_ARNOLDI || MODE == SM_AZ) {
     if (a.use_sell) {
-      const unsigned grid = (unsigned)(a.ld / kBlock);  // one block per 256-row tile (4 slices)
+      // one block per 256-row tile (4 slices), after the finaliser's blocks
+      const unsigned grid = (unsigned)(a.ld / kBlock + fa.n);
       const bool d16 = a.sell_dcol != nullptr;
       if (a.arn64 && d16)
         hipLaunchKernelGGL((k_sell<double, TX, TY, MODE, true>), dim3(grid), dim3(kBlock), 0, st, a,
-                           static_cast<const double*>(a.sell_val), x, y, j);
+                           static_cast<const double*>(a.sell_val), x, y, j, fa);
       else if (a.arn64)
         hipLaunchKernelGGL((k_sell<double, TX, TY, MODE, false>), dim3(grid), dim3(kBlock), 0, st, a,
-                           static_cast<const double*>(a.sell_val), x, y, j);
+                           static_cast<const double*>(a.sell_val), x, y, j, fa);
       else if (d16)
         hipLaunchKernelGGL((k_sell<float, TX, TY, MODE, true>), dim3(grid), dim3(kBlock), 0, st, a,
-                           static_cast<const float*>(a.sell_val), x, y, j);
+                           static_cast<const float*>(a.sell_val), x, y, j, fa);
       else
         hipLaunchKernelGGL((k_sell<float, TX, TY, MODE, false>), dim3(grid), dim3(kBlock), 0, st, a,
-                           static_cast<const float*>(a.sell_val), x, y, j);
+                           static_cast<const float*>(a.sell_val), x, y, j, fa);
       return hipGetLastError();
     }
   }
+  if (fa.n) return hipErrorInvalidValue;  // the finaliser rides only on the sliced product
   auto go = [&](auto kern, const auto* vals, size_t acc_bytes) {
     hipLaunchKernelGGL(kern, dim3(a.nrb), dim3(kBlock), (size_t)a.spmv_budget * acc_bytes, st, a, vals, x, y,
                        nullptr, j);
@@ -2323,18 +2432,19 @@ hipError_t launch_cgs_pass1(const KArgs& a, int j, hipStream_t st, bool with_fin
 
 template <typename TV, typename TW, int L>
 static hipError_t launch_axpy_mdot_L(const KArgs& a, int j, hipStream_t st, const SegTab** used) {
-  if constexpr (sizeof(TW) == 8) {
-    auto kern = k_axpy_mdot64<TV, TW, L>;
+  auto go = [&](auto kern) -> hipError_t {
     const SegTab& sg = split_for(a, kern);
     hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, rev_pass2(j));
     *used = &sg;
-  } else {
-    auto kern = k_axpy_mdot<TV, TW, L>;
-    const SegTab& sg = split_for(a, kern);
-    hipLaunchKernelGGL(kern, dim3(sg.G), dim3(kBlock), 0, st, a, sg, j, rev_pass2(j));
-    *used = &sg;
+    return hipGetLastError();
+  };
+  if (a.wsc_defer) {
+    if constexpr (sizeof(TV) < 4) return hipErrorInvalidValue;
+    else if constexpr (sizeof(TW) == 8) return go(k_axpy_mdot64_ds<TV, TW, L>);
+    else return go(k_axpy_mdot_ds<TV, TW, L>);
   }
-  return hipGetLastError();
+  if constexpr (sizeof(TW) == 8) return go(k_axpy_mdot64<TV, TW, L>);
+  else return go(k_axpy_mdot<TV, TW, L>);
 }
 
 hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin) {
@@ -2351,6 +2461,7 @@ hipError_t launch_cgs_pass2(const KArgs& a, int j, hipStream_t st, bool with_fin
         default: return launch_axpy_mdot_L<TV, TW, 64>(a, j, st, &used);
       }
     }
+    if (a.wsc_defer) return hipErrorInvalidValue;  // (the split form has no deferred-scale variant)
     for (int c0 = 0; c0 < ncol; c0 += 64) {
       auto kern = k_axpy<TV, TW, 64>;
       const SegTab& sg = split_for(a, kern);
@@ -2374,15 +2485,8 @@ hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st) {
     using TV = decltype(tv);
     using TW = decltype(tw);
     if (j + 1 <= 64) {
-      const int L = lanes_for(j + 1);
-      const void* k = nullptr;
-      if constexpr (sizeof(TW) == 8) {
-        k = L == 8 ? (const void*)k_axpy_mdot64<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64<TV, TW, 16>
-          : L == 32 ? (const void*)k_axpy_mdot64<TV, TW, 32> : (const void*)k_axpy_mdot64<TV, TW, 64>;
-      } else {
-        k = L == 8 ? (const void*)k_axpy_mdot<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot<TV, TW, 16>
-          : L == 32 ? (const void*)k_axpy_mdot<TV, TW, 32> : (const void*)k_axpy_mdot<TV, TW, 64>;
-      }
+      const void* k = axpy_mdot_fn<TV, TW>(lanes_for(j + 1), a.wsc_defer != 0);
+      if (!k) return hipErrorInvalidValue;
       used = &a.seg[occupancy_of(k) - 1];
     } else {
       used = &a.seg[occupancy_of((const void*)k_mdot<TV, TW, 64>) - 1];
@@ -2397,16 +2501,15 @@ hipError_t launch_finalize_pass2(const KArgs& a, int j, hipStream_t st) {
 // partial rows, which the completing reduction reads).
 static const SegTab* pass1_split(const KArgs& a, int j) {
   const SegTab* used = nullptr;
-  launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+  const hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
     using TV = decltype(tv);
     using TW = decltype(tw);
-    const int L = j + 1 <= 64 ? lanes_for(j + 1) : 64;
-    const void* k = L == 8 ? (const void*)k_mdot<TV, TW, 8> : L == 16 ? (const void*)k_mdot<TV, TW, 16>
-                  : L == 32 ? (const void*)k_mdot<TV, TW, 32> : (const void*)k_mdot<TV, TW, 64>;
+    const void* k = mdot_fn<TV, TW>(j + 1 <= 64 ? lanes_for(j + 1) : 64, a.wsc_defer != 0);
+    if (!k) return hipErrorInvalidValue;
     used = &a.seg[occupancy_of(k) - 1];
     return hipSuccess;
   });
-  return used;
+  return e == hipSuccess ? used : nullptr;
 }
 
 hipError_t launch_finalize_pass1(const KArgs& a, int j, hipStream_t st) {
@@ -2422,9 +2525,9 @@ hipError_t launch_residual_finish(const KArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The per-step finaliser after the last pass of step j (k_fin_step), on the
-// partial rows that pass wrote.
-hipError_t launch_finalize_final(const KArgs& a, int j, hipStream_t st) {
+// The split of the last pass of step j (whose partial rows the per-step
+// finaliser reads) and the table it wrote them to.
+static const SegTab* final_split(const KArgs& a, int j, const double** src_out) {
   const SegTab* used = nullptr;
   const double* src = a.part;
   hipError_t e = launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
@@ -2446,9 +2549,38 @@ hipError_t launch_finalize_final(const KArgs& a, int j, hipStream_t st) {
     used = &a.seg[occupancy_of(k) - 1];
     return hipSuccess;
   });
-  if (e != hipSuccess || !used) return e != hipSuccess ? e : hipErrorInvalidValue;
+  if (e != hipSuccess) return nullptr;
+  *src_out = src;
+  return used;
+}
+
+// The per-step finaliser after the last pass of step j (k_fin_step), on the
+// partial rows that pass wrote.
+hipError_t launch_finalize_final(const KArgs& a, int j, hipStream_t st) {
+  const double* src = nullptr;
+  const SegTab* used = final_split(a, j, &src);
+  if (!used) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_fin_step, dim3(a.S), dim3(kBlock), 0, st, a, src, used->nseg, used->sys_sg0, used->sys_nsg, j);
   return hipGetLastError();
+}
+
+hipError_t launch_spmv_fin(const KArgs& a, int j_fin, hipStream_t st) {
+  if (!a.use_sell || !a.wsc_defer || a.precond != 0 || j_fin + 1 >= a.m) return hipErrorInvalidValue;
+  FinArgs fa;
+  const SegTab* used = final_split(a, j_fin, &fa.src);
+  if (!used) return hipErrorInvalidValue;
+  fa.n = (a.S + 7) / 8 * 8;
+  fa.j = j_fin;
+  fa.rows = used->nseg;
+  fa.r0 = used->sys_sg0;
+  fa.nr = used->sys_nsg;
+  const int j = j_fin + 1;
+  return launch_by_prec(a.prec, [&](auto tv, auto tw) -> hipError_t {
+    using TV = decltype(tv);
+    using TW = decltype(tw);
+    const TV* x = reinterpret_cast<const TV*>(a.V) + (int64_t)j * a.ld;
+    return spmv_values<TV, TW, SM_ARNOLDI>(a, x, (TW*)a.w, j, st, fa);
+  });
 }
 
 hipError_t launch_final_pass(const KArgs& a, int j, hipStream_t st, bool with_fin) {
@@ -2502,20 +2634,11 @@ hipError_t launch_config(const KArgs& a, int family, int j, int32_t* grid, int32
         G = a.use_sell ? (int)(a.ld / kBlock) : a.nrb;
         return hipSuccess;
       case 1:
-        k = L == 8 ? (const void*)k_mdot<TV, TW, 8> : L == 16 ? (const void*)k_mdot<TV, TW, 16>
-          : L == 32 ? (const void*)k_mdot<TV, TW, 32> : (const void*)k_mdot<TV, TW, 64>;
-        return hipSuccess;
+        k = mdot_fn<TV, TW>(L, a.wsc_defer != 0);
+        return k ? hipSuccess : hipErrorInvalidValue;
       case 2:
-        if (j + 1 > 64) {
-          k = (const void*)k_mdot<TV, TW, 64>;
-        } else if constexpr (sizeof(TW) == 8) {
-          k = L == 8 ? (const void*)k_axpy_mdot64<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot64<TV, TW, 16>
-            : L == 32 ? (const void*)k_axpy_mdot64<TV, TW, 32> : (const void*)k_axpy_mdot64<TV, TW, 64>;
-        } else {
-          k = L == 8 ? (const void*)k_axpy_mdot<TV, TW, 8> : L == 16 ? (const void*)k_axpy_mdot<TV, TW, 16>
-            : L == 32 ? (const void*)k_axpy_mdot<TV, TW, 32> : (const void*)k_axpy_mdot<TV, TW, 64>;
-        }
-        return hipSuccess;
+        k = j + 1 > 64 ? (const void*)k_mdot<TV, TW, 64> : axpy_mdot_fn<TV, TW>(L, a.wsc_defer != 0);
+        return k ? hipSuccess : hipErrorInvalidValue;
       case 3:
         if (a.ortho == 0) {
           G = a.seg[kMgsOcc - 1].G;
@@ -2591,15 +2714,12 @@ hipError_t prepare_occupancy(int prec) {
         (const void*)k_final_tile<TV, TW, 32>, (const void*)k_final_tile<TV, TW, 64>,
         (const void*)k_final<TV, TW>, (const void*)k_mgs<TV, TW>, (const void*)k_mgs_final<TV, TW>};
     for (const void* k : ks) occupancy_of(k);
-    // the fused projection-2 kernel in the variant that is launched
-    if constexpr (sizeof(TW) == 8) {
-      const void* kf[] = {(const void*)k_axpy_mdot64<TV, TW, 8>, (const void*)k_axpy_mdot64<TV, TW, 16>,
-                          (const void*)k_axpy_mdot64<TV, TW, 32>, (const void*)k_axpy_mdot64<TV, TW, 64>};
-      for (const void* k : kf) occupancy_of(k);
-    } else {
-      const void* kf[] = {(const void*)k_axpy_mdot<TV, TW, 8>, (const void*)k_axpy_mdot<TV, TW, 16>,
-                          (const void*)k_axpy_mdot<TV, TW, 32>, (const void*)k_axpy_mdot<TV, TW, 64>};
-      for (const void* k : kf) occupancy_of(k);
+    // the fused projection-2 kernel in the variant that is launched, and the
+    // deferred-scale variants of both projections where they exist
+    for (int L : {8, 16, 32, 64}) {
+      occupancy_of(axpy_mdot_fn<TV, TW>(L, false));
+      if (const void* k = mdot_fn<TV, TW>(L, true)) occupancy_of(k);
+      if (const void* k = axpy_mdot_fn<TV, TW>(L, true)) occupancy_of(k);
     }
     return hipSuccess;
   });

@@ -274,11 +274,14 @@ class Solver:
         return {"grid": g.value, "block": b.value, "per_cu": o.value, "basis_align": al.value}
 
     def spmv_config(self):
-        """The Arnoldi SpMV the handle runs: dict(format, block_nnz, xcd_remap)."""
-        f, bn, xr = C.c_int32(), C.c_int32(), C.c_int32()
-        L.check(self.lib.gmres_spmv_config(self.h, C.byref(f), C.byref(bn), C.byref(xr)), "gmres_spmv_config")
+        """The Arnoldi SpMV the handle runs: dict(format, block_nnz, xcd_remap,
+        fin_merged) (fin_merged: each step's finaliser runs in the next
+        product's launch and the projections apply v_j's decode scale)."""
+        f, bn, xr, fm = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        L.check(self.lib.gmres_spmv_config(self.h, C.byref(f), C.byref(bn), C.byref(xr), C.byref(fm)),
+                "gmres_spmv_config")
         fmt = {v: k for k, v in L.SPMV_FORMATS.items()}[f.value]
-        return {"format": fmt, "block_nnz": bn.value, "xcd_remap": bool(xr.value)}
+        return {"format": fmt, "block_nnz": bn.value, "xcd_remap": bool(xr.value), "fin_merged": bool(fm.value)}
 
     def time_kernel(self, kernel, j, reps=20):
         """(mean ms per launch, algorithmic bytes per launch) of one hot-path kernel."""

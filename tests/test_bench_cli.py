@@ -48,6 +48,12 @@ def test_tile_widths_follow_the_column():
                                                                      list(range(50)))]
     sell16 = dict(sell, format="sell16")
     assert bench.kernel_units("spmv", 50, "fp32", "cgsr", sell16)[0][0] == "k_sell<float, float, float, 0, true>"
+    # the finaliser merged into the product: the first two projections run their _ds kernels
+    merged = dict(sell16, fin_merged=True)
+    assert bench.kernel_units("pass1", 50, "fp32", "cgsr", merged)[3][0] == "k_mdot_ds<float, float, 64>"
+    assert bench.kernel_units("pass2", 50, "fp64", "cgsr", merged)[0][0].startswith("k_axpy_mdot64_ds<double, double")
+    assert bench.kernel_units("pass2", 50, "fp32", "cgsr", merged)[3][0] == "k_axpy_mdot_ds<float, float, 64>"
+    assert bench.kernel_units("final", 50, "fp32", "cgsr", merged)[3][0] == "k_final_tile<float, float, 64>"
     csr = dict(sell, format="csr")
     assert bench.kernel_units("spmv", 50, "fp64", "cgsr", csr)[0][0] == "k_spmv<double, double, double, 0>"
     assert bench.kernel_units("spmv", 50, "limited", "cgsr", csr)[0][0] == "k_spmv<float, float, double, 0>"

@@ -50,12 +50,12 @@ PEAK_HBM_GBS = 8000.0
 # counter reads for the 1 GiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); void
 # once the kernel source changes
 TRAFFIC = {
-    "kernel_source_sha256": "676f263a22ec8ea9ce52fcdcf8d23381d10df79b18656f22b526ec79d146be4e",
+    "kernel_source_sha256": "c039eb5a874701ebcbedb0f24359cafcf553969b59e9a064a9a445b68d6f29c5",
     "bytes_per_launch": {
-        "k_axpy_mdot_ds<float, float, 64>": 365527707,
-        "k_mdot_ds<float, float, 64>": 357170679,
-        "k_final_tile<float, float, 64>": 364140129,
-        "k_sell<float, float, float, 0, true>": 107726658,
+        "k_axpy_mdot_ds<float, float, 64>": 364456778,
+        "k_mdot_ds<float, float, 64>": 356072821,
+        "k_final_tile<float, float, 64>": 364140105,
+        "k_sell<float, float, float, 0, true>": 116114767,
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2011_01850_amd", "csrc", "gmres_kernels.hip")

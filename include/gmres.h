@@ -495,11 +495,14 @@ int gmres_launch_config(gmres_handle h, int32_t family, int32_t j, int32_t* grid
  * workgroups are mapped onto one XCD; *fin_merged = 1 when the finaliser of
  * Arnoldi step j (column j of H, the Givens step, the decode scale of
  * v_{j+1}) runs in the same launch as the product A v_{j+1}, which then
- * stores w unscaled and leaves the decode scale to the first two CGSR
- * projections (their k_mdot_ds / k_axpy_mdot_ds / k_axpy_mdot64_ds kernels):
- * sliced ELL product, CGSR, no preconditioner, a 4- or 8-byte basis,
- * m <= 64, no orthogonality monitor.  Any output may be NULL.  ESTATE on the
- * persistent batch schedule. */
+ * stores w unscaled and leaves the decode scale to the passes that read w
+ * first (the first two CGSR projections, in their k_mdot_ds / k_axpy_mdot_ds
+ * / k_axpy_mdot64_ds kernels; the first two MGS steps and, at j = 0, the
+ * last MGS pass): sliced ELL product, CGSR with m <= 64 or MGS, no
+ * preconditioner, a 4- or 8-byte basis (not a float64 product into a
+ * float32 w), no orthogonality monitor.  The solve is the same bit for bit
+ * either way.  Any output may be NULL.  ESTATE on the persistent batch
+ * schedule. */
 int gmres_spmv_config(gmres_handle h, int32_t* format, int32_t* block_nnz, int32_t* xcd_remap,
                       int32_t* fin_merged);
 

@@ -424,11 +424,11 @@ hipError_t enqueue_cycle(gmres_ctx* h, hipStream_t st) {
       e = launch_cgs_pass1(a, j, st);
       if (e == hipSuccess) e = launch_cgs_pass2(a, j, st);
       if (e == hipSuccess) e = launch_final_pass(a, j, st, !ride);
-      if (e == hipSuccess && ride) e = j + 1 < a.m ? launch_spmv_fin(a, j, st) : launch_finalize_final(a, j, st);
     } else {
       for (int i = 0; i <= j && e == hipSuccess; ++i) e = launch_mgs_dot(a, j, i, st);
-      if (e == hipSuccess) e = launch_final_pass(a, j, st);
+      if (e == hipSuccess) e = launch_final_pass(a, j, st, !ride);
     }
+    if (e == hipSuccess && ride) e = j + 1 < a.m ? launch_spmv_fin(a, j, st) : launch_finalize_final(a, j, st);
     if (e == hipSuccess && two && j + 1 <= a.m) e = launch_encode(a, j + 1, st);
     if (e == hipSuccess && a.orth_restart > 0.0) e = launch_orth_check(a, j, st);
   }
@@ -1087,13 +1087,14 @@ void setup(gmres_ctx* h, int32_t nsys, const int64_t* n, const int64_t* nnz, con
     a.use_sell = sell ? 1 : 0;
   }
   // the finaliser of each step rides on the next step's sliced product
-  // (CGSR over register tiles, no preconditioner, a 4- or 8-byte basis, no
-  // orthogonality monitor); the product then leaves v_j's scale to the
-  // projections, which round the scaled w exactly as the product would
-  // have (not so for a float64 product into a float32 w: left out)
-  a.wsc_defer = !h->persistent && a.use_sell && opt->ortho == GMRES_CGSR && opt->precond == GMRES_PRECOND_NONE &&
-                (prec == P32 || prec == P64 || prec == PL32) && !(prec == P32 && a.arn64) && m <= 64 &&
-                opt->orth_restart <= 0.0;
+  // (CGSR over register tiles or MGS, no preconditioner, a 4- or 8-byte
+  // basis, no orthogonality monitor); the product then leaves v_j's scale
+  // to the first passes that read w, which round the scaled w exactly as
+  // the product would have (not so for a float64 product into a float32 w:
+  // left out)
+  a.wsc_defer = !h->persistent && a.use_sell && (opt->ortho == GMRES_MGS || m <= 64) &&
+                opt->precond == GMRES_PRECOND_NONE && (prec == P32 || prec == P64 || prec == PL32) &&
+                !(prec == P32 && a.arn64) && opt->orth_restart <= 0.0;
   h->xs = h->alloc<double>(h->ld);
   h->ys = h->alloc<double>(h->ld);
   hip_check(hipStreamSynchronize(h->stream));

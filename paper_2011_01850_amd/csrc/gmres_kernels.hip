@@ -1271,6 +1271,11 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
     const int s = seg_sys(a, sg, k);
     if (!gated_s(a, s, on0)) continue;
     const ACC cprev = i > 0 ? (ACC)mgs_complete(a, sg, s, k == sys_seg0(a, sg, s), i - 1, pin) : (ACC)0;
+    // steps 0 and 1 read w as the Arnoldi product stored it: without v_j's
+    // decode scale when the product left it out (applied here with the
+    // product's rounding, apart from the sums that follow)
+    const bool ds = a.wsc_defer && i <= 1;
+    const ACC wsc = ds ? (ACC)a.sc[(int64_t)s * (a.m + 1) + j] : (ACC)1;
     int t0, nt;
     seg_tiles(a, sg, k, t0, nt);
     ACC d = (ACC)0, ww = (ACC)0;
@@ -1282,6 +1287,7 @@ __global__ __launch_bounds__(kBlock) void k_mgs(KArgs a, SegTab sg, int j, int i
       for (int q = 0; q < kMgsUnroll; ++q) {
         r[q] = seg_row(t0, nt, u + q < nt ? u + q : u, i & 1);
         wv[q] = (ACC)w[r[q]];
+        if (ds) wv[q] = mul_nofuse(wv[q], wsc);
         pv[q] = i > 0 ? (ACC)ldv(vp[r[q]]) : (ACC)0;
         iv[q] = (ACC)ldv(vi[r[q]]);
       }
@@ -1325,6 +1331,9 @@ __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab
     const int s = seg_sys(a, sg, k);
     if (!gated_s(a, s, on0)) continue;
     const ACC cj = (ACC)mgs_complete(a, sgp, s, k == sys_seg0(a, sg, s), j, pin);
+    // (at j = 0 no step has stored w yet: the deferred scale, as in k_mgs)
+    const bool ds = a.wsc_defer && j == 0;
+    const ACC wsc = ds ? (ACC)a.sc[(int64_t)s * (a.m + 1) + j] : (ACC)1;
     int t0, nt;
     seg_tiles(a, sg, k, t0, nt);
     ACC sq = (ACC)0, mx = (ACC)0;
@@ -1335,6 +1344,7 @@ __global__ __launch_bounds__(kBlock) void k_mgs_final(KArgs a, SegTab sg, SegTab
       for (int q = 0; q < kMgsUnroll; ++q) {
         r[q] = seg_row(t0, nt, u + q < nt ? u + q : u, (j + 1) & 1);
         wv[q] = (ACC)w[r[q]];
+        if (ds) wv[q] = mul_nofuse(wv[q], wsc);
         jv[q] = (ACC)ldv(vj[r[q]]);
       }
 #pragma unroll
